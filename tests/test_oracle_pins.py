@@ -66,7 +66,7 @@ def hyp_series(a, b, c, gam, dlt, n):
 
 @pytest.mark.parametrize("loops,indices,d0", [
     (1, (1, 1), 4), (1, (1, 1, 1, 1), 4), (2, (1,) * 7, 4), (1, (1,), 4), (2, (1, 1, 1, 1, 2), 4),
-    (1, (2, 1), 6),
+    (1, (2, 1), 6), (2, (1, 1, 1), 4), (3, (1, 1, 1, 1), 4),
 ])
 def test_prefactor_vs_gamma_taylor(loops, indices, d0):
     lead, ser = prefactor.feynman_prefactor(loops, indices, d0, 6)
@@ -197,6 +197,16 @@ def test_massive_bubble_above_threshold(lam):
     assert tot[0] == pytest.approx(1.0, abs=1e-12)
     assert abs(tot[1] - fin) < 1e-10
     assert not pos.any()
+
+
+def test_minus_i0_on_negative_real_axis():
+    """A factor that is real and negative takes Log = ln|P| - i pi (F - i0 of eq. (1))."""
+    sec = Sector(a=np.array([0.0]), b=np.array([0.0]), factors=[
+        Factor(0.0, -1.0, np.array([-1.0, -1.0]), np.array([[0], [1]], dtype=np.uint8))])
+    got = quad_sector_f(sec, 1, nodes=60, power=1, complex_mode=True, lam=0.0)
+    # int (-(1+x) - i0)^(-eps) dx = 1 - eps int_0^1 (ln(1+x) - i pi) dx + ...
+    assert got[0] == pytest.approx(1.0, abs=1e-14)
+    assert abs(got[1] - (-(2 * math.log(2) - 1) + 1j * math.pi)) < 1e-13
 
 
 def deformable_2d_sector():
