@@ -354,3 +354,28 @@ def test_bubble_estimates_calibrated():
     zs = np.array(zs)
     assert np.all(np.abs(zs) < 5.0)
     assert np.mean(np.abs(zs) < 2.0) > 0.7
+
+
+# ------------------------------------------------------------------ the paper's worked example
+
+def test_box_worked_example_section_4_3():
+    """Massless on-shell box, S = 3, T = 1 (section 4.3): the paper prints
+    -4.38658 + (1.3333 +- 0.000019)/ep^2 - (0.732466 +- 0.000667)/ep +- 0.001.
+    Textbook value in the same normalisation: 4/(3 ep^2) - (2 ln 3 / 3)/ep - 4 pi^2 / 9."""
+    from sectorgen.feynman import box_problem
+    prob = box_problem(3.0, 1.0)
+    lead, pref = integrate.prefactor_for(prob)
+    x1, w1 = gl_nodes(36, 5)
+    g = np.meshgrid(x1, x1, x1, indexing="ij")
+    gw = np.meshgrid(w1, w1, w1, indexing="ij")
+    x = np.stack([v.ravel() for v in g], axis=1)
+    w = np.prod(np.stack([v.ravel() for v in gw], axis=1), axis=1)
+    tot = 0
+    for sec in prob.sectors:
+        vals, _, _ = integrand.sector_orders(sec, x, prob.order_min, prob.order_max, lead, pref)
+        tot = tot + vals @ w
+    printed = [(1.3333, 0.000019), (-0.732466, 0.000667), (-4.38658, 0.001)]
+    for (v, e), got in zip(printed, tot):
+        assert abs(got - v) < 3 * e + 5e-5
+    exact = [4 / 3, -2 * math.log(3) / 3, -4 * math.pi ** 2 / 9]
+    assert np.allclose(tot, exact, rtol=2e-6, atol=2e-6)
