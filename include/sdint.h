@@ -1,0 +1,191 @@
+/*
+ * sdint.h - C ABI of the MI355X sector-integrand library (libsdint.so).
+ *
+ * The library evaluates eps-expanded, sector-decomposed Feynman-parameter
+ * integrands at very many sampling points on one AMD Instinct MI355X (gfx950)
+ * and reduces them to eps-expansion coefficients with error estimates, the
+ * numerical-integration stage of the sector-decomposition method described in
+ * FIESTA 4 (A.V. Smirnov, arXiv:1511.03614): section 1 and eq. (2) define the
+ * integrals, section 4.3 (SDEvaluate) the output (coefficients of eps^k with
+ * "pm" errors combined in the mean-square norm), section 4.4 the Vegas
+ * integrator and the contour deformation (ComplexMode), section 4.6 the
+ * worker's single-point evaluation and TestF check.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: SDI_OK (0) or a negative SDI_E* code.  The message of the
+ *    last failure on a context is available from sdi_last_error(ctx) until the
+ *    next call on that context.  On error no output argument is written,
+ *    except where an entry point says otherwise.
+ *  - Host pointers are plain CPU memory; arguments documented as "device" are
+ *    HIP device pointers (e.g. torch tensors on cuda:N) on the context's device.
+ *  - A context is not thread-safe: use one context per host thread.
+ *  - Device work is issued on the context's stream; entry points that return
+ *    host results synchronise that stream before returning.
+ */
+#ifndef SDINT_H
+#define SDINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SDI_OK = 0,
+  SDI_EINVAL = -1,      /* invalid argument or input outside the supported domain   */
+  SDI_ENOMEM = -2,      /* host or device allocation failed, or workspace too small */
+  SDI_EDEVICE = -3,     /* a HIP call failed                                        */
+  SDI_ENOTSUP = -4,     /* valid input that this build does not support            */
+  SDI_ENONFINITE = -5,  /* results written, but some integrand values were NaN/Inf  */
+  SDI_ESTATE = -6       /* call order violated (e.g. flow sampler before training)  */
+};
+
+#define SDI_MAX_VARS 16     /* variables per sector                          */
+#define SDI_MAX_FACTORS 4   /* regular factors P_m per sector                */
+#define SDI_MAX_SINGULAR 4  /* variables with a_j = -1 per sector            */
+#define SDI_MAX_ORDERS 8    /* requested orders, and internal log-power depth */
+
+typedef struct sdi_ctx sdi_ctx;
+typedef struct sdi_problem sdi_problem;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device_ordinal`.  `hip_stream` is a
+ * hipStream_t to issue work on (the caller keeps ownership), or NULL for a
+ * library-owned stream.  *out receives the context. */
+int sdi_ctx_create(int device_ordinal, void* hip_stream, sdi_ctx** out);
+void sdi_ctx_destroy(sdi_ctx* ctx);
+/* Message of the last failed call on ctx ("" if none).  Owned by ctx. */
+const char* sdi_last_error(const sdi_ctx* ctx);
+/* Device description (name, CUs, LDS, clock) as text: the GPUData command of
+ * section 4.6.  Writes at most len bytes including the terminating NUL. */
+int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
+
+/* Integrator parameters, the SetCurrentIntegratorParameter command of
+ * section 4.6.  Keys (values are decimal text unless noted):
+ *   lattice_log2   m, lattice points per shift N = 2^m          (default 16, 4..30)
+ *   shifts         R, random shifts per sector                  (default 16, 2..256)
+ *   seed           64-bit seed of the Philox4x32-10 shifts     (default 1)
+ *   baker          1: tent-transform the lattice, 0: off        (default 1)
+ *   warmup         Vegas grid-adaptation iterations             (default 0)
+ *   warmup_log2    lattice points per warm-up iteration         (default 14)
+ *   nbins          Vegas bins per dimension, power of 2 <= 256  (default 128)
+ *   tile_log2      points per work tile                         (default 14)
+ *   ppt            points per thread: 0 = autotuned, 1, 2 or 4  (default 0)
+ *   tune           off | cached | search                        (default cached)
+ * Unknown keys or malformed values return SDI_EINVAL. */
+int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value);
+int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len);
+
+/* ------------------------------------------------------------------ problem */
+
+/* One sector (section 1, eq. (2) after sector decomposition):
+ *
+ *   I_s = c_s int_[0,1]^n prod_j x_j^(a_j + b_j eps) prod_m P_m(x)^(gamma_m + delta_m eps) dx,
+ *   P_m(x) = sum_t coef_t prod_j x_j^exps_tj.
+ *
+ * a_j must be exactly -1 (then b_j != 0) or greater than -1.  All arrays are
+ * host memory owned by the caller and copied by sdi_problem_create. */
+typedef struct {
+  int32_t nvars;              /* n, 1..SDI_MAX_VARS                                 */
+  int32_t nfactors;           /* M, 0..SDI_MAX_FACTORS                              */
+  int32_t deform_factor;      /* index of the F polynomial among the factors, or -1 */
+  int32_t reserved;           /* must be 0                                          */
+  double coeff_re, coeff_im;  /* c_s                                                */
+  const double* mono_a;       /* [n] a_j                                            */
+  const double* mono_b;       /* [n] b_j                                            */
+  const int32_t* deform_mono; /* [n] exponents of the monomial factored out of F, so
+                                 that the sector's full F is x^deform_mono P_F; NULL = 0 */
+  const int32_t* fac_nterms;  /* [M] terms per factor                               */
+  const double* fac_gamma;    /* [M] gamma_m                                        */
+  const double* fac_delta;    /* [M] delta_m                                        */
+  const double* term_coef;    /* [sum nterms] coefficients, factor-major            */
+  const uint8_t* term_exps;   /* [sum nterms][n] exponents, row-major               */
+} sdi_sector_desc;
+
+/* The problem: sectors, requested orders, prefactor series, complex mode.
+ * Result_k = sum_i Pi_i sum_s I_s[eps^(k - pref_lead - i)] for
+ * k = order_min .. order_max (at most SDI_MAX_ORDERS orders). */
+typedef struct {
+  int32_t nsectors;
+  const sdi_sector_desc* sectors;
+  int32_t order_min, order_max;
+  int32_t pref_lead, pref_len;  /* Pi(eps) = sum_{i<pref_len} Pi_i eps^(pref_lead + i) */
+  const double* pref_re;        /* [pref_len]                                          */
+  const double* pref_im;        /* [pref_len] or NULL                                  */
+  int32_t complex_mode;         /* 1: deform x -> x - i lambda x (1-x) dF/dx (section 4.4) */
+  double lambda;
+} sdi_problem_desc;
+
+/* Validate and compile a problem into device tables (one host-to-device upload).
+ * Returns SDI_EINVAL for inputs outside the domain above and SDI_ENOTSUP for
+ * valid inputs beyond this build (more than SDI_MAX_SINGULAR singular
+ * variables, exponents above 3 in real mode or 7 in complex mode). */
+int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* desc, sdi_problem** out);
+void sdi_problem_destroy(sdi_problem* prob);
+int sdi_problem_norders(const sdi_problem* prob);
+
+/* Laurent series of the Feynman prefactor of eq. (2) with (i pi^(d/2))^l and
+ * exp(-l gamma_E eps) pulled out (section 4.3):
+ *   Pi(eps) = exp(l gamma_E eps) Gamma(A - l d/2) / prod_i Gamma(a_i),  d = d0 - 2 eps,
+ * A = sum of the `nprops` indices (each >= 1).  Writes *lead and out[0..len-1]. */
+int sdi_prefactor_feynman(int32_t loops, const int32_t* indices, int32_t nprops, int32_t d0,
+                          int32_t len, int32_t* lead, double* out);
+
+/* Rank-1 lattice generating vector for N = 2^m points and `dims` dimensions
+ * (component-by-component search), as used by the integrator.  out[dims]. */
+int sdi_lattice_vector(int32_t m, int32_t dims, uint32_t* out);
+
+/* ------------------------------------------------------------------ integrate */
+
+typedef struct {
+  int32_t order_min, norders;   /* filled by the library                              */
+  double* val_re;               /* [norders] caller-allocated                         */
+  double* val_im;
+  double* err_re;               /* one standard deviation, re and im apart            */
+  double* err_im;
+  int64_t n_evals;              /* sector-point evaluations, all orders at once       */
+  int64_t n_nonfinite;          /* non-finite weighted values (they enter the sums)   */
+  int64_t n_imf_positive;       /* points with Im F(z) > 0 (TestF of section 4.6)     */
+  double ms_sample_eval_reduce; /* device time of the final pass                      */
+  double ms_refit;              /* device time of the warm-up iterations and refits   */
+  double ms_total;
+} sdi_result;
+
+/* Bytes of device workspace sdi_integrate needs under the current parameters. */
+size_t sdi_workspace_bytes(sdi_ctx* ctx, const sdi_problem* prob);
+
+/* Integrate every sector: optional Vegas warm-up iterations (grid refit),
+ * then the frozen-grid pass over R shifted lattices; per-sector means and
+ * shift-to-shift errors; root-sum-square combination (section 4.3).
+ * `dev_workspace` is device memory of at least sdi_workspace_bytes, or NULL
+ * to let the library allocate (kept with the problem for reuse).  Synchronises
+ * the stream and fills *out; returns SDI_ENONFINITE (with *out filled) if any
+ * value was not finite. */
+int sdi_integrate(sdi_ctx* ctx, sdi_problem* prob, void* dev_workspace, size_t ws_bytes,
+                  sdi_result* out);
+
+/* Per-sector results of the last sdi_integrate: mean[K][2] (re, im),
+ * err[K][2], per_shift[R][K][2] (may be NULL), *nevals. */
+int sdi_sector_results(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, double* mean,
+                       double* err, double* per_shift, int64_t* nevals);
+
+/* Values of every requested order of sector s (prefactor and c_s folded in,
+ * no sampling weight) at caller points: the justEvaluate integrator of
+ * section 4.4.  x: device [npts][n] doubles in the sector's variable order;
+ * out: device [npts][K][2] doubles (re, im).  Stream-ordered; synchronises. */
+int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, const void* x_dev,
+                 int64_t npts, void* out_dev);
+
+/* The exact points and weights the integrator uses for sector s, shift r,
+ * lattice indices i0 .. i0+npts-1, under the current grid of that sector:
+ * x: device [npts][n], w: device [npts] (NULL allowed).  Synchronises. */
+int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, int32_t shift,
+                      int64_t i0, int64_t npts, void* x_dev, void* w_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDINT_H */

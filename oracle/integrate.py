@@ -31,7 +31,7 @@ class SectorEstimate:
     mean: np.ndarray       # (K,) complex
     err_re: np.ndarray     # (K,)
     err_im: np.ndarray     # (K,)
-    n_nonfinite: int
+    n_nonfinite: int       # points where some order is not finite
     n_imf_positive: int
     grid: Optional[np.ndarray]
 
@@ -70,12 +70,13 @@ def integrate_sector(problem, s: int, m: int, nshifts: int, seed: int, pref_lead
         grid = points.identity_grid(n, nbins)
     nonfinite = 0
     imfpos = 0
+    kf_max = problem.order_max - pref_lead
     for it in range(warmup):
         zw = points.cbc_vector(warmup_m, n)
         sh = points.shift_table(seed, s, nshifts + it + 1, n, warmup_m)[nshifts + it]
         x, w, b = points.sector_points(zw, warmup_m, sh, 0, 1 << warmup_m, grid, baker)
-        vals, _, _ = sector_values(problem, s, x, pref_lead, pref)
-        h = vegas.histogram(b, vals * w[None, :], nbins)
+        f, _, _ = integrand.sector_f(sec, x, kf_max, problem.complex_mode, problem.lam)
+        h = vegas.histogram(b, f * w[None, :], nbins)
         grid = vegas.refit(grid, vegas.importance(h))
     z = points.cbc_vector(m, n)
     shifts = points.shift_table(seed, s, nshifts, n, m)
@@ -85,7 +86,7 @@ def integrate_sector(problem, s: int, m: int, nshifts: int, seed: int, pref_lead
         x, w, _ = points.sector_points(z, m, shifts[r], 0, N, grid if use_grid else None, baker)
         vals, _, pos = sector_values(problem, s, x, pref_lead, pref)
         wf = vals * w[None, :]
-        nonfinite += int(np.sum(~np.isfinite(wf)))
+        nonfinite += int(np.sum(~np.all(np.isfinite(wf), axis=0)))
         imfpos += int(np.sum(pos))
         for k in range(K):
             q[r, k] = fsum_c(wf[k]) / N

@@ -6,8 +6,9 @@ The paper's default integrator is Cuba's Vegas (section 4.4, CurrentIntegrator);
 Cuba's own constants are not given there, so this is Lepage's published
 refinement with the constants stated in the design doc:
 
-* importance of a point: rho = sum_k |w F_k|^2 / H_{j,k}, where H_{j,k} is the
-  iteration's total of |w F_k|^2 (so every order counts equally);
+* importance of a point: rho = sum_k |w f_k|^2 / H_{j,k} over the sector's
+  internal eps orders f_k (before the prefactor series multiplies them), where
+  H_{j,k} is the iteration's total of |w f_k|^2 (so every order counts equally);
 * per dimension j and bin b: d_b = sum of rho over the points in bin b;
 * smoothing: d'_b = (d_{b-1} + d_b + d_{b+1}) / 3, two-point means at the ends;
 * compression: r_b = d'_b / sum d', m_b = ((r_b - 1) / ln r_b)^alpha
@@ -23,9 +24,9 @@ ALPHA = 1.5
 
 
 def histogram(bins: np.ndarray, wf: np.ndarray, nbins: int) -> np.ndarray:
-    """h[j, b, k] = sum over points with bin b in dim j of |w F_k|^2.
+    """h[j, b, k] = sum over points with bin b in dim j of |w f_k|^2.
 
-    bins: (npts, n) bin indices; wf: (K, npts) weighted values (real or complex).
+    bins: (npts, n) bin indices; wf: (K, npts) weighted internal orders.
     """
     npts, n = bins.shape
     a2 = np.abs(wf) ** 2

@@ -1,0 +1,283 @@
+"""Python binding of libsdint (the C ABI in include/sdint.h).
+
+Argument marshalling only: every function here has the name of the C entry
+point it calls, converts Python/NumPy/torch arguments to C types and checks the
+status.  All numerical work runs in the HIP library; if ``libsdint.so`` is not
+built, every call raises.
+
+PyTorch provides device memory and streams: a context is created on torch's
+current stream, and device arguments are torch tensors on that device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "SdiError", "load_library", "library_path", "declared_functions",
+    "sdi_ctx_create", "sdi_ctx_destroy", "sdi_last_error", "sdi_device_info",
+    "sdi_set_param", "sdi_get_param", "sdi_prefactor_feynman", "sdi_lattice_vector",
+    "sdi_problem_create", "sdi_problem_destroy", "sdi_problem_norders", "sdi_workspace_bytes",
+    "sdi_integrate", "sdi_sector_results", "sdi_evaluate", "sdi_sample_points",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsdint.so")
+_HEADER = os.path.join(os.path.dirname(_HERE), "include", "sdint.h")
+_lib = None
+
+SDI_CODES = {0: "SDI_OK", -1: "SDI_EINVAL", -2: "SDI_ENOMEM", -3: "SDI_EDEVICE", -4: "SDI_ENOTSUP",
+             -5: "SDI_ENONFINITE", -6: "SDI_ESTATE"}
+KMAX = 8
+
+
+class SdiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{SDI_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SectorDesc(C.Structure):
+    _fields_ = [("nvars", C.c_int32), ("nfactors", C.c_int32), ("deform_factor", C.c_int32),
+                ("reserved", C.c_int32), ("coeff_re", C.c_double), ("coeff_im", C.c_double),
+                ("mono_a", C.POINTER(C.c_double)), ("mono_b", C.POINTER(C.c_double)),
+                ("deform_mono", C.POINTER(C.c_int32)), ("fac_nterms", C.POINTER(C.c_int32)),
+                ("fac_gamma", C.POINTER(C.c_double)), ("fac_delta", C.POINTER(C.c_double)),
+                ("term_coef", C.POINTER(C.c_double)), ("term_exps", C.POINTER(C.c_uint8))]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("nsectors", C.c_int32), ("sectors", C.POINTER(SectorDesc)),
+                ("order_min", C.c_int32), ("order_max", C.c_int32),
+                ("pref_lead", C.c_int32), ("pref_len", C.c_int32),
+                ("pref_re", C.POINTER(C.c_double)), ("pref_im", C.POINTER(C.c_double)),
+                ("complex_mode", C.c_int32), ("lambda_", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("order_min", C.c_int32), ("norders", C.c_int32),
+                ("val_re", C.POINTER(C.c_double)), ("val_im", C.POINTER(C.c_double)),
+                ("err_re", C.POINTER(C.c_double)), ("err_im", C.POINTER(C.c_double)),
+                ("n_evals", C.c_int64), ("n_nonfinite", C.c_int64), ("n_imf_positive", C.c_int64),
+                ("ms_sample_eval_reduce", C.c_double), ("ms_refit", C.c_double), ("ms_total", C.c_double)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def declared_functions() -> list:
+    """Names of the functions include/sdint.h declares."""
+    text = open(_HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sdi_[a-z_0-9]+)\s*\(", text)))
+
+
+def load_library():
+    """Load libsdint.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is not built; run __graft_entry__.build() first")
+    try:
+        import torch  # noqa: F401  (its HIP runtime is the one the library binds to)
+    except ImportError:
+        pass
+    lib = C.CDLL(_LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    sig = {
+        "sdi_ctx_create": (C.c_int, [C.c_int, vp, C.POINTER(vp)]),
+        "sdi_ctx_destroy": (None, [vp]),
+        "sdi_last_error": (C.c_char_p, [vp]),
+        "sdi_device_info": (C.c_int, [vp, C.c_char_p, C.c_size_t]),
+        "sdi_set_param": (C.c_int, [vp, C.c_char_p, C.c_char_p]),
+        "sdi_get_param": (C.c_int, [vp, C.c_char_p, C.c_char_p, C.c_size_t]),
+        "sdi_prefactor_feynman": (C.c_int, [i32, C.POINTER(i32), i32, i32, i32, C.POINTER(i32), dp]),
+        "sdi_lattice_vector": (C.c_int, [i32, i32, C.POINTER(C.c_uint32)]),
+        "sdi_problem_create": (C.c_int, [vp, C.POINTER(ProblemDesc), C.POINTER(vp)]),
+        "sdi_problem_destroy": (None, [vp]),
+        "sdi_problem_norders": (C.c_int, [vp]),
+        "sdi_workspace_bytes": (C.c_size_t, [vp, vp]),
+        "sdi_integrate": (C.c_int, [vp, vp, vp, C.c_size_t, C.POINTER(Result)]),
+        "sdi_sector_results": (C.c_int, [vp, vp, i32, dp, dp, dp, C.POINTER(i64)]),
+        "sdi_evaluate": (C.c_int, [vp, vp, i32, vp, i64, vp]),
+        "sdi_sample_points": (C.c_int, [vp, vp, i32, i32, i64, i64, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, ctx=None, allow=()):
+    if rc != 0 and rc not in allow:
+        msg = load_library().sdi_last_error(ctx).decode() if ctx else ""
+        raise SdiError(rc, msg)
+    return rc
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+# ---------------------------------------------------------------- context
+
+def sdi_ctx_create(device: int = 0, stream: Optional[int] = None):
+    """Context on `device`; stream defaults to torch's current stream on it."""
+    lib = load_library()
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream(device).cuda_stream
+    h = C.c_void_p()
+    _check(lib.sdi_ctx_create(device, C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def sdi_ctx_destroy(ctx):
+    load_library().sdi_ctx_destroy(ctx)
+
+
+def sdi_last_error(ctx) -> str:
+    return load_library().sdi_last_error(ctx).decode()
+
+
+def sdi_device_info(ctx) -> str:
+    buf = C.create_string_buffer(512)
+    _check(load_library().sdi_device_info(ctx, buf, 512), ctx)
+    return buf.value.decode()
+
+
+def sdi_set_param(ctx, key: str, value):
+    _check(load_library().sdi_set_param(ctx, key.encode(), str(value).encode()), ctx)
+
+
+def sdi_get_param(ctx, key: str) -> str:
+    buf = C.create_string_buffer(64)
+    _check(load_library().sdi_get_param(ctx, key.encode(), buf, 64), ctx)
+    return buf.value.decode()
+
+
+def sdi_prefactor_feynman(loops: int, indices, d0: int, length: int):
+    idx = np.ascontiguousarray(indices, dtype=np.int32)
+    out = np.zeros(length)
+    lead = C.c_int32()
+    _check(load_library().sdi_prefactor_feynman(loops, idx.ctypes.data_as(C.POINTER(C.c_int32)), len(idx), d0,
+                                                length, C.byref(lead), _dptr(out)))
+    return int(lead.value), out
+
+
+def sdi_lattice_vector(m: int, dims: int) -> np.ndarray:
+    out = np.zeros(dims, dtype=np.uint32)
+    _check(load_library().sdi_lattice_vector(m, dims, out.ctypes.data_as(C.POINTER(C.c_uint32))))
+    return out
+
+
+# ---------------------------------------------------------------- problem
+
+def _prefactor_of(problem):
+    """Prefactor series of a sectorgen.Problem (explicit, or expanded by the library)."""
+    if problem.feynman is None:
+        p = np.asarray(problem.pref, dtype=np.complex128)
+        return problem.pref_lead, p.real.copy(), p.imag.copy()
+    f = problem.feynman
+    lead, _ = sdi_prefactor_feynman(f.loops, f.indices, f.d0, 1)
+    max_s = max(int(np.sum(s.a == -1.0)) for s in problem.sectors)
+    length = max(1, problem.order_max - lead + max_s + 1)
+    lead, ser = sdi_prefactor_feynman(f.loops, f.indices, f.d0, length)
+    return lead, ser, np.zeros_like(ser)
+
+
+def sdi_problem_create(ctx, problem):
+    """Compile a sectorgen.Problem into the library (copies every input)."""
+    keep = []
+    descs = (SectorDesc * len(problem.sectors))()
+    for i, s in enumerate(problem.sectors):
+        a = np.ascontiguousarray(s.a, dtype=np.float64)
+        b = np.ascontiguousarray(s.b, dtype=np.float64)
+        nt = np.array([len(f.coef) for f in s.factors], dtype=np.int32)
+        g = np.array([f.gamma for f in s.factors], dtype=np.float64)
+        d = np.array([f.delta for f in s.factors], dtype=np.float64)
+        coef = np.ascontiguousarray(np.concatenate([f.coef for f in s.factors]) if s.factors else np.zeros(0))
+        exps = np.ascontiguousarray(np.concatenate([f.exps for f in s.factors]).astype(np.uint8)
+                                    if s.factors else np.zeros((0, s.n), np.uint8))
+        dm = (np.ascontiguousarray(s.deform_mono, dtype=np.int32) if s.deform_mono is not None else None)
+        keep += [a, b, nt, g, d, coef, exps, dm]
+        c = complex(s.coeff)
+        descs[i] = SectorDesc(
+            s.n, len(s.factors), s.deform_factor, 0, c.real, c.imag, _dptr(a), _dptr(b),
+            dm.ctypes.data_as(C.POINTER(C.c_int32)) if dm is not None else None,
+            nt.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(g), _dptr(d), _dptr(coef),
+            exps.ctypes.data_as(C.POINTER(C.c_uint8)))
+    lead, pre, pim = _prefactor_of(problem)
+    pre = np.ascontiguousarray(pre, dtype=np.float64)
+    pim = np.ascontiguousarray(pim, dtype=np.float64)
+    keep += [pre, pim]
+    pd = ProblemDesc(len(problem.sectors), descs, problem.order_min, problem.order_max, lead, len(pre),
+                     _dptr(pre), _dptr(pim), int(problem.complex_mode), float(problem.lam))
+    h = C.c_void_p()
+    _check(load_library().sdi_problem_create(ctx, C.byref(pd), C.byref(h)), ctx)
+    return h
+
+
+def sdi_problem_destroy(prob):
+    load_library().sdi_problem_destroy(prob)
+
+
+def sdi_problem_norders(prob) -> int:
+    return int(load_library().sdi_problem_norders(prob))
+
+
+def sdi_workspace_bytes(ctx, prob) -> int:
+    return int(load_library().sdi_workspace_bytes(ctx, prob))
+
+
+# ---------------------------------------------------------------- integrate
+
+def sdi_integrate(ctx, prob, workspace=None) -> dict:
+    """Run the integrator; `workspace` is an optional torch uint8 cuda tensor."""
+    K = sdi_problem_norders(prob)
+    arrs = [np.zeros(K) for _ in range(4)]
+    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0)
+    ptr, nbytes = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()), workspace.numel())
+    rc = _check(load_library().sdi_integrate(ctx, prob, ptr, nbytes, C.byref(res)), ctx, allow=(-5,))
+    return {"status": rc, "order_min": res.order_min, "value": arrs[0] + 1j * arrs[1],
+            "err_re": arrs[2], "err_im": arrs[3], "n_evals": res.n_evals, "n_nonfinite": res.n_nonfinite,
+            "n_imf_positive": res.n_imf_positive, "ms_final": res.ms_sample_eval_reduce,
+            "ms_warmup": res.ms_refit, "ms_total": res.ms_total}
+
+
+def sdi_sector_results(ctx, prob, s: int, nshifts: int):
+    K = sdi_problem_norders(prob)
+    mean = np.zeros((K, 2))
+    err = np.zeros((K, 2))
+    per = np.zeros((nshifts, K, 2))
+    nev = C.c_int64()
+    _check(load_library().sdi_sector_results(ctx, prob, s, _dptr(mean), _dptr(err), _dptr(per), C.byref(nev)), ctx)
+    return mean[:, 0] + 1j * mean[:, 1], err, per[..., 0] + 1j * per[..., 1], int(nev.value)
+
+
+def sdi_evaluate(ctx, prob, s: int, x):
+    """x: torch float64 cuda tensor (npts, n); returns a cuda tensor (npts, K, 2)."""
+    import torch
+    K = sdi_problem_norders(prob)
+    x = x.contiguous()
+    out = torch.empty((x.shape[0], K, 2), dtype=torch.float64, device=x.device)
+    _check(load_library().sdi_evaluate(ctx, prob, s, C.c_void_p(x.data_ptr()), x.shape[0],
+                                       C.c_void_p(out.data_ptr())), ctx)
+    return out
+
+
+def sdi_sample_points(ctx, prob, s: int, shift: int, i0: int, npts: int, nvars: int, device=0):
+    import torch
+    x = torch.empty((npts, nvars), dtype=torch.float64, device=f"cuda:{device}")
+    w = torch.empty((npts,), dtype=torch.float64, device=f"cuda:{device}")
+    _check(load_library().sdi_sample_points(ctx, prob, s, shift, i0, npts, C.c_void_p(x.data_ptr()),
+                                            C.c_void_p(w.data_ptr())), ctx)
+    return x, w

@@ -1,0 +1,36 @@
+// Explicit-point evaluation (justEvaluate) and dispatch of the tile kernel families.
+#include "kernels.h"
+#include "tiles_real.hpp"
+
+namespace sdi {
+
+int launch_tiles_real_nv4(int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv8(int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv16(int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int occupancy_tiles_real_nv4(int ppt, int km, size_t shmem);
+int occupancy_tiles_real_nv8(int ppt, int km, size_t shmem);
+int occupancy_tiles_real_nv16(int ppt, int km, size_t shmem);
+
+int launch_tiles_real(int nvmax, int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st) {
+  if (nvmax <= 4) return launch_tiles_real_nv4(ppt, km, grid, shmem, a, st);
+  if (nvmax <= 8) return launch_tiles_real_nv8(ppt, km, grid, shmem, a, st);
+  return launch_tiles_real_nv16(ppt, km, grid, shmem, a, st);
+}
+
+int tiles_real_occupancy(int nvmax, int ppt, int km, size_t shmem) {
+  if (nvmax <= 4) return occupancy_tiles_real_nv4(ppt, km, shmem);
+  if (nvmax <= 8) return occupancy_tiles_real_nv8(ppt, km, shmem);
+  return occupancy_tiles_real_nv16(ppt, km, shmem);
+}
+
+int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st) {
+  if (a.npts <= 0) return 0;
+  const unsigned g = (unsigned)((a.npts + BLOCK - 1) / BLOCK);
+  if (km == 4)
+    k_eval_points_real<4><<<dim3(g), dim3(BLOCK), 0, st>>>(a);
+  else
+    k_eval_points_real<8><<<dim3(g), dim3(BLOCK), 0, st>>>(a);
+  return (int)hipGetLastError();
+}
+
+}  // namespace sdi

@@ -1,0 +1,360 @@
+// Real-mode sector-integrand evaluation on gfx950: device building blocks.
+//
+// One wave evaluates 64 x PPT points of one sector at a time.  Everything that
+// depends on the sector (term lists, exponents, gamma/delta, fold matrix) is
+// read from the SecDev record and the Term tables with wave-uniform scalar
+// loads, so it lands in SGPRs; per-point data (x, powers, logs, series) stays
+// in VGPRs.  The method (pole subtraction at x_j = 0 and eps expansion of
+// x^(b eps) and P^(delta eps) into log powers; paper section 1 and eq. (2))
+// is evaluated per corner W of the singular set S:
+//   G0_W = prod_m P_m(x^(W))^gamma_m,  Lambda_W = sum_m delta_m ln P_m(x^(W)),
+//   f_k += (-1)^|W\T| prod_{T} 1/b prod_{S\T} 1/x_j G0_W (L_T + Lambda_W)^q / q!,
+// q = k + |T|, with L_T = sum_{j in S\T} b_j ln x_j + sum_{j not in S} b_j ln x_j,
+// then F_k = mono * sum fold[k][kk] f_kk carries c_s and the prefactor series.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sdint_internal.h"
+
+namespace sdi {
+
+// --------------------------------------------------------------- compensated sums
+
+// Knuth's branch-free two-sum: s + v = t + err exactly.
+__device__ __forceinline__ void two_sum_acc(double& s, double& c, double v) {
+  const double t = s + v;
+  const double bp = t - s;
+  const double err = (s - (t - bp)) + (v - bp);
+  s = t;
+  c += err;
+}
+
+// (hi, lo) += (h2, l2) as double-double.
+__device__ __forceinline__ void dd_add(double& hi, double& lo, double h2, double l2) {
+  const double s = hi + h2;
+  const double bp = s - hi;
+  const double e = (hi - (s - bp)) + (h2 - bp);
+  const double l = lo + l2 + e;
+  hi = s + l;
+  lo = l - (hi - s);
+}
+
+// --------------------------------------------------------------- sampling
+
+// Shifted rank-1 lattice coordinate, exact: U = (i * (z << (53-m)) + D) mod 2^53.
+__device__ __forceinline__ double lattice_coord(uint64_t i, uint64_t zp, uint64_t d) {
+  const uint64_t u = (i * zp + d) & MASK53;
+  return (double)u * 0x1p-53;
+}
+
+// Tent map u -> 2u (u < 1/2), 2(1-u) otherwise: exact in fp64.
+__device__ __forceinline__ double tent(double u) {
+  return u < 0.5 ? 2.0 * u : 2.0 * (1.0 - u);
+}
+
+// Vegas map of one coordinate, no contraction so that the host reference
+// arithmetic (one rounding per operation) is reproduced bit for bit.
+__device__ __forceinline__ double vegas_coord(const double* __restrict__ g, int nb, double u,
+                                              double& w) {
+#pragma clang fp contract(off)
+  const double un = u * (double)nb;
+  int b = (int)un;
+  b = b > nb - 1 ? nb - 1 : b;
+  const double d = un - (double)b;
+  const double lo = g[b];
+  const double width = g[b + 1] - lo;
+  const double prod = d * width;
+  w = w * ((double)nb * width);
+  return lo + prod;
+}
+
+// Points i = i_first .. i_first+PPT-1 (consecutive lattice indices) of one sector and shift.
+// Writes x in internal variable order and the Vegas weight; also the bins (warm-up).
+template <int NV, int PPT>
+__device__ __forceinline__ void make_points(const SecDev* __restrict__ S, const uint64_t* __restrict__ zp,
+                                            const uint64_t* __restrict__ sh, const double* __restrict__ lgrid,
+                                            uint64_t i_first, double (&x)[PPT][NV], double (&w)[PPT],
+                                            int (&bins)[PPT][NV]) {
+  const int n = S->n;
+  const int flags = S->flags;
+  const int nb = S->nbins;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) w[p] = 1.0;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    if (j < n) {
+      const int oj = S->perm[j];
+      const uint64_t z = zp[oj];
+      const uint64_t d = sh[oj];
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        double u = lattice_coord(i_first + (uint64_t)p, z, d);
+        if (flags & F_BAKER) u = tent(u);
+        if (flags & F_USE_GRID) {
+          const double un = u * (double)nb;
+          int b = (int)un;
+          bins[p][j] = b > nb - 1 ? nb - 1 : b;
+          u = vegas_coord(lgrid + oj * (nb + 1), nb, u, w[p]);
+        } else {
+          bins[p][j] = 0;
+        }
+        x[p][j] = u;
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        x[p][j] = 0.5;
+        bins[p][j] = 0;
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------- polynomials
+
+// sum_t coef_t prod_j x_j^e_tj over one term list, for PPT points.  The term
+// index is wave-uniform, so coef and the exponent word sit in SGPRs and every
+// exponent bit is a scalar branch; the empty asm keeps the compiler from
+// turning the skipped multiplies into per-lane selects.
+template <int NV, int PPT>
+__device__ __forceinline__ void poly_real(const Term* __restrict__ t, uint32_t cnt,
+                                          const double (&x)[PPT][NV], const double (&x2)[PPT][NV],
+                                          double (&out)[PPT]) {
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) out[p] = 0.0;
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const double c = t[i].coef;
+    const uint64_t e = t[i].exps;
+    double m[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) m[p] = c;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      if (e & (1ull << (4 * j))) {
+        asm volatile("" ::);
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) m[p] *= x[p][j];
+      }
+      if (e & (2ull << (4 * j))) {
+        asm volatile("" ::);
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) m[p] *= x2[p][j];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) out[p] += m[p];
+  }
+}
+
+// Mantissa in [0.5, 1) and binary exponent; non-positive values give NaN so that
+// logarithms of non-positive factors stay NaN in real mode.
+__device__ __forceinline__ double mant_exp(double v, int& e) {
+  const double m = frexp(v, &e);
+  return v > 0.0 ? m : __builtin_nan("");
+}
+
+// G0 and Lambda at corner W for PPT points.
+template <int NV, int PPT>
+__device__ __forceinline__ void corner_regular(const SecDev* __restrict__ S, const Term* __restrict__ terms,
+                                               int W, const double (&x)[PPT][NV],
+                                               const double (&x2)[PPT][NV], double (&g0)[PPT],
+                                               double (&lam)[PPT]) {
+  const int nfac = S->nfac;
+  const int flags = S->flags;
+  if (flags & F_INT_POW) {
+    double num[PPT], den[PPT], mnum[PPT], mden[PPT];
+    int esum[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      num[p] = 1.0; den[p] = 1.0; mnum[p] = 1.0; mden[p] = 1.0; esum[p] = 0;
+    }
+#pragma unroll
+    for (int fm = 0; fm < MAXF; ++fm) {
+      if (fm < nfac) {
+        double P[PPT];
+        poly_real<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, x2, P);
+        const int g = S->gam_int[fm];
+        const int d = S->del_int[fm];
+        const int ga = g < 0 ? -g : g;
+        const int da = d < 0 ? -d : d;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          int e;
+          const double mt = mant_exp(P[p], e);
+          double pg = 1.0, md = 1.0;
+          for (int k = 0; k < ga; ++k) pg *= P[p];
+          for (int k = 0; k < da; ++k) md *= mt;
+          if (g >= 0) num[p] *= pg; else den[p] *= pg;
+          if (d >= 0) mnum[p] *= md; else mden[p] *= md;
+          esum[p] += d * e;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      g0[p] = num[p] / den[p];
+      lam[p] = log(mnum[p] / mden[p]) + (double)esum[p] * 0.69314718055994530942;
+    }
+  } else {
+    double lg[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) { lg[p] = 0.0; lam[p] = 0.0; }
+#pragma unroll
+    for (int fm = 0; fm < MAXF; ++fm) {
+      if (fm < nfac) {
+        double P[PPT];
+        poly_real<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, x2, P);
+        const double gm = S->gam[fm];
+        const double dm = S->del[fm];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          const double l = log(P[p]);
+          lg[p] += gm * l;
+          lam[p] += dm * l;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) g0[p] = exp(lg[p]);
+  }
+}
+
+// Adds t_q = base z^q / q! to f[OFF + q] for the orders the sector keeps.
+template <int OFF, int KM>
+__device__ __forceinline__ void add_series(double (&f)[KM], double t, double z, int kf) {
+#pragma unroll
+  for (int kk = OFF; kk < KM; ++kk) {
+    if (kk < kf) {
+      f[kk] += t;
+      t = t * z * (1.0 / (double)(kk - OFF + 1));
+    }
+  }
+}
+
+// f_kk (kk = k + ns, k = -ns .. kf-1-ns) of one sector at PPT points, times the
+// non-singular monomial.  Internal variables 0..ns-1 are the singular ones.
+// Corners W and subsets T of S are wave-uniform runtime loops; the offset of
+// q = 0 in f (ns - |T|) selects one of MAXS+1 static accumulation bodies.
+template <int NV, int PPT, int KM>
+__device__ __forceinline__ void eval_f_real(const SecDev* __restrict__ S, const Term* __restrict__ terms,
+                                            const double (&x)[PPT][NV], double (&f)[PPT][KM]) {
+  const int n = S->n;
+  const int ns = S->ns;
+  const int kf = S->kf;
+  const int flags = S->flags;
+  double x2[PPT][NV];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) x2[p][j] = x[p][j] * x[p][j];
+
+  double lx[PPT][MAXS], ix[PPT][MAXS];
+#pragma unroll
+  for (int i = 0; i < MAXS; ++i) {
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      lx[p][i] = 0.0;
+      ix[p][i] = 1.0;
+    }
+    if (i < ns && i < NV) {
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        lx[p][i] = log(x[p][i < NV ? i : 0]);
+        ix[p][i] = 1.0 / x[p][i < NV ? i : 0];
+      }
+    }
+  }
+
+  // L_rest = sum_{j >= ns} b_j ln x_j and the monomial prod_{j >= ns} x_j^a_j
+  double lrest[PPT], mono[PPT];
+  if (flags & F_INT_MONO) {
+    double pn[PPT], pd[PPT];
+    int es[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) { pn[p] = 1.0; pd[p] = 1.0; es[p] = 0; mono[p] = 1.0; }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      if (j >= ns && j < n) {
+        const int bj = S->b_int[j];
+        const int aj = S->a_int[j];
+        const int ba = bj < 0 ? -bj : bj;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          int e;
+          const double mt = frexp(x[p][j], &e);
+          double q = 1.0;
+          for (int k = 0; k < ba; ++k) q *= mt;
+          if (bj >= 0) pn[p] *= q; else pd[p] *= q;
+          es[p] += bj * e;
+          for (int k = 0; k < aj; ++k) mono[p] *= x[p][j];
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PPT; ++p)
+      lrest[p] = log(pn[p] / pd[p]) + (double)es[p] * 0.69314718055994530942;
+  } else {
+    double la[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) { lrest[p] = 0.0; la[p] = 0.0; }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      if (j >= ns && j < n) {
+        const double bj = S->b[j];
+        const double aj = S->a[j];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          const double l = log(x[p][j]);
+          lrest[p] += bj * l;
+          la[p] += aj * l;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) mono[p] = exp(la[p]);
+  }
+
+#pragma unroll
+  for (int p = 0; p < PPT; ++p)
+#pragma unroll
+    for (int k = 0; k < KM; ++k) f[p][k] = 0.0;
+
+  const int C = 1 << ns;
+  for (int W = 0; W < C; ++W) {
+    double g0[PPT], lam[PPT];
+    corner_regular<NV, PPT>(S, terms, W, x, x2, g0, lam);
+    for (int T = W;; T = (T - 1) & W) {
+      const int nt = __builtin_popcount(T);
+      const int off = ns - nt;
+      const double ib = S->invb[T];
+      const double sgn = (__builtin_popcount(W & ~T) & 1) ? -ib : ib;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        double coef = sgn * g0[p];
+        double z = lrest[p] + lam[p];
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) {
+          if (i < ns && !((T >> i) & 1)) {
+            coef *= ix[p][i];
+            z += S->bS[i] * lx[p][i];
+          }
+        }
+        switch (off) {
+          case 0: add_series<0, KM>(f[p], coef, z, kf); break;
+          case 1: add_series<1, KM>(f[p], coef, z, kf); break;
+          case 2: add_series<2, KM>(f[p], coef, z, kf); break;
+          case 3: add_series<3, KM>(f[p], coef, z, kf); break;
+          default: add_series<4, KM>(f[p], coef, z, kf); break;
+        }
+      }
+      if (T == 0) break;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PPT; ++p)
+#pragma unroll
+    for (int k = 0; k < KM; ++k) f[p][k] *= mono[p];
+}
+
+}  // namespace sdi

@@ -1,0 +1,65 @@
+// Host-side declarations of libsdint: context, compiled problem, helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sdint.h"
+#include "sdint_internal.h"
+
+namespace sdi {
+
+struct Params {
+  int m = 16;            // lattice_log2
+  int R = 16;            // shifts
+  uint64_t seed = 1;
+  int baker = 1;
+  int warmup = 0;
+  int mw = 14;           // warmup_log2
+  int nbins = 128;
+  int tile_log2 = 14;
+  int ppt = 0;           // 0: autotune
+  int tune = 1;          // 0 off, 1 cached, 2 search
+};
+
+const std::vector<uint32_t>& lattice_vector16(int m);
+int prefactor_series(int loops, const int32_t* idx, int nprops, int d0, int len, int* lead, double* out,
+                     std::string& err);
+
+}  // namespace sdi
+
+struct sdi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  sdi::Params params;
+  hipDeviceProp_t prop{};
+  int ncu = 0;
+  std::vector<std::pair<std::string, int>> tune_cache;   // key -> ppt
+};
+
+struct sdi_problem {
+  sdi_ctx* ctx = nullptr;
+  int nsec = 0, K = 0, order_min = 0, kfmax = 0, nvmax = 4, complex_mode = 0;
+  double lambda = 0.0;
+  std::vector<sdi::SecDev> secs;      // host copy (updated per integrate)
+  std::vector<sdi::Term> terms;
+  std::vector<double> cost;           // relative cost per point of each sector
+  sdi::SecDev* d_secs = nullptr;
+  sdi::Term* d_terms = nullptr;
+  double* d_grids = nullptr;          // persistent Vegas grids
+  size_t grid_doubles = 0;
+  int grid_nbins = 0;
+  bool grid_valid = false;
+  void* d_ws = nullptr;               // library-owned workspace
+  size_t ws_size = 0;
+  // results of the last integrate
+  int last_R = 0;
+  bool have_results = false;
+  std::vector<double> sec_stats;      // [nsec][KMAX][4]
+  std::vector<double> per_shift;      // [nsec*R][KMAX][2]
+  std::vector<int64_t> sec_evals;
+};

@@ -1,0 +1,347 @@
+// Small kernels around the tile pass: Philox shifts, fixed-order reductions of
+// tile partials, per-sector estimates and their combination, Vegas histogram
+// reduction and grid refit, and the point-sampling hook.
+#include <hip/hip_runtime.h>
+
+#include "eval_real.hpp"
+#include "kernels.h"
+
+namespace sdi {
+
+// ------------------------------------------------------------ fill (graph-safe zeroing)
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------ Philox4x32-10 shifts
+
+__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c[0];
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2];
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0;
+    const uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// D_{s,r,j}: 53 bits (word0 << 21 | word1 >> 11) of Philox(key = seed, counter =
+// (j, r, s, t)), redrawn (t = 1, 2, ...) while D is a multiple of 2^(53-m).
+__global__ void k_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t seed,
+                         uint64_t* shifts) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nsec * rows * MAXV) return;
+  const int j = (int)(gid % MAXV);
+  const int r = (int)((gid / MAXV) % rows);
+  const int s = (int)(gid / ((int64_t)MAXV * rows));
+  const SecDev& S = secs[s];
+  uint64_t* out = shifts + ((size_t)S.shift_row + r) * MAXV + j;
+  if (j >= S.n) {
+    *out = 0;
+    return;
+  }
+  const int m = r < nfinal ? S.m : S.mw;
+  const uint64_t mod = 1ull << (53 - m);
+  uint64_t d = 1;
+  for (uint32_t t = 0; t < 64u; ++t) {
+    uint32_t c[4] = {(uint32_t)j, (uint32_t)r, (uint32_t)S.sector, t};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t v = (((uint64_t)c[0] << 21) | ((uint64_t)c[1] >> 11)) & MASK53;
+    if (v % mod != 0) {
+      d = v;
+      break;
+    }
+  }
+  *out = d;
+}
+
+// ------------------------------------------------------------ reductions
+
+// Per (sector, final shift): fixed-order double-double sums over the pair's
+// tiles of every internal order, Q_kk = sum / N, then the prefactor fold
+// Q_k = sum_kk fold[k][kk] Q_kk (linear, so it commutes with the sum).
+// out: [npairs][KMAX][2] = Q_re, Q_im.
+__global__ void k_reduce_pairs(const double* partial, const int32_t* pair_start, const int32_t* pair_sector,
+                               const SecDev* secs, int npairs, double* out) {
+  const int pr = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pr >= npairs) return;
+  const SecDev& S = secs[pair_sector[pr]];
+  const double N = (double)(1ull << S.m);
+  double qr[KMAX], qi[KMAX];
+  for (int kk = 0; kk < KMAX; ++kk) {
+    double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0;
+    for (int t = pair_start[pr]; t < pair_start[pr + 1]; ++t) {
+      const double* p = partial + ((size_t)t * KMAX + kk) * PART_STRIDE;
+      dd_add(hr, lr, p[0], p[1]);
+      dd_add(hi, li, p[2], p[3]);
+    }
+    qr[kk] = (hr + lr) / N;
+    qi[kk] = (hi + li) / N;
+  }
+  for (int k = 0; k < KMAX; ++k) {
+    double re = 0.0, im = 0.0;
+    if (k < S.K) {
+      for (int kk = 0; kk < KMAX; ++kk) {
+        re += S.fold_re[k][kk] * qr[kk] - S.fold_im[k][kk] * qi[kk];
+        im += S.fold_re[k][kk] * qi[kk] + S.fold_im[k][kk] * qr[kk];
+      }
+    }
+    out[((size_t)pr * KMAX + k) * 2] = re;
+    out[((size_t)pr * KMAX + k) * 2 + 1] = im;
+  }
+}
+
+// Per sector and order: mean over the R shifts and the shift-to-shift error
+// sigma^2 = sum_r (Q_r - mean)^2 / (R (R - 1)), real and imaginary apart.
+// out: [nsec][KMAX][4] = mean_re, mean_im, err_re, err_im.
+__global__ void k_sector_stats(const double* per_shift, int nsec, int R, double* out) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nsec * KMAX) return;
+  const int s = gid / KMAX;
+  const int k = gid % KMAX;
+  double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0;
+  for (int r = 0; r < R; ++r) {
+    const double* q = per_shift + (((size_t)s * R + r) * KMAX + k) * 2;
+    dd_add(hr, lr, q[0], 0.0);
+    dd_add(hi, li, q[1], 0.0);
+  }
+  const double mr = (hr + lr) / R;
+  const double mi = (hi + li) / R;
+  double vr = 0.0, vi = 0.0;
+  for (int r = 0; r < R; ++r) {
+    const double* q = per_shift + (((size_t)s * R + r) * KMAX + k) * 2;
+    vr += (q[0] - mr) * (q[0] - mr);
+    vi += (q[1] - mi) * (q[1] - mi);
+  }
+  const double den = R > 1 ? (double)R * (R - 1) : 1.0;
+  double* o = out + ((size_t)s * KMAX + k) * 4;
+  o[0] = mr;
+  o[1] = mi;
+  o[2] = R > 1 ? sqrt(vr / den) : 0.0;
+  o[3] = R > 1 ? sqrt(vi / den) : 0.0;
+}
+
+// Result_k = sum_s mean_{s,k}, err_k = sqrt(sum_s err_{s,k}^2), in sector order;
+// counts of non-finite values.  res: [KMAX][4]; counts: [2].
+__global__ void k_combine(const double* sec_stats, int nsec, const int32_t* nonfinite, int ntiles,
+                          double* res, int64_t* counts) {
+  const int k = threadIdx.x;
+  if (k < KMAX) {
+    double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0, er = 0.0, ei = 0.0;
+    for (int s = 0; s < nsec; ++s) {
+      const double* q = sec_stats + ((size_t)s * KMAX + k) * 4;
+      dd_add(hr, lr, q[0], 0.0);
+      dd_add(hi, li, q[1], 0.0);
+      er += q[2] * q[2];
+      ei += q[3] * q[3];
+    }
+    res[k * 4 + 0] = hr + lr;
+    res[k * 4 + 1] = hi + li;
+    res[k * 4 + 2] = sqrt(er);
+    res[k * 4 + 3] = sqrt(ei);
+  } else if (k == KMAX) {
+    int64_t nf = 0;
+    for (int t = 0; t < ntiles; ++t) nf += nonfinite[t];
+    counts[0] = nf;
+    counts[1] = 0;
+  }
+}
+
+// ------------------------------------------------------------ Vegas
+
+__global__ void k_grid_identity(const SecDev* secs, int nsec, double* grids) {
+  const int s = blockIdx.x;
+  if (s >= nsec) return;
+  const SecDev& S = secs[s];
+  const int nb = S.nbins;
+  for (int i = threadIdx.x; i < S.n * (nb + 1); i += blockDim.x) {
+    const int b = i % (nb + 1);
+    grids[S.grid_off + i] = (double)b / (double)nb;
+  }
+}
+
+// Sector histogram = sum of its warm-up tiles' histograms, in tile order.
+__global__ void k_hist_reduce(const double* hist, const int64_t* hist_off, const int32_t* sec_tile_start,
+                              const SecDev* secs, const int64_t* hsec_off, int nsec, int64_t total,
+                              const int64_t* hsec_prefix, double* hsec) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  // locate sector by binary search over hsec_prefix
+  int lo = 0, hi = nsec - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (hsec_prefix[mid] <= gid) lo = mid; else hi = mid - 1;
+  }
+  const int s = lo;
+  const int64_t e = gid - hsec_prefix[s];
+  double acc = 0.0;
+  for (int t = sec_tile_start[s]; t < sec_tile_start[s + 1]; ++t) acc += hist[hist_off[t] + e];
+  hsec[hsec_off[s] + e] = acc;
+  (void)secs;
+}
+
+// Lepage refit of one (sector, dimension): importance d_b = sum_k h_bk / H_k over
+// the internal orders k,
+// 3-point smoothing, compression m_b = ((r_b - 1)/ln r_b)^alpha, equal shares.
+__global__ void k_refit(const SecDev* secs, int nsec, const double* hsec, const int64_t* hsec_off,
+                        double* grids, double* tmp, double alpha) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nsec * MAXV) return;
+  const int s = gid / MAXV;
+  const int j = gid % MAXV;
+  const SecDev& S = secs[s];
+  if (j >= S.n) return;
+  const int nb = S.nbins;
+  const int K = S.kf;        // histogram rows are the internal eps orders f_kk
+  if (K <= 0) return;
+  const double* h = hsec + hsec_off[s] + (size_t)j * nb * K;
+  double H[KMAX];
+  bool any = false;
+  for (int k = 0; k < KMAX; ++k) {
+    H[k] = 0.0;
+    if (k < K)
+      for (int b = 0; b < nb; ++b) H[k] += h[(size_t)b * K + k];
+    if (H[k] > 0.0) any = true;
+  }
+  if (!any) return;
+  auto dval = [&](int b) {
+    double d = 0.0;
+    for (int k = 0; k < K; ++k)
+      if (H[k] > 0.0) d += h[(size_t)b * K + k] / H[k];
+    return d;
+  };
+  auto smooth = [&](int b) {
+    if (b == 0) return (dval(0) + dval(1)) / 2.0;
+    if (b == nb - 1) return (dval(nb - 2) + dval(nb - 1)) / 2.0;
+    return (dval(b - 1) + dval(b) + dval(b + 1)) / 3.0;
+  };
+  double tot = 0.0;
+  for (int b = 0; b < nb; ++b) tot += smooth(b);
+  auto mval = [&](int b) {
+    const double r = smooth(b) / tot;
+    if (r == 0.0) return 0.0;
+    if (fabs(r - 1.0) < 1e-12) return 1.0;
+    return pow((r - 1.0) / log(r), alpha);
+  };
+  double msum = 0.0;
+  for (int b = 0; b < nb; ++b) msum += mval(b);
+  const double share = msum / nb;
+  double* g = grids + S.grid_off + (size_t)j * (nb + 1);
+  double* o = tmp + S.grid_off + (size_t)j * (nb + 1);
+  double acc = 0.0;
+  int b = 0;
+  double mb = mval(0);
+  for (int k = 1; k < nb; ++k) {
+    const double t = k * share;
+    while (b < nb - 1 && acc + mb <= t) {
+      acc += mb;
+      ++b;
+      mb = mval(b);
+    }
+    double frac = mb > 0.0 ? (t - acc) / mb : 1.0;
+    frac = frac < 1.0 ? frac : 1.0;
+    o[k] = g[b] + frac * (g[b + 1] - g[b]);
+  }
+  for (int k = 1; k < nb; ++k) g[k] = o[k];
+  g[0] = 0.0;
+  g[nb] = 1.0;
+}
+
+// ------------------------------------------------------------ sampling hook
+
+__global__ void k_sample_points(SampleArgs A) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.npts) return;
+  const SecDev* S = A.sec;
+  const int n = S->n;
+  const int nb = S->nbins;
+  double w = 1.0;
+  for (int oj = 0; oj < n; ++oj) {
+    double u = lattice_coord(A.i0 + (uint64_t)i, A.zp[oj], A.shift[oj]);
+    if (S->flags & F_BAKER) u = tent(u);
+    if (S->flags & F_USE_GRID) u = vegas_coord(A.grid + (size_t)oj * (nb + 1), nb, u, w);
+    A.x[i * n + oj] = u;
+  }
+  if (A.w) A.w[i] = w;
+}
+
+// ------------------------------------------------------------ launchers
+
+#define SDI_CHECK(call)                    \
+  do {                                     \
+    hipError_t e_ = (call);                \
+    if (e_ != hipSuccess) return (int)e_;  \
+  } while (0)
+
+int launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return 0;
+  k_fill_i32<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(p, v, n);
+  return (int)hipGetLastError();
+}
+
+int launch_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t seed, uint64_t* shifts,
+                  hipStream_t st) {
+  const int64_t tot = (int64_t)nsec * rows * MAXV;
+  k_shifts<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st>>>(secs, nsec, rows, nfinal, seed, shifts);
+  return (int)hipGetLastError();
+}
+
+int launch_reduce_pairs(const double* partial, const int32_t* pair_start, const int32_t* pair_sector,
+                        const SecDev* secs, int npairs, double* out, hipStream_t st) {
+  k_reduce_pairs<<<dim3((npairs + 63) / 64), dim3(64), 0, st>>>(partial, pair_start, pair_sector, secs,
+                                                                npairs, out);
+  return (int)hipGetLastError();
+}
+
+int launch_sector_stats(const double* per_shift, int nsec, int R, double* out, hipStream_t st) {
+  const int tot = nsec * KMAX;
+  k_sector_stats<<<dim3((tot + 127) / 128), dim3(128), 0, st>>>(per_shift, nsec, R, out);
+  return (int)hipGetLastError();
+}
+
+int launch_combine(const double* sec_stats, int nsec, const int32_t* nonfinite, int ntiles, double* res,
+                   int64_t* counts, hipStream_t st) {
+  k_combine<<<dim3(1), dim3(64), 0, st>>>(sec_stats, nsec, nonfinite, ntiles, res, counts);
+  return (int)hipGetLastError();
+}
+
+int launch_grid_identity(const SecDev* secs, int nsec, double* grids, hipStream_t st) {
+  k_grid_identity<<<dim3(nsec), dim3(256), 0, st>>>(secs, nsec, grids);
+  return (int)hipGetLastError();
+}
+
+int launch_hist_reduce(const double* hist, const int64_t* hist_off, const int32_t* sec_tile_start,
+                       const SecDev* secs, const int64_t* hsec_off, int nsec, int64_t total,
+                       const int64_t* hsec_prefix, double* hsec, hipStream_t st) {
+  if (total <= 0) return 0;
+  k_hist_reduce<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st>>>(
+      hist, hist_off, sec_tile_start, secs, hsec_off, nsec, total, hsec_prefix, hsec);
+  return (int)hipGetLastError();
+}
+
+int launch_refit(const SecDev* secs, int nsec, const double* hsec, const int64_t* hsec_off, double* grids,
+                 double* tmp, double alpha, hipStream_t st) {
+  const int tot = nsec * MAXV;
+  k_refit<<<dim3((tot + 63) / 64), dim3(64), 0, st>>>(secs, nsec, hsec, hsec_off, grids, tmp, alpha);
+  return (int)hipGetLastError();
+}
+
+int launch_sample_points(const SampleArgs& a, hipStream_t st) {
+  if (a.npts <= 0) return 0;
+  k_sample_points<<<dim3((unsigned)((a.npts + 255) / 256)), dim3(256), 0, st>>>(a);
+  return (int)hipGetLastError();
+}
+
+}  // namespace sdi

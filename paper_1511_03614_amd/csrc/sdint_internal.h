@@ -1,0 +1,111 @@
+// Internal layout shared by the host compiler (api.cpp) and the HIP kernels.
+//
+// A compiled problem lives in device memory as:
+//   SecDev[nsec]      one record per sector, read by the kernels with
+//                     wave-uniform scalar loads (the "sector tape");
+//   Term[]            polynomial terms, one contiguous list per
+//                     (sector, factor, corner W), so the corner x_W = 0 of the
+//                     pole subtraction is a choice of list, not a branch;
+//   uint64 zp[][16]   lattice generating vector, pre-shifted by 53 - m;
+//   uint64 shift[][]  53-bit Philox shifts per (sector, shift, variable);
+//   double grid[]     Vegas grids, (n x (NB+1)) per sector.
+// Inside a sector record the variables are reordered so that the singular
+// variables (a_j = -1) come first; perm[] maps back to the caller's order so
+// that point coordinates, shifts and grids stay attached to the caller's
+// variable j.
+#pragma once
+#include <stdint.h>
+
+namespace sdi {
+
+constexpr int MAXV = 16;     // variables per sector
+constexpr int MAXF = 4;      // regular factors per sector
+constexpr int MAXS = 4;      // singular variables per sector
+constexpr int MAXC = 16;     // corners 2^MAXS
+constexpr int KMAX = 8;      // result orders and internal f orders
+constexpr int NBMAX = 256;   // Vegas bins per dimension
+constexpr int BLOCK = 256;   // threads per block of the tile kernels
+constexpr uint64_t MASK53 = (1ull << 53) - 1;
+
+// Polynomial term: coefficient and packed exponents, one nibble per variable:
+// bit 0 multiplies by x, bit 1 by x^2, bit 2 by x^4.
+struct alignas(16) Term {
+  double coef;
+  uint64_t exps;
+};
+
+enum SecFlags : int32_t {
+  F_HAS_IM = 1,        // fold coefficients have imaginary parts
+  F_INT_POW = 2,       // all gamma_m, delta_m integers: powers by products, one log per corner
+  F_INT_MONO = 4,      // non-singular a_j small non-negative integers, b_j integers |b| <= 8
+  F_USE_GRID = 8,      // Vegas map active
+  F_BAKER = 16,        // tent transform of the lattice
+};
+
+struct alignas(16) SecDev {
+  int32_t n, ns, nfac, kf;          // variables, singular variables, factors, f orders
+  int32_t K, flags, nvc, cls;       // result orders, SecFlags, variable class, kernel class
+  int32_t grid_off, shift_row, m, mw;  // grid offset (doubles), row of shift table, log2 N, warm-up log2 N
+  int32_t nbins, sector, pad0, pad1;
+  int32_t perm[MAXV];               // internal variable j = caller variable perm[j]
+  int32_t a_int[MAXV];              // integer a_j (F_INT_MONO)
+  int32_t b_int[MAXV];              // integer b_j (F_INT_MONO)
+  uint32_t tab_off[MAXF][MAXC];     // term list offset per (factor, corner)
+  uint32_t tab_cnt[MAXF][MAXC];
+  int32_t gam_int[MAXF], del_int[MAXF];
+  double gam[MAXF], del[MAXF];
+  double a[MAXV], b[MAXV];
+  double invb[MAXC];                // prod_{i in T} 1/b_{S_i} per subset mask T
+  double bS[MAXS];
+  double fold_re[KMAX][KMAX];       // F_k = mono * sum_kk fold[k][kk] f_kk
+  double fold_im[KMAX][KMAX];
+};
+
+struct alignas(16) TileDesc {
+  int32_t sector;
+  int32_t shift;      // row in the shift table (final shifts 0..R-1, warm-up R+it)
+  uint32_t i0;        // first lattice index
+  uint32_t count;     // points in the tile
+};
+
+// Per-tile partial sums per internal order f_kk (the prefactor fold is linear and
+// is applied after the reduction): hi/lo of sum w f (re), hi/lo (im).
+constexpr int PART_STRIDE = 4;      // doubles per order
+
+struct TileArgs {
+  const SecDev* secs;
+  const Term* terms;
+  const uint64_t* zp;        // [nsec][MAXV] generating vector << (53 - m) of this pass
+  const uint64_t* shifts;    // [rows][MAXV]
+  const double* grids;
+  const TileDesc* tiles;     // canonical order
+  const int32_t* order;      // processing order (LPT), indices into tiles
+  double* partial;           // [ntiles][KMAX][PART_STRIDE]
+  int32_t* nonfinite;        // [ntiles]
+  double* hist;              // warm-up histograms [ntiles][n*NB*K] or null
+  const int64_t* hist_off;   // per tile offset into hist (doubles)
+  int32_t* counter;          // work counter (zeroed by the launcher's fill kernel)
+  int32_t ntiles;
+  int32_t mode;              // 0 final pass, 1 warm-up (histograms)
+};
+
+struct EvalArgs {            // explicit points (justEvaluate / parity)
+  const SecDev* sec;
+  const Term* terms;
+  const double* x;           // [npts][n] caller variable order
+  double* out;               // [npts][K][2]
+  int64_t npts;
+};
+
+struct SampleArgs {
+  const SecDev* sec;
+  const uint64_t* zp;        // [MAXV] of this sector
+  const uint64_t* shift;     // [MAXV] row
+  const double* grid;
+  double* x;                 // [npts][n] caller order
+  double* w;                 // [npts] or null
+  uint64_t i0;
+  int64_t npts;
+};
+
+}  // namespace sdi

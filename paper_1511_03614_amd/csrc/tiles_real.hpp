@@ -1,0 +1,188 @@
+// Persistent multi-sector tile kernel (real mode).
+//
+// One launch covers every (sector, shift, index range) tile of a pass.  Blocks
+// take tiles from an atomic counter in longest-first order; the tile's sector
+// record selects, with a wave-uniform switch, the evaluator instance compiled
+// for its variable class and number of singular variables.  Each tile writes
+// its own partial sums (and, in warm-up, its own Vegas histogram), so the
+// result does not depend on which block ran which tile.
+#pragma once
+#include "eval_real.hpp"
+
+namespace sdi {
+
+template <int NV, int PPT, int KM>
+__device__ __forceinline__ void run_tile_real(const TileArgs& A, const SecDev* __restrict__ S,
+                                              const TileDesc& td, const double* __restrict__ lgrid,
+                                              double* __restrict__ lhist, double (&s)[KM],
+                                              double (&c)[KM], int& nonfin) {
+  const uint32_t step = (uint32_t)blockDim.x * PPT;
+  for (uint32_t off = threadIdx.x * PPT; off < td.count; off += step) {
+    // Re-read the sector record every iteration instead of pinning all of it in
+    // SGPRs for the whole tile (scalar loads are cheap and cached).
+    asm volatile("" ::: "memory");
+    const uint64_t* zp = A.zp + (size_t)td.sector * MAXV;
+    const uint64_t* sh = A.shifts + ((size_t)S->shift_row + td.shift) * MAXV;
+    double x[PPT][NV], w[PPT];
+    int bins[PPT][NV];
+    make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+    double f[PPT][KM];
+    eval_f_real<NV, PPT, KM>(S, A.terms, x, f);
+    const int kf = S->kf;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        const double v = w[p] * f[p][k];
+        two_sum_acc(s[k], c[k], v);
+        bad |= !isfinite(v);
+      }
+      nonfin += bad ? 1 : 0;
+      if (lhist) {
+        const int n = S->n;
+        const int nb = S->nbins;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (k < kf) {
+            const double v = w[p] * f[p][k];
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+              if (j < n) atomicAdd(&lhist[((size_t)S->perm[j] * nb + bins[p][j]) * kf + k], v * v);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int NVMAX, int PPT, int KM>
+__global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
+  extern __shared__ double smem[];
+  __shared__ int s_tile;
+  __shared__ int s_nonfin;
+  __shared__ double s_red[BLOCK / 64][KM][2];
+  constexpr int NVC = NVMAX <= 4 ? 0 : (NVMAX <= 8 ? 1 : 2);
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_tile = atomicAdd(A.counter, 1);
+      s_nonfin = 0;
+    }
+    __syncthreads();
+    const int ti = __builtin_amdgcn_readfirstlane(s_tile);
+    if (ti >= A.ntiles) return;
+    const int tc = A.order[ti];
+    const TileDesc td = A.tiles[tc];
+    const SecDev* S = A.secs + td.sector;
+    const int n = S->n;
+    const int nb = S->nbins;
+    const int kf = S->kf;
+    double* lgrid = nullptr;
+    double* lhist = nullptr;
+    size_t soff = 0;
+    if (S->flags & F_USE_GRID) {
+      lgrid = smem;
+      const double* g = A.grids + S->grid_off;
+      for (int i = threadIdx.x; i < n * (nb + 1); i += blockDim.x) lgrid[i] = g[i];
+      soff = (size_t)n * (nb + 1);
+    }
+    if (A.mode == 1) {
+      lhist = smem + soff;
+      for (int i = threadIdx.x; i < n * nb * kf; i += blockDim.x) lhist[i] = 0.0;
+    }
+    __syncthreads();
+
+    double s[KM], c[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) { s[k] = 0.0; c[k] = 0.0; }
+    int nonfin = 0;
+    const int cls = S->cls;
+    switch (cls) {
+      case 0:
+        run_tile_real<4, PPT, KM>(A, S, td, lgrid, lhist, s, c, nonfin);
+        break;
+      case 1:
+        if constexpr (NVC >= 1) run_tile_real<8, PPT, KM>(A, S, td, lgrid, lhist, s, c, nonfin);
+        break;
+      case 2:
+        if constexpr (NVC >= 2) run_tile_real<16, PPT, KM>(A, S, td, lgrid, lhist, s, c, nonfin);
+        break;
+      default:
+        break;
+    }
+
+    // block reduction: double-double sums over lanes, then over waves in order
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      double hi = s[k] + c[k];
+      double lo = c[k] - (hi - s[k]);
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double h2 = __shfl_xor(hi, o, 64);
+        const double l2 = __shfl_xor(lo, o, 64);
+        dd_add(hi, lo, h2, l2);
+      }
+      if (lane == 0) {
+        s_red[wave][k][0] = hi;
+        s_red[wave][k][1] = lo;
+      }
+    }
+    if (nonfin) atomicAdd(&s_nonfin, nonfin);
+    __syncthreads();
+    if (threadIdx.x < KM) {
+      const int k = threadIdx.x;
+      double hi = s_red[0][k][0], lo = s_red[0][k][1];
+      for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) dd_add(hi, lo, s_red[wv][k][0], s_red[wv][k][1]);
+      double* out = A.partial + ((size_t)tc * KMAX + k) * PART_STRIDE;
+      out[0] = hi;
+      out[1] = lo;
+      out[2] = 0.0;
+      out[3] = 0.0;
+    }
+    if (threadIdx.x == 0) A.nonfinite[tc] = s_nonfin;
+    if (A.mode == 1) {
+      double* gh = A.hist + A.hist_off[tc];
+      for (int i = threadIdx.x; i < n * nb * kf; i += blockDim.x) gh[i] = lhist[i];
+    }
+  }
+}
+
+// Values of every result order at caller points (justEvaluate, parity checks).
+template <int NV, int KM>
+__device__ __forceinline__ void eval_point_real(const EvalArgs& A, int64_t i) {
+  const SecDev* S = A.sec;
+  const int n = S->n;
+  const int K = S->K;
+  double x[1][NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) x[0][j] = j < n ? A.x[i * n + S->perm[j]] : 0.5;
+  double f[1][KM];
+  eval_f_real<NV, 1, KM>(S, A.terms, x, f);
+  for (int k = 0; k < K; ++k) {
+    double fr = 0.0, fi = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) {
+      fr += S->fold_re[k][kk] * f[0][kk];
+      fi += S->fold_im[k][kk] * f[0][kk];
+    }
+    A.out[(i * K + k) * 2] = fr;
+    A.out[(i * K + k) * 2 + 1] = fi;
+  }
+}
+
+template <int KM>
+__global__ void __launch_bounds__(BLOCK) k_eval_points_real(EvalArgs A) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.npts) return;
+  switch (A.sec->cls) {
+    case 0: eval_point_real<4, KM>(A, i); break;
+    case 1: eval_point_real<8, KM>(A, i); break;
+    case 2: eval_point_real<16, KM>(A, i); break;
+    default: break;
+  }
+}
+
+}  // namespace sdi
