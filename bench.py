@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark: sector-integrand evaluations per second on one MI355X.
+
+One step = one call of sdi_integrate on the synthetic 64-sector workload
+(3-6 variables, 4-20 terms per factor, up to 2 singular variables, orders
+eps^-2..eps^0): Vegas warm-up (5 iterations of 2^14 lattice points per sector,
+histograms and grid refit) followed by the frozen-grid pass over 16 shifted
+rank-1 lattices of 2^16 points per sector, the compensated reductions and the
+combination.  Inputs (compiled sector tables) are resident on the GPU before
+timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X: 256 CUs x 4 SIMD x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
+WORKLOAD = dict(lattice_log2=16, shifts=16, seed=1, warmup=5, warmup_log2=14, nbins=128, tile_log2=14)
+KERNEL_SOURCES = ["paper_1511_03614_amd/csrc/eval_real.hpp", "paper_1511_03614_amd/csrc/tiles_real.hpp",
+                  "paper_1511_03614_amd/csrc/sdint_internal.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def sector_work(sec, order_max: int, pref_lead: int, use_grid: bool):
+    """Algorithmic FP64 operations (add/sub/mul/div = 1, FMA = 2) and logarithms per evaluation.
+
+    Counts the arithmetic of the method as the tile kernel performs it: lattice
+    tent map and Vegas map, powers x^2, the polynomial terms of every corner
+    (one multiply per exponent bit, one add), integer powers of the factors,
+    the subtraction/series combination for every (corner, subset) pair, the
+    monomial and the weighted accumulation.  Logarithms are counted apart and
+    not as flops; integer work and compensation (two-sum) are not counted.
+    """
+    import numpy as np
+    n = sec.n
+    S = [j for j in range(n) if sec.a[j] == -1.0]
+    ns = len(S)
+    kf = max(0, order_max - pref_lead + ns + 1)
+    fl = 2 * n + (6 * n + 2 if use_grid else 0)
+    fl += n + 2 * ns
+    logs = ns + 1
+    fl += sum(abs(int(sec.b[j])) + int(sec.a[j]) for j in range(n) if j not in S) + 3
+    for W in range(1 << ns):
+        zero = [S[i] for i in range(ns) if W >> i & 1]
+        for fac in sec.factors:
+            alive = np.all(fac.exps[:, zero] == 0, axis=1) if zero else np.ones(len(fac.coef), bool)
+            e = fac.exps[alive].astype(np.int64)
+            fl += int(np.sum((e & 1) != 0) + np.sum((e & 2) != 0)) + int(alive.sum())
+            fl += abs(int(fac.gamma)) + abs(int(fac.delta))
+        fl += 4
+        logs += 1
+        for T in range(1 << ns):
+            if T & ~W:
+                continue
+            nt = bin(T).count("1")
+            fl += 1 + 3 * (ns - nt) + 3 * max(0, kf - (ns - nt))
+    fl += 3 * kf
+    return fl, logs
+
+
+def cpu_baseline(problem, m: int) -> dict:
+    """The oracle as it stands, on all sectors, one shift of 2^m lattice points each."""
+    import numpy as np
+    from oracle import integrand, integrate, points
+    lead, pref = integrate.prefactor_for(problem)
+    evals = 0
+    t0 = time.perf_counter()
+    for s, sec in enumerate(problem.sectors):
+        z = points.cbc_vector(m, sec.n)
+        sh = points.shift_table(1, s, 1, sec.n, m)[0]
+        x, w, _ = points.sector_points(z, m, sh, 0, 1 << m)
+        vals, _, _ = integrand.sector_orders(sec, x, problem.order_min, problem.order_max, lead, pref)
+        q = [integrate.fsum_c(v) for v in vals * w[None, :]]
+        evals += 1 << m
+        assert np.all(np.isfinite(q))
+    dt = time.perf_counter() - t0
+    return {"value": evals / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"all {len(problem.sectors)} sectors x 1 shift x 2^{m} lattice points "
+                      f"({evals} evals, {dt:.1f} s, numpy fp64 single thread)"}
+
+
+def traffic_from_profiles(ms_kernel: float):
+    """HBM bytes per launch of the tile kernel from the committed counter summary, if current."""
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.json")):
+        try:
+            d = json.load(open(path))
+        except (OSError, ValueError):
+            continue
+        if d.get("kernel_hash") == kernel_hash() and d.get("workload") == "synthetic64":
+            return d.get("bytes_per_launch")
+    return None
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-log2", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "sectors shard across GPUs as described in DESIGN.md, but no multi-GPU run is made.",
+              file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    import paper_1511_03614_amd as P
+    import sectorgen
+
+    problem = sectorgen.config2()
+    ctx = P.sdi_ctx_create(0)
+    for k, v in WORKLOAD.items():
+        P.sdi_set_param(ctx, k, v)
+    h = P.sdi_problem_create(ctx, problem)
+    for _ in range(args.warmup):
+        P.sdi_integrate(ctx, h)
+    torch.cuda.synchronize()
+    kms, evals = [], 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = P.sdi_integrate(ctx, h)
+        kms.append(r["ms_eval_kernel"])
+        evals += r["n_evals"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt / args.steps * 1e3
+    # roofline of the dominant kernel (final-pass tile kernel)
+    lead = problem.pref_lead
+    N = 1 << WORKLOAD["lattice_log2"]
+    R = WORKLOAD["shifts"]
+    fl_launch, logs_launch = 0, 0
+    for sec in problem.sectors:
+        fl, lg = sector_work(sec, problem.order_max, lead, use_grid=WORKLOAD["warmup"] > 0)
+        fl_launch += fl * R * N
+        logs_launch += lg * R * N
+    ms_k = float(np.mean(kms))
+    achieved = fl_launch / (ms_k * 1e-3) / 1e12
+    out = {
+        "metric": "sector-integrand evals/s (FP64) + error vs plain QMC at equal GPU time",
+        "value": evals / dt,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "synthetic64: 64 sectors, 3-6 variables, 4-20 terms per factor, "
+                               "|S| <= 2, orders eps^-2..eps^0; Vegas warm-up 5 x 2^14 points, "
+                               "final pass 16 shifts x 2^16 lattice points per sector",
+                   "evals_per_step": evals // args.steps, "points_per_thread": r["ppt"],
+                   "blocks": r["blocks"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": traffic_from_profiles(ms_k),
+                     "kernel": "k_tiles_real (final pass)", "ms_per_launch": ms_k,
+                     "flops_per_launch": fl_launch, "logs_per_s": logs_launch / (ms_k * 1e-3)},
+        "error_vs_plain_qmc": None,
+        "result": {"orders": list(range(problem.order_min, problem.order_max + 1)),
+                   "value": [float(v.real) for v in r["value"]], "err": [float(e) for e in r["err_re"]]},
+    }
+    P.sdi_problem_destroy(h)
+    P.sdi_ctx_destroy(ctx)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(problem, args.cpu_log2)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

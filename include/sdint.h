@@ -152,6 +152,9 @@ typedef struct {
   double ms_sample_eval_reduce; /* device time of the final pass                      */
   double ms_refit;              /* device time of the warm-up iterations and refits   */
   double ms_total;
+  double ms_eval_kernel;        /* device time of the final-pass tile kernel alone    */
+  int32_t points_per_thread;    /* launch configuration of that kernel                */
+  int32_t blocks;
 } sdi_result;
 
 /* Bytes of device workspace sdi_integrate needs under the current parameters. */

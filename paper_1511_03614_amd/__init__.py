@@ -63,7 +63,8 @@ class Result(C.Structure):
                 ("val_re", C.POINTER(C.c_double)), ("val_im", C.POINTER(C.c_double)),
                 ("err_re", C.POINTER(C.c_double)), ("err_im", C.POINTER(C.c_double)),
                 ("n_evals", C.c_int64), ("n_nonfinite", C.c_int64), ("n_imf_positive", C.c_int64),
-                ("ms_sample_eval_reduce", C.c_double), ("ms_refit", C.c_double), ("ms_total", C.c_double)]
+                ("ms_sample_eval_reduce", C.c_double), ("ms_refit", C.c_double), ("ms_total", C.c_double),
+                ("ms_eval_kernel", C.c_double), ("points_per_thread", C.c_int32), ("blocks", C.c_int32)]
 
 
 def library_path() -> str:
@@ -244,13 +245,14 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
     """Run the integrator; `workspace` is an optional torch uint8 cuda tensor."""
     K = sdi_problem_norders(prob)
     arrs = [np.zeros(K) for _ in range(4)]
-    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0)
+    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0)
     ptr, nbytes = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()), workspace.numel())
     rc = _check(load_library().sdi_integrate(ctx, prob, ptr, nbytes, C.byref(res)), ctx, allow=(-5,))
     return {"status": rc, "order_min": res.order_min, "value": arrs[0] + 1j * arrs[1],
             "err_re": arrs[2], "err_im": arrs[3], "n_evals": res.n_evals, "n_nonfinite": res.n_nonfinite,
             "n_imf_positive": res.n_imf_positive, "ms_final": res.ms_sample_eval_reduce,
-            "ms_warmup": res.ms_refit, "ms_total": res.ms_total}
+            "ms_warmup": res.ms_refit, "ms_total": res.ms_total, "ms_eval_kernel": res.ms_eval_kernel,
+            "ppt": res.points_per_thread, "blocks": res.blocks}
 
 
 def sdi_sector_results(ctx, prob, s: int, nshifts: int):

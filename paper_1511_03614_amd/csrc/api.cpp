@@ -228,7 +228,7 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P) {
   }
   // persistent grids live with the problem
   if (pb->grid_doubles < goff || pb->grid_nbins != prm.nbins) {
-    if (pb->d_grids) hipFree(pb->d_grids);
+    if (pb->d_grids) (void)hipFree(pb->d_grids);
     pb->d_grids = nullptr;
     pb->grid_doubles = 0;
     pb->grid_valid = false;
@@ -287,7 +287,7 @@ int sdi_ctx_create(int device_ordinal, void* hip_stream, sdi_ctx** out) {
 
 void sdi_ctx_destroy(sdi_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 
@@ -559,10 +559,10 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
 
 void sdi_problem_destroy(sdi_problem* pb) {
   if (!pb) return;
-  if (pb->d_secs) hipFree(pb->d_secs);
-  if (pb->d_terms) hipFree(pb->d_terms);
-  if (pb->d_grids) hipFree(pb->d_grids);
-  if (pb->d_ws) hipFree(pb->d_ws);
+  if (pb->d_secs) (void)hipFree(pb->d_secs);
+  if (pb->d_terms) (void)hipFree(pb->d_terms);
+  if (pb->d_grids) (void)hipFree(pb->d_grids);
+  if (pb->d_ws) (void)hipFree(pb->d_ws);
   delete pb;
 }
 
@@ -592,7 +592,7 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
     if (ws_bytes < need) return fail(ctx, SDI_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
   } else {
     if (pb->ws_size < need) {
-      if (pb->d_ws) hipFree(pb->d_ws);
+      if (pb->d_ws) (void)hipFree(pb->d_ws);
       pb->d_ws = nullptr;
       pb->ws_size = 0;
       HIPCHK(ctx, hipMalloc(&pb->d_ws, need));
@@ -677,7 +677,12 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   F.ntiles = nft;
   F.mode = 0;
   const int gf = persistent_grid(ctx, pb->nvmax, ppt, km, P.shmem_final, nft);
+  hipEvent_t evk0, evk1;
+  HIPCHK(ctx, hipEventCreate(&evk0));
+  HIPCHK(ctx, hipEventCreate(&evk1));
+  HIPCHK(ctx, hipEventRecord(evk0, st));
   KCHK(ctx, launch_tiles_real(pb->nvmax, ppt, km, gf, P.shmem_final, F, st));
+  HIPCHK(ctx, hipEventRecord(evk1, st));
   KCHK(ctx, launch_reduce_pairs(P.d_partial, P.d_pair_start, P.d_pair_sector, pb->d_secs, npairs, P.d_per_shift, st));
   KCHK(ctx, launch_sector_stats(P.d_per_shift, nsec, prm.R, P.d_sec_stats, st));
   KCHK(ctx, launch_combine(P.d_sec_stats, nsec, P.d_nonfinite, nft, P.d_res, P.d_counts, st));
@@ -691,12 +696,11 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   HIPCHK(ctx, hipMemcpyAsync(pb->sec_stats.data(), P.d_sec_stats, pb->sec_stats.size() * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipMemcpyAsync(pb->per_shift.data(), P.d_per_shift, pb->per_shift.size() * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
-  float ms_w = 0.f, ms_f = 0.f;
-  hipEventElapsedTime(&ms_w, ev0, ev1);
-  hipEventElapsedTime(&ms_f, ev1, ev2);
-  hipEventDestroy(ev0);
-  hipEventDestroy(ev1);
-  hipEventDestroy(ev2);
+  float ms_w = 0.f, ms_f = 0.f, ms_k = 0.f;
+  (void)hipEventElapsedTime(&ms_w, ev0, ev1);
+  (void)hipEventElapsedTime(&ms_f, ev1, ev2);
+  (void)hipEventElapsedTime(&ms_k, evk0, evk1);
+  for (hipEvent_t e : {ev0, ev1, ev2, evk0, evk1}) (void)hipEventDestroy(e);
   pb->last_R = prm.R;
   pb->have_results = true;
   const int64_t per_sec = (int64_t)prm.R << prm.m;
@@ -715,6 +719,9 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   out->ms_sample_eval_reduce = ms_f;
   out->ms_refit = ms_w;
   out->ms_total = ms_w + ms_f;
+  out->ms_eval_kernel = ms_k;
+  out->points_per_thread = ppt;
+  out->blocks = gf;
   return counts[0] ? fail(ctx, SDI_ENONFINITE, "non-finite integrand values") : SDI_OK;
 }
 
@@ -793,8 +800,8 @@ int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* pbc, int32_t s, int32_t s
   A.npts = npts;
   if (e == 0) e = launch_sample_points(A, st);
   hipError_t he = hipStreamSynchronize(st);
-  hipFree(d_sh);
-  hipFree(d_zp);
+  (void)hipFree(d_sh);
+  (void)hipFree(d_zp);
   if (e != 0) return fail(ctx, SDI_EDEVICE, std::string("sample kernel: ") + hipGetErrorString((hipError_t)e));
   if (he != hipSuccess) return fail(ctx, SDI_EDEVICE, std::string("sample sync: ") + hipGetErrorString(he));
   return SDI_OK;
