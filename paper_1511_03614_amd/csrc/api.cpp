@@ -99,7 +99,8 @@ struct Plan {
   double* d_hsec = nullptr;
   int64_t* d_hsec_off = nullptr;
   int64_t* d_hsec_prefix = nullptr;
-  double* d_grid_tmp = nullptr;
+  int64_t* d_pair_nonfinite = nullptr;
+  int64_t* d_sec_nonfinite = nullptr;
   Carve carve;
 };
 
@@ -208,6 +209,8 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P) {
   C.add((void**)&P.d_sec_stats, (size_t)nsec * KMAX * 4 * 8);
   C.add((void**)&P.d_res, KMAX * 4 * 8);
   C.add((void**)&P.d_counts, 2 * 8);
+  C.add((void**)&P.d_pair_nonfinite, npairs * 8);
+  C.add((void**)&P.d_sec_nonfinite, (size_t)nsec * 8);
   C.add((void**)&P.d_counter, 8 * 4);
   C.add((void**)&P.d_shifts, (size_t)nsec * P.rows * MAXV * 8);
   C.add((void**)&P.d_zp_final, (size_t)nsec * MAXV * 8);
@@ -224,7 +227,6 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P) {
     C.add((void**)&P.d_hsec, (size_t)P.hsec_total * 8);
     C.add((void**)&P.d_hsec_off, nsec * 8);
     C.add((void**)&P.d_hsec_prefix, nsec * 8);
-    C.add((void**)&P.d_grid_tmp, goff * 8);
   }
   // persistent grids live with the problem
   if (pb->grid_doubles < goff || pb->grid_nbins != prm.nbins) {
@@ -241,9 +243,10 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P) {
   return SDI_OK;
 }
 
-int choose_ppt(sdi_ctx* ctx, const sdi_problem* pb) {
-  if (ctx->params.ppt > 0) return ctx->params.ppt;
-  return pb->nvmax >= 16 ? 1 : 2;
+// Candidate points-per-thread values of the tile kernel for a variable class.
+std::vector<int> ppt_candidates(int nvmax) {
+  if (nvmax >= 16) return {1, 2};
+  return {1, 2, 4};
 }
 
 int persistent_grid(sdi_ctx* ctx, int nvmax, int ppt, int km, size_t shmem, size_t ntiles) {
@@ -344,6 +347,9 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
   } else if (k == "ppt") {
     if (!(iv == 0 || iv == 1 || iv == 2 || iv == 4)) return fail(ctx, SDI_EINVAL, "ppt must be 0, 1, 2 or 4");
     p.ppt = (int)iv;
+  } else if (k == "graph") {
+    if (!range(0, 1)) return fail(ctx, SDI_EINVAL, "graph must be 0 or 1");
+    p.graph = (int)iv;
   } else {
     return fail(ctx, SDI_EINVAL, "unknown parameter " + k);
   }
@@ -367,6 +373,7 @@ int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len) {
   else if (k == "nbins") v = p.nbins;
   else if (k == "tile_log2") v = p.tile_log2;
   else if (k == "ppt") v = p.ppt;
+  else if (k == "graph") v = p.graph;
   else return fail(ctx, SDI_EINVAL, "unknown parameter " + k);
   snprintf(buf, len, "%lld", v);
   return SDI_OK;
@@ -559,6 +566,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
 
 void sdi_problem_destroy(sdi_problem* pb) {
   if (!pb) return;
+  delete pb->pass;
   if (pb->d_secs) (void)hipFree(pb->d_secs);
   if (pb->d_terms) (void)hipFree(pb->d_terms);
   if (pb->d_grids) (void)hipFree(pb->d_grids);
@@ -571,41 +579,192 @@ int sdi_problem_norders(const sdi_problem* pb) { return pb ? pb->K : SDI_EINVAL;
 size_t sdi_workspace_bytes(sdi_ctx* ctx, const sdi_problem* prob) {
   if (!ctx || !prob) return 0;
   Plan P;
-  if (make_plan(ctx, const_cast<sdi_problem*>(prob), P) != SDI_OK) return 0;
-  return P.carve.total();
+  sdi_problem tmp = *prob;        // make_plan edits per-sector fields; work on a copy
+  tmp.d_grids = nullptr;
+  tmp.grid_doubles = (size_t)-1;  // do not (re)allocate grids here
+  tmp.grid_nbins = ctx->params.nbins;
+  tmp.pass = nullptr;
+  const int rc = make_plan(ctx, &tmp, P);
+  return rc == SDI_OK ? P.carve.total() : 0;
 }
 
-int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, sdi_result* out) {
-  if (!ctx || !pb || !out) return fail(ctx, SDI_EINVAL, "integrate: null argument");
-  if (pb->ctx != ctx) return fail(ctx, SDI_EINVAL, "problem belongs to another context");
-  if (!out->val_re || !out->val_im || !out->err_re || !out->err_im)
-    return fail(ctx, SDI_EINVAL, "integrate: result arrays must be allocated");
-  HIPCHK(ctx, hipSetDevice(ctx->device));
-  const Params& prm = ctx->params;
-  if (prm.mw > 24 || prm.m > 30) return fail(ctx, SDI_EINVAL, "lattice too large");
+}  // extern "C"
+
+namespace sdi {
+
+struct PassState {
+  std::string key;
   Plan P;
-  int rc = make_plan(ctx, pb, P);
-  if (rc != SDI_OK) return rc;
+  int ppt = 1, km = 4, gf = 1, gw = 1;
+  hipGraphExec_t exec = nullptr;
+  bool graph_failed = false;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  ~PassState() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace sdi
+
+namespace {
+
+std::string pass_key(const Params& p, const void* ws, size_t wsb) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "m%d R%d s%llu b%d w%d mw%d nb%d t%d p%d g%d ws%p:%zu", p.m, p.R,
+           (unsigned long long)p.seed, p.baker, p.warmup, p.mw, p.nbins, p.tile_log2, p.ppt, p.graph, ws, wsb);
+  return buf;
+}
+
+// Enqueue one full pass (shifts, warm-up iterations, final pass, reductions) on st.
+int record_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
+  const Params& prm = ctx->params;
+  Plan& P = S.P;
+  const int nsec = pb->nsec;
+  const int npairs = (int)P.pair_sector.size();
+  const int nft = (int)P.ftiles.size();
+  HIPCHK(ctx, hipEventRecord(S.ev[0], st));
+  KCHK(ctx, launch_shifts(pb->d_secs, nsec, P.rows, prm.R, prm.seed, P.d_shifts, st));
+  TileArgs A{};
+  A.secs = pb->d_secs;
+  A.terms = pb->d_terms;
+  A.shifts = P.d_shifts;
+  A.grids = pb->d_grids;
+  if (prm.warmup > 0) {
+    KCHK(ctx, launch_grid_identity(pb->d_secs, nsec, pb->d_grids, st));
+    const int nwt = (int)P.wtiles.size();
+    for (int it = 0; it < prm.warmup; ++it) {
+      KCHK(ctx, launch_fill_i32(P.d_counter, 0, 1, st));
+      TileArgs W = A;
+      W.zp = P.d_zp_warm;
+      W.tiles = P.d_wtiles + (size_t)it * nwt;
+      W.order = P.d_worder;
+      W.partial = P.d_wpartial;
+      W.nonfinite = P.d_wnonfinite;
+      W.hist = P.d_whist;
+      W.hist_off = P.d_whist_off;
+      W.counter = P.d_counter;
+      W.ntiles = nwt;
+      W.mode = 1;
+      KCHK(ctx, launch_tiles_real(pb->nvmax, S.ppt, S.km, S.gw, P.shmem_warm, W, st));
+      KCHK(ctx, launch_hist_reduce(P.d_whist, P.d_whist_off, P.d_wsec_start, pb->d_secs, P.d_hsec_off, nsec,
+                                   P.hsec_total, P.d_hsec_prefix, P.d_hsec, st));
+      KCHK(ctx, launch_refit(pb->d_secs, nsec, P.d_hsec, P.d_hsec_off, pb->d_grids, 1.5, st));
+    }
+  }
+  HIPCHK(ctx, hipEventRecord(S.ev[1], st));
+  KCHK(ctx, launch_fill_i32(P.d_counter + 1, 0, 1, st));
+  TileArgs F = A;
+  F.zp = P.d_zp_final;
+  F.tiles = P.d_ftiles;
+  F.order = P.d_forder;
+  F.partial = P.d_partial;
+  F.nonfinite = P.d_nonfinite;
+  F.counter = P.d_counter + 1;
+  F.ntiles = nft;
+  F.mode = 0;
+  HIPCHK(ctx, hipEventRecord(S.ev[2], st));
+  KCHK(ctx, launch_tiles_real(pb->nvmax, S.ppt, S.km, S.gf, P.shmem_final, F, st));
+  HIPCHK(ctx, hipEventRecord(S.ev[3], st));
+  KCHK(ctx, launch_reduce_pairs(P.d_partial, P.d_pair_start, P.d_pair_sector, pb->d_secs, npairs, P.d_per_shift,
+                                P.d_nonfinite, P.d_pair_nonfinite, st));
+  KCHK(ctx, launch_sector_stats(P.d_per_shift, nsec, prm.R, P.d_sec_stats, P.d_pair_nonfinite, P.d_sec_nonfinite, st));
+  KCHK(ctx, launch_combine(P.d_sec_stats, nsec, P.d_sec_nonfinite, P.d_res, P.d_counts, st));
+  HIPCHK(ctx, hipEventRecord(S.ev[4], st));
+  return SDI_OK;
+}
+
+// Times the final-pass tile kernel for each points-per-thread candidate on the
+// problem's own tiles and keeps the fastest (cached per device, class and problem shape).
+int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
+  const Params& prm = ctx->params;
+  char keyb[256];
+  snprintf(keyb, sizeof keyb, "%s|nv%d|km%d|sec%d|terms%zu|m%d|t%d|grid%d", ctx->prop.gcnArchName, pb->nvmax,
+           S.km, pb->nsec, pb->terms.size(), prm.m, prm.tile_log2, prm.warmup > 0);
+  const std::string key(keyb);
+  if (prm.tune == 1)
+    for (auto& kv : ctx->tune_cache)
+      if (kv.first == key) return kv.second;
+  Plan& P = S.P;
+  KCHK(ctx, launch_shifts(pb->d_secs, pb->nsec, P.rows, prm.R, prm.seed, P.d_shifts, st));
+  if (prm.warmup > 0) KCHK(ctx, launch_grid_identity(pb->d_secs, pb->nsec, pb->d_grids, st));
+  TileArgs F{};
+  F.secs = pb->d_secs;
+  F.terms = pb->d_terms;
+  F.shifts = P.d_shifts;
+  F.grids = pb->d_grids;
+  F.zp = P.d_zp_final;
+  F.tiles = P.d_ftiles;
+  F.order = P.d_forder;
+  F.partial = P.d_partial;
+  F.nonfinite = P.d_nonfinite;
+  F.counter = P.d_counter + 1;
+  F.ntiles = (int)P.ftiles.size();
+  F.mode = 0;
+  int best = 1;
+  float best_ms = 1e30f;
+  for (int ppt : ppt_candidates(pb->nvmax)) {
+    const int g = persistent_grid(ctx, pb->nvmax, ppt, S.km, P.shmem_final, P.ftiles.size());
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      KCHK(ctx, launch_fill_i32(F.counter, 0, 1, st));
+      HIPCHK(ctx, hipEventRecord(S.ev[2], st));
+      KCHK(ctx, launch_tiles_real(pb->nvmax, ppt, S.km, g, P.shmem_final, F, st));
+      HIPCHK(ctx, hipEventRecord(S.ev[3], st));
+      HIPCHK(ctx, hipEventSynchronize(S.ev[3]));
+      HIPCHK(ctx, hipEventElapsedTime(&ms, S.ev[2], S.ev[3]));
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = ppt;
+    }
+  }
+  ctx->tune_cache.push_back({key, best});
+  return best;
+}
+
+// (Re)build the cached pass state when parameters or workspace change.
+int prepare_pass(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes) {
+  const Params& prm = ctx->params;
+  const std::string key = pass_key(prm, dev_ws, ws_bytes);
+  if (pb->pass && pb->pass->key == key) return SDI_OK;
+  delete pb->pass;
+  pb->pass = nullptr;
+  PassState* S = new PassState();
+  int rc = make_plan(ctx, pb, S->P);
+  if (rc != SDI_OK) {
+    delete S;
+    return rc;
+  }
+  Plan& P = S->P;
   const size_t need = P.carve.total();
   void* base = dev_ws;
   if (base) {
-    if (ws_bytes < need) return fail(ctx, SDI_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (ws_bytes < need) {
+      delete S;
+      return fail(ctx, SDI_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    }
   } else {
     if (pb->ws_size < need) {
       if (pb->d_ws) (void)hipFree(pb->d_ws);
       pb->d_ws = nullptr;
       pb->ws_size = 0;
-      HIPCHK(ctx, hipMalloc(&pb->d_ws, need));
+      if (hipMalloc(&pb->d_ws, need) != hipSuccess) {
+        delete S;
+        return fail(ctx, SDI_ENOMEM, "workspace allocation failed");
+      }
       pb->ws_size = need;
     }
     base = pb->d_ws;
   }
   P.carve.assign(base);
+  pb->pass = S;
+  for (auto& e : S->ev) HIPCHK(ctx, hipEventCreate(&e));
   hipStream_t st = ctx->stream;
   const int nsec = pb->nsec;
   const int npairs = (int)P.pair_sector.size();
   const int nft = (int)P.ftiles.size();
-  // uploads (small host tables)
   HIPCHK(ctx, hipMemcpyAsync(pb->d_secs, pb->secs.data(), pb->secs.size() * sizeof(SecDev), hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(P.d_ftiles, P.ftiles.data(), nft * sizeof(TileDesc), hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(P.d_forder, P.forder.data(), nft * 4, hipMemcpyHostToDevice, st));
@@ -626,67 +785,64 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
     HIPCHK(ctx, hipMemcpyAsync(P.d_hsec_off, P.hsec_off.data(), nsec * 8, hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(P.d_hsec_prefix, P.hsec_prefix.data(), nsec * 8, hipMemcpyHostToDevice, st));
   }
-  const int ppt = choose_ppt(ctx, pb);
-  const int km = pb->kfmax <= 4 ? 4 : 8;
-  hipEvent_t ev0, ev1, ev2;
-  HIPCHK(ctx, hipEventCreate(&ev0));
-  HIPCHK(ctx, hipEventCreate(&ev1));
-  HIPCHK(ctx, hipEventCreate(&ev2));
-  HIPCHK(ctx, hipEventRecord(ev0, st));
-  KCHK(ctx, launch_shifts(pb->d_secs, nsec, P.rows, prm.R, prm.seed, P.d_shifts, st));
-  TileArgs A{};
-  A.secs = pb->d_secs;
-  A.terms = pb->d_terms;
-  A.shifts = P.d_shifts;
-  A.grids = pb->d_grids;
-  if (prm.warmup > 0) {
-    KCHK(ctx, launch_grid_identity(pb->d_secs, nsec, pb->d_grids, st));
-    const int nwt = (int)P.wtiles.size();
-    const int gw = persistent_grid(ctx, pb->nvmax, ppt, km, P.shmem_warm, nwt);
-    for (int it = 0; it < prm.warmup; ++it) {
-      KCHK(ctx, launch_fill_i32(P.d_counter, 0, 1, st));
-      TileArgs W = A;
-      W.zp = P.d_zp_warm;
-      W.tiles = P.d_wtiles + (size_t)it * nwt;
-      W.order = P.d_worder;
-      W.partial = P.d_wpartial;
-      W.nonfinite = P.d_wnonfinite;
-      W.hist = P.d_whist;
-      W.hist_off = P.d_whist_off;
-      W.counter = P.d_counter;
-      W.ntiles = nwt;
-      W.mode = 1;
-      KCHK(ctx, launch_tiles_real(pb->nvmax, ppt, km, gw, P.shmem_warm, W, st));
-      KCHK(ctx, launch_hist_reduce(P.d_whist, P.d_whist_off, P.d_wsec_start, pb->d_secs, P.d_hsec_off, nsec,
-                                   P.hsec_total, P.d_hsec_prefix, P.d_hsec, st));
-      KCHK(ctx, launch_refit(pb->d_secs, nsec, P.d_hsec, P.d_hsec_off, pb->d_grids, P.d_grid_tmp, 1.5, st));
-    }
-    pb->grid_valid = true;
-  } else {
-    pb->grid_valid = false;
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  S->km = pb->kfmax <= 4 ? 4 : 8;
+  if (prm.ppt > 0) S->ppt = prm.ppt;
+  else if (prm.tune == 0) S->ppt = pb->nvmax >= 16 ? 1 : 2;
+  else {
+    rc = autotune_ppt(ctx, pb, *S, st);
+    if (rc < 0) return rc;
+    S->ppt = rc;
   }
-  HIPCHK(ctx, hipEventRecord(ev1, st));
-  KCHK(ctx, launch_fill_i32(P.d_counter + 1, 0, 1, st));
-  TileArgs F = A;
-  F.zp = P.d_zp_final;
-  F.tiles = P.d_ftiles;
-  F.order = P.d_forder;
-  F.partial = P.d_partial;
-  F.nonfinite = P.d_nonfinite;
-  F.counter = P.d_counter + 1;
-  F.ntiles = nft;
-  F.mode = 0;
-  const int gf = persistent_grid(ctx, pb->nvmax, ppt, km, P.shmem_final, nft);
-  hipEvent_t evk0, evk1;
-  HIPCHK(ctx, hipEventCreate(&evk0));
-  HIPCHK(ctx, hipEventCreate(&evk1));
-  HIPCHK(ctx, hipEventRecord(evk0, st));
-  KCHK(ctx, launch_tiles_real(pb->nvmax, ppt, km, gf, P.shmem_final, F, st));
-  HIPCHK(ctx, hipEventRecord(evk1, st));
-  KCHK(ctx, launch_reduce_pairs(P.d_partial, P.d_pair_start, P.d_pair_sector, pb->d_secs, npairs, P.d_per_shift, st));
-  KCHK(ctx, launch_sector_stats(P.d_per_shift, nsec, prm.R, P.d_sec_stats, st));
-  KCHK(ctx, launch_combine(P.d_sec_stats, nsec, P.d_nonfinite, nft, P.d_res, P.d_counts, st));
-  HIPCHK(ctx, hipEventRecord(ev2, st));
+  S->gf = persistent_grid(ctx, pb->nvmax, S->ppt, S->km, P.shmem_final, P.ftiles.size());
+  S->gw = prm.warmup > 0 ? persistent_grid(ctx, pb->nvmax, S->ppt, S->km, P.shmem_warm, P.wtiles.size()) : 1;
+  if (prm.graph) {
+    // Capture the whole pass once; replays skip the launch overheads.  Any
+    // failure falls back to eager launches on this key.
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const int rr = record_pass(ctx, pb, *S, st);
+      const hipError_t ec = hipStreamEndCapture(st, &g);
+      if (rr == SDI_OK && ec == hipSuccess && g && hipGraphInstantiate(&S->exec, g, nullptr, nullptr, 0) == hipSuccess) {
+        // instantiated
+      } else {
+        S->exec = nullptr;
+        S->graph_failed = true;
+      }
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+    } else {
+      S->graph_failed = true;
+    }
+  }
+  S->key = key;
+  return SDI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, sdi_result* out) {
+  if (!ctx || !pb || !out) return fail(ctx, SDI_EINVAL, "integrate: null argument");
+  if (pb->ctx != ctx) return fail(ctx, SDI_EINVAL, "problem belongs to another context");
+  if (!out->val_re || !out->val_im || !out->err_re || !out->err_im)
+    return fail(ctx, SDI_EINVAL, "integrate: result arrays must be allocated");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const Params& prm = ctx->params;
+  int rc = prepare_pass(ctx, pb, dev_ws, ws_bytes);
+  if (rc != SDI_OK) return rc;
+  PassState& S = *pb->pass;
+  Plan& P = S.P;
+  hipStream_t st = ctx->stream;
+  const int nsec = pb->nsec;
+  const int npairs = (int)P.pair_sector.size();
+  if (S.exec) {
+    HIPCHK(ctx, hipGraphLaunch(S.exec, st));
+  } else {
+    rc = record_pass(ctx, pb, S, st);
+    if (rc != SDI_OK) return rc;
+  }
   std::vector<double> res(KMAX * 4);
   int64_t counts[2] = {0, 0};
   pb->sec_stats.assign((size_t)nsec * KMAX * 4, 0.0);
@@ -697,10 +853,10 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   HIPCHK(ctx, hipMemcpyAsync(pb->per_shift.data(), P.d_per_shift, pb->per_shift.size() * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
   float ms_w = 0.f, ms_f = 0.f, ms_k = 0.f;
-  (void)hipEventElapsedTime(&ms_w, ev0, ev1);
-  (void)hipEventElapsedTime(&ms_f, ev1, ev2);
-  (void)hipEventElapsedTime(&ms_k, evk0, evk1);
-  for (hipEvent_t e : {ev0, ev1, ev2, evk0, evk1}) (void)hipEventDestroy(e);
+  (void)hipEventElapsedTime(&ms_w, S.ev[0], S.ev[1]);
+  (void)hipEventElapsedTime(&ms_f, S.ev[1], S.ev[4]);
+  (void)hipEventElapsedTime(&ms_k, S.ev[2], S.ev[3]);
+  pb->grid_valid = prm.warmup > 0;
   pb->last_R = prm.R;
   pb->have_results = true;
   const int64_t per_sec = (int64_t)prm.R << prm.m;
@@ -720,8 +876,8 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   out->ms_refit = ms_w;
   out->ms_total = ms_w + ms_f;
   out->ms_eval_kernel = ms_k;
-  out->points_per_thread = ppt;
-  out->blocks = gf;
+  out->points_per_thread = S.ppt;
+  out->blocks = S.gf;
   return counts[0] ? fail(ctx, SDI_ENONFINITE, "non-finite integrand values") : SDI_OK;
 }
 

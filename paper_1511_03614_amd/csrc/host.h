@@ -22,6 +22,7 @@ struct Params {
   int tile_log2 = 14;
   int ppt = 0;           // 0: autotune
   int tune = 1;          // 0 off, 1 cached, 2 search
+  int graph = 1;         // capture the pass into a hipGraph and replay it
 };
 
 const std::vector<uint32_t>& lattice_vector16(int m);
@@ -40,6 +41,10 @@ struct sdi_ctx {
   int ncu = 0;
   std::vector<std::pair<std::string, int>> tune_cache;   // key -> ppt
 };
+
+namespace sdi {
+struct PassState;   // cached plan, uploaded tables and captured graph (api.cpp)
+}
 
 struct sdi_problem {
   sdi_ctx* ctx = nullptr;
@@ -62,4 +67,5 @@ struct sdi_problem {
   std::vector<double> sec_stats;      // [nsec][KMAX][4]
   std::vector<double> per_shift;      // [nsec*R][KMAX][2]
   std::vector<int64_t> sec_evals;
+  sdi::PassState* pass = nullptr;
 };

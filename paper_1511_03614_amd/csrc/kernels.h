@@ -11,16 +11,18 @@ int launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 int launch_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t seed, uint64_t* shifts,
                   hipStream_t st);
 int launch_reduce_pairs(const double* partial, const int32_t* pair_start, const int32_t* pair_sector,
-                        const SecDev* secs, int npairs, double* out, hipStream_t st);
-int launch_sector_stats(const double* per_shift, int nsec, int R, double* out, hipStream_t st);
-int launch_combine(const double* sec_stats, int nsec, const int32_t* nonfinite, int ntiles, double* res,
-                   int64_t* counts, hipStream_t st);
+                        const SecDev* secs, int npairs, double* out, const int32_t* nonfinite,
+                        int64_t* pair_nonfinite, hipStream_t st);
+int launch_sector_stats(const double* per_shift, int nsec, int R, double* out, const int64_t* pair_nonfinite,
+                        int64_t* sec_nonfinite, hipStream_t st);
+int launch_combine(const double* sec_stats, int nsec, const int64_t* sec_nonfinite, double* res, int64_t* counts,
+                   hipStream_t st);
 int launch_grid_identity(const SecDev* secs, int nsec, double* grids, hipStream_t st);
 int launch_hist_reduce(const double* hist, const int64_t* hist_off, const int32_t* sec_tile_start,
                        const SecDev* secs, const int64_t* hsec_off, int nsec, int64_t total,
                        const int64_t* hsec_prefix, double* hsec, hipStream_t st);
 int launch_refit(const SecDev* secs, int nsec, const double* hsec, const int64_t* hsec_off, double* grids,
-                 double* tmp, double alpha, hipStream_t st);
+                 double alpha, hipStream_t st);
 int launch_sample_points(const SampleArgs& a, hipStream_t st);
 
 // Tile kernel of variable class nvmax (4, 8 or 16), points per thread ppt (1, 2, 4)

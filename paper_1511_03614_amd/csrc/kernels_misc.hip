@@ -74,10 +74,14 @@ __global__ void k_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uin
 // Q_k = sum_kk fold[k][kk] Q_kk (linear, so it commutes with the sum).
 // out: [npairs][KMAX][2] = Q_re, Q_im.
 __global__ void k_reduce_pairs(const double* partial, const int32_t* pair_start, const int32_t* pair_sector,
-                               const SecDev* secs, int npairs, double* out) {
+                               const SecDev* secs, int npairs, double* out, const int32_t* nonfinite,
+                               int64_t* pair_nonfinite) {
   const int pr = blockIdx.x * blockDim.x + threadIdx.x;
   if (pr >= npairs) return;
   const SecDev& S = secs[pair_sector[pr]];
+  int64_t nf = 0;
+  for (int t = pair_start[pr]; t < pair_start[pr + 1]; ++t) nf += nonfinite[t];
+  pair_nonfinite[pr] = nf;
   const double N = (double)(1ull << S.m);
   double qr[KMAX], qi[KMAX];
   for (int kk = 0; kk < KMAX; ++kk) {
@@ -106,11 +110,17 @@ __global__ void k_reduce_pairs(const double* partial, const int32_t* pair_start,
 // Per sector and order: mean over the R shifts and the shift-to-shift error
 // sigma^2 = sum_r (Q_r - mean)^2 / (R (R - 1)), real and imaginary apart.
 // out: [nsec][KMAX][4] = mean_re, mean_im, err_re, err_im.
-__global__ void k_sector_stats(const double* per_shift, int nsec, int R, double* out) {
+__global__ void k_sector_stats(const double* per_shift, int nsec, int R, double* out,
+                               const int64_t* pair_nonfinite, int64_t* sec_nonfinite) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= nsec * KMAX) return;
   const int s = gid / KMAX;
   const int k = gid % KMAX;
+  if (k == 0) {
+    int64_t nf = 0;
+    for (int r = 0; r < R; ++r) nf += pair_nonfinite[(size_t)s * R + r];
+    sec_nonfinite[s] = nf;
+  }
   double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0;
   for (int r = 0; r < R; ++r) {
     const double* q = per_shift + (((size_t)s * R + r) * KMAX + k) * 2;
@@ -133,29 +143,60 @@ __global__ void k_sector_stats(const double* per_shift, int nsec, int R, double*
   o[3] = R > 1 ? sqrt(vi / den) : 0.0;
 }
 
-// Result_k = sum_s mean_{s,k}, err_k = sqrt(sum_s err_{s,k}^2), in sector order;
-// counts of non-finite values.  res: [KMAX][4]; counts: [2].
-__global__ void k_combine(const double* sec_stats, int nsec, const int32_t* nonfinite, int ntiles,
-                          double* res, int64_t* counts) {
-  const int k = threadIdx.x;
+// Result_k = sum_s mean_{s,k}, err_k = sqrt(sum_s err_{s,k}^2): one block per
+// order; thread t sums a contiguous run of sectors in order, then a fixed
+// tree over threads (deterministic).  Block KMAX sums the non-finite counts.
+// res: [KMAX][4]; counts: [2].
+constexpr int COMBINE_THREADS = 256;
+__global__ void __launch_bounds__(COMBINE_THREADS) k_combine(const double* sec_stats, int nsec,
+                                                            const int64_t* sec_nonfinite, double* res,
+                                                            int64_t* counts) {
+  __shared__ double sh[COMBINE_THREADS][6];
+  __shared__ int64_t si[COMBINE_THREADS];
+  const int k = blockIdx.x;
+  const int t = threadIdx.x;
+  const int chunk = (nsec + COMBINE_THREADS - 1) / COMBINE_THREADS;
+  const int s0 = t * chunk;
+  const int s1 = min(nsec, s0 + chunk);
   if (k < KMAX) {
     double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0, er = 0.0, ei = 0.0;
-    for (int s = 0; s < nsec; ++s) {
+    for (int s = s0; s < s1; ++s) {
       const double* q = sec_stats + ((size_t)s * KMAX + k) * 4;
       dd_add(hr, lr, q[0], 0.0);
       dd_add(hi, li, q[1], 0.0);
       er += q[2] * q[2];
       ei += q[3] * q[3];
     }
-    res[k * 4 + 0] = hr + lr;
-    res[k * 4 + 1] = hi + li;
-    res[k * 4 + 2] = sqrt(er);
-    res[k * 4 + 3] = sqrt(ei);
-  } else if (k == KMAX) {
+    sh[t][0] = hr; sh[t][1] = lr; sh[t][2] = hi; sh[t][3] = li; sh[t][4] = er; sh[t][5] = ei;
+    __syncthreads();
+    for (int w = COMBINE_THREADS / 2; w >= 1; w >>= 1) {
+      if (t < w) {
+        dd_add(sh[t][0], sh[t][1], sh[t + w][0], sh[t + w][1]);
+        dd_add(sh[t][2], sh[t][3], sh[t + w][2], sh[t + w][3]);
+        sh[t][4] += sh[t + w][4];
+        sh[t][5] += sh[t + w][5];
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      res[k * 4 + 0] = sh[0][0] + sh[0][1];
+      res[k * 4 + 1] = sh[0][2] + sh[0][3];
+      res[k * 4 + 2] = sqrt(sh[0][4]);
+      res[k * 4 + 3] = sqrt(sh[0][5]);
+    }
+  } else {
     int64_t nf = 0;
-    for (int t = 0; t < ntiles; ++t) nf += nonfinite[t];
-    counts[0] = nf;
-    counts[1] = 0;
+    for (int s = s0; s < s1; ++s) nf += sec_nonfinite[s];
+    si[t] = nf;
+    __syncthreads();
+    for (int w = COMBINE_THREADS / 2; w >= 1; w >>= 1) {
+      if (t < w) si[t] += si[t + w];
+      __syncthreads();
+    }
+    if (t == 0) {
+      counts[0] = si[0];
+      counts[1] = 0;
+    }
   }
 }
 
@@ -192,71 +233,94 @@ __global__ void k_hist_reduce(const double* hist, const int64_t* hist_off, const
   (void)secs;
 }
 
-// Lepage refit of one (sector, dimension): importance d_b = sum_k h_bk / H_k over
-// the internal orders k,
-// 3-point smoothing, compression m_b = ((r_b - 1)/ln r_b)^alpha, equal shares.
-__global__ void k_refit(const SecDev* secs, int nsec, const double* hsec, const int64_t* hsec_off,
-                        double* grids, double* tmp, double alpha) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= nsec * MAXV) return;
-  const int s = gid / MAXV;
-  const int j = gid % MAXV;
+// Lepage refit of one (sector, dimension) per block, one thread per bin:
+// importance d_b = sum_k h_bk / H_k over the internal orders k, 3-point
+// smoothing, compression m_b = ((r_b - 1)/ln r_b)^alpha, equal shares of
+// sum m per new bin, linear inside the old bins.  The running sums are taken
+// by one thread in bin order; per-bin work and the search for each new edge
+// run in parallel.
+__global__ void __launch_bounds__(NBMAX) k_refit(const SecDev* secs, int nsec, const double* hsec,
+                                                 const int64_t* hsec_off, double* grids, double alpha) {
+  __shared__ double d[NBMAX], sm[NBMAX], mm[NBMAX], cum[NBMAX + 1], g[NBMAX + 1];
+  __shared__ double H[KMAX], tot_s, share_s;
+  __shared__ int any_s;
+  const int s = blockIdx.x / MAXV;
+  const int j = blockIdx.x % MAXV;
+  if (s >= nsec) return;
   const SecDev& S = secs[s];
-  if (j >= S.n) return;
-  const int nb = S.nbins;
   const int K = S.kf;        // histogram rows are the internal eps orders f_kk
-  if (K <= 0) return;
+  if (j >= S.n || K <= 0) return;
+  const int nb = S.nbins;
+  const int b = threadIdx.x;
   const double* h = hsec + hsec_off[s] + (size_t)j * nb * K;
-  double H[KMAX];
-  bool any = false;
-  for (int k = 0; k < KMAX; ++k) {
-    H[k] = 0.0;
-    if (k < K)
-      for (int b = 0; b < nb; ++b) H[k] += h[(size_t)b * K + k];
-    if (H[k] > 0.0) any = true;
-  }
-  if (!any) return;
-  auto dval = [&](int b) {
-    double d = 0.0;
-    for (int k = 0; k < K; ++k)
-      if (H[k] > 0.0) d += h[(size_t)b * K + k] / H[k];
-    return d;
-  };
-  auto smooth = [&](int b) {
-    if (b == 0) return (dval(0) + dval(1)) / 2.0;
-    if (b == nb - 1) return (dval(nb - 2) + dval(nb - 1)) / 2.0;
-    return (dval(b - 1) + dval(b) + dval(b + 1)) / 3.0;
-  };
-  double tot = 0.0;
-  for (int b = 0; b < nb; ++b) tot += smooth(b);
-  auto mval = [&](int b) {
-    const double r = smooth(b) / tot;
-    if (r == 0.0) return 0.0;
-    if (fabs(r - 1.0) < 1e-12) return 1.0;
-    return pow((r - 1.0) / log(r), alpha);
-  };
-  double msum = 0.0;
-  for (int b = 0; b < nb; ++b) msum += mval(b);
-  const double share = msum / nb;
-  double* g = grids + S.grid_off + (size_t)j * (nb + 1);
-  double* o = tmp + S.grid_off + (size_t)j * (nb + 1);
-  double acc = 0.0;
-  int b = 0;
-  double mb = mval(0);
-  for (int k = 1; k < nb; ++k) {
-    const double t = k * share;
-    while (b < nb - 1 && acc + mb <= t) {
-      acc += mb;
-      ++b;
-      mb = mval(b);
+  double* gr = grids + S.grid_off + (size_t)j * (nb + 1);
+  if (b <= nb) g[b] = gr[b];
+  if (b == 0) {
+    any_s = 0;
+    for (int k = 0; k < K; ++k) {
+      double acc = 0.0;
+      for (int i = 0; i < nb; ++i) acc += h[(size_t)i * K + k];
+      H[k] = acc;
+      if (acc > 0.0) any_s = 1;
     }
-    double frac = mb > 0.0 ? (t - acc) / mb : 1.0;
-    frac = frac < 1.0 ? frac : 1.0;
-    o[k] = g[b] + frac * (g[b + 1] - g[b]);
   }
-  for (int k = 1; k < nb; ++k) g[k] = o[k];
-  g[0] = 0.0;
-  g[nb] = 1.0;
+  __syncthreads();
+  if (!any_s) return;
+  if (b < nb) {
+    double v = 0.0;
+    for (int k = 0; k < K; ++k)
+      if (H[k] > 0.0) v += h[(size_t)b * K + k] / H[k];
+    d[b] = v;
+  }
+  __syncthreads();
+  if (b < nb) {
+    if (b == 0) sm[b] = (d[0] + d[1]) / 2.0;
+    else if (b == nb - 1) sm[b] = (d[nb - 2] + d[nb - 1]) / 2.0;
+    else sm[b] = (d[b - 1] + d[b] + d[b + 1]) / 3.0;
+  }
+  __syncthreads();
+  if (b == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < nb; ++i) acc += sm[i];
+    tot_s = acc;
+  }
+  __syncthreads();
+  if (b < nb) {
+    const double r = sm[b] / tot_s;
+    double m;
+    if (r == 0.0) m = 0.0;
+    else if (fabs(r - 1.0) < 1e-12) m = 1.0;
+    else m = pow((r - 1.0) / log(r), alpha);
+    mm[b] = m;
+  }
+  __syncthreads();
+  if (b == 0) {
+    double acc = 0.0;
+    cum[0] = 0.0;
+    for (int i = 0; i < nb; ++i) {
+      acc += mm[i];
+      cum[i + 1] = acc;
+    }
+    share_s = acc / nb;
+  }
+  __syncthreads();
+  if (b >= 1 && b < nb) {
+    const double t = b * share_s;
+    // first bin c (capped at nb-1) whose running sum passes t: cum[c] <= t < cum[c] + m_c
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cum[mid] + mm[mid] <= t) lo = mid + 1; else hi = mid;
+    }
+    const int c = lo;
+    double frac = mm[c] > 0.0 ? (t - cum[c]) / mm[c] : 1.0;
+    frac = frac < 1.0 ? frac : 1.0;
+    gr[b] = g[c] + frac * (g[c + 1] - g[c]);
+  }
+  if (b == 0) {
+    gr[0] = 0.0;
+    gr[nb] = 1.0;
+  }
 }
 
 // ------------------------------------------------------------ sampling hook
@@ -299,21 +363,24 @@ int launch_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t s
 }
 
 int launch_reduce_pairs(const double* partial, const int32_t* pair_start, const int32_t* pair_sector,
-                        const SecDev* secs, int npairs, double* out, hipStream_t st) {
+                        const SecDev* secs, int npairs, double* out, const int32_t* nonfinite,
+                        int64_t* pair_nonfinite, hipStream_t st) {
   k_reduce_pairs<<<dim3((npairs + 63) / 64), dim3(64), 0, st>>>(partial, pair_start, pair_sector, secs,
-                                                                npairs, out);
+                                                                npairs, out, nonfinite, pair_nonfinite);
   return (int)hipGetLastError();
 }
 
-int launch_sector_stats(const double* per_shift, int nsec, int R, double* out, hipStream_t st) {
+int launch_sector_stats(const double* per_shift, int nsec, int R, double* out, const int64_t* pair_nonfinite,
+                        int64_t* sec_nonfinite, hipStream_t st) {
   const int tot = nsec * KMAX;
-  k_sector_stats<<<dim3((tot + 127) / 128), dim3(128), 0, st>>>(per_shift, nsec, R, out);
+  k_sector_stats<<<dim3((tot + 127) / 128), dim3(128), 0, st>>>(per_shift, nsec, R, out, pair_nonfinite,
+                                                                sec_nonfinite);
   return (int)hipGetLastError();
 }
 
-int launch_combine(const double* sec_stats, int nsec, const int32_t* nonfinite, int ntiles, double* res,
-                   int64_t* counts, hipStream_t st) {
-  k_combine<<<dim3(1), dim3(64), 0, st>>>(sec_stats, nsec, nonfinite, ntiles, res, counts);
+int launch_combine(const double* sec_stats, int nsec, const int64_t* sec_nonfinite, double* res, int64_t* counts,
+                   hipStream_t st) {
+  k_combine<<<dim3(KMAX + 1), dim3(COMBINE_THREADS), 0, st>>>(sec_stats, nsec, sec_nonfinite, res, counts);
   return (int)hipGetLastError();
 }
 
@@ -332,9 +399,8 @@ int launch_hist_reduce(const double* hist, const int64_t* hist_off, const int32_
 }
 
 int launch_refit(const SecDev* secs, int nsec, const double* hsec, const int64_t* hsec_off, double* grids,
-                 double* tmp, double alpha, hipStream_t st) {
-  const int tot = nsec * MAXV;
-  k_refit<<<dim3((tot + 63) / 64), dim3(64), 0, st>>>(secs, nsec, hsec, hsec_off, grids, tmp, alpha);
+                 double alpha, hipStream_t st) {
+  k_refit<<<dim3(nsec * MAXV), dim3(NBMAX), 0, st>>>(secs, nsec, hsec, hsec_off, grids, alpha);
   return (int)hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ def ctx():
 
 def set_params(ctx, **kw):
     base = dict(lattice_log2=10, shifts=4, seed=1, baker=1, warmup=0, warmup_log2=10, nbins=32,
-                tile_log2=14, ppt=0)
+                tile_log2=14, ppt=0, graph=1)
     base.update(kw)
     for k, v in base.items():
         P.sdi_set_param(ctx, k, v)
@@ -285,3 +285,47 @@ def test_errors_are_reported(ctx):
             P.sdi_evaluate(ctx, h, 5, torch.zeros((4, 1), dtype=torch.float64, device="cuda"))
     finally:
         P.sdi_problem_destroy(h)
+
+
+def test_graph_replays_match_eager(ctx):
+    """The captured pass replayed several times, with eager torch work and syncs in between,
+    gives exactly the eager result every time (no warm-up: fully deterministic sums)."""
+    prob = sectorgen.config2()
+    set_params(ctx, lattice_log2=11, shifts=4, seed=21, graph=0)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        eager = P.sdi_integrate(ctx, h)
+        per_e = [P.sdi_sector_results(ctx, h, s, 4)[2] for s in range(0, 64, 7)]
+        P.sdi_set_param(ctx, "graph", 1)
+        for rep in range(4):
+            junk = torch.randn(4096, device="cuda").mul_(3.0).sum().item()
+            torch.cuda.synchronize()
+            g = P.sdi_integrate(ctx, h)
+            assert np.array_equal(g["value"], eager["value"]), rep
+            assert np.array_equal(g["err_re"], eager["err_re"]), rep
+            per_g = [P.sdi_sector_results(ctx, h, s, 4)[2] for s in range(0, 64, 7)]
+            for a, b in zip(per_e, per_g):
+                assert np.array_equal(a, b)
+            assert np.isfinite(junk)
+    finally:
+        P.sdi_problem_destroy(h)
+        P.sdi_set_param(ctx, "graph", 1)
+
+
+def test_graph_with_warmup_matches_eager(ctx):
+    prob = sectorgen.config2()
+    prob.sectors = prob.sectors[:16]
+    set_params(ctx, lattice_log2=10, shifts=4, seed=2, warmup=3, warmup_log2=10, nbins=64, graph=0)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        eager = P.sdi_integrate(ctx, h)
+        P.sdi_set_param(ctx, "graph", 1)
+        for rep in range(3):
+            torch.cuda.synchronize()
+            g = P.sdi_integrate(ctx, h)
+            scale = np.abs(eager["value"]) + 1e-300
+            assert np.all(np.abs(g["value"] - eager["value"]) <= 1e-12 * scale), rep
+    finally:
+        P.sdi_problem_destroy(h)
+        P.sdi_set_param(ctx, "graph", 1)
+        P.sdi_set_param(ctx, "warmup", 0)
