@@ -247,6 +247,9 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
     arrs = [np.zeros(K) for _ in range(4)]
     res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0)
     ptr, nbytes = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()), workspace.numel())
+    if workspace is not None:
+        import torch
+        torch.cuda.current_stream(workspace.device).synchronize()
     rc = _check(load_library().sdi_integrate(ctx, prob, ptr, nbytes, C.byref(res)), ctx, allow=(-5,))
     return {"status": rc, "order_min": res.order_min, "value": arrs[0] + 1j * arrs[1],
             "err_re": arrs[2], "err_im": arrs[3], "n_evals": res.n_evals, "n_nonfinite": res.n_nonfinite,
@@ -271,6 +274,7 @@ def sdi_evaluate(ctx, prob, s: int, x):
     K = sdi_problem_norders(prob)
     x = x.contiguous()
     out = torch.empty((x.shape[0], K, 2), dtype=torch.float64, device=x.device)
+    torch.cuda.current_stream(x.device).synchronize()
     _check(load_library().sdi_evaluate(ctx, prob, s, C.c_void_p(x.data_ptr()), x.shape[0],
                                        C.c_void_p(out.data_ptr())), ctx)
     return out
@@ -280,6 +284,7 @@ def sdi_sample_points(ctx, prob, s: int, shift: int, i0: int, npts: int, nvars: 
     import torch
     x = torch.empty((npts, nvars), dtype=torch.float64, device=f"cuda:{device}")
     w = torch.empty((npts,), dtype=torch.float64, device=f"cuda:{device}")
+    torch.cuda.current_stream(device).synchronize()
     _check(load_library().sdi_sample_points(ctx, prob, s, shift, i0, npts, C.c_void_p(x.data_ptr()),
                                             C.c_void_p(w.data_ptr())), ctx)
     return x, w

@@ -278,7 +278,8 @@ int sdi_ctx_create(int device_ordinal, void* hip_stream, sdi_ctx** out) {
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    // A blocking stream: ordered with the legacy default stream that torch uses by default.
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
       delete c;
       return SDI_EDEVICE;
     }
