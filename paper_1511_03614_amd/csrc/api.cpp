@@ -204,13 +204,13 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P) {
   C.add((void**)&P.d_pair_start, (npairs + 1) * 4);
   C.add((void**)&P.d_pair_sector, npairs * 4);
   C.add((void**)&P.d_partial, nft * KMAX * PART_STRIDE * 8);
-  C.add((void**)&P.d_nonfinite, nft * 4);
+  C.add((void**)&P.d_nonfinite, nft * 8);
   C.add((void**)&P.d_per_shift, npairs * KMAX * 2 * 8);
   C.add((void**)&P.d_sec_stats, (size_t)nsec * KMAX * 4 * 8);
   C.add((void**)&P.d_res, KMAX * 4 * 8);
   C.add((void**)&P.d_counts, 2 * 8);
-  C.add((void**)&P.d_pair_nonfinite, npairs * 8);
-  C.add((void**)&P.d_sec_nonfinite, (size_t)nsec * 8);
+  C.add((void**)&P.d_pair_nonfinite, npairs * 16);
+  C.add((void**)&P.d_sec_nonfinite, (size_t)nsec * 16);
   C.add((void**)&P.d_counter, 8 * 4);
   C.add((void**)&P.d_shifts, (size_t)nsec * P.rows * MAXV * 8);
   C.add((void**)&P.d_zp_final, (size_t)nsec * MAXV * 8);
@@ -221,7 +221,7 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P) {
     C.add((void**)&P.d_worder, nwt * 4);
     C.add((void**)&P.d_whist_off, nwt * 8);
     C.add((void**)&P.d_wsec_start, (nsec + 1) * 4);
-    C.add((void**)&P.d_wnonfinite, nwt * 4);
+    C.add((void**)&P.d_wnonfinite, nwt * 8);
     C.add((void**)&P.d_wpartial, nwt * KMAX * PART_STRIDE * 8);
     C.add((void**)&P.d_whist, (size_t)P.whist_total * 8);
     C.add((void**)&P.d_hsec, (size_t)P.hsec_total * 8);
@@ -244,13 +244,21 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P) {
 }
 
 // Candidate points-per-thread values of the tile kernel for a variable class.
-std::vector<int> ppt_candidates(int nvmax) {
-  if (nvmax >= 16) return {1, 2};
+std::vector<int> ppt_candidates(const sdi_problem* pb) {
+  if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{1, 2} : std::vector<int>{1};
+  if (pb->nvmax >= 16) return {1, 2};
   return {1, 2, 4};
 }
 
-int persistent_grid(sdi_ctx* ctx, int nvmax, int ppt, int km, size_t shmem, size_t ntiles) {
-  int occ = tiles_real_occupancy(nvmax, ppt, km, shmem);
+// The tile-kernel family of a problem: real, or complex (contour deformation).
+int launch_tiles(const sdi_problem* pb, int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st) {
+  if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
+  return launch_tiles_real(pb->nvmax, ppt, km, grid, shmem, a, st);
+}
+
+int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int ppt, int km, size_t shmem, size_t ntiles) {
+  const int nvmax = pb->nvmax;
+  int occ = pb->complex_mode ? tiles_cplx_occupancy(nvmax, ppt, km, shmem) : tiles_real_occupancy(nvmax, ppt, km, shmem);
   if (occ < 1) occ = 1;
   const size_t g = (size_t)occ * std::max(ctx->ncu, 1);
   return (int)std::max<size_t>(1, std::min(g, ntiles));
@@ -406,7 +414,8 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
   const int K = d->order_max - d->order_min + 1;
   if (K < 1 || K > KMAX) return fail(ctx, SDI_EINVAL, "need 1..8 requested orders");
   if (d->pref_len < 1 || d->pref_len > 64 || !d->pref_re) return fail(ctx, SDI_EINVAL, "prefactor series missing");
-  if (d->complex_mode) return fail(ctx, SDI_ENOTSUP, "complex mode (contour deformation) is not in this build");
+  if (d->complex_mode && !(std::isfinite(d->lambda) && d->lambda >= 0.0))
+    return fail(ctx, SDI_EINVAL, "lambda must be finite and non-negative");
   sdi_problem* pb = new sdi_problem();
   pb->ctx = ctx;
   pb->nsec = d->nsectors;
@@ -444,6 +453,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
       }
     }
     if ((int)S.size() > MAXS) return bad(SDI_ENOTSUP, where + "more than 4 singular variables");
+    if (d->complex_mode && n > 8) return bad(SDI_ENOTSUP, where + "complex mode supports up to 8 variables");
     SecDev R{};
     R.n = n;
     R.ns = (int)S.size();
@@ -452,7 +462,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     if (R.kf > KMAX) return bad(SDI_ENOTSUP, where + "more than 8 internal eps orders");
     R.K = K;
     R.nvc = n <= 4 ? 0 : (n <= 8 ? 1 : 2);
-    R.cls = R.nvc;
+    R.cls = R.nvc;   // complex mode: 0 (n <= 4) or 1 (n <= 8)
     R.sector = s;
     std::vector<int> perm(S);
     perm.insert(perm.end(), rest.begin(), rest.end());
@@ -502,7 +512,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
         if (!std::isfinite(sd.term_coef[t0 + t])) return bad(SDI_EINVAL, where + "term coefficient not finite");
         for (int j = 0; j < n; ++j)
           if (sd.term_exps[(t0 + t) * n + j] > 3)
-            return bad(SDI_ENOTSUP, where + "exponents above 3 are not supported in real mode");
+            return bad(SDI_ENOTSUP, where + "polynomial exponents above 3 are not supported");
       }
       for (int W = 0; W < (1 << R.ns); ++W) {
         R.tab_off[m][W] = (uint32_t)pb->terms.size();
@@ -521,6 +531,72 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
         R.tab_cnt[m][W] = cnt;
       }
       t0 += nt;
+    }
+    if (d->complex_mode) {
+      // derivative lists of the full F = x^mono * P_F (internal variable order), per corner
+      CplxDev X{};
+      X.lam = d->lambda;
+      X.fac_f = sd.deform_factor;
+      for (int j = 0; j < n; ++j) X.mono_f[j] = sd.deform_mono ? sd.deform_mono[perm[j]] : 0;
+      for (int j = 0; j < n; ++j)
+        if (X.mono_f[j] < 0 || X.mono_f[j] > 7) return bad(SDI_ENOTSUP, where + "deform_mono outside 0..7");
+      X.nd = n + n * (n + 1) / 2;
+      X.dir_off = (int32_t)pb->dir.size();
+      pb->dir.resize(pb->dir.size() + (size_t)X.nd * MAXC * 2, 0);
+      if (sd.deform_factor >= 0) {
+        // full-F terms: coefficient and integer exponents
+        size_t tf = 0;
+        for (int m = 0; m < sd.deform_factor; ++m) tf += sd.fac_nterms[m];
+        const int ntf = sd.fac_nterms[sd.deform_factor];
+        std::vector<std::pair<double, std::vector<int>>> F;
+        for (int t = 0; t < ntf; ++t) {
+          std::vector<int> e(n);
+          for (int j = 0; j < n; ++j) e[j] = sd.term_exps[(tf + t) * n + perm[j]] + X.mono_f[j];
+          F.push_back({sd.term_coef[tf + t], e});
+        }
+        auto deriv = [&](const std::vector<std::pair<double, std::vector<int>>>& P, int j) {
+          std::vector<std::pair<double, std::vector<int>>> D;
+          for (auto& t : P)
+            if (t.second[j] > 0) {
+              auto e = t.second;
+              const double c = t.first * e[j];
+              e[j] -= 1;
+              D.push_back({c, e});
+            }
+          return D;
+        };
+        auto emit = [&](int dd, const std::vector<std::pair<double, std::vector<int>>>& P) -> bool {
+          for (int W = 0; W < (1 << R.ns); ++W) {
+            const uint32_t off = (uint32_t)pb->terms.size();
+            uint32_t cnt = 0;
+            for (auto& t : P) {
+              bool alive = true;
+              for (int i = 0; i < R.ns; ++i)
+                if ((W >> i & 1) && t.second[i] != 0) alive = false;
+              if (!alive) continue;
+              uint64_t word = 0;
+              for (int j = 0; j < n; ++j) {
+                if (t.second[j] > 7) return false;
+                word |= (uint64_t)t.second[j] << (4 * j);
+              }
+              pb->terms.push_back(Term{t.first, word});
+              ++cnt;
+            }
+            pb->dir[(size_t)X.dir_off + ((size_t)dd * MAXC + W) * 2] = off;
+            pb->dir[(size_t)X.dir_off + ((size_t)dd * MAXC + W) * 2 + 1] = cnt;
+          }
+          return true;
+        };
+        for (int j = 0; j < n; ++j)
+          if (!emit(j, deriv(F, j))) return bad(SDI_ENOTSUP, where + "full-F exponents above 7");
+        for (int j = 0; j < n; ++j) {
+          const auto Dj = deriv(F, j);
+          for (int k = 0; k <= j; ++k)
+            if (!emit(n + j * (j + 1) / 2 + k, deriv(Dj, k)))
+              return bad(SDI_ENOTSUP, where + "full-F exponents above 7");
+        }
+      }
+      pb->cx.push_back(X);
     }
     // fold: F_k = sum_kk c_s Pi_i f_kk, i = k - lead - (kk - ns)
     bool has_im = false;
@@ -547,6 +623,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     pb->cost.push_back(c);
     pb->secs.push_back(R);
     pb->nvmax = std::max(pb->nvmax, n <= 4 ? 4 : (n <= 8 ? 8 : 16));
+    if (d->complex_mode) c *= 8.0 + 2.0 * n * n;
     pb->kfmax = std::max(pb->kfmax, R.kf);
   }
   if (pb->terms.empty()) pb->terms.push_back(Term{0.0, 0});
@@ -557,6 +634,15 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     e = hipMemcpy(pb->d_terms, pb->terms.data(), pb->terms.size() * sizeof(Term), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(pb->d_secs, pb->secs.data(), pb->secs.size() * sizeof(SecDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess && pb->complex_mode) {
+    if (pb->dir.empty()) pb->dir.push_back(0);
+    e = hipMalloc((void**)&pb->d_cx, pb->cx.size() * sizeof(CplxDev));
+    if (e == hipSuccess) e = hipMalloc((void**)&pb->d_dir, pb->dir.size() * sizeof(uint32_t));
+    if (e == hipSuccess)
+      e = hipMemcpy(pb->d_cx, pb->cx.data(), pb->cx.size() * sizeof(CplxDev), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(pb->d_dir, pb->dir.data(), pb->dir.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     sdi_problem_destroy(pb);
     return fail(ctx, SDI_EDEVICE, std::string("problem upload: ") + hipGetErrorString(e));
@@ -572,6 +658,8 @@ void sdi_problem_destroy(sdi_problem* pb) {
   if (pb->d_terms) (void)hipFree(pb->d_terms);
   if (pb->d_grids) (void)hipFree(pb->d_grids);
   if (pb->d_ws) (void)hipFree(pb->d_ws);
+  if (pb->d_cx) (void)hipFree(pb->d_cx);
+  if (pb->d_dir) (void)hipFree(pb->d_dir);
   delete pb;
 }
 
@@ -648,7 +736,7 @@ int record_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
       W.counter = P.d_counter;
       W.ntiles = nwt;
       W.mode = 1;
-      KCHK(ctx, launch_tiles_real(pb->nvmax, S.ppt, S.km, S.gw, P.shmem_warm, W, st));
+      KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gw, P.shmem_warm, W, st));
       KCHK(ctx, launch_hist_reduce(P.d_whist, P.d_whist_off, P.d_wsec_start, pb->d_secs, P.d_hsec_off, nsec,
                                    P.hsec_total, P.d_hsec_prefix, P.d_hsec, st));
       KCHK(ctx, launch_refit(pb->d_secs, nsec, P.d_hsec, P.d_hsec_off, pb->d_grids, 1.5, st));
@@ -666,7 +754,7 @@ int record_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
   F.ntiles = nft;
   F.mode = 0;
   HIPCHK(ctx, hipEventRecord(S.ev[2], st));
-  KCHK(ctx, launch_tiles_real(pb->nvmax, S.ppt, S.km, S.gf, P.shmem_final, F, st));
+  KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gf, P.shmem_final, F, st));
   HIPCHK(ctx, hipEventRecord(S.ev[3], st));
   KCHK(ctx, launch_reduce_pairs(P.d_partial, P.d_pair_start, P.d_pair_sector, pb->d_secs, npairs, P.d_per_shift,
                                 P.d_nonfinite, P.d_pair_nonfinite, st));
@@ -681,8 +769,8 @@ int record_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
 int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
   const Params& prm = ctx->params;
   char keyb[256];
-  snprintf(keyb, sizeof keyb, "%s|nv%d|km%d|sec%d|terms%zu|m%d|t%d|grid%d", ctx->prop.gcnArchName, pb->nvmax,
-           S.km, pb->nsec, pb->terms.size(), prm.m, prm.tile_log2, prm.warmup > 0);
+  snprintf(keyb, sizeof keyb, "%s|c%d|nv%d|km%d|sec%d|terms%zu|m%d|t%d|grid%d", ctx->prop.gcnArchName,
+           pb->complex_mode, pb->nvmax, S.km, pb->nsec, pb->terms.size(), prm.m, prm.tile_log2, prm.warmup > 0);
   const std::string key(keyb);
   if (prm.tune == 1)
     for (auto& kv : ctx->tune_cache)
@@ -705,13 +793,13 @@ int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
   F.mode = 0;
   int best = 1;
   float best_ms = 1e30f;
-  for (int ppt : ppt_candidates(pb->nvmax)) {
-    const int g = persistent_grid(ctx, pb->nvmax, ppt, S.km, P.shmem_final, P.ftiles.size());
+  for (int ppt : ppt_candidates(pb)) {
+    const int g = persistent_grid(ctx, pb, ppt, S.km, P.shmem_final, P.ftiles.size());
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       KCHK(ctx, launch_fill_i32(F.counter, 0, 1, st));
       HIPCHK(ctx, hipEventRecord(S.ev[2], st));
-      KCHK(ctx, launch_tiles_real(pb->nvmax, ppt, S.km, g, P.shmem_final, F, st));
+      KCHK(ctx, launch_tiles(pb, ppt, S.km, g, P.shmem_final, F, st));
       HIPCHK(ctx, hipEventRecord(S.ev[3], st));
       HIPCHK(ctx, hipEventSynchronize(S.ev[3]));
       HIPCHK(ctx, hipEventElapsedTime(&ms, S.ev[2], S.ev[3]));
@@ -789,14 +877,14 @@ int prepare_pass(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes) {
   HIPCHK(ctx, hipStreamSynchronize(st));
   S->km = pb->kfmax <= 4 ? 4 : 8;
   if (prm.ppt > 0) S->ppt = prm.ppt;
-  else if (prm.tune == 0) S->ppt = pb->nvmax >= 16 ? 1 : 2;
+  else if (prm.tune == 0) S->ppt = (pb->nvmax >= 16 || pb->complex_mode) ? 1 : 2;
   else {
     rc = autotune_ppt(ctx, pb, *S, st);
     if (rc < 0) return rc;
     S->ppt = rc;
   }
-  S->gf = persistent_grid(ctx, pb->nvmax, S->ppt, S->km, P.shmem_final, P.ftiles.size());
-  S->gw = prm.warmup > 0 ? persistent_grid(ctx, pb->nvmax, S->ppt, S->km, P.shmem_warm, P.wtiles.size()) : 1;
+  S->gf = persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_final, P.ftiles.size());
+  S->gw = prm.warmup > 0 ? persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_warm, P.wtiles.size()) : 1;
   if (prm.graph) {
     // Capture the whole pass once; replays skip the launch overheads.  Any
     // failure falls back to eager launches on this key.
@@ -917,7 +1005,10 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_d
   A.x = (const double*)x_dev;
   A.out = (double*)out_dev;
   A.npts = npts;
-  KCHK(ctx, launch_eval_points_real(pb->kfmax <= 4 ? 4 : 8, A, ctx->stream));
+  if (pb->complex_mode)
+    KCHK(ctx, launch_eval_points_cplx(pb->kfmax <= 4 ? 4 : 8, A, pb->d_cx + s, pb->d_dir, ctx->stream));
+  else
+    KCHK(ctx, launch_eval_points_real(pb->kfmax <= 4 ? 4 : 8, A, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   return SDI_OK;
 }

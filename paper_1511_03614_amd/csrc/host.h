@@ -68,4 +68,9 @@ struct sdi_problem {
   std::vector<double> per_shift;      // [nsec*R][KMAX][2]
   std::vector<int64_t> sec_evals;
   sdi::PassState* pass = nullptr;
+  // complex mode
+  std::vector<sdi::CplxDev> cx;
+  std::vector<uint32_t> dir;
+  sdi::CplxDev* d_cx = nullptr;
+  uint32_t* d_dir = nullptr;
 };

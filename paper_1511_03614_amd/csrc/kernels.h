@@ -32,4 +32,11 @@ int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st);
 // Occupancy (resident blocks per CU) of a tile kernel instance; 0 if not built.
 int tiles_real_occupancy(int nvmax, int ppt, int km, size_t shmem);
 
+// Complex mode: nvmax 4 or 8; cx is the CplxDev array (tile kernel) or one sector's
+// record (point evaluation); dir the derivative-list directory.
+int launch_tiles_cplx(int nvmax, int ppt, int km, int grid, size_t shmem, const TileArgs& a, const void* cx,
+                      const uint32_t* dir, hipStream_t st);
+int tiles_cplx_occupancy(int nvmax, int ppt, int km, size_t shmem);
+int launch_eval_points_cplx(int km, const EvalArgs& a, const void* cx, const uint32_t* dir, hipStream_t st);
+
 }  // namespace sdi

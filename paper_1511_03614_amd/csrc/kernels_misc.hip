@@ -79,9 +79,13 @@ __global__ void k_reduce_pairs(const double* partial, const int32_t* pair_start,
   const int pr = blockIdx.x * blockDim.x + threadIdx.x;
   if (pr >= npairs) return;
   const SecDev& S = secs[pair_sector[pr]];
-  int64_t nf = 0;
-  for (int t = pair_start[pr]; t < pair_start[pr + 1]; ++t) nf += nonfinite[t];
-  pair_nonfinite[pr] = nf;
+  int64_t nf = 0, np = 0;
+  for (int t = pair_start[pr]; t < pair_start[pr + 1]; ++t) {
+    nf += nonfinite[2 * t];
+    np += nonfinite[2 * t + 1];
+  }
+  pair_nonfinite[2 * pr] = nf;
+  pair_nonfinite[2 * pr + 1] = np;
   const double N = (double)(1ull << S.m);
   double qr[KMAX], qi[KMAX];
   for (int kk = 0; kk < KMAX; ++kk) {
@@ -116,10 +120,10 @@ __global__ void k_sector_stats(const double* per_shift, int nsec, int R, double*
   if (gid >= nsec * KMAX) return;
   const int s = gid / KMAX;
   const int k = gid % KMAX;
-  if (k == 0) {
+  if (k < 2) {
     int64_t nf = 0;
-    for (int r = 0; r < R; ++r) nf += pair_nonfinite[(size_t)s * R + r];
-    sec_nonfinite[s] = nf;
+    for (int r = 0; r < R; ++r) nf += pair_nonfinite[2 * ((size_t)s * R + r) + k];
+    sec_nonfinite[2 * s + k] = nf;
   }
   double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0;
   for (int r = 0; r < R; ++r) {
@@ -185,17 +189,17 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(const double* sec_s
       res[k * 4 + 3] = sqrt(sh[0][5]);
     }
   } else {
-    int64_t nf = 0;
-    for (int s = s0; s < s1; ++s) nf += sec_nonfinite[s];
-    si[t] = nf;
-    __syncthreads();
-    for (int w = COMBINE_THREADS / 2; w >= 1; w >>= 1) {
-      if (t < w) si[t] += si[t + w];
+    for (int c = 0; c < 2; ++c) {
+      int64_t nf = 0;
+      for (int s = s0; s < s1; ++s) nf += sec_nonfinite[2 * s + c];
+      si[t] = nf;
       __syncthreads();
-    }
-    if (t == 0) {
-      counts[0] = si[0];
-      counts[1] = 0;
+      for (int w = COMBINE_THREADS / 2; w >= 1; w >>= 1) {
+        if (t < w) si[t] += si[t + w];
+        __syncthreads();
+      }
+      if (t == 0) counts[c] = si[0];
+      __syncthreads();
     }
   }
 }

@@ -61,6 +61,16 @@ struct alignas(16) SecDev {
   double fold_im[KMAX][KMAX];
 };
 
+// Complex-mode tables of one sector, next to its SecDev record.
+struct alignas(16) CplxDev {
+  int32_t nd;                  // derivative polynomials: n first, then n(n+1)/2 second (k <= j)
+  int32_t dir_off;             // offset of this sector's (offset, count) directory [nd][MAXC][2]
+  int32_t mono_f[MAXV];        // exponents of the monomial factored out of F (internal order)
+  int32_t fac_f;               // factor index of F, -1 if none
+  int32_t pad;
+  double lam;
+};
+
 struct alignas(16) TileDesc {
   int32_t sector;
   int32_t shift;      // row in the shift table (final shifts 0..R-1, warm-up R+it)
@@ -81,7 +91,7 @@ struct TileArgs {
   const TileDesc* tiles;     // canonical order
   const int32_t* order;      // processing order (LPT), indices into tiles
   double* partial;           // [ntiles][KMAX][PART_STRIDE]
-  int32_t* nonfinite;        // [ntiles]
+  int32_t* nonfinite;        // [ntiles][2]: non-finite points, points with Im F(z) > 0
   double* hist;              // warm-up histograms [ntiles][n*NB*K] or null
   const int64_t* hist_off;   // per tile offset into hist (doubles)
   int32_t* counter;          // work counter (zeroed by the launcher's fill kernel)

@@ -1,0 +1,44 @@
+// Instances of the complex-mode (contour-deformed) tile kernel and point evaluator.
+#include "kernels.h"
+#include "tiles_cplx.hpp"
+
+namespace sdi {
+
+int launch_tiles_cplx(int nvmax, int ppt, int km, int grid, size_t shmem, const TileArgs& a, const void* cx,
+                      const uint32_t* dir, hipStream_t st) {
+  const CplxArgs X{(const CplxDev*)cx, dir};
+#define SDI_L(NV, P, K)                                                                \
+  if (nvmax == NV && ppt == P && km == K) {                                             \
+    k_tiles_cplx<NV, P, K><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a, X);               \
+    return (int)hipGetLastError();                                                      \
+  }
+  SDI_L(4, 1, 4) SDI_L(4, 2, 4) SDI_L(4, 1, 8) SDI_L(4, 2, 8) SDI_L(8, 1, 4) SDI_L(8, 1, 8)
+#undef SDI_L
+  return (int)hipErrorInvalidValue;
+}
+
+int tiles_cplx_occupancy(int nvmax, int ppt, int km, size_t shmem) {
+  int nb = 0;
+#define SDI_O(NV, P, K)                                                                                    \
+  if (nvmax == NV && ppt == P && km == K) {                                                                 \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles_cplx<NV, P, K>, BLOCK, shmem) != hipSuccess) \
+      return 0;                                                                                             \
+    return nb;                                                                                              \
+  }
+  SDI_O(4, 1, 4) SDI_O(4, 2, 4) SDI_O(4, 1, 8) SDI_O(4, 2, 8) SDI_O(8, 1, 4) SDI_O(8, 1, 8)
+#undef SDI_O
+  return 0;
+}
+
+int launch_eval_points_cplx(int km, const EvalArgs& a, const void* cx, const uint32_t* dir, hipStream_t st) {
+  if (a.npts <= 0) return 0;
+  const CplxArgs X{(const CplxDev*)cx, dir};
+  const unsigned g = (unsigned)((a.npts + BLOCK - 1) / BLOCK);
+  if (km == 4)
+    k_eval_points_cplx<4><<<dim3(g), dim3(BLOCK), 0, st>>>(a, X);
+  else
+    k_eval_points_cplx<8><<<dim3(g), dim3(BLOCK), 0, st>>>(a, X);
+  return (int)hipGetLastError();
+}
+
+}  // namespace sdi

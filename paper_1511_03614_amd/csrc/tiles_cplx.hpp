@@ -1,0 +1,205 @@
+// Persistent multi-sector tile kernel, complex mode (contour deformation).
+// Same scheduling, partial sums and reductions as the real kernel; each tile
+// also counts the points where Im F(z) > 0 (the TestF check of section 4.6).
+#pragma once
+#include "eval_cplx.hpp"
+
+namespace sdi {
+
+struct CplxArgs {
+  const CplxDev* cx;        // [nsec] (tile kernel) or the evaluated sector's record
+  const uint32_t* dir;      // derivative-list directory
+};
+
+template <int NV, int PPT, int KM>
+__device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs& X, const SecDev* __restrict__ S,
+                                              const TileDesc& td, const double* __restrict__ lgrid,
+                                              double* __restrict__ lhist, double (&sr)[KM], double (&cr)[KM],
+                                              double (&si)[KM], double (&ci)[KM], int& nonfin, int& npos) {
+  const uint32_t step = (uint32_t)blockDim.x * PPT;
+  const CplxDev* cx = X.cx + td.sector;
+  for (uint32_t off = threadIdx.x * PPT; off < td.count; off += step) {
+    asm volatile("" ::: "memory");
+    const uint64_t* zp = A.zp + (size_t)td.sector * MAXV;
+    const uint64_t* sh = A.shifts + ((size_t)S->shift_row + td.shift) * MAXV;
+    double x[PPT][NV], w[PPT];
+    int bins[PPT][NV];
+    make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+    cd f[PPT][KM];
+    int imf[PPT];
+    eval_f_cplx<NV, PPT, KM>(S, cx, X.dir, A.terms, x, f, imf);
+    const int kf = S->kf;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        const double vr = w[p] * f[p][k].re;
+        const double vi = w[p] * f[p][k].im;
+        two_sum_acc(sr[k], cr[k], vr);
+        two_sum_acc(si[k], ci[k], vi);
+        bad |= !isfinite(vr) || !isfinite(vi);
+      }
+      nonfin += bad ? 1 : 0;
+      npos += imf[p];
+      if (lhist) {
+        const int n = S->n;
+        const int nb = S->nbins;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (k < kf) {
+            const double v2 = w[p] * w[p] * (f[p][k].re * f[p][k].re + f[p][k].im * f[p][k].im);
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+              if (j < n) atomicAdd(&lhist[((size_t)S->perm[j] * nb + bins[p][j]) * kf + k], v2);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Double-double sum over the 64 lanes of a wave (every lane ends with the total).
+__device__ __forceinline__ void wave_dd_reduce(double hi, double lo, double& ohi, double& olo) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double h2 = __shfl_xor(hi, o, 64);
+    const double l2 = __shfl_xor(lo, o, 64);
+    dd_add(hi, lo, h2, l2);
+  }
+  ohi = hi;
+  olo = lo;
+}
+
+template <int NVMAX, int PPT, int KM>
+__global__ void __launch_bounds__(BLOCK) k_tiles_cplx(TileArgs A, CplxArgs X) {
+  extern __shared__ double smem[];
+  __shared__ int s_tile, s_nonfin, s_pos;
+  __shared__ double s_red[BLOCK / 64][KM][4];
+  constexpr int NVC = NVMAX <= 4 ? 0 : 1;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_tile = atomicAdd(A.counter, 1);
+      s_nonfin = 0;
+      s_pos = 0;
+    }
+    __syncthreads();
+    const int ti = __builtin_amdgcn_readfirstlane(s_tile);
+    if (ti >= A.ntiles) return;
+    const int tc = A.order[ti];
+    const TileDesc td = A.tiles[tc];
+    const SecDev* S = A.secs + td.sector;
+    const int n = S->n;
+    const int nb = S->nbins;
+    const int kf = S->kf;
+    double* lgrid = nullptr;
+    double* lhist = nullptr;
+    size_t soff = 0;
+    if (S->flags & F_USE_GRID) {
+      lgrid = smem;
+      const double* g = A.grids + S->grid_off;
+      for (int i = threadIdx.x; i < n * (nb + 1); i += blockDim.x) lgrid[i] = g[i];
+      soff = (size_t)n * (nb + 1);
+    }
+    if (A.mode == 1) {
+      lhist = smem + soff;
+      for (int i = threadIdx.x; i < n * nb * kf; i += blockDim.x) lhist[i] = 0.0;
+    }
+    __syncthreads();
+    double sr[KM], cr[KM], si[KM], ci[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) { sr[k] = 0.0; cr[k] = 0.0; si[k] = 0.0; ci[k] = 0.0; }
+    int nonfin = 0, npos = 0;
+    switch (S->cls) {
+      case 0:
+        run_tile_cplx<4, PPT, KM>(A, X, S, td, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+        break;
+      case 1:
+        if constexpr (NVC >= 1) run_tile_cplx<8, PPT, KM>(A, X, S, td, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+        break;
+      default:
+        break;
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      double h, l;
+      double hi = sr[k] + cr[k];
+      double lo = cr[k] - (hi - sr[k]);
+      wave_dd_reduce(hi, lo, h, l);
+      double h2, l2;
+      hi = si[k] + ci[k];
+      lo = ci[k] - (hi - si[k]);
+      wave_dd_reduce(hi, lo, h2, l2);
+      if (lane == 0) {
+        s_red[wave][k][0] = h;
+        s_red[wave][k][1] = l;
+        s_red[wave][k][2] = h2;
+        s_red[wave][k][3] = l2;
+      }
+    }
+    if (nonfin) atomicAdd(&s_nonfin, nonfin);
+    if (npos) atomicAdd(&s_pos, npos);
+    __syncthreads();
+    if (threadIdx.x < KM) {
+      const int k = threadIdx.x;
+      double hr = s_red[0][k][0], lr = s_red[0][k][1], hi = s_red[0][k][2], li = s_red[0][k][3];
+      for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) {
+        dd_add(hr, lr, s_red[wv][k][0], s_red[wv][k][1]);
+        dd_add(hi, li, s_red[wv][k][2], s_red[wv][k][3]);
+      }
+      double* out = A.partial + ((size_t)tc * KMAX + k) * PART_STRIDE;
+      out[0] = hr;
+      out[1] = lr;
+      out[2] = hi;
+      out[3] = li;
+    }
+    if (threadIdx.x == 0) {
+      A.nonfinite[2 * tc] = s_nonfin;
+      A.nonfinite[2 * tc + 1] = s_pos;
+    }
+    if (A.mode == 1) {
+      double* gh = A.hist + A.hist_off[tc];
+      for (int i = threadIdx.x; i < n * nb * kf; i += blockDim.x) gh[i] = lhist[i];
+    }
+  }
+}
+
+template <int NV, int KM>
+__device__ __forceinline__ void eval_point_cplx(const EvalArgs& A, const CplxArgs& X, int64_t i) {
+  const SecDev* S = A.sec;
+  const int n = S->n;
+  const int K = S->K;
+  double x[1][NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) x[0][j] = j < n ? A.x[i * n + S->perm[j]] : 0.5;
+  cd f[1][KM];
+  int imf[1];
+  eval_f_cplx<NV, 1, KM>(S, X.cx, X.dir, A.terms, x, f, imf);
+  (void)imf;
+  for (int k = 0; k < K; ++k) {
+    double fr = 0.0, fi = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) {
+      fr += S->fold_re[k][kk] * f[0][kk].re - S->fold_im[k][kk] * f[0][kk].im;
+      fi += S->fold_re[k][kk] * f[0][kk].im + S->fold_im[k][kk] * f[0][kk].re;
+    }
+    A.out[(i * K + k) * 2] = fr;
+    A.out[(i * K + k) * 2 + 1] = fi;
+  }
+}
+
+template <int KM>
+__global__ void __launch_bounds__(BLOCK) k_eval_points_cplx(EvalArgs A, CplxArgs X) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.npts) return;
+  switch (A.sec->cls) {
+    case 0: eval_point_cplx<4, KM>(A, X, i); break;
+    case 1: eval_point_cplx<8, KM>(A, X, i); break;
+    default: break;
+  }
+}
+
+}  // namespace sdi

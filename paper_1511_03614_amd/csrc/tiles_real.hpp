@@ -142,7 +142,10 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
       out[2] = 0.0;
       out[3] = 0.0;
     }
-    if (threadIdx.x == 0) A.nonfinite[tc] = s_nonfin;
+    if (threadIdx.x == 0) {
+      A.nonfinite[2 * tc] = s_nonfin;
+      A.nonfinite[2 * tc + 1] = 0;
+    }
     if (A.mode == 1) {
       double* gh = A.hist + A.hist_off[tc];
       for (int i = threadIdx.x; i < n * nb * kf; i += blockDim.x) gh[i] = lhist[i];
