@@ -119,3 +119,34 @@ def integrate(problem, m: int, nshifts: int, seed: int, baker: bool = True, nbin
            for s in idx]
     val, er, ei = combine(est)
     return est, val, er, ei
+
+
+def neyman_allocation(estimates: List[SectorEstimate], budget: int, nshifts: int, lo: int, hi: int):
+    """Per-sector lattice log2 for a final-pass budget from pilot errors.
+
+    For every order k with a nonzero total T_k = sum_s (err_re^2 + err_im^2),
+    sector s gets the weight sqrt(err_re^2 + err_im^2) / sqrt(T_k); weights add
+    over orders; the sector's share of the budget is proportional to its weight
+    (equal shares if every error is zero), and the lattice log2 is the nearest
+    integer to log2(share / R), clamped to [lo, hi].  Variance-proportional
+    (Neyman) allocation of sampling effort; the paper's integrator adapts
+    points within one integral only (section 4.4), so this reading is stated in
+    DESIGN.md.
+    """
+    nsec = len(estimates)
+    K = estimates[0].mean.shape[0]
+    w = np.zeros(nsec)
+    for k in range(K):
+        tot = sum(e.err_re[k] ** 2 + e.err_im[k] ** 2 for e in estimates)
+        if not tot > 0.0 or not math.isfinite(tot):
+            continue
+        for s, e in enumerate(estimates):
+            w[s] += math.sqrt(e.err_re[k] ** 2 + e.err_im[k] ** 2) / math.sqrt(tot)
+    W = float(np.sum(w))
+    out = []
+    for s in range(nsec):
+        share = budget * w[s] / W if W > 0.0 else budget / nsec
+        x = share / nshifts
+        v = int(math.floor(math.log2(x) + 0.5)) if x >= 1.0 else 0
+        out.append(min(max(v, lo), hi))
+    return out

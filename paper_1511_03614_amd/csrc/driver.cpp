@@ -1,0 +1,734 @@
+// Integration driver: work plans, the cached and graph-captured pass, the
+// points-per-thread autotuner, variance-driven budget allocation, and the
+// integrate / per-sector results / sampling-hook entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "host.h"
+#include "kernels.h"
+
+namespace sdi {
+
+#define HIPCHK(ctx, call)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return fail(ctx, SDI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+#define KCHK(ctx, call)                                                                          \
+  do {                                                                                           \
+    int e_ = (call);                                                                             \
+    if (e_ != 0)                                                                                 \
+      return fail(ctx, SDI_EDEVICE, std::string(#call) + ": " + hipGetErrorString((hipError_t)e_)); \
+  } while (0)
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace carving: a list of (pointer slot, bytes).
+struct Carve {
+  std::vector<std::pair<void**, size_t>> items;
+  void add(void** p, size_t bytes) { items.push_back({p, align256(std::max<size_t>(bytes, 8))}); }
+  size_t total() const {
+    size_t t = 0;
+    for (auto& i : items) t += i.second;
+    return t;
+  }
+  void assign(void* base) {
+    char* b = (char*)base;
+    for (auto& i : items) {
+      *i.first = b;
+      b += i.second;
+    }
+  }
+};
+
+}  // namespace
+
+// Everything one pass needs: per-sector lattice sizes, tiles and their order,
+// the device copy of the sector records for this pass, and workspace slots.
+struct Plan {
+  int R = 0, rows = 0;
+  bool warm = false;
+  std::vector<int> msec;
+  std::vector<SecDev> secs;
+  std::vector<TileDesc> ftiles;
+  std::vector<int32_t> forder, pair_start, pair_sector;
+  std::vector<TileDesc> wtiles;
+  std::vector<int32_t> worder, wsec_start;
+  std::vector<int64_t> whist_off, hsec_off, hsec_prefix;
+  int64_t whist_total = 0, hsec_total = 0;
+  size_t shmem_final = 0, shmem_warm = 0;
+  std::vector<uint64_t> zp_final, zp_warm;
+  SecDev* d_secs = nullptr;
+  TileDesc* d_ftiles = nullptr;
+  int32_t* d_forder = nullptr;
+  int32_t* d_pair_start = nullptr;
+  int32_t* d_pair_sector = nullptr;
+  double* d_partial = nullptr;
+  int32_t* d_nonfinite = nullptr;
+  double* d_per_shift = nullptr;
+  double* d_sec_stats = nullptr;
+  double* d_res = nullptr;
+  int64_t* d_counts = nullptr;
+  int64_t* d_pair_nonfinite = nullptr;
+  int64_t* d_sec_nonfinite = nullptr;
+  int32_t* d_counter = nullptr;
+  uint64_t* d_shifts = nullptr;
+  uint64_t* d_zp_final = nullptr;
+  uint64_t* d_zp_warm = nullptr;
+  TileDesc* d_wtiles = nullptr;
+  int32_t* d_worder = nullptr;
+  int64_t* d_whist_off = nullptr;
+  int32_t* d_wsec_start = nullptr;
+  int32_t* d_wnonfinite = nullptr;
+  double* d_wpartial = nullptr;
+  double* d_whist = nullptr;
+  double* d_hsec = nullptr;
+  int64_t* d_hsec_off = nullptr;
+  int64_t* d_hsec_prefix = nullptr;
+  Carve carve;
+};
+
+struct PassState {
+  std::string key;
+  Plan P;
+  int ppt = 1, km = 4, gf = 1, gw = 1;
+  hipGraphExec_t exec = nullptr;
+  void* own_ws = nullptr;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  ~PassState() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (own_ws) (void)hipFree(own_ws);
+  }
+};
+
+void free_passes(std::vector<PassState*>& v) {
+  for (PassState* p : v) delete p;
+  v.clear();
+}
+
+namespace {
+
+void lpt_order(const std::vector<TileDesc>& tiles, const std::vector<double>& cost, std::vector<int32_t>& order) {
+  order.resize(tiles.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double ca = cost[tiles[a].sector] * tiles[a].count;
+    const double cb = cost[tiles[b].sector] * tiles[b].count;
+    return ca > cb;
+  });
+}
+
+// Grid offsets and parameter-dependent fields of the sector records.
+void sector_fields(const Params& prm, const sdi_problem* pb, const std::vector<int>& msec, int rows,
+                   std::vector<SecDev>& secs, size_t& goff) {
+  secs = pb->secs;
+  goff = 0;
+  for (int s = 0; s < pb->nsec; ++s) {
+    SecDev& S = secs[s];
+    S.m = msec[s];
+    S.mw = prm.mw;
+    S.nbins = prm.nbins;
+    S.shift_row = s * rows;
+    S.grid_off = (int32_t)goff;
+    goff += (size_t)S.n * (prm.nbins + 1);
+    S.flags &= ~(F_USE_GRID | F_BAKER);
+    if (prm.baker) S.flags |= F_BAKER;
+    if (prm.warmup > 0) S.flags |= F_USE_GRID;
+  }
+}
+
+int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& msec, bool warm) {
+  const Params& prm = ctx->params;
+  P.R = prm.R;
+  P.rows = prm.R + prm.warmup;
+  P.warm = warm && prm.warmup > 0;
+  P.msec = msec;
+  const int nsec = pb->nsec;
+  size_t goff = 0;
+  sector_fields(prm, pb, msec, P.rows, P.secs, goff);
+  for (int s = 0; s < nsec; ++s)
+    if (msec[s] < 4 || msec[s] > 30) return fail(ctx, SDI_EINVAL, "lattice log2 outside 4..30");
+  P.pair_start.clear();
+  P.pair_sector.clear();
+  P.ftiles.clear();
+  for (int s = 0; s < nsec; ++s) {
+    const uint32_t N = 1u << msec[s];
+    const uint32_t tsz = std::min<uint32_t>(N, 1u << prm.tile_log2);
+    for (int r = 0; r < prm.R; ++r) {
+      P.pair_start.push_back((int32_t)P.ftiles.size());
+      P.pair_sector.push_back(s);
+      for (uint32_t i0 = 0; i0 < N; i0 += tsz) P.ftiles.push_back(TileDesc{s, r, i0, tsz});
+    }
+  }
+  P.pair_start.push_back((int32_t)P.ftiles.size());
+  lpt_order(P.ftiles, pb->cost, P.forder);
+  P.wtiles.clear();
+  P.whist_off.clear();
+  P.wsec_start.clear();
+  P.hsec_off.clear();
+  P.hsec_prefix.clear();
+  P.whist_total = P.hsec_total = 0;
+  if (P.warm) {
+    const uint32_t Nw = 1u << prm.mw;
+    const uint32_t wsz = std::min<uint32_t>(Nw, 1u << std::min(prm.tile_log2, 12));
+    for (int s = 0; s < nsec; ++s) {
+      const SecDev& S = P.secs[s];
+      P.wsec_start.push_back((int32_t)P.wtiles.size());
+      const int64_t hs = (int64_t)S.n * prm.nbins * std::max(S.kf, 1);
+      P.hsec_off.push_back(P.hsec_total);
+      P.hsec_prefix.push_back(P.hsec_total);
+      P.hsec_total += hs;
+      for (uint32_t i0 = 0; i0 < Nw; i0 += wsz) {
+        P.wtiles.push_back(TileDesc{s, prm.R, i0, wsz});
+        P.whist_off.push_back(P.whist_total);
+        P.whist_total += hs;
+      }
+    }
+    P.wsec_start.push_back((int32_t)P.wtiles.size());
+    lpt_order(P.wtiles, pb->cost, P.worder);
+  }
+  size_t gmax = 0, hmax = 0;
+  for (int s = 0; s < nsec; ++s) {
+    const SecDev& S = P.secs[s];
+    gmax = std::max(gmax, (size_t)S.n * (prm.nbins + 1));
+    hmax = std::max(hmax, (size_t)S.n * prm.nbins * std::max(S.kf, 1));
+  }
+  P.shmem_final = prm.warmup > 0 ? gmax * 8 : 0;
+  P.shmem_warm = (gmax + hmax) * 8;
+  if (P.warm && P.shmem_warm > 64 * 1024)
+    return fail(ctx, SDI_ENOTSUP, "Vegas grid plus histogram exceed 64 KiB of LDS; lower nbins");
+  P.zp_final.assign((size_t)nsec * MAXV, 0);
+  for (int s = 0; s < nsec; ++s) {
+    const std::vector<uint32_t>& zf = lattice_vector16(msec[s]);
+    for (int j = 0; j < MAXV; ++j) P.zp_final[(size_t)s * MAXV + j] = (uint64_t)zf[j] << (53 - msec[s]);
+  }
+  if (P.warm) {
+    const std::vector<uint32_t>& zw = lattice_vector16(prm.mw);
+    P.zp_warm.assign((size_t)nsec * MAXV, 0);
+    for (int s = 0; s < nsec; ++s)
+      for (int j = 0; j < MAXV; ++j) P.zp_warm[(size_t)s * MAXV + j] = (uint64_t)zw[j] << (53 - prm.mw);
+  }
+  Carve& C = P.carve;
+  C.items.clear();
+  const size_t nft = P.ftiles.size(), npairs = P.pair_sector.size();
+  C.add((void**)&P.d_secs, (size_t)nsec * sizeof(SecDev));
+  C.add((void**)&P.d_ftiles, nft * sizeof(TileDesc));
+  C.add((void**)&P.d_forder, nft * 4);
+  C.add((void**)&P.d_pair_start, (npairs + 1) * 4);
+  C.add((void**)&P.d_pair_sector, npairs * 4);
+  C.add((void**)&P.d_partial, nft * KMAX * PART_STRIDE * 8);
+  C.add((void**)&P.d_nonfinite, nft * 8);
+  C.add((void**)&P.d_per_shift, npairs * KMAX * 2 * 8);
+  C.add((void**)&P.d_sec_stats, (size_t)nsec * KMAX * 4 * 8);
+  C.add((void**)&P.d_res, KMAX * 4 * 8);
+  C.add((void**)&P.d_counts, 2 * 8);
+  C.add((void**)&P.d_pair_nonfinite, npairs * 16);
+  C.add((void**)&P.d_sec_nonfinite, (size_t)nsec * 16);
+  C.add((void**)&P.d_counter, 8 * 4);
+  C.add((void**)&P.d_shifts, (size_t)nsec * P.rows * MAXV * 8);
+  C.add((void**)&P.d_zp_final, (size_t)nsec * MAXV * 8);
+  if (P.warm) {
+    const size_t nwt = P.wtiles.size();
+    C.add((void**)&P.d_zp_warm, (size_t)nsec * MAXV * 8);
+    C.add((void**)&P.d_wtiles, nwt * sizeof(TileDesc) * prm.warmup);
+    C.add((void**)&P.d_worder, nwt * 4);
+    C.add((void**)&P.d_whist_off, nwt * 8);
+    C.add((void**)&P.d_wsec_start, (nsec + 1) * 4);
+    C.add((void**)&P.d_wnonfinite, nwt * 8);
+    C.add((void**)&P.d_wpartial, nwt * KMAX * PART_STRIDE * 8);
+    C.add((void**)&P.d_whist, (size_t)P.whist_total * 8);
+    C.add((void**)&P.d_hsec, (size_t)P.hsec_total * 8);
+    C.add((void**)&P.d_hsec_off, nsec * 8);
+    C.add((void**)&P.d_hsec_prefix, nsec * 8);
+  }
+  // persistent Vegas grids live with the problem
+  if (prm.warmup > 0 && (pb->grid_doubles < goff || pb->grid_nbins != prm.nbins)) {
+    if (pb->d_grids) (void)hipFree(pb->d_grids);
+    pb->d_grids = nullptr;
+    pb->grid_doubles = 0;
+    pb->grid_valid = false;
+    HIPCHK(ctx, hipMalloc((void**)&pb->d_grids, goff * 8));
+    pb->grid_doubles = goff;
+    pb->grid_nbins = prm.nbins;
+  }
+  return SDI_OK;
+}
+
+std::vector<int> ppt_candidates(const sdi_problem* pb) {
+  if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{1, 2} : std::vector<int>{1};
+  if (pb->nvmax >= 16) return {1, 2};
+  return {1, 2, 4};
+}
+
+int launch_tiles(const sdi_problem* pb, int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st) {
+  if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
+  return launch_tiles_real(pb->nvmax, ppt, km, grid, shmem, a, st);
+}
+
+int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int ppt, int km, size_t shmem, size_t ntiles) {
+  const int nvmax = pb->nvmax;
+  int occ = pb->complex_mode ? tiles_cplx_occupancy(nvmax, ppt, km, shmem) : tiles_real_occupancy(nvmax, ppt, km, shmem);
+  if (occ < 1) occ = 1;
+  const size_t g = (size_t)occ * std::max(ctx->ncu, 1);
+  return (int)std::max<size_t>(1, std::min(g, ntiles));
+}
+
+std::string pass_key(const Params& p, const std::vector<int>& msec, bool warm, const void* ws, size_t wsb) {
+  char buf[320];
+  unsigned long long h = 1469598103934665603ull;
+  for (int m : msec) h = (h ^ (unsigned)m) * 1099511628211ull;
+  snprintf(buf, sizeof buf, "R%d s%llu b%d w%d/%d mw%d nb%d t%d p%d g%d m%llx ws%p:%zu", p.R,
+           (unsigned long long)p.seed, p.baker, p.warmup, (int)warm, p.mw, p.nbins, p.tile_log2, p.ppt, p.graph, h,
+           ws, wsb);
+  return buf;
+}
+
+TileArgs base_args(const sdi_problem* pb, const Plan& P) {
+  TileArgs A{};
+  A.secs = P.d_secs;
+  A.terms = pb->d_terms;
+  A.shifts = P.d_shifts;
+  A.grids = pb->d_grids;
+  return A;
+}
+
+TileArgs final_args(const sdi_problem* pb, const Plan& P) {
+  TileArgs F = base_args(pb, P);
+  F.zp = P.d_zp_final;
+  F.tiles = P.d_ftiles;
+  F.order = P.d_forder;
+  F.partial = P.d_partial;
+  F.nonfinite = P.d_nonfinite;
+  F.counter = P.d_counter + 1;
+  F.ntiles = (int)P.ftiles.size();
+  F.mode = 0;
+  return F;
+}
+
+// Enqueue one full pass (shifts, warm-up iterations, final pass, reductions) on st.
+int record_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
+  const Params& prm = ctx->params;
+  Plan& P = S.P;
+  const int nsec = pb->nsec;
+  const int npairs = (int)P.pair_sector.size();
+  HIPCHK(ctx, hipEventRecord(S.ev[0], st));
+  KCHK(ctx, launch_shifts(P.d_secs, nsec, P.rows, prm.R, prm.seed, P.d_shifts, st));
+  if (P.warm) {
+    KCHK(ctx, launch_grid_identity(P.d_secs, nsec, pb->d_grids, st));
+    const int nwt = (int)P.wtiles.size();
+    for (int it = 0; it < prm.warmup; ++it) {
+      KCHK(ctx, launch_fill_i32(P.d_counter, 0, 1, st));
+      TileArgs W = base_args(pb, P);
+      W.zp = P.d_zp_warm;
+      W.tiles = P.d_wtiles + (size_t)it * nwt;
+      W.order = P.d_worder;
+      W.partial = P.d_wpartial;
+      W.nonfinite = P.d_wnonfinite;
+      W.hist = P.d_whist;
+      W.hist_off = P.d_whist_off;
+      W.counter = P.d_counter;
+      W.ntiles = nwt;
+      W.mode = 1;
+      KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gw, P.shmem_warm, W, st));
+      KCHK(ctx, launch_hist_reduce(P.d_whist, P.d_whist_off, P.d_wsec_start, P.d_secs, P.d_hsec_off, nsec,
+                                   P.hsec_total, P.d_hsec_prefix, P.d_hsec, st));
+      KCHK(ctx, launch_refit(P.d_secs, nsec, P.d_hsec, P.d_hsec_off, pb->d_grids, 1.5, st));
+    }
+  }
+  HIPCHK(ctx, hipEventRecord(S.ev[1], st));
+  KCHK(ctx, launch_fill_i32(P.d_counter + 1, 0, 1, st));
+  const TileArgs F = final_args(pb, P);
+  HIPCHK(ctx, hipEventRecord(S.ev[2], st));
+  KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gf, P.shmem_final, F, st));
+  HIPCHK(ctx, hipEventRecord(S.ev[3], st));
+  KCHK(ctx, launch_reduce_pairs(P.d_partial, P.d_pair_start, P.d_pair_sector, P.d_secs, npairs, P.d_per_shift,
+                                P.d_nonfinite, P.d_pair_nonfinite, st));
+  KCHK(ctx, launch_sector_stats(P.d_per_shift, nsec, prm.R, P.d_sec_stats, P.d_pair_nonfinite, P.d_sec_nonfinite, st));
+  KCHK(ctx, launch_combine(P.d_sec_stats, nsec, P.d_sec_nonfinite, P.d_res, P.d_counts, st));
+  HIPCHK(ctx, hipEventRecord(S.ev[4], st));
+  return SDI_OK;
+}
+
+// Times the final-pass tile kernel for each points-per-thread candidate on the
+// problem's own tiles and keeps the fastest (cached per device, class and problem shape).
+int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
+  const Params& prm = ctx->params;
+  Plan& P = S.P;
+  char keyb[320];
+  snprintf(keyb, sizeof keyb, "%s|c%d|nv%d|km%d|sec%d|terms%zu|tiles%zu|t%d|grid%d", ctx->prop.gcnArchName,
+           pb->complex_mode, pb->nvmax, S.km, pb->nsec, pb->terms.size(), P.ftiles.size(), prm.tile_log2,
+           prm.warmup > 0);
+  const std::string key(keyb);
+  if (prm.tune == 1)
+    for (auto& kv : ctx->tune_cache)
+      if (kv.first == key) return kv.second;
+  KCHK(ctx, launch_shifts(P.d_secs, pb->nsec, P.rows, prm.R, prm.seed, P.d_shifts, st));
+  if (prm.warmup > 0 && !pb->grid_valid) KCHK(ctx, launch_grid_identity(P.d_secs, pb->nsec, pb->d_grids, st));
+  const TileArgs F = final_args(pb, P);
+  int best = 1;
+  float best_ms = 1e30f;
+  for (int ppt : ppt_candidates(pb)) {
+    const int g = persistent_grid(ctx, pb, ppt, S.km, P.shmem_final, P.ftiles.size());
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      KCHK(ctx, launch_fill_i32(F.counter, 0, 1, st));
+      HIPCHK(ctx, hipEventRecord(S.ev[2], st));
+      KCHK(ctx, launch_tiles(pb, ppt, S.km, g, P.shmem_final, F, st));
+      HIPCHK(ctx, hipEventRecord(S.ev[3], st));
+      HIPCHK(ctx, hipEventSynchronize(S.ev[3]));
+      HIPCHK(ctx, hipEventElapsedTime(&ms, S.ev[2], S.ev[3]));
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = ppt;
+    }
+  }
+  ctx->tune_cache.push_back({key, best});
+  return best;
+}
+
+// The cached pass for (parameters, per-sector lattice sizes, warm-up flag,
+// workspace), built, uploaded, tuned and captured on first use.
+int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool warm, void* dev_ws, size_t ws_bytes,
+             PassState** out) {
+  const Params& prm = ctx->params;
+  const std::string key = pass_key(prm, msec, warm, dev_ws, ws_bytes);
+  for (size_t i = 0; i < pb->passes.size(); ++i)
+    if (pb->passes[i]->key == key) {
+      *out = pb->passes[i];
+      return SDI_OK;
+    }
+  PassState* S = new PassState();
+  int rc = make_plan(ctx, pb, S->P, msec, warm);
+  if (rc != SDI_OK) {
+    delete S;
+    return rc;
+  }
+  Plan& P = S->P;
+  const size_t need = P.carve.total();
+  void* base = dev_ws;
+  if (base) {
+    if (ws_bytes < need) {
+      delete S;
+      return fail(ctx, SDI_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    }
+  } else {
+    if (hipMalloc(&S->own_ws, need) != hipSuccess) {
+      delete S;
+      return fail(ctx, SDI_ENOMEM, "workspace allocation failed");
+    }
+    base = S->own_ws;
+  }
+  P.carve.assign(base);
+  // keep at most four plans; plans on a caller workspace share it, so keep only the newest of those
+  if (dev_ws) {
+    for (size_t i = 0; i < pb->passes.size();)
+      if (!pb->passes[i]->own_ws) {
+        delete pb->passes[i];
+        pb->passes.erase(pb->passes.begin() + i);
+      } else {
+        ++i;
+      }
+  }
+  if (pb->passes.size() >= 4) {
+    delete pb->passes.front();
+    pb->passes.erase(pb->passes.begin());
+  }
+  pb->passes.push_back(S);
+  for (auto& e : S->ev) HIPCHK(ctx, hipEventCreate(&e));
+  hipStream_t st = ctx->stream;
+  const int nsec = pb->nsec;
+  const int npairs = (int)P.pair_sector.size();
+  const int nft = (int)P.ftiles.size();
+  HIPCHK(ctx, hipMemcpyAsync(P.d_secs, P.secs.data(), (size_t)nsec * sizeof(SecDev), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(P.d_ftiles, P.ftiles.data(), nft * sizeof(TileDesc), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(P.d_forder, P.forder.data(), nft * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(P.d_pair_start, P.pair_start.data(), (npairs + 1) * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(P.d_pair_sector, P.pair_sector.data(), npairs * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(P.d_zp_final, P.zp_final.data(), P.zp_final.size() * 8, hipMemcpyHostToDevice, st));
+  std::vector<TileDesc> wall;
+  if (P.warm) {
+    const size_t nwt = P.wtiles.size();
+    wall.reserve(nwt * prm.warmup);
+    for (int it = 0; it < prm.warmup; ++it)
+      for (const TileDesc& t : P.wtiles) wall.push_back(TileDesc{t.sector, prm.R + it, t.i0, t.count});
+    HIPCHK(ctx, hipMemcpyAsync(P.d_zp_warm, P.zp_warm.data(), P.zp_warm.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(P.d_wtiles, wall.data(), wall.size() * sizeof(TileDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(P.d_worder, P.worder.data(), nwt * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(P.d_whist_off, P.whist_off.data(), nwt * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(P.d_wsec_start, P.wsec_start.data(), (nsec + 1) * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(P.d_hsec_off, P.hsec_off.data(), nsec * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(P.d_hsec_prefix, P.hsec_prefix.data(), nsec * 8, hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  S->km = pb->kfmax <= 4 ? 4 : 8;
+  if (prm.ppt > 0) {
+    S->ppt = prm.ppt;
+  } else if (prm.tune == 0) {
+    S->ppt = (pb->nvmax >= 16 || pb->complex_mode) ? 1 : 2;
+  } else {
+    rc = autotune_ppt(ctx, pb, *S, st);
+    if (rc < 0) return rc;
+    S->ppt = rc;
+  }
+  S->gf = persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_final, P.ftiles.size());
+  S->gw = P.warm ? persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_warm, P.wtiles.size()) : 1;
+  if (prm.graph) {
+    // Capture the whole pass once; replays skip the launch overheads.  Any
+    // failure falls back to eager launches for this plan.
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const int rr = record_pass(ctx, pb, *S, st);
+      const hipError_t ec = hipStreamEndCapture(st, &g);
+      if (!(rr == SDI_OK && ec == hipSuccess && g && hipGraphInstantiate(&S->exec, g, nullptr, nullptr, 0) == hipSuccess))
+        S->exec = nullptr;
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+    }
+  }
+  S->key = key;
+  *out = S;
+  return SDI_OK;
+}
+
+struct PassOut {
+  std::vector<double> res, sec_stats, per_shift;
+  int64_t counts[2] = {0, 0};
+  float ms_warm = 0.f, ms_final = 0.f, ms_kernel = 0.f;
+};
+
+int run_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, PassOut& o) {
+  hipStream_t st = ctx->stream;
+  Plan& P = S.P;
+  if (S.exec) {
+    HIPCHK(ctx, hipGraphLaunch(S.exec, st));
+  } else {
+    const int rc = record_pass(ctx, pb, S, st);
+    if (rc != SDI_OK) return rc;
+  }
+  o.res.assign(KMAX * 4, 0.0);
+  o.sec_stats.assign((size_t)pb->nsec * KMAX * 4, 0.0);
+  o.per_shift.assign(P.pair_sector.size() * KMAX * 2, 0.0);
+  HIPCHK(ctx, hipMemcpyAsync(o.res.data(), P.d_res, o.res.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(o.counts, P.d_counts, 16, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(o.sec_stats.data(), P.d_sec_stats, o.sec_stats.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(o.per_shift.data(), P.d_per_shift, o.per_shift.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  (void)hipEventElapsedTime(&o.ms_warm, S.ev[0], S.ev[1]);
+  (void)hipEventElapsedTime(&o.ms_final, S.ev[1], S.ev[4]);
+  (void)hipEventElapsedTime(&o.ms_kernel, S.ev[2], S.ev[3]);
+  return SDI_OK;
+}
+
+}  // namespace
+
+// Neyman-style allocation of the final-pass budget: for every order k with a
+// nonzero total, sector s gets the weight sigma_{s,k} / sqrt(sum_s sigma_{s,k}^2)
+// (sigma^2 = err_re^2 + err_im^2 of the pilot); weights add over orders;
+// n_s = budget * weight_s / sum weight, and m_s = round(log2(n_s / R)) clamped
+// to [alloc_min, alloc_max].  Equal weights when every pilot error is zero.
+std::vector<int> neyman_allocation(const sdi_problem* pb, const std::vector<double>& sec_stats, const Params& prm) {
+  const int nsec = pb->nsec;
+  std::vector<double> wsec(nsec, 0.0);
+  for (int k = 0; k < pb->K; ++k) {
+    double tot = 0.0;
+    for (int s = 0; s < nsec; ++s) {
+      const double* q = sec_stats.data() + ((size_t)s * KMAX + k) * 4;
+      tot += q[2] * q[2] + q[3] * q[3];
+    }
+    if (!(tot > 0.0) || !std::isfinite(tot)) continue;
+    const double rt = std::sqrt(tot);
+    for (int s = 0; s < nsec; ++s) {
+      const double* q = sec_stats.data() + ((size_t)s * KMAX + k) * 4;
+      wsec[s] += std::sqrt(q[2] * q[2] + q[3] * q[3]) / rt;
+    }
+  }
+  double W = 0.0;
+  for (double w : wsec) W += w;
+  std::vector<int> m(nsec);
+  for (int s = 0; s < nsec; ++s) {
+    const double ns = W > 0.0 ? (double)prm.budget * wsec[s] / W : (double)prm.budget / nsec;
+    const double x = ns / prm.R;
+    int v = x >= 1.0 ? (int)std::lround(std::log2(x)) : 0;
+    m[s] = std::min(std::max(v, prm.alloc_min), prm.alloc_max);
+  }
+  return m;
+}
+
+}  // namespace sdi
+
+using namespace sdi;
+
+extern "C" {
+
+size_t sdi_workspace_bytes(sdi_ctx* ctx, const sdi_problem* prob) {
+  if (!ctx || !prob) return 0;
+  const Params& prm = ctx->params;
+  Plan P;
+  sdi_problem tmp = *prob;        // make_plan may resize the problem's grids; plan on a copy
+  tmp.passes.clear();
+  tmp.d_grids = nullptr;
+  tmp.grid_doubles = (size_t)-1;
+  tmp.grid_nbins = prm.nbins;
+  // with allocation the largest final pass is every sector at alloc_max
+  const int m = prm.budget > 0 ? prm.alloc_max : prm.m;
+  const int rc = make_plan(ctx, &tmp, P, std::vector<int>(prob->nsec, m), prm.budget == 0);
+  return rc == SDI_OK ? P.carve.total() : 0;
+}
+
+int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, sdi_result* out) {
+  if (!ctx || !pb || !out) return fail(ctx, SDI_EINVAL, "integrate: null argument");
+  if (pb->ctx != ctx) return fail(ctx, SDI_EINVAL, "problem belongs to another context");
+  if (!out->val_re || !out->val_im || !out->err_re || !out->err_im)
+    return fail(ctx, SDI_EINVAL, "integrate: result arrays must be allocated");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const Params& prm = ctx->params;
+  if (prm.budget > 0 && dev_ws) return fail(ctx, SDI_ENOTSUP, "budget allocation needs the library workspace");
+  if (prm.alloc_min > prm.alloc_max) return fail(ctx, SDI_EINVAL, "alloc_min_log2 > alloc_max_log2");
+  const int nsec = pb->nsec;
+  PassOut o;
+  float ms_pilot = 0.f;
+  int64_t pilot_evals = 0;
+  std::vector<int> msec(nsec, prm.m);
+  bool warm = prm.warmup > 0;
+  PassState* S = nullptr;
+  int rc;
+  if (prm.budget > 0) {
+    rc = get_pass(ctx, pb, std::vector<int>(nsec, prm.pilot_log2), warm, nullptr, 0, &S);
+    if (rc != SDI_OK) return rc;
+    rc = run_pass(ctx, pb, *S, o);
+    if (rc != SDI_OK) return rc;
+    ms_pilot = o.ms_warm + o.ms_final;
+    if (prm.warmup > 0) pb->grid_valid = true;   // the final pass reuses the adapted grids
+    pilot_evals = ((int64_t)prm.R << prm.pilot_log2) * nsec;
+    msec = neyman_allocation(pb, o.sec_stats, prm);
+    warm = false;
+  }
+  rc = get_pass(ctx, pb, msec, warm, dev_ws, ws_bytes, &S);
+  if (rc != SDI_OK) return rc;
+  const bool had_warm = S->P.warm;
+  rc = run_pass(ctx, pb, *S, o);
+  if (rc != SDI_OK) return rc;
+  if (prm.warmup > 0 && (had_warm || prm.budget > 0)) pb->grid_valid = true;
+  if (prm.warmup == 0) pb->grid_valid = false;
+  pb->last_R = prm.R;
+  pb->have_results = true;
+  pb->sec_stats = o.sec_stats;
+  pb->per_shift = o.per_shift;
+  pb->sec_evals.assign(nsec, 0);
+  int64_t final_evals = 0;
+  for (int s = 0; s < nsec; ++s) {
+    pb->sec_evals[s] = (int64_t)prm.R << msec[s];
+    final_evals += pb->sec_evals[s];
+  }
+  out->order_min = pb->order_min;
+  out->norders = pb->K;
+  for (int k = 0; k < pb->K; ++k) {
+    out->val_re[k] = o.res[k * 4 + 0];
+    out->val_im[k] = o.res[k * 4 + 1];
+    out->err_re[k] = o.res[k * 4 + 2];
+    out->err_im[k] = o.res[k * 4 + 3];
+  }
+  out->n_evals = final_evals + pilot_evals + (prm.warmup > 0 ? (int64_t)prm.warmup * nsec * ((int64_t)1 << prm.mw) : 0);
+  out->n_nonfinite = o.counts[0];
+  out->n_imf_positive = o.counts[1];
+  out->ms_sample_eval_reduce = o.ms_final;
+  out->ms_refit = o.ms_warm + ms_pilot;
+  out->ms_total = o.ms_warm + o.ms_final + ms_pilot;
+  out->ms_eval_kernel = o.ms_kernel;
+  out->points_per_thread = S->ppt;
+  out->blocks = S->gf;
+  return o.counts[0] ? fail(ctx, SDI_ENONFINITE, "non-finite integrand values") : SDI_OK;
+}
+
+int sdi_sector_results(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, double* mean, double* err, double* per_shift,
+                       int64_t* nevals) {
+  if (!ctx || !pb || !mean || !err) return fail(ctx, SDI_EINVAL, "sector_results: null argument");
+  if (!pb->have_results) return fail(ctx, SDI_ESTATE, "no integration has run on this problem");
+  if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");
+  for (int k = 0; k < pb->K; ++k) {
+    const double* q = pb->sec_stats.data() + ((size_t)s * KMAX + k) * 4;
+    mean[2 * k] = q[0];
+    mean[2 * k + 1] = q[1];
+    err[2 * k] = q[2];
+    err[2 * k + 1] = q[3];
+  }
+  if (per_shift)
+    for (int r = 0; r < pb->last_R; ++r)
+      for (int k = 0; k < pb->K; ++k) {
+        const double* q = pb->per_shift.data() + (((size_t)s * pb->last_R + r) * KMAX + k) * 2;
+        per_shift[((size_t)r * pb->K + k) * 2] = q[0];
+        per_shift[((size_t)r * pb->K + k) * 2 + 1] = q[1];
+      }
+  if (nevals) *nevals = pb->sec_evals[s];
+  return SDI_OK;
+}
+
+int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, int32_t shift, int64_t i0, int64_t npts,
+                      void* x_dev, void* w_dev) {
+  if (!ctx || !pb || (!x_dev && npts > 0)) return fail(ctx, SDI_EINVAL, "sample_points: null argument");
+  if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");
+  const Params& prm = ctx->params;
+  if (shift < 0 || shift >= prm.R) return fail(ctx, SDI_EINVAL, "shift index out of range");
+  if (npts < 0 || i0 < 0 || i0 + npts > ((int64_t)1 << prm.m)) return fail(ctx, SDI_EINVAL, "point range outside the lattice");
+  if (npts == 0) return SDI_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  // this sector's record under the current parameters, on its own device copy
+  const int rows = prm.R + prm.warmup;
+  std::vector<SecDev> secs;
+  size_t goff = 0;
+  sector_fields(prm, pb, std::vector<int>(pb->nsec, prm.m), rows, secs, goff);
+  const bool use_grid = pb->grid_valid && prm.warmup > 0 && pb->d_grids && pb->grid_nbins == prm.nbins &&
+                        pb->grid_doubles >= goff;
+  SecDev one = secs[s];
+  if (!use_grid) one.flags &= ~F_USE_GRID;
+  one.shift_row = 0;
+  std::vector<uint64_t> zp(MAXV);
+  const std::vector<uint32_t>& z = lattice_vector16(prm.m);
+  for (int j = 0; j < MAXV; ++j) zp[j] = (uint64_t)z[j] << (53 - prm.m);
+  hipStream_t st = ctx->stream;
+  SecDev* d_one = nullptr;
+  uint64_t* d_sh = nullptr;
+  uint64_t* d_zp = nullptr;
+  hipError_t he = hipMalloc((void**)&d_one, sizeof(SecDev));
+  if (he == hipSuccess) he = hipMalloc((void**)&d_sh, (size_t)(shift + 1) * MAXV * 8);
+  if (he == hipSuccess) he = hipMalloc((void**)&d_zp, MAXV * 8);
+  int e = 0;
+  if (he == hipSuccess) he = hipMemcpyAsync(d_one, &one, sizeof(SecDev), hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(d_zp, zp.data(), MAXV * 8, hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) e = launch_shifts(d_one, 1, shift + 1, shift + 1, prm.seed, d_sh, st);
+  if (he == hipSuccess && e == 0) {
+    SampleArgs A{};
+    A.sec = d_one;
+    A.zp = d_zp;
+    A.shift = d_sh + (size_t)shift * MAXV;
+    A.grid = use_grid ? pb->d_grids + secs[s].grid_off : nullptr;
+    A.x = (double*)x_dev;
+    A.w = (double*)w_dev;
+    A.i0 = (uint64_t)i0;
+    A.npts = npts;
+    e = launch_sample_points(A, st);
+  }
+  const hipError_t hs = hipStreamSynchronize(st);
+  if (d_one) (void)hipFree(d_one);
+  if (d_sh) (void)hipFree(d_sh);
+  if (d_zp) (void)hipFree(d_zp);
+  if (he != hipSuccess) return fail(ctx, SDI_EDEVICE, std::string("sample setup: ") + hipGetErrorString(he));
+  if (e != 0) return fail(ctx, SDI_EDEVICE, std::string("sample kernel: ") + hipGetErrorString((hipError_t)e));
+  if (hs != hipSuccess) return fail(ctx, SDI_EDEVICE, std::string("sample sync: ") + hipGetErrorString(hs));
+  return SDI_OK;
+}
+
+}  // extern "C"

@@ -178,7 +178,6 @@ __device__ __forceinline__ void eval_f_cplx(const SecDev* __restrict__ S, const 
     for (int k = 0; k < KM; ++k) f[p][k] = cd{0.0, 0.0};
   }
   const int C = 1 << ns;
-  const int nd = X->nd;
   for (int W = 0; W < C; ++W) {
     // corner point y: singular variables in W are zero
     double y[PPT][NV];

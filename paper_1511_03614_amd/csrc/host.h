@@ -9,6 +9,8 @@
 #include "../../include/sdint.h"
 #include "sdint_internal.h"
 
+struct sdi_ctx;
+
 namespace sdi {
 
 struct Params {
@@ -23,9 +25,16 @@ struct Params {
   int ppt = 0;           // 0: autotune
   int tune = 1;          // 0 off, 1 cached, 2 search
   int graph = 1;         // capture the pass into a hipGraph and replay it
+  int64_t budget = 0;    // total final-pass evaluations to distribute by variance (0: uniform m)
+  int alloc_min = 12;    // bounds of the per-sector lattice log2 under allocation
+  int alloc_max = 20;
+  int pilot_log2 = 12;   // lattice log2 of the pilot pass that measures the variances
 };
 
 const std::vector<uint32_t>& lattice_vector16(int m);
+struct PassState;
+void free_passes(std::vector<PassState*>& v);
+int fail(sdi_ctx* ctx, int code, const std::string& msg);
 int prefactor_series(int loops, const int32_t* idx, int nprops, int d0, int len, int* lead, double* out,
                      std::string& err);
 
@@ -41,10 +50,6 @@ struct sdi_ctx {
   int ncu = 0;
   std::vector<std::pair<std::string, int>> tune_cache;   // key -> ppt
 };
-
-namespace sdi {
-struct PassState;   // cached plan, uploaded tables and captured graph (api.cpp)
-}
 
 struct sdi_problem {
   sdi_ctx* ctx = nullptr;
@@ -67,7 +72,7 @@ struct sdi_problem {
   std::vector<double> sec_stats;      // [nsec][KMAX][4]
   std::vector<double> per_shift;      // [nsec*R][KMAX][2]
   std::vector<int64_t> sec_evals;
-  sdi::PassState* pass = nullptr;
+  std::vector<sdi::PassState*> passes;   // cached plans (most recent last)
   // complex mode
   std::vector<sdi::CplxDev> cx;
   std::vector<uint32_t> dir;

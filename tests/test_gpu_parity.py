@@ -329,3 +329,32 @@ def test_graph_with_warmup_matches_eager(ctx):
         P.sdi_problem_destroy(h)
         P.sdi_set_param(ctx, "graph", 1)
         P.sdi_set_param(ctx, "warmup", 0)
+
+
+def test_budget_allocation_matches_oracle(ctx):
+    """Pilot pass, variance-driven lattice sizes, final pass: sizes equal the oracle's rule
+    applied to the oracle's own pilot, and the final per-shift means agree."""
+    prob = sectorgen.config2()
+    prob.sectors = prob.sectors[:12]
+    R, pilot, lo, hi = 4, 8, 6, 12
+    budget = 12 * R * (1 << 9)
+    set_params(ctx, shifts=R, seed=31, budget=budget, pilot_log2=pilot, alloc_min_log2=lo, alloc_max_log2=hi)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        res = P.sdi_integrate(ctx, h)
+        lead, pref = integrate.prefactor_for(prob)
+        est = [integrate.integrate_sector(prob, s, pilot, R, 31, lead, pref) for s in range(12)]
+        m_or = integrate.neyman_allocation(est, budget, R, lo, hi)
+        m_gpu = []
+        for s in range(12):
+            _, _, per, nev = P.sdi_sector_results(ctx, h, s, R)
+            m_gpu.append(int(nev // R).bit_length() - 1)
+            if s % 4 == 0:
+                oq, scale = oracle_shift_values(prob, s, m_or[s], R, 31)
+                assert_close_shift(per, oq, scale, f"allocated sector {s}")
+        assert m_gpu == m_or
+        assert len(set(m_gpu)) > 1                      # the allocation is not uniform
+        assert res["n_evals"] == sum(R << m for m in m_gpu) + 12 * (R << pilot)
+    finally:
+        P.sdi_problem_destroy(h)
+        P.sdi_set_param(ctx, "budget", 0)

@@ -379,3 +379,17 @@ def test_box_worked_example_section_4_3():
         assert abs(got - v) < 3 * e + 5e-5
     exact = [4 / 3, -2 * math.log(3) / 3, -4 * math.pi ** 2 / 9]
     assert np.allclose(tot, exact, rtol=2e-6, atol=2e-6)
+
+
+def test_neyman_allocation_properties():
+    """Shares follow the errors, clamps hold, equal errors give equal sizes."""
+    from oracle.integrate import SectorEstimate, neyman_allocation
+
+    def est(e):
+        return SectorEstimate(np.zeros((2, 1), complex), np.zeros(1, complex), np.array([e]), np.array([0.0]), 0, 0, None)
+    m = neyman_allocation([est(1.0), est(4.0), est(0.25)], 3 * 16 * 1024, 16, 4, 20)
+    assert m[1] > m[0] > m[2]
+    assert m[1] - m[0] == 2 and m[0] - m[2] == 2
+    assert neyman_allocation([est(1.0)] * 4, 4 * 16 * 1024, 16, 4, 20) == [10] * 4
+    assert neyman_allocation([est(0.0)] * 3, 3 * 16 * 256, 16, 4, 20) == [8] * 3
+    assert neyman_allocation([est(1e9), est(1e-9)], 1 << 40, 16, 6, 12) == [12, 6]
