@@ -111,7 +111,8 @@ def test_integrate_massive_bubble(ctx):
     beta = math.sqrt(1 - 4 / 5.0)
     fin = 2 - beta * math.log((1 + beta) / (1 - beta)) + 1j * math.pi * beta
     v = res["value"]
-    assert abs(v[0] - 1.0) < 1e-9
+    assert abs(v[0].real - 1.0) < 6 * res["err_re"][0] + 1e-12
+    assert abs(v[0].imag) < 6 * res["err_im"][0] + 1e-12
     assert abs(v[1].real - fin.real) < 6 * res["err_re"][1] + 1e-9
     assert abs(v[1].imag - fin.imag) < 6 * res["err_im"][1] + 1e-9
 
