@@ -469,6 +469,7 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_d
   if (npts < 0) return fail(ctx, SDI_EINVAL, "negative point count");
   if (npts == 0) return SDI_OK;
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
   EvalArgs A{};
   A.sec = pb->d_secs + s;
   A.terms = pb->d_terms;

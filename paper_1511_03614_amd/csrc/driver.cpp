@@ -102,14 +102,16 @@ struct PassState {
   std::string key;
   Plan P;
   int ppt = 1, km = 4, gf = 1, gw = 1;
-  hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};   // warm-up, final tiles, reductions
   void* own_ws = nullptr;
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // recorded between segment launches
   ~PassState() {
-    if (exec) (void)hipGraphExecDestroy(exec);
+    for (hipGraphExec_t x : exec)
+      if (x) (void)hipGraphExecDestroy(x);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
     if (own_ws) (void)hipFree(own_ws);
+    (void)hipGetLastError();
   }
 };
 
@@ -317,47 +319,47 @@ TileArgs final_args(const sdi_problem* pb, const Plan& P) {
   return F;
 }
 
-// Enqueue one full pass (shifts, warm-up iterations, final pass, reductions) on st.
-int record_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
+// Enqueue one segment of a pass on st: 0 = shifts and warm-up iterations,
+// 1 = the final-pass tile kernel, 2 = reductions and combination.
+int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStream_t st) {
   const Params& prm = ctx->params;
   Plan& P = S.P;
   const int nsec = pb->nsec;
   const int npairs = (int)P.pair_sector.size();
-  HIPCHK(ctx, hipEventRecord(S.ev[0], st));
-  KCHK(ctx, launch_shifts(P.d_secs, nsec, P.rows, prm.R, prm.seed, P.d_shifts, st));
-  if (P.warm) {
-    KCHK(ctx, launch_grid_identity(P.d_secs, nsec, pb->d_grids, st));
-    const int nwt = (int)P.wtiles.size();
-    for (int it = 0; it < prm.warmup; ++it) {
-      KCHK(ctx, launch_fill_i32(P.d_counter, 0, 1, st));
-      TileArgs W = base_args(pb, P);
-      W.zp = P.d_zp_warm;
-      W.tiles = P.d_wtiles + (size_t)it * nwt;
-      W.order = P.d_worder;
-      W.partial = P.d_wpartial;
-      W.nonfinite = P.d_wnonfinite;
-      W.hist = P.d_whist;
-      W.hist_off = P.d_whist_off;
-      W.counter = P.d_counter;
-      W.ntiles = nwt;
-      W.mode = 1;
-      KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gw, P.shmem_warm, W, st));
-      KCHK(ctx, launch_hist_reduce(P.d_whist, P.d_whist_off, P.d_wsec_start, P.d_secs, P.d_hsec_off, nsec,
-                                   P.hsec_total, P.d_hsec_prefix, P.d_hsec, st));
-      KCHK(ctx, launch_refit(P.d_secs, nsec, P.d_hsec, P.d_hsec_off, pb->d_grids, 1.5, st));
+  if (seg == 0) {
+    KCHK(ctx, launch_shifts(P.d_secs, nsec, P.rows, prm.R, prm.seed, P.d_shifts, st));
+    if (P.warm) {
+      KCHK(ctx, launch_grid_identity(P.d_secs, nsec, pb->d_grids, st));
+      const int nwt = (int)P.wtiles.size();
+      for (int it = 0; it < prm.warmup; ++it) {
+        KCHK(ctx, launch_fill_i32(P.d_counter, 0, 1, st));
+        TileArgs W = base_args(pb, P);
+        W.zp = P.d_zp_warm;
+        W.tiles = P.d_wtiles + (size_t)it * nwt;
+        W.order = P.d_worder;
+        W.partial = P.d_wpartial;
+        W.nonfinite = P.d_wnonfinite;
+        W.hist = P.d_whist;
+        W.hist_off = P.d_whist_off;
+        W.counter = P.d_counter;
+        W.ntiles = nwt;
+        W.mode = 1;
+        KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gw, P.shmem_warm, W, st));
+        KCHK(ctx, launch_hist_reduce(P.d_whist, P.d_whist_off, P.d_wsec_start, P.d_secs, P.d_hsec_off, nsec,
+                                     P.hsec_total, P.d_hsec_prefix, P.d_hsec, st));
+        KCHK(ctx, launch_refit(P.d_secs, nsec, P.d_hsec, P.d_hsec_off, pb->d_grids, 1.5, st));
+      }
     }
+  } else if (seg == 1) {
+    KCHK(ctx, launch_fill_i32(P.d_counter + 1, 0, 1, st));
+    KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gf, P.shmem_final, final_args(pb, P), st));
+  } else {
+    KCHK(ctx, launch_reduce_pairs(P.d_partial, P.d_pair_start, P.d_pair_sector, P.d_secs, npairs, P.d_per_shift,
+                                  P.d_nonfinite, P.d_pair_nonfinite, st));
+    KCHK(ctx, launch_sector_stats(P.d_per_shift, nsec, prm.R, P.d_sec_stats, P.d_pair_nonfinite, P.d_sec_nonfinite,
+                                  st));
+    KCHK(ctx, launch_combine(P.d_sec_stats, nsec, P.d_sec_nonfinite, P.d_res, P.d_counts, st));
   }
-  HIPCHK(ctx, hipEventRecord(S.ev[1], st));
-  KCHK(ctx, launch_fill_i32(P.d_counter + 1, 0, 1, st));
-  const TileArgs F = final_args(pb, P);
-  HIPCHK(ctx, hipEventRecord(S.ev[2], st));
-  KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gf, P.shmem_final, F, st));
-  HIPCHK(ctx, hipEventRecord(S.ev[3], st));
-  KCHK(ctx, launch_reduce_pairs(P.d_partial, P.d_pair_start, P.d_pair_sector, P.d_secs, npairs, P.d_per_shift,
-                                P.d_nonfinite, P.d_pair_nonfinite, st));
-  KCHK(ctx, launch_sector_stats(P.d_per_shift, nsec, prm.R, P.d_sec_stats, P.d_pair_nonfinite, P.d_sec_nonfinite, st));
-  KCHK(ctx, launch_combine(P.d_sec_stats, nsec, P.d_sec_nonfinite, P.d_res, P.d_counts, st));
-  HIPCHK(ctx, hipEventRecord(S.ev[4], st));
   return SDI_OK;
 }
 
@@ -384,11 +386,11 @@ int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       KCHK(ctx, launch_fill_i32(F.counter, 0, 1, st));
-      HIPCHK(ctx, hipEventRecord(S.ev[2], st));
+      HIPCHK(ctx, hipEventRecord(S.ev[1], st));
       KCHK(ctx, launch_tiles(pb, ppt, S.km, g, P.shmem_final, F, st));
-      HIPCHK(ctx, hipEventRecord(S.ev[3], st));
-      HIPCHK(ctx, hipEventSynchronize(S.ev[3]));
-      HIPCHK(ctx, hipEventElapsedTime(&ms, S.ev[2], S.ev[3]));
+      HIPCHK(ctx, hipEventRecord(S.ev[2], st));
+      HIPCHK(ctx, hipEventSynchronize(S.ev[2]));
+      HIPCHK(ctx, hipEventElapsedTime(&ms, S.ev[1], S.ev[2]));
     }
     if (ms < best_ms) {
       best_ms = ms;
@@ -486,17 +488,24 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   S->gf = persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_final, P.ftiles.size());
   S->gw = P.warm ? persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_warm, P.wtiles.size()) : 1;
   if (prm.graph) {
-    // Capture the whole pass once; replays skip the launch overheads.  Any
-    // failure falls back to eager launches for this plan.
-    hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-      const int rr = record_pass(ctx, pb, *S, st);
+    // Capture each segment once; replays skip the launch overheads.  Timing
+    // events stay outside the graphs, between segment launches.  Any failure
+    // falls back to eager launches for that segment.
+    for (int seg = 0; seg < 3; ++seg) {
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      const int rr = record_segment(ctx, pb, *S, seg, st);
       const hipError_t ec = hipStreamEndCapture(st, &g);
-      if (!(rr == SDI_OK && ec == hipSuccess && g && hipGraphInstantiate(&S->exec, g, nullptr, nullptr, 0) == hipSuccess))
-        S->exec = nullptr;
+      if (!(rr == SDI_OK && ec == hipSuccess && g &&
+            hipGraphInstantiate(&S->exec[seg], g, nullptr, nullptr, 0) == hipSuccess))
+        S->exec[seg] = nullptr;
       if (g) (void)hipGraphDestroy(g);
       (void)hipGetLastError();
     }
+    ctx->err.clear();
   }
   S->key = key;
   *out = S;
@@ -512,12 +521,16 @@ struct PassOut {
 int run_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, PassOut& o) {
   hipStream_t st = ctx->stream;
   Plan& P = S.P;
-  if (S.exec) {
-    HIPCHK(ctx, hipGraphLaunch(S.exec, st));
-  } else {
-    const int rc = record_pass(ctx, pb, S, st);
-    if (rc != SDI_OK) return rc;
+  for (int seg = 0; seg < 3; ++seg) {
+    HIPCHK(ctx, hipEventRecord(S.ev[seg], st));
+    if (S.exec[seg]) {
+      HIPCHK(ctx, hipGraphLaunch(S.exec[seg], st));
+    } else {
+      const int rc = record_segment(ctx, pb, S, seg, st);
+      if (rc != SDI_OK) return rc;
+    }
   }
+  HIPCHK(ctx, hipEventRecord(S.ev[3], st));
   o.res.assign(KMAX * 4, 0.0);
   o.sec_stats.assign((size_t)pb->nsec * KMAX * 4, 0.0);
   o.per_shift.assign(P.pair_sector.size() * KMAX * 2, 0.0);
@@ -526,9 +539,9 @@ int run_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, PassOut& o) {
   HIPCHK(ctx, hipMemcpyAsync(o.sec_stats.data(), P.d_sec_stats, o.sec_stats.size() * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipMemcpyAsync(o.per_shift.data(), P.d_per_shift, o.per_shift.size() * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
-  (void)hipEventElapsedTime(&o.ms_warm, S.ev[0], S.ev[1]);
-  (void)hipEventElapsedTime(&o.ms_final, S.ev[1], S.ev[4]);
-  (void)hipEventElapsedTime(&o.ms_kernel, S.ev[2], S.ev[3]);
+  HIPCHK(ctx, hipEventElapsedTime(&o.ms_warm, S.ev[0], S.ev[1]));
+  HIPCHK(ctx, hipEventElapsedTime(&o.ms_kernel, S.ev[1], S.ev[2]));
+  HIPCHK(ctx, hipEventElapsedTime(&o.ms_final, S.ev[1], S.ev[3]));
   return SDI_OK;
 }
 
@@ -594,6 +607,7 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   if (!out->val_re || !out->val_im || !out->err_re || !out->err_im)
     return fail(ctx, SDI_EINVAL, "integrate: result arrays must be allocated");
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
   const Params& prm = ctx->params;
   if (prm.budget > 0 && dev_ws) return fail(ctx, SDI_ENOTSUP, "budget allocation needs the library workspace");
   if (prm.alloc_min > prm.alloc_max) return fail(ctx, SDI_EINVAL, "alloc_min_log2 > alloc_max_log2");
@@ -685,6 +699,7 @@ int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, int32_t sh
   if (npts < 0 || i0 < 0 || i0 + npts > ((int64_t)1 << prm.m)) return fail(ctx, SDI_EINVAL, "point range outside the lattice");
   if (npts == 0) return SDI_OK;
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
   // this sector's record under the current parameters, on its own device copy
   const int rows = prm.R + prm.warmup;
   std::vector<SecDev> secs;

@@ -301,6 +301,7 @@ def test_graph_replays_match_eager(ctx):
             junk = torch.randn(4096, device="cuda").mul_(3.0).sum().item()
             torch.cuda.synchronize()
             g = P.sdi_integrate(ctx, h)
+            assert g["ms_eval_kernel"] > 0 and g["ms_total"] >= g["ms_eval_kernel"]
             assert np.array_equal(g["value"], eager["value"]), rep
             assert np.array_equal(g["err_re"], eager["err_re"]), rep
             per_g = [P.sdi_sector_results(ctx, h, s, 4)[2] for s in range(0, 64, 7)]
