@@ -5,6 +5,7 @@
 
 #include "eval_real.hpp"
 #include "kernels.h"
+#include "philox.hpp"
 
 namespace sdi {
 
@@ -16,26 +17,6 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
 }
 
 // ------------------------------------------------------------ Philox4x32-10 shifts
-
-__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint32_t lo0 = 0xD2511F53u * c[0];
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
-    const uint32_t lo1 = 0xCD9E8D57u * c[2];
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
-    const uint32_t n0 = hi1 ^ c[1] ^ k0;
-    const uint32_t n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-  }
-}
 
 // D_{s,r,j}: 53 bits (word0 << 21 | word1 >> 11) of Philox(key = seed, counter =
 // (j, r, s, t)), redrawn (t = 1, 2, ...) while D is a multiple of 2^(53-m).
@@ -87,8 +68,13 @@ __global__ void k_reduce_pairs(const double* partial, const int32_t* pair_start,
   pair_nonfinite[2 * pr] = nf;
   pair_nonfinite[2 * pr + 1] = np;
   const double N = (double)(1ull << S.m);
+  // only the sector's kf internal orders are written by the tile kernels
+  const int kf = S.kf;
   double qr[KMAX], qi[KMAX];
   for (int kk = 0; kk < KMAX; ++kk) {
+    qr[kk] = 0.0;
+    qi[kk] = 0.0;
+    if (kk >= kf) continue;
     double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0;
     for (int t = pair_start[pr]; t < pair_start[pr + 1]; ++t) {
       const double* p = partial + ((size_t)t * KMAX + kk) * PART_STRIDE;
@@ -101,7 +87,7 @@ __global__ void k_reduce_pairs(const double* partial, const int32_t* pair_start,
   for (int k = 0; k < KMAX; ++k) {
     double re = 0.0, im = 0.0;
     if (k < S.K) {
-      for (int kk = 0; kk < KMAX; ++kk) {
+      for (int kk = 0; kk < kf; ++kk) {
         re += S.fold_re[k][kk] * qr[kk] - S.fold_im[k][kk] * qi[kk];
         im += S.fold_re[k][kk] * qi[kk] + S.fold_im[k][kk] * qr[kk];
       }

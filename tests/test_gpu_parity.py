@@ -209,7 +209,8 @@ def test_integrate_deterministic_and_workspace(ctx):
         a = P.sdi_integrate(ctx, h)
         b = P.sdi_integrate(ctx, h)
         nb = P.sdi_workspace_bytes(ctx, h)
-        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        # a caller workspace full of NaN bytes: nothing may be read before it is written
+        ws = torch.full((nb,), 255, dtype=torch.uint8, device="cuda")
         c = P.sdi_integrate(ctx, h, ws)
         for r in (b, c):
             assert np.array_equal(a["value"], r["value"])
