@@ -16,7 +16,8 @@ Definition (one flow per sector, n variables):
   conditions on A_l = the others (for n = 1, B_l = {0} and A_l is empty);
 * MLP_l: a0 = bf16(2 h_A - 1); a1 = bf16(relu(W1 a0 + b1)); a2 = bf16(relu(W2 a1 + b2));
   logits = W3 a2 + b3 with bf16 weights, H = 64 hidden units, NB = 32 logits per
-  transformed variable;
+  transformed variable; every bf16 rounding (weights, input, activations) is
+  straight-through in the gradient;
 * Q_{j,k} = softmax_k(logits_j): bin probabilities of variable j;
 * forward (data h -> latent y), per j in B_l: b = min(floor(h_j NB), NB - 1),
   y_j = sum_{k<b} Q_k + (h_j NB - b) Q_b, log J += log(NB Q_b);
@@ -120,7 +121,7 @@ def _probs(p: dict, hA: torch.Tensor, nb: int) -> torch.Tensor:
     if hA.shape[1] == 0:
         a0 = torch.zeros((npts, 1), dtype=torch.float64)
     else:
-        a0 = bf16(2.0 * hA - 1.0)
+        a0 = ste_bf16(2.0 * hA - 1.0)
     a1 = ste_bf16(torch.relu(a0 @ ste_bf16(p["W1"]).T + p["b1"]))
     a2 = ste_bf16(torch.relu(a1 @ ste_bf16(p["W2"]).T + p["b2"]))
     logits = a2 @ ste_bf16(p["W3"]).T + p["b3"]
