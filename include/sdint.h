@@ -75,6 +75,15 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *   tile_log2      points per work tile                         (default 14)
  *   ppt            points per thread: 0 = autotuned, 1, 2 or 4  (default 0)
  *   tune           off | cached | search                        (default cached)
+ *   graph          1: capture each pass into HIP graphs and replay them (default 1)
+ *   budget         total final-pass evaluations distributed over the sectors by
+ *                  their pilot-pass errors (Neyman allocation); 0 = every
+ *                  sector gets 2^lattice_log2 per shift            (default 0)
+ *   alloc_min_log2, alloc_max_log2   bounds of the per-sector lattice log2
+ *                  under allocation                             (default 12, 20)
+ *   pilot_log2     lattice log2 of the pilot pass               (default 12)
+ *   sampler        0: shifted lattice (+ Vegas grid), 1: the learned flow of
+ *                  sdi_flow_init (warmup must be 0)             (default 0)
  * Unknown keys or malformed values return SDI_EINVAL. */
 int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value);
 int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len);
@@ -187,6 +196,50 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, const void* x
  * x: device [npts][n], w: device [npts] (NULL allowed).  Synchronises. */
 int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, int32_t shift,
                       int64_t i0, int64_t npts, void* x_dev, void* w_dev);
+
+/* ---------------------------------------------------------- learned sampler
+ * The importance-sampling map that replaces the Vegas grid of section 4.4 for
+ * sampler = 1: per sector a flow of 4 piecewise-linear coupling layers (32
+ * bins; conditioner MLP with 64 hidden units, bf16 weights and activations on
+ * the matrix cores, fp32 accumulation; the map and its Jacobian in fp64, so
+ * the weight 1/q is exact for the map applied).  Parameters are fp32, per
+ * sector in the order layer 0..3 x (W1 [64][max(nA,1)], b1 [64], W2 [64][64],
+ * b2 [64], W3 [nB*32][64], b3 [nB*32]); layer l transforms the variables
+ * j = l mod 2 (variable 0 when n = 1) given the others.  All calls are
+ * stream-ordered on ctx's stream and synchronise it; device buffers are the
+ * caller's.  Errors: SDI_EINVAL (arguments), SDI_ESTATE (no flow yet),
+ * SDI_ENOMEM, SDI_EDEVICE. */
+
+/* (Re)create every sector's flow: W1, W2 uniform in +-1/sqrt(fan_in) from
+ * Philox4x32-10 (key seed, counter (index in layer, layer, sector,
+ * 0x464c4f57)), biases and W3 zero (the identity map); Adam state cleared. */
+int sdi_flow_init(sdi_ctx* ctx, sdi_problem* prob, uint64_t seed);
+/* fp32 parameters of sector s's flow (negative error code without a flow). */
+int64_t sdi_flow_nparams(const sdi_problem* prob, int32_t s);
+/* Copy sector s's parameters to / from host memory (n = sdi_flow_nparams). */
+int sdi_flow_params(sdi_ctx* ctx, sdi_problem* prob, int32_t s, float* out, int64_t n);
+int sdi_flow_set_params(sdi_ctx* ctx, sdi_problem* prob, int32_t s, const float* in, int64_t n);
+/* Latent points u (device [npts][n]) to x (device [npts][n]) and log q(x)
+ * (device [npts]) by the inverse layers 3..0. */
+int sdi_flow_sample(sdi_ctx* ctx, sdi_problem* prob, int32_t s, const void* u_dev, int64_t npts,
+                    void* x_dev, void* lq_dev);
+/* Gradient of L = -sum_i c_i log q(x_i) with respect to sector s's
+ * parameters (straight-through for every bf16 rounding) into the library's
+ * gradient buffer and, if grad_out is not NULL, to host grad_out[nparams].
+ * x: device [npts][n], c: device [npts]. */
+int sdi_flow_grad(sdi_ctx* ctx, sdi_problem* prob, int32_t s, const void* x_dev, const void* c_dev,
+                  int64_t npts, float* grad_out);
+/* Overwrite sector s's slot of the gradient buffer from host memory. */
+int sdi_flow_set_grad(sdi_ctx* ctx, sdi_problem* prob, int32_t s, const float* in, int64_t n);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8; moments and update in fp64,
+ * stored in fp32) of every sector's parameters from the gradient buffer. */
+int sdi_flow_adam(sdi_ctx* ctx, sdi_problem* prob, double lr);
+/* Train every sector's flow on the GPU for `iters` steps of 2^batch_log2
+ * latent lattice points (shift rows 65536 + step of the Philox shifts),
+ * loss weights c_i = sum_k (|F_k(x_i)|^2 / q_i^2) / S_k with S_k the batch
+ * total of order k; one Adam step per iteration.  *ms_out: device time. */
+int sdi_flow_train(sdi_ctx* ctx, sdi_problem* prob, int32_t iters, int32_t batch_log2, double lr,
+                   float* ms_out);
 
 #ifdef __cplusplus
 }

@@ -23,6 +23,8 @@ __all__ = [
     "sdi_set_param", "sdi_get_param", "sdi_prefactor_feynman", "sdi_lattice_vector",
     "sdi_problem_create", "sdi_problem_destroy", "sdi_problem_norders", "sdi_workspace_bytes",
     "sdi_integrate", "sdi_sector_results", "sdi_evaluate", "sdi_sample_points",
+    "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
+    "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -108,6 +110,15 @@ def load_library():
         "sdi_sector_results": (C.c_int, [vp, vp, i32, dp, dp, dp, C.POINTER(i64)]),
         "sdi_evaluate": (C.c_int, [vp, vp, i32, vp, i64, vp]),
         "sdi_sample_points": (C.c_int, [vp, vp, i32, i32, i64, i64, vp, vp]),
+        "sdi_flow_init": (C.c_int, [vp, vp, C.c_uint64]),
+        "sdi_flow_nparams": (i64, [vp, i32]),
+        "sdi_flow_params": (C.c_int, [vp, vp, i32, C.POINTER(C.c_float), i64]),
+        "sdi_flow_set_params": (C.c_int, [vp, vp, i32, C.POINTER(C.c_float), i64]),
+        "sdi_flow_sample": (C.c_int, [vp, vp, i32, vp, i64, vp, vp]),
+        "sdi_flow_grad": (C.c_int, [vp, vp, i32, vp, vp, i64, C.POINTER(C.c_float)]),
+        "sdi_flow_set_grad": (C.c_int, [vp, vp, i32, C.POINTER(C.c_float), i64]),
+        "sdi_flow_adam": (C.c_int, [vp, vp, C.c_double]),
+        "sdi_flow_train": (C.c_int, [vp, vp, i32, i32, C.c_double, C.POINTER(C.c_float)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -288,3 +299,71 @@ def sdi_sample_points(ctx, prob, s: int, shift: int, i0: int, npts: int, nvars: 
     _check(load_library().sdi_sample_points(ctx, prob, s, shift, i0, npts, C.c_void_p(x.data_ptr()),
                                             C.c_void_p(w.data_ptr())), ctx)
     return x, w
+
+
+# ---------------------------------------------------------------- learned sampler
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def sdi_flow_init(ctx, prob, seed: int):
+    _check(load_library().sdi_flow_init(ctx, prob, seed & 0xFFFFFFFFFFFFFFFF), ctx)
+
+
+def sdi_flow_nparams(prob, s: int) -> int:
+    n = load_library().sdi_flow_nparams(prob, s)
+    if n < 0:
+        raise SdiError(int(n), "no flow or sector out of range")
+    return int(n)
+
+
+def sdi_flow_params(ctx, prob, s: int) -> np.ndarray:
+    out = np.empty(sdi_flow_nparams(prob, s), dtype=np.float32)
+    _check(load_library().sdi_flow_params(ctx, prob, s, _fptr(out), out.size), ctx)
+    return out
+
+
+def sdi_flow_set_params(ctx, prob, s: int, values):
+    v = np.ascontiguousarray(values, dtype=np.float32)
+    _check(load_library().sdi_flow_set_params(ctx, prob, s, _fptr(v), v.size), ctx)
+
+
+def sdi_flow_sample(ctx, prob, s: int, u):
+    """u: torch float64 cuda tensor (npts, n); returns (x, log q) cuda tensors."""
+    import torch
+    u = u.contiguous()
+    x = torch.empty_like(u)
+    lq = torch.empty((u.shape[0],), dtype=torch.float64, device=u.device)
+    torch.cuda.current_stream(u.device).synchronize()
+    _check(load_library().sdi_flow_sample(ctx, prob, s, C.c_void_p(u.data_ptr()), u.shape[0],
+                                          C.c_void_p(x.data_ptr()), C.c_void_p(lq.data_ptr())), ctx)
+    return x, lq
+
+
+def sdi_flow_grad(ctx, prob, s: int, x, c) -> np.ndarray:
+    """x: (npts, n), c: (npts,) torch float64 cuda tensors; returns the fp32 gradient."""
+    import torch
+    x = x.contiguous()
+    c = c.contiguous()
+    g = np.empty(sdi_flow_nparams(prob, s), dtype=np.float32)
+    torch.cuda.current_stream(x.device).synchronize()
+    _check(load_library().sdi_flow_grad(ctx, prob, s, C.c_void_p(x.data_ptr()), C.c_void_p(c.data_ptr()),
+                                        x.shape[0], _fptr(g)), ctx)
+    return g
+
+
+def sdi_flow_set_grad(ctx, prob, s: int, values):
+    v = np.ascontiguousarray(values, dtype=np.float32)
+    _check(load_library().sdi_flow_set_grad(ctx, prob, s, _fptr(v), v.size), ctx)
+
+
+def sdi_flow_adam(ctx, prob, lr: float):
+    _check(load_library().sdi_flow_adam(ctx, prob, float(lr)), ctx)
+
+
+def sdi_flow_train(ctx, prob, iters: int, batch_log2: int, lr: float) -> float:
+    """Trains every sector's flow on the GPU; returns the device time in ms."""
+    ms = C.c_float(0.0)
+    _check(load_library().sdi_flow_train(ctx, prob, iters, batch_log2, float(lr), C.byref(ms)), ctx)
+    return float(ms.value)

@@ -27,20 +27,7 @@ int fail(sdi_ctx* ctx, int code, const std::string& msg) {
 
 namespace {
 
-#define HIPCHK(ctx, call)                                                                        \
-  do {                                                                                           \
-    hipError_t e_ = (call);                                                                      \
-    if (e_ != hipSuccess)                                                                        \
-      return fail(ctx, SDI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
-  } while (0)
 
-#define KCHK(ctx, call)                                                                          \
-  do {                                                                                           \
-    int e_ = (call);                                                                             \
-    if (e_ != 0)                                                                                 \
-      return fail(ctx, SDI_EDEVICE,                                                              \
-                  std::string(#call) + ": " + hipGetErrorString((hipError_t)e_));               \
-  } while (0)
 
 bool is_int(double v, double lim) { return std::isfinite(v) && v == std::floor(v) && std::fabs(v) <= lim; }
 
@@ -150,6 +137,9 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
   } else if (k == "alloc_max_log2") {
     if (!range(4, 26)) return fail(ctx, SDI_EINVAL, "alloc_max_log2 must be in 4..26");
     p.alloc_max = (int)iv;
+  } else if (k == "sampler") {
+    if (!range(0, 1)) return fail(ctx, SDI_EINVAL, "sampler must be 0 (lattice) or 1 (flow)");
+    p.sampler = (int)iv;
   } else if (k == "pilot_log2") {
     if (!range(4, 20)) return fail(ctx, SDI_EINVAL, "pilot_log2 must be in 4..20");
     p.pilot_log2 = (int)iv;
@@ -181,6 +171,7 @@ int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len) {
   else if (k == "alloc_min_log2") v = p.alloc_min;
   else if (k == "alloc_max_log2") v = p.alloc_max;
   else if (k == "pilot_log2") v = p.pilot_log2;
+  else if (k == "sampler") v = p.sampler;
   else return fail(ctx, SDI_EINVAL, "unknown parameter " + k);
   snprintf(buf, len, "%lld", v);
   return SDI_OK;
@@ -458,6 +449,7 @@ void sdi_problem_destroy(sdi_problem* pb) {
   if (pb->d_ws) (void)hipFree(pb->d_ws);
   if (pb->d_cx) (void)hipFree(pb->d_cx);
   if (pb->d_dir) (void)hipFree(pb->d_dir);
+  delete pb->flow;
   delete pb;
 }
 

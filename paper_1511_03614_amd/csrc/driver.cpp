@@ -15,49 +15,16 @@
 
 namespace sdi {
 
-#define HIPCHK(ctx, call)                                                                        \
-  do {                                                                                           \
-    hipError_t e_ = (call);                                                                      \
-    if (e_ != hipSuccess)                                                                        \
-      return fail(ctx, SDI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
-  } while (0)
-
-#define KCHK(ctx, call)                                                                          \
-  do {                                                                                           \
-    int e_ = (call);                                                                             \
-    if (e_ != 0)                                                                                 \
-      return fail(ctx, SDI_EDEVICE, std::string(#call) + ": " + hipGetErrorString((hipError_t)e_)); \
-  } while (0)
-
-namespace {
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-// Workspace carving: a list of (pointer slot, bytes).
-struct Carve {
-  std::vector<std::pair<void**, size_t>> items;
-  void add(void** p, size_t bytes) { items.push_back({p, align256(std::max<size_t>(bytes, 8))}); }
-  size_t total() const {
-    size_t t = 0;
-    for (auto& i : items) t += i.second;
-    return t;
-  }
-  void assign(void* base) {
-    char* b = (char*)base;
-    for (auto& i : items) {
-      *i.first = b;
-      b += i.second;
-    }
-  }
-};
-
-}  // namespace
 
 // Everything one pass needs: per-sector lattice sizes, tiles and their order,
 // the device copy of the sector records for this pass, and workspace slots.
 struct Plan {
   int R = 0, rows = 0;
   bool warm = false;
+  bool flow = false;             // final points come from the learned sampler
+  std::vector<PointRun> fruns;   // per final tile: its points in the flow buffers
+  std::vector<int64_t> fchunk, fx_off, fpt_off;
+  int64_t fx_total = 0, fpt_total = 0;
   std::vector<int> msec;
   std::vector<SecDev> secs;
   std::vector<TileDesc> ftiles;
@@ -84,6 +51,12 @@ struct Plan {
   int32_t* d_counter = nullptr;
   uint64_t* d_shifts = nullptr;
   uint64_t* d_zp_final = nullptr;
+  PointRun* d_fruns = nullptr;
+  int64_t* d_fchunk = nullptr;
+  int64_t* d_fx_off = nullptr;
+  int64_t* d_fpt_off = nullptr;
+  double* d_px = nullptr;
+  double* d_pw = nullptr;
   uint64_t* d_zp_warm = nullptr;
   TileDesc* d_wtiles = nullptr;
   int32_t* d_worder = nullptr;
@@ -156,6 +129,9 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   P.R = prm.R;
   P.rows = prm.R + prm.warmup;
   P.warm = warm && prm.warmup > 0;
+  P.flow = prm.sampler == 1;
+  if (P.flow && !pb->flow) return fail(ctx, SDI_ESTATE, "sampler flow needs sdi_flow_init on this problem");
+  if (P.flow && prm.warmup > 0) return fail(ctx, SDI_ENOTSUP, "the flow sampler replaces the Vegas warm-up (set warmup 0)");
   P.msec = msec;
   const int nsec = pb->nsec;
   size_t goff = 0;
@@ -176,6 +152,27 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   }
   P.pair_start.push_back((int32_t)P.ftiles.size());
   lpt_order(P.ftiles, pb->cost, P.forder);
+  P.fruns.clear();
+  P.fchunk.clear();
+  P.fx_off.clear();
+  P.fpt_off.clear();
+  P.fx_total = P.fpt_total = 0;
+  if (P.flow) {
+    int64_t chunks = 0;
+    for (const TileDesc& t : P.ftiles) {
+      const SecDev& S = P.secs[t.sector];
+      P.fruns.push_back(PointRun{t.sector, S.shift_row + t.shift, t.i0, t.count, P.fpt_total, P.fx_total});
+      P.fchunk.push_back(chunks);
+      P.fx_off.push_back(P.fx_total);
+      P.fpt_off.push_back(P.fpt_total);
+      chunks += ((int64_t)t.count + 63) / 64;
+      P.fx_total += (int64_t)t.count * S.n;
+      P.fpt_total += t.count;
+    }
+    P.fchunk.push_back(chunks);
+    if ((P.fx_total + P.fpt_total) * 8 > ((int64_t)64 << 30))
+      return fail(ctx, SDI_ENOTSUP, "flow pass needs more than 64 GiB of point buffers; lower the lattice size");
+  }
   P.wtiles.clear();
   P.whist_off.clear();
   P.wsec_start.clear();
@@ -241,6 +238,14 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   C.add((void**)&P.d_counter, 8 * 4);
   C.add((void**)&P.d_shifts, (size_t)nsec * P.rows * MAXV * 8);
   C.add((void**)&P.d_zp_final, (size_t)nsec * MAXV * 8);
+  if (P.flow) {
+    C.add((void**)&P.d_fruns, P.fruns.size() * sizeof(PointRun));
+    C.add((void**)&P.d_fchunk, P.fchunk.size() * 8);
+    C.add((void**)&P.d_fx_off, P.fx_off.size() * 8);
+    C.add((void**)&P.d_fpt_off, P.fpt_off.size() * 8);
+    C.add((void**)&P.d_px, (size_t)P.fx_total * 8);
+    C.add((void**)&P.d_pw, (size_t)P.fpt_total * 8);
+  }
   if (P.warm) {
     const size_t nwt = P.wtiles.size();
     C.add((void**)&P.d_zp_warm, (size_t)nsec * MAXV * 8);
@@ -291,9 +296,9 @@ std::string pass_key(const Params& p, const std::vector<int>& msec, bool warm, c
   char buf[320];
   unsigned long long h = 1469598103934665603ull;
   for (int m : msec) h = (h ^ (unsigned)m) * 1099511628211ull;
-  snprintf(buf, sizeof buf, "R%d s%llu b%d w%d/%d mw%d nb%d t%d p%d g%d m%llx ws%p:%zu", p.R,
-           (unsigned long long)p.seed, p.baker, p.warmup, (int)warm, p.mw, p.nbins, p.tile_log2, p.ppt, p.graph, h,
-           ws, wsb);
+  snprintf(buf, sizeof buf, "R%d s%llu b%d w%d/%d mw%d nb%d t%d p%d g%d f%d m%llx ws%p:%zu", p.R,
+           (unsigned long long)p.seed, p.baker, p.warmup, (int)warm, p.mw, p.nbins, p.tile_log2, p.ppt, p.graph,
+           p.sampler, h, ws, wsb);
   return buf;
 }
 
@@ -315,7 +320,11 @@ TileArgs final_args(const sdi_problem* pb, const Plan& P) {
   F.nonfinite = P.d_nonfinite;
   F.counter = P.d_counter + 1;
   F.ntiles = (int)P.ftiles.size();
-  F.mode = 0;
+  F.mode = P.flow ? 2 : 0;
+  F.px = P.d_px;
+  F.pw = P.d_pw;
+  F.x_off = P.d_fx_off;
+  F.pt_off = P.d_fpt_off;
   return F;
 }
 
@@ -328,6 +337,24 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
   const int npairs = (int)P.pair_sector.size();
   if (seg == 0) {
     KCHK(ctx, launch_shifts(P.d_secs, nsec, P.rows, prm.R, prm.seed, P.d_shifts, st));
+    if (P.flow) {
+      const FlowState& Fl = *pb->flow;
+      FlowTileArgs A{};
+      A.fs = Fl.d_desc;
+      A.params = Fl.d_params;
+      A.bw = Fl.d_bw;
+      A.zp = P.d_zp_final;
+      A.shifts = P.d_shifts;
+      A.tiles = P.d_fruns;
+      A.chunk_prefix = P.d_fchunk;
+      A.ntiles = (int)P.fruns.size();
+      A.baker = prm.baker;
+      A.nchunks = P.fchunk.back();
+      A.x = P.d_px;
+      A.w = P.d_pw;
+      A.lq = nullptr;
+      KCHK(ctx, launch_flow_sample_tiles(A, st));
+    }
     if (P.warm) {
       KCHK(ctx, launch_grid_identity(P.d_secs, nsec, pb->d_grids, st));
       const int nwt = (int)P.wtiles.size();
@@ -460,6 +487,12 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   HIPCHK(ctx, hipMemcpyAsync(P.d_pair_start, P.pair_start.data(), (npairs + 1) * 4, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(P.d_pair_sector, P.pair_sector.data(), npairs * 4, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(P.d_zp_final, P.zp_final.data(), P.zp_final.size() * 8, hipMemcpyHostToDevice, st));
+  if (P.flow) {
+    HIPCHK(ctx, hipMemcpyAsync(P.d_fruns, P.fruns.data(), P.fruns.size() * sizeof(PointRun), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(P.d_fchunk, P.fchunk.data(), P.fchunk.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(P.d_fx_off, P.fx_off.data(), P.fx_off.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(P.d_fpt_off, P.fpt_off.data(), P.fpt_off.size() * 8, hipMemcpyHostToDevice, st));
+  }
   std::vector<TileDesc> wall;
   if (P.warm) {
     const size_t nwt = P.wtiles.size();
@@ -476,7 +509,9 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   }
   HIPCHK(ctx, hipStreamSynchronize(st));
   S->km = pb->kfmax <= 4 ? 4 : 8;
-  if (prm.ppt > 0) {
+  if (P.flow) {
+    S->ppt = 1;   // explicit points are read by the one-point-per-thread instances
+  } else if (prm.ppt > 0) {
     S->ppt = prm.ppt;
   } else if (prm.tune == 0) {
     S->ppt = (pb->nvmax >= 16 || pb->complex_mode) ? 1 : 2;

@@ -33,4 +33,14 @@ int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st) {
   return (int)hipGetLastError();
 }
 
+int launch_eval_tiles_real(int km, const EvalTilesArgs& a, hipStream_t st) {
+  if (a.nchunks <= 0) return 0;
+  const unsigned g = (unsigned)(a.nchunks < (1 << 20) ? a.nchunks : (1 << 20));
+  if (km == 4)
+    k_eval_tiles_real<4><<<dim3(g), dim3(BLOCK), 0, st>>>(a);
+  else
+    k_eval_tiles_real<8><<<dim3(g), dim3(BLOCK), 0, st>>>(a);
+  return (int)hipGetLastError();
+}
+
 }  // namespace sdi

@@ -48,6 +48,16 @@ __device__ __forceinline__ double lattice_coord(uint64_t i, uint64_t zp, uint64_
   return (double)u * 0x1p-53;
 }
 
+// Index of the run holding chunk c: the last r with prefix[r] <= c.
+__device__ __forceinline__ int find_run(const int64_t* prefix, int nruns, int64_t c) {
+  int lo = 0, hi = nruns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Tent map u -> 2u (u < 1/2), 2(1-u) otherwise: exact in fp64.
 __device__ __forceinline__ double tent(double u) {
   return u < 0.5 ? 2.0 * u : 2.0 * (1.0 - u);

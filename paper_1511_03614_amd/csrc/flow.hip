@@ -1,0 +1,81 @@
+// Launchers of the learned-sampler kernels (coupling flow on matrix cores).
+#include "flow.hpp"
+#include "kernels.h"
+
+namespace sdi {
+
+namespace {
+unsigned clamp_grid(int64_t want, int64_t cap) {
+  if (want < 1) want = 1;
+  return (unsigned)(want < cap ? want : cap);
+}
+}  // namespace
+
+int launch_flow_init(const FlowSecDesc* fs, int nsec, float* params, uint64_t seed, hipStream_t st) {
+  if (nsec <= 0) return 0;
+  k_flow_init<<<dim3(32, nsec), dim3(256), 0, st>>>(fs, nsec, params, seed);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_copies(const FlowSecDesc* fs, int nsec, const float* params, uint16_t* bw, hipStream_t st) {
+  if (nsec <= 0) return 0;
+  k_flow_copies<<<dim3(32, nsec), dim3(256), 0, st>>>(fs, nsec, params, bw);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_adam(float* params, const float* grad, float* m, float* v, int64_t n, double lr, double bc1,
+                     double bc2, hipStream_t st) {
+  if (n <= 0) return 0;
+  k_flow_adam<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(params, grad, m, v, n, lr, bc1, bc2);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_sample(const FlowSampleArgs& a, hipStream_t st) {
+  if (a.npts <= 0) return 0;
+  const int64_t groups = (a.npts + 15) / 16;
+  k_flow_sample<<<dim3(clamp_grid((groups + 3) / 4, 8192)), dim3(256), 0, st>>>(a);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_sample_tiles(const FlowTileArgs& a, hipStream_t st) {
+  if (a.nchunks <= 0) return 0;
+  k_flow_sample_tiles<<<dim3(clamp_grid(a.nchunks, 1 << 20)), dim3(256), 0, st>>>(a);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_fwd_store(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st) {
+  if (a.ntiles <= 0) return 0;
+  k_flow_fwd_store<<<dim3(blocks_per_tile, a.ntiles), dim3(256), 0, st>>>(a);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_bwd_layer(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st) {
+  if (a.ntiles <= 0) return 0;
+  k_flow_bwd_layer<<<dim3(blocks_per_tile, a.ntiles), dim3(256), 0, st>>>(a);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_grad_reduce(const FlowSecDesc* fs, const FlowTile* tiles, int ntiles, int layer, const float* part,
+                            int64_t part_stride, int nblk, int64_t max_lsize, float* grad, hipStream_t st) {
+  if (ntiles <= 0) return 0;
+  k_flow_grad_reduce<<<dim3((unsigned)((max_lsize + 255) / 256), ntiles), dim3(256), 0, st>>>(
+      fs, tiles, layer, part, part_stride, nblk, grad);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* f, const double* lq, double* c,
+                        hipStream_t st) {
+  if (ntiles <= 0) return 0;
+  k_flow_weights<<<dim3(ntiles), dim3(256), 0, st>>>(tiles, K, f, lq, c);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_shifts(const FlowSecDesc* fs, int nsec, int iters, int m, uint64_t seed, uint32_t row0,
+                       uint64_t* out, hipStream_t st) {
+  const int64_t tot = (int64_t)iters * nsec * MAXV;
+  if (tot <= 0) return 0;
+  k_flow_shifts<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st>>>(fs, nsec, iters, m, seed, row0, out);
+  return (int)hipGetLastError();
+}
+
+}  // namespace sdi

@@ -1,0 +1,406 @@
+// Host side of the learned sampler: parameter layout and initialisation,
+// the parity hooks (sample, gradient, Adam), and the on-GPU training loop
+// (sample a batch through the flow, evaluate the integrand there, form the
+// loss weights, back-propagate, Adam, refresh the bf16 copies).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "host.h"
+#include "kernels.h"
+
+namespace sdi {
+
+FlowState::~FlowState() {
+  for (void* p : {(void*)d_desc, (void*)d_params, (void*)d_bw, (void*)d_m, (void*)d_v, (void*)d_grad, d_scratch})
+    if (p) (void)hipFree(p);
+}
+
+namespace {
+
+// Coupling masks: layer l transforms B_l = {j : j = l mod 2} given A_l = the
+// others; a one-variable flow transforms variable 0 in every layer.
+void flow_masks(int n, int l, std::vector<int>& A, std::vector<int>& B) {
+  A.clear();
+  B.clear();
+  if (n == 1) {
+    B.push_back(0);
+    return;
+  }
+  for (int j = 0; j < n; ++j) (j % 2 == l % 2 ? B : A).push_back(j);
+}
+
+void flow_layout(const sdi_problem* pb, FlowState& F) {
+  F.desc.assign(pb->nsec, FlowSecDesc{});
+  int64_t base = 0, bw = 0;
+  F.max_lsize = 0;
+  for (int s = 0; s < pb->nsec; ++s) {
+    FlowSecDesc& D = F.desc[s];
+    D.n = pb->secs[s].n;
+    D.base = base;
+    int64_t off = 0;
+    for (int l = 0; l < FL_L; ++l) {
+      std::vector<int> A, B;
+      flow_masks(D.n, l, A, B);
+      FlowLayerDesc& L = D.layer[l];
+      L.nA = (int)A.size();
+      L.nB = (int)B.size();
+      for (int k = 0; k < FL_MAXB; ++k) {
+        L.A[k] = k < L.nA ? A[k] : 0;
+        L.B[k] = k < L.nB ? B[k] : 0;
+      }
+      const int nA1 = std::max(L.nA, 1);
+      const int nO = L.nB * FL_NB;
+      L.w1 = off; off += (int64_t)FL_H * nA1;
+      L.b1 = off; off += FL_H;
+      L.w2 = off; off += (int64_t)FL_H * FL_H;
+      L.b2 = off; off += FL_H;
+      L.w3 = off; off += (int64_t)nO * FL_H;
+      L.b3 = off; off += nO;
+      F.max_lsize = std::max(F.max_lsize, off - L.w1);
+      L.c1 = bw; bw += FL_H * FL_K1;
+      L.c2 = bw; bw += FL_H * FL_H;
+      L.c3 = bw; bw += (int64_t)nO * FL_H;
+      L.t1 = bw; bw += FL_K1 * FL_H;
+      L.t2 = bw; bw += FL_H * FL_H;
+      L.t3 = bw; bw += (int64_t)FL_H * nO;
+    }
+    D.nparam = (int32_t)off;
+    base += off;
+  }
+  F.nparam = base;
+  F.nbw = bw;
+}
+
+int flow_ready(sdi_ctx* ctx, const sdi_problem* pb) {
+  if (!pb->flow) return fail(ctx, SDI_ESTATE, "no learned sampler on this problem (call sdi_flow_init first)");
+  return SDI_OK;
+}
+
+// Grows the flow's scratch to at least `bytes`.
+int flow_scratch(sdi_ctx* ctx, FlowState& F, size_t bytes) {
+  if (F.scratch_bytes >= bytes) return SDI_OK;
+  if (F.d_scratch) (void)hipFree(F.d_scratch);
+  F.d_scratch = nullptr;
+  F.scratch_bytes = 0;
+  if (hipMalloc(&F.d_scratch, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, SDI_ENOMEM, "flow scratch allocation failed (" + std::to_string(bytes) + " bytes)");
+  }
+  F.scratch_bytes = bytes;
+  return SDI_OK;
+}
+
+int blocks_per_run(int64_t count) {
+  const int64_t chunks = (count + FL_CHUNK - 1) / FL_CHUNK;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, (chunks + 3) / 4));
+}
+
+}  // namespace
+
+// Gradient of -sum_i c_i log q(x_i) for every run (one run per sector) into F.d_grad.
+int flow_gradient(sdi_ctx* ctx, sdi_problem* pb, const PointRun* d_runs, int nruns, int64_t max_count,
+                  const double* x, const double* c, double* hsave, double* dl, float* part, hipStream_t st) {
+  FlowState& F = *pb->flow;
+  FlowBatchArgs A{};
+  A.fs = F.d_desc;
+  A.params = F.d_params;
+  A.bw = F.d_bw;
+  A.tiles = d_runs;
+  A.ntiles = nruns;
+  A.x = x;
+  A.c = c;
+  A.hsave = hsave;
+  A.dl = dl;
+  A.part = part;
+  A.part_stride = F.max_lsize;
+  const int bpt = blocks_per_run(max_count);
+  const int bfw = (int)std::max<int64_t>(1, std::min<int64_t>(256, (max_count + 63) / 64));
+  KCHK(ctx, launch_flow_fwd_store(A, bfw, st));
+  for (int l = FL_L - 1; l >= 0; --l) {
+    A.layer = l;
+    KCHK(ctx, launch_flow_bwd_layer(A, bpt, st));
+    KCHK(ctx, launch_flow_grad_reduce(F.d_desc, d_runs, nruns, l, part, F.max_lsize, bpt, F.max_lsize, F.d_grad, st));
+  }
+  return SDI_OK;
+}
+
+size_t flow_grad_part_bytes(const FlowState& F, int nruns, int64_t max_count) {
+  return (size_t)nruns * blocks_per_run(max_count) * F.max_lsize * sizeof(float);
+}
+
+}  // namespace sdi
+
+using namespace sdi;
+
+extern "C" {
+
+int sdi_flow_init(sdi_ctx* ctx, sdi_problem* pb, uint64_t seed) {
+  if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_init: null argument");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  for (int s = 0; s < pb->nsec; ++s)
+    if (pb->secs[s].n > 2 * FL_MAXB) return fail(ctx, SDI_ENOTSUP, "flow: more than 16 variables");
+  free_passes(pb->passes);   // cached passes hold the old parameter pointers
+  delete pb->flow;
+  pb->flow = new FlowState();
+  FlowState& F = *pb->flow;
+  F.seed = seed;
+  flow_layout(pb, F);
+  const size_t np = (size_t)std::max<int64_t>(F.nparam, 1);
+  HIPCHK(ctx, hipMalloc((void**)&F.d_desc, sizeof(FlowSecDesc) * std::max(pb->nsec, 1)));
+  HIPCHK(ctx, hipMalloc((void**)&F.d_params, np * 4));
+  HIPCHK(ctx, hipMalloc((void**)&F.d_m, np * 4));
+  HIPCHK(ctx, hipMalloc((void**)&F.d_v, np * 4));
+  HIPCHK(ctx, hipMalloc((void**)&F.d_grad, np * 4));
+  HIPCHK(ctx, hipMalloc((void**)&F.d_bw, (size_t)std::max<int64_t>(F.nbw, 1) * 2));
+  hipStream_t st = ctx->stream;
+  HIPCHK(ctx, hipMemcpyAsync(F.d_desc, F.desc.data(), sizeof(FlowSecDesc) * pb->nsec, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemsetAsync(F.d_m, 0, np * 4, st));
+  HIPCHK(ctx, hipMemsetAsync(F.d_v, 0, np * 4, st));
+  HIPCHK(ctx, hipMemsetAsync(F.d_grad, 0, np * 4, st));
+  KCHK(ctx, launch_flow_init(F.d_desc, pb->nsec, F.d_params, seed, st));
+  KCHK(ctx, launch_flow_copies(F.d_desc, pb->nsec, F.d_params, F.d_bw, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return SDI_OK;
+}
+
+int64_t sdi_flow_nparams(const sdi_problem* pb, int32_t s) {
+  if (!pb || !pb->flow || s < 0 || s >= pb->nsec) return SDI_EINVAL;
+  return pb->flow->desc[s].nparam;
+}
+
+int sdi_flow_params(sdi_ctx* ctx, sdi_problem* pb, int32_t s, float* out, int64_t n) {
+  if (!ctx || !pb || !out) return fail(ctx, SDI_EINVAL, "flow_params: null argument");
+  int rc = flow_ready(ctx, pb);
+  if (rc) return rc;
+  if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");
+  const FlowSecDesc& D = pb->flow->desc[s];
+  if (n != D.nparam) return fail(ctx, SDI_EINVAL, "flow_params: wrong parameter count");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipMemcpyAsync(out, pb->flow->d_params + D.base, n * 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return SDI_OK;
+}
+
+int sdi_flow_set_params(sdi_ctx* ctx, sdi_problem* pb, int32_t s, const float* in, int64_t n) {
+  if (!ctx || !pb || !in) return fail(ctx, SDI_EINVAL, "flow_set_params: null argument");
+  int rc = flow_ready(ctx, pb);
+  if (rc) return rc;
+  if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");
+  FlowState& F = *pb->flow;
+  const FlowSecDesc& D = F.desc[s];
+  if (n != D.nparam) return fail(ctx, SDI_EINVAL, "flow_set_params: wrong parameter count");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipMemcpyAsync(F.d_params + D.base, in, n * 4, hipMemcpyHostToDevice, ctx->stream));
+  KCHK(ctx, launch_flow_copies(F.d_desc, pb->nsec, F.d_params, F.d_bw, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return SDI_OK;
+}
+
+int sdi_flow_sample(sdi_ctx* ctx, sdi_problem* pb, int32_t s, const void* u_dev, int64_t npts, void* x_dev,
+                    void* lq_dev) {
+  if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_sample: null argument");
+  int rc = flow_ready(ctx, pb);
+  if (rc) return rc;
+  if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");
+  if (npts < 0) return fail(ctx, SDI_EINVAL, "negative point count");
+  if (npts == 0) return SDI_OK;
+  if (!u_dev || !x_dev || !lq_dev) return fail(ctx, SDI_EINVAL, "flow_sample: null buffer");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  FlowState& F = *pb->flow;
+  FlowSampleArgs A{F.d_desc, F.d_params, F.d_bw, (const double*)u_dev, (double*)x_dev, (double*)lq_dev, s, npts};
+  KCHK(ctx, launch_flow_sample(A, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return SDI_OK;
+}
+
+int sdi_flow_grad(sdi_ctx* ctx, sdi_problem* pb, int32_t s, const void* x_dev, const void* c_dev, int64_t npts,
+                  float* grad_out) {
+  if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_grad: null argument");
+  int rc = flow_ready(ctx, pb);
+  if (rc) return rc;
+  if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");
+  if (npts <= 0 || npts > (int64_t)UINT32_MAX) return fail(ctx, SDI_EINVAL, "flow_grad: point count out of range");
+  if (!x_dev || !c_dev) return fail(ctx, SDI_EINVAL, "flow_grad: null buffer");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  FlowState& F = *pb->flow;
+  const int n = F.desc[s].n;
+  Carve C;
+  PointRun* d_run = nullptr;
+  double *hsave = nullptr, *dl = nullptr;
+  float* part = nullptr;
+  C.add((void**)&d_run, sizeof(PointRun));
+  C.add((void**)&hsave, (size_t)npts * FL_L * n * 8);
+  C.add((void**)&dl, (size_t)npts * n * 8);
+  C.add((void**)&part, flow_grad_part_bytes(F, 1, npts));
+  rc = flow_scratch(ctx, F, C.total());
+  if (rc) return rc;
+  C.assign(F.d_scratch);
+  hipStream_t st = ctx->stream;
+  const PointRun run{s, 0, 0u, (uint32_t)npts, 0, 0};
+  HIPCHK(ctx, hipMemcpyAsync(d_run, &run, sizeof run, hipMemcpyHostToDevice, st));
+  rc = flow_gradient(ctx, pb, d_run, 1, npts, (const double*)x_dev, (const double*)c_dev, hsave, dl, part, st);
+  if (rc) return rc;
+  if (grad_out)
+    HIPCHK(ctx, hipMemcpyAsync(grad_out, F.d_grad + F.desc[s].base, (size_t)F.desc[s].nparam * 4,
+                               hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return SDI_OK;
+}
+
+int sdi_flow_set_grad(sdi_ctx* ctx, sdi_problem* pb, int32_t s, const float* in, int64_t n) {
+  if (!ctx || !pb || !in) return fail(ctx, SDI_EINVAL, "flow_set_grad: null argument");
+  int rc = flow_ready(ctx, pb);
+  if (rc) return rc;
+  if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");
+  FlowState& F = *pb->flow;
+  if (n != F.desc[s].nparam) return fail(ctx, SDI_EINVAL, "flow_set_grad: wrong parameter count");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipMemcpyAsync(F.d_grad + F.desc[s].base, in, n * 4, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return SDI_OK;
+}
+
+int sdi_flow_adam(sdi_ctx* ctx, sdi_problem* pb, double lr) {
+  if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_adam: null argument");
+  int rc = flow_ready(ctx, pb);
+  if (rc) return rc;
+  if (!(lr > 0.0) || !std::isfinite(lr)) return fail(ctx, SDI_EINVAL, "flow_adam: learning rate must be positive");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  FlowState& F = *pb->flow;
+  F.t += 1;
+  const double bc1 = 1.0 - std::pow(0.9, (double)F.t), bc2 = 1.0 - std::pow(0.999, (double)F.t);
+  KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.nparam, lr, bc1, bc2, ctx->stream));
+  KCHK(ctx, launch_flow_copies(F.d_desc, pb->nsec, F.d_params, F.d_bw, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return SDI_OK;
+}
+
+// Training: `iters` steps; each draws 2^batch_log2 latent lattice points per
+// sector (training shift rows 65536 + it), maps them through the flow,
+// evaluates the integrand there, and takes one Adam step on the loss weights
+// c_i = sum_k (|f_k|^2 / q^2) / S_k.
+int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, int32_t iters, int32_t batch_log2, double lr, float* ms_out) {
+  if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_train: null argument");
+  int rc = flow_ready(ctx, pb);
+  if (rc) return rc;
+  if (iters < 0 || iters > 100000) return fail(ctx, SDI_EINVAL, "flow_train: iterations out of range");
+  if (batch_log2 < 6 || batch_log2 > 20) return fail(ctx, SDI_EINVAL, "flow_train: batch_log2 must be in 6..20");
+  if (!(lr > 0.0) || !std::isfinite(lr)) return fail(ctx, SDI_EINVAL, "flow_train: learning rate must be positive");
+  if (ms_out) *ms_out = 0.f;
+  if (iters == 0) return SDI_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  FlowState& F = *pb->flow;
+  const int nsec = pb->nsec, K = pb->K;
+  const int64_t Bt = (int64_t)1 << batch_log2;
+  std::vector<PointRun> runs(nsec);
+  std::vector<int64_t> pre64(nsec + 1), pre256(nsec + 1);
+  int64_t xtot = 0;
+  for (int s = 0; s < nsec; ++s) {
+    runs[s] = PointRun{s, s, 0u, (uint32_t)Bt, (int64_t)s * Bt, xtot};
+    xtot += Bt * F.desc[s].n;
+    pre64[s] = (int64_t)s * (Bt / FL_CHUNK);
+    pre256[s] = (int64_t)s * ((Bt + BLOCK - 1) / BLOCK);
+  }
+  pre64[nsec] = (int64_t)nsec * (Bt / FL_CHUNK);
+  pre256[nsec] = (int64_t)nsec * ((Bt + BLOCK - 1) / BLOCK);
+  const int64_t npts = Bt * nsec;
+  std::vector<uint64_t> zp((size_t)nsec * MAXV, 0);
+  const std::vector<uint32_t>& z = lattice_vector16(batch_log2);
+  for (int s = 0; s < nsec; ++s)
+    for (int j = 0; j < MAXV; ++j) zp[(size_t)s * MAXV + j] = (uint64_t)z[j] << (53 - batch_log2);
+  Carve C;
+  PointRun* d_runs = nullptr;
+  int64_t *d_pre64 = nullptr, *d_pre256 = nullptr;
+  uint64_t *d_zp = nullptr, *d_shifts = nullptr;
+  double *x = nullptr, *w = nullptr, *lq = nullptr, *f = nullptr, *c = nullptr, *hsave = nullptr, *dl = nullptr;
+  float* part = nullptr;
+  C.add((void**)&d_runs, sizeof(PointRun) * nsec);
+  C.add((void**)&d_pre64, 8 * (nsec + 1));
+  C.add((void**)&d_pre256, 8 * (nsec + 1));
+  C.add((void**)&d_zp, zp.size() * 8);
+  C.add((void**)&d_shifts, (size_t)iters * nsec * MAXV * 8);
+  C.add((void**)&x, (size_t)xtot * 8);
+  C.add((void**)&w, (size_t)npts * 8);
+  C.add((void**)&lq, (size_t)npts * 8);
+  C.add((void**)&f, (size_t)npts * K * 2 * 8);
+  C.add((void**)&c, (size_t)npts * 8);
+  C.add((void**)&hsave, (size_t)xtot * FL_L * 8);
+  C.add((void**)&dl, (size_t)xtot * 8);
+  C.add((void**)&part, flow_grad_part_bytes(F, nsec, Bt));
+  rc = flow_scratch(ctx, F, C.total());
+  if (rc) return rc;
+  C.assign(F.d_scratch);
+  hipStream_t st = ctx->stream;
+  HIPCHK(ctx, hipMemcpyAsync(d_runs, runs.data(), sizeof(PointRun) * nsec, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_pre64, pre64.data(), 8 * (nsec + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_pre256, pre256.data(), 8 * (nsec + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_zp, zp.data(), zp.size() * 8, hipMemcpyHostToDevice, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  HIPCHK(ctx, hipEventRecord(e0, st));
+  KCHK(ctx, launch_flow_shifts(F.d_desc, nsec, iters, batch_log2, ctx->params.seed, 65536u, d_shifts, st));
+  const int km = pb->kfmax <= 4 ? 4 : 8;
+  for (int it = 0; it < iters; ++it) {
+    FlowTileArgs S{};
+    S.fs = F.d_desc;
+    S.params = F.d_params;
+    S.bw = F.d_bw;
+    S.zp = d_zp;
+    S.shifts = d_shifts + (size_t)it * nsec * MAXV;
+    S.tiles = d_runs;
+    S.chunk_prefix = d_pre64;
+    S.ntiles = nsec;
+    S.baker = ctx->params.baker;
+    S.nchunks = pre64[nsec];
+    S.x = x;
+    S.w = w;
+    S.lq = lq;
+    KCHK(ctx, launch_flow_sample_tiles(S, st));
+    EvalTilesArgs E{};
+    E.secs = pb->d_secs;
+    E.terms = pb->d_terms;
+    E.runs = d_runs;
+    E.chunk_prefix = d_pre256;
+    E.nruns = nsec;
+    E.K = K;
+    E.nchunks = pre256[nsec];
+    E.x = x;
+    E.out = f;
+    if (pb->complex_mode)
+      KCHK(ctx, launch_eval_tiles_cplx(km, E, pb->d_cx, pb->d_dir, st));
+    else
+      KCHK(ctx, launch_eval_tiles_real(km, E, st));
+    KCHK(ctx, launch_flow_weights(d_runs, nsec, K, f, lq, c, st));
+    rc = flow_gradient(ctx, pb, d_runs, nsec, Bt, x, c, hsave, dl, part, st);
+    if (rc) return rc;
+    F.t += 1;
+    const double bc1 = 1.0 - std::pow(0.9, (double)F.t), bc2 = 1.0 - std::pow(0.999, (double)F.t);
+    KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.nparam, lr, bc1, bc2, st));
+    KCHK(ctx, launch_flow_copies(F.d_desc, nsec, F.d_params, F.d_bw, st));
+  }
+  HIPCHK(ctx, hipEventRecord(e1, st));
+  HIPCHK(ctx, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+  if (ms_out) *ms_out = ms;
+  return SDI_OK;
+}
+
+}  // extern "C"

@@ -2,14 +2,33 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
 
 #include "../../include/sdint.h"
+#include "flow_types.h"
 #include "sdint_internal.h"
 
 struct sdi_ctx;
+
+// Return from the calling API function with SDI_EDEVICE if a HIP call (HIPCHK)
+// or a kernel launcher (KCHK, returns a hipError_t value) fails.
+#define HIPCHK(ctx, call)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return sdi::fail(ctx, SDI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define KCHK(ctx, call)                                                                          \
+  do {                                                                                           \
+    int e_ = (call);                                                                             \
+    if (e_ != 0)                                                                                 \
+      return sdi::fail(ctx, SDI_EDEVICE,                                                         \
+                       std::string(#call) + ": " + hipGetErrorString((hipError_t)e_));          \
+  } while (0)
 
 namespace sdi {
 
@@ -29,11 +48,51 @@ struct Params {
   int alloc_min = 12;    // bounds of the per-sector lattice log2 under allocation
   int alloc_max = 20;
   int pilot_log2 = 12;   // lattice log2 of the pilot pass that measures the variances
+  int sampler = 0;       // 0: lattice (+ Vegas grid), 1: the learned flow
 };
 
 const std::vector<uint32_t>& lattice_vector16(int m);
 struct PassState;
 void free_passes(std::vector<PassState*>& v);
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace carving: a list of (pointer slot, bytes).
+struct Carve {
+  std::vector<std::pair<void**, size_t>> items;
+  void add(void** p, size_t bytes) { items.push_back({p, align256(std::max<size_t>(bytes, 8))}); }
+  size_t total() const {
+    size_t t = 0;
+    for (auto& i : items) t += i.second;
+    return t;
+  }
+  void assign(void* base) {
+    char* b = (char*)base;
+    for (auto& i : items) {
+      *i.first = b;
+      b += i.second;
+    }
+  }
+};
+
+// Learned sampler of a problem: one coupling flow per sector.
+struct FlowState {
+  uint64_t seed = 0;
+  int64_t nparam = 0;        // fp32 parameters of all flows
+  int64_t nbw = 0;           // bf16 weight-copy elements
+  int64_t max_lsize = 0;     // largest layer (parameters)
+  int64_t t = 0;             // Adam steps taken
+  std::vector<FlowSecDesc> desc;
+  FlowSecDesc* d_desc = nullptr;
+  float* d_params = nullptr;
+  uint16_t* d_bw = nullptr;
+  float* d_m = nullptr;
+  float* d_v = nullptr;
+  float* d_grad = nullptr;
+  void* d_scratch = nullptr; // training and gradient buffers, grown on demand
+  size_t scratch_bytes = 0;
+  ~FlowState();
+};
 int fail(sdi_ctx* ctx, int code, const std::string& msg);
 int prefactor_series(int loops, const int32_t* idx, int nprops, int d0, int len, int* lead, double* out,
                      std::string& err);
@@ -78,4 +137,6 @@ struct sdi_problem {
   std::vector<uint32_t> dir;
   sdi::CplxDev* d_cx = nullptr;
   uint32_t* d_dir = nullptr;
+  // learned sampler (created by sdi_flow_init)
+  sdi::FlowState* flow = nullptr;
 };

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "flow_types.h"
 #include "sdint_internal.h"
 
 namespace sdi {
@@ -38,5 +39,25 @@ int launch_tiles_cplx(int nvmax, int ppt, int km, int grid, size_t shmem, const 
                       const uint32_t* dir, hipStream_t st);
 int tiles_cplx_occupancy(int nvmax, int ppt, int km, size_t shmem);
 int launch_eval_points_cplx(int km, const EvalArgs& a, const void* cx, const uint32_t* dir, hipStream_t st);
+
+// Explicit points of several sectors (training batches).
+int launch_eval_tiles_real(int km, const EvalTilesArgs& a, hipStream_t st);
+int launch_eval_tiles_cplx(int km, const EvalTilesArgs& a, const void* cx, const uint32_t* dir, hipStream_t st);
+
+// Learned sampler (coupling flow).
+int launch_flow_init(const FlowSecDesc* fs, int nsec, float* params, uint64_t seed, hipStream_t st);
+int launch_flow_copies(const FlowSecDesc* fs, int nsec, const float* params, uint16_t* bw, hipStream_t st);
+int launch_flow_adam(float* params, const float* grad, float* m, float* v, int64_t n, double lr, double bc1,
+                     double bc2, hipStream_t st);
+int launch_flow_sample(const FlowSampleArgs& a, hipStream_t st);
+int launch_flow_sample_tiles(const FlowTileArgs& a, hipStream_t st);
+int launch_flow_fwd_store(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st);
+int launch_flow_bwd_layer(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st);
+int launch_flow_grad_reduce(const FlowSecDesc* fs, const FlowTile* tiles, int ntiles, int layer, const float* part,
+                            int64_t part_stride, int nblk, int64_t max_lsize, float* grad, hipStream_t st);
+int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* f, const double* lq, double* c,
+                        hipStream_t st);
+int launch_flow_shifts(const FlowSecDesc* fs, int nsec, int iters, int m, uint64_t seed, uint32_t row0,
+                       uint64_t* out, hipStream_t st);
 
 }  // namespace sdi

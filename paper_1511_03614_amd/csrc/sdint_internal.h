@@ -96,7 +96,35 @@ struct TileArgs {
   const int64_t* hist_off;   // per tile offset into hist (doubles)
   int32_t* counter;          // work counter (zeroed by the launcher's fill kernel)
   int32_t ntiles;
-  int32_t mode;              // 0 final pass, 1 warm-up (histograms)
+  int32_t mode;              // 0 final pass, 1 warm-up (histograms), 2 explicit points
+  const double* px;          // mode 2: caller-order points of tile t at px + x_off[t]
+  const double* pw;          //         and their weights at pw + pt_off[t]
+  const int64_t* x_off;
+  const int64_t* pt_off;
+};
+
+// A run of points of one sector (explicit-point passes and flow batches):
+// lattice indices i0 .. i0+count-1 with shift row `row`; per-point outputs at
+// point offset pt_off, caller-order coordinates at double offset x_off.
+struct PointRun {
+  int32_t sector;
+  int32_t row;
+  uint32_t i0;
+  uint32_t count;
+  int64_t pt_off;
+  int64_t x_off;
+};
+
+struct EvalTilesArgs {       // explicit points of several sectors (training batches)
+  const SecDev* secs;
+  const Term* terms;
+  const PointRun* runs;
+  const int64_t* chunk_prefix;  // [nruns + 1], chunks of BLOCK points
+  int32_t nruns;
+  int32_t K;                 // result orders (output stride)
+  int64_t nchunks;
+  const double* x;
+  double* out;               // [pt][K][2]
 };
 
 struct EvalArgs {            // explicit points (justEvaluate / parity)

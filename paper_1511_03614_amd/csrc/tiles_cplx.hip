@@ -41,4 +41,15 @@ int launch_eval_points_cplx(int km, const EvalArgs& a, const void* cx, const uin
   return (int)hipGetLastError();
 }
 
+int launch_eval_tiles_cplx(int km, const EvalTilesArgs& a, const void* cx, const uint32_t* dir, hipStream_t st) {
+  if (a.nchunks <= 0) return 0;
+  const CplxArgs X{(const CplxDev*)cx, dir};
+  const unsigned g = (unsigned)(a.nchunks < (1 << 20) ? a.nchunks : (1 << 20));
+  if (km == 4)
+    k_eval_tiles_cplx<4><<<dim3(g), dim3(BLOCK), 0, st>>>(a, X);
+  else
+    k_eval_tiles_cplx<8><<<dim3(g), dim3(BLOCK), 0, st>>>(a, X);
+  return (int)hipGetLastError();
+}
+
 }  // namespace sdi

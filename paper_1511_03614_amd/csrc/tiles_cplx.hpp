@@ -13,7 +13,7 @@ struct CplxArgs {
 
 template <int NV, int PPT, int KM>
 __device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs& X, const SecDev* __restrict__ S,
-                                              const TileDesc& td, const double* __restrict__ lgrid,
+                                              const TileDesc& td, int tc, const double* __restrict__ lgrid,
                                               double* __restrict__ lhist, double (&sr)[KM], double (&cr)[KM],
                                               double (&si)[KM], double (&ci)[KM], int& nonfin, int& npos) {
   const uint32_t step = (uint32_t)blockDim.x * PPT;
@@ -24,7 +24,23 @@ __device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs&
     const uint64_t* sh = A.shifts + ((size_t)S->shift_row + td.shift) * MAXV;
     double x[PPT][NV], w[PPT];
     int bins[PPT][NV];
-    make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+    if constexpr (PPT == 1) {
+      if (A.mode == 2) {
+        // explicit points (a learned sampler): caller order, weight 1/q
+        const int n = S->n;
+        const double* xp = A.px + A.x_off[tc] + (size_t)off * n;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          x[0][j] = j < n ? xp[S->perm[j]] : 0.5;
+          bins[0][j] = 0;
+        }
+        w[0] = A.pw[A.pt_off[tc] + off];
+      } else {
+        make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+      }
+    } else {
+      make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+    }
     cd f[PPT][KM];
     int imf[PPT];
     eval_f_cplx<NV, PPT, KM>(S, cx, X.dir, A.terms, x, f, imf);
@@ -113,10 +129,10 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_cplx(TileArgs A, CplxArgs X) {
     int nonfin = 0, npos = 0;
     switch (S->cls) {
       case 0:
-        run_tile_cplx<4, PPT, KM>(A, X, S, td, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+        run_tile_cplx<4, PPT, KM>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
         break;
       case 1:
-        if constexpr (NVC >= 1) run_tile_cplx<8, PPT, KM>(A, X, S, td, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+        if constexpr (NVC >= 1) run_tile_cplx<8, PPT, KM>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
         break;
       default:
         break;
@@ -199,6 +215,29 @@ __global__ void __launch_bounds__(BLOCK) k_eval_points_cplx(EvalArgs A, CplxArgs
     case 0: eval_point_cplx<4, KM>(A, X, i); break;
     case 1: eval_point_cplx<8, KM>(A, X, i); break;
     default: break;
+  }
+}
+
+// Values of every result order at the explicit points of several sectors.
+template <int KM>
+__global__ void __launch_bounds__(BLOCK) k_eval_tiles_cplx(EvalTilesArgs T, CplxArgs X) {
+  for (int64_t c = blockIdx.x; c < T.nchunks; c += gridDim.x) {
+    const int r = find_run(T.chunk_prefix, T.nruns, c);
+    const PointRun run = T.runs[r];
+    const int64_t i = (c - T.chunk_prefix[r]) * BLOCK + threadIdx.x;
+    if (i >= (int64_t)run.count) continue;
+    EvalArgs A;
+    A.sec = T.secs + run.sector;
+    A.terms = T.terms;
+    A.x = T.x + run.x_off;
+    A.out = T.out + run.pt_off * T.K * 2;
+    A.npts = run.count;
+    const CplxArgs Xs{X.cx + run.sector, X.dir};
+    switch (A.sec->cls) {
+      case 0: eval_point_cplx<4, KM>(A, Xs, i); break;
+      case 1: eval_point_cplx<8, KM>(A, Xs, i); break;
+      default: break;
+    }
   }
 }
 

@@ -13,7 +13,7 @@ namespace sdi {
 
 template <int NV, int PPT, int KM>
 __device__ __forceinline__ void run_tile_real(const TileArgs& A, const SecDev* __restrict__ S,
-                                              const TileDesc& td, const double* __restrict__ lgrid,
+                                              const TileDesc& td, int tc, const double* __restrict__ lgrid,
                                               double* __restrict__ lhist, double (&s)[KM],
                                               double (&c)[KM], int& nonfin) {
   const uint32_t step = (uint32_t)blockDim.x * PPT;
@@ -25,7 +25,23 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, const SecDev* _
     const uint64_t* sh = A.shifts + ((size_t)S->shift_row + td.shift) * MAXV;
     double x[PPT][NV], w[PPT];
     int bins[PPT][NV];
-    make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+    if constexpr (PPT == 1) {
+      if (A.mode == 2) {
+        // explicit points (a learned sampler): caller order, weight 1/q
+        const int n = S->n;
+        const double* xp = A.px + A.x_off[tc] + (size_t)off * n;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          x[0][j] = j < n ? xp[S->perm[j]] : 0.5;
+          bins[0][j] = 0;
+        }
+        w[0] = A.pw[A.pt_off[tc] + off];
+      } else {
+        make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+      }
+    } else {
+      make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+    }
     double f[PPT][KM];
     eval_f_real<NV, PPT, KM>(S, A.terms, x, f);
     const int kf = S->kf;
@@ -100,13 +116,13 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
     const int cls = S->cls;
     switch (cls) {
       case 0:
-        run_tile_real<4, PPT, KM>(A, S, td, lgrid, lhist, s, c, nonfin);
+        run_tile_real<4, PPT, KM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       case 1:
-        if constexpr (NVC >= 1) run_tile_real<8, PPT, KM>(A, S, td, lgrid, lhist, s, c, nonfin);
+        if constexpr (NVC >= 1) run_tile_real<8, PPT, KM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       case 2:
-        if constexpr (NVC >= 2) run_tile_real<16, PPT, KM>(A, S, td, lgrid, lhist, s, c, nonfin);
+        if constexpr (NVC >= 2) run_tile_real<16, PPT, KM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       default:
         break;
@@ -185,6 +201,29 @@ __global__ void __launch_bounds__(BLOCK) k_eval_points_real(EvalArgs A) {
     case 1: eval_point_real<8, KM>(A, i); break;
     case 2: eval_point_real<16, KM>(A, i); break;
     default: break;
+  }
+}
+
+// Values of every result order at the explicit points of several sectors.
+template <int KM>
+__global__ void __launch_bounds__(BLOCK) k_eval_tiles_real(EvalTilesArgs T) {
+  for (int64_t c = blockIdx.x; c < T.nchunks; c += gridDim.x) {
+    const int r = find_run(T.chunk_prefix, T.nruns, c);
+    const PointRun run = T.runs[r];
+    const int64_t i = (c - T.chunk_prefix[r]) * BLOCK + threadIdx.x;
+    if (i >= (int64_t)run.count) continue;
+    EvalArgs A;
+    A.sec = T.secs + run.sector;
+    A.terms = T.terms;
+    A.x = T.x + run.x_off;
+    A.out = T.out + run.pt_off * T.K * 2;
+    A.npts = run.count;
+    switch (A.sec->cls) {
+      case 0: eval_point_real<4, KM>(A, i); break;
+      case 1: eval_point_real<8, KM>(A, i); break;
+      case 2: eval_point_real<16, KM>(A, i); break;
+      default: break;
+    }
   }
 }
 
