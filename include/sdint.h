@@ -134,7 +134,9 @@ typedef struct {
  * variables, exponents above 3 in real mode or 7 in complex mode). */
 int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* desc, sdi_problem** out);
 void sdi_problem_destroy(sdi_problem* prob);
+/* Number of result orders K / of sectors of a problem (SDI_EINVAL for NULL). */
 int sdi_problem_norders(const sdi_problem* prob);
+int sdi_problem_nsectors(const sdi_problem* prob);
 
 /* Laurent series of the Feynman prefactor of eq. (2) with (i pi^(d/2))^l and
  * exp(-l gamma_E eps) pulled out (section 4.3):
@@ -196,6 +198,20 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, const void* x
  * x: device [npts][n], w: device [npts] (NULL allowed).  Synchronises. */
 int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, int32_t shift,
                       int64_t i0, int64_t npts, void* x_dev, void* w_dev);
+
+/* Automatic deformation size (the ComplexMode tuning of section 4.4) for a
+ * complex-mode problem: per sector, candidates lam_k = top * k / split
+ * (k = split .. 1, top = lambda_max at first) are tested on the first
+ * 2^points_log2 points of the sector's tent-transformed rank-1 lattice (Philox
+ * shift row 65535 of the context's seed); the largest lam_k under which no
+ * test point has Im F(z) > 0 at any corner x_W = 0 of the pole subtraction is
+ * kept.  If none passes, top /= split and the search repeats (four rounds at
+ * most, then lam = 0).  conservative != 0 halves the result
+ * (ConservativeComplexShift).  The chosen values replace the problem's lambda
+ * for every later call; lam_out (host, [nsectors], may be NULL) receives them.
+ * split in 1..16, points_log2 in 4..20; SDI_ESTATE for a real-mode problem. */
+int sdi_tune_deformation(sdi_ctx* ctx, sdi_problem* prob, double lambda_max, int32_t split,
+                         int32_t points_log2, int32_t conservative, double* lam_out);
 
 /* ---------------------------------------------------------- learned sampler
  * The importance-sampling map that replaces the Vegas grid of section 4.4 for

@@ -21,10 +21,10 @@ __all__ = [
     "SdiError", "load_library", "library_path", "declared_functions",
     "sdi_ctx_create", "sdi_ctx_destroy", "sdi_last_error", "sdi_device_info",
     "sdi_set_param", "sdi_get_param", "sdi_prefactor_feynman", "sdi_lattice_vector",
-    "sdi_problem_create", "sdi_problem_destroy", "sdi_problem_norders", "sdi_workspace_bytes",
+    "sdi_problem_create", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_workspace_bytes",
     "sdi_integrate", "sdi_sector_results", "sdi_evaluate", "sdi_sample_points",
     "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
-    "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train",
+    "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_tune_deformation",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -105,11 +105,13 @@ def load_library():
         "sdi_problem_create": (C.c_int, [vp, C.POINTER(ProblemDesc), C.POINTER(vp)]),
         "sdi_problem_destroy": (None, [vp]),
         "sdi_problem_norders": (C.c_int, [vp]),
+        "sdi_problem_nsectors": (C.c_int, [vp]),
         "sdi_workspace_bytes": (C.c_size_t, [vp, vp]),
         "sdi_integrate": (C.c_int, [vp, vp, vp, C.c_size_t, C.POINTER(Result)]),
         "sdi_sector_results": (C.c_int, [vp, vp, i32, dp, dp, dp, C.POINTER(i64)]),
         "sdi_evaluate": (C.c_int, [vp, vp, i32, vp, i64, vp]),
         "sdi_sample_points": (C.c_int, [vp, vp, i32, i32, i64, i64, vp, vp]),
+        "sdi_tune_deformation": (C.c_int, [vp, vp, C.c_double, i32, i32, i32, dp]),
         "sdi_flow_init": (C.c_int, [vp, vp, C.c_uint64]),
         "sdi_flow_nparams": (i64, [vp, i32]),
         "sdi_flow_params": (C.c_int, [vp, vp, i32, C.POINTER(C.c_float), i64]),
@@ -242,6 +244,16 @@ def sdi_problem_destroy(prob):
     load_library().sdi_problem_destroy(prob)
 
 
+def sdi_problem_nsectors(prob) -> int:
+    return _check_count(load_library().sdi_problem_nsectors(prob))
+
+
+def _check_count(v: int) -> int:
+    if v < 0:
+        raise SdiError(v, "invalid problem handle")
+    return int(v)
+
+
 def sdi_problem_norders(prob) -> int:
     return int(load_library().sdi_problem_norders(prob))
 
@@ -299,6 +311,17 @@ def sdi_sample_points(ctx, prob, s: int, shift: int, i0: int, npts: int, nvars: 
     _check(load_library().sdi_sample_points(ctx, prob, s, shift, i0, npts, C.c_void_p(x.data_ptr()),
                                             C.c_void_p(w.data_ptr())), ctx)
     return x, w
+
+
+# ---------------------------------------------------------------- deformation size
+
+def sdi_tune_deformation(ctx, prob, lambda_max: float, split: int = 4, points_log2: int = 10,
+                         conservative: bool = False) -> np.ndarray:
+    """Chooses every sector's deformation size on the GPU; returns them (host array)."""
+    out = np.zeros(sdi_problem_nsectors(prob), dtype=np.float64)
+    _check(load_library().sdi_tune_deformation(ctx, prob, float(lambda_max), split, points_log2,
+                                               1 if conservative else 0, _dptr(out)), ctx)
+    return out
 
 
 # ---------------------------------------------------------------- learned sampler

@@ -455,6 +455,8 @@ void sdi_problem_destroy(sdi_problem* pb) {
 
 int sdi_problem_norders(const sdi_problem* pb) { return pb ? pb->K : SDI_EINVAL; }
 
+int sdi_problem_nsectors(const sdi_problem* pb) { return pb ? pb->nsec : SDI_EINVAL; }
+
 int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_dev, int64_t npts, void* out_dev) {
   if (!ctx || !pb || (!x_dev && npts > 0) || (!out_dev && npts > 0)) return fail(ctx, SDI_EINVAL, "evaluate: null argument");
   if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");

@@ -336,7 +336,7 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
   const int nsec = pb->nsec;
   const int npairs = (int)P.pair_sector.size();
   if (seg == 0) {
-    KCHK(ctx, launch_shifts(P.d_secs, nsec, P.rows, prm.R, prm.seed, P.d_shifts, st));
+    KCHK(ctx, launch_shifts(P.d_secs, nsec, P.rows, prm.R, prm.seed, 0u, P.d_shifts, st));
     if (P.flow) {
       const FlowState& Fl = *pb->flow;
       FlowTileArgs A{};
@@ -403,7 +403,7 @@ int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
   if (prm.tune == 1)
     for (auto& kv : ctx->tune_cache)
       if (kv.first == key) return kv.second;
-  KCHK(ctx, launch_shifts(P.d_secs, pb->nsec, P.rows, prm.R, prm.seed, P.d_shifts, st));
+  KCHK(ctx, launch_shifts(P.d_secs, pb->nsec, P.rows, prm.R, prm.seed, 0u, P.d_shifts, st));
   if (prm.warmup > 0 && !pb->grid_valid) KCHK(ctx, launch_grid_identity(P.d_secs, pb->nsec, pb->d_grids, st));
   const TileArgs F = final_args(pb, P);
   int best = 1;
@@ -758,7 +758,7 @@ int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, int32_t sh
   int e = 0;
   if (he == hipSuccess) he = hipMemcpyAsync(d_one, &one, sizeof(SecDev), hipMemcpyHostToDevice, st);
   if (he == hipSuccess) he = hipMemcpyAsync(d_zp, zp.data(), MAXV * 8, hipMemcpyHostToDevice, st);
-  if (he == hipSuccess) e = launch_shifts(d_one, 1, shift + 1, shift + 1, prm.seed, d_sh, st);
+  if (he == hipSuccess) e = launch_shifts(d_one, 1, shift + 1, shift + 1, prm.seed, 0u, d_sh, st);
   if (he == hipSuccess && e == 0) {
     SampleArgs A{};
     A.sec = d_one;

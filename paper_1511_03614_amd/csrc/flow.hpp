@@ -141,8 +141,67 @@ __device__ __forceinline__ void softmax_bins(const f32x4_t lo, const f32x4_t hi,
   for (int i = 0; i < 8; ++i) sd += (double)e[i];
   sd += __shfl_xor(sd, 16, 64);
   sd += __shfl_xor(sd, 32, 64);
+  const double inv = 1.0 / sd;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) q[i] = (double)e[i] / sd;
+  for (int i = 0; i < 8; ++i) q[i] = (double)e[i] * inv;
+}
+
+// Inverse coupling of one variable with the bins spread over the sample's 4
+// lanes (lane group g holds bins 4g..4g+3 and 16+4g..16+4g+3): block sums and
+// an exclusive prefix over the groups give each lane the running sums at its
+// bins; the selected bin b is the last one whose running sum is <= y, found as
+// the largest local candidate.  Every lane of the sample returns x and
+// log(NB q_b).
+__device__ __forceinline__ double invert_bins_lanes(const double (&q)[8], double y, double& lterm) {
+  const int lane = threadIdx.x & 63;
+  const int s = lane & 15, g = lane >> 4;
+  const double lo = (q[0] + q[1]) + (q[2] + q[3]);
+  const double hi = (q[4] + q[5]) + (q[6] + q[7]);
+  double L[4], H[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    L[k] = __shfl(lo, s + 16 * k, 64);
+    H[k] = __shfl(hi, s + 16 * k, 64);
+  }
+  double clo = 0.0, chi = ((L[0] + L[1]) + L[2]) + L[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k < g) {
+      clo += L[k];
+      chi += H[k];
+    }
+  int cand = -1;
+  double cb = 0.0, qb = 1.0;
+  double c = clo;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (c <= y) {
+      cand = 4 * g + i;
+      cb = c;
+      qb = q[i];
+    }
+    c += q[i];
+  }
+  c = chi;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (c <= y) {
+      cand = 16 + 4 * g + i;
+      cb = c;
+      qb = q[4 + i];
+    }
+    c += q[4 + i];
+  }
+  int b = cand;
+  b = max(b, __shfl_xor(b, 16, 64));
+  b = max(b, __shfl_xor(b, 32, 64));
+  const int owner = s + 16 * ((b & 15) >> 2);
+  cb = __shfl(cb, owner, 64);
+  qb = __shfl(qb, owner, 64);
+  double frac = (y - cb) / qb;
+  frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
+  lterm = log((double)FL_NB * qb);
+  return ((double)b + frac) / (double)FL_NB;
 }
 
 // Stores this lane's 8 probabilities into the sample's row of 32 (LDS).
@@ -153,25 +212,6 @@ __device__ __forceinline__ void store_bins(double* qrow, const double (&q)[8]) {
     qrow[4 * g + i] = q[i];
     qrow[16 + 4 * g + i] = q[4 + i];
   }
-}
-
-// Inverse coupling of one variable: latent y -> data, and the log Jacobian term.
-// qrow: the sample's 32 bin probabilities in bin order.
-__device__ __forceinline__ double invert_bins(const double* qrow, double y, double& lterm) {
-  double cum = 0.0, cb = 0.0;
-  int b = 0;
-  for (int k = 0; k < FL_NB; ++k) {
-    if (cum <= y) {
-      b = k;
-      cb = cum;
-    }
-    cum += qrow[k];
-  }
-  const double qb = qrow[b];
-  double frac = (y - cb) / qb;
-  frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
-  lterm = log((double)FL_NB * qb);
-  return ((double)b + frac) / (double)FL_NB;
 }
 
 // Forward coupling of one variable: data h -> latent y; bin b, offset alpha, q_b.
@@ -201,10 +241,10 @@ __device__ __forceinline__ bf16x4_t layer_input(const FlowLayerDesc& D, const do
 
 // Latent points -> data points for 16 samples per wave (all 64 lanes of the
 // wave call it together).  hs: LDS [16][16] doubles, this wave's sample
-// states; qs: LDS [16][32] doubles.  On return hs holds x, and lq (per lane,
-// of sample l%16) the log density.
+// states.  On return hs holds x, and lq (per lane, of sample l%16) the log
+// density.
 __device__ __forceinline__ void flow_inverse16(const FlowSecDesc* __restrict__ F, const float* __restrict__ P,
-                                               const uint16_t* __restrict__ bw, double* hs, double* qs, double& lq) {
+                                               const uint16_t* __restrict__ bw, double* hs, double& lq) {
   const int lane = threadIdx.x & 63;
   const int s = lane & 15, g = lane >> 4;
   lq = 0.0;
@@ -217,11 +257,9 @@ __device__ __forceinline__ void flow_inverse16(const FlowSecDesc* __restrict__ F
       mlp_logits(bw, P, D, hid, jj, lo, hi);
       double q[8];
       softmax_bins(lo, hi, q);
-      store_bins(qs + s * FL_NB, q);
-      wave_sync();
       const int j = D.B[jj];
       double lt;
-      const double xn = invert_bins(qs + s * FL_NB, hs[s * 16 + j], lt);
+      const double xn = invert_bins_lanes(q, hs[s * 16 + j], lt);
       lq += lt;
       wave_sync();
       if (g == 0) hs[s * 16 + j] = xn;
@@ -236,12 +274,10 @@ __device__ __forceinline__ void flow_inverse16(const FlowSecDesc* __restrict__ F
 // Latent u -> x, log q for one sector (explicit latent points).
 __global__ void __launch_bounds__(256) k_flow_sample(FlowSampleArgs A) {
   __shared__ double hs_all[4][16 * 16];
-  __shared__ double qs_all[4][16 * FL_NB];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int s = lane & 15, g = lane >> 4;
   double* hs = hs_all[wave];
-  double* qs = qs_all[wave];
   const FlowSecDesc* F = A.fs + A.sector;
   const int n = F->n;
   const float* P = A.params + F->base;
@@ -253,7 +289,7 @@ __global__ void __launch_bounds__(256) k_flow_sample(FlowSampleArgs A) {
       for (int j = 0; j < 16; ++j) hs[s * 16 + j] = (valid && j < n) ? A.u[i * n + j] : 0.5;
     wave_sync();
     double lq;
-    flow_inverse16(F, P, A.bw, hs, qs, lq);
+    flow_inverse16(F, P, A.bw, hs, lq);
     if (valid && g == 0) {
       for (int j = 0; j < n; ++j) A.x[i * n + j] = hs[s * 16 + j];
       A.lq[i] = lq;
@@ -267,12 +303,10 @@ __global__ void __launch_bounds__(256) k_flow_sample(FlowSampleArgs A) {
 // through the flow: the sampler of a pass or of a training batch.
 __global__ void __launch_bounds__(256) k_flow_sample_tiles(FlowTileArgs A) {
   __shared__ double hs_all[4][16 * 16];
-  __shared__ double qs_all[4][16 * FL_NB];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int s = lane & 15, g = lane >> 4;
   double* hs = hs_all[wave];
-  double* qs = qs_all[wave];
   for (int64_t c = blockIdx.x; c < A.nchunks; c += gridDim.x) {
     const int t = find_run(A.chunk_prefix, A.ntiles, c);
     const FlowTile T = A.tiles[t];
@@ -294,7 +328,7 @@ __global__ void __launch_bounds__(256) k_flow_sample_tiles(FlowTileArgs A) {
     }
     wave_sync();
     double lq;
-    flow_inverse16(F, A.params + F->base, A.bw, hs, qs, lq);
+    flow_inverse16(F, A.params + F->base, A.bw, hs, lq);
     if (valid && g == 0) {
       double* xo = A.x + T.x_off + local * n;
       for (int j = 0; j < n; ++j) xo[j] = hs[s * 16 + j];

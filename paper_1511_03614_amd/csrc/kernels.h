@@ -9,8 +9,8 @@
 namespace sdi {
 
 int launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
-int launch_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t seed, uint64_t* shifts,
-                  hipStream_t st);
+int launch_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t seed, uint32_t row0,
+                  uint64_t* shifts, hipStream_t st);
 int launch_reduce_pairs(const double* partial, const int32_t* pair_start, const int32_t* pair_sector,
                         const SecDev* secs, int npairs, double* out, const int32_t* nonfinite,
                         int64_t* pair_nonfinite, hipStream_t st);
@@ -39,6 +39,11 @@ int launch_tiles_cplx(int nvmax, int ppt, int km, int grid, size_t shmem, const 
                       const uint32_t* dir, hipStream_t st);
 int tiles_cplx_occupancy(int nvmax, int ppt, int km, size_t shmem);
 int launch_eval_points_cplx(int km, const EvalArgs& a, const void* cx, const uint32_t* dir, hipStream_t st);
+// Deformation-size test: fail[s] |= 1 << k when some test point of sector s has
+// Im F(z) > 0 at some corner with lam = cand[s * ncand + k] (ncand <= 16).
+int launch_lambda_test(int nvmax, const SecDev* secs, int nsec, const void* cx, const uint32_t* dir,
+                       const Term* terms, const uint64_t* zp, const uint64_t* shifts, int64_t npts,
+                       const double* cand, int ncand, int32_t* fail, hipStream_t st);
 
 // Explicit points of several sectors (training batches).
 int launch_eval_tiles_real(int km, const EvalTilesArgs& a, hipStream_t st);

@@ -19,8 +19,8 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
 // ------------------------------------------------------------ Philox4x32-10 shifts
 
 // D_{s,r,j}: 53 bits (word0 << 21 | word1 >> 11) of Philox(key = seed, counter =
-// (j, r, s, t)), redrawn (t = 1, 2, ...) while D is a multiple of 2^(53-m).
-__global__ void k_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t seed,
+// (j, row0 + r, s, t)), redrawn (t = 1, 2, ...) while D is a multiple of 2^(53-m).
+__global__ void k_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t seed, uint32_t row0,
                          uint64_t* shifts) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)nsec * rows * MAXV) return;
@@ -37,7 +37,7 @@ __global__ void k_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uin
   const uint64_t mod = 1ull << (53 - m);
   uint64_t d = 1;
   for (uint32_t t = 0; t < 64u; ++t) {
-    uint32_t c[4] = {(uint32_t)j, (uint32_t)r, (uint32_t)S.sector, t};
+    uint32_t c[4] = {(uint32_t)j, row0 + (uint32_t)r, (uint32_t)S.sector, t};
     philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
     const uint64_t v = (((uint64_t)c[0] << 21) | ((uint64_t)c[1] >> 11)) & MASK53;
     if (v % mod != 0) {
@@ -345,10 +345,10 @@ int launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
   return (int)hipGetLastError();
 }
 
-int launch_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t seed, uint64_t* shifts,
+int launch_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t seed, uint32_t row0, uint64_t* shifts,
                   hipStream_t st) {
   const int64_t tot = (int64_t)nsec * rows * MAXV;
-  k_shifts<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st>>>(secs, nsec, rows, nfinal, seed, shifts);
+  k_shifts<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st>>>(secs, nsec, rows, nfinal, seed, row0, shifts);
   return (int)hipGetLastError();
 }
 

@@ -52,4 +52,17 @@ int launch_eval_tiles_cplx(int km, const EvalTilesArgs& a, const void* cx, const
   return (int)hipGetLastError();
 }
 
+int launch_lambda_test(int nvmax, const SecDev* secs, int nsec, const void* cx, const uint32_t* dir,
+                       const Term* terms, const uint64_t* zp, const uint64_t* shifts, int64_t npts,
+                       const double* cand, int ncand, int32_t* fail, hipStream_t st) {
+  if (nsec <= 0 || npts <= 0) return 0;
+  const dim3 grid((unsigned)((npts + BLOCK - 1) / BLOCK), (unsigned)nsec);
+  const CplxDev* c = (const CplxDev*)cx;
+  if (nvmax <= 4)
+    k_lambda_test<4><<<grid, dim3(BLOCK), 0, st>>>(secs, c, dir, terms, zp, shifts, npts, cand, ncand, fail);
+  else
+    k_lambda_test<8><<<grid, dim3(BLOCK), 0, st>>>(secs, c, dir, terms, zp, shifts, npts, cand, ncand, fail);
+  return (int)hipGetLastError();
+}
+
 }  // namespace sdi

@@ -241,4 +241,76 @@ __global__ void __launch_bounds__(BLOCK) k_eval_tiles_cplx(EvalTilesArgs T, Cplx
   }
 }
 
+// True when Im F(z) > 0 at some corner x_W = 0 of the pole subtraction for
+// the deformation size lam (the F - i0 side is left): the per-point test of
+// the automatic deformation-size search.
+template <int NV>
+__device__ __forceinline__ bool imf_any_corner(const SecDev* __restrict__ S, const CplxDev* __restrict__ X,
+                                               const uint32_t* __restrict__ dir, const Term* __restrict__ terms,
+                                               const double (&x)[1][NV], double lam) {
+  const int n = S->n;
+  const int ns = S->ns;
+  const int facf = X->fac_f;
+  if (facf < 0) return false;
+  double x2[1][NV], x4[1][NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    x2[0][j] = x[0][j] * x[0][j];
+    x4[0][j] = x2[0][j] * x2[0][j];
+  }
+  bool pos = false;
+  const int C = 1 << ns;
+  for (int W = 0; W < C; ++W) {
+    cd z[1][NV], z2[1][NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const double y = (j < MAXS && ((W >> j) & 1)) ? 0.0 : x[0][j];
+      double g = 0.0;
+      if (j < n) {
+        double v[1];
+        const uint32_t* d = dir + (size_t)X->dir_off + ((size_t)j * MAXC + W) * 2;
+        poly_real3<NV, 1>(terms + d[0], d[1], x, x2, x4, v);
+        g = v[0];
+      }
+      const double t = lam * (1.0 - y) * g;
+      z[0][j] = cd{y, -y * t};
+      z2[0][j] = cmul(z[0][j], z[0][j]);
+    }
+    cd P[1];
+    poly_cplx<NV, 1>(terms + S->tab_off[facf][W], S->tab_cnt[facf][W], z, z2, P);
+    cd fz = P[0];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int e = X->mono_f[j];
+      for (int k = 0; k < e; ++k) fz = cmul(fz, z[0][j]);
+    }
+    pos = pos || (fz.im > 0.0);
+  }
+  return pos;
+}
+
+template <int NVMAX>
+__global__ void __launch_bounds__(BLOCK) k_lambda_test(const SecDev* secs, const CplxDev* cx, const uint32_t* dir,
+                                                       const Term* terms, const uint64_t* zp, const uint64_t* shifts,
+                                                       int64_t npts, const double* cand, int ncand, int32_t* fail) {
+  __shared__ int32_t s_fail;
+  const int s = blockIdx.y;
+  const SecDev* S = secs + s;
+  if (threadIdx.x == 0) s_fail = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t mask = 0;
+  if (i < npts) {
+    double x[1][NVMAX], w[1];
+    int bins[1][NVMAX];
+    make_points<NVMAX, 1>(S, zp + (size_t)s * MAXV, shifts + (size_t)S->shift_row * MAXV, nullptr, (uint64_t)i, x,
+                          w, bins);
+    for (int k = 0; k < ncand; ++k)
+      if (imf_any_corner<NVMAX>(S, cx + s, dir, terms, x, cand[s * ncand + k])) mask |= 1 << k;
+  }
+  if (mask) atomicOr(&s_fail, mask);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_fail) atomicOr(fail + s, s_fail);
+}
+
 }  // namespace sdi

@@ -151,3 +151,65 @@ def test_integrate_massive_double_box_subset(ctx):
         assert res["n_imf_positive"] == tot_pos
     finally:
         P.sdi_problem_destroy(h)
+
+
+def test_tuned_lambda_matches_oracle(ctx):
+    """The GPU deformation-size search picks exactly the oracle's candidate per sector."""
+    from oracle import deform
+    set_params(ctx, seed=5)
+    for prob in (double_box_problem(5.0, -2.0, 1.0, order_max=0, complex_mode=True, lam=0.5),
+                 massive_bubble_problem(5.0, 1.0, 0.5)):
+        h = P.sdi_problem_create(ctx, prob)
+        try:
+            for split, m, cons in ((4, 10, False), (3, 8, True)):
+                lam = P.sdi_tune_deformation(ctx, h, 0.5, split, m, cons)
+                olam = [deform.tune_lambda(sec, s, 0.5, split, m, 5, cons) for s, sec in enumerate(prob.sectors)]
+                assert list(lam) == olam, (prob.name, split, m)
+        finally:
+            P.sdi_problem_destroy(h)
+
+
+def test_integrate_with_tuned_lambda_matches_oracle(ctx):
+    """After tuning, the deformed pass reproduces the oracle at each sector's own lambda."""
+    prob = double_box_problem(5.0, -2.0, 1.0, order_max=0, complex_mode=True, lam=0.5)
+    idx = [0, 5, 12, 24]
+    prob.sectors = [prob.sectors[i] for i in idx]
+    m, R = 9, 2
+    set_params(ctx, lattice_log2=m, shifts=R, seed=12)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        lam = P.sdi_tune_deformation(ctx, h, 0.5, 4, 10)
+        assert np.all(lam < 0.5) and np.all(lam > 0.0)
+        res = P.sdi_integrate(ctx, h)
+        tot_pos = 0
+        for s in range(len(prob.sectors)):
+            _, _, per, _ = P.sdi_sector_results(ctx, h, s, R)
+            one = sectorgen.Problem(sectors=[prob.sectors[s]], order_min=prob.order_min, order_max=prob.order_max,
+                                    feynman=prob.feynman, complex_mode=True, lam=float(lam[s]))
+            oq, scale, npos = oracle_shift_values_c_sector(one, prob.sectors[s], s, m, R, 12)
+            tot_pos += npos
+            assert_close_shift(per, oq, scale, f"tuned double box sector {s}")
+        assert res["n_imf_positive"] == tot_pos
+    finally:
+        P.sdi_problem_destroy(h)
+
+
+def oracle_shift_values_c_sector(one, sec, s, m, R, seed):
+    """oracle_shift_values_c for sector index s of a larger problem (its shifts are keyed by s)."""
+    lead, pref = integrate.prefactor_for(one)
+    z = points.cbc_vector(m, sec.n)
+    sh = points.shift_table(seed, s, R, sec.n, m)
+    N = 1 << m
+    K = one.norders
+    q = np.zeros((R, K), dtype=complex)
+    scale = np.zeros(K)
+    npos = 0
+    for r in range(R):
+        x, w, _ = points.sector_points(z, m, sh[r], 0, N, None, True)
+        vals, _, pos = integrand.sector_orders(sec, x, one.order_min, one.order_max, lead, pref, True, one.lam)
+        npos += int(pos.sum())
+        wf = vals * w[None, :]
+        for k in range(K):
+            q[r, k] = integrate.fsum_c(wf[k]) / N
+            scale[k] = max(scale[k], float(np.mean(np.abs(wf[k]))))
+    return q, scale, npos
