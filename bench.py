@@ -106,6 +106,89 @@ def traffic_from_profiles(ms_kernel: float):
     return None
 
 
+def _set(P, ctx, **kw):
+    base = dict(lattice_log2=12, shifts=16, seed=1, baker=1, warmup=0, graph=1, sampler=0, budget=0, ppt=0,
+                tile_log2=14)
+    base.update(kw)
+    for k, v in base.items():
+        P.sdi_set_param(ctx, k, v)
+
+
+def _err(r):
+    """Per-order absolute error (real and imaginary parts combined)."""
+    import numpy as np
+    return np.hypot(r["err_re"], r["err_im"])
+
+
+def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, share=0.9, max_sel=48,
+                          iters=20, batch_log2=10, lr=3e-3, m_flow=12, plain_ms=(10, 17)):
+    """Error of the learned+batched form against plain batched QMC at equal GPU time.
+
+    Learned form: a plain pilot pass picks the sectors that carry `share` of the
+    pilot variance (orders weighted equally, at most max_sel sectors); their
+    flows are trained on the GPU and validated against the lattice (a flow is
+    kept only where it lowers its sector's variance); then one pass samples
+    the kept sectors through their flows and the rest on the lattice.  Its GPU
+    time is pilot + training + validation + pass.  Plain form: lattice passes of 2^m points per shift for m in
+    plain_ms; its error at the learned form's time is interpolated in
+    log(error) against log(time).  Device times are the library's own
+    (HIP events on its stream)."""
+    import numpy as np
+    h = P.sdi_problem_create(ctx, problem)
+    try:
+        ns = len(problem.sectors)
+        if lambda_max is not None:
+            P.sdi_tune_deformation(ctx, h, lambda_max, 4, 10)
+        plain = []
+        for m in range(*plain_ms):
+            _set(P, ctx, lattice_log2=m)
+            P.sdi_integrate(ctx, h)              # plan, tune and capture once
+            r = P.sdi_integrate(ctx, h)
+            plain.append((m, r["ms_total"], _err(r), r))
+        _set(P, ctx, lattice_log2=m_pilot)
+        P.sdi_integrate(ctx, h)
+        pilot = P.sdi_integrate(ctx, h)
+        var = np.zeros((ns, problem.norders))
+        for s in range(ns):
+            _, err, _, _ = P.sdi_sector_results(ctx, h, s, 16)
+            var[s] = err[:, 0] ** 2 + err[:, 1] ** 2
+        tot = var.sum(axis=0)
+        w = (var / np.where(tot > 0, tot, 1.0)).sum(axis=1)
+        order = np.argsort(-w)
+        cum = np.cumsum(w[order]) / max(w.sum(), 1e-300)
+        nsel = int(min(max_sel, np.searchsorted(cum, share) + 1, ns))
+        sel = sorted(int(s) for s in order[:nsel])
+        P.sdi_flow_init(ctx, h, 1)
+        ms_train = P.sdi_flow_train(ctx, h, iters, batch_log2, lr, sectors=sel)
+        kept, ms_val = P.sdi_flow_validate(ctx, h, m_pilot)
+        _set(P, ctx, lattice_log2=m_flow, sampler=1)
+        fr = P.sdi_integrate(ctx, h)
+        t_learned = pilot["ms_total"] + ms_train + ms_val + fr["ms_total"]
+        ef = _err(fr)
+        t = np.array([p[1] for p in plain])
+        ep = np.array([p[2] for p in plain])
+        k = int(np.clip(np.searchsorted(t, t_learned), 1, len(t) - 1))
+        a = (np.log(t_learned) - np.log(t[k - 1])) / (np.log(t[k]) - np.log(t[k - 1]))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            e_eq = np.exp((1 - a) * np.log(ep[k - 1]) + a * np.log(ep[k]))
+            ratio = np.where(ef > 0, e_eq / ef, np.nan)
+        top = problem.norders - 1
+        return {
+            "config": name, "orders": list(range(problem.order_min, problem.order_max + 1)),
+            "flow_sectors_trained": nsel, "flow_sectors_kept": int(kept.sum()), "sectors": ns,
+            "train": {"iters": iters, "batch": 1 << batch_log2, "ms": ms_train}, "validate_ms": ms_val,
+            "pilot_ms": pilot["ms_total"],
+            "learned": {"ms_total": t_learned, "lattice_log2": m_flow, "err": ef.tolist(),
+                        "value_re": fr["value"].real.tolist(), "value_im": fr["value"].imag.tolist()},
+            "plain": [{"lattice_log2": m, "ms": ms, "err": e.tolist()} for m, ms, e, _ in plain],
+            "plain_err_at_equal_time": e_eq.tolist(),
+            "error_ratio_plain_over_learned": ratio.tolist(),
+            "error_ratio_top_order": float(ratio[top]),
+        }
+    finally:
+        P.sdi_problem_destroy(h)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +196,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-log2", type=int, default=16)
+    ap.add_argument("--no-equal-time", action="store_true",
+                    help="skip the learned-sampler comparison (double box, Euclidean and physical)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -179,6 +264,16 @@ def main() -> int:
                    "value": [float(v.real) for v in r["value"]], "err": [float(e) for e in r["err_re"]]},
     }
     P.sdi_problem_destroy(h)
+    if not args.no_equal_time:
+        from sectorgen.feynman import double_box_problem
+        out["error_vs_plain_qmc"] = [
+            equal_time_comparison(P, ctx, "double box, s=-3, t=-1, massless (Euclidean, 282 sectors, eps^-4..eps^0)",
+                                  double_box_problem(-3.0, -1.0, 0.0, order_max=0)),
+            equal_time_comparison(P, ctx, "double box, s=5, t=-2, m^2=1 (physical, contour deformation, "
+                                          "lambda tuned in (0, 0.5], 30 sectors, eps^-4..eps^0)",
+                                  double_box_problem(5.0, -2.0, 1.0, order_max=0, complex_mode=True, lam=0.5),
+                                  lambda_max=0.5),
+        ]
     P.sdi_ctx_destroy(ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, args.cpu_log2)

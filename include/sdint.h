@@ -248,14 +248,28 @@ int sdi_flow_grad(sdi_ctx* ctx, sdi_problem* prob, int32_t s, const void* x_dev,
 /* Overwrite sector s's slot of the gradient buffer from host memory. */
 int sdi_flow_set_grad(sdi_ctx* ctx, sdi_problem* prob, int32_t s, const float* in, int64_t n);
 /* One Adam step (beta 0.9, 0.999, eps 1e-8; moments and update in fp64,
- * stored in fp32) of every sector's parameters from the gradient buffer. */
+ * stored in fp32) of every sector's parameters from the gradient buffer
+ * (bias correction by each sector's own step count). */
 int sdi_flow_adam(sdi_ctx* ctx, sdi_problem* prob, double lr);
-/* Train every sector's flow on the GPU for `iters` steps of 2^batch_log2
- * latent lattice points (shift rows 65536 + step of the Philox shifts),
- * loss weights c_i = sum_k (|F_k(x_i)|^2 / q_i^2) / S_k with S_k the batch
- * total of order k; one Adam step per iteration.  *ms_out: device time. */
-int sdi_flow_train(sdi_ctx* ctx, sdi_problem* prob, int32_t iters, int32_t batch_log2, double lr,
-                   float* ms_out);
+/* Train the flows of the listed sectors (all sectors when `sectors` is NULL)
+ * on the GPU for `iters` steps of 2^batch_log2 latent lattice points per
+ * sector (shift rows 65536 + step of the Philox shifts), loss weights
+ * c_i = sum_k (|F_k(x_i)|^2 / q_i^2) / S_k with S_k the batch total of order
+ * k; one Adam step per iteration (per-sector step counts).  The trained
+ * sectors become active.  *ms_out: device time (may be NULL). */
+int sdi_flow_train(sdi_ctx* ctx, sdi_problem* prob, const int32_t* sectors, int32_t nsel, int32_t iters,
+                   int32_t batch_log2, double lr, float* ms_out);
+/* Sectors whose flow is active take their points from it in passes with
+ * sampler = 1; the others stay on the lattice (with sdi_flow_set_params or
+ * training a sector becomes active; sdi_flow_init clears every flag). */
+int sdi_flow_set_active(sdi_ctx* ctx, sdi_problem* prob, int32_t s, int32_t active);
+/* Validation with the lattice as the judge: one lattice pass and one flow pass
+ * at 2^lattice_log2 points per shift (other parameters from ctx); an active
+ * sector keeps its flow only if the mean over orders of var_flow/var_lattice
+ * is below 1.  kept (host [nsectors], may be NULL) receives the active flags,
+ * *ms_out (may be NULL) the device time of the two passes.  The per-sector
+ * results left on the problem are those of the flow pass. */
+int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* prob, int32_t lattice_log2, int32_t* kept, float* ms_out);
 
 #ifdef __cplusplus
 }

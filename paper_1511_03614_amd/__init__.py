@@ -24,7 +24,8 @@ __all__ = [
     "sdi_problem_create", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_workspace_bytes",
     "sdi_integrate", "sdi_sector_results", "sdi_evaluate", "sdi_sample_points",
     "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
-    "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_tune_deformation",
+    "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_flow_set_active", "sdi_flow_validate",
+    "sdi_tune_deformation",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -120,7 +121,9 @@ def load_library():
         "sdi_flow_grad": (C.c_int, [vp, vp, i32, vp, vp, i64, C.POINTER(C.c_float)]),
         "sdi_flow_set_grad": (C.c_int, [vp, vp, i32, C.POINTER(C.c_float), i64]),
         "sdi_flow_adam": (C.c_int, [vp, vp, C.c_double]),
-        "sdi_flow_train": (C.c_int, [vp, vp, i32, i32, C.c_double, C.POINTER(C.c_float)]),
+        "sdi_flow_train": (C.c_int, [vp, vp, C.POINTER(i32), i32, i32, i32, C.c_double, C.POINTER(C.c_float)]),
+        "sdi_flow_set_active": (C.c_int, [vp, vp, i32, i32]),
+        "sdi_flow_validate": (C.c_int, [vp, vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -385,8 +388,26 @@ def sdi_flow_adam(ctx, prob, lr: float):
     _check(load_library().sdi_flow_adam(ctx, prob, float(lr)), ctx)
 
 
-def sdi_flow_train(ctx, prob, iters: int, batch_log2: int, lr: float) -> float:
-    """Trains every sector's flow on the GPU; returns the device time in ms."""
+def sdi_flow_train(ctx, prob, iters: int, batch_log2: int, lr: float, sectors=None) -> float:
+    """Trains the flows of `sectors` (all if None) on the GPU; returns the device time in ms."""
     ms = C.c_float(0.0)
-    _check(load_library().sdi_flow_train(ctx, prob, iters, batch_log2, float(lr), C.byref(ms)), ctx)
+    if sectors is None:
+        ptr, n = None, 0
+    else:
+        sel = np.ascontiguousarray(sectors, dtype=np.int32)
+        ptr, n = sel.ctypes.data_as(C.POINTER(C.c_int32)), sel.size
+    _check(load_library().sdi_flow_train(ctx, prob, ptr, n, iters, batch_log2, float(lr), C.byref(ms)), ctx)
     return float(ms.value)
+
+
+def sdi_flow_set_active(ctx, prob, s: int, active: bool):
+    _check(load_library().sdi_flow_set_active(ctx, prob, s, 1 if active else 0), ctx)
+
+
+def sdi_flow_validate(ctx, prob, lattice_log2: int):
+    """Deactivates flows that do not lower their sector's variance; returns (kept flags, device ms)."""
+    kept = np.zeros(sdi_problem_nsectors(prob), dtype=np.int32)
+    ms = C.c_float(0.0)
+    _check(load_library().sdi_flow_validate(ctx, prob, lattice_log2, kept.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            C.byref(ms)), ctx)
+    return kept.astype(bool), float(ms.value)

@@ -29,6 +29,7 @@ struct Plan {
   std::vector<SecDev> secs;
   std::vector<TileDesc> ftiles;
   std::vector<int32_t> forder, pair_start, pair_sector;
+  std::vector<int32_t> xorder;   // flow tiles (LPT order); forder then holds the lattice tiles
   std::vector<TileDesc> wtiles;
   std::vector<int32_t> worder, wsec_start;
   std::vector<int64_t> whist_off, hsec_off, hsec_prefix;
@@ -38,6 +39,7 @@ struct Plan {
   SecDev* d_secs = nullptr;
   TileDesc* d_ftiles = nullptr;
   int32_t* d_forder = nullptr;
+  int32_t* d_xorder = nullptr;
   int32_t* d_pair_start = nullptr;
   int32_t* d_pair_sector = nullptr;
   double* d_partial = nullptr;
@@ -74,7 +76,7 @@ struct Plan {
 struct PassState {
   std::string key;
   Plan P;
-  int ppt = 1, km = 4, gf = 1, gw = 1;
+  int ppt = 1, km = 4, gf = 1, gw = 1, gx = 1;
   hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};   // warm-up, final tiles, reductions
   void* own_ws = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // recorded between segment launches
@@ -152,14 +154,22 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   }
   P.pair_start.push_back((int32_t)P.ftiles.size());
   lpt_order(P.ftiles, pb->cost, P.forder);
+  P.xorder.clear();
   P.fruns.clear();
   P.fchunk.clear();
   P.fx_off.clear();
   P.fpt_off.clear();
   P.fx_total = P.fpt_total = 0;
   if (P.flow) {
+    // sectors with an active flow take their points from it; the others stay on the lattice
+    const std::vector<uint8_t>& act = pb->flow->active;
     int64_t chunks = 0;
     for (const TileDesc& t : P.ftiles) {
+      if (!act[t.sector]) {
+        P.fx_off.push_back(-1);
+        P.fpt_off.push_back(-1);
+        continue;
+      }
       const SecDev& S = P.secs[t.sector];
       P.fruns.push_back(PointRun{t.sector, S.shift_row + t.shift, t.i0, t.count, P.fpt_total, P.fx_total});
       P.fchunk.push_back(chunks);
@@ -170,6 +180,9 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
       P.fpt_total += t.count;
     }
     P.fchunk.push_back(chunks);
+    std::vector<int32_t> lat;
+    for (int32_t t : P.forder) (act[P.ftiles[t].sector] ? P.xorder : lat).push_back(t);
+    P.forder.swap(lat);
     if ((P.fx_total + P.fpt_total) * 8 > ((int64_t)64 << 30))
       return fail(ctx, SDI_ENOTSUP, "flow pass needs more than 64 GiB of point buffers; lower the lattice size");
   }
@@ -225,6 +238,7 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   C.add((void**)&P.d_secs, (size_t)nsec * sizeof(SecDev));
   C.add((void**)&P.d_ftiles, nft * sizeof(TileDesc));
   C.add((void**)&P.d_forder, nft * 4);
+  C.add((void**)&P.d_xorder, nft * 4);
   C.add((void**)&P.d_pair_start, (npairs + 1) * 4);
   C.add((void**)&P.d_pair_sector, npairs * 4);
   C.add((void**)&P.d_partial, nft * KMAX * PART_STRIDE * 8);
@@ -311,16 +325,17 @@ TileArgs base_args(const sdi_problem* pb, const Plan& P) {
   return A;
 }
 
-TileArgs final_args(const sdi_problem* pb, const Plan& P) {
+// The final pass's lattice tiles (flow = false) or flow-sampled tiles (flow = true).
+TileArgs final_args(const sdi_problem* pb, const Plan& P, bool flow = false) {
   TileArgs F = base_args(pb, P);
   F.zp = P.d_zp_final;
   F.tiles = P.d_ftiles;
-  F.order = P.d_forder;
+  F.order = flow ? P.d_xorder : P.d_forder;
   F.partial = P.d_partial;
   F.nonfinite = P.d_nonfinite;
-  F.counter = P.d_counter + 1;
-  F.ntiles = (int)P.ftiles.size();
-  F.mode = P.flow ? 2 : 0;
+  F.counter = P.d_counter + (flow ? 2 : 1);
+  F.ntiles = (int)(flow ? P.xorder.size() : P.forder.size());
+  F.mode = flow ? 2 : 0;
   F.px = P.d_px;
   F.pw = P.d_pw;
   F.x_off = P.d_fx_off;
@@ -378,8 +393,10 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
       }
     }
   } else if (seg == 1) {
-    KCHK(ctx, launch_fill_i32(P.d_counter + 1, 0, 1, st));
-    KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gf, P.shmem_final, final_args(pb, P), st));
+    KCHK(ctx, launch_fill_i32(P.d_counter + 1, 0, 2, st));
+    if (!P.forder.empty()) KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gf, P.shmem_final, final_args(pb, P), st));
+    if (!P.xorder.empty())
+      KCHK(ctx, launch_tiles(pb, 1, S.km, S.gx, P.shmem_final, final_args(pb, P, true), st));
   } else {
     KCHK(ctx, launch_reduce_pairs(P.d_partial, P.d_pair_start, P.d_pair_sector, P.d_secs, npairs, P.d_per_shift,
                                   P.d_nonfinite, P.d_pair_nonfinite, st));
@@ -406,10 +423,11 @@ int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
   KCHK(ctx, launch_shifts(P.d_secs, pb->nsec, P.rows, prm.R, prm.seed, 0u, P.d_shifts, st));
   if (prm.warmup > 0 && !pb->grid_valid) KCHK(ctx, launch_grid_identity(P.d_secs, pb->nsec, pb->d_grids, st));
   const TileArgs F = final_args(pb, P);
+  if (F.ntiles == 0) return 1;
   int best = 1;
   float best_ms = 1e30f;
   for (int ppt : ppt_candidates(pb)) {
-    const int g = persistent_grid(ctx, pb, ppt, S.km, P.shmem_final, P.ftiles.size());
+    const int g = persistent_grid(ctx, pb, ppt, S.km, P.shmem_final, P.forder.size());
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       KCHK(ctx, launch_fill_i32(F.counter, 0, 1, st));
@@ -483,7 +501,9 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   const int nft = (int)P.ftiles.size();
   HIPCHK(ctx, hipMemcpyAsync(P.d_secs, P.secs.data(), (size_t)nsec * sizeof(SecDev), hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(P.d_ftiles, P.ftiles.data(), nft * sizeof(TileDesc), hipMemcpyHostToDevice, st));
-  HIPCHK(ctx, hipMemcpyAsync(P.d_forder, P.forder.data(), nft * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(P.d_forder, P.forder.data(), P.forder.size() * 4, hipMemcpyHostToDevice, st));
+  if (!P.xorder.empty())
+    HIPCHK(ctx, hipMemcpyAsync(P.d_xorder, P.xorder.data(), P.xorder.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(P.d_pair_start, P.pair_start.data(), (npairs + 1) * 4, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(P.d_pair_sector, P.pair_sector.data(), npairs * 4, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(P.d_zp_final, P.zp_final.data(), P.zp_final.size() * 8, hipMemcpyHostToDevice, st));
@@ -509,9 +529,7 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   }
   HIPCHK(ctx, hipStreamSynchronize(st));
   S->km = pb->kfmax <= 4 ? 4 : 8;
-  if (P.flow) {
-    S->ppt = 1;   // explicit points are read by the one-point-per-thread instances
-  } else if (prm.ppt > 0) {
+  if (prm.ppt > 0) {
     S->ppt = prm.ppt;
   } else if (prm.tune == 0) {
     S->ppt = (pb->nvmax >= 16 || pb->complex_mode) ? 1 : 2;
@@ -520,7 +538,9 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
     if (rc < 0) return rc;
     S->ppt = rc;
   }
-  S->gf = persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_final, P.ftiles.size());
+  S->gf = persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_final, std::max<size_t>(1, P.forder.size()));
+  // explicit (flow) points are read by the one-point-per-thread instances
+  S->gx = persistent_grid(ctx, pb, 1, S->km, P.shmem_final, std::max<size_t>(1, P.xorder.size()));
   S->gw = P.warm ? persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_warm, P.wtiles.size()) : 1;
   if (prm.graph) {
     // Capture each segment once; replays skip the launch overheads.  Timing

@@ -1,4 +1,6 @@
 // Launchers of the learned-sampler kernels (coupling flow on matrix cores).
+#include <algorithm>
+
 #include "flow.hpp"
 #include "kernels.h"
 
@@ -23,10 +25,12 @@ int launch_flow_copies(const FlowSecDesc* fs, int nsec, const float* params, uin
   return (int)hipGetLastError();
 }
 
-int launch_flow_adam(float* params, const float* grad, float* m, float* v, int64_t n, double lr, double bc1,
-                     double bc2, hipStream_t st) {
-  if (n <= 0) return 0;
-  k_flow_adam<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(params, grad, m, v, n, lr, bc1, bc2);
+int launch_flow_adam(float* params, const float* grad, float* m, float* v, const FlowSecDesc* fs,
+                     const FlowTile* runs, int nruns, int64_t max_nparam, double lr, const double* bc,
+                     hipStream_t st) {
+  if (nruns <= 0) return 0;
+  const unsigned gx = (unsigned)std::min<int64_t>(64, (max_nparam + 255) / 256);
+  k_flow_adam<<<dim3(gx, nruns), dim3(256), 0, st>>>(params, grad, m, v, fs, runs, lr, bc);
   return (int)hipGetLastError();
 }
 
@@ -70,11 +74,12 @@ int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* 
   return (int)hipGetLastError();
 }
 
-int launch_flow_shifts(const FlowSecDesc* fs, int nsec, int iters, int m, uint64_t seed, uint32_t row0,
-                       uint64_t* out, hipStream_t st) {
-  const int64_t tot = (int64_t)iters * nsec * MAXV;
+int launch_flow_shifts(const FlowSecDesc* fs, const FlowTile* runs, int nruns, int iters, int m, uint64_t seed,
+                       uint32_t row0, uint64_t* out, hipStream_t st) {
+  const int64_t tot = (int64_t)iters * nruns * MAXV;
   if (tot <= 0) return 0;
-  k_flow_shifts<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st>>>(fs, nsec, iters, m, seed, row0, out);
+  k_flow_shifts<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st>>>(fs, runs, nruns, iters, m, seed, row0,
+                                                                           out);
   return (int)hipGetLastError();
 }
 

@@ -406,23 +406,28 @@ __global__ void k_flow_copies(const FlowSecDesc* fs, int nsec, const float* P, u
   }
 }
 
-// Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the fp32 master parameters:
-// moments and update in fp64, each stored value rounded to fp32; bc1, bc2 =
-// 1 - beta^t.
-__global__ void k_flow_adam(float* P, const float* G, float* M, float* V, int64_t n, double lr, double bc1,
-                            double bc2) {
+// Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the fp32 master parameters of
+// the sectors of `runs` (blockIdx.y = run): moments and update in fp64, each
+// stored value rounded to fp32; bc[2 r], bc[2 r + 1] = 1 - beta^t of that
+// sector's step count.
+__global__ void k_flow_adam(float* P, const float* G, float* M, float* V, const FlowSecDesc* fs,
+                            const FlowTile* runs, double lr, const double* bc) {
 #pragma clang fp contract(off)
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const FlowSecDesc& F = fs[runs[blockIdx.y].sector];
+  const double bc1 = bc[2 * blockIdx.y], bc2 = bc[2 * blockIdx.y + 1];
   const double b1 = 0.9, b2 = 0.999;
-  const double g = (double)G[i];
-  const float m = (float)(b1 * (double)M[i] + (1.0 - b1) * g);
-  const float v = (float)(b2 * (double)V[i] + (1.0 - b2) * g * g);
-  M[i] = m;
-  V[i] = v;
-  const double mh = (double)m / bc1;
-  const double vh = (double)v / bc2;
-  P[i] = (float)((double)P[i] - lr * mh / (sqrt(vh) + 1e-8));
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < F.nparam;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = F.base + k;
+    const double g = (double)G[i];
+    const float m = (float)(b1 * (double)M[i] + (1.0 - b1) * g);
+    const float v = (float)(b2 * (double)V[i] + (1.0 - b2) * g * g);
+    M[i] = m;
+    V[i] = v;
+    const double mh = (double)m / bc1;
+    const double vh = (double)v / bc2;
+    P[i] = (float)((double)P[i] - lr * mh / (sqrt(vh) + 1e-8));
+  }
 }
 
 // ---------------------------------------------------------------- gradient
@@ -753,15 +758,17 @@ __global__ void __launch_bounds__(256) k_flow_weights(const FlowTile* tiles, int
 }
 
 // Training shifts: D(seed, sector, row0 + it, j) for a lattice of 2^m points,
-// out[(it * nsec + s) * MAXV + j] (zero beyond the sector's variables); the
-// draw is redrawn while it is a multiple of 2^(53-m), as for the pass shifts.
-__global__ void k_flow_shifts(const FlowSecDesc* fs, int nsec, int iters, int m, uint64_t seed, uint32_t row0,
-                              uint64_t* out) {
+// out[(it * nruns + r) * MAXV + j] for the sector of run r (zero beyond its
+// variables); the draw is redrawn while it is a multiple of 2^(53-m), as for
+// the pass shifts.
+__global__ void k_flow_shifts(const FlowSecDesc* fs, const FlowTile* runs, int nruns, int iters, int m,
+                              uint64_t seed, uint32_t row0, uint64_t* out) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (int64_t)iters * nsec * MAXV) return;
+  if (gid >= (int64_t)iters * nruns * MAXV) return;
   const int j = (int)(gid % MAXV);
-  const int s = (int)((gid / MAXV) % nsec);
-  const int it = (int)(gid / ((int64_t)MAXV * nsec));
+  const int r = (int)((gid / MAXV) % nruns);
+  const int it = (int)(gid / ((int64_t)MAXV * nruns));
+  const int s = runs[r].sector;
   uint64_t d = 0;
   if (j < fs[s].n) {
     const uint64_t mod = 1ull << (53 - m);

@@ -69,6 +69,7 @@ void flow_layout(const sdi_problem* pb, FlowState& F) {
       L.t3 = bw; bw += (int64_t)FL_H * nO;
     }
     D.nparam = (int32_t)off;
+    F.max_nparam = std::max(F.max_nparam, D.nparam);
     base += off;
   }
   F.nparam = base;
@@ -150,6 +151,8 @@ int sdi_flow_init(sdi_ctx* ctx, sdi_problem* pb, uint64_t seed) {
   FlowState& F = *pb->flow;
   F.seed = seed;
   flow_layout(pb, F);
+  F.t.assign(pb->nsec, 0);
+  F.active.assign(pb->nsec, 0);
   const size_t np = (size_t)std::max<int64_t>(F.nparam, 1);
   HIPCHK(ctx, hipMalloc((void**)&F.d_desc, sizeof(FlowSecDesc) * std::max(pb->nsec, 1)));
   HIPCHK(ctx, hipMalloc((void**)&F.d_params, np * 4));
@@ -198,6 +201,18 @@ int sdi_flow_set_params(sdi_ctx* ctx, sdi_problem* pb, int32_t s, const float* i
   HIPCHK(ctx, hipMemcpyAsync(F.d_params + D.base, in, n * 4, hipMemcpyHostToDevice, ctx->stream));
   KCHK(ctx, launch_flow_copies(F.d_desc, pb->nsec, F.d_params, F.d_bw, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (!F.active[s]) free_passes(pb->passes);   // the split of the pass between lattice and flow changes
+  F.active[s] = 1;
+  return SDI_OK;
+}
+
+int sdi_flow_set_active(sdi_ctx* ctx, sdi_problem* pb, int32_t s, int32_t active) {
+  if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_set_active: null argument");
+  int rc = flow_ready(ctx, pb);
+  if (rc) return rc;
+  if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");
+  pb->flow->active[s] = active ? 1 : 0;
+  free_passes(pb->passes);   // the split of the pass between lattice and flow changed
   return SDI_OK;
 }
 
@@ -275,59 +290,101 @@ int sdi_flow_adam(sdi_ctx* ctx, sdi_problem* pb, double lr) {
   HIPCHK(ctx, hipSetDevice(ctx->device));
   (void)hipGetLastError();
   FlowState& F = *pb->flow;
-  F.t += 1;
-  const double bc1 = 1.0 - std::pow(0.9, (double)F.t), bc2 = 1.0 - std::pow(0.999, (double)F.t);
-  KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.nparam, lr, bc1, bc2, ctx->stream));
-  KCHK(ctx, launch_flow_copies(F.d_desc, pb->nsec, F.d_params, F.d_bw, ctx->stream));
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const int nsec = pb->nsec;
+  std::vector<PointRun> runs(nsec);
+  std::vector<double> bc(2 * (size_t)nsec);
+  for (int s = 0; s < nsec; ++s) {
+    runs[s] = PointRun{s, 0, 0u, 0u, 0, 0};
+    F.t[s] += 1;
+    bc[2 * s] = 1.0 - std::pow(0.9, (double)F.t[s]);
+    bc[2 * s + 1] = 1.0 - std::pow(0.999, (double)F.t[s]);
+  }
+  Carve C;
+  PointRun* d_runs = nullptr;
+  double* d_bc = nullptr;
+  C.add((void**)&d_runs, sizeof(PointRun) * nsec);
+  C.add((void**)&d_bc, bc.size() * 8);
+  rc = flow_scratch(ctx, F, C.total());
+  if (rc) return rc;
+  C.assign(F.d_scratch);
+  hipStream_t st = ctx->stream;
+  HIPCHK(ctx, hipMemcpyAsync(d_runs, runs.data(), sizeof(PointRun) * nsec, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_bc, bc.data(), bc.size() * 8, hipMemcpyHostToDevice, st));
+  KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.d_desc, d_runs, nsec, F.max_nparam, lr, d_bc, st));
+  KCHK(ctx, launch_flow_copies(F.d_desc, nsec, F.d_params, F.d_bw, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
   return SDI_OK;
 }
 
-// Training: `iters` steps; each draws 2^batch_log2 latent lattice points per
-// sector (training shift rows 65536 + it), maps them through the flow,
-// evaluates the integrand there, and takes one Adam step on the loss weights
-// c_i = sum_k (|f_k|^2 / q^2) / S_k.
-int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, int32_t iters, int32_t batch_log2, double lr, float* ms_out) {
+// Training: `iters` steps for the selected sectors (all when sectors is NULL);
+// each step draws 2^batch_log2 latent lattice points per sector (training
+// shift rows 65536 + step), maps them through the flow, evaluates the
+// integrand there, and takes one Adam step on the loss weights
+// c_i = sum_k (|f_k|^2 / q^2) / S_k.  The trained sectors become active.
+int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_t nsel, int32_t iters,
+                   int32_t batch_log2, double lr, float* ms_out) {
   if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_train: null argument");
   int rc = flow_ready(ctx, pb);
   if (rc) return rc;
   if (iters < 0 || iters > 100000) return fail(ctx, SDI_EINVAL, "flow_train: iterations out of range");
   if (batch_log2 < 6 || batch_log2 > 20) return fail(ctx, SDI_EINVAL, "flow_train: batch_log2 must be in 6..20");
   if (!(lr > 0.0) || !std::isfinite(lr)) return fail(ctx, SDI_EINVAL, "flow_train: learning rate must be positive");
+  std::vector<int32_t> sel;
+  if (sectors) {
+    if (nsel < 0 || nsel > pb->nsec) return fail(ctx, SDI_EINVAL, "flow_train: bad sector count");
+    std::vector<uint8_t> seen(pb->nsec, 0);
+    for (int i = 0; i < nsel; ++i) {
+      if (sectors[i] < 0 || sectors[i] >= pb->nsec || seen[sectors[i]])
+        return fail(ctx, SDI_EINVAL, "flow_train: sector list has an invalid or repeated index");
+      seen[sectors[i]] = 1;
+      sel.push_back(sectors[i]);
+    }
+  } else {
+    for (int s = 0; s < pb->nsec; ++s) sel.push_back(s);
+  }
   if (ms_out) *ms_out = 0.f;
-  if (iters == 0) return SDI_OK;
+  if (iters == 0 || sel.empty()) return SDI_OK;
   HIPCHK(ctx, hipSetDevice(ctx->device));
   (void)hipGetLastError();
   FlowState& F = *pb->flow;
-  const int nsec = pb->nsec, K = pb->K;
+  const int nr = (int)sel.size(), K = pb->K;
   const int64_t Bt = (int64_t)1 << batch_log2;
-  std::vector<PointRun> runs(nsec);
-  std::vector<int64_t> pre64(nsec + 1), pre256(nsec + 1);
+  std::vector<PointRun> runs(nr);
+  std::vector<int64_t> pre64(nr + 1), pre256(nr + 1);
   int64_t xtot = 0;
-  for (int s = 0; s < nsec; ++s) {
-    runs[s] = PointRun{s, s, 0u, (uint32_t)Bt, (int64_t)s * Bt, xtot};
-    xtot += Bt * F.desc[s].n;
-    pre64[s] = (int64_t)s * (Bt / FL_CHUNK);
-    pre256[s] = (int64_t)s * ((Bt + BLOCK - 1) / BLOCK);
+  for (int r = 0; r < nr; ++r) {
+    runs[r] = PointRun{sel[r], r, 0u, (uint32_t)Bt, (int64_t)r * Bt, xtot};
+    xtot += Bt * F.desc[sel[r]].n;
+    pre64[r] = (int64_t)r * (Bt / FL_CHUNK);
+    pre256[r] = (int64_t)r * ((Bt + BLOCK - 1) / BLOCK);
   }
-  pre64[nsec] = (int64_t)nsec * (Bt / FL_CHUNK);
-  pre256[nsec] = (int64_t)nsec * ((Bt + BLOCK - 1) / BLOCK);
-  const int64_t npts = Bt * nsec;
-  std::vector<uint64_t> zp((size_t)nsec * MAXV, 0);
+  pre64[nr] = (int64_t)nr * (Bt / FL_CHUNK);
+  pre256[nr] = (int64_t)nr * ((Bt + BLOCK - 1) / BLOCK);
+  const int64_t npts = Bt * nr;
+  std::vector<uint64_t> zp((size_t)pb->nsec * MAXV, 0);
   const std::vector<uint32_t>& z = lattice_vector16(batch_log2);
-  for (int s = 0; s < nsec; ++s)
+  for (int s = 0; s < pb->nsec; ++s)
     for (int j = 0; j < MAXV; ++j) zp[(size_t)s * MAXV + j] = (uint64_t)z[j] << (53 - batch_log2);
+  std::vector<double> bc((size_t)iters * nr * 2);
+  for (int it = 0; it < iters; ++it)
+    for (int r = 0; r < nr; ++r) {
+      const double t = (double)(F.t[sel[r]] + it + 1);
+      bc[((size_t)it * nr + r) * 2] = 1.0 - std::pow(0.9, t);
+      bc[((size_t)it * nr + r) * 2 + 1] = 1.0 - std::pow(0.999, t);
+    }
   Carve C;
   PointRun* d_runs = nullptr;
   int64_t *d_pre64 = nullptr, *d_pre256 = nullptr;
   uint64_t *d_zp = nullptr, *d_shifts = nullptr;
   double *x = nullptr, *w = nullptr, *lq = nullptr, *f = nullptr, *c = nullptr, *hsave = nullptr, *dl = nullptr;
+  double* d_bc = nullptr;
   float* part = nullptr;
-  C.add((void**)&d_runs, sizeof(PointRun) * nsec);
-  C.add((void**)&d_pre64, 8 * (nsec + 1));
-  C.add((void**)&d_pre256, 8 * (nsec + 1));
+  C.add((void**)&d_runs, sizeof(PointRun) * nr);
+  C.add((void**)&d_pre64, 8 * (nr + 1));
+  C.add((void**)&d_pre256, 8 * (nr + 1));
   C.add((void**)&d_zp, zp.size() * 8);
-  C.add((void**)&d_shifts, (size_t)iters * nsec * MAXV * 8);
+  C.add((void**)&d_shifts, (size_t)iters * nr * MAXV * 8);
+  C.add((void**)&d_bc, bc.size() * 8);
   C.add((void**)&x, (size_t)xtot * 8);
   C.add((void**)&w, (size_t)npts * 8);
   C.add((void**)&lq, (size_t)npts * 8);
@@ -335,15 +392,16 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, int32_t iters, int32_t batch_l
   C.add((void**)&c, (size_t)npts * 8);
   C.add((void**)&hsave, (size_t)xtot * FL_L * 8);
   C.add((void**)&dl, (size_t)xtot * 8);
-  C.add((void**)&part, flow_grad_part_bytes(F, nsec, Bt));
+  C.add((void**)&part, flow_grad_part_bytes(F, nr, Bt));
   rc = flow_scratch(ctx, F, C.total());
   if (rc) return rc;
   C.assign(F.d_scratch);
   hipStream_t st = ctx->stream;
-  HIPCHK(ctx, hipMemcpyAsync(d_runs, runs.data(), sizeof(PointRun) * nsec, hipMemcpyHostToDevice, st));
-  HIPCHK(ctx, hipMemcpyAsync(d_pre64, pre64.data(), 8 * (nsec + 1), hipMemcpyHostToDevice, st));
-  HIPCHK(ctx, hipMemcpyAsync(d_pre256, pre256.data(), 8 * (nsec + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_runs, runs.data(), sizeof(PointRun) * nr, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_pre64, pre64.data(), 8 * (nr + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_pre256, pre256.data(), 8 * (nr + 1), hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(d_zp, zp.data(), zp.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_bc, bc.data(), bc.size() * 8, hipMemcpyHostToDevice, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(ctx, hipEventCreate(&e0));
   HIPCHK(ctx, hipEventCreate(&e1));
@@ -355,7 +413,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, int32_t iters, int32_t batch_l
     }
   } guard{e0, e1};
   HIPCHK(ctx, hipEventRecord(e0, st));
-  KCHK(ctx, launch_flow_shifts(F.d_desc, nsec, iters, batch_log2, ctx->params.seed, 65536u, d_shifts, st));
+  KCHK(ctx, launch_flow_shifts(F.d_desc, d_runs, nr, iters, batch_log2, ctx->params.seed, 65536u, d_shifts, st));
   const int km = pb->kfmax <= 4 ? 4 : 8;
   for (int it = 0; it < iters; ++it) {
     FlowTileArgs S{};
@@ -363,12 +421,12 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, int32_t iters, int32_t batch_l
     S.params = F.d_params;
     S.bw = F.d_bw;
     S.zp = d_zp;
-    S.shifts = d_shifts + (size_t)it * nsec * MAXV;
+    S.shifts = d_shifts + (size_t)it * nr * MAXV;
     S.tiles = d_runs;
     S.chunk_prefix = d_pre64;
-    S.ntiles = nsec;
+    S.ntiles = nr;
     S.baker = ctx->params.baker;
-    S.nchunks = pre64[nsec];
+    S.nchunks = pre64[nr];
     S.x = x;
     S.w = w;
     S.lq = lq;
@@ -378,28 +436,96 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, int32_t iters, int32_t batch_l
     E.terms = pb->d_terms;
     E.runs = d_runs;
     E.chunk_prefix = d_pre256;
-    E.nruns = nsec;
+    E.nruns = nr;
     E.K = K;
-    E.nchunks = pre256[nsec];
+    E.nchunks = pre256[nr];
     E.x = x;
     E.out = f;
     if (pb->complex_mode)
       KCHK(ctx, launch_eval_tiles_cplx(km, E, pb->d_cx, pb->d_dir, st));
     else
       KCHK(ctx, launch_eval_tiles_real(km, E, st));
-    KCHK(ctx, launch_flow_weights(d_runs, nsec, K, f, lq, c, st));
-    rc = flow_gradient(ctx, pb, d_runs, nsec, Bt, x, c, hsave, dl, part, st);
+    KCHK(ctx, launch_flow_weights(d_runs, nr, K, f, lq, c, st));
+    rc = flow_gradient(ctx, pb, d_runs, nr, Bt, x, c, hsave, dl, part, st);
     if (rc) return rc;
-    F.t += 1;
-    const double bc1 = 1.0 - std::pow(0.9, (double)F.t), bc2 = 1.0 - std::pow(0.999, (double)F.t);
-    KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.nparam, lr, bc1, bc2, st));
-    KCHK(ctx, launch_flow_copies(F.d_desc, nsec, F.d_params, F.d_bw, st));
+    KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.d_desc, d_runs, nr, F.max_nparam, lr,
+                               d_bc + (size_t)it * nr * 2, st));
+    KCHK(ctx, launch_flow_copies(F.d_desc, pb->nsec, F.d_params, F.d_bw, st));
   }
   HIPCHK(ctx, hipEventRecord(e1, st));
   HIPCHK(ctx, hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
   if (ms_out) *ms_out = ms;
+  for (int s : sel) {
+    F.t[s] += iters;
+    F.active[s] = 1;
+  }
+  free_passes(pb->passes);   // the split of the pass between lattice and flow may have changed
+  return SDI_OK;
+}
+
+// Keeps a sector's flow only where it lowers that sector's variance: one
+// lattice pass and one flow pass at 2^lattice_log2 points per shift (the
+// context's other parameters), per active sector r_s = mean over the orders
+// with nonzero lattice variance of var_flow / var_lattice; the flow stays
+// active when r_s < 1.  kept (host, [nsectors], may be NULL) receives the flags.
+int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32_t* kept, float* ms_out) {
+  if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_validate: null argument");
+  int rc = flow_ready(ctx, pb);
+  if (rc) return rc;
+  if (lattice_log2 < 4 || lattice_log2 > 24) return fail(ctx, SDI_EINVAL, "flow_validate: lattice_log2 in 4..24");
+  FlowState& F = *pb->flow;
+  const Params saved = ctx->params;
+  std::vector<double> v[2];
+  const int K = pb->K;
+  std::vector<double> re(K), im(K), er(K), ei(K);
+  double ms = 0.0;
+  for (int pass = 0; pass < 2; ++pass) {
+    ctx->params.m = lattice_log2;
+    ctx->params.sampler = pass;
+    ctx->params.warmup = 0;
+    ctx->params.budget = 0;
+    sdi_result res{};
+    res.val_re = re.data();
+    res.val_im = im.data();
+    res.err_re = er.data();
+    res.err_im = ei.data();
+    rc = sdi_integrate(ctx, pb, nullptr, 0, &res);
+    if (rc != SDI_OK && rc != SDI_ENONFINITE) {
+      ctx->params = saved;
+      return rc;
+    }
+    ms += res.ms_total;
+    v[pass].assign((size_t)pb->nsec * K, 0.0);
+    for (int s = 0; s < pb->nsec; ++s)
+      for (int k = 0; k < K; ++k) {
+        const double* q = pb->sec_stats.data() + ((size_t)s * KMAX + k) * 4;
+        v[pass][(size_t)s * K + k] = q[2] * q[2] + q[3] * q[3];
+      }
+  }
+  ctx->params = saved;
+  bool changed = false;
+  for (int s = 0; s < pb->nsec; ++s) {
+    if (F.active[s]) {
+      double sum = 0.0;
+      int cnt = 0;
+      for (int k = 0; k < K; ++k) {
+        const double vl = v[0][(size_t)s * K + k];
+        if (vl > 0.0) {
+          sum += v[1][(size_t)s * K + k] / vl;
+          ++cnt;
+        }
+      }
+      if (!(cnt > 0 && sum / cnt < 1.0)) {
+        F.active[s] = 0;
+        changed = true;
+      }
+    }
+    if (kept) kept[s] = F.active[s];
+  }
+  if (changed) free_passes(pb->passes);
+  if (ms_out) *ms_out = (float)ms;
   return SDI_OK;
 }
 

@@ -81,7 +81,9 @@ struct FlowState {
   int64_t nparam = 0;        // fp32 parameters of all flows
   int64_t nbw = 0;           // bf16 weight-copy elements
   int64_t max_lsize = 0;     // largest layer (parameters)
-  int64_t t = 0;             // Adam steps taken
+  int32_t max_nparam = 0;   // largest flow (parameters)
+  std::vector<int64_t> t;    // Adam steps taken, per sector
+  std::vector<uint8_t> active;  // sectors whose flow samples the integration passes
   std::vector<FlowSecDesc> desc;
   FlowSecDesc* d_desc = nullptr;
   float* d_params = nullptr;

@@ -52,8 +52,10 @@ int launch_eval_tiles_cplx(int km, const EvalTilesArgs& a, const void* cx, const
 // Learned sampler (coupling flow).
 int launch_flow_init(const FlowSecDesc* fs, int nsec, float* params, uint64_t seed, hipStream_t st);
 int launch_flow_copies(const FlowSecDesc* fs, int nsec, const float* params, uint16_t* bw, hipStream_t st);
-int launch_flow_adam(float* params, const float* grad, float* m, float* v, int64_t n, double lr, double bc1,
-                     double bc2, hipStream_t st);
+// Adam over the parameters of the sectors of runs; bc: device [nruns][2] = 1 - beta1^t, 1 - beta2^t.
+int launch_flow_adam(float* params, const float* grad, float* m, float* v, const FlowSecDesc* fs,
+                     const FlowTile* runs, int nruns, int64_t max_nparam, double lr, const double* bc,
+                     hipStream_t st);
 int launch_flow_sample(const FlowSampleArgs& a, hipStream_t st);
 int launch_flow_sample_tiles(const FlowTileArgs& a, hipStream_t st);
 int launch_flow_fwd_store(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st);
@@ -62,7 +64,7 @@ int launch_flow_grad_reduce(const FlowSecDesc* fs, const FlowTile* tiles, int nt
                             int64_t part_stride, int nblk, int64_t max_lsize, float* grad, hipStream_t st);
 int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* f, const double* lq, double* c,
                         hipStream_t st);
-int launch_flow_shifts(const FlowSecDesc* fs, int nsec, int iters, int m, uint64_t seed, uint32_t row0,
-                       uint64_t* out, hipStream_t st);
+int launch_flow_shifts(const FlowSecDesc* fs, const FlowTile* runs, int nruns, int iters, int m, uint64_t seed,
+                       uint32_t row0, uint64_t* out, hipStream_t st);
 
 }  // namespace sdi

@@ -35,7 +35,7 @@ import sectorgen  # noqa: E402
 from sectorgen import Factor, Sector  # noqa: E402
 from oracle import flow, integrand, integrate, points  # noqa: E402
 
-from test_gpu_parity import log, set_params  # noqa: E402
+from test_gpu_parity import assert_close_shift, log, oracle_shift_values, set_params  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -212,18 +212,24 @@ def peaked_sector(e0=0.003):
 
 
 def test_flow_pass_uses_the_hook_map(ctx):
-    prob = sectorgen.Problem(sectors=[peaked_sector(), problem_with_dims([3]).sectors[0]], order_min=0, order_max=0)
+    """Sectors 0 and 2 sample through their flows, sector 1 (inactive) stays on the lattice."""
+    prob = sectorgen.Problem(sectors=[peaked_sector(), problem_with_dims([4]).sectors[0],
+                                      problem_with_dims([3]).sectors[0]], order_min=0, order_max=0)
     m, R = 10, 4
     set_params(ctx, lattice_log2=m, shifts=R, seed=7, sampler=1)
     h = P.sdi_problem_create(ctx, prob)
     try:
         P.sdi_flow_init(ctx, h, 3)
-        for s, sec in enumerate(prob.sectors):
-            P.sdi_flow_set_params(ctx, h, s, random_fp32_params(sec.n, 40 + s))
+        for s in (0, 2):
+            P.sdi_flow_set_params(ctx, h, s, random_fp32_params(prob.sectors[s].n, 40 + s))
         res = P.sdi_integrate(ctx, h)
         assert res["status"] == 0
         lead, pref = integrate.prefactor_for(prob)
-        for s, sec in enumerate(prob.sectors):
+        _, _, per, _ = P.sdi_sector_results(ctx, h, 1, R)
+        oq, scale = oracle_shift_values(prob, 1, m, R, 7)
+        assert_close_shift(per, oq, scale, "lattice sector in a flow pass")
+        for s in (0, 2):
+            sec = prob.sectors[s]
             _, _, per, _ = P.sdi_sector_results(ctx, h, s, R)
             z = points.cbc_vector(m, sec.n)
             sh = points.shift_table(7, s, R, sec.n, m)
@@ -264,6 +270,32 @@ def test_training_on_gpu_lowers_the_variance(ctx):
         P.sdi_flow_init(ctx, h, 2)
         P.sdi_flow_train(ctx, h, 60, 11, 5e-3)
         assert np.array_equal(P.sdi_flow_params(ctx, h, 0), p1)
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
+
+
+def test_training_a_subset_leaves_the_rest(ctx):
+    prob = sectorgen.Problem(sectors=[peaked_sector(), problem_with_dims([3]).sectors[0]], order_min=0, order_max=0)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        set_params(ctx, seed=11)
+        P.sdi_flow_init(ctx, h, 2)
+        before = [P.sdi_flow_params(ctx, h, s) for s in range(2)]
+        P.sdi_flow_train(ctx, h, 5, 9, 5e-3, sectors=[0])
+        assert not np.array_equal(P.sdi_flow_params(ctx, h, 0), before[0])
+        assert np.array_equal(P.sdi_flow_params(ctx, h, 1), before[1])
+        with pytest.raises(P.SdiError):
+            P.sdi_flow_train(ctx, h, 5, 9, 5e-3, sectors=[0, 0])
+        # a pass with the flow sampler: sector 1 is inactive, so it matches the plain lattice pass
+        m, R = 10, 4
+        set_params(ctx, lattice_log2=m, shifts=R, seed=11, sampler=1)
+        P.sdi_integrate(ctx, h)
+        _, _, per_flow, _ = P.sdi_sector_results(ctx, h, 1, R)
+        set_params(ctx, lattice_log2=m, shifts=R, seed=11, sampler=0)
+        P.sdi_integrate(ctx, h)
+        _, _, per_plain, _ = P.sdi_sector_results(ctx, h, 1, R)
+        assert np.allclose(per_flow, per_plain, rtol=1e-12, atol=0.0)
     finally:
         P.sdi_problem_destroy(h)
         set_params(ctx)
