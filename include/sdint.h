@@ -264,9 +264,9 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* prob, const int32_t* sectors, int3
  * training a sector becomes active; sdi_flow_init clears every flag). */
 int sdi_flow_set_active(sdi_ctx* ctx, sdi_problem* prob, int32_t s, int32_t active);
 /* Validation with the lattice as the judge: one lattice pass and one flow pass
- * at 2^lattice_log2 points per shift (other parameters from ctx); an active
- * sector keeps its flow only if the mean over orders of var_flow/var_lattice
- * is below 1.  kept (host [nsectors], may be NULL) receives the active flags,
+ * at 2^lattice_log2 points per shift (other parameters from ctx); with V_k the
+ * lattice pass's total variance of order k, an active sector keeps its flow
+ * only if sum_k var_flow(s,k)/V_k < sum_k var_lattice(s,k)/V_k.  kept (host [nsectors], may be NULL) receives the active flags,
  * *ms_out (may be NULL) the device time of the two passes.  The per-sector
  * results left on the problem are those of the flow pass. */
 int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* prob, int32_t lattice_log2, int32_t* kept, float* ms_out);

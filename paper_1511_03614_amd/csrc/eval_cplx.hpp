@@ -48,7 +48,7 @@ __device__ __forceinline__ cd cexp_(cd z) {
 
 // Real polynomial with exponent bits x, x^2, x^4 (exponents up to 7).
 template <int NV, int PPT>
-__device__ __forceinline__ void poly_real3(const Term* __restrict__ t, uint32_t cnt, const double (&x)[PPT][NV],
+__device__ __forceinline__ void poly_real3(CTerm* t, uint32_t cnt, const double (&x)[PPT][NV],
                                            const double (&x2)[PPT][NV], const double (&x4)[PPT][NV],
                                            double (&out)[PPT]) {
 #pragma unroll
@@ -84,7 +84,7 @@ __device__ __forceinline__ void poly_real3(const Term* __restrict__ t, uint32_t 
 
 // Polynomial with real coefficients at complex points (exponents up to 3).
 template <int NV, int PPT>
-__device__ __forceinline__ void poly_cplx(const Term* __restrict__ t, uint32_t cnt, const cd (&z)[PPT][NV],
+__device__ __forceinline__ void poly_cplx(CTerm* t, uint32_t cnt, const cd (&z)[PPT][NV],
                                           const cd (&z2)[PPT][NV], cd (&out)[PPT]) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) out[p] = cd{0.0, 0.0};
@@ -115,8 +115,7 @@ __device__ __forceinline__ void poly_cplx(const Term* __restrict__ t, uint32_t c
 // f_kk of one sector at PPT points, complex mode.  imf counts points whose F(z)
 // has a positive imaginary part at some corner.
 template <int NV, int PPT, int KM>
-__device__ __forceinline__ void eval_f_cplx(const SecDev* __restrict__ S, const CplxDev* __restrict__ X,
-                                            const uint32_t* __restrict__ dir, const Term* __restrict__ terms,
+__device__ __forceinline__ void eval_f_cplx(CSec* S, const SDI_TAPE CplxDev* X, CU32* dir, CTerm* terms,
                                             const double (&x)[PPT][NV], cd (&f)[PPT][KM], int (&imf)[PPT]) {
   constexpr int NT = NV * (NV + 1) / 2;
   const int n = S->n;
@@ -193,7 +192,7 @@ __device__ __forceinline__ void eval_f_cplx(const SecDev* __restrict__ S, const 
       for (int p = 0; p < PPT; ++p) g[p][j] = 0.0;
       if (j < n && facf >= 0) {
         double v[PPT];
-        const uint32_t* d = dir + (size_t)X->dir_off + ((size_t)j * MAXC + W) * 2;
+        CU32* d = dir + (size_t)X->dir_off + ((size_t)j * MAXC + W) * 2;
         poly_real3<NV, PPT>(terms + d[0], d[1], x, x2, x4, v);
 #pragma unroll
         for (int p = 0; p < PPT; ++p) g[p][j] = v[p];
@@ -219,7 +218,7 @@ __device__ __forceinline__ void eval_f_cplx(const SecDev* __restrict__ S, const 
             // second derivative (k, j), k <= j, is polynomial n + j(j+1)/2 + k
             double v[PPT];
             const int dd = n + j * (j + 1) / 2 + k;
-            const uint32_t* d = dir + (size_t)X->dir_off + ((size_t)dd * MAXC + W) * 2;
+            CU32* d = dir + (size_t)X->dir_off + ((size_t)dd * MAXC + W) * 2;
             poly_real3<NV, PPT>(terms + d[0], d[1], x, x2, x4, v);
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {

@@ -19,6 +19,22 @@
 
 namespace sdi {
 
+// The sector tape (SecDev records, Term lists, complex tables, derivative
+// directory, lattice vectors and shifts) is read-only while a kernel runs, and
+// is read at wave-uniform addresses.  Reading it through the constant address
+// space lets those loads compile to scalar loads into SGPRs, although the
+// kernels also store to global memory (which otherwise forces vector loads and
+// readfirstlane).
+#define SDI_TAPE __attribute__((address_space(4)))
+typedef const SDI_TAPE SecDev CSec;
+typedef const SDI_TAPE Term CTerm;
+typedef const SDI_TAPE uint64_t CU64;
+typedef const SDI_TAPE uint32_t CU32;
+template <class T>
+__device__ __forceinline__ const SDI_TAPE T* tape(const T* p) {
+  return (const SDI_TAPE T*)p;
+}
+
 // --------------------------------------------------------------- compensated sums
 
 // Knuth's branch-free two-sum: s + v = t + err exactly.
@@ -82,8 +98,7 @@ __device__ __forceinline__ double vegas_coord(const double* __restrict__ g, int 
 // Points i = i_first .. i_first+PPT-1 (consecutive lattice indices) of one sector and shift.
 // Writes x in internal variable order and the Vegas weight; also the bins (warm-up).
 template <int NV, int PPT>
-__device__ __forceinline__ void make_points(const SecDev* __restrict__ S, const uint64_t* __restrict__ zp,
-                                            const uint64_t* __restrict__ sh, const double* __restrict__ lgrid,
+__device__ __forceinline__ void make_points(CSec* S, CU64* zp, CU64* sh, const double* __restrict__ lgrid,
                                             uint64_t i_first, double (&x)[PPT][NV], double (&w)[PPT],
                                             int (&bins)[PPT][NV]) {
   const int n = S->n;
@@ -128,7 +143,7 @@ __device__ __forceinline__ void make_points(const SecDev* __restrict__ S, const 
 // exponent bit is a scalar branch; the empty asm keeps the compiler from
 // turning the skipped multiplies into per-lane selects.
 template <int NV, int PPT>
-__device__ __forceinline__ void poly_real(const Term* __restrict__ t, uint32_t cnt,
+__device__ __forceinline__ void poly_real(CTerm* t, uint32_t cnt,
                                           const double (&x)[PPT][NV], const double (&x2)[PPT][NV],
                                           double (&out)[PPT]) {
 #pragma unroll
@@ -166,7 +181,7 @@ __device__ __forceinline__ double mant_exp(double v, int& e) {
 
 // G0 and Lambda at corner W for PPT points.
 template <int NV, int PPT>
-__device__ __forceinline__ void corner_regular(const SecDev* __restrict__ S, const Term* __restrict__ terms,
+__device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
                                                int W, const double (&x)[PPT][NV],
                                                const double (&x2)[PPT][NV], double (&g0)[PPT],
                                                double (&lam)[PPT]) {
@@ -247,7 +262,7 @@ __device__ __forceinline__ void add_series(double (&f)[KM], double t, double z, 
 // Corners W and subsets T of S are wave-uniform runtime loops; the offset of
 // q = 0 in f (ns - |T|) selects one of MAXS+1 static accumulation bodies.
 template <int NV, int PPT, int KM>
-__device__ __forceinline__ void eval_f_real(const SecDev* __restrict__ S, const Term* __restrict__ terms,
+__device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms,
                                             const double (&x)[PPT][NV], double (&f)[PPT][KM]) {
   const int n = S->n;
   const int ns = S->ns;

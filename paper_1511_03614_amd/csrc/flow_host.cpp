@@ -465,11 +465,13 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
   return SDI_OK;
 }
 
-// Keeps a sector's flow only where it lowers that sector's variance: one
-// lattice pass and one flow pass at 2^lattice_log2 points per shift (the
-// context's other parameters), per active sector r_s = mean over the orders
-// with nonzero lattice variance of var_flow / var_lattice; the flow stays
-// active when r_s < 1.  kept (host, [nsectors], may be NULL) receives the flags.
+// Keeps a sector's flow only where it lowers that sector's share of the
+// error: one lattice pass and one flow pass at 2^lattice_log2 points per shift
+// (the context's other parameters); with V_k the lattice pass's total variance
+// of order k, the flow of sector s stays active when
+// sum_k var_flow(s,k) / V_k < sum_k var_lattice(s,k) / V_k, i.e. when it lowers
+// the sector's contribution to the relative variance of the result, summed
+// over the orders.  kept (host, [nsectors], may be NULL) receives the flags.
 int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32_t* kept, float* ms_out) {
   if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_validate: null argument");
   int rc = flow_ready(ctx, pb);
@@ -505,19 +507,19 @@ int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32
       }
   }
   ctx->params = saved;
+  std::vector<double> V(K, 0.0);
+  for (int s = 0; s < pb->nsec; ++s)
+    for (int k = 0; k < K; ++k) V[k] += v[0][(size_t)s * K + k];
   bool changed = false;
   for (int s = 0; s < pb->nsec; ++s) {
     if (F.active[s]) {
-      double sum = 0.0;
-      int cnt = 0;
-      for (int k = 0; k < K; ++k) {
-        const double vl = v[0][(size_t)s * K + k];
-        if (vl > 0.0) {
-          sum += v[1][(size_t)s * K + k] / vl;
-          ++cnt;
+      double sf = 0.0, sl = 0.0;
+      for (int k = 0; k < K; ++k)
+        if (V[k] > 0.0) {
+          sf += v[1][(size_t)s * K + k] / V[k];
+          sl += v[0][(size_t)s * K + k] / V[k];
         }
-      }
-      if (!(cnt > 0 && sum / cnt < 1.0)) {
+      if (!(sf < sl)) {
         F.active[s] = 0;
         changed = true;
       }

@@ -12,16 +12,16 @@ struct CplxArgs {
 };
 
 template <int NV, int PPT, int KM>
-__device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs& X, const SecDev* __restrict__ S,
+__device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs& X, CSec* S,
                                               const TileDesc& td, int tc, const double* __restrict__ lgrid,
                                               double* __restrict__ lhist, double (&sr)[KM], double (&cr)[KM],
                                               double (&si)[KM], double (&ci)[KM], int& nonfin, int& npos) {
   const uint32_t step = (uint32_t)blockDim.x * PPT;
-  const CplxDev* cx = X.cx + td.sector;
+  const SDI_TAPE CplxDev* cx = tape(X.cx) + td.sector;
   for (uint32_t off = threadIdx.x * PPT; off < td.count; off += step) {
     asm volatile("" ::: "memory");
-    const uint64_t* zp = A.zp + (size_t)td.sector * MAXV;
-    const uint64_t* sh = A.shifts + ((size_t)S->shift_row + td.shift) * MAXV;
+    CU64* zp = tape(A.zp) + (size_t)td.sector * MAXV;
+    CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
     double x[PPT][NV], w[PPT];
     int bins[PPT][NV];
     if constexpr (PPT == 1) {
@@ -43,7 +43,7 @@ __device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs&
     }
     cd f[PPT][KM];
     int imf[PPT];
-    eval_f_cplx<NV, PPT, KM>(S, cx, X.dir, A.terms, x, f, imf);
+    eval_f_cplx<NV, PPT, KM>(S, cx, tape(X.dir), tape(A.terms), x, f, imf);
     const int kf = S->kf;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_cplx(TileArgs A, CplxArgs X) {
     if (ti >= A.ntiles) return;
     const int tc = A.order[ti];
     const TileDesc td = A.tiles[tc];
-    const SecDev* S = A.secs + td.sector;
+    CSec* S = tape(A.secs) + td.sector;
     const int n = S->n;
     const int nb = S->nbins;
     const int kf = S->kf;
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_cplx(TileArgs A, CplxArgs X) {
 
 template <int NV, int KM>
 __device__ __forceinline__ void eval_point_cplx(const EvalArgs& A, const CplxArgs& X, int64_t i) {
-  const SecDev* S = A.sec;
+  CSec* S = tape(A.sec);
   const int n = S->n;
   const int K = S->K;
   double x[1][NV];
@@ -193,7 +193,7 @@ __device__ __forceinline__ void eval_point_cplx(const EvalArgs& A, const CplxArg
   for (int j = 0; j < NV; ++j) x[0][j] = j < n ? A.x[i * n + S->perm[j]] : 0.5;
   cd f[1][KM];
   int imf[1];
-  eval_f_cplx<NV, 1, KM>(S, X.cx, X.dir, A.terms, x, f, imf);
+  eval_f_cplx<NV, 1, KM>(S, tape(X.cx), tape(X.dir), tape(A.terms), x, f, imf);
   (void)imf;
   for (int k = 0; k < K; ++k) {
     double fr = 0.0, fi = 0.0;
@@ -211,7 +211,7 @@ template <int KM>
 __global__ void __launch_bounds__(BLOCK) k_eval_points_cplx(EvalArgs A, CplxArgs X) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.npts) return;
-  switch (A.sec->cls) {
+  switch (tape(A.sec)->cls) {
     case 0: eval_point_cplx<4, KM>(A, X, i); break;
     case 1: eval_point_cplx<8, KM>(A, X, i); break;
     default: break;
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(BLOCK) k_eval_tiles_cplx(EvalTilesArgs T, Cplx
     A.out = T.out + run.pt_off * T.K * 2;
     A.npts = run.count;
     const CplxArgs Xs{X.cx + run.sector, X.dir};
-    switch (A.sec->cls) {
+    switch (tape(A.sec)->cls) {
       case 0: eval_point_cplx<4, KM>(A, Xs, i); break;
       case 1: eval_point_cplx<8, KM>(A, Xs, i); break;
       default: break;
@@ -245,8 +245,7 @@ __global__ void __launch_bounds__(BLOCK) k_eval_tiles_cplx(EvalTilesArgs T, Cplx
 // the deformation size lam (the F - i0 side is left): the per-point test of
 // the automatic deformation-size search.
 template <int NV>
-__device__ __forceinline__ bool imf_any_corner(const SecDev* __restrict__ S, const CplxDev* __restrict__ X,
-                                               const uint32_t* __restrict__ dir, const Term* __restrict__ terms,
+__device__ __forceinline__ bool imf_any_corner(CSec* S, const SDI_TAPE CplxDev* X, CU32* dir, CTerm* terms,
                                                const double (&x)[1][NV], double lam) {
   const int n = S->n;
   const int ns = S->ns;
@@ -268,7 +267,7 @@ __device__ __forceinline__ bool imf_any_corner(const SecDev* __restrict__ S, con
       double g = 0.0;
       if (j < n) {
         double v[1];
-        const uint32_t* d = dir + (size_t)X->dir_off + ((size_t)j * MAXC + W) * 2;
+        CU32* d = dir + (size_t)X->dir_off + ((size_t)j * MAXC + W) * 2;
         poly_real3<NV, 1>(terms + d[0], d[1], x, x2, x4, v);
         g = v[0];
       }
@@ -295,7 +294,7 @@ __global__ void __launch_bounds__(BLOCK) k_lambda_test(const SecDev* secs, const
                                                        int64_t npts, const double* cand, int ncand, int32_t* fail) {
   __shared__ int32_t s_fail;
   const int s = blockIdx.y;
-  const SecDev* S = secs + s;
+  CSec* S = tape(secs) + s;
   if (threadIdx.x == 0) s_fail = 0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -303,10 +302,10 @@ __global__ void __launch_bounds__(BLOCK) k_lambda_test(const SecDev* secs, const
   if (i < npts) {
     double x[1][NVMAX], w[1];
     int bins[1][NVMAX];
-    make_points<NVMAX, 1>(S, zp + (size_t)s * MAXV, shifts + (size_t)S->shift_row * MAXV, nullptr, (uint64_t)i, x,
-                          w, bins);
+    make_points<NVMAX, 1>(S, tape(zp) + (size_t)s * MAXV, tape(shifts) + (size_t)S->shift_row * MAXV, nullptr,
+                          (uint64_t)i, x, w, bins);
     for (int k = 0; k < ncand; ++k)
-      if (imf_any_corner<NVMAX>(S, cx + s, dir, terms, x, cand[s * ncand + k])) mask |= 1 << k;
+      if (imf_any_corner<NVMAX>(S, tape(cx) + s, tape(dir), tape(terms), x, cand[s * ncand + k])) mask |= 1 << k;
   }
   if (mask) atomicOr(&s_fail, mask);
   __syncthreads();

@@ -12,7 +12,7 @@
 namespace sdi {
 
 template <int NV, int PPT, int KM>
-__device__ __forceinline__ void run_tile_real(const TileArgs& A, const SecDev* __restrict__ S,
+__device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
                                               const TileDesc& td, int tc, const double* __restrict__ lgrid,
                                               double* __restrict__ lhist, double (&s)[KM],
                                               double (&c)[KM], int& nonfin) {
@@ -21,8 +21,8 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, const SecDev* _
     // Re-read the sector record every iteration instead of pinning all of it in
     // SGPRs for the whole tile (scalar loads are cheap and cached).
     asm volatile("" ::: "memory");
-    const uint64_t* zp = A.zp + (size_t)td.sector * MAXV;
-    const uint64_t* sh = A.shifts + ((size_t)S->shift_row + td.shift) * MAXV;
+    CU64* zp = tape(A.zp) + (size_t)td.sector * MAXV;
+    CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
     double x[PPT][NV], w[PPT];
     int bins[PPT][NV];
     if constexpr (PPT == 1) {
@@ -43,7 +43,7 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, const SecDev* _
       make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
     }
     double f[PPT][KM];
-    eval_f_real<NV, PPT, KM>(S, A.terms, x, f);
+    eval_f_real<NV, PPT, KM>(S, tape(A.terms), x, f);
     const int kf = S->kf;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
     if (ti >= A.ntiles) return;
     const int tc = A.order[ti];
     const TileDesc td = A.tiles[tc];
-    const SecDev* S = A.secs + td.sector;
+    CSec* S = tape(A.secs) + td.sector;
     const int n = S->n;
     const int nb = S->nbins;
     const int kf = S->kf;
@@ -172,14 +172,14 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
 // Values of every result order at caller points (justEvaluate, parity checks).
 template <int NV, int KM>
 __device__ __forceinline__ void eval_point_real(const EvalArgs& A, int64_t i) {
-  const SecDev* S = A.sec;
+  CSec* S = tape(A.sec);
   const int n = S->n;
   const int K = S->K;
   double x[1][NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) x[0][j] = j < n ? A.x[i * n + S->perm[j]] : 0.5;
   double f[1][KM];
-  eval_f_real<NV, 1, KM>(S, A.terms, x, f);
+  eval_f_real<NV, 1, KM>(S, tape(A.terms), x, f);
   for (int k = 0; k < K; ++k) {
     double fr = 0.0, fi = 0.0;
 #pragma unroll
@@ -196,7 +196,7 @@ template <int KM>
 __global__ void __launch_bounds__(BLOCK) k_eval_points_real(EvalArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.npts) return;
-  switch (A.sec->cls) {
+  switch (tape(A.sec)->cls) {
     case 0: eval_point_real<4, KM>(A, i); break;
     case 1: eval_point_real<8, KM>(A, i); break;
     case 2: eval_point_real<16, KM>(A, i); break;
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(BLOCK) k_eval_tiles_real(EvalTilesArgs T) {
     A.x = T.x + run.x_off;
     A.out = T.out + run.pt_off * T.K * 2;
     A.npts = run.count;
-    switch (A.sec->cls) {
+    switch (tape(A.sec)->cls) {
       case 0: eval_point_real<4, KM>(A, i); break;
       case 1: eval_point_real<8, KM>(A, i); break;
       case 2: eval_point_real<16, KM>(A, i); break;
