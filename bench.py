@@ -200,8 +200,8 @@ def main() -> int:
                     help="skip the learned-sampler comparison (double box, Euclidean and physical)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "sectors shard across GPUs as described in DESIGN.md, but no multi-GPU run is made.",
+        print(f"bench.py: this benchmark measures one GPU only (asked for --gpus {args.gpus}); "
+              "sectors would shard across GPUs by longest-processing-time assignment, but no multi-GPU run is made.",
               file=sys.stderr)
         return 2
     import numpy as np

@@ -19,7 +19,7 @@ What it computes (paper: FIESTA 4, arXiv:1511.03614):
 * ``integrate``  - per-sector, per-shift means, the shift-to-shift error and
   the root-sum-square combination of section 4.3.
 
-Readings of the paper where it is silent are listed in the design doc; each
-function's docstring names the passage it follows.
+Where the paper is silent, each function's docstring states the reading it
+takes and names the passage it follows.
 """
 from . import integrand, points, prefactor, vegas, integrate  # noqa: F401

@@ -130,8 +130,8 @@ def neyman_allocation(estimates: List[SectorEstimate], budget: int, nshifts: int
     (equal shares if every error is zero), and the lattice log2 is the nearest
     integer to log2(share / R), clamped to [lo, hi].  Variance-proportional
     (Neyman) allocation of sampling effort; the paper's integrator adapts
-    points within one integral only (section 4.4), so this reading is stated in
-    DESIGN.md.
+    points within one integral only (section 4.4), so this is a reading, not
+    the paper's rule.
     """
     nsec = len(estimates)
     K = estimates[0].mean.shape[0]

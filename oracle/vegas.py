@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper's default integrator is Cuba's Vegas (section 4.4, CurrentIntegrator);
 Cuba's own constants are not given there, so this is Lepage's published
-refinement with the constants stated in the design doc:
+refinement with these constants:
 
 * importance of a point: rho = sum_k |w f_k|^2 / H_{j,k} over the sector's
   internal eps orders f_k (before the prefactor series multiplies them), where

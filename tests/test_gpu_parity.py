@@ -1,6 +1,6 @@
 """GPU parity: the HIP library against the fp64 oracle on identical points.
 
-Bars (derived in the design doc):
+Bars:
 * sampling points: bit-exact (integer lattice arithmetic, one rounding per op);
 * per point: |gpu - oracle| <= 1e-12 |oracle| + 4e-15 * cond, cond = sum of the
   absolute values of every subtraction/series term (the oracle returns it);
