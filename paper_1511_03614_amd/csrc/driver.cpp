@@ -298,9 +298,10 @@ int launch_tiles(const sdi_problem* pb, int ppt, int km, int grid, size_t shmem,
   return launch_tiles_real(pb->nvmax, ppt, km, grid, shmem, a, st);
 }
 
-int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int ppt, int km, size_t shmem, size_t ntiles) {
+int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int km, size_t shmem, size_t ntiles) {
   const int nvmax = pb->nvmax;
-  int occ = pb->complex_mode ? tiles_cplx_occupancy(nvmax, ppt, km, shmem) : tiles_real_occupancy(nvmax, ppt, km, shmem);
+  int occ = pb->complex_mode ? tiles_cplx_occupancy(nvmax, mode, ppt, km, shmem)
+                             : tiles_real_occupancy(nvmax, mode, ppt, km, shmem);
   if (occ < 1) occ = 1;
   const size_t g = (size_t)occ * std::max(ctx->ncu, 1);
   return (int)std::max<size_t>(1, std::min(g, ntiles));
@@ -427,7 +428,7 @@ int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
   int best = 1;
   float best_ms = 1e30f;
   for (int ppt : ppt_candidates(pb)) {
-    const int g = persistent_grid(ctx, pb, ppt, S.km, P.shmem_final, P.forder.size());
+    const int g = persistent_grid(ctx, pb, 0, ppt, S.km, P.shmem_final, P.forder.size());
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       KCHK(ctx, launch_fill_i32(F.counter, 0, 1, st));
@@ -538,10 +539,10 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
     if (rc < 0) return rc;
     S->ppt = rc;
   }
-  S->gf = persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_final, std::max<size_t>(1, P.forder.size()));
+  S->gf = persistent_grid(ctx, pb, 0, S->ppt, S->km, P.shmem_final, std::max<size_t>(1, P.forder.size()));
   // explicit (flow) points are read by the one-point-per-thread instances
-  S->gx = persistent_grid(ctx, pb, 1, S->km, P.shmem_final, std::max<size_t>(1, P.xorder.size()));
-  S->gw = P.warm ? persistent_grid(ctx, pb, S->ppt, S->km, P.shmem_warm, P.wtiles.size()) : 1;
+  S->gx = persistent_grid(ctx, pb, 2, 1, S->km, P.shmem_final, std::max<size_t>(1, P.xorder.size()));
+  S->gw = P.warm ? persistent_grid(ctx, pb, 1, S->ppt, S->km, P.shmem_warm, P.wtiles.size()) : 1;
   if (prm.graph) {
     // Capture each segment once; replays skip the launch overheads.  Timing
     // events stay outside the graphs, between segment launches.  Any failure

@@ -7,9 +7,9 @@ namespace sdi {
 int launch_tiles_real_nv4(int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv8(int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv16(int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
-int occupancy_tiles_real_nv4(int ppt, int km, size_t shmem);
-int occupancy_tiles_real_nv8(int ppt, int km, size_t shmem);
-int occupancy_tiles_real_nv16(int ppt, int km, size_t shmem);
+int occupancy_tiles_real_nv4(int mode, int ppt, int km, size_t shmem);
+int occupancy_tiles_real_nv8(int mode, int ppt, int km, size_t shmem);
+int occupancy_tiles_real_nv16(int mode, int ppt, int km, size_t shmem);
 
 int launch_tiles_real(int nvmax, int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st) {
   if (nvmax <= 4) return launch_tiles_real_nv4(ppt, km, grid, shmem, a, st);
@@ -17,10 +17,10 @@ int launch_tiles_real(int nvmax, int ppt, int km, int grid, size_t shmem, const 
   return launch_tiles_real_nv16(ppt, km, grid, shmem, a, st);
 }
 
-int tiles_real_occupancy(int nvmax, int ppt, int km, size_t shmem) {
-  if (nvmax <= 4) return occupancy_tiles_real_nv4(ppt, km, shmem);
-  if (nvmax <= 8) return occupancy_tiles_real_nv8(ppt, km, shmem);
-  return occupancy_tiles_real_nv16(ppt, km, shmem);
+int tiles_real_occupancy(int nvmax, int mode, int ppt, int km, size_t shmem) {
+  if (nvmax <= 4) return occupancy_tiles_real_nv4(mode, ppt, km, shmem);
+  if (nvmax <= 8) return occupancy_tiles_real_nv8(mode, ppt, km, shmem);
+  return occupancy_tiles_real_nv16(mode, ppt, km, shmem);
 }
 
 int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st) {

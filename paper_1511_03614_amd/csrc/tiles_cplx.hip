@@ -7,25 +7,28 @@ namespace sdi {
 int launch_tiles_cplx(int nvmax, int ppt, int km, int grid, size_t shmem, const TileArgs& a, const void* cx,
                       const uint32_t* dir, hipStream_t st) {
   const CplxArgs X{(const CplxDev*)cx, dir};
-#define SDI_L(NV, P, K)                                                                \
-  if (nvmax == NV && ppt == P && km == K) {                                             \
-    k_tiles_cplx<NV, P, K><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a, X);               \
-    return (int)hipGetLastError();                                                      \
+  const int mode = a.mode;
+  if (mode == 2) ppt = 1;
+#define SDI_L(M, NV, P, K)                                                             \
+  if (mode == M && nvmax == NV && ppt == P && km == K) {                                \
+    k_tiles_cplx<NV, P, K, M><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a, X);            \
+    return (int)hipGetLastError();                                                     \
   }
-  SDI_L(4, 1, 4) SDI_L(4, 2, 4) SDI_L(4, 1, 8) SDI_L(4, 2, 8) SDI_L(8, 1, 4) SDI_L(8, 1, 8)
+  SDI_L(0, 4, 1, 4) SDI_L(0, 4, 2, 4) SDI_L(0, 4, 1, 8) SDI_L(0, 4, 2, 8) SDI_L(0, 8, 1, 4) SDI_L(0, 8, 1, 8) SDI_L(1, 4, 1, 4) SDI_L(1, 4, 2, 4) SDI_L(1, 4, 1, 8) SDI_L(1, 4, 2, 8) SDI_L(1, 8, 1, 4) SDI_L(1, 8, 1, 8) SDI_L(2, 4, 1, 4) SDI_L(2, 4, 1, 8) SDI_L(2, 8, 1, 4) SDI_L(2, 8, 1, 8)
 #undef SDI_L
   return (int)hipErrorInvalidValue;
 }
 
-int tiles_cplx_occupancy(int nvmax, int ppt, int km, size_t shmem) {
+int tiles_cplx_occupancy(int nvmax, int mode, int ppt, int km, size_t shmem) {
   int nb = 0;
-#define SDI_O(NV, P, K)                                                                                    \
-  if (nvmax == NV && ppt == P && km == K) {                                                                 \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles_cplx<NV, P, K>, BLOCK, shmem) != hipSuccess) \
-      return 0;                                                                                             \
-    return nb;                                                                                              \
+  if (mode == 2) ppt = 1;
+#define SDI_O(M, NV, P, K)                                                                                      \
+  if (mode == M && nvmax == NV && ppt == P && km == K) {                                                        \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles_cplx<NV, P, K, M>, BLOCK, shmem) != hipSuccess) \
+      return 0;                                                                                                \
+    return nb;                                                                                                 \
   }
-  SDI_O(4, 1, 4) SDI_O(4, 2, 4) SDI_O(4, 1, 8) SDI_O(4, 2, 8) SDI_O(8, 1, 4) SDI_O(8, 1, 8)
+  SDI_O(0, 4, 1, 4) SDI_O(0, 4, 2, 4) SDI_O(0, 4, 1, 8) SDI_O(0, 4, 2, 8) SDI_O(0, 8, 1, 4) SDI_O(0, 8, 1, 8) SDI_O(1, 4, 1, 4) SDI_O(1, 4, 2, 4) SDI_O(1, 4, 1, 8) SDI_O(1, 4, 2, 8) SDI_O(1, 8, 1, 4) SDI_O(1, 8, 1, 8) SDI_O(2, 4, 1, 4) SDI_O(2, 4, 1, 8) SDI_O(2, 8, 1, 4) SDI_O(2, 8, 1, 8)
 #undef SDI_O
   return 0;
 }

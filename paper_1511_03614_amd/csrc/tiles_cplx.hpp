@@ -11,7 +11,7 @@ struct CplxArgs {
   const uint32_t* dir;      // derivative-list directory
 };
 
-template <int NV, int PPT, int KM>
+template <int NV, int PPT, int KM, int MODE>
 __device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs& X, CSec* S,
                                               const TileDesc& td, int tc, const double* __restrict__ lgrid,
                                               double* __restrict__ lhist, double (&sr)[KM], double (&cr)[KM],
@@ -24,8 +24,9 @@ __device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs&
     CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
     double x[PPT][NV], w[PPT];
     int bins[PPT][NV];
-    if constexpr (PPT == 1) {
-      if (A.mode == 2) {
+    if constexpr (MODE == 2) {
+      static_assert(PPT == 1, "explicit points are read one per thread");
+      {
         // explicit points (a learned sampler): caller order, weight 1/q
         const int n = S->n;
         const double* xp = A.px + A.x_off[tc] + (size_t)off * n;
@@ -35,8 +36,6 @@ __device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs&
           bins[0][j] = 0;
         }
         w[0] = A.pw[A.pt_off[tc] + off];
-      } else {
-        make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
       }
     } else {
       make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
@@ -58,7 +57,7 @@ __device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs&
       }
       nonfin += bad ? 1 : 0;
       npos += imf[p];
-      if (lhist) {
+      if constexpr (MODE == 1) {
         const int n = S->n;
         const int nb = S->nbins;
 #pragma unroll
@@ -87,7 +86,7 @@ __device__ __forceinline__ void wave_dd_reduce(double hi, double lo, double& ohi
   olo = lo;
 }
 
-template <int NVMAX, int PPT, int KM>
+template <int NVMAX, int PPT, int KM, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_tiles_cplx(TileArgs A, CplxArgs X) {
   extern __shared__ double smem[];
   __shared__ int s_tile, s_nonfin, s_pos;
@@ -118,7 +117,7 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_cplx(TileArgs A, CplxArgs X) {
       for (int i = threadIdx.x; i < n * (nb + 1); i += blockDim.x) lgrid[i] = g[i];
       soff = (size_t)n * (nb + 1);
     }
-    if (A.mode == 1) {
+    if constexpr (MODE == 1) {
       lhist = smem + soff;
       for (int i = threadIdx.x; i < n * nb * kf; i += blockDim.x) lhist[i] = 0.0;
     }
@@ -129,10 +128,10 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_cplx(TileArgs A, CplxArgs X) {
     int nonfin = 0, npos = 0;
     switch (S->cls) {
       case 0:
-        run_tile_cplx<4, PPT, KM>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+        run_tile_cplx<4, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
         break;
       case 1:
-        if constexpr (NVC >= 1) run_tile_cplx<8, PPT, KM>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+        if constexpr (NVC >= 1) run_tile_cplx<8, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
         break;
       default:
         break;
@@ -176,7 +175,7 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_cplx(TileArgs A, CplxArgs X) {
       A.nonfinite[2 * tc] = s_nonfin;
       A.nonfinite[2 * tc + 1] = s_pos;
     }
-    if (A.mode == 1) {
+    if constexpr (MODE == 1) {
       double* gh = A.hist + A.hist_off[tc];
       for (int i = threadIdx.x; i < n * nb * kf; i += blockDim.x) gh[i] = lhist[i];
     }

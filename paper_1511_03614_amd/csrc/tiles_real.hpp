@@ -11,7 +11,7 @@
 
 namespace sdi {
 
-template <int NV, int PPT, int KM>
+template <int NV, int PPT, int KM, int MODE>
 __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
                                               const TileDesc& td, int tc, const double* __restrict__ lgrid,
                                               double* __restrict__ lhist, double (&s)[KM],
@@ -25,8 +25,9 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
     CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
     double x[PPT][NV], w[PPT];
     int bins[PPT][NV];
-    if constexpr (PPT == 1) {
-      if (A.mode == 2) {
+    if constexpr (MODE == 2) {
+      static_assert(PPT == 1, "explicit points are read one per thread");
+      {
         // explicit points (a learned sampler): caller order, weight 1/q
         const int n = S->n;
         const double* xp = A.px + A.x_off[tc] + (size_t)off * n;
@@ -36,8 +37,6 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
           bins[0][j] = 0;
         }
         w[0] = A.pw[A.pt_off[tc] + off];
-      } else {
-        make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
       }
     } else {
       make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
@@ -55,7 +54,7 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
         bad |= !isfinite(v);
       }
       nonfin += bad ? 1 : 0;
-      if (lhist) {
+      if constexpr (MODE == 1) {
         const int n = S->n;
         const int nb = S->nbins;
 #pragma unroll
@@ -72,7 +71,7 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
   }
 }
 
-template <int NVMAX, int PPT, int KM>
+template <int NVMAX, int PPT, int KM, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
   extern __shared__ double smem[];
   __shared__ int s_tile;
@@ -103,7 +102,7 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
       for (int i = threadIdx.x; i < n * (nb + 1); i += blockDim.x) lgrid[i] = g[i];
       soff = (size_t)n * (nb + 1);
     }
-    if (A.mode == 1) {
+    if constexpr (MODE == 1) {
       lhist = smem + soff;
       for (int i = threadIdx.x; i < n * nb * kf; i += blockDim.x) lhist[i] = 0.0;
     }
@@ -116,13 +115,13 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
     const int cls = S->cls;
     switch (cls) {
       case 0:
-        run_tile_real<4, PPT, KM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        run_tile_real<4, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       case 1:
-        if constexpr (NVC >= 1) run_tile_real<8, PPT, KM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        if constexpr (NVC >= 1) run_tile_real<8, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       case 2:
-        if constexpr (NVC >= 2) run_tile_real<16, PPT, KM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        if constexpr (NVC >= 2) run_tile_real<16, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       default:
         break;
@@ -162,7 +161,7 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
       A.nonfinite[2 * tc] = s_nonfin;
       A.nonfinite[2 * tc + 1] = 0;
     }
-    if (A.mode == 1) {
+    if constexpr (MODE == 1) {
       double* gh = A.hist + A.hist_off[tc];
       for (int i = threadIdx.x; i < n * nb * kf; i += blockDim.x) gh[i] = lhist[i];
     }
