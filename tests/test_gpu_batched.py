@@ -43,7 +43,7 @@ def test_config4_allocation_at_scale(ctx):
         est = []
         for s in range(ns):
             mean, err, _, _ = P.sdi_sector_results(ctx, h, s, R)
-            est.append(integrate.SectorEstimate(q=None, mean=mean[:, 0] + 1j * mean[:, 1], err_re=err[:, 0],
+            est.append(integrate.SectorEstimate(q=None, mean=mean, err_re=err[:, 0],
                                                 err_im=err[:, 1], n_nonfinite=0, n_imf_positive=0, grid=None))
         m_rule = integrate.neyman_allocation(est, budget, R, lo, hi)
         set_params(ctx, shifts=R, seed=41, budget=budget, pilot_log2=pilot, alloc_min_log2=lo, alloc_max_log2=hi)
