@@ -267,8 +267,11 @@ int sdi_flow_set_active(sdi_ctx* ctx, sdi_problem* prob, int32_t s, int32_t acti
  * at 2^lattice_log2 points per shift (other parameters from ctx); with V_k the
  * lattice pass's total variance of order k, an active sector keeps its flow
  * only if sum_k var_flow(s,k)/V_k < sum_k var_lattice(s,k)/V_k.  kept (host [nsectors], may be NULL) receives the active flags,
- * *ms_out (may be NULL) the device time of the two passes.  The per-sector
- * results left on the problem are those of the flow pass. */
+ * *ms_out (may be NULL) the device time of the passes run.  If the problem's
+ * last results come from a lattice pass with the same lattice_log2, shifts and
+ * seed (no warm-up, no allocation), they serve as the lattice pass and only
+ * the flow pass runs.  The per-sector results left on the problem are those of
+ * the flow pass. */
 int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* prob, int32_t lattice_log2, int32_t* kept, float* ms_out);
 
 #ifdef __cplusplus

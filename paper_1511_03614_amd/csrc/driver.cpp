@@ -695,6 +695,10 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   if (prm.warmup == 0) pb->grid_valid = false;
   pb->last_R = prm.R;
   pb->have_results = true;
+  pb->last_sampler = prm.sampler;
+  pb->last_m = prm.budget > 0 ? -1 : prm.m;
+  pb->last_warmup = prm.warmup;
+  pb->last_seed = prm.seed;
   pb->sec_stats = o.sec_stats;
   pb->per_shift = o.per_shift;
   pb->sec_evals.assign(nsec, 0);

@@ -19,9 +19,11 @@ int launch_flow_init(const FlowSecDesc* fs, int nsec, float* params, uint64_t se
   return (int)hipGetLastError();
 }
 
-int launch_flow_copies(const FlowSecDesc* fs, int nsec, const float* params, uint16_t* bw, hipStream_t st) {
-  if (nsec <= 0) return 0;
-  k_flow_copies<<<dim3(32, nsec), dim3(256), 0, st>>>(fs, nsec, params, bw);
+int launch_flow_copies(const FlowSecDesc* fs, const FlowTile* runs, int nruns, int nsec, const float* params,
+                       uint16_t* bw, hipStream_t st) {
+  const int ny = runs ? nruns : nsec;
+  if (ny <= 0) return 0;
+  k_flow_copies<<<dim3(32, ny), dim3(256), 0, st>>>(fs, runs, nsec, params, bw);
   return (int)hipGetLastError();
 }
 

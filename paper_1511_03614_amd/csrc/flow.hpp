@@ -372,9 +372,10 @@ __global__ void k_flow_init(const FlowSecDesc* fs, int nsec, float* P, uint64_t 
   }
 }
 
-// bf16 copies (padded row-major and transposed) of every weight matrix.
-__global__ void k_flow_copies(const FlowSecDesc* fs, int nsec, const float* P, uint16_t* bw) {
-  const int s = blockIdx.y;
+// bf16 copies (padded row-major and transposed) of every weight matrix of the
+// sectors of `runs` (blockIdx.y = run), or of sector blockIdx.y when runs is null.
+__global__ void k_flow_copies(const FlowSecDesc* fs, const FlowTile* runs, int nsec, const float* P, uint16_t* bw) {
+  const int s = runs ? runs[blockIdx.y].sector : (int)blockIdx.y;
   if (s >= nsec) return;
   const FlowSecDesc& F = fs[s];
   const float* Ps = P + F.base;

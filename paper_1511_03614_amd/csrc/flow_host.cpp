@@ -95,9 +95,13 @@ int flow_scratch(sdi_ctx* ctx, FlowState& F, size_t bytes) {
   return SDI_OK;
 }
 
-int blocks_per_run(int64_t count) {
+// Blocks of the backward kernels per run: about 512 blocks in total (one per
+// CU is what their register use allows, twice over), at least 4 chunks per
+// block when there are chunks to spare, at most one block per chunk.
+int blocks_per_run(int64_t count, int nruns) {
   const int64_t chunks = (count + FL_CHUNK - 1) / FL_CHUNK;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(64, (chunks + 3) / 4));
+  const int64_t want = (512 + nruns - 1) / std::max(nruns, 1);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, std::max<int64_t>(want, (chunks + 3) / 4)));
 }
 
 }  // namespace
@@ -118,7 +122,7 @@ int flow_gradient(sdi_ctx* ctx, sdi_problem* pb, const PointRun* d_runs, int nru
   A.dl = dl;
   A.part = part;
   A.part_stride = F.max_lsize;
-  const int bpt = blocks_per_run(max_count);
+  const int bpt = blocks_per_run(max_count, nruns);
   const int bfw = (int)std::max<int64_t>(1, std::min<int64_t>(256, (max_count + 63) / 64));
   KCHK(ctx, launch_flow_fwd_store(A, bfw, st));
   for (int l = FL_L - 1; l >= 0; --l) {
@@ -130,7 +134,7 @@ int flow_gradient(sdi_ctx* ctx, sdi_problem* pb, const PointRun* d_runs, int nru
 }
 
 size_t flow_grad_part_bytes(const FlowState& F, int nruns, int64_t max_count) {
-  return (size_t)nruns * blocks_per_run(max_count) * F.max_lsize * sizeof(float);
+  return (size_t)nruns * blocks_per_run(max_count, nruns) * F.max_lsize * sizeof(float);
 }
 
 }  // namespace sdi
@@ -166,7 +170,7 @@ int sdi_flow_init(sdi_ctx* ctx, sdi_problem* pb, uint64_t seed) {
   HIPCHK(ctx, hipMemsetAsync(F.d_v, 0, np * 4, st));
   HIPCHK(ctx, hipMemsetAsync(F.d_grad, 0, np * 4, st));
   KCHK(ctx, launch_flow_init(F.d_desc, pb->nsec, F.d_params, seed, st));
-  KCHK(ctx, launch_flow_copies(F.d_desc, pb->nsec, F.d_params, F.d_bw, st));
+  KCHK(ctx, launch_flow_copies(F.d_desc, nullptr, 0, pb->nsec, F.d_params, F.d_bw, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
   return SDI_OK;
 }
@@ -199,7 +203,7 @@ int sdi_flow_set_params(sdi_ctx* ctx, sdi_problem* pb, int32_t s, const float* i
   if (n != D.nparam) return fail(ctx, SDI_EINVAL, "flow_set_params: wrong parameter count");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   HIPCHK(ctx, hipMemcpyAsync(F.d_params + D.base, in, n * 4, hipMemcpyHostToDevice, ctx->stream));
-  KCHK(ctx, launch_flow_copies(F.d_desc, pb->nsec, F.d_params, F.d_bw, ctx->stream));
+  KCHK(ctx, launch_flow_copies(F.d_desc, nullptr, 0, pb->nsec, F.d_params, F.d_bw, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   if (!F.active[s]) free_passes(pb->passes);   // the split of the pass between lattice and flow changes
   F.active[s] = 1;
@@ -311,7 +315,7 @@ int sdi_flow_adam(sdi_ctx* ctx, sdi_problem* pb, double lr) {
   HIPCHK(ctx, hipMemcpyAsync(d_runs, runs.data(), sizeof(PointRun) * nsec, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(d_bc, bc.data(), bc.size() * 8, hipMemcpyHostToDevice, st));
   KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.d_desc, d_runs, nsec, F.max_nparam, lr, d_bc, st));
-  KCHK(ctx, launch_flow_copies(F.d_desc, nsec, F.d_params, F.d_bw, st));
+  KCHK(ctx, launch_flow_copies(F.d_desc, nullptr, 0, nsec, F.d_params, F.d_bw, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
   return SDI_OK;
 }
@@ -412,48 +416,82 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
       if (b) (void)hipEventDestroy(b);
     }
   } guard{e0, e1};
-  HIPCHK(ctx, hipEventRecord(e0, st));
-  KCHK(ctx, launch_flow_shifts(F.d_desc, d_runs, nr, iters, batch_log2, ctx->params.seed, 65536u, d_shifts, st));
   const int km = pb->kfmax <= 4 ? 4 : 8;
-  for (int it = 0; it < iters; ++it) {
-    FlowTileArgs S{};
-    S.fs = F.d_desc;
-    S.params = F.d_params;
-    S.bw = F.d_bw;
-    S.zp = d_zp;
-    S.shifts = d_shifts + (size_t)it * nr * MAXV;
-    S.tiles = d_runs;
-    S.chunk_prefix = d_pre64;
-    S.ntiles = nr;
-    S.baker = ctx->params.baker;
-    S.nchunks = pre64[nr];
-    S.x = x;
-    S.w = w;
-    S.lq = lq;
-    KCHK(ctx, launch_flow_sample_tiles(S, st));
-    EvalTilesArgs E{};
-    E.secs = pb->d_secs;
-    E.terms = pb->d_terms;
-    E.runs = d_runs;
-    E.chunk_prefix = d_pre256;
-    E.nruns = nr;
-    E.K = K;
-    E.nchunks = pre256[nr];
-    E.x = x;
-    E.out = f;
-    if (pb->complex_mode)
-      KCHK(ctx, launch_eval_tiles_cplx(km, E, pb->d_cx, pb->d_dir, st));
-    else
-      KCHK(ctx, launch_eval_tiles_real(km, E, st));
-    KCHK(ctx, launch_flow_weights(d_runs, nr, K, f, lq, c, st));
-    rc = flow_gradient(ctx, pb, d_runs, nr, Bt, x, c, hsave, dl, part, st);
-    if (rc) return rc;
-    KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.d_desc, d_runs, nr, F.max_nparam, lr,
-                               d_bc + (size_t)it * nr * 2, st));
-    KCHK(ctx, launch_flow_copies(F.d_desc, pb->nsec, F.d_params, F.d_bw, st));
+  // every step of every iteration, enqueued on st
+  auto enqueue = [&]() -> int {
+    KCHK(ctx, launch_flow_shifts(F.d_desc, d_runs, nr, iters, batch_log2, ctx->params.seed, 65536u, d_shifts, st));
+    for (int it = 0; it < iters; ++it) {
+      FlowTileArgs S{};
+      S.fs = F.d_desc;
+      S.params = F.d_params;
+      S.bw = F.d_bw;
+      S.zp = d_zp;
+      S.shifts = d_shifts + (size_t)it * nr * MAXV;
+      S.tiles = d_runs;
+      S.chunk_prefix = d_pre64;
+      S.ntiles = nr;
+      S.baker = ctx->params.baker;
+      S.nchunks = pre64[nr];
+      S.x = x;
+      S.w = w;
+      S.lq = lq;
+      KCHK(ctx, launch_flow_sample_tiles(S, st));
+      EvalTilesArgs E{};
+      E.secs = pb->d_secs;
+      E.terms = pb->d_terms;
+      E.runs = d_runs;
+      E.chunk_prefix = d_pre256;
+      E.nruns = nr;
+      E.K = K;
+      E.nchunks = pre256[nr];
+      E.x = x;
+      E.out = f;
+      if (pb->complex_mode)
+        KCHK(ctx, launch_eval_tiles_cplx(km, E, pb->d_cx, pb->d_dir, st));
+      else
+        KCHK(ctx, launch_eval_tiles_real(km, E, st));
+      KCHK(ctx, launch_flow_weights(d_runs, nr, K, f, lq, c, st));
+      const int r2 = flow_gradient(ctx, pb, d_runs, nr, Bt, x, c, hsave, dl, part, st);
+      if (r2) return r2;
+      KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.d_desc, d_runs, nr, F.max_nparam, lr,
+                                 d_bc + (size_t)it * nr * 2, st));
+      KCHK(ctx, launch_flow_copies(F.d_desc, d_runs, nr, pb->nsec, F.d_params, F.d_bw, st));
+    }
+    return SDI_OK;
+  };
+  // one graph for the whole loop (launch overheads dominate small batches);
+  // eager launches if capture is off or fails
+  struct GraphGuard {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    ~GraphGuard() {
+      if (ge) (void)hipGraphExecDestroy(ge);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } gg;
+  if (ctx->params.graph) {
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const int rr = enqueue();
+      const hipError_t ec = hipStreamEndCapture(st, &gg.g);
+      if (!(rr == SDI_OK && ec == hipSuccess && gg.g &&
+            hipGraphInstantiate(&gg.ge, gg.g, nullptr, nullptr, 0) == hipSuccess))
+        gg.ge = nullptr;
+    }
+    (void)hipGetLastError();
+    ctx->err.clear();
   }
-  HIPCHK(ctx, hipEventRecord(e1, st));
-  HIPCHK(ctx, hipEventSynchronize(e1));
+  if (gg.ge) {
+    HIPCHK(ctx, hipEventRecord(e0, st));
+    HIPCHK(ctx, hipGraphLaunch(gg.ge, st));
+    HIPCHK(ctx, hipEventRecord(e1, st));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+  } else {
+    HIPCHK(ctx, hipEventRecord(e0, st));
+    rc = enqueue();
+    if (rc) return rc;
+    HIPCHK(ctx, hipEventRecord(e1, st));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+  }
   float ms = 0.f;
   HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
   if (ms_out) *ms_out = ms;
@@ -483,7 +521,18 @@ int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32
   const int K = pb->K;
   std::vector<double> re(K), im(K), er(K), ei(K);
   double ms = 0.0;
-  for (int pass = 0; pass < 2; ++pass) {
+  // a lattice pass with these parameters that already ran is not repeated
+  const bool reuse = pb->have_results && pb->last_sampler == 0 && pb->last_m == lattice_log2 &&
+                     pb->last_R == saved.R && pb->last_seed == saved.seed && pb->last_warmup == 0;
+  for (int pass = reuse ? 1 : 0; pass < 2; ++pass) {
+    if (pass == 1 && reuse) {
+      v[0].assign((size_t)pb->nsec * K, 0.0);
+      for (int s = 0; s < pb->nsec; ++s)
+        for (int k = 0; k < K; ++k) {
+          const double* q = pb->sec_stats.data() + ((size_t)s * KMAX + k) * 4;
+          v[0][(size_t)s * K + k] = q[2] * q[2] + q[3] * q[3];
+        }
+    }
     ctx->params.m = lattice_log2;
     ctx->params.sampler = pass;
     ctx->params.warmup = 0;

@@ -130,6 +130,10 @@ struct sdi_problem {
   // results of the last integrate
   int last_R = 0;
   bool have_results = false;
+  int last_sampler = -1;              // parameters of the pass that produced the last results
+  int last_m = -1;                    // uniform lattice log2, -1 under budget allocation
+  int last_warmup = 0;
+  uint64_t last_seed = 0;
   std::vector<double> sec_stats;      // [nsec][KMAX][4]
   std::vector<double> per_shift;      // [nsec*R][KMAX][2]
   std::vector<int64_t> sec_evals;

@@ -53,7 +53,9 @@ int launch_eval_tiles_cplx(int km, const EvalTilesArgs& a, const void* cx, const
 
 // Learned sampler (coupling flow).
 int launch_flow_init(const FlowSecDesc* fs, int nsec, float* params, uint64_t seed, hipStream_t st);
-int launch_flow_copies(const FlowSecDesc* fs, int nsec, const float* params, uint16_t* bw, hipStream_t st);
+// bf16 copies of the flows of the sectors of runs (all nsec sectors when runs is null).
+int launch_flow_copies(const FlowSecDesc* fs, const FlowTile* runs, int nruns, int nsec, const float* params,
+                       uint16_t* bw, hipStream_t st);
 // Adam over the parameters of the sectors of runs; bc: device [nruns][2] = 1 - beta1^t, 1 - beta2^t.
 int launch_flow_adam(float* params, const float* grad, float* m, float* v, const FlowSecDesc* fs,
                      const FlowTile* runs, int nruns, int64_t max_nparam, double lr, const double* bc,
