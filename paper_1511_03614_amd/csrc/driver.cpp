@@ -76,7 +76,7 @@ struct Plan {
 struct PassState {
   std::string key;
   Plan P;
-  int ppt = 1, km = 4, gf = 1, gw = 1, gx = 1;
+  int ppt = 1, wpe = 4, km = 4, gf = 1, gw = 1, gx = 1;
   hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};   // warm-up, final tiles, reductions
   void* own_ws = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // recorded between segment launches
@@ -287,21 +287,31 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   return SDI_OK;
 }
 
-std::vector<int> ppt_candidates(const sdi_problem* pb) {
-  if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{1, 2} : std::vector<int>{1};
-  if (pb->nvmax >= 16) return {1, 2};
-  return {1, 2, 4};
+// Final-pass launch variants the autotuner times, encoded as 10 * points per
+// thread + minimum waves per SIMD (0: the compiler's choice, complex mode).
+std::vector<int> tile_variants(const sdi_problem* pb) {
+  if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{10, 20} : std::vector<int>{10};
+  if (pb->nvmax >= 16) return {14, 23, 24};
+  return {14, 23, 24, 42};
 }
 
-int launch_tiles(const sdi_problem* pb, int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st) {
+// The variant used for a fixed points-per-thread request.
+int default_variant(const sdi_problem* pb, int ppt) {
+  if (pb->complex_mode) return 10 * ppt;
+  return ppt == 4 ? 42 : 10 * ppt + 4;
+}
+
+int launch_tiles(const sdi_problem* pb, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
+                 hipStream_t st) {
   if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
-  return launch_tiles_real(pb->nvmax, ppt, km, grid, shmem, a, st);
+  return launch_tiles_real(pb->nvmax, ppt, wpe, km, grid, shmem, a, st);
 }
 
-int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int km, size_t shmem, size_t ntiles) {
+int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int wpe, int km, size_t shmem,
+                    size_t ntiles) {
   const int nvmax = pb->nvmax;
   int occ = pb->complex_mode ? tiles_cplx_occupancy(nvmax, mode, ppt, km, shmem)
-                             : tiles_real_occupancy(nvmax, mode, ppt, km, shmem);
+                             : tiles_real_occupancy(nvmax, mode, ppt, wpe, km, shmem);
   if (occ < 1) occ = 1;
   const size_t g = (size_t)occ * std::max(ctx->ncu, 1);
   return (int)std::max<size_t>(1, std::min(g, ntiles));
@@ -387,7 +397,7 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
         W.counter = P.d_counter;
         W.ntiles = nwt;
         W.mode = 1;
-        KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gw, P.shmem_warm, W, st));
+        KCHK(ctx, launch_tiles(pb, S.ppt, S.wpe, S.km, S.gw, P.shmem_warm, W, st));
         KCHK(ctx, launch_hist_reduce(P.d_whist, P.d_whist_off, P.d_wsec_start, P.d_secs, P.d_hsec_off, nsec,
                                      P.hsec_total, P.d_hsec_prefix, P.d_hsec, st));
         KCHK(ctx, launch_refit(P.d_secs, nsec, P.d_hsec, P.d_hsec_off, pb->d_grids, 1.5, st));
@@ -395,9 +405,10 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
     }
   } else if (seg == 1) {
     KCHK(ctx, launch_fill_i32(P.d_counter + 1, 0, 2, st));
-    if (!P.forder.empty()) KCHK(ctx, launch_tiles(pb, S.ppt, S.km, S.gf, P.shmem_final, final_args(pb, P), st));
+    if (!P.forder.empty())
+      KCHK(ctx, launch_tiles(pb, S.ppt, S.wpe, S.km, S.gf, P.shmem_final, final_args(pb, P), st));
     if (!P.xorder.empty())
-      KCHK(ctx, launch_tiles(pb, 1, S.km, S.gx, P.shmem_final, final_args(pb, P, true), st));
+      KCHK(ctx, launch_tiles(pb, 1, 4, S.km, S.gx, P.shmem_final, final_args(pb, P, true), st));
   } else {
     KCHK(ctx, launch_reduce_pairs(P.d_partial, P.d_pair_start, P.d_pair_sector, P.d_secs, npairs, P.d_per_shift,
                                   P.d_nonfinite, P.d_pair_nonfinite, st));
@@ -408,8 +419,9 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
   return SDI_OK;
 }
 
-// Times the final-pass tile kernel for each points-per-thread candidate on the
-// problem's own tiles and keeps the fastest (cached per device, class and problem shape).
+// Times the final-pass tile kernel for each launch variant (points per thread x
+// minimum waves per SIMD) on the problem's own tiles and keeps the fastest
+// (cached per device, class and problem shape); returns the encoded variant.
 int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
   const Params& prm = ctx->params;
   Plan& P = S.P;
@@ -424,23 +436,24 @@ int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
   KCHK(ctx, launch_shifts(P.d_secs, pb->nsec, P.rows, prm.R, prm.seed, 0u, P.d_shifts, st));
   if (prm.warmup > 0 && !pb->grid_valid) KCHK(ctx, launch_grid_identity(P.d_secs, pb->nsec, pb->d_grids, st));
   const TileArgs F = final_args(pb, P);
-  if (F.ntiles == 0) return 1;
-  int best = 1;
+  if (F.ntiles == 0) return default_variant(pb, 1);
+  int best = default_variant(pb, 1);
   float best_ms = 1e30f;
-  for (int ppt : ppt_candidates(pb)) {
-    const int g = persistent_grid(ctx, pb, 0, ppt, S.km, P.shmem_final, P.forder.size());
+  for (int v : tile_variants(pb)) {
+    const int ppt = v / 10, wpe = v % 10;
+    const int g = persistent_grid(ctx, pb, 0, ppt, wpe, S.km, P.shmem_final, P.forder.size());
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       KCHK(ctx, launch_fill_i32(F.counter, 0, 1, st));
       HIPCHK(ctx, hipEventRecord(S.ev[1], st));
-      KCHK(ctx, launch_tiles(pb, ppt, S.km, g, P.shmem_final, F, st));
+      KCHK(ctx, launch_tiles(pb, ppt, wpe, S.km, g, P.shmem_final, F, st));
       HIPCHK(ctx, hipEventRecord(S.ev[2], st));
       HIPCHK(ctx, hipEventSynchronize(S.ev[2]));
       HIPCHK(ctx, hipEventElapsedTime(&ms, S.ev[1], S.ev[2]));
     }
     if (ms < best_ms) {
       best_ms = ms;
-      best = ppt;
+      best = v;
     }
   }
   ctx->tune_cache.push_back({key, best});
@@ -530,19 +543,22 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   }
   HIPCHK(ctx, hipStreamSynchronize(st));
   S->km = pb->kfmax <= 4 ? 4 : 8;
+  int variant;
   if (prm.ppt > 0) {
-    S->ppt = prm.ppt;
+    variant = default_variant(pb, prm.ppt);
   } else if (prm.tune == 0) {
-    S->ppt = (pb->nvmax >= 16 || pb->complex_mode) ? 1 : 2;
+    variant = pb->complex_mode ? 10 : 24;
   } else {
     rc = autotune_ppt(ctx, pb, *S, st);
     if (rc < 0) return rc;
-    S->ppt = rc;
+    variant = rc;
   }
-  S->gf = persistent_grid(ctx, pb, 0, S->ppt, S->km, P.shmem_final, std::max<size_t>(1, P.forder.size()));
+  S->ppt = variant / 10;
+  S->wpe = variant % 10;
+  S->gf = persistent_grid(ctx, pb, 0, S->ppt, S->wpe, S->km, P.shmem_final, std::max<size_t>(1, P.forder.size()));
   // explicit (flow) points are read by the one-point-per-thread instances
-  S->gx = persistent_grid(ctx, pb, 2, 1, S->km, P.shmem_final, std::max<size_t>(1, P.xorder.size()));
-  S->gw = P.warm ? persistent_grid(ctx, pb, 1, S->ppt, S->km, P.shmem_warm, P.wtiles.size()) : 1;
+  S->gx = persistent_grid(ctx, pb, 2, 1, 4, S->km, P.shmem_final, std::max<size_t>(1, P.xorder.size()));
+  S->gw = P.warm ? persistent_grid(ctx, pb, 1, S->ppt, S->wpe, S->km, P.shmem_warm, P.wtiles.size()) : 1;
   if (prm.graph) {
     // Capture each segment once; replays skip the launch overheads.  Timing
     // events stay outside the graphs, between segment launches.  Any failure

@@ -4,23 +4,28 @@
 
 namespace sdi {
 
-int launch_tiles_real_nv4(int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
-int launch_tiles_real_nv8(int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
-int launch_tiles_real_nv16(int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
-int occupancy_tiles_real_nv4(int mode, int ppt, int km, size_t shmem);
-int occupancy_tiles_real_nv8(int mode, int ppt, int km, size_t shmem);
-int occupancy_tiles_real_nv16(int mode, int ppt, int km, size_t shmem);
+int launch_tiles_real_nv4(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv6(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv8(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv16(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int occupancy_tiles_real_nv4(int mode, int ppt, int wpe, int km, size_t shmem);
+int occupancy_tiles_real_nv6(int mode, int ppt, int wpe, int km, size_t shmem);
+int occupancy_tiles_real_nv8(int mode, int ppt, int wpe, int km, size_t shmem);
+int occupancy_tiles_real_nv16(int mode, int ppt, int wpe, int km, size_t shmem);
 
-int launch_tiles_real(int nvmax, int ppt, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st) {
-  if (nvmax <= 4) return launch_tiles_real_nv4(ppt, km, grid, shmem, a, st);
-  if (nvmax <= 8) return launch_tiles_real_nv8(ppt, km, grid, shmem, a, st);
-  return launch_tiles_real_nv16(ppt, km, grid, shmem, a, st);
+int launch_tiles_real(int nvmax, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
+                      hipStream_t st) {
+  if (nvmax <= 4) return launch_tiles_real_nv4(ppt, wpe, km, grid, shmem, a, st);
+  if (nvmax <= 6) return launch_tiles_real_nv6(ppt, wpe, km, grid, shmem, a, st);
+  if (nvmax <= 8) return launch_tiles_real_nv8(ppt, wpe, km, grid, shmem, a, st);
+  return launch_tiles_real_nv16(ppt, wpe, km, grid, shmem, a, st);
 }
 
-int tiles_real_occupancy(int nvmax, int mode, int ppt, int km, size_t shmem) {
-  if (nvmax <= 4) return occupancy_tiles_real_nv4(mode, ppt, km, shmem);
-  if (nvmax <= 8) return occupancy_tiles_real_nv8(mode, ppt, km, shmem);
-  return occupancy_tiles_real_nv16(mode, ppt, km, shmem);
+int tiles_real_occupancy(int nvmax, int mode, int ppt, int wpe, int km, size_t shmem) {
+  if (nvmax <= 4) return occupancy_tiles_real_nv4(mode, ppt, wpe, km, shmem);
+  if (nvmax <= 6) return occupancy_tiles_real_nv6(mode, ppt, wpe, km, shmem);
+  if (nvmax <= 8) return occupancy_tiles_real_nv8(mode, ppt, wpe, km, shmem);
+  return occupancy_tiles_real_nv16(mode, ppt, wpe, km, shmem);
 }
 
 int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st) {

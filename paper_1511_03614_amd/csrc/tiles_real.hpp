@@ -71,8 +71,10 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
   }
 }
 
-template <int NVMAX, int PPT, int KM, int MODE>
-__global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
+// WPE: minimum waves per SIMD the register allocation must allow (the
+// autotuner picks it with PPT; occupancy pays more than a few spills here).
+template <int NVMAX, int PPT, int KM, int MODE, int WPE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_tiles_real(TileArgs A) {
   extern __shared__ double smem[];
   __shared__ int s_tile;
   __shared__ int s_nonfin;
@@ -118,7 +120,10 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_real(TileArgs A) {
         run_tile_real<4, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       case 1:
-        if constexpr (NVC >= 1) run_tile_real<8, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        if constexpr (NVMAX == 6)
+          run_tile_real<6, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        else if constexpr (NVC >= 1)
+          run_tile_real<8, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       case 2:
         if constexpr (NVC >= 2) run_tile_real<16, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
