@@ -120,6 +120,19 @@ def _err(r):
     return np.hypot(r["err_re"], r["err_im"])
 
 
+PEAK_BF16_MFMA_TFLOPS = 2500.0   # MI355X dense bf16 matrix peak
+
+
+def flow_layer_flops(n: int) -> int:
+    """Algorithmic flops of one conditioner forward (the three products) summed over the 4 layers."""
+    tot = 0
+    for l in range(4):
+        nb = 1 if n == 1 else len([j for j in range(n) if j % 2 == l % 2])
+        na = 0 if n == 1 else n - nb
+        tot += 2 * (64 * max(na, 1) + 64 * 64 + 64 * 32 * nb)
+    return tot
+
+
 def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, share=0.9, max_sel=48,
                           iters=20, batch_log2=10, lr=3e-3, m_flow=12, plain_ms=(10, 17)):
     """Error of the learned+batched form against plain batched QMC at equal GPU time.
@@ -163,6 +176,12 @@ def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, sh
         kept, ms_val = P.sdi_flow_validate(ctx, h, m_pilot)
         _set(P, ctx, lattice_log2=m_flow, sampler=1)
         fr = P.sdi_integrate(ctx, h)
+        # matrix-core work of the learned sampler: training does one forward per
+        # layer plus, per layer, a recomputed forward and the two backward
+        # products (dW and dx), i.e. 4x the forward flops; sampling 1x
+        f_train = sum(4 * flow_layer_flops(problem.sectors[s].n) for s in sel) * iters * (1 << batch_log2)
+        n_kept = [s for s in range(ns) if kept[s]]
+        f_sample = sum(flow_layer_flops(problem.sectors[s].n) for s in n_kept) * 16 * (1 << m_flow)
         t_learned = pilot["ms_total"] + ms_train + ms_val + fr["ms_total"]
         ef = _err(fr)
         t = np.array([p[1] for p in plain])
@@ -176,7 +195,13 @@ def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, sh
         return {
             "config": name, "orders": list(range(problem.order_min, problem.order_max + 1)),
             "flow_sectors_trained": nsel, "flow_sectors_kept": int(kept.sum()), "sectors": ns,
-            "train": {"iters": iters, "batch": 1 << batch_log2, "ms": ms_train}, "validate_ms": ms_val,
+            "train": {"iters": iters, "batch": 1 << batch_log2, "ms": ms_train,
+                      "mfma_bf16_tflops": f_train / (ms_train * 1e-3) / 1e12,
+                      "mfma_frac": f_train / (ms_train * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS},
+            "flow_sampling": {"ms": fr["ms_warmup"], "points": len(n_kept) * 16 << m_flow,
+                              "mfma_bf16_tflops": (f_sample / (fr["ms_warmup"] * 1e-3) / 1e12
+                                                   if fr["ms_warmup"] > 0 else None)},
+            "validate_ms": ms_val,
             "pilot_ms": pilot["ms_total"],
             "learned": {"ms_total": t_learned, "lattice_log2": m_flow, "err": ef.tolist(),
                         "value_re": fr["value"].real.tolist(), "value_im": fr["value"].imag.tolist()},

@@ -14,7 +14,7 @@ int launch_tiles_cplx(int nvmax, int ppt, int km, int grid, size_t shmem, const 
     k_tiles_cplx<NV, P, K, M><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a, X);            \
     return (int)hipGetLastError();                                                     \
   }
-  SDI_L(0, 4, 1, 4) SDI_L(0, 4, 2, 4) SDI_L(0, 4, 1, 8) SDI_L(0, 4, 2, 8) SDI_L(0, 8, 1, 4) SDI_L(0, 8, 1, 8) SDI_L(1, 4, 1, 4) SDI_L(1, 4, 2, 4) SDI_L(1, 4, 1, 8) SDI_L(1, 4, 2, 8) SDI_L(1, 8, 1, 4) SDI_L(1, 8, 1, 8) SDI_L(2, 4, 1, 4) SDI_L(2, 4, 1, 8) SDI_L(2, 8, 1, 4) SDI_L(2, 8, 1, 8)
+  SDI_L(0, 4, 1, 4) SDI_L(0, 4, 2, 4) SDI_L(0, 4, 1, 8) SDI_L(0, 4, 2, 8) SDI_L(0, 6, 1, 4) SDI_L(0, 6, 1, 8) SDI_L(0, 8, 1, 4) SDI_L(0, 8, 1, 8) SDI_L(1, 4, 1, 4) SDI_L(1, 4, 2, 4) SDI_L(1, 4, 1, 8) SDI_L(1, 4, 2, 8) SDI_L(1, 6, 1, 4) SDI_L(1, 6, 1, 8) SDI_L(1, 8, 1, 4) SDI_L(1, 8, 1, 8) SDI_L(2, 4, 1, 4) SDI_L(2, 4, 1, 8) SDI_L(2, 6, 1, 4) SDI_L(2, 6, 1, 8) SDI_L(2, 8, 1, 4) SDI_L(2, 8, 1, 8)
 #undef SDI_L
   return (int)hipErrorInvalidValue;
 }
@@ -28,7 +28,7 @@ int tiles_cplx_occupancy(int nvmax, int mode, int ppt, int km, size_t shmem) {
       return 0;                                                                                                \
     return nb;                                                                                                 \
   }
-  SDI_O(0, 4, 1, 4) SDI_O(0, 4, 2, 4) SDI_O(0, 4, 1, 8) SDI_O(0, 4, 2, 8) SDI_O(0, 8, 1, 4) SDI_O(0, 8, 1, 8) SDI_O(1, 4, 1, 4) SDI_O(1, 4, 2, 4) SDI_O(1, 4, 1, 8) SDI_O(1, 4, 2, 8) SDI_O(1, 8, 1, 4) SDI_O(1, 8, 1, 8) SDI_O(2, 4, 1, 4) SDI_O(2, 4, 1, 8) SDI_O(2, 8, 1, 4) SDI_O(2, 8, 1, 8)
+  SDI_O(0, 4, 1, 4) SDI_O(0, 4, 2, 4) SDI_O(0, 4, 1, 8) SDI_O(0, 4, 2, 8) SDI_O(0, 6, 1, 4) SDI_O(0, 6, 1, 8) SDI_O(0, 8, 1, 4) SDI_O(0, 8, 1, 8) SDI_O(1, 4, 1, 4) SDI_O(1, 4, 2, 4) SDI_O(1, 4, 1, 8) SDI_O(1, 4, 2, 8) SDI_O(1, 6, 1, 4) SDI_O(1, 6, 1, 8) SDI_O(1, 8, 1, 4) SDI_O(1, 8, 1, 8) SDI_O(2, 4, 1, 4) SDI_O(2, 4, 1, 8) SDI_O(2, 6, 1, 4) SDI_O(2, 6, 1, 8) SDI_O(2, 8, 1, 4) SDI_O(2, 8, 1, 8)
 #undef SDI_O
   return 0;
 }
@@ -63,6 +63,8 @@ int launch_lambda_test(int nvmax, const SecDev* secs, int nsec, const void* cx, 
   const CplxDev* c = (const CplxDev*)cx;
   if (nvmax <= 4)
     k_lambda_test<4><<<grid, dim3(BLOCK), 0, st>>>(secs, c, dir, terms, zp, shifts, npts, cand, ncand, fail);
+  else if (nvmax <= 6)
+    k_lambda_test<6><<<grid, dim3(BLOCK), 0, st>>>(secs, c, dir, terms, zp, shifts, npts, cand, ncand, fail);
   else
     k_lambda_test<8><<<grid, dim3(BLOCK), 0, st>>>(secs, c, dir, terms, zp, shifts, npts, cand, ncand, fail);
   return (int)hipGetLastError();

@@ -131,7 +131,10 @@ __global__ void __launch_bounds__(BLOCK) k_tiles_cplx(TileArgs A, CplxArgs X) {
         run_tile_cplx<4, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
         break;
       case 1:
-        if constexpr (NVC >= 1) run_tile_cplx<8, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+        if constexpr (NVMAX == 6)
+          run_tile_cplx<6, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+        else if constexpr (NVC >= 1)
+          run_tile_cplx<8, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
         break;
       default:
         break;
