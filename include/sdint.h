@@ -105,8 +105,8 @@ typedef struct {
   double coeff_re, coeff_im;  /* c_s                                                */
   const double* mono_a;       /* [n] a_j                                            */
   const double* mono_b;       /* [n] b_j                                            */
-  const int32_t* deform_mono; /* [n] exponents of the monomial factored out of F, so
-                                 that the sector's full F is x^deform_mono P_F; NULL = 0 */
+  const int32_t* deform_mono; /* [n] exponents of a monomial m: the deformation follows
+                                 the gradient of x^m P_F; NULL = 0 (P_F itself)     */
   const int32_t* fac_nterms;  /* [M] terms per factor                               */
   const double* fac_gamma;    /* [M] gamma_m                                        */
   const double* fac_delta;    /* [M] delta_m                                        */

@@ -53,9 +53,9 @@ class Sector:
     """One sector: monomial exponents a_j + b_j eps, factors, coefficient c_s.
 
     ``deform_factor`` names the factor that is the sector's F polynomial (used
-    by the contour deformation in complex mode) and ``deform_mono`` the integer
-    exponents of the monomial that decomposition factored out of F, so that the
-    sector's full F is x^deform_mono * P_F(x).
+    by the contour deformation in complex mode).  The deformation follows the
+    gradient of x^deform_mono * P_F(x); None (zeros) deforms along P_F itself,
+    the polynomial with a constant term that carries the F - i0 branch.
     """
     a: np.ndarray                    # (n,) float64, -1 exactly or > -1
     b: np.ndarray                    # (n,) float64

@@ -129,8 +129,16 @@ def decompose(polys: List[Poly], expo: List[Tuple[float, float]], mono_a: List[F
 
 
 def feynman_sectors(U: Poly, F: Poly, indices: Sequence[int], loops: int, d0: int = 4,
-                    masses_present: bool = False) -> List[Sector]:
-    """Primary sectors x_k = 1 of eq. (2), then iterated decomposition of U and F."""
+                    masses_present: bool = False, deform_full_f: bool = False) -> List[Sector]:
+    """Primary sectors x_k = 1 of eq. (2), then iterated decomposition of U and F.
+
+    In complex mode the deformation follows the gradient of the sector's
+    reduced F (the factor left after the monomial is taken out, which has a
+    constant term).  With ``deform_full_f`` it follows the full F = x^mono P_F
+    instead: then the deformation shrinks with the monomial near the faces where
+    it vanishes while P_F can still cross zero there, so Im P_F(z) only grows
+    linearly away from such a face and the integrand's variance diverges.
+    """
     n = len(indices)
     A = sum(indices)
     gU = Fraction(A) - Fraction((loops + 1) * d0, 2)
@@ -171,7 +179,8 @@ def feynman_sectors(U: Poly, F: Poly, indices: Sequence[int], loops: int, d0: in
             if any(float(v) < -1 for v in a):
                 raise NotImplementedError("sector exponent below -1 needs higher-order subtraction")
             secs.append(Sector(a=np.array([float(v) for v in a]), b=np.array([float(v) for v in b]),
-                               factors=facs, coeff=1.0, deform_factor=1, deform_mono=mono_F))
+                               factors=facs, coeff=1.0, deform_factor=1,
+                               deform_mono=mono_F if deform_full_f else np.zeros(n - 1, dtype=np.int32)))
     return secs
 
 
