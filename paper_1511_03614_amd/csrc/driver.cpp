@@ -379,7 +379,7 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
       A.x = P.d_px;
       A.w = P.d_pw;
       A.lq = nullptr;
-      KCHK(ctx, launch_flow_sample_tiles(A, st));
+      KCHK(ctx, launch_flow_sample_tiles(A, pb->nvmax, st));
     }
     if (P.warm) {
       KCHK(ctx, launch_grid_identity(P.d_secs, nsec, pb->d_grids, st));

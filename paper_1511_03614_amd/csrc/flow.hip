@@ -36,16 +36,27 @@ int launch_flow_adam(float* params, const float* grad, float* m, float* v, const
   return (int)hipGetLastError();
 }
 
-int launch_flow_sample(const FlowSampleArgs& a, hipStream_t st) {
+int launch_flow_sample(const FlowSampleArgs& a, int nvmax, hipStream_t st) {
   if (a.npts <= 0) return 0;
-  const int64_t groups = (a.npts + 15) / 16;
-  k_flow_sample<<<dim3(clamp_grid((groups + 3) / 4, 8192)), dim3(256), 0, st>>>(a);
+  const dim3 grid(clamp_grid((a.npts + 63) / 64, 1 << 16)), block(64);
+  if (nvmax <= 4)
+    k_flow_sample<4><<<grid, block, 0, st>>>(a);
+  else if (nvmax <= 8)
+    k_flow_sample<8><<<grid, block, 0, st>>>(a);
+  else
+    k_flow_sample<16><<<grid, block, 0, st>>>(a);
   return (int)hipGetLastError();
 }
 
-int launch_flow_sample_tiles(const FlowTileArgs& a, hipStream_t st) {
+int launch_flow_sample_tiles(const FlowTileArgs& a, int nvmax, hipStream_t st) {
   if (a.nchunks <= 0) return 0;
-  k_flow_sample_tiles<<<dim3(clamp_grid(a.nchunks, 1 << 20)), dim3(256), 0, st>>>(a);
+  const dim3 grid(clamp_grid(a.nchunks, 1 << 22)), block(64);
+  if (nvmax <= 4)
+    k_flow_sample_tiles<4><<<grid, block, 0, st>>>(a);
+  else if (nvmax <= 8)
+    k_flow_sample_tiles<8><<<grid, block, 0, st>>>(a);
+  else
+    k_flow_sample_tiles<16><<<grid, block, 0, st>>>(a);
   return (int)hipGetLastError();
 }
 

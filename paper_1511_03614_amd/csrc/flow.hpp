@@ -146,64 +146,6 @@ __device__ __forceinline__ void softmax_bins(const f32x4_t lo, const f32x4_t hi,
   for (int i = 0; i < 8; ++i) q[i] = (double)e[i] * inv;
 }
 
-// Inverse coupling of one variable with the bins spread over the sample's 4
-// lanes (lane group g holds bins 4g..4g+3 and 16+4g..16+4g+3): block sums and
-// an exclusive prefix over the groups give each lane the running sums at its
-// bins; the selected bin b is the last one whose running sum is <= y, found as
-// the largest local candidate.  Every lane of the sample returns x and
-// log(NB q_b).
-__device__ __forceinline__ double invert_bins_lanes(const double (&q)[8], double y, double& lterm) {
-  const int lane = threadIdx.x & 63;
-  const int s = lane & 15, g = lane >> 4;
-  const double lo = (q[0] + q[1]) + (q[2] + q[3]);
-  const double hi = (q[4] + q[5]) + (q[6] + q[7]);
-  double L[4], H[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    L[k] = __shfl(lo, s + 16 * k, 64);
-    H[k] = __shfl(hi, s + 16 * k, 64);
-  }
-  double clo = 0.0, chi = ((L[0] + L[1]) + L[2]) + L[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    if (k < g) {
-      clo += L[k];
-      chi += H[k];
-    }
-  int cand = -1;
-  double cb = 0.0, qb = 1.0;
-  double c = clo;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (c <= y) {
-      cand = 4 * g + i;
-      cb = c;
-      qb = q[i];
-    }
-    c += q[i];
-  }
-  c = chi;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (c <= y) {
-      cand = 16 + 4 * g + i;
-      cb = c;
-      qb = q[4 + i];
-    }
-    c += q[4 + i];
-  }
-  int b = cand;
-  b = max(b, __shfl_xor(b, 16, 64));
-  b = max(b, __shfl_xor(b, 32, 64));
-  const int owner = s + 16 * ((b & 15) >> 2);
-  cb = __shfl(cb, owner, 64);
-  qb = __shfl(qb, owner, 64);
-  double frac = (y - cb) / qb;
-  frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
-  lterm = log((double)FL_NB * qb);
-  return ((double)b + frac) / (double)FL_NB;
-}
-
 // Stores this lane's 8 probabilities into the sample's row of 32 (LDS).
 __device__ __forceinline__ void store_bins(double* qrow, const double (&q)[8]) {
   const int g = (threadIdx.x & 63) >> 4;
@@ -239,99 +181,283 @@ __device__ __forceinline__ bf16x4_t layer_input(const FlowLayerDesc& D, const do
   return pack_bf4(in[0], in[1], in[2], in[3]);
 }
 
-// Latent points -> data points for 16 samples per wave (all 64 lanes of the
-// wave call it together).  hs: LDS [16][16] doubles, this wave's sample
-// states.  On return hs holds x, and lq (per lane, of sample l%16) the log
-// density.
-__device__ __forceinline__ void flow_inverse16(const FlowSecDesc* __restrict__ F, const float* __restrict__ P,
-                                               const uint16_t* __restrict__ bw, double* hs, double& lq) {
+// ---------------------------------------------------------------- sampling
+//
+// The sampler runs one 64-sample chunk per wave with lane = sample: the
+// sample's state h (fp64) stays in registers, the conditioner's products take
+// the 64 samples as four 16-column tiles (so each weight operand is loaded
+// once per 64 samples), the hidden products use the K = 32 matrix-core
+// instruction, and the 32 logits of a transformed variable are moved through
+// LDS so that each lane finishes its own sample's softmax, bin search and
+// Jacobian without cross-lane traffic.
+
+typedef __bf16 bfv4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bfv8_t __attribute__((ext_vector_type(8)));
+
+constexpr int FL_LGS = 36;   // floats per sample row of the wave's logit buffer (32 used)
+constexpr int FL_A0S = 12;   // bf16 per sample row of the staged conditioner inputs (8 used)
+
+__device__ __forceinline__ f32x4_t mfma32(bfv8_t a, bfv8_t b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4_t mfma16b(bfv4_t a, bfv4_t b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4_t, a), __builtin_bit_cast(bf16x4_t, b),
+                                                   c, 0, 0, 0);
+}
+__device__ __forceinline__ bfv4_t ld_bfv4(const uint16_t* p) { return *reinterpret_cast<const bfv4_t*>(p); }
+__device__ __forceinline__ bfv8_t cat8(bfv4_t a, bfv4_t b) {
+  return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+__device__ __forceinline__ bfv4_t relu_bf4(f32x4_t v, float4 b) {
+  bfv4_t o;
+  o[0] = (__bf16)fmaxf(v[0] + b.x, 0.f);
+  o[1] = (__bf16)fmaxf(v[1] + b.y, 0.f);
+  o[2] = (__bf16)fmaxf(v[2] + b.z, 0.f);
+  o[3] = (__bf16)fmaxf(v[3] + b.w, 0.f);
+  return o;
+}
+__device__ __forceinline__ float4 ld_f4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+// e^x for x <= 0: 2^t with t = x log2(e), the product split Cody-Waite style
+// into its fp32 rounding t and the remainder (x log2(e) - t), which enters as
+// the first-order factor 1 + remainder * ln 2.  About one ulp, like expf, in a
+// third of the instructions; results below 2^-126 may flush to zero, which
+// only drops bins of negligible probability.
+__device__ __forceinline__ float exp_nonpos(float x) {
+  const float l2e_hi = 1.44269502e+00f;   // log2(e) rounded to fp32
+  const float l2e_lo = 1.92596299e-08f;   // log2(e) - l2e_hi
+  const float t = x * l2e_hi;
+  const float rem = fmaf(x, l2e_hi, -t) + x * l2e_lo;
+  return __builtin_amdgcn_exp2f(t) * fmaf(rem, 0.693147182f, 1.0f);
+}
+
+// Weight operand of the K = 32 products for output rows ob*16.. and inputs
+// 32c..32c+31 of a [rows][64] bf16 matrix.  Within a K = 32 step the lane of
+// group g supplies inputs 32c + 4g + (0..3) and 32c + 16 + 4g + (0..3): the
+// same order in which the previous layer's accumulators (rows 4g..4g+3 of two
+// 16-row blocks) feed the activation operand, so no data moves between layers.
+__device__ __forceinline__ bfv8_t w_k32(const uint16_t* W, int ob, int c) {
   const int lane = threadIdx.x & 63;
-  const int s = lane & 15, g = lane >> 4;
+  const int r = lane & 15, g = lane >> 4;
+  const uint16_t* row = W + (ob * 16 + r) * FL_H + 32 * c + 4 * g;
+  return cat8(ld_bfv4(row), ld_bfv4(row + 16));
+}
+
+// LDS of one sampling wave: the logit buffer (also the staging area of the
+// conditioner inputs) and the 64 sample states, one padded row per lane so
+// that lanes indexing the same variable hit distinct banks.
+template <int NV>
+struct FlowWaveLds {
+  float lg[64 * FL_LGS];
+  double h[64 * (NV + 1)];
+};
+
+// Inverse of all coupling layers for the wave's 64 samples (all lanes call it
+// together).  h: this lane's sample row in LDS, latent on entry, data point on
+// return; lq: log q of the sample.  lds: the wave's logit buffer.
+template <int NV>
+__device__ __forceinline__ void flow_inverse_wave(const SDI_TAPE FlowSecDesc* F, const float* __restrict__ P,
+                                                  const uint16_t* __restrict__ bw, double* h, float* lds,
+                                                  double& lq) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  __bf16* a0s = reinterpret_cast<__bf16*>(lds);
+  const int n = F->n;
   lq = 0.0;
   for (int l = FL_L - 1; l >= 0; --l) {
-    const FlowLayerDesc& D = F->layer[l];
-    MlpHidden hid;
-    mlp_hidden(bw, P, D, layer_input(D, hs + s * 16), hid);
-    for (int jj = 0; jj < D.nB; ++jj) {
-      f32x4_t lo, hi;
-      mlp_logits(bw, P, D, hid, jj, lo, hi);
-      double q[8];
-      softmax_bins(lo, hi, q);
-      const int j = D.B[jj];
-      double lt;
-      const double xn = invert_bins_lanes(q, hs[s * 16 + j], lt);
-      lq += lt;
+    const SDI_TAPE FlowLayerDesc* D = &F->layer[l];
+    const int nA = D->nA, nB = D->nB;
+    // conditioner inputs bf16(2 h_A - 1), staged so that every lane can read
+    // the 4-row slices of the four sample tiles.  The coupling masks are the
+    // parity masks, so input k is variable 2k + 1 - (l mod 2).
+    {
+      const bool odd = (l & 1) != 0;
+      bfv4_t v0, v1;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        float a = 0.f;
+        if (2 * k + 1 < NV && k < nA) a = (float)(2.0 * h[2 * k + (odd ? 0 : 1)] - 1.0);
+        if (k < 4) v0[k] = (__bf16)a; else v1[k - 4] = (__bf16)a;
+      }
+      *reinterpret_cast<bfv4_t*>(a0s + lane * FL_A0S) = v0;
+      *reinterpret_cast<bfv4_t*>(a0s + lane * FL_A0S + 4) = v1;
+    }
+    wave_sync();
+    bfv4_t b0[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      if (g < 2) {
+        b0[nt] = *reinterpret_cast<const bfv4_t*>(a0s + (16 * nt + r) * FL_A0S + 4 * g);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b0[nt][k] = (__bf16)0.f;
+      }
+    }
+    wave_sync();
+    // hidden layers
+    bfv4_t a1[4][4], a2[4][4];   // [sample tile][row block]
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+      const bfv4_t w = ld_bfv4(bw + D->c1 + (ob * 16 + r) * FL_K1 + 4 * g);
+      const float4 b = ld_f4(P + D->b1 + ob * 16 + 4 * g);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) a1[nt][ob] = relu_bf4(mfma16b(w, b0[nt], f32x4_t{0.f, 0.f, 0.f, 0.f}), b);
+    }
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+      f32x4_t acc[4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const bfv8_t w = w_k32(bw + D->c2, ob, c);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma32(w, cat8(a1[nt][2 * c], a1[nt][2 * c + 1]), acc[nt]);
+      }
+      const float4 b = ld_f4(P + D->b2 + ob * 16 + 4 * g);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) a2[nt][ob] = relu_bf4(acc[nt], b);
+    }
+    for (int jj = 0; jj < nB; ++jj) {
+      // logits of variable jj -> LDS [sample][bin]
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int ob = 2 * jj + half;
+        f32x4_t acc[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const bfv8_t w = w_k32(bw + D->c3, ob, c);
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma32(w, cat8(a2[nt][2 * c], a2[nt][2 * c + 1]), acc[nt]);
+        }
+        const float4 b = ld_f4(P + D->b3 + ob * 16 + 4 * g);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+          *reinterpret_cast<float4*>(lds + (16 * nt + r) * FL_LGS + half * 16 + 4 * g) =
+              make_float4(acc[nt][0] + b.x, acc[nt][1] + b.y, acc[nt][2] + b.z, acc[nt][3] + b.w);
+      }
       wave_sync();
-      if (g == 0) hs[s * 16 + j] = xn;
+      float e[FL_NB];
+#pragma unroll
+      for (int k = 0; k < FL_NB; k += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(lds + lane * FL_LGS + k);
+        e[k] = v.x;
+        e[k + 1] = v.y;
+        e[k + 2] = v.z;
+        e[k + 3] = v.w;
+      }
       wave_sync();
+      // softmax: fp32 exponentials, fp64 sums
+      float mx = e[0];
+#pragma unroll
+      for (int k = 1; k < FL_NB; ++k) mx = fmaxf(mx, e[k]);
+      double gs[FL_NB / 4];
+#pragma unroll
+      for (int m = 0; m < FL_NB / 4; ++m) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[4 * m + i] = exp_nonpos(e[4 * m + i] - mx);
+        gs[m] = (((double)e[4 * m] + (double)e[4 * m + 1]) + (double)e[4 * m + 2]) + (double)e[4 * m + 3];
+      }
+      const double sd = ((gs[0] + gs[1]) + (gs[2] + gs[3])) + ((gs[4] + gs[5]) + (gs[6] + gs[7]));
+      const double inv = 1.0 / sd;
+      // bin search: the last bin whose running sum is <= y, first over groups of 4 bins
+      const int j = n == 1 ? 0 : 2 * jj + (l & 1);
+      const double y = h[j];
+      double c = 0.0, cg = 0.0;
+      int gsel = 0;
+#pragma unroll
+      for (int m = 0; m < FL_NB / 4; ++m) {
+        if (c * inv <= y) {
+          gsel = m;
+          cg = c;
+        }
+        c += gs[m];
+      }
+      float eg[4] = {e[0], e[1], e[2], e[3]};
+#pragma unroll
+      for (int m = 1; m < FL_NB / 4; ++m)
+        if (gsel == m) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) eg[i] = e[4 * m + i];
+        }
+      int b = 4 * gsel;
+      double cb = cg, eb = (double)eg[0];
+      c = cg;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (c * inv <= y) {
+          b = 4 * gsel + i;
+          cb = c;
+          eb = (double)eg[i];
+        }
+        c += (double)eg[i];
+      }
+      const double qb = eb * inv;
+      double frac = (y - cb * inv) / qb;
+      frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
+      h[j] = ((double)b + frac) / (double)FL_NB;
+      lq += log((double)FL_NB * qb);
     }
   }
 }
 
-// ---------------------------------------------------------------- sampling
-
-
-// Latent u -> x, log q for one sector (explicit latent points).
-__global__ void __launch_bounds__(256) k_flow_sample(FlowSampleArgs A) {
-  __shared__ double hs_all[4][16 * 16];
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int s = lane & 15, g = lane >> 4;
-  double* hs = hs_all[wave];
-  const FlowSecDesc* F = A.fs + A.sector;
+// Latent u -> x, log q for one sector (explicit latent points); one wave per
+// block and per 64-sample chunk.
+template <int NV>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_flow_sample(FlowSampleArgs A) {
+  __shared__ __attribute__((aligned(16))) FlowWaveLds<NV> L;
+  const int lane = threadIdx.x;
+  double* h = L.h + lane * (NV + 1);
+  const SDI_TAPE FlowSecDesc* F = tape(A.fs) + A.sector;
   const int n = F->n;
   const float* P = A.params + F->base;
-  const int64_t groups = (A.npts + 15) / 16;
-  for (int64_t grp = (int64_t)blockIdx.x * 4 + wave; grp < groups; grp += (int64_t)gridDim.x * 4) {
-    const int64_t i = grp * 16 + s;
+  const int64_t chunks = (A.npts + 63) / 64;
+  for (int64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
+    const int64_t i = ch * 64 + lane;
     const bool valid = i < A.npts;
-    if (g == 0)
-      for (int j = 0; j < 16; ++j) hs[s * 16 + j] = (valid && j < n) ? A.u[i * n + j] : 0.5;
-    wave_sync();
+    for (int j = 0; j < n; ++j) h[j] = valid ? A.u[i * n + j] : 0.5;
     double lq;
-    flow_inverse16(F, P, A.bw, hs, lq);
-    if (valid && g == 0) {
-      for (int j = 0; j < n; ++j) A.x[i * n + j] = hs[s * 16 + j];
+    flow_inverse_wave<NV>(F, P, A.bw, h, L.lg, lq);
+    if (valid) {
+      for (int j = 0; j < n; ++j) A.x[i * n + j] = h[j];
       A.lq[i] = lq;
     }
     wave_sync();
   }
 }
 
-
 // Shifted-lattice latent points (tent-transformed when baker is set) pushed
-// through the flow: the sampler of a pass or of a training batch.
-__global__ void __launch_bounds__(256) k_flow_sample_tiles(FlowTileArgs A) {
-  __shared__ double hs_all[4][16 * 16];
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int s = lane & 15, g = lane >> 4;
-  double* hs = hs_all[wave];
+// through the flow: the sampler of a pass or of a training batch.  One wave
+// per block and per 64-point chunk; a chunk never spans two tiles.
+template <int NV>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_flow_sample_tiles(FlowTileArgs A) {
+  __shared__ __attribute__((aligned(16))) FlowWaveLds<NV> L;
+  const int lane = threadIdx.x;
+  double* h = L.h + lane * (NV + 1);
   for (int64_t c = blockIdx.x; c < A.nchunks; c += gridDim.x) {
     const int t = find_run(A.chunk_prefix, A.ntiles, c);
     const FlowTile T = A.tiles[t];
-    const FlowSecDesc* F = A.fs + T.sector;
+    const SDI_TAPE FlowSecDesc* F = tape(A.fs) + T.sector;
     const int n = F->n;
-    const int64_t local = (c - A.chunk_prefix[t]) * FL_CHUNK + wave * 16 + s;
+    const int64_t local = (c - A.chunk_prefix[t]) * FL_CHUNK + lane;
     const bool valid = local < (int64_t)T.count;
-    if (g == 0) {
-      const uint64_t* zp = A.zp + (size_t)T.sector * MAXV;
-      const uint64_t* sh = A.shifts + (size_t)T.row * MAXV;
-      for (int j = 0; j < 16; ++j) {
-        double u = 0.5;
-        if (valid && j < n) {
-          u = lattice_coord((uint64_t)T.i0 + (uint64_t)local, zp[j], sh[j]);
-          if (A.baker) u = tent(u);
-        }
-        hs[s * 16 + j] = u;
+    CU64* zp = tape(A.zp) + (size_t)T.sector * MAXV;
+    CU64* sh = tape(A.shifts) + (size_t)T.row * MAXV;
+    for (int j = 0; j < n; ++j) {
+      double u = 0.5;
+      if (valid) {
+        u = lattice_coord((uint64_t)T.i0 + (uint64_t)local, zp[j], sh[j]);
+        if (A.baker) u = tent(u);
       }
+      h[j] = u;
     }
-    wave_sync();
     double lq;
-    flow_inverse16(F, A.params + F->base, A.bw, hs, lq);
-    if (valid && g == 0) {
+    flow_inverse_wave<NV>(F, A.params + F->base, A.bw, h, L.lg, lq);
+    if (valid) {
       double* xo = A.x + T.x_off + local * n;
-      for (int j = 0; j < n; ++j) xo[j] = hs[s * 16 + j];
+      for (int j = 0; j < n; ++j) xo[j] = h[j];
       A.w[T.pt_off + local] = exp(-lq);
       if (A.lq) A.lq[T.pt_off + local] = lq;
     }

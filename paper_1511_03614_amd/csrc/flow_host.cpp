@@ -233,7 +233,7 @@ int sdi_flow_sample(sdi_ctx* ctx, sdi_problem* pb, int32_t s, const void* u_dev,
   (void)hipGetLastError();
   FlowState& F = *pb->flow;
   FlowSampleArgs A{F.d_desc, F.d_params, F.d_bw, (const double*)u_dev, (double*)x_dev, (double*)lq_dev, s, npts};
-  KCHK(ctx, launch_flow_sample(A, ctx->stream));
+  KCHK(ctx, launch_flow_sample(A, pb->nvmax, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   return SDI_OK;
 }
@@ -435,7 +435,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
       S.x = x;
       S.w = w;
       S.lq = lq;
-      KCHK(ctx, launch_flow_sample_tiles(S, st));
+      KCHK(ctx, launch_flow_sample_tiles(S, pb->nvmax, st));
       EvalTilesArgs E{};
       E.secs = pb->d_secs;
       E.terms = pb->d_terms;

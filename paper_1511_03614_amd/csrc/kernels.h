@@ -62,8 +62,8 @@ int launch_flow_copies(const FlowSecDesc* fs, const FlowTile* runs, int nruns, i
 int launch_flow_adam(float* params, const float* grad, float* m, float* v, const FlowSecDesc* fs,
                      const FlowTile* runs, int nruns, int64_t max_nparam, double lr, const double* bc,
                      hipStream_t st);
-int launch_flow_sample(const FlowSampleArgs& a, hipStream_t st);
-int launch_flow_sample_tiles(const FlowTileArgs& a, hipStream_t st);
+int launch_flow_sample(const FlowSampleArgs& a, int nvmax, hipStream_t st);
+int launch_flow_sample_tiles(const FlowTileArgs& a, int nvmax, hipStream_t st);
 int launch_flow_fwd_store(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st);
 int launch_flow_bwd_layer(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st);
 int launch_flow_grad_reduce(const FlowSecDesc* fs, const FlowTile* tiles, int ntiles, int layer, const float* part,
