@@ -60,23 +60,23 @@ int launch_flow_sample_tiles(const FlowTileArgs& a, int nvmax, hipStream_t st) {
   return (int)hipGetLastError();
 }
 
-int launch_flow_fwd_store(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st) {
-  if (a.ntiles <= 0) return 0;
-  k_flow_fwd_store<<<dim3(blocks_per_tile, a.ntiles), dim3(256), 0, st>>>(a);
+int launch_flow_grad(const FlowGradArgs& a, int nvmax, hipStream_t st) {
+  if (a.nchunks <= 0) return 0;
+  const dim3 grid(clamp_grid(a.nchunks, 1 << 22)), block(64);
+  if (nvmax <= 4)
+    k_flow_grad<4><<<grid, block, 0, st>>>(a);
+  else if (nvmax <= 8)
+    k_flow_grad<8><<<grid, block, 0, st>>>(a);
+  else
+    k_flow_grad<16><<<grid, block, 0, st>>>(a);
   return (int)hipGetLastError();
 }
 
-int launch_flow_bwd_layer(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st) {
-  if (a.ntiles <= 0) return 0;
-  k_flow_bwd_layer<<<dim3(blocks_per_tile, a.ntiles), dim3(256), 0, st>>>(a);
-  return (int)hipGetLastError();
-}
-
-int launch_flow_grad_reduce(const FlowSecDesc* fs, const FlowTile* tiles, int ntiles, int layer, const float* part,
-                            int64_t part_stride, int nblk, int64_t max_lsize, float* grad, hipStream_t st) {
-  if (ntiles <= 0) return 0;
-  k_flow_grad_reduce<<<dim3((unsigned)((max_lsize + 255) / 256), ntiles), dim3(256), 0, st>>>(
-      fs, tiles, layer, part, part_stride, nblk, grad);
+int launch_flow_chunk_reduce(const FlowSecDesc* fs, const FlowTile* runs, const int64_t* chunk_prefix, int nruns,
+                             const float* part, int64_t stride, int64_t max_nparam, float* grad, hipStream_t st) {
+  if (nruns <= 0) return 0;
+  k_flow_chunk_reduce<<<dim3((unsigned)((max_nparam + 255) / 256), nruns), dim3(256), 0, st>>>(
+      fs, runs, chunk_prefix, part, stride, grad);
   return (int)hipGetLastError();
 }
 

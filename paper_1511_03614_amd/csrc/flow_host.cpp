@@ -95,46 +95,34 @@ int flow_scratch(sdi_ctx* ctx, FlowState& F, size_t bytes) {
   return SDI_OK;
 }
 
-// Blocks of the backward kernels per run: about 512 blocks in total (one per
-// CU is what their register use allows, twice over), at least 4 chunks per
-// block when there are chunks to spare, at most one block per chunk.
-int blocks_per_run(int64_t count, int nruns) {
-  const int64_t chunks = (count + FL_CHUNK - 1) / FL_CHUNK;
-  const int64_t want = (512 + nruns - 1) / std::max(nruns, 1);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, std::max<int64_t>(want, (chunks + 3) / 4)));
-}
-
 }  // namespace
 
-// Gradient of -sum_i c_i log q(x_i) for every run (one run per sector) into F.d_grad.
-int flow_gradient(sdi_ctx* ctx, sdi_problem* pb, const PointRun* d_runs, int nruns, int64_t max_count,
-                  const double* x, const double* c, double* hsave, double* dl, float* part, hipStream_t st) {
+// Gradient of -sum_i c_i log q(x_i) for every run (one run per sector) into
+// F.d_grad: per-chunk gradients, then their fixed-order sum per run.
+int flow_gradient(sdi_ctx* ctx, sdi_problem* pb, const PointRun* d_runs, const int64_t* d_chunk_prefix, int nruns,
+                  int64_t nchunks, const double* x, const double* c, double* hsave, float* part, hipStream_t st) {
   FlowState& F = *pb->flow;
-  FlowBatchArgs A{};
+  FlowGradArgs A{};
   A.fs = F.d_desc;
   A.params = F.d_params;
   A.bw = F.d_bw;
-  A.tiles = d_runs;
-  A.ntiles = nruns;
+  A.runs = d_runs;
+  A.chunk_prefix = d_chunk_prefix;
+  A.nruns = nruns;
+  A.nchunks = nchunks;
   A.x = x;
   A.c = c;
   A.hsave = hsave;
-  A.dl = dl;
   A.part = part;
-  A.part_stride = F.max_lsize;
-  const int bpt = blocks_per_run(max_count, nruns);
-  const int bfw = (int)std::max<int64_t>(1, std::min<int64_t>(256, (max_count + 63) / 64));
-  KCHK(ctx, launch_flow_fwd_store(A, bfw, st));
-  for (int l = FL_L - 1; l >= 0; --l) {
-    A.layer = l;
-    KCHK(ctx, launch_flow_bwd_layer(A, bpt, st));
-    KCHK(ctx, launch_flow_grad_reduce(F.d_desc, d_runs, nruns, l, part, F.max_lsize, bpt, F.max_lsize, F.d_grad, st));
-  }
+  A.part_stride = F.max_nparam;
+  KCHK(ctx, launch_flow_grad(A, pb->nvmax, st));
+  KCHK(ctx, launch_flow_chunk_reduce(F.d_desc, d_runs, d_chunk_prefix, nruns, part, F.max_nparam, F.max_nparam,
+                                     F.d_grad, st));
   return SDI_OK;
 }
 
-size_t flow_grad_part_bytes(const FlowState& F, int nruns, int64_t max_count) {
-  return (size_t)nruns * blocks_per_run(max_count, nruns) * F.max_lsize * sizeof(float);
+size_t flow_grad_part_bytes(const FlowState& F, int64_t nchunks) {
+  return (size_t)nchunks * F.max_nparam * sizeof(float);
 }
 
 }  // namespace sdi
@@ -250,21 +238,26 @@ int sdi_flow_grad(sdi_ctx* ctx, sdi_problem* pb, int32_t s, const void* x_dev, c
   (void)hipGetLastError();
   FlowState& F = *pb->flow;
   const int n = F.desc[s].n;
+  const int64_t nchunks = (npts + FL_CHUNK - 1) / FL_CHUNK;
   Carve C;
   PointRun* d_run = nullptr;
-  double *hsave = nullptr, *dl = nullptr;
+  int64_t* d_prefix = nullptr;
+  double* hsave = nullptr;
   float* part = nullptr;
   C.add((void**)&d_run, sizeof(PointRun));
+  C.add((void**)&d_prefix, 2 * sizeof(int64_t));
   C.add((void**)&hsave, (size_t)npts * FL_L * n * 8);
-  C.add((void**)&dl, (size_t)npts * n * 8);
-  C.add((void**)&part, flow_grad_part_bytes(F, 1, npts));
+  C.add((void**)&part, flow_grad_part_bytes(F, nchunks));
   rc = flow_scratch(ctx, F, C.total());
   if (rc) return rc;
   C.assign(F.d_scratch);
   hipStream_t st = ctx->stream;
   const PointRun run{s, 0, 0u, (uint32_t)npts, 0, 0};
+  const int64_t prefix[2] = {0, nchunks};
   HIPCHK(ctx, hipMemcpyAsync(d_run, &run, sizeof run, hipMemcpyHostToDevice, st));
-  rc = flow_gradient(ctx, pb, d_run, 1, npts, (const double*)x_dev, (const double*)c_dev, hsave, dl, part, st);
+  HIPCHK(ctx, hipMemcpyAsync(d_prefix, prefix, sizeof prefix, hipMemcpyHostToDevice, st));
+  rc = flow_gradient(ctx, pb, d_run, d_prefix, 1, nchunks, (const double*)x_dev, (const double*)c_dev, hsave, part,
+                     st);
   if (rc) return rc;
   if (grad_out)
     HIPCHK(ctx, hipMemcpyAsync(grad_out, F.d_grad + F.desc[s].base, (size_t)F.desc[s].nparam * 4,
@@ -380,7 +373,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
   PointRun* d_runs = nullptr;
   int64_t *d_pre64 = nullptr, *d_pre256 = nullptr;
   uint64_t *d_zp = nullptr, *d_shifts = nullptr;
-  double *x = nullptr, *w = nullptr, *lq = nullptr, *f = nullptr, *c = nullptr, *hsave = nullptr, *dl = nullptr;
+  double *x = nullptr, *w = nullptr, *lq = nullptr, *f = nullptr, *c = nullptr, *hsave = nullptr;
   double* d_bc = nullptr;
   float* part = nullptr;
   C.add((void**)&d_runs, sizeof(PointRun) * nr);
@@ -395,8 +388,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
   C.add((void**)&f, (size_t)npts * K * 2 * 8);
   C.add((void**)&c, (size_t)npts * 8);
   C.add((void**)&hsave, (size_t)xtot * FL_L * 8);
-  C.add((void**)&dl, (size_t)xtot * 8);
-  C.add((void**)&part, flow_grad_part_bytes(F, nr, Bt));
+  C.add((void**)&part, flow_grad_part_bytes(F, pre64[nr]));
   rc = flow_scratch(ctx, F, C.total());
   if (rc) return rc;
   C.assign(F.d_scratch);
@@ -451,7 +443,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
       else
         KCHK(ctx, launch_eval_tiles_real(km, E, st));
       KCHK(ctx, launch_flow_weights(d_runs, nr, K, f, lq, c, st));
-      const int r2 = flow_gradient(ctx, pb, d_runs, nr, Bt, x, c, hsave, dl, part, st);
+      const int r2 = flow_gradient(ctx, pb, d_runs, d_pre64, nr, pre64[nr], x, c, hsave, part, st);
       if (r2) return r2;
       KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.d_desc, d_runs, nr, F.max_nparam, lr,
                                  d_bc + (size_t)it * nr * 2, st));

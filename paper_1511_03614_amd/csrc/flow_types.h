@@ -18,8 +18,7 @@ constexpr int FL_H = 64;       // hidden units
 constexpr int FL_NB = 32;      // bins per transformed variable
 constexpr int FL_K1 = 16;      // first-layer input width (padded)
 constexpr int FL_MAXB = 8;     // transformed / conditioning variables per layer (n <= 16)
-constexpr int FL_CHUNK = 64;   // samples per block step of the gradient kernels (4 waves x 16)
-constexpr int FL_LS = 68;      // bf16 per feature row of the LDS operand tiles (64 samples + pad)
+constexpr int FL_CHUNK = 64;   // samples per wave of the sampling and gradient kernels
 constexpr int FL_MAXO = FL_MAXB * FL_NB;  // logits per layer at most
 
 struct FlowLayerDesc {
@@ -65,18 +64,18 @@ struct FlowTileArgs {
   double* lq;                    // log q at pt_off (may be null)
 };
 
-struct FlowBatchArgs {
+struct FlowGradArgs {
   const FlowSecDesc* fs;
   const float* params;
   const uint16_t* bw;
-  const FlowTile* tiles;     // one tile per batch (sector); row and i0 unused
-  int32_t ntiles;
-  int32_t layer;
-  const double* x;           // caller-order points at x_off
-  const double* c;           // loss weights at pt_off
-  double* hsave;             // layer inputs: [x_off * FL_L + (i * FL_L + l) * n + j]
-  double* dl;                // d loss / d h of the current layer output, at x_off
-  float* part;               // [ntiles][gridDim.x][part_stride] per-block partial gradients
+  const FlowTile* runs;          // one run per sector: count, x_off, pt_off (row and i0 unused)
+  const int64_t* chunk_prefix;   // [nruns + 1], chunks of 64 samples
+  int32_t nruns;
+  int64_t nchunks;
+  const double* x;               // caller-order points at x_off
+  const double* c;               // loss weights at pt_off
+  double* hsave;                 // layer inputs: [(x_off + i * n) * FL_L + l * n + j]
+  float* part;                   // [nchunks][part_stride] per-chunk gradients
   int64_t part_stride;
 };
 

@@ -64,10 +64,9 @@ int launch_flow_adam(float* params, const float* grad, float* m, float* v, const
                      hipStream_t st);
 int launch_flow_sample(const FlowSampleArgs& a, int nvmax, hipStream_t st);
 int launch_flow_sample_tiles(const FlowTileArgs& a, int nvmax, hipStream_t st);
-int launch_flow_fwd_store(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st);
-int launch_flow_bwd_layer(const FlowBatchArgs& a, int blocks_per_tile, hipStream_t st);
-int launch_flow_grad_reduce(const FlowSecDesc* fs, const FlowTile* tiles, int ntiles, int layer, const float* part,
-                            int64_t part_stride, int nblk, int64_t max_lsize, float* grad, hipStream_t st);
+int launch_flow_grad(const FlowGradArgs& a, int nvmax, hipStream_t st);
+int launch_flow_chunk_reduce(const FlowSecDesc* fs, const FlowTile* runs, const int64_t* chunk_prefix, int nruns,
+                             const float* part, int64_t stride, int64_t max_nparam, float* grad, hipStream_t st);
 int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* f, const double* lq, double* c,
                         hipStream_t st);
 int launch_flow_shifts(const FlowSecDesc* fs, const FlowTile* runs, int nruns, int iters, int m, uint64_t seed,
