@@ -296,11 +296,13 @@ __device__ __forceinline__ void forward_bin(const float* row, float mx, const do
 
 // Inverse of all coupling layers for the wave's 64 samples (all lanes call it
 // together).  h: this lane's state row, latent on entry, data point on
-// return; lq: log q of the sample.
+// return; lq: log q of the sample.  hsave (may be null): receives the state
+// after each layer l, which is that layer's input in the forward direction,
+// at hsave[l * n + j].
 template <int NV>
 __device__ __forceinline__ void flow_inverse_wave(const SDI_TAPE FlowSecDesc* F, const float* __restrict__ P,
                                                   const uint16_t* __restrict__ bw, double* h, float* lds,
-                                                  double& lq) {
+                                                  double& lq, double* hsave) {
   const int lane = threadIdx.x & 63;
   const int n = F->n;
   lq = 0.0;
@@ -355,6 +357,8 @@ __device__ __forceinline__ void flow_inverse_wave(const SDI_TAPE FlowSecDesc* F,
       h[j] = ((double)b + frac) / (double)FL_NB;
       lq += log((double)FL_NB * qb);
     }
+    if (hsave)
+      for (int j = 0; j < n; ++j) hsave[l * n + j] = h[j];
   }
 }
 
@@ -374,7 +378,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
     const bool valid = i < A.npts;
     for (int j = 0; j < n; ++j) h[j] = valid ? A.u[i * n + j] : 0.5;
     double lq;
-    flow_inverse_wave<NV>(F, P, A.bw, h, L.lg, lq);
+    flow_inverse_wave<NV>(F, P, A.bw, h, L.lg, lq, nullptr);
     if (valid) {
       for (int j = 0; j < n; ++j) A.x[i * n + j] = h[j];
       A.lq[i] = lq;
@@ -409,7 +413,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
       h[j] = u;
     }
     double lq;
-    flow_inverse_wave<NV>(F, A.params + F->base, A.bw, h, L.lg, lq);
+    double* hs = (A.hsave && valid) ? A.hsave + (T.x_off + local * n) * FL_L : nullptr;
+    flow_inverse_wave<NV>(F, A.params + F->base, A.bw, h, L.lg, lq, hs);
     if (valid) {
       double* xo = A.x + T.x_off + local * n;
       for (int j = 0; j < n; ++j) xo[j] = h[j];
@@ -576,8 +581,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_
       h[j] = valid ? A.x[T.x_off + local * n + j] : 0.5;
       dl[j] = 0.0;
     }
-    // forward: data -> latent
-    for (int l = 0; l < FL_L; ++l) {
+    // forward: data -> latent (skipped when the sampler stored the layer inputs)
+    for (int l = 0; l < (A.inputs_saved ? 0 : FL_L); ++l) {
       const SDI_TAPE FlowLayerDesc* D = &F->layer[l];
       if (valid)
         for (int j = 0; j < n; ++j) hs[l * n + j] = h[j];
@@ -632,14 +637,17 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_
         const double qb = eb * inv;
         const double y = cbu * inv + alpha * qb;
         const double dy = dl[j];
-        // d/dlogit_k of (dy y - c log q_b) = q_k dy (ind_k - y) - c (delta_kb - q_k)
+        // d/dlogit_k of (dy y - c log q_b) = q_k (dy (ind_k - y) + c) - c delta_kb, with
+        // ind_k = 1 below b, alpha at b, 0 above; in fp32 (the result is rounded to bf16)
+        const float invf = (float)inv;
+        const float a_lo = (float)(dy * (1.0 - y) + cw), a_hi = (float)(cw - dy * y);
+        const float g_b = (float)(qb * (dy * (alpha - y) + cw) - cw);
         bfv4_t gv[FL_NB / 4];
 #pragma unroll
         for (int k = 0; k < FL_NB; ++k) {
-          const double qk = (double)e[k] * inv;
-          const double ind = k < b ? 1.0 : (k == b ? alpha : 0.0);
-          const double gk = qk * (dy * (ind - y) + cw) - (k == b ? cw : 0.0);
-          gv[k >> 2][k & 3] = (__bf16)(float)gk;
+          float gk = e[k] * invf * (k < b ? a_lo : a_hi);
+          if (k == b) gk = g_b;
+          gv[k >> 2][k & 3] = (__bf16)gk;
         }
         dl[j] = dy * FL_NB * qb;
         wave_sync();

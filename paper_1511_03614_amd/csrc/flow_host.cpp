@@ -100,7 +100,8 @@ int flow_scratch(sdi_ctx* ctx, FlowState& F, size_t bytes) {
 // Gradient of -sum_i c_i log q(x_i) for every run (one run per sector) into
 // F.d_grad: per-chunk gradients, then their fixed-order sum per run.
 int flow_gradient(sdi_ctx* ctx, sdi_problem* pb, const PointRun* d_runs, const int64_t* d_chunk_prefix, int nruns,
-                  int64_t nchunks, const double* x, const double* c, double* hsave, float* part, hipStream_t st) {
+                  int64_t nchunks, const double* x, const double* c, double* hsave, bool inputs_saved, float* part,
+                  hipStream_t st) {
   FlowState& F = *pb->flow;
   FlowGradArgs A{};
   A.fs = F.d_desc;
@@ -113,6 +114,7 @@ int flow_gradient(sdi_ctx* ctx, sdi_problem* pb, const PointRun* d_runs, const i
   A.x = x;
   A.c = c;
   A.hsave = hsave;
+  A.inputs_saved = inputs_saved ? 1 : 0;
   A.part = part;
   A.part_stride = F.max_nparam;
   KCHK(ctx, launch_flow_grad(A, pb->nvmax, st));
@@ -256,8 +258,8 @@ int sdi_flow_grad(sdi_ctx* ctx, sdi_problem* pb, int32_t s, const void* x_dev, c
   const int64_t prefix[2] = {0, nchunks};
   HIPCHK(ctx, hipMemcpyAsync(d_run, &run, sizeof run, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(d_prefix, prefix, sizeof prefix, hipMemcpyHostToDevice, st));
-  rc = flow_gradient(ctx, pb, d_run, d_prefix, 1, nchunks, (const double*)x_dev, (const double*)c_dev, hsave, part,
-                     st);
+  rc = flow_gradient(ctx, pb, d_run, d_prefix, 1, nchunks, (const double*)x_dev, (const double*)c_dev, hsave, false,
+                     part, st);
   if (rc) return rc;
   if (grad_out)
     HIPCHK(ctx, hipMemcpyAsync(grad_out, F.d_grad + F.desc[s].base, (size_t)F.desc[s].nparam * 4,
@@ -427,6 +429,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
       S.x = x;
       S.w = w;
       S.lq = lq;
+      S.hsave = hsave;
       KCHK(ctx, launch_flow_sample_tiles(S, pb->nvmax, st));
       EvalTilesArgs E{};
       E.secs = pb->d_secs;
@@ -443,7 +446,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
       else
         KCHK(ctx, launch_eval_tiles_real(km, E, st));
       KCHK(ctx, launch_flow_weights(d_runs, nr, K, f, lq, c, st));
-      const int r2 = flow_gradient(ctx, pb, d_runs, d_pre64, nr, pre64[nr], x, c, hsave, part, st);
+      const int r2 = flow_gradient(ctx, pb, d_runs, d_pre64, nr, pre64[nr], x, c, hsave, true, part, st);
       if (r2) return r2;
       KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.d_desc, d_runs, nr, F.max_nparam, lr,
                                  d_bc + (size_t)it * nr * 2, st));

@@ -62,6 +62,7 @@ struct FlowTileArgs {
   double* x;                     // caller-order points at x_off
   double* w;                     // 1 / q at pt_off
   double* lq;                    // log q at pt_off (may be null)
+  double* hsave;                 // each layer's input, [(x_off + i * n) * FL_L + l * n + j] (may be null)
 };
 
 struct FlowGradArgs {
@@ -75,6 +76,7 @@ struct FlowGradArgs {
   const double* x;               // caller-order points at x_off
   const double* c;               // loss weights at pt_off
   double* hsave;                 // layer inputs: [(x_off + i * n) * FL_L + l * n + j]
+  int32_t inputs_saved;          // hsave already holds them (written by the sampler)
   float* part;                   // [nchunks][part_stride] per-chunk gradients
   int64_t part_stride;
 };
