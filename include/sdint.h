@@ -264,9 +264,13 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* prob, const int32_t* sectors, int3
  * training a sector becomes active; sdi_flow_init clears every flag). */
 int sdi_flow_set_active(sdi_ctx* ctx, sdi_problem* prob, int32_t s, int32_t active);
 /* Validation with the lattice as the judge: one lattice pass and one flow pass
- * at 2^lattice_log2 points per shift (other parameters from ctx); with V_k the
- * lattice pass's total variance of order k, an active sector keeps its flow
- * only if sum_k var_flow(s,k)/V_k < sum_k var_lattice(s,k)/V_k.  kept (host [nsectors], may be NULL) receives the active flags,
+ * at 2^lattice_log2 points per shift (other parameters from ctx); with I_k and
+ * V_k the lattice pass's estimate and total variance of order k and
+ * S_k = max(|I_k|^2, V_k), an active sector keeps its flow only if
+ * sum_k var_flow(s,k)/S_k < sum_k var_lattice(s,k)/S_k (its share of the
+ * squared relative errors of the coefficients) and, in every order, the flow
+ * pass's estimate of the sector lies within 5 combined standard errors of the
+ * lattice pass's.  kept (host [nsectors], may be NULL) receives the active flags,
  * *ms_out (may be NULL) the device time of the passes run.  If the problem's
  * last results come from a lattice pass with the same lattice_log2, shifts and
  * seed (no warm-up, no allocation), they serve as the lattice pass and only

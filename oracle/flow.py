@@ -18,7 +18,11 @@ Definition (one flow per sector, n variables):
   logits = W3 a2 + b3 with bf16 weights, H = 64 hidden units, NB = 32 logits per
   transformed variable; every bf16 rounding (weights, input, activations) is
   straight-through in the gradient;
-* Q_{j,k} = softmax_k(logits_j): bin probabilities of variable j;
+* Q_{j,k} = softmax_k(max(logits_j, max_k logits_j - 60)): bin probabilities of
+  variable j, each logit raised to at most 60 below the largest (a constant of
+  the map, no gradient through it), so that every bin keeps a positive
+  probability in fp32 and the map's density is positive on the whole cube, which
+  an unbiased importance-sampling estimator needs;
 * forward (data h -> latent y), per j in B_l: b = min(floor(h_j NB), NB - 1),
   y_j = sum_{k<b} Q_k + (h_j NB - b) Q_b, log J += log(NB Q_b);
 * inverse (latent -> data): b = the last bin whose running sum cum_b <= y_j,
@@ -49,6 +53,7 @@ L_LAYERS = 4
 HIDDEN = 64
 NBINS = 32
 INIT_TAG = 0x464C4F57
+LOGIT_RANGE = 60.0
 
 
 def masks(n: int):
@@ -124,8 +129,9 @@ def _probs(p: dict, hA: torch.Tensor, nb: int) -> torch.Tensor:
         a0 = ste_bf16(2.0 * hA - 1.0)
     a1 = ste_bf16(torch.relu(a0 @ ste_bf16(p["W1"]).T + p["b1"]))
     a2 = ste_bf16(torch.relu(a1 @ ste_bf16(p["W2"]).T + p["b2"]))
-    logits = a2 @ ste_bf16(p["W3"]).T + p["b3"]
-    return torch.softmax(logits.reshape(npts, nb, NBINS), dim=2)
+    logits = (a2 @ ste_bf16(p["W3"]).T + p["b3"]).reshape(npts, nb, NBINS)
+    floor = torch.amax(logits, dim=2, keepdim=True).detach() - LOGIT_RANGE
+    return torch.softmax(torch.maximum(logits, floor), dim=2)
 
 
 def log_q(params: List[dict], x: torch.Tensor) -> torch.Tensor:

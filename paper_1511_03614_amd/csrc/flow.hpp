@@ -10,8 +10,9 @@
 // 64 samples and the accumulator layout of one layer (lane holds rows
 // 4g..4g+3 of sample column l%16, g = l/16) is exactly the activation operand
 // of the next.  The 32 logits of a transformed variable go through LDS so that
-// each lane finishes its own sample's softmax (fp32 exponentials, fp64
-// normalisation), bin search and Jacobian (fp64) without cross-lane traffic;
+// each lane finishes its own sample's softmax (fp32 exponentials of logits
+// held within FL_ZRANGE of the largest, fp64 normalisation), bin search and
+// Jacobian (fp64) without cross-lane traffic;
 // the importance weight 1/q is the exact Jacobian of the map actually applied,
 // so the estimator stays unbiased whatever the network's precision.
 //
@@ -241,9 +242,14 @@ __device__ __forceinline__ void logits_to_lds(const uint16_t* __restrict__ bw, c
   }
 }
 
-// Softmax of this lane's row of 32 logits: e_k = exp(z_k - max) in fp32, gs =
-// fp64 sums of the groups of 4 bins; returns the fp64 total.  The row stays
-// in LDS (a bin's e_k can be recomputed from it bit-identically).
+// exp(z - max) of one logit, with z raised to at most FL_ZRANGE below the
+// maximum so that every bin keeps a positive probability (the map's density
+// stays positive on the whole cube).
+__device__ __forceinline__ float bin_exp(float z, float mx) { return exp_nonpos(fmaxf(z - mx, -FL_ZRANGE)); }
+
+// Softmax of this lane's row of 32 logits: e_k = bin_exp(z_k, max) in fp32,
+// gs = fp64 sums of the groups of 4 bins; returns the fp64 total.  The row
+// stays in LDS (a bin's e_k can be recomputed from it bit-identically).
 __device__ __forceinline__ double lane_softmax(const float* row, float& mx, float (&e)[FL_NB], double (&gs)[FL_NB / 4]) {
 #pragma unroll
   for (int k = 0; k < FL_NB; k += 4) {
@@ -259,7 +265,7 @@ __device__ __forceinline__ double lane_softmax(const float* row, float& mx, floa
 #pragma unroll
   for (int m = 0; m < FL_NB / 4; ++m) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) e[4 * m + i] = exp_nonpos(e[4 * m + i] - mx);
+    for (int i = 0; i < 4; ++i) e[4 * m + i] = bin_exp(e[4 * m + i], mx);
     gs[m] = (((double)e[4 * m] + (double)e[4 * m + 1]) + (double)e[4 * m + 2]) + (double)e[4 * m + 3];
   }
   return ((gs[0] + gs[1]) + (gs[2] + gs[3])) + ((gs[4] + gs[5]) + (gs[6] + gs[7]));
@@ -281,7 +287,7 @@ __device__ __forceinline__ void forward_bin(const float* row, float mx, const do
   for (int m = 0; m < FL_NB / 4; ++m)
     if (m < gb) c += gs[m];
   const float4 v = *reinterpret_cast<const float4*>(row + 4 * gb);
-  const float eg[4] = {exp_nonpos(v.x - mx), exp_nonpos(v.y - mx), exp_nonpos(v.z - mx), exp_nonpos(v.w - mx)};
+  const float eg[4] = {bin_exp(v.x, mx), bin_exp(v.y, mx), bin_exp(v.z, mx), bin_exp(v.w, mx)};
   double e = (double)eg[0];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -642,11 +648,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_
         const float invf = (float)inv;
         const float a_lo = (float)(dy * (1.0 - y) + cw), a_hi = (float)(cw - dy * y);
         const float g_b = (float)(qb * (dy * (alpha - y) + cw) - cw);
+        // a logit held at the range bound has no gradient
+        const float e_floor = bin_exp(-FL_ZRANGE, 0.f);
         bfv4_t gv[FL_NB / 4];
 #pragma unroll
         for (int k = 0; k < FL_NB; ++k) {
           float gk = e[k] * invf * (k < b ? a_lo : a_hi);
           if (k == b) gk = g_b;
+          if (e[k] <= e_floor) gk = 0.f;
           gv[k >> 2][k & 3] = (__bf16)gk;
         }
         dl[j] = dy * FL_NB * qb;

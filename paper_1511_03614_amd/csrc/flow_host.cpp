@@ -500,11 +500,14 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
 
 // Keeps a sector's flow only where it lowers that sector's share of the
 // error: one lattice pass and one flow pass at 2^lattice_log2 points per shift
-// (the context's other parameters); with V_k the lattice pass's total variance
-// of order k, the flow of sector s stays active when
-// sum_k var_flow(s,k) / V_k < sum_k var_lattice(s,k) / V_k, i.e. when it lowers
-// the sector's contribution to the relative variance of the result, summed
-// over the orders.  kept (host, [nsectors], may be NULL) receives the flags.
+// (the context's other parameters).  With I_k and V_k the lattice pass's
+// estimate and total variance of order k and S_k = max(|I_k|^2, V_k), the flow
+// of sector s stays active when sum_k var_flow(s,k) / S_k < sum_k
+// var_lattice(s,k) / S_k: the sector's contribution to the squared relative
+// errors of the coefficients, summed over the orders, so that the orders with
+// the largest relative error decide; and when, in every order, the two
+// estimates of the sector agree within 5 combined standard errors.  kept
+// (host, [nsectors], may be NULL) receives the flags.
 int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32_t* kept, float* ms_out) {
   if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_validate: null argument");
   int rc = flow_ready(ctx, pb);
@@ -512,7 +515,8 @@ int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32
   if (lattice_log2 < 4 || lattice_log2 > 24) return fail(ctx, SDI_EINVAL, "flow_validate: lattice_log2 in 4..24");
   FlowState& F = *pb->flow;
   const Params saved = ctx->params;
-  std::vector<double> v[2];
+  // per sector and order: variance of each pass; mean (re, im) of the lattice and of the flow pass
+  std::vector<double> v[2], mean[2], fmean[2];
   const int K = pb->K;
   std::vector<double> re(K), im(K), er(K), ei(K);
   double ms = 0.0;
@@ -522,10 +526,14 @@ int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32
   for (int pass = reuse ? 1 : 0; pass < 2; ++pass) {
     if (pass == 1 && reuse) {
       v[0].assign((size_t)pb->nsec * K, 0.0);
+      mean[0].assign((size_t)pb->nsec * K, 0.0);
+      mean[1].assign((size_t)pb->nsec * K, 0.0);
       for (int s = 0; s < pb->nsec; ++s)
         for (int k = 0; k < K; ++k) {
           const double* q = pb->sec_stats.data() + ((size_t)s * KMAX + k) * 4;
           v[0][(size_t)s * K + k] = q[2] * q[2] + q[3] * q[3];
+          mean[0][(size_t)s * K + k] = q[0];
+          mean[1][(size_t)s * K + k] = q[1];
         }
     }
     ctx->params.m = lattice_log2;
@@ -544,16 +552,30 @@ int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32
     }
     ms += res.ms_total;
     v[pass].assign((size_t)pb->nsec * K, 0.0);
+    std::vector<double>* mm = pass == 0 ? mean : fmean;
+    mm[0].assign((size_t)pb->nsec * K, 0.0);
+    mm[1].assign((size_t)pb->nsec * K, 0.0);
     for (int s = 0; s < pb->nsec; ++s)
       for (int k = 0; k < K; ++k) {
         const double* q = pb->sec_stats.data() + ((size_t)s * KMAX + k) * 4;
         v[pass][(size_t)s * K + k] = q[2] * q[2] + q[3] * q[3];
+        mm[0][(size_t)s * K + k] = q[0];
+        mm[1][(size_t)s * K + k] = q[1];
       }
   }
   ctx->params = saved;
+  // scale of order k: the squared magnitude of its lattice estimate, or the
+  // lattice pass's total variance of that order where that is larger
   std::vector<double> V(K, 0.0);
-  for (int s = 0; s < pb->nsec; ++s)
-    for (int k = 0; k < K; ++k) V[k] += v[0][(size_t)s * K + k];
+  for (int k = 0; k < K; ++k) {
+    double tr = 0.0, ti = 0.0, tv = 0.0;
+    for (int s = 0; s < pb->nsec; ++s) {
+      tr += mean[0][(size_t)s * K + k];
+      ti += mean[1][(size_t)s * K + k];
+      tv += v[0][(size_t)s * K + k];
+    }
+    V[k] = std::max(tr * tr + ti * ti, tv);
+  }
   bool changed = false;
   for (int s = 0; s < pb->nsec; ++s) {
     if (F.active[s]) {
@@ -563,7 +585,17 @@ int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32
           sf += v[1][(size_t)s * K + k] / V[k];
           sl += v[0][(size_t)s * K + k] / V[k];
         }
-      if (!(sf < sl)) {
+      // the two passes estimate the same integral: a flow whose estimate sits
+      // more than 5 combined standard errors from the lattice's in some order
+      // is rejected whatever its variance (a map that rarely visits part of
+      // the cube can look precise and still be off)
+      bool consistent = true;
+      for (int k = 0; k < K; ++k) {
+        const size_t i = (size_t)s * K + k;
+        const double dr = fmean[0][i] - mean[0][i], di = fmean[1][i] - mean[1][i];
+        if (!(dr * dr + di * di <= 25.0 * (v[0][i] + v[1][i]))) consistent = false;
+      }
+      if (!(sf < sl) || !consistent) {
         F.active[s] = 0;
         changed = true;
       }

@@ -20,6 +20,7 @@ constexpr int FL_K1 = 16;      // first-layer input width (padded)
 constexpr int FL_MAXB = 8;     // transformed / conditioning variables per layer (n <= 16)
 constexpr int FL_CHUNK = 64;   // samples per wave of the sampling and gradient kernels
 constexpr int FL_MAXO = FL_MAXB * FL_NB;  // logits per layer at most
+constexpr float FL_ZRANGE = 60.f;         // logits are raised to at most this far below the largest
 
 struct FlowLayerDesc {
   int32_t nA, nB;

@@ -299,3 +299,43 @@ def test_training_a_subset_leaves_the_rest(ctx):
     finally:
         P.sdi_problem_destroy(h)
         set_params(ctx)
+
+
+def test_validation_keeps_only_flows_that_help(ctx):
+    """sdi_flow_validate's kept flags equal the criterion recomputed from the two passes'
+    per-sector results: with S_k = max(|I_k|^2, V_k) from the lattice pass, a flow
+    stays where sum_k var_flow(s,k)/S_k < sum_k var_lattice(s,k)/S_k and every
+    order's two estimates agree within 5 combined standard errors.  The trained flow
+    of the peaked sector stays; flows with random weights on smooth sectors go."""
+    smooth = [problem_with_dims([3]).sectors[0], problem_with_dims([4]).sectors[0]]
+    prob = sectorgen.Problem(sectors=[peaked_sector()] + smooth, order_min=0, order_max=0)
+    m, R = 10, 16
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        set_params(ctx, lattice_log2=m, shifts=R, seed=5)
+        P.sdi_flow_init(ctx, h, 4)
+        P.sdi_flow_train(ctx, h, 60, 11, 5e-3, sectors=[0])
+        P.sdi_flow_set_params(ctx, h, 1, random_fp32_params(smooth[0].n, 9, scale=2.0))
+        P.sdi_flow_set_params(ctx, h, 2, random_fp32_params(smooth[1].n, 10, scale=40.0))
+        passes = []
+        for sampler in (0, 1):
+            set_params(ctx, lattice_log2=m, shifts=R, seed=5, sampler=sampler)
+            P.sdi_integrate(ctx, h)
+            passes.append([P.sdi_sector_results(ctx, h, s, R) for s in range(3)])
+        set_params(ctx, lattice_log2=m, shifts=R, seed=5, sampler=0)
+        kept, ms = P.sdi_flow_validate(ctx, h, m)
+        mean = [np.array([passes[p][s][0] for s in range(3)]) for p in (0, 1)]   # [sector][order]
+        var = [np.array([np.sum(passes[p][s][1] ** 2, axis=1) for s in range(3)]) for p in (0, 1)]
+        S = np.maximum(np.abs(mean[0].sum(axis=0)) ** 2, var[0].sum(axis=0))
+        want = []
+        for s in range(3):
+            better = (var[1][s] / S).sum() < (var[0][s] / S).sum()
+            agree = bool(np.all(np.abs(mean[1][s] - mean[0][s]) ** 2 <= 25.0 * (var[0][s] + var[1][s])))
+            log(f"sector {s}: lattice {mean[0][s]} +- {np.sqrt(var[0][s])}, flow {mean[1][s]} +- {np.sqrt(var[1][s])}")
+            want.append(better and agree)
+        log(f"validation: kept {list(kept)}, criterion {want}, {ms:.2f} ms")
+        assert [bool(k) for k in kept] == want
+        assert want == [True, False, False]
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)

@@ -111,3 +111,22 @@ def test_training_lowers_variance():
         flow.adam_step(P, G, st, lr=3e-3)
     v1 = var_of(P)
     assert v1 < 0.3 * v0, (v0, v1)
+
+
+def test_bin_probabilities_stay_positive():
+    """Extreme weights push logits hundreds apart; the logit range bound keeps every
+    bin probability positive (>= e^-60 / 32) and the map invertible."""
+    n = 3
+    P = random_params(n, 5, scale=200.0)
+    u = lattice(n, 9)
+    h = torch.tensor(u, dtype=torch.float64)
+    A, B = flow.masks(n)[0]
+    Q = flow._probs(P[0], h[:, A], len(B))
+    assert float(Q.min()) >= math.exp(-60.0) / flow.NBINS * 0.999
+    logits_gap = (torch.amax(Q, dim=2) / torch.amin(Q, dim=2)).max()
+    assert float(logits_gap) > 1e20          # the bound is active here
+    x, lq = flow.sample(P, u)
+    y, lq2 = flow.forward(P, torch.tensor(x))
+    assert np.all(np.isfinite(lq))
+    ok = np.abs(y.numpy() - u).max(axis=1) < 1e-6
+    assert ok.mean() > 0.99
