@@ -134,81 +134,107 @@ def flow_layer_flops(n: int) -> int:
 
 
 def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, share=0.9, max_sel=48,
-                          iters=20, batch_log2=10, lr=3e-3, m_flow=12, plain_ms=(10, 17)):
+                          iters=40, batch_log2=11, lr=3e-3, finals=None, plains=None, common=None,
+                          select_on="relative", references=None):
     """Error of the learned+batched form against plain batched QMC at equal GPU time.
 
-    Learned form: a plain pilot pass picks the sectors that carry `share` of the
-    pilot variance (orders weighted equally, at most max_sel sectors); their
-    flows are trained on the GPU and validated against the lattice (a flow is
-    kept only where it lowers its sector's variance); then one pass samples
-    the kept sectors through their flows and the rest on the lattice.  Its GPU
-    time is pilot + training + validation + pass.  Plain form: lattice passes of 2^m points per shift for m in
-    plain_ms; its error at the learned form's time is interpolated in
-    log(error) against log(time).  Device times are the library's own
-    (HIP events on its stream)."""
+    Learned form: a plain pilot pass (2^m_pilot lattice points per shift) picks
+    the sectors that carry `share` of the pilot's error (select_on = "relative":
+    orders weighted by their squared relative error; "top": the highest order
+    only, which then also sets the order weights of training and validation;
+    at most max_sel sectors); their flows are trained on
+    the GPU and validated against the lattice (a flow is kept only where it
+    lowers its sector's share of the relative errors and agrees with the
+    lattice); then a final pass samples the kept sectors through their flows and
+    the rest on the lattice, at each operating point of `finals` (parameter
+    sets).  Its GPU time is pilot + training + validation + final pass.  Plain
+    form: lattice passes at each parameter set of `plains`; its error at the
+    learned form's time is interpolated in log(error) against log(time).
+    `common` parameters apply to every pass; `references` (parameter sets) are
+    further plain passes reported beside the baseline (e.g. plain QMC with the
+    variance-driven allocation, which isolates the flows' share of the gain).
+    Device times are the library's own (HIP events on its stream)."""
     import numpy as np
+    finals = finals or [dict(lattice_log2=12), dict(lattice_log2=13)]
+    plains = plains or [dict(lattice_log2=m) for m in range(10, 17)]
+    common = common or {}
     h = P.sdi_problem_create(ctx, problem)
+
+    def run(**kw):
+        _set(P, ctx, **{**common, **kw})
+        P.sdi_integrate(ctx, h)              # plan, tune and capture once
+        return P.sdi_integrate(ctx, h)
+
     try:
         ns = len(problem.sectors)
         if lambda_max is not None:
             P.sdi_tune_deformation(ctx, h, lambda_max, 4, 10)
         plain = []
-        for m in range(*plain_ms):
-            _set(P, ctx, lattice_log2=m)
-            P.sdi_integrate(ctx, h)              # plan, tune and capture once
-            r = P.sdi_integrate(ctx, h)
-            plain.append((m, r["ms_total"], _err(r), r))
-        _set(P, ctx, lattice_log2=m_pilot)
-        P.sdi_integrate(ctx, h)
-        pilot = P.sdi_integrate(ctx, h)
+        for kw in plains:
+            r = run(**kw)
+            plain.append((kw, r["ms_total"], _err(r)))
+        plain.sort(key=lambda p: p[1])
+        refs = []
+        for kw in references or []:
+            r = run(**kw)
+            refs.append({"params": kw, "ms": r["ms_total"], "err": _err(r).tolist()})
+        pilot = run(lattice_log2=m_pilot, budget=0)
         var = np.zeros((ns, problem.norders))
+        val = np.zeros(problem.norders, dtype=complex)
         for s in range(ns):
-            _, err, _, _ = P.sdi_sector_results(ctx, h, s, 16)
+            mean, err, _, _ = P.sdi_sector_results(ctx, h, s, 16)
             var[s] = err[:, 0] ** 2 + err[:, 1] ** 2
-        tot = var.sum(axis=0)
-        w = (var / np.where(tot > 0, tot, 1.0)).sum(axis=1)
+            val += mean
+        scale = np.maximum(np.abs(val) ** 2, var.sum(axis=0))
+        if select_on == "top":
+            scale[:-1] = np.inf
+        w = (var / np.where(scale > 0, scale, 1.0)).sum(axis=1)
         order = np.argsort(-w)
         cum = np.cumsum(w[order]) / max(w.sum(), 1e-300)
         nsel = int(min(max_sel, np.searchsorted(cum, share) + 1, ns))
         sel = sorted(int(s) for s in order[:nsel])
+        ow = None
+        if select_on == "top":
+            ow = np.zeros(problem.norders)
+            ow[-1] = 1.0
         P.sdi_flow_init(ctx, h, 1)
-        ms_train = P.sdi_flow_train(ctx, h, iters, batch_log2, lr, sectors=sel)
-        kept, ms_val = P.sdi_flow_validate(ctx, h, m_pilot)
-        _set(P, ctx, lattice_log2=m_flow, sampler=1)
-        fr = P.sdi_integrate(ctx, h)
-        # matrix-core work of the learned sampler: training does one forward per
-        # layer plus, per layer, a recomputed forward and the two backward
-        # products (dW and dx), i.e. 4x the forward flops; sampling 1x
-        f_train = sum(4 * flow_layer_flops(problem.sectors[s].n) for s in sel) * iters * (1 << batch_log2)
+        ms_train = P.sdi_flow_train(ctx, h, iters, batch_log2, lr, sectors=sel, order_weights=ow)
+        kept, ms_val = P.sdi_flow_validate(ctx, h, m_pilot, order_weights=ow)
         n_kept = [s for s in range(ns) if kept[s]]
-        f_sample = sum(flow_layer_flops(problem.sectors[s].n) for s in n_kept) * 16 * (1 << m_flow)
-        t_learned = pilot["ms_total"] + ms_train + ms_val + fr["ms_total"]
-        ef = _err(fr)
+        # matrix-core work of the learned sampler: training does, per layer, a
+        # recomputed forward and the two backward products (weights and inputs),
+        # 3x the forward flops, plus the sampling forward: 4x
+        f_train = sum(4 * flow_layer_flops(problem.sectors[s].n) for s in sel) * iters * (1 << batch_log2)
         t = np.array([p[1] for p in plain])
         ep = np.array([p[2] for p in plain])
-        k = int(np.clip(np.searchsorted(t, t_learned), 1, len(t) - 1))
-        a = (np.log(t_learned) - np.log(t[k - 1])) / (np.log(t[k]) - np.log(t[k - 1]))
-        with np.errstate(divide="ignore", invalid="ignore"):
-            e_eq = np.exp((1 - a) * np.log(ep[k - 1]) + a * np.log(ep[k]))
-            ratio = np.where(ef > 0, e_eq / ef, np.nan)
-        top = problem.norders - 1
+        points = []
+        for kw in finals:
+            fr = run(**kw, sampler=1)
+            t_learned = pilot["ms_total"] + ms_train + ms_val + fr["ms_total"]
+            ef = _err(fr)
+            k = int(np.clip(np.searchsorted(t, t_learned), 1, len(t) - 1))
+            a = (np.log(t_learned) - np.log(t[k - 1])) / (np.log(t[k]) - np.log(t[k - 1]))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                e_eq = np.exp((1 - a) * np.log(ep[k - 1]) + a * np.log(ep[k]))
+                ratio = np.where(ef > 0, e_eq / ef, np.nan)
+            points.append({"final": kw, "ms_total": t_learned, "ms_final_pass": fr["ms_total"],
+                           "ms_flow_sampling": fr["ms_warmup"], "err": ef.tolist(),
+                           "value_re": fr["value"].real.tolist(), "value_im": fr["value"].imag.tolist(),
+                           "plain_err_at_equal_time": e_eq.tolist(),
+                           "error_ratio_plain_over_learned": ratio.tolist(),
+                           "error_ratio_top_order": float(ratio[problem.norders - 1])})
         return {
-            "config": name, "orders": list(range(problem.order_min, problem.order_max + 1)),
-            "flow_sectors_trained": nsel, "flow_sectors_kept": int(kept.sum()), "sectors": ns,
+            "config": name, "orders": list(range(problem.order_min, problem.order_max + 1)), "sectors": ns,
+            "flow_sectors_trained": nsel, "flow_sectors_kept": len(n_kept),
+            "pilot": {"lattice_log2": m_pilot, "ms": pilot["ms_total"]},
             "train": {"iters": iters, "batch": 1 << batch_log2, "ms": ms_train,
                       "mfma_bf16_tflops": f_train / (ms_train * 1e-3) / 1e12,
                       "mfma_frac": f_train / (ms_train * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS},
-            "flow_sampling": {"ms": fr["ms_warmup"], "points": len(n_kept) * 16 << m_flow,
-                              "mfma_bf16_tflops": (f_sample / (fr["ms_warmup"] * 1e-3) / 1e12
-                                                   if fr["ms_warmup"] > 0 else None)},
             "validate_ms": ms_val,
-            "pilot_ms": pilot["ms_total"],
-            "learned": {"ms_total": t_learned, "lattice_log2": m_flow, "err": ef.tolist(),
-                        "value_re": fr["value"].real.tolist(), "value_im": fr["value"].imag.tolist()},
-            "plain": [{"lattice_log2": m, "ms": ms, "err": e.tolist()} for m, ms, e, _ in plain],
-            "plain_err_at_equal_time": e_eq.tolist(),
-            "error_ratio_plain_over_learned": ratio.tolist(),
-            "error_ratio_top_order": float(ratio[top]),
+            "learned": points,
+            "plain": [{"params": kw, "ms": ms, "err": e.tolist()} for kw, ms, e in plain],
+            "plain_references": refs,
+            "error_ratio_top_order": [p["error_ratio_top_order"] for p in points],
         }
     finally:
         P.sdi_problem_destroy(h)
@@ -291,13 +317,23 @@ def main() -> int:
     P.sdi_problem_destroy(h)
     if not args.no_equal_time:
         from sectorgen.feynman import double_box_problem
+        lat = [dict(lattice_log2=m) for m in range(10, 17)]
+        alloc = dict(pilot_log2=10, alloc_min_log2=12, alloc_max_log2=20)
         out["error_vs_plain_qmc"] = [
             equal_time_comparison(P, ctx, "double box, s=-3, t=-1, massless (Euclidean, 282 sectors, eps^-4..eps^0)",
-                                  double_box_problem(-3.0, -1.0, 0.0, order_max=0)),
+                                  double_box_problem(-3.0, -1.0, 0.0, order_max=0), plains=lat,
+                                  finals=[dict(lattice_log2=m) for m in (12, 13, 14)]),
+            equal_time_comparison(P, ctx, "batched2000: 2000 synthetic sectors, 4-9 variables, 5-40 terms, "
+                                          "eps^-3..eps^0; learned form with per-sector budgets 2^16..2^24 "
+                                          "by Neyman allocation, plain form uniform",
+                                  sectorgen.config4(), m_pilot=10, max_sel=64, common=alloc,
+                                  plains=[dict(lattice_log2=m) for m in range(10, 16)],
+                                  references=[dict(budget=1 << b) for b in (28, 29, 30)],
+                                  finals=[dict(budget=1 << b) for b in (28, 29, 30)]),
             equal_time_comparison(P, ctx, "double box, s=5, t=-2, m^2=1 (physical, contour deformation, "
                                           "lambda tuned in (0, 0.5], 30 sectors, eps^-4..eps^0)",
                                   double_box_problem(5.0, -2.0, 1.0, order_max=0, complex_mode=True, lam=0.5),
-                                  lambda_max=0.5),
+                                  lambda_max=0.5, plains=lat, finals=[dict(lattice_log2=m) for m in (12, 13, 14)]),
         ]
     P.sdi_ctx_destroy(ctx)
     if not args.no_cpu_baseline:

@@ -254,11 +254,13 @@ int sdi_flow_adam(sdi_ctx* ctx, sdi_problem* prob, double lr);
 /* Train the flows of the listed sectors (all sectors when `sectors` is NULL)
  * on the GPU for `iters` steps of 2^batch_log2 latent lattice points per
  * sector (shift rows 65536 + step of the Philox shifts), loss weights
- * c_i = sum_k (|F_k(x_i)|^2 / q_i^2) / S_k with S_k the batch total of order
- * k; one Adam step per iteration (per-sector step counts).  The trained
- * sectors become active.  *ms_out: device time (may be NULL). */
+ * c_i = sum_k w_k (|F_k(x_i)|^2 / q_i^2) / S_k with S_k the batch total of
+ * order k and w_k = order_weights[k] (host [norders], finite, >= 0, not all
+ * zero; NULL = all 1: which coefficients the maps should serve); one Adam
+ * step per iteration (per-sector step counts).  The trained sectors become
+ * active.  *ms_out: device time (may be NULL). */
 int sdi_flow_train(sdi_ctx* ctx, sdi_problem* prob, const int32_t* sectors, int32_t nsel, int32_t iters,
-                   int32_t batch_log2, double lr, float* ms_out);
+                   int32_t batch_log2, double lr, const double* order_weights, float* ms_out);
 /* Sectors whose flow is active take their points from it in passes with
  * sampler = 1; the others stay on the lattice (with sdi_flow_set_params or
  * training a sector becomes active; sdi_flow_init clears every flag). */
@@ -267,16 +269,18 @@ int sdi_flow_set_active(sdi_ctx* ctx, sdi_problem* prob, int32_t s, int32_t acti
  * at 2^lattice_log2 points per shift (other parameters from ctx); with I_k and
  * V_k the lattice pass's estimate and total variance of order k and
  * S_k = max(|I_k|^2, V_k), an active sector keeps its flow only if
- * sum_k var_flow(s,k)/S_k < sum_k var_lattice(s,k)/S_k (its share of the
- * squared relative errors of the coefficients) and, in every order, the flow
- * pass's estimate of the sector lies within 5 combined standard errors of the
+ * sum_k w_k var_flow(s,k)/S_k < sum_k w_k var_lattice(s,k)/S_k (its share of
+ * the squared relative errors of the coefficients, w_k = order_weights[k],
+ * host [norders] >= 0, NULL = all 1) and, in every order, the flow pass's
+ * estimate of the sector lies within 5 combined standard errors of the
  * lattice pass's.  kept (host [nsectors], may be NULL) receives the active flags,
  * *ms_out (may be NULL) the device time of the passes run.  If the problem's
  * last results come from a lattice pass with the same lattice_log2, shifts and
  * seed (no warm-up, no allocation), they serve as the lattice pass and only
  * the flow pass runs.  The per-sector results left on the problem are those of
  * the flow pass. */
-int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* prob, int32_t lattice_log2, int32_t* kept, float* ms_out);
+int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* prob, int32_t lattice_log2, const double* order_weights,
+                      int32_t* kept, float* ms_out);
 
 #ifdef __cplusplus
 }

@@ -220,13 +220,15 @@ def adam_step(params, grads, st: AdamState, lr: float, b1=0.9, b2=0.999, eps=1e-
     return params
 
 
-def importance_weights(f: np.ndarray, logq: np.ndarray) -> np.ndarray:
-    """c_i = sum_k (|f_k(x_i)|^2 / q_i^2) / S_k, S_k the batch total of that order (zero orders skipped)."""
+def importance_weights(f: np.ndarray, logq: np.ndarray, order_weights=None) -> np.ndarray:
+    """c_i = sum_k w_k (|f_k(x_i)|^2 / q_i^2) / S_k, S_k the batch total of that order
+    (zero orders skipped), w_k the caller's order weights (default 1)."""
     w2 = np.exp(-2.0 * logq)
     a = np.abs(f) ** 2 * w2[None, :]
     c = np.zeros(f.shape[1])
     for k in range(f.shape[0]):
         tot = a[k].sum()
-        if tot > 0.0 and np.isfinite(tot):
-            c += a[k] / tot
+        wk = 1.0 if order_weights is None else float(order_weights[k])
+        if tot > 0.0 and np.isfinite(tot) and wk != 0.0:
+            c += wk * a[k] / tot
     return c

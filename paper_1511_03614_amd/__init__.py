@@ -121,9 +121,10 @@ def load_library():
         "sdi_flow_grad": (C.c_int, [vp, vp, i32, vp, vp, i64, C.POINTER(C.c_float)]),
         "sdi_flow_set_grad": (C.c_int, [vp, vp, i32, C.POINTER(C.c_float), i64]),
         "sdi_flow_adam": (C.c_int, [vp, vp, C.c_double]),
-        "sdi_flow_train": (C.c_int, [vp, vp, C.POINTER(i32), i32, i32, i32, C.c_double, C.POINTER(C.c_float)]),
+        "sdi_flow_train": (C.c_int, [vp, vp, C.POINTER(i32), i32, i32, i32, C.c_double, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_float)]),
         "sdi_flow_set_active": (C.c_int, [vp, vp, i32, i32]),
-        "sdi_flow_validate": (C.c_int, [vp, vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]),
+        "sdi_flow_validate": (C.c_int, [vp, vp, i32, C.POINTER(C.c_double), C.POINTER(i32), C.POINTER(C.c_float)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -388,7 +389,16 @@ def sdi_flow_adam(ctx, prob, lr: float):
     _check(load_library().sdi_flow_adam(ctx, prob, float(lr)), ctx)
 
 
-def sdi_flow_train(ctx, prob, iters: int, batch_log2: int, lr: float, sectors=None) -> float:
+def _order_weights(prob, order_weights):
+    if order_weights is None:
+        return None, None
+    w = np.ascontiguousarray(order_weights, dtype=np.float64)
+    if w.shape != (sdi_problem_norders(prob),):
+        raise ValueError("order_weights needs one weight per result order")
+    return w, _dptr(w)
+
+
+def sdi_flow_train(ctx, prob, iters: int, batch_log2: int, lr: float, sectors=None, order_weights=None) -> float:
     """Trains the flows of `sectors` (all if None) on the GPU; returns the device time in ms."""
     ms = C.c_float(0.0)
     if sectors is None:
@@ -396,7 +406,8 @@ def sdi_flow_train(ctx, prob, iters: int, batch_log2: int, lr: float, sectors=No
     else:
         sel = np.ascontiguousarray(sectors, dtype=np.int32)
         ptr, n = sel.ctypes.data_as(C.POINTER(C.c_int32)), sel.size
-    _check(load_library().sdi_flow_train(ctx, prob, ptr, n, iters, batch_log2, float(lr), C.byref(ms)), ctx)
+    w, wp = _order_weights(prob, order_weights)
+    _check(load_library().sdi_flow_train(ctx, prob, ptr, n, iters, batch_log2, float(lr), wp, C.byref(ms)), ctx)
     return float(ms.value)
 
 
@@ -404,10 +415,11 @@ def sdi_flow_set_active(ctx, prob, s: int, active: bool):
     _check(load_library().sdi_flow_set_active(ctx, prob, s, 1 if active else 0), ctx)
 
 
-def sdi_flow_validate(ctx, prob, lattice_log2: int):
-    """Deactivates flows that do not lower their sector's variance; returns (kept flags, device ms)."""
+def sdi_flow_validate(ctx, prob, lattice_log2: int, order_weights=None):
+    """Deactivates flows that do not lower their sector's share of the relative errors; returns (kept, device ms)."""
     kept = np.zeros(sdi_problem_nsectors(prob), dtype=np.int32)
     ms = C.c_float(0.0)
-    _check(load_library().sdi_flow_validate(ctx, prob, lattice_log2, kept.ctypes.data_as(C.POINTER(C.c_int32)),
+    w, wp = _order_weights(prob, order_weights)
+    _check(load_library().sdi_flow_validate(ctx, prob, lattice_log2, wp, kept.ctypes.data_as(C.POINTER(C.c_int32)),
                                             C.byref(ms)), ctx)
     return kept.astype(bool), float(ms.value)

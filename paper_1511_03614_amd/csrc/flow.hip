@@ -80,10 +80,10 @@ int launch_flow_chunk_reduce(const FlowSecDesc* fs, const FlowTile* runs, const 
   return (int)hipGetLastError();
 }
 
-int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* f, const double* lq, double* c,
-                        hipStream_t st) {
+int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* f, const double* lq, const double* ow,
+                        double* c, hipStream_t st) {
   if (ntiles <= 0) return 0;
-  k_flow_weights<<<dim3(ntiles), dim3(256), 0, st>>>(tiles, K, f, lq, c);
+  k_flow_weights<<<dim3(ntiles), dim3(256), 0, st>>>(tiles, K, f, lq, ow, c);
   return (int)hipGetLastError();
 }
 

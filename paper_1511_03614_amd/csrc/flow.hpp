@@ -778,11 +778,11 @@ __global__ void k_flow_chunk_reduce(const FlowSecDesc* fs, const FlowTile* runs,
 }
 
 
-// Loss weights of one batch per block: c_i = sum_k (|f_k(x_i)|^2 / q_i^2) / S_k,
+// Loss weights of one batch per block: c_i = sum_k w_k (|f_k(x_i)|^2 / q_i^2) / S_k,
 // S_k the batch total of that order, orders with a zero or non-finite total
-// skipped.  f: [pt][K][2] (result orders), lq: log q.
+// skipped.  f: [pt][K][2] (result orders), lq: log q, ow: the order weights w_k.
 __global__ void __launch_bounds__(256) k_flow_weights(const FlowTile* tiles, int K, const double* f,
-                                                      const double* lq, double* c) {
+                                                      const double* lq, const double* ow, double* c) {
   __shared__ double red[256];
   __shared__ double inv[KMAX];
   const FlowTile T = tiles[blockIdx.x];
@@ -802,7 +802,7 @@ __global__ void __launch_bounds__(256) k_flow_weights(const FlowTile* tiles, int
     }
     if (threadIdx.x == 0) {
       const double tot = red[0];
-      inv[k] = (tot > 0.0 && isfinite(tot)) ? 1.0 / tot : 0.0;
+      inv[k] = (tot > 0.0 && isfinite(tot)) ? ow[k] / tot : 0.0;
     }
     __syncthreads();
   }

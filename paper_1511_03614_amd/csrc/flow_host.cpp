@@ -319,15 +319,27 @@ int sdi_flow_adam(sdi_ctx* ctx, sdi_problem* pb, double lr) {
 // each step draws 2^batch_log2 latent lattice points per sector (training
 // shift rows 65536 + step), maps them through the flow, evaluates the
 // integrand there, and takes one Adam step on the loss weights
-// c_i = sum_k (|f_k|^2 / q^2) / S_k.  The trained sectors become active.
+// c_i = sum_k w_k (|f_k|^2 / q^2) / S_k (w_k: order_weights, 1 when NULL).
+// The trained sectors become active.
 int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_t nsel, int32_t iters,
-                   int32_t batch_log2, double lr, float* ms_out) {
+                   int32_t batch_log2, double lr, const double* order_weights, float* ms_out) {
   if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_train: null argument");
   int rc = flow_ready(ctx, pb);
   if (rc) return rc;
   if (iters < 0 || iters > 100000) return fail(ctx, SDI_EINVAL, "flow_train: iterations out of range");
   if (batch_log2 < 6 || batch_log2 > 20) return fail(ctx, SDI_EINVAL, "flow_train: batch_log2 must be in 6..20");
   if (!(lr > 0.0) || !std::isfinite(lr)) return fail(ctx, SDI_EINVAL, "flow_train: learning rate must be positive");
+  std::vector<double> ow(pb->K, 1.0);
+  if (order_weights) {
+    double tot = 0.0;
+    for (int k = 0; k < pb->K; ++k) {
+      if (!(order_weights[k] >= 0.0) || !std::isfinite(order_weights[k]))
+        return fail(ctx, SDI_EINVAL, "flow_train: order weights must be finite and >= 0");
+      ow[k] = order_weights[k];
+      tot += ow[k];
+    }
+    if (!(tot > 0.0)) return fail(ctx, SDI_EINVAL, "flow_train: order weights are all zero");
+  }
   std::vector<int32_t> sel;
   if (sectors) {
     if (nsel < 0 || nsel > pb->nsec) return fail(ctx, SDI_EINVAL, "flow_train: bad sector count");
@@ -376,9 +388,10 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
   int64_t *d_pre64 = nullptr, *d_pre256 = nullptr;
   uint64_t *d_zp = nullptr, *d_shifts = nullptr;
   double *x = nullptr, *w = nullptr, *lq = nullptr, *f = nullptr, *c = nullptr, *hsave = nullptr;
-  double* d_bc = nullptr;
+  double *d_bc = nullptr, *d_ow = nullptr;
   float* part = nullptr;
   C.add((void**)&d_runs, sizeof(PointRun) * nr);
+  C.add((void**)&d_ow, (size_t)K * 8);
   C.add((void**)&d_pre64, 8 * (nr + 1));
   C.add((void**)&d_pre256, 8 * (nr + 1));
   C.add((void**)&d_zp, zp.size() * 8);
@@ -400,6 +413,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
   HIPCHK(ctx, hipMemcpyAsync(d_pre256, pre256.data(), 8 * (nr + 1), hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(d_zp, zp.data(), zp.size() * 8, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(d_bc, bc.data(), bc.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_ow, ow.data(), (size_t)K * 8, hipMemcpyHostToDevice, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(ctx, hipEventCreate(&e0));
   HIPCHK(ctx, hipEventCreate(&e1));
@@ -445,7 +459,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
         KCHK(ctx, launch_eval_tiles_cplx(km, E, pb->d_cx, pb->d_dir, st));
       else
         KCHK(ctx, launch_eval_tiles_real(km, E, st));
-      KCHK(ctx, launch_flow_weights(d_runs, nr, K, f, lq, c, st));
+      KCHK(ctx, launch_flow_weights(d_runs, nr, K, f, lq, d_ow, c, st));
       const int r2 = flow_gradient(ctx, pb, d_runs, d_pre64, nr, pre64[nr], x, c, hsave, true, part, st);
       if (r2) return r2;
       KCHK(ctx, launch_flow_adam(F.d_params, F.d_grad, F.d_m, F.d_v, F.d_desc, d_runs, nr, F.max_nparam, lr,
@@ -505,14 +519,23 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
 // of sector s stays active when sum_k var_flow(s,k) / S_k < sum_k
 // var_lattice(s,k) / S_k: the sector's contribution to the squared relative
 // errors of the coefficients, summed over the orders, so that the orders with
-// the largest relative error decide; and when, in every order, the two
-// estimates of the sector agree within 5 combined standard errors.  kept
-// (host, [nsectors], may be NULL) receives the flags.
-int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32_t* kept, float* ms_out) {
+// the largest relative error decide (each term times the caller's weight of
+// that order, 1 by default); and when, in every order, the two estimates of
+// the sector agree within 5 combined standard errors.  kept (host,
+// [nsectors], may be NULL) receives the flags.
+int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, const double* order_weights,
+                      int32_t* kept, float* ms_out) {
   if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_validate: null argument");
   int rc = flow_ready(ctx, pb);
   if (rc) return rc;
   if (lattice_log2 < 4 || lattice_log2 > 24) return fail(ctx, SDI_EINVAL, "flow_validate: lattice_log2 in 4..24");
+  std::vector<double> ow(pb->K, 1.0);
+  if (order_weights)
+    for (int k = 0; k < pb->K; ++k) {
+      if (!(order_weights[k] >= 0.0) || !std::isfinite(order_weights[k]))
+        return fail(ctx, SDI_EINVAL, "flow_validate: order weights must be finite and >= 0");
+      ow[k] = order_weights[k];
+    }
   FlowState& F = *pb->flow;
   const Params saved = ctx->params;
   // per sector and order: variance of each pass; mean (re, im) of the lattice and of the flow pass
@@ -582,8 +605,8 @@ int sdi_flow_validate(sdi_ctx* ctx, sdi_problem* pb, int32_t lattice_log2, int32
       double sf = 0.0, sl = 0.0;
       for (int k = 0; k < K; ++k)
         if (V[k] > 0.0) {
-          sf += v[1][(size_t)s * K + k] / V[k];
-          sl += v[0][(size_t)s * K + k] / V[k];
+          sf += ow[k] * v[1][(size_t)s * K + k] / V[k];
+          sl += ow[k] * v[0][(size_t)s * K + k] / V[k];
         }
       // the two passes estimate the same integral: a flow whose estimate sits
       // more than 5 combined standard errors from the lattice's in some order

@@ -67,8 +67,8 @@ int launch_flow_sample_tiles(const FlowTileArgs& a, int nvmax, hipStream_t st);
 int launch_flow_grad(const FlowGradArgs& a, int nvmax, hipStream_t st);
 int launch_flow_chunk_reduce(const FlowSecDesc* fs, const FlowTile* runs, const int64_t* chunk_prefix, int nruns,
                              const float* part, int64_t stride, int64_t max_nparam, float* grad, hipStream_t st);
-int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* f, const double* lq, double* c,
-                        hipStream_t st);
+int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* f, const double* lq, const double* ow,
+                        double* c, hipStream_t st);
 int launch_flow_shifts(const FlowSecDesc* fs, const FlowTile* runs, int nruns, int iters, int m, uint64_t seed,
                        uint32_t row0, uint64_t* out, hipStream_t st);
 

@@ -339,3 +339,43 @@ def test_validation_keeps_only_flows_that_help(ctx):
     finally:
         P.sdi_problem_destroy(h)
         set_params(ctx)
+
+
+def test_validation_order_weights(ctx):
+    """With order weights the kept flags follow the weighted criterion, recomputed here
+    from the two passes for weights (1, 0), (0, 1) and (1, 1) on a two-order problem."""
+    secs = [problem_with_dims([3]).sectors[0], problem_with_dims([4]).sectors[0]]
+    prob = sectorgen.Problem(sectors=secs, order_min=0, order_max=1)
+    m, R = 9, 16
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        for weights in ([1.0, 0.0], [0.0, 1.0], [1.0, 1.0]):
+            set_params(ctx, lattice_log2=m, shifts=R, seed=6)
+            P.sdi_flow_init(ctx, h, 5)
+            P.sdi_flow_set_params(ctx, h, 0, random_fp32_params(secs[0].n, 21, scale=0.8))
+            P.sdi_flow_set_params(ctx, h, 1, random_fp32_params(secs[1].n, 22, scale=0.8))
+            passes = []
+            for sampler in (0, 1):
+                set_params(ctx, lattice_log2=m, shifts=R, seed=6, sampler=sampler)
+                P.sdi_integrate(ctx, h)
+                passes.append([P.sdi_sector_results(ctx, h, s, R) for s in range(2)])
+            set_params(ctx, lattice_log2=m, shifts=R, seed=6, sampler=0)
+            kept, _ = P.sdi_flow_validate(ctx, h, m, order_weights=weights)
+            mean = [np.array([passes[p][s][0] for s in range(2)]) for p in (0, 1)]
+            var = [np.array([np.sum(passes[p][s][1] ** 2, axis=1) for s in range(2)]) for p in (0, 1)]
+            S = np.maximum(np.abs(mean[0].sum(axis=0)) ** 2, var[0].sum(axis=0))
+            w = np.array(weights)
+            want = []
+            for s in range(2):
+                better = (w * var[1][s] / S).sum() < (w * var[0][s] / S).sum()
+                agree = bool(np.all(np.abs(mean[1][s] - mean[0][s]) ** 2 <= 25.0 * (var[0][s] + var[1][s])))
+                want.append(bool(better and agree))
+            log(f"weights {weights}: kept {list(kept)}, criterion {want}")
+            assert [bool(k) for k in kept] == want
+        with pytest.raises(ValueError):
+            P.sdi_flow_validate(ctx, h, m, order_weights=[1.0])
+        with pytest.raises(P.SdiError):
+            P.sdi_flow_validate(ctx, h, m, order_weights=[-1.0, 1.0])
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
