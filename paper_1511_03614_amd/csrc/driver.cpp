@@ -288,29 +288,29 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
 }
 
 // Final-pass launch variants the autotuner times, encoded as 10 * points per
-// thread + minimum waves per SIMD (0: the compiler's choice, complex mode).
+// thread + minimum waves per SIMD (1: no constraint).
 std::vector<int> tile_variants(const sdi_problem* pb) {
-  if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{10, 20} : std::vector<int>{10};
+  if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{11, 12, 21} : std::vector<int>{11, 12};
   if (pb->nvmax >= 16) return {14, 23, 24};
   return {14, 23, 24, 42};
 }
 
 // The variant used for a fixed points-per-thread request.
 int default_variant(const sdi_problem* pb, int ppt) {
-  if (pb->complex_mode) return 10 * ppt;
+  if (pb->complex_mode) return 10 * ppt + 1;
   return ppt == 4 ? 42 : 10 * ppt + 4;
 }
 
 int launch_tiles(const sdi_problem* pb, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
                  hipStream_t st) {
-  if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
+  if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, wpe, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
   return launch_tiles_real(pb->nvmax, ppt, wpe, km, grid, shmem, a, st);
 }
 
 int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int wpe, int km, size_t shmem,
                     size_t ntiles) {
   const int nvmax = pb->nvmax;
-  int occ = pb->complex_mode ? tiles_cplx_occupancy(nvmax, mode, ppt, km, shmem)
+  int occ = pb->complex_mode ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, shmem)
                              : tiles_real_occupancy(nvmax, mode, ppt, wpe, km, shmem);
   if (occ < 1) occ = 1;
   const size_t g = (size_t)occ * std::max(ctx->ncu, 1);
@@ -547,7 +547,7 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   if (prm.ppt > 0) {
     variant = default_variant(pb, prm.ppt);
   } else if (prm.tune == 0) {
-    variant = pb->complex_mode ? 10 : 24;
+    variant = pb->complex_mode ? 11 : 24;
   } else {
     rc = autotune_ppt(ctx, pb, *S, st);
     if (rc < 0) return rc;

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "cplx_args.h"
 #include "flow_types.h"
 #include "sdint_internal.h"
 
@@ -39,9 +40,18 @@ int tiles_real_occupancy(int nvmax, int mode, int ppt, int wpe, int km, size_t s
 
 // Complex mode: nvmax 4 or 8; cx is the CplxDev array (tile kernel) or one sector's
 // record (point evaluation); dir the derivative-list directory.
-int launch_tiles_cplx(int nvmax, int ppt, int km, int grid, size_t shmem, const TileArgs& a, const void* cx,
-                      const uint32_t* dir, hipStream_t st);
-int tiles_cplx_occupancy(int nvmax, int mode, int ppt, int km, size_t shmem);
+int launch_tiles_cplx(int nvmax, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
+                      const void* cx, const uint32_t* dir, hipStream_t st);
+int tiles_cplx_occupancy(int nvmax, int mode, int ppt, int wpe, int km, size_t shmem);
+int launch_tiles_cplx_nv4(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, const CplxArgs& X,
+                          hipStream_t st);
+int launch_tiles_cplx_nv6(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, const CplxArgs& X,
+                          hipStream_t st);
+int launch_tiles_cplx_nv8(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, const CplxArgs& X,
+                          hipStream_t st);
+int occupancy_tiles_cplx_nv4(int mode, int ppt, int wpe, int km, size_t shmem);
+int occupancy_tiles_cplx_nv6(int mode, int ppt, int wpe, int km, size_t shmem);
+int occupancy_tiles_cplx_nv8(int mode, int ppt, int wpe, int km, size_t shmem);
 int launch_eval_points_cplx(int km, const EvalArgs& a, const void* cx, const uint32_t* dir, hipStream_t st);
 // Deformation-size test: fail[s] |= 1 << k when some test point of sector s has
 // Im F(z) > 0 at some corner with lam = cand[s * ncand + k] (ncand <= 16).

@@ -1,35 +1,23 @@
-// Instances of the complex-mode (contour-deformed) tile kernel and point evaluator.
+// Dispatch of the complex-mode (contour-deformed) tile kernel over its variable
+// classes, and the complex point evaluators.
 #include "kernels.h"
 #include "tiles_cplx.hpp"
 
 namespace sdi {
 
-int launch_tiles_cplx(int nvmax, int ppt, int km, int grid, size_t shmem, const TileArgs& a, const void* cx,
-                      const uint32_t* dir, hipStream_t st) {
+int launch_tiles_cplx(int nvmax, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
+                      const void* cx, const uint32_t* dir, hipStream_t st) {
   const CplxArgs X{(const CplxDev*)cx, dir};
-  const int mode = a.mode;
-  if (mode == 2) ppt = 1;
-#define SDI_L(M, NV, P, K)                                                             \
-  if (mode == M && nvmax == NV && ppt == P && km == K) {                                \
-    k_tiles_cplx<NV, P, K, M><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a, X);            \
-    return (int)hipGetLastError();                                                     \
-  }
-  SDI_L(0, 4, 1, 4) SDI_L(0, 4, 2, 4) SDI_L(0, 4, 1, 8) SDI_L(0, 4, 2, 8) SDI_L(0, 6, 1, 4) SDI_L(0, 6, 1, 8) SDI_L(0, 8, 1, 4) SDI_L(0, 8, 1, 8) SDI_L(1, 4, 1, 4) SDI_L(1, 4, 2, 4) SDI_L(1, 4, 1, 8) SDI_L(1, 4, 2, 8) SDI_L(1, 6, 1, 4) SDI_L(1, 6, 1, 8) SDI_L(1, 8, 1, 4) SDI_L(1, 8, 1, 8) SDI_L(2, 4, 1, 4) SDI_L(2, 4, 1, 8) SDI_L(2, 6, 1, 4) SDI_L(2, 6, 1, 8) SDI_L(2, 8, 1, 4) SDI_L(2, 8, 1, 8)
-#undef SDI_L
+  if (nvmax <= 4) return launch_tiles_cplx_nv4(ppt, wpe, km, grid, shmem, a, X, st);
+  if (nvmax <= 6) return launch_tiles_cplx_nv6(ppt, wpe, km, grid, shmem, a, X, st);
+  if (nvmax <= 8) return launch_tiles_cplx_nv8(ppt, wpe, km, grid, shmem, a, X, st);
   return (int)hipErrorInvalidValue;
 }
 
-int tiles_cplx_occupancy(int nvmax, int mode, int ppt, int km, size_t shmem) {
-  int nb = 0;
-  if (mode == 2) ppt = 1;
-#define SDI_O(M, NV, P, K)                                                                                      \
-  if (mode == M && nvmax == NV && ppt == P && km == K) {                                                        \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles_cplx<NV, P, K, M>, BLOCK, shmem) != hipSuccess) \
-      return 0;                                                                                                \
-    return nb;                                                                                                 \
-  }
-  SDI_O(0, 4, 1, 4) SDI_O(0, 4, 2, 4) SDI_O(0, 4, 1, 8) SDI_O(0, 4, 2, 8) SDI_O(0, 6, 1, 4) SDI_O(0, 6, 1, 8) SDI_O(0, 8, 1, 4) SDI_O(0, 8, 1, 8) SDI_O(1, 4, 1, 4) SDI_O(1, 4, 2, 4) SDI_O(1, 4, 1, 8) SDI_O(1, 4, 2, 8) SDI_O(1, 6, 1, 4) SDI_O(1, 6, 1, 8) SDI_O(1, 8, 1, 4) SDI_O(1, 8, 1, 8) SDI_O(2, 4, 1, 4) SDI_O(2, 4, 1, 8) SDI_O(2, 6, 1, 4) SDI_O(2, 6, 1, 8) SDI_O(2, 8, 1, 4) SDI_O(2, 8, 1, 8)
-#undef SDI_O
+int tiles_cplx_occupancy(int nvmax, int mode, int ppt, int wpe, int km, size_t shmem) {
+  if (nvmax <= 4) return occupancy_tiles_cplx_nv4(mode, ppt, wpe, km, shmem);
+  if (nvmax <= 6) return occupancy_tiles_cplx_nv6(mode, ppt, wpe, km, shmem);
+  if (nvmax <= 8) return occupancy_tiles_cplx_nv8(mode, ppt, wpe, km, shmem);
   return 0;
 }
 

@@ -2,14 +2,10 @@
 // Same scheduling, partial sums and reductions as the real kernel; each tile
 // also counts the points where Im F(z) > 0 (the TestF check of section 4.6).
 #pragma once
+#include "cplx_args.h"
 #include "eval_cplx.hpp"
 
 namespace sdi {
-
-struct CplxArgs {
-  const CplxDev* cx;        // [nsec] (tile kernel) or the evaluated sector's record
-  const uint32_t* dir;      // derivative-list directory
-};
 
 template <int NV, int PPT, int KM, int MODE>
 __device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs& X, CSec* S,
@@ -86,8 +82,11 @@ __device__ __forceinline__ void wave_dd_reduce(double hi, double lo, double& ohi
   olo = lo;
 }
 
-template <int NVMAX, int PPT, int KM, int MODE>
-__global__ void __launch_bounds__(BLOCK) k_tiles_cplx(TileArgs A, CplxArgs X) {
+// WPE: minimum waves per SIMD the register allocation must allow (1 = no
+// constraint; 2 trades some scratch spills for twice the waves).
+template <int NVMAX, int PPT, int KM, int MODE, int WPE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_tiles_cplx(TileArgs A,
+                                                                                                 CplxArgs X) {
   extern __shared__ double smem[];
   __shared__ int s_tile, s_nonfin, s_pos;
   __shared__ double s_red[BLOCK / 64][KM][4];
