@@ -113,7 +113,7 @@ def test_identity_map_is_exact(ctx):
         P.sdi_problem_destroy(h)
 
 
-@pytest.mark.parametrize("n,npts", [(1, 1000), (2, 4096), (3, 777), (6, 2048)])
+@pytest.mark.parametrize("n,npts", [(1, 1000), (2, 4096), (3, 777), (6, 2048), (9, 1100), (13, 512)])
 def test_flow_sample_matches_oracle(ctx, n, npts):
     prob = problem_with_dims([n])
     h = P.sdi_problem_create(ctx, prob)
@@ -138,7 +138,7 @@ def test_flow_sample_matches_oracle(ctx, n, npts):
         P.sdi_problem_destroy(h)
 
 
-@pytest.mark.parametrize("n,npts", [(1, 300), (2, 1000), (3, 2048), (5, 4096)])
+@pytest.mark.parametrize("n,npts", [(1, 300), (2, 1000), (3, 2048), (5, 4096), (9, 1500)])
 def test_flow_gradient_matches_oracle(ctx, n, npts):
     prob = problem_with_dims([n])
     h = P.sdi_problem_create(ctx, prob)
