@@ -379,3 +379,40 @@ def test_validation_order_weights(ctx):
     finally:
         P.sdi_problem_destroy(h)
         set_params(ctx)
+
+
+def test_learned_double_box_agrees_with_lattice(ctx):
+    """End to end on the Euclidean double box (282 sectors): flows trained for the sectors
+    with the largest errors, validated, then a mixed pass.  Every order agrees with a
+    large lattice pass within 5 combined standard errors, and the eps^0 error at the
+    same points per shift is smaller than the lattice's."""
+    from sectorgen.feynman import double_box_problem
+    prob = double_box_problem(-3.0, -1.0, 0.0, order_max=0)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        set_params(ctx, lattice_log2=16, shifts=16, seed=1)
+        ref = P.sdi_integrate(ctx, h)
+        set_params(ctx, lattice_log2=11, shifts=16, seed=1)
+        pilot = P.sdi_integrate(ctx, h)
+        err = np.array([np.hypot(*P.sdi_sector_results(ctx, h, s, 16)[1][-1]) for s in range(len(prob.sectors))])
+        sel = sorted(int(s) for s in np.argsort(-err)[:16])
+        P.sdi_flow_init(ctx, h, 1)
+        P.sdi_flow_train(ctx, h, 20, 11, 6e-3, sectors=sel)
+        kept, _ = P.sdi_flow_validate(ctx, h, 11)
+        set_params(ctx, lattice_log2=13, shifts=16, seed=1, sampler=1)
+        learned = P.sdi_integrate(ctx, h)
+        set_params(ctx, lattice_log2=13, shifts=16, seed=1, sampler=0)
+        plain = P.sdi_integrate(ctx, h)
+        e_l = np.hypot(learned["err_re"], learned["err_im"])
+        e_r = np.hypot(ref["err_re"], ref["err_im"])
+        log(f"kept {int(kept.sum())}/{len(sel)}; eps^0: learned {learned['value'][-1].real:.5f} +- {e_l[-1]:.2e}, "
+            f"lattice 2^13 +- {np.hypot(plain['err_re'], plain['err_im'])[-1]:.2e}, "
+            f"lattice 2^16 {ref['value'][-1].real:.5f} +- {e_r[-1]:.2e}")
+        assert kept.sum() >= len(sel) // 2
+        for k in range(prob.norders):
+            d = abs(learned["value"][k] - ref["value"][k])
+            assert d <= 5.0 * math.hypot(e_l[k], e_r[k]) + 1e-12, (k, d, e_l[k], e_r[k])
+        assert e_l[-1] < np.hypot(plain["err_re"], plain["err_im"])[-1]
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
