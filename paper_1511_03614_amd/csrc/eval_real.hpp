@@ -138,38 +138,68 @@ __device__ __forceinline__ void make_points(CSec* S, CU64* zp, CU64* sh, const d
 
 // --------------------------------------------------------------- polynomials
 
-// sum_t coef_t prod_j x_j^e_tj over one term list, for PPT points.  The term
-// index is wave-uniform, so coef and the exponent word sit in SGPRs and every
-// exponent bit is a scalar branch; the empty asm keeps the compiler from
-// turning the skipped multiplies into per-lane selects.
+// out += coef prod_j x_j^e_j for one term, PPT points.  The exponent word is
+// wave-uniform (an SGPR), so every exponent bit is a scalar branch; the empty
+// asm keeps the compiler from turning the skipped multiplies into per-lane
+// selects.
+template <int NV, int PPT>
+__device__ __forceinline__ void add_term(double c, uint64_t e, const double (&x)[PPT][NV],
+                                         const double (&x2)[PPT][NV], double (&out)[PPT]) {
+  double m[PPT];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) m[p] = c;
+  // 32-bit halves of the word: one scalar test per bit instead of a 64-bit compare
+  const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const uint32_t w = j < 8 ? elo : ehi;
+    const int sh = 4 * (j & 7);
+    if (w & (1u << sh)) {
+      asm volatile("" ::);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) m[p] *= x[p][j];
+    }
+    if (w & (2u << sh)) {
+      asm volatile("" ::);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) m[p] *= x2[p][j];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) out[p] += m[p];
+}
+
+// sum_t coef_t prod_j x_j^e_tj over one term list, for PPT points, terms in
+// list order.  Terms are read four at a time so that their scalar loads are in
+// flight together (one wait per four terms instead of one per term).
 template <int NV, int PPT>
 __device__ __forceinline__ void poly_real(CTerm* t, uint32_t cnt,
                                           const double (&x)[PPT][NV], const double (&x2)[PPT][NV],
                                           double (&out)[PPT]) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) out[p] = 0.0;
-  for (uint32_t i = 0; i < cnt; ++i) {
-    const double c = t[i].coef;
-    const uint64_t e = t[i].exps;
-    double m[PPT];
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) m[p] = c;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      if (e & (1ull << (4 * j))) {
-        asm volatile("" ::);
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) m[p] *= x[p][j];
-      }
-      if (e & (2ull << (4 * j))) {
-        asm volatile("" ::);
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) m[p] *= x2[p][j];
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) out[p] += m[p];
+  uint32_t i = 0;
+  for (; i + 4 <= cnt; i += 4) {
+    const double c0 = t[i].coef, c1 = t[i + 1].coef, c2 = t[i + 2].coef, c3 = t[i + 3].coef;
+    const uint64_t e0 = t[i].exps, e1 = t[i + 1].exps, e2 = t[i + 2].exps, e3 = t[i + 3].exps;
+    add_term<NV, PPT>(c0, e0, x, x2, out);
+    add_term<NV, PPT>(c1, e1, x, x2, out);
+    add_term<NV, PPT>(c2, e2, x, x2, out);
+    add_term<NV, PPT>(c3, e3, x, x2, out);
   }
+  for (; i < cnt; ++i) add_term<NV, PPT>(t[i].coef, t[i].exps, x, x2, out);
+}
+
+// 1/v for positive normal v: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - v r), each of which squares the relative
+// error; within an ulp or two of the correctly rounded quotient, in half the
+// instructions of an IEEE division.
+__device__ __forceinline__ double fast_rcp(double v) {
+  double r = __builtin_amdgcn_rcp(v);
+  double e = fma(-v, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-v, r, 1.0);
+  return fma(r, e, r);
 }
 
 // Mantissa in [0.5, 1) and binary exponent; non-positive values give NaN so that
@@ -216,10 +246,12 @@ __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
         }
       }
     }
+    // one reciprocal serves both quotients: num/den and mnum/mden
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-      g0[p] = num[p] / den[p];
-      lam[p] = log(mnum[p] / mden[p]) + (double)esum[p] * 0.69314718055994530942;
+      const double inv = fast_rcp(den[p] * mden[p]);
+      g0[p] = num[p] * mden[p] * inv;
+      lam[p] = log(mnum[p] * den[p] * inv) + (double)esum[p] * 0.69314718055994530942;
     }
   } else {
     double lg[PPT];
@@ -286,7 +318,7 @@ __device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms,
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
         lx[p][i] = log(x[p][i < NV ? i : 0]);
-        ix[p][i] = 1.0 / x[p][i < NV ? i : 0];
+        ix[p][i] = fast_rcp(x[p][i < NV ? i : 0]);
       }
     }
   }
@@ -318,7 +350,7 @@ __device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms,
     }
 #pragma unroll
     for (int p = 0; p < PPT; ++p)
-      lrest[p] = log(pn[p] / pd[p]) + (double)es[p] * 0.69314718055994530942;
+      lrest[p] = log(pn[p] * fast_rcp(pd[p])) + (double)es[p] * 0.69314718055994530942;
   } else {
     double la[PPT];
 #pragma unroll
