@@ -46,70 +46,86 @@ __device__ __forceinline__ cd cexp_(cd z) {
   return cd{e * c, e * s};
 }
 
-// Real polynomial with exponent bits x, x^2, x^4 (exponents up to 7).
+// out += coef prod_j x_j^e_j for one term with exponent bits x, x^2, x^4; the
+// bits are tested on 32-bit halves of the wave-uniform word (scalar branches).
+template <int NV, int PPT>
+__device__ __forceinline__ void add_term3(double c, uint64_t e, const double (&x)[PPT][NV],
+                                          const double (&x2)[PPT][NV], const double (&x4)[PPT][NV],
+                                          double (&out)[PPT]) {
+  double m[PPT];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) m[p] = c;
+  const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const uint32_t w = j < 8 ? elo : ehi;
+    const int sh = 4 * (j & 7);
+    if (w & (1u << sh)) {
+      asm volatile("" ::);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) m[p] *= x[p][j];
+    }
+    if (w & (2u << sh)) {
+      asm volatile("" ::);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) m[p] *= x2[p][j];
+    }
+    if (w & (4u << sh)) {
+      asm volatile("" ::);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) m[p] *= x4[p][j];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) out[p] += m[p];
+}
+
+// Real polynomial with exponent bits x, x^2, x^4 (exponents up to 7), terms in
+// list order.
 template <int NV, int PPT>
 __device__ __forceinline__ void poly_real3(CTerm* t, uint32_t cnt, const double (&x)[PPT][NV],
                                            const double (&x2)[PPT][NV], const double (&x4)[PPT][NV],
                                            double (&out)[PPT]) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) out[p] = 0.0;
-  for (uint32_t i = 0; i < cnt; ++i) {
-    const double c = t[i].coef;
-    const uint64_t e = t[i].exps;
-    double m[PPT];
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) m[p] = c;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      if (e & (1ull << (4 * j))) {
-        asm volatile("" ::);
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) m[p] *= x[p][j];
-      }
-      if (e & (2ull << (4 * j))) {
-        asm volatile("" ::);
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) m[p] *= x2[p][j];
-      }
-      if (e & (4ull << (4 * j))) {
-        asm volatile("" ::);
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) m[p] *= x4[p][j];
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) out[p] += m[p];
-  }
+  for (uint32_t i = 0; i < cnt; ++i) add_term3<NV, PPT>(t[i].coef, t[i].exps, x, x2, x4, out);
 }
 
-// Polynomial with real coefficients at complex points (exponents up to 3).
+// out += coef prod_j z_j^e_j for one term at complex points (exponents up to 3).
+template <int NV, int PPT>
+__device__ __forceinline__ void add_term_c(double c, uint64_t e, const cd (&z)[PPT][NV], const cd (&z2)[PPT][NV],
+                                           cd (&out)[PPT]) {
+  cd m[PPT];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) m[p] = cd{c, 0.0};
+  const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const uint32_t w = j < 8 ? elo : ehi;
+    const int sh = 4 * (j & 7);
+    if (w & (1u << sh)) {
+      asm volatile("" ::);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) m[p] = cmul(m[p], z[p][j]);
+    }
+    if (w & (2u << sh)) {
+      asm volatile("" ::);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) m[p] = cmul(m[p], z2[p][j]);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) out[p] = cadd(out[p], m[p]);
+}
+
+// Polynomial with real coefficients at complex points (exponents up to 3),
+// terms in list order.
 template <int NV, int PPT>
 __device__ __forceinline__ void poly_cplx(CTerm* t, uint32_t cnt, const cd (&z)[PPT][NV],
                                           const cd (&z2)[PPT][NV], cd (&out)[PPT]) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) out[p] = cd{0.0, 0.0};
-  for (uint32_t i = 0; i < cnt; ++i) {
-    const double c = t[i].coef;
-    const uint64_t e = t[i].exps;
-    cd m[PPT];
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) m[p] = cd{c, 0.0};
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      if (e & (1ull << (4 * j))) {
-        asm volatile("" ::);
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) m[p] = cmul(m[p], z[p][j]);
-      }
-      if (e & (2ull << (4 * j))) {
-        asm volatile("" ::);
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) m[p] = cmul(m[p], z2[p][j]);
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) out[p] = cadd(out[p], m[p]);
-  }
+  for (uint32_t i = 0; i < cnt; ++i) add_term_c<NV, PPT>(t[i].coef, t[i].exps, z, z2, out);
 }
 
 // f_kk of one sector at PPT points, complex mode.  imf counts points whose F(z)
