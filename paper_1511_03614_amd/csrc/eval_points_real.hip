@@ -38,13 +38,16 @@ int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st) {
   return (int)hipGetLastError();
 }
 
-int launch_eval_tiles_real(int km, const EvalTilesArgs& a, hipStream_t st) {
+int launch_eval_tiles_real(int km, int nvmax, const EvalTilesArgs& a, hipStream_t st) {
   if (a.nchunks <= 0) return 0;
-  const unsigned g = (unsigned)(a.nchunks < (1 << 20) ? a.nchunks : (1 << 20));
-  if (km == 4)
-    k_eval_tiles_real<4><<<dim3(g), dim3(BLOCK), 0, st>>>(a);
-  else
-    k_eval_tiles_real<8><<<dim3(g), dim3(BLOCK), 0, st>>>(a);
+  const dim3 g((unsigned)(a.nchunks < (1 << 20) ? a.nchunks : (1 << 20))), b(BLOCK);
+#define SDI_E(K, NV) k_eval_tiles_real<K, NV><<<g, b, 0, st>>>(a)
+  if (km == 4) {
+    if (nvmax <= 4) SDI_E(4, 4); else if (nvmax <= 6) SDI_E(4, 6); else if (nvmax <= 8) SDI_E(4, 8); else SDI_E(4, 16);
+  } else {
+    if (nvmax <= 4) SDI_E(8, 4); else if (nvmax <= 6) SDI_E(8, 6); else if (nvmax <= 8) SDI_E(8, 8); else SDI_E(8, 16);
+  }
+#undef SDI_E
   return (int)hipGetLastError();
 }
 

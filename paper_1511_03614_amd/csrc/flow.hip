@@ -60,15 +60,24 @@ int launch_flow_sample_tiles(const FlowTileArgs& a, int nvmax, hipStream_t st) {
   return (int)hipGetLastError();
 }
 
-int launch_flow_grad(const FlowGradArgs& a, int nvmax, hipStream_t st) {
+int launch_flow_grad(const FlowGradArgs& a, int nvmax, int ncu, hipStream_t st) {
   if (a.nchunks <= 0) return 0;
   const dim3 grid(clamp_grid(a.nchunks, 1 << 22)), block(64);
-  if (nvmax <= 4)
-    k_flow_grad<4><<<grid, block, 0, st>>>(a);
-  else if (nvmax <= 8)
-    k_flow_grad<8><<<grid, block, 0, st>>>(a);
-  else
-    k_flow_grad<16><<<grid, block, 0, st>>>(a);
+  // fewer chunks than 2 waves per SIMD: latency decides, take the spill-free instance
+  const bool wide = a.nchunks > 8 * (int64_t)(ncu > 0 ? ncu : 256);
+#define SDI_G(NV)                                                  \
+  if (wide)                                                        \
+    k_flow_grad<NV, 2><<<grid, block, 0, st>>>(a);                 \
+  else                                                             \
+    k_flow_grad<NV, 1><<<grid, block, 0, st>>>(a);
+  if (nvmax <= 4) {
+    SDI_G(4)
+  } else if (nvmax <= 8) {
+    SDI_G(8)
+  } else {
+    SDI_G(16)
+  }
+#undef SDI_G
   return (int)hipGetLastError();
 }
 

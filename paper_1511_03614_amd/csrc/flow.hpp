@@ -561,8 +561,11 @@ __device__ __forceinline__ f32x4_t smp_rowsum(const bfv4_t (&gT)[4], bfv8_t ones
 // layer's input), then back through the layers; writes the chunk's gradient of
 // -sum_i c_i log q(x_i) (every parameter of the sector's flow) to its row of
 // `part`.  Padding samples of a partial chunk carry c = 0 and contribute zero.
-template <int NV>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_flow_grad(FlowGradArgs A) {
+// WPE = 1: all 512 registers per lane, no scratch (for batches with fewer
+// chunks than SIMDs, where a wave's latency is the step's); WPE = 2: two waves
+// per SIMD with some spills (large batches).
+template <int NV, int WPE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) k_flow_grad(FlowGradArgs A) {
   __shared__ __attribute__((aligned(16))) FlowGradLds<NV> L;
   const int lane = threadIdx.x;
   const int r = lane & 15, g = lane >> 4;

@@ -117,7 +117,7 @@ int flow_gradient(sdi_ctx* ctx, sdi_problem* pb, const PointRun* d_runs, const i
   A.inputs_saved = inputs_saved ? 1 : 0;
   A.part = part;
   A.part_stride = F.max_nparam;
-  KCHK(ctx, launch_flow_grad(A, pb->nvmax, st));
+  KCHK(ctx, launch_flow_grad(A, pb->nvmax, ctx->ncu, st));
   KCHK(ctx, launch_flow_chunk_reduce(F.d_desc, d_runs, d_chunk_prefix, nruns, part, F.max_nparam, F.max_nparam,
                                      F.d_grad, st));
   return SDI_OK;
@@ -458,7 +458,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
       if (pb->complex_mode)
         KCHK(ctx, launch_eval_tiles_cplx(km, E, pb->d_cx, pb->d_dir, st));
       else
-        KCHK(ctx, launch_eval_tiles_real(km, E, st));
+        KCHK(ctx, launch_eval_tiles_real(km, pb->nvmax, E, st));
       KCHK(ctx, launch_flow_weights(d_runs, nr, K, f, lq, d_ow, c, st));
       const int r2 = flow_gradient(ctx, pb, d_runs, d_pre64, nr, pre64[nr], x, c, hsave, true, part, st);
       if (r2) return r2;

@@ -60,7 +60,7 @@ int launch_lambda_test(int nvmax, const SecDev* secs, int nsec, const void* cx, 
                        const double* cand, int ncand, int32_t* fail, hipStream_t st);
 
 // Explicit points of several sectors (training batches).
-int launch_eval_tiles_real(int km, const EvalTilesArgs& a, hipStream_t st);
+int launch_eval_tiles_real(int km, int nvmax, const EvalTilesArgs& a, hipStream_t st);
 int launch_eval_tiles_cplx(int km, const EvalTilesArgs& a, const void* cx, const uint32_t* dir, hipStream_t st);
 
 // Learned sampler (coupling flow).
@@ -74,7 +74,7 @@ int launch_flow_adam(float* params, const float* grad, float* m, float* v, const
                      hipStream_t st);
 int launch_flow_sample(const FlowSampleArgs& a, int nvmax, hipStream_t st);
 int launch_flow_sample_tiles(const FlowTileArgs& a, int nvmax, hipStream_t st);
-int launch_flow_grad(const FlowGradArgs& a, int nvmax, hipStream_t st);
+int launch_flow_grad(const FlowGradArgs& a, int nvmax, int ncu, hipStream_t st);
 int launch_flow_chunk_reduce(const FlowSecDesc* fs, const FlowTile* runs, const int64_t* chunk_prefix, int nruns,
                              const float* part, int64_t stride, int64_t max_nparam, float* grad, hipStream_t st);
 int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* f, const double* lq, const double* ow,

@@ -208,8 +208,10 @@ __global__ void __launch_bounds__(BLOCK) k_eval_points_real(EvalArgs A) {
   }
 }
 
-// Values of every result order at the explicit points of several sectors.
-template <int KM>
+// Values of every result order at the explicit points of several sectors;
+// NVMAX: the problem's variable class (the 6-variable class needs fewer
+// registers than the 8-variable one).
+template <int KM, int NVMAX>
 __global__ void __launch_bounds__(BLOCK) k_eval_tiles_real(EvalTilesArgs T) {
   for (int64_t c = blockIdx.x; c < T.nchunks; c += gridDim.x) {
     const int r = find_run(T.chunk_prefix, T.nruns, c);
@@ -224,8 +226,15 @@ __global__ void __launch_bounds__(BLOCK) k_eval_tiles_real(EvalTilesArgs T) {
     A.npts = run.count;
     switch (tape(A.sec)->cls) {
       case 0: eval_point_real<4, KM>(A, i); break;
-      case 1: eval_point_real<8, KM>(A, i); break;
-      case 2: eval_point_real<16, KM>(A, i); break;
+      case 1:
+        if constexpr (NVMAX == 6)
+          eval_point_real<6, KM>(A, i);
+        else if constexpr (NVMAX >= 8)
+          eval_point_real<8, KM>(A, i);
+        break;
+      case 2:
+        if constexpr (NVMAX >= 16) eval_point_real<16, KM>(A, i);
+        break;
       default: break;
     }
   }

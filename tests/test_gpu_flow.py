@@ -194,6 +194,14 @@ def test_adam_step_bit_exact(ctx):
                 g = P.sdi_flow_params(ctx, h, s)
                 o = flatten(params[s]).astype(np.float32)
                 assert np.array_equal(g.view(np.uint32), o.view(np.uint32)), (step, s)
+        # the Adam step leaves the bf16 weight copies current: sampling after it equals
+        # sampling after the copies are rebuilt from the same parameters
+        for s, sec in enumerate(prob.sectors):
+            u = torch.from_numpy(lattice_latent(sec.n, 10, 3)).cuda()
+            x1, lq1 = P.sdi_flow_sample(ctx, h, s, u)
+            P.sdi_flow_set_params(ctx, h, s, P.sdi_flow_params(ctx, h, s))
+            x2, lq2 = P.sdi_flow_sample(ctx, h, s, u)
+            assert torch.equal(x1, x2) and torch.equal(lq1, lq2), s
     finally:
         P.sdi_problem_destroy(h)
 
