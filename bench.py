@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X: 256 CUs x 4 SIMD x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
-WORKLOAD = dict(lattice_log2=16, shifts=16, seed=1, warmup=5, warmup_log2=14, nbins=128, tile_log2=14)
+WORKLOAD = dict(lattice_log2=16, shifts=16, seed=1, warmup=5, warmup_log2=14, nbins=128, tile_log2=0)
 KERNEL_SOURCES = ["paper_1511_03614_amd/csrc/eval_real.hpp", "paper_1511_03614_amd/csrc/tiles_real.hpp",
                   "paper_1511_03614_amd/csrc/sdint_internal.h"]
 
@@ -108,7 +108,7 @@ def traffic_from_profiles(ms_kernel: float):
 
 def _set(P, ctx, **kw):
     base = dict(lattice_log2=12, shifts=16, seed=1, baker=1, warmup=0, graph=1, sampler=0, budget=0, ppt=0,
-                tile_log2=14)
+                tile_log2=0)
     base.update(kw)
     for k, v in base.items():
         P.sdi_set_param(ctx, k, v)
@@ -317,7 +317,7 @@ def main() -> int:
                                "|S| <= 2, orders eps^-2..eps^0; Vegas warm-up 5 x 2^14 points, "
                                "final pass 16 shifts x 2^16 lattice points per sector",
                    "evals_per_step": evals // args.steps, "points_per_thread": r["ppt"],
-                   "blocks": r["blocks"]},
+                   "waves_per_simd": r["waves_per_simd"], "tile_log2": r["tile_log2"], "blocks": r["blocks"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": traffic_from_profiles(ms_k),
                      "kernel": "k_tiles_real (final pass)", "ms_per_launch": ms_k,

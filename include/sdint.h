@@ -72,9 +72,15 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *   warmup         Vegas grid-adaptation iterations             (default 0)
  *   warmup_log2    lattice points per warm-up iteration         (default 14)
  *   nbins          Vegas bins per dimension, power of 2 <= 256  (default 128)
- *   tile_log2      points per work tile                         (default 14)
+ *   tile_log2      points per final-pass work tile: 0 = autotuned among
+ *                  2^10..2^14 (2^14 when tune is off), or 6..24 (default 0)
  *   ppt            points per thread: 0 = autotuned, 1, 2 or 4  (default 0)
- *   tune           off | cached | search                        (default cached)
+ *   tune           off | cached | search: the autotuner times the final-pass
+ *                  kernel on the problem's own tiles for each launch variant
+ *                  and tile size; "cached" reuses a decision for the same
+ *                  device, problem shape and requests (sdi_tune_save/load
+ *                  keep decisions across processes), "search" always times
+ *                                                               (default cached)
  *   graph          1: capture each pass into HIP graphs and replay them (default 1)
  *   budget         total final-pass evaluations distributed over the sectors by
  *                  their pilot-pass errors (Neyman allocation); 0 = every
@@ -87,6 +93,22 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  * Unknown keys or malformed values return SDI_EINVAL. */
 int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value);
 int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len);
+
+/* Autotuner decisions.  Section 2.2 sizes each GPU batch from the device's
+ * multiprocessor count and memory; here the launch variant (points per
+ * thread, waves per SIMD) and the final-pass tile size are instead chosen by
+ * timing the kernel, once per device, problem shape and request, and kept in
+ * ctx.  sdi_tune_save writes every decision of ctx to the file `path` as JSON,
+ * together with the hash of the sources the library was built from
+ * (the device name is part of every entry's key); returns SDI_OK or
+ * SDI_EINVAL if the file cannot be written.  sdi_tune_load reads such a file
+ * into ctx (an entry with the key of an existing one replaces it) and returns
+ * the number of entries loaded: 0 if the file comes from another kernel build,
+ * SDI_EINVAL if it cannot be read or is not in the format sdi_tune_save
+ * writes (ctx is then unchanged).  A loaded decision is used under tune =
+ * cached. */
+int sdi_tune_save(sdi_ctx* ctx, const char* path);
+int sdi_tune_load(sdi_ctx* ctx, const char* path);
 
 /* ------------------------------------------------------------------ problem */
 
@@ -166,6 +188,8 @@ typedef struct {
   double ms_eval_kernel;        /* device time of the final-pass tile kernel alone    */
   int32_t points_per_thread;    /* launch configuration of that kernel                */
   int32_t blocks;
+  int32_t tile_log2;            /* final-pass tile size used (log2 of points)         */
+  int32_t waves_per_simd;       /* minimum waves per SIMD the kernel was built for    */
 } sdi_result;
 
 /* Bytes of device workspace sdi_integrate needs under the current parameters. */

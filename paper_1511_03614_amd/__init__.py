@@ -20,7 +20,7 @@ import numpy as np
 __all__ = [
     "SdiError", "load_library", "library_path", "declared_functions",
     "sdi_ctx_create", "sdi_ctx_destroy", "sdi_last_error", "sdi_device_info",
-    "sdi_set_param", "sdi_get_param", "sdi_prefactor_feynman", "sdi_lattice_vector",
+    "sdi_set_param", "sdi_get_param", "sdi_tune_save", "sdi_tune_load", "sdi_prefactor_feynman", "sdi_lattice_vector",
     "sdi_problem_create", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_workspace_bytes",
     "sdi_integrate", "sdi_sector_results", "sdi_evaluate", "sdi_sample_points",
     "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
@@ -67,7 +67,8 @@ class Result(C.Structure):
                 ("err_re", C.POINTER(C.c_double)), ("err_im", C.POINTER(C.c_double)),
                 ("n_evals", C.c_int64), ("n_nonfinite", C.c_int64), ("n_imf_positive", C.c_int64),
                 ("ms_sample_eval_reduce", C.c_double), ("ms_refit", C.c_double), ("ms_total", C.c_double),
-                ("ms_eval_kernel", C.c_double), ("points_per_thread", C.c_int32), ("blocks", C.c_int32)]
+                ("ms_eval_kernel", C.c_double), ("points_per_thread", C.c_int32), ("blocks", C.c_int32),
+                ("tile_log2", C.c_int32), ("waves_per_simd", C.c_int32)]
 
 
 def library_path() -> str:
@@ -101,6 +102,8 @@ def load_library():
         "sdi_device_info": (C.c_int, [vp, C.c_char_p, C.c_size_t]),
         "sdi_set_param": (C.c_int, [vp, C.c_char_p, C.c_char_p]),
         "sdi_get_param": (C.c_int, [vp, C.c_char_p, C.c_char_p, C.c_size_t]),
+        "sdi_tune_save": (C.c_int, [vp, C.c_char_p]),
+        "sdi_tune_load": (C.c_int, [vp, C.c_char_p]),
         "sdi_prefactor_feynman": (C.c_int, [i32, C.POINTER(i32), i32, i32, i32, C.POINTER(i32), dp]),
         "sdi_lattice_vector": (C.c_int, [i32, i32, C.POINTER(C.c_uint32)]),
         "sdi_problem_create": (C.c_int, [vp, C.POINTER(ProblemDesc), C.POINTER(vp)]),
@@ -180,6 +183,18 @@ def sdi_get_param(ctx, key: str) -> str:
     buf = C.create_string_buffer(64)
     _check(load_library().sdi_get_param(ctx, key.encode(), buf, 64), ctx)
     return buf.value.decode()
+
+
+def sdi_tune_save(ctx, path: str):
+    _check(load_library().sdi_tune_save(ctx, os.fsencode(path)), ctx)
+
+
+def sdi_tune_load(ctx, path: str) -> int:
+    """Number of autotuner decisions loaded (0 for a file of another kernel build)."""
+    rc = load_library().sdi_tune_load(ctx, os.fsencode(path))
+    if rc < 0:
+        _check(rc, ctx)
+    return int(rc)
 
 
 def sdi_prefactor_feynman(loops: int, indices, d0: int, length: int):
@@ -272,7 +287,7 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
     """Run the integrator; `workspace` is an optional torch uint8 cuda tensor."""
     K = sdi_problem_norders(prob)
     arrs = [np.zeros(K) for _ in range(4)]
-    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0)
+    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0)
     ptr, nbytes = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()), workspace.numel())
     if workspace is not None:
         import torch
@@ -282,7 +297,8 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
             "err_re": arrs[2], "err_im": arrs[3], "n_evals": res.n_evals, "n_nonfinite": res.n_nonfinite,
             "n_imf_positive": res.n_imf_positive, "ms_final": res.ms_sample_eval_reduce,
             "ms_warmup": res.ms_refit, "ms_total": res.ms_total, "ms_eval_kernel": res.ms_eval_kernel,
-            "ppt": res.points_per_thread, "blocks": res.blocks}
+            "ppt": res.points_per_thread, "blocks": res.blocks, "tile_log2": res.tile_log2,
+            "waves_per_simd": res.waves_per_simd}
 
 
 def sdi_sector_results(ctx, prob, s: int, nshifts: int):

@@ -24,17 +24,34 @@ SOURCES = ["tiles_real_nv4.hip", "tiles_real_nv6.hip", "tiles_real_nv8.hip", "ti
            "kernels_misc.hip", "flow.hip", "api.cpp", "driver.cpp", "flow_host.cpp", "deform_host.cpp", "lattice_cbc.cpp", "prefactor.cpp"]
 
 
+def kernel_hash() -> str:
+    """FNV-1a 64 over every source of the library, in name order (keys saved autotuner decisions)."""
+    h = 0xCBF29CE484222325
+    for name in sorted(os.listdir(CSRC)):
+        if not name.endswith((".hip", ".hpp", ".h", ".cpp")):
+            continue
+        with open(os.path.join(CSRC, name), "rb") as f:
+            for b in name.encode() + b"\0" + f.read():
+                h = ((h ^ b) * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return f"{h:016x}"
+
+
 def _compile(src: str) -> tuple:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + COMMON + lang + [f'-DSDI_KERNEL_HASH="{_HASH}"', "-c", os.path.join(CSRC, src), "-o", obj]
     t = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     return src, r.returncode, msg, time.time() - t, obj
 
 
+_HASH = ""
+
+
 def build(verbose: bool = True, jobs: int = 0) -> str:
+    global _HASH
+    _HASH = kernel_hash()
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, min(16, os.cpu_count() or 1)))
     objs = []

@@ -120,7 +120,7 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
     if (!range(2, NBMAX) || (iv & (iv - 1))) return fail(ctx, SDI_EINVAL, "nbins must be a power of 2 in 2..256");
     p.nbins = (int)iv;
   } else if (k == "tile_log2") {
-    if (!range(6, 24)) return fail(ctx, SDI_EINVAL, "tile_log2 must be in 6..24");
+    if (!(iv == 0 || range(6, 24))) return fail(ctx, SDI_EINVAL, "tile_log2 must be 0 (autotuned) or in 6..24");
     p.tile_log2 = (int)iv;
   } else if (k == "ppt") {
     if (!(iv == 0 || iv == 1 || iv == 2 || iv == 4)) return fail(ctx, SDI_EINVAL, "ppt must be 0, 1, 2 or 4");

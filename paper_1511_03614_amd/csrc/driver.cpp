@@ -20,6 +20,7 @@ namespace sdi {
 // the device copy of the sector records for this pass, and workspace slots.
 struct Plan {
   int R = 0, rows = 0;
+  int tile_log2 = 14;            // points per final-pass tile (log2; shorter lattices make one tile)
   bool warm = false;
   bool flow = false;             // final points come from the learned sampler
   std::vector<PointRun> fruns;   // per final tile: its points in the flow buffers
@@ -126,9 +127,10 @@ void sector_fields(const Params& prm, const sdi_problem* pb, const std::vector<i
   }
 }
 
-int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& msec, bool warm) {
+int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& msec, bool warm, int tile_log2) {
   const Params& prm = ctx->params;
   P.R = prm.R;
+  P.tile_log2 = tile_log2;
   P.rows = prm.R + prm.warmup;
   P.warm = warm && prm.warmup > 0;
   P.flow = prm.sampler == 1;
@@ -145,7 +147,7 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   P.ftiles.clear();
   for (int s = 0; s < nsec; ++s) {
     const uint32_t N = 1u << msec[s];
-    const uint32_t tsz = std::min<uint32_t>(N, 1u << prm.tile_log2);
+    const uint32_t tsz = std::min<uint32_t>(N, 1u << tile_log2);
     for (int r = 0; r < prm.R; ++r) {
       P.pair_start.push_back((int32_t)P.ftiles.size());
       P.pair_sector.push_back(s);
@@ -194,7 +196,7 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   P.whist_total = P.hsec_total = 0;
   if (P.warm) {
     const uint32_t Nw = 1u << prm.mw;
-    const uint32_t wsz = std::min<uint32_t>(Nw, 1u << std::min(prm.tile_log2, 12));
+    const uint32_t wsz = std::min<uint32_t>(Nw, 1u << std::min(tile_log2, 12));
     for (int s = 0; s < nsec; ++s) {
       const SecDev& S = P.secs[s];
       P.wsec_start.push_back((int32_t)P.wtiles.size());
@@ -299,6 +301,16 @@ std::vector<int> tile_variants(const sdi_problem* pb) {
 int default_variant(const sdi_problem* pb, int ppt) {
   if (pb->complex_mode) return 10 * ppt + 1;
   return ppt == 4 ? 42 : 10 * ppt + 4;
+}
+
+// Whether an encoded variant is one the tuner or a points-per-thread request
+// can select for the problem's class.
+bool variant_known(const sdi_problem* pb, int v) {
+  for (int u : tile_variants(pb))
+    if (u == v) return true;
+  for (int p : {1, 2, 4})
+    if (default_variant(pb, p) == v) return true;
+  return false;
 }
 
 int launch_tiles(const sdi_problem* pb, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
@@ -419,96 +431,44 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
   return SDI_OK;
 }
 
-// Times the final-pass tile kernel for each launch variant (points per thread x
-// minimum waves per SIMD) on the problem's own tiles and keeps the fastest
-// (cached per device, class and problem shape); returns the encoded variant.
-int autotune_ppt(sdi_ctx* ctx, sdi_problem* pb, PassState& S, hipStream_t st) {
-  const Params& prm = ctx->params;
-  Plan& P = S.P;
-  char keyb[320];
-  snprintf(keyb, sizeof keyb, "%s|c%d|nv%d|km%d|sec%d|terms%zu|tiles%zu|t%d|grid%d", ctx->prop.gcnArchName,
-           pb->complex_mode, pb->nvmax, S.km, pb->nsec, pb->terms.size(), P.ftiles.size(), prm.tile_log2,
-           prm.warmup > 0);
-  const std::string key(keyb);
-  if (prm.tune == 1)
-    for (auto& kv : ctx->tune_cache)
-      if (kv.first == key) return kv.second;
-  KCHK(ctx, launch_shifts(P.d_secs, pb->nsec, P.rows, prm.R, prm.seed, 0u, P.d_shifts, st));
-  if (prm.warmup > 0 && !pb->grid_valid) KCHK(ctx, launch_grid_identity(P.d_secs, pb->nsec, pb->d_grids, st));
-  const TileArgs F = final_args(pb, P);
-  if (F.ntiles == 0) return default_variant(pb, 1);
-  int best = default_variant(pb, 1);
-  float best_ms = 1e30f;
-  for (int v : tile_variants(pb)) {
-    const int ppt = v / 10, wpe = v % 10;
-    const int g = persistent_grid(ctx, pb, 0, ppt, wpe, S.km, P.shmem_final, P.forder.size());
-    float ms = 0.f;
-    for (int rep = 0; rep < 2; ++rep) {
-      KCHK(ctx, launch_fill_i32(F.counter, 0, 1, st));
-      HIPCHK(ctx, hipEventRecord(S.ev[1], st));
-      KCHK(ctx, launch_tiles(pb, ppt, wpe, S.km, g, P.shmem_final, F, st));
-      HIPCHK(ctx, hipEventRecord(S.ev[2], st));
-      HIPCHK(ctx, hipEventSynchronize(S.ev[2]));
-      HIPCHK(ctx, hipEventElapsedTime(&ms, S.ev[1], S.ev[2]));
-    }
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = v;
-    }
-  }
-  ctx->tune_cache.push_back({key, best});
-  return best;
+// Final-pass tile sizes (log2) to consider: the requested one, or under
+// tile_log2 = 0 every size from 2^10 to 2^14 points that is not longer than
+// the longest lattice (a tile never exceeds its sector's lattice, so larger
+// sizes would repeat a plan), largest first.  Without tuning the automatic
+// size is 2^14.
+std::vector<int> tile_candidates(const Params& prm, const std::vector<int>& msec) {
+  if (prm.tile_log2 > 0) return {prm.tile_log2};
+  if (prm.tune == 0) return {14};
+  int mmax = 4;
+  for (int m : msec) mmax = std::max(mmax, m);
+  const int hi = std::min(14, mmax), lo = std::min(10, hi);
+  std::vector<int> v;
+  for (int t = hi; t >= lo; --t) v.push_back(t);
+  return v;
 }
 
-// The cached pass for (parameters, per-sector lattice sizes, warm-up flag,
-// workspace), built, uploaded, tuned and captured on first use.
-int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool warm, void* dev_ws, size_t ws_bytes,
-             PassState** out) {
+// Builds the plan for one tile size on dev_ws (or on the pass's own
+// allocation), uploads it and waits for the copies.
+int setup_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, const std::vector<int>& msec, bool warm, int tile_log2,
+               void* dev_ws, size_t ws_bytes) {
   const Params& prm = ctx->params;
-  const std::string key = pass_key(prm, msec, warm, dev_ws, ws_bytes);
-  for (size_t i = 0; i < pb->passes.size(); ++i)
-    if (pb->passes[i]->key == key) {
-      *out = pb->passes[i];
-      return SDI_OK;
-    }
-  PassState* S = new PassState();
-  int rc = make_plan(ctx, pb, S->P, msec, warm);
-  if (rc != SDI_OK) {
-    delete S;
-    return rc;
-  }
-  Plan& P = S->P;
+  int rc = make_plan(ctx, pb, S.P, msec, warm, tile_log2);
+  if (rc != SDI_OK) return rc;
+  Plan& P = S.P;
   const size_t need = P.carve.total();
   void* base = dev_ws;
   if (base) {
-    if (ws_bytes < need) {
-      delete S;
-      return fail(ctx, SDI_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-    }
+    if (ws_bytes < need) return fail(ctx, SDI_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
   } else {
-    if (hipMalloc(&S->own_ws, need) != hipSuccess) {
-      delete S;
+    if (hipMalloc(&S.own_ws, need) != hipSuccess) {
+      S.own_ws = nullptr;
+      (void)hipGetLastError();
       return fail(ctx, SDI_ENOMEM, "workspace allocation failed");
     }
-    base = S->own_ws;
+    base = S.own_ws;
   }
   P.carve.assign(base);
-  // keep at most four plans; plans on a caller workspace share it, so keep only the newest of those
-  if (dev_ws) {
-    for (size_t i = 0; i < pb->passes.size();)
-      if (!pb->passes[i]->own_ws) {
-        delete pb->passes[i];
-        pb->passes.erase(pb->passes.begin() + i);
-      } else {
-        ++i;
-      }
-  }
-  if (pb->passes.size() >= 4) {
-    delete pb->passes.front();
-    pb->passes.erase(pb->passes.begin());
-  }
-  pb->passes.push_back(S);
-  for (auto& e : S->ev) HIPCHK(ctx, hipEventCreate(&e));
+  for (auto& e : S.ev) HIPCHK(ctx, hipEventCreate(&e));
   hipStream_t st = ctx->stream;
   const int nsec = pb->nsec;
   const int npairs = (int)P.pair_sector.size();
@@ -542,19 +502,149 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
     HIPCHK(ctx, hipMemcpyAsync(P.d_hsec_prefix, P.hsec_prefix.data(), nsec * 8, hipMemcpyHostToDevice, st));
   }
   HIPCHK(ctx, hipStreamSynchronize(st));
-  S->km = pb->kfmax <= 4 ? 4 : 8;
-  int variant;
-  if (prm.ppt > 0) {
-    variant = default_variant(pb, prm.ppt);
-  } else if (prm.tune == 0) {
-    variant = pb->complex_mode ? 11 : 24;
-  } else {
-    rc = autotune_ppt(ctx, pb, *S, st);
-    if (rc < 0) return rc;
-    variant = rc;
+  S.km = pb->kfmax <= 4 ? 4 : 8;
+  return SDI_OK;
+}
+
+// Device time of one final-pass tile launch of an encoded variant on S's
+// lattice tiles (the second of two launches; the first warms caches and code).
+int time_final(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int variant, float* ms_out) {
+  const Params& prm = ctx->params;
+  hipStream_t st = ctx->stream;
+  Plan& P = S.P;
+  KCHK(ctx, launch_shifts(P.d_secs, pb->nsec, P.rows, prm.R, prm.seed, 0u, P.d_shifts, st));
+  if (prm.warmup > 0 && !pb->grid_valid) KCHK(ctx, launch_grid_identity(P.d_secs, pb->nsec, pb->d_grids, st));
+  const TileArgs F = final_args(pb, P);
+  const int ppt = variant / 10, wpe = variant % 10;
+  const int g = persistent_grid(ctx, pb, 0, ppt, wpe, S.km, P.shmem_final, P.forder.size());
+  float ms = 0.f;
+  for (int rep = 0; rep < 2; ++rep) {
+    KCHK(ctx, launch_fill_i32(F.counter, 0, 1, st));
+    HIPCHK(ctx, hipEventRecord(S.ev[1], st));
+    KCHK(ctx, launch_tiles(pb, ppt, wpe, S.km, g, P.shmem_final, F, st));
+    HIPCHK(ctx, hipEventRecord(S.ev[2], st));
+    HIPCHK(ctx, hipEventSynchronize(S.ev[2]));
+    HIPCHK(ctx, hipEventElapsedTime(&ms, S.ev[1], S.ev[2]));
   }
-  S->ppt = variant / 10;
-  S->wpe = variant % 10;
+  *ms_out = ms;
+  return SDI_OK;
+}
+
+// Everything the tuned launch depends on: device, kernel build, problem class
+// and shape, per-sector lattice sizes, the tile and points-per-thread requests.
+std::string tune_key(const sdi_ctx* ctx, const sdi_problem* pb, const std::vector<int>& msec, bool warm) {
+  const Params& p = ctx->params;
+  unsigned long long h = 1469598103934665603ull;
+  for (int m : msec) h = (h ^ (unsigned)m) * 1099511628211ull;
+  if (p.sampler == 1 && pb->flow)
+    for (uint8_t a : pb->flow->active) h = (h ^ a) * 1099511628211ull;
+  char buf[320];
+  snprintf(buf, sizeof buf, "%s|c%d|nv%d|kf%d|sec%d|terms%zu|m%llx|R%d|w%d|t%d|p%d|s%d", ctx->prop.gcnArchName,
+           pb->complex_mode, pb->nvmax, pb->kfmax, pb->nsec, pb->terms.size(), h, p.R, (int)(warm && p.warmup > 0),
+           p.tile_log2, p.ppt, p.sampler);
+  return buf;
+}
+
+// The autotuner: times the final-pass tile kernel on the problem's own tiles
+// for every launch variant (points per thread x minimum waves per SIMD) at the
+// largest candidate tile size, then for each smaller tile size with the best
+// variant so far, and keeps the fastest pair.  Results are cached per
+// tune_key (and can be saved and loaded with the kernel build's hash).
+// fixed_variant >= 0 skips the variant search.  With a caller workspace every
+// candidate plan is built on it in turn; a size that does not fit is skipped.
+int autotune(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool warm, const std::vector<int>& tiles,
+             int fixed_variant, void* dev_ws, size_t ws_bytes, TuneChoice& out) {
+  const Params& prm = ctx->params;
+  const std::string key = tune_key(ctx, pb, msec, warm);
+  if (prm.tune == 1)
+    for (const TuneEntry& e : ctx->tune_cache)
+      if (e.key == key && variant_known(pb, e.variant) &&
+          std::find(tiles.begin(), tiles.end(), e.tile_log2) != tiles.end() &&
+          (fixed_variant < 0 || e.variant == fixed_variant)) {
+        out = TuneChoice{e.tile_log2, e.variant};
+        return SDI_OK;
+      }
+  TuneChoice best{tiles.front(), fixed_variant >= 0 ? fixed_variant : default_variant(pb, 1)};
+  float best_ms = 1e30f;
+  for (size_t i = 0; i < tiles.size(); ++i) {
+    PassState C;
+    int rc = setup_pass(ctx, pb, C, msec, warm, tiles[i], dev_ws, ws_bytes);
+    if (rc == SDI_ENOMEM && i > 0) {
+      ctx->err.clear();
+      continue;
+    }
+    if (rc != SDI_OK) return rc;
+    if (C.P.forder.empty()) break;   // no lattice tiles to time
+    const std::vector<int> vs = (i == 0 && fixed_variant < 0) ? tile_variants(pb) : std::vector<int>{best.variant};
+    for (int v : vs) {
+      float ms = 0.f;
+      rc = time_final(ctx, pb, C, v, &ms);
+      if (rc != SDI_OK) return rc;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = TuneChoice{tiles[i], v};
+      }
+    }
+  }
+  bool found = false;
+  for (TuneEntry& e : ctx->tune_cache)
+    if (e.key == key) {
+      e.tile_log2 = best.tile_log2;
+      e.variant = best.variant;
+      found = true;
+    }
+  if (!found) ctx->tune_cache.push_back(TuneEntry{key, best.tile_log2, best.variant});
+  out = best;
+  return SDI_OK;
+}
+
+// The cached pass for (parameters, per-sector lattice sizes, warm-up flag,
+// workspace), tuned, built, uploaded and captured on first use.
+int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool warm, void* dev_ws, size_t ws_bytes,
+             PassState** out) {
+  const Params& prm = ctx->params;
+  const std::string key = pass_key(prm, msec, warm, dev_ws, ws_bytes);
+  for (size_t i = 0; i < pb->passes.size(); ++i)
+    if (pb->passes[i]->key == key) {
+      *out = pb->passes[i];
+      return SDI_OK;
+    }
+  // plans on a caller workspace share it: drop them before anything writes there
+  if (dev_ws) {
+    for (size_t i = 0; i < pb->passes.size();)
+      if (!pb->passes[i]->own_ws) {
+        delete pb->passes[i];
+        pb->passes.erase(pb->passes.begin() + i);
+      } else {
+        ++i;
+      }
+  }
+  const std::vector<int> tiles = tile_candidates(prm, msec);
+  TuneChoice ch{tiles.front(), -1};
+  if (prm.ppt > 0)
+    ch.variant = default_variant(pb, prm.ppt);
+  else if (prm.tune == 0)
+    ch.variant = pb->complex_mode ? 11 : 24;
+  if (ch.variant < 0 || tiles.size() > 1) {
+    const int rc = autotune(ctx, pb, msec, warm, tiles, ch.variant, dev_ws, ws_bytes, ch);
+    if (rc != SDI_OK) return rc;
+  }
+  PassState* S = new PassState();
+  int rc = setup_pass(ctx, pb, *S, msec, warm, ch.tile_log2, dev_ws, ws_bytes);
+  if (rc != SDI_OK) {
+    delete S;
+    return rc;
+  }
+  // keep at most four plans
+  if (pb->passes.size() >= 4) {
+    delete pb->passes.front();
+    pb->passes.erase(pb->passes.begin());
+  }
+  pb->passes.push_back(S);
+  hipStream_t st = ctx->stream;
+  Plan& P = S->P;
+  S->ppt = ch.variant / 10;
+  S->wpe = ch.variant % 10;
   S->gf = persistent_grid(ctx, pb, 0, S->ppt, S->wpe, S->km, P.shmem_final, std::max<size_t>(1, P.forder.size()));
   // explicit (flow) points are read by the one-point-per-thread instances
   S->gx = persistent_grid(ctx, pb, 2, 1, 4, S->km, P.shmem_final, std::max<size_t>(1, P.xorder.size()));
@@ -654,6 +744,49 @@ std::vector<int> neyman_allocation(const sdi_problem* pb, const std::vector<doub
 
 }  // namespace sdi
 
+namespace {
+
+// Minimal reader for the file sdi_tune_save writes: string values hold no
+// quotes or escapes, numbers are small integers.
+struct TuneReader {
+  const std::string& t;
+  size_t p = 0;
+  explicit TuneReader(const std::string& s) : t(s) {}
+  void ws() {
+    while (p < t.size() && (t[p] == ' ' || t[p] == '\n' || t[p] == '\r' || t[p] == '\t')) ++p;
+  }
+  bool lit(char c) {
+    ws();
+    if (p < t.size() && t[p] == c) {
+      ++p;
+      return true;
+    }
+    return false;
+  }
+  bool str(std::string& out) {
+    if (!lit('"')) return false;
+    const size_t q = t.find('"', p);
+    if (q == std::string::npos) return false;
+    out = t.substr(p, q - p);
+    if (out.find('\\') != std::string::npos) return false;
+    p = q + 1;
+    return true;
+  }
+  bool num(int& out) {
+    ws();
+    size_t q = p;
+    if (q < t.size() && t[q] == '-') ++q;
+    const size_t d0 = q;
+    while (q < t.size() && t[q] >= '0' && t[q] <= '9' && q - d0 < 9) ++q;
+    if (q == d0 || (q < t.size() && t[q] >= '0' && t[q] <= '9')) return false;
+    out = std::stoi(t.substr(p, q - p));
+    p = q;
+    return true;
+  }
+};
+
+}  // namespace
+
 using namespace sdi;
 
 extern "C" {
@@ -669,8 +802,14 @@ size_t sdi_workspace_bytes(sdi_ctx* ctx, const sdi_problem* prob) {
   tmp.grid_nbins = prm.nbins;
   // with allocation the largest final pass is every sector at alloc_max
   const int m = prm.budget > 0 ? prm.alloc_max : prm.m;
-  const int rc = make_plan(ctx, &tmp, P, std::vector<int>(prob->nsec, m), prm.budget == 0);
-  return rc == SDI_OK ? P.carve.total() : 0;
+  const std::vector<int> msec(prob->nsec, m);
+  // every tile size the autotuner may try is built on the same workspace
+  size_t need = 0;
+  for (int t : tile_candidates(prm, msec)) {
+    if (make_plan(ctx, &tmp, P, msec, prm.budget == 0, t) != SDI_OK) return 0;
+    need = std::max(need, P.carve.total());
+  }
+  return need;
 }
 
 int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, sdi_result* out) {
@@ -740,6 +879,8 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   out->ms_eval_kernel = o.ms_kernel;
   out->points_per_thread = S->ppt;
   out->blocks = S->gf;
+  out->tile_log2 = S->P.tile_log2;
+  out->waves_per_simd = S->wpe;
   return o.counts[0] ? fail(ctx, SDI_ENONFINITE, "non-finite integrand values") : SDI_OK;
 }
 
@@ -820,6 +961,97 @@ int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, int32_t sh
   if (e != 0) return fail(ctx, SDI_EDEVICE, std::string("sample kernel: ") + hipGetErrorString((hipError_t)e));
   if (hs != hipSuccess) return fail(ctx, SDI_EDEVICE, std::string("sample sync: ") + hipGetErrorString(hs));
   return SDI_OK;
+}
+
+// Autotuner cache as JSON: {"format": ..., "kernel_hash": ..., "entries":
+// [{"key": ..., "tile_log2": t, "points_per_thread": p, "waves_per_simd": w}, ...]}.
+int sdi_tune_save(sdi_ctx* ctx, const char* path) {
+  if (!ctx || !path) return fail(ctx, SDI_EINVAL, "tune_save: null argument");
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(ctx, SDI_EINVAL, std::string("tune_save: cannot open ") + path);
+  fprintf(f, "{\n  \"format\": \"sdint-autotune-1\",\n  \"kernel_hash\": \"%s\",\n  \"entries\": [", SDI_KERNEL_HASH);
+  for (size_t i = 0; i < ctx->tune_cache.size(); ++i) {
+    const TuneEntry& e = ctx->tune_cache[i];
+    fprintf(f, "%s\n    {\"key\": \"%s\", \"tile_log2\": %d, \"points_per_thread\": %d, \"waves_per_simd\": %d}",
+            i ? "," : "", e.key.c_str(), e.tile_log2, e.variant / 10, e.variant % 10);
+  }
+  fprintf(f, "\n  ]\n}\n");
+  const bool ok = !ferror(f);
+  if (fclose(f) != 0 || !ok) return fail(ctx, SDI_EINVAL, std::string("tune_save: write failed on ") + path);
+  return SDI_OK;
+}
+
+int sdi_tune_load(sdi_ctx* ctx, const char* path) {
+  if (!ctx || !path) return fail(ctx, SDI_EINVAL, "tune_load: null argument");
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(ctx, SDI_EINVAL, std::string("tune_load: cannot open ") + path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof buf, f)) > 0 && text.size() < ((size_t)16 << 20)) text.append(buf, got);
+  fclose(f);
+  const std::string bad = std::string("tune_load: malformed file ") + path;
+  TuneReader r(text);
+  std::string k, v, format, hash;
+  std::vector<TuneEntry> entries;
+  if (!r.lit('{')) return fail(ctx, SDI_EINVAL, bad);
+  bool first = true;
+  while (!r.lit('}')) {
+    if (!first && !r.lit(',')) return fail(ctx, SDI_EINVAL, bad);
+    first = false;
+    if (!r.str(k) || !r.lit(':')) return fail(ctx, SDI_EINVAL, bad);
+    if (k == "format" || k == "kernel_hash") {
+      if (!r.str(v)) return fail(ctx, SDI_EINVAL, bad);
+      (k == "format" ? format : hash) = v;
+    } else if (k == "entries") {
+      if (!r.lit('[')) return fail(ctx, SDI_EINVAL, bad);
+      bool efirst = true;
+      while (!r.lit(']')) {
+        if (!efirst && !r.lit(',')) return fail(ctx, SDI_EINVAL, bad);
+        efirst = false;
+        if (!r.lit('{')) return fail(ctx, SDI_EINVAL, bad);
+        TuneEntry e{"", -1, -1};
+        int ppt = -1, wpe = -1;
+        bool ffirst = true;
+        while (!r.lit('}')) {
+          if (!ffirst && !r.lit(',')) return fail(ctx, SDI_EINVAL, bad);
+          ffirst = false;
+          std::string fk;
+          if (!r.str(fk) || !r.lit(':')) return fail(ctx, SDI_EINVAL, bad);
+          bool ok;
+          if (fk == "key") ok = r.str(e.key);
+          else if (fk == "tile_log2") ok = r.num(e.tile_log2);
+          else if (fk == "points_per_thread") ok = r.num(ppt);
+          else if (fk == "waves_per_simd") ok = r.num(wpe);
+          else ok = false;
+          if (!ok) return fail(ctx, SDI_EINVAL, bad);
+        }
+        if (e.key.empty() || e.tile_log2 < 6 || e.tile_log2 > 24 || !(ppt == 1 || ppt == 2 || ppt == 4) ||
+            wpe < 1 || wpe > 9)
+          return fail(ctx, SDI_EINVAL, bad);
+        e.variant = 10 * ppt + wpe;
+        entries.push_back(e);
+      }
+    } else {
+      return fail(ctx, SDI_EINVAL, bad);
+    }
+  }
+  r.ws();
+  if (r.p != text.size() || format != "sdint-autotune-1") return fail(ctx, SDI_EINVAL, bad);
+  // entries of another kernel build are stale: load none of them
+  if (hash != SDI_KERNEL_HASH) return 0;
+  int n = 0;
+  for (const TuneEntry& e : entries) {
+    bool found = false;
+    for (TuneEntry& c : ctx->tune_cache)
+      if (c.key == e.key) {
+        c = e;
+        found = true;
+      }
+    if (!found) ctx->tune_cache.push_back(e);
+    ++n;
+  }
+  return n;
 }
 
 }  // extern "C"

@@ -30,6 +30,12 @@ struct sdi_ctx;
                        std::string(#call) + ": " + hipGetErrorString((hipError_t)e_));          \
   } while (0)
 
+// Hash of the kernel sources this library was built from (set by the build);
+// saved autotuner entries of another build are not loaded.
+#ifndef SDI_KERNEL_HASH
+#define SDI_KERNEL_HASH "unversioned"
+#endif
+
 namespace sdi {
 
 struct Params {
@@ -40,7 +46,7 @@ struct Params {
   int warmup = 0;
   int mw = 14;           // warmup_log2
   int nbins = 128;
-  int tile_log2 = 14;
+  int tile_log2 = 0;     // 0: autotuned (2^14 with tuning off)
   int ppt = 0;           // 0: autotune
   int tune = 1;          // 0 off, 1 cached, 2 search
   int graph = 1;         // capture the pass into a hipGraph and replay it
@@ -49,6 +55,16 @@ struct Params {
   int alloc_max = 20;
   int pilot_log2 = 12;   // lattice log2 of the pilot pass that measures the variances
   int sampler = 0;       // 0: lattice (+ Vegas grid), 1: the learned flow
+};
+
+// One autotuner decision: final-pass tile size and launch variant
+// (10 * points per thread + minimum waves per SIMD).
+struct TuneChoice {
+  int tile_log2, variant;
+};
+struct TuneEntry {
+  std::string key;
+  int tile_log2, variant;
 };
 
 const std::vector<uint32_t>& lattice_vector16(int m);
@@ -109,7 +125,7 @@ struct sdi_ctx {
   sdi::Params params;
   hipDeviceProp_t prop{};
   int ncu = 0;
-  std::vector<std::pair<std::string, int>> tune_cache;   // key -> ppt
+  std::vector<sdi::TuneEntry> tune_cache;
 };
 
 struct sdi_problem {
