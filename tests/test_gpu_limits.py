@@ -1,0 +1,207 @@
+"""Parity at the largest shapes the library accepts, and rejection beyond them.
+
+Real mode: 16 variables, 4 singular variables (16 corners, 81 corner/subset
+pairs), 4 factors with exponents up to 3, 8 orders (eps^-4 .. eps^3, the
+deepest internal series), on the integer-exponent and the general paths.
+Complex mode: 8 variables with 4 singular ones and a sign-changing F.
+Bars as in test_gpu_parity.py."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1511_03614_amd as P  # noqa: E402
+import sectorgen  # noqa: E402
+from sectorgen import Factor, Problem, Sector, SplitMix64  # noqa: E402
+from oracle import integrand, integrate, points  # noqa: E402
+
+from test_gpu_parity import REL_INT, log, set_params  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.sdi_ctx_create(0)
+    yield c
+    P.sdi_ctx_destroy(c)
+
+
+def poly(rng, n, nterms, emax=3, signs=False):
+    exps = {tuple([0] * n)}
+    rows = [tuple([0] * n)]
+    while len(rows) < nterms:
+        e = tuple(rng.randint(0, emax) if rng.uniform() < 0.3 else 0 for _ in range(n))
+        if e not in exps:
+            exps.add(e)
+            rows.append(e)
+    coef = [1.0] + [(0.1 + 0.9 * rng.uniform()) * (-1.0 if signs and rng.uniform() < 0.4 else 1.0)
+                    for _ in rows[1:]]
+    return np.array(coef), np.array(rows, dtype=np.uint8)
+
+
+def max_real_problem():
+    """Three 16-variable sectors with 4 singular variables and 4 factors."""
+    rng = SplitMix64(1601)
+    secs = []
+    for kind in ("integer", "general", "mixed"):
+        n = 16
+        a = np.zeros(n)
+        b = np.array([float(rng.randint(-2, 2)) for _ in range(n)])
+        a[:4] = -1.0
+        b[:4] = [1.0, -2.0, 2.0, -1.0]
+        if kind != "integer":
+            a[4:8] = [0.5, 0.25, 1.0, 2.0]
+            b[4:8] = [0.5, -1.5, 1.0, 0.0]
+        facs = []
+        for fm in range(4):
+            c, e = poly(rng, n, 8 + 6 * fm)
+            if kind == "integer" or (kind == "mixed" and fm % 2 == 0):
+                g, d = float(rng.choice([-3, -2, -1, 1, 2])), float(rng.choice([-2, -1, 1, 2]))
+            else:
+                g, d = rng.choice([-1.5, -0.5, 0.5, 1.25]), rng.choice([-1.0, -0.5, 0.75])
+            facs.append(Factor(g, d, c, e))
+        secs.append(Sector(a=a, b=b, factors=facs, coeff=1.0 + 0.5j * (kind == "mixed")))
+    return Problem(sectors=secs, order_min=-4, order_max=3, name="max16")
+
+
+def max_complex_problem():
+    """Two 8-variable deformed sectors with 4 singular variables."""
+    rng = SplitMix64(802)
+    secs = []
+    for s in range(2):
+        n = 8
+        a = np.zeros(n)
+        b = np.array([float(rng.randint(-2, 2)) for _ in range(n)])
+        a[:4] = -1.0
+        b[:4] = [1.0, -1.0, 2.0, -2.0]
+        cu, eu = poly(rng, n, 10)
+        cf, ef = poly(rng, n, 14, signs=True)
+        cg, eg = poly(rng, n, 6)
+        facs = [Factor(-2.0 + s, 3.0, cu, eu), Factor(-1.0 - s, -2.0, cf, ef), Factor(1.0, 1.0, cg, eg)]
+        secs.append(Sector(a=a, b=b, factors=facs, deform_factor=1, deform_mono=np.zeros(n, np.int32)))
+    return Problem(sectors=secs, order_min=-4, order_max=3, complex_mode=True, lam=0.2, name="max8c")
+
+
+def pointwise(ctx, prob, s, x_np):
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        g = P.sdi_evaluate(ctx, h, s, torch.from_numpy(x_np).cuda()).cpu().numpy()
+    finally:
+        P.sdi_problem_destroy(h)
+    lead, pref = integrate.prefactor_for(prob)
+    args = (True, prob.lam) if prob.complex_mode else ()
+    vals, cond, _ = integrand.sector_orders(prob.sectors[s], x_np, prob.order_min, prob.order_max, lead, pref,
+                                            *args)
+    gv = g[..., 0].T + 1j * g[..., 1].T
+    d = np.abs(gv - vals)
+    strict = d <= 1e-12 * np.abs(vals)
+    # where the subtraction terms cancel by less than 100x, the cond clause is below
+    # the strict one (4e-13 relative), so the strict clause alone must hold there
+    assert strict[cond <= 100 * np.abs(vals)].all()
+    return d <= 1e-12 * np.abs(vals) + 4e-15 * cond, strict
+
+
+@pytest.mark.parametrize("which", ["real16", "complex8"])
+def test_pointwise_at_maximum_shapes(ctx, which):
+    prob = max_real_problem() if which == "real16" else max_complex_problem()
+    assert prob.norders == 8
+    rng = np.random.default_rng(16)
+    set_params(ctx)
+    for s, sec in enumerate(prob.sectors):
+        x = rng.uniform(1e-6, 1.0, size=(1024, sec.n))
+        x[:32] = rng.uniform(1e-8, 1e-3, size=(32, sec.n))
+        ok, strict = pointwise(ctx, prob, s, x)
+        log(f"{which} sector {s}: strict-clause fraction {strict.mean():.4f}")
+        assert ok.all(), f"{which} sector {s}: {np.argwhere(~ok)[:5]}"
+        assert strict.mean() > 0.75
+
+
+def oracle_shift_values_cond(prob, s, m, R, seed):
+    """Per-shift means, mean |wF| and the rounding bound 4e-15 * mean(w * cond) per order."""
+    lead, pref = integrate.prefactor_for(prob)
+    sec = prob.sectors[s]
+    z = points.cbc_vector(m, sec.n)
+    sh = points.shift_table(seed, s, R, sec.n, m)
+    N = 1 << m
+    K = prob.norders
+    q = np.zeros((R, K), dtype=complex)
+    scale = np.zeros(K)
+    bound = np.zeros((R, K))
+    args = (True, prob.lam) if prob.complex_mode else ()
+    for r in range(R):
+        x, w, _ = points.sector_points(z, m, sh[r], 0, N, None, True)
+        vals, cond, _ = integrand.sector_orders(sec, x, prob.order_min, prob.order_max, lead, pref, *args)
+        wf = vals * w[None, :]
+        for k in range(K):
+            q[r, k] = integrate.fsum_c(wf[k]) / N
+            scale[k] = max(scale[k], float(np.mean(np.abs(wf[k]))))
+            bound[r, k] = 4e-15 * float(np.mean(cond[k] * w))
+    return q, scale, bound
+
+
+@pytest.mark.parametrize("which", ["real16", "complex8"])
+def test_integrate_at_maximum_shapes(ctx, which):
+    """Shift means against the oracle at the 1e-10 bar, widened only where the
+    rounding bound of the subtraction sums (the per-point cond clause averaged
+    over the shift) is larger: with 4 singular variables the eps^3 coefficient of
+    a shift can cancel so much that no fp64 evaluation order reaches 1e-10."""
+    prob = max_real_problem() if which == "real16" else max_complex_problem()
+    m, R, seed = 10, 4, 5
+    set_params(ctx, lattice_log2=m, shifts=R, seed=seed, tile_log2=0)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        res = P.sdi_integrate(ctx, h)
+        tot = np.zeros(prob.norders, dtype=complex)
+        scal = np.zeros(prob.norders)
+        btot = np.zeros(prob.norders)
+        widened = 0
+        for s in range(len(prob.sectors)):
+            _, _, per, _ = P.sdi_sector_results(ctx, h, s, R)
+            oq, scale, bound = oracle_shift_values_cond(prob, s, m, R, seed)
+            strict = REL_INT * np.maximum(np.abs(oq), scale[None, :])
+            tol = np.maximum(strict, bound)
+            widened += int((bound > strict).sum())
+            d = np.abs(per - oq)
+            assert (d <= tol).all(), f"{which} sector {s}: max d/tol {np.max(d / tol)}"
+            assert (d[bound <= strict] <= strict[bound <= strict]).all()
+            tot += oq.mean(axis=0)
+            scal += scale
+            btot += bound.mean(axis=0)
+        log(f"{which}: {widened} of {len(prob.sectors) * R * prob.norders} shift means need the rounding bound")
+        assert np.all(np.abs(res["value"] - tot) <= np.maximum(REL_INT * np.maximum(np.abs(tot), scal), btot))
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
+
+
+def test_shapes_beyond_the_limits_are_rejected(ctx):
+    base = max_real_problem().sectors[0]
+
+    def sector(n=16, ns=4, emax=3, nfac=4):
+        a = np.zeros(n)
+        a[:ns] = -1.0
+        b = np.ones(n)
+        e = np.zeros((2, n), dtype=np.uint8)
+        e[1, -1] = emax
+        facs = [Factor(-1.0, 1.0, np.array([1.0, 0.5]), e.copy()) for _ in range(nfac)]
+        return Sector(a=a, b=b, factors=facs)
+
+    cases = {
+        "17 variables": Problem(sectors=[sector(n=17)], order_min=-4, order_max=0),
+        "5 singular variables": Problem(sectors=[sector(ns=5)], order_min=-5, order_max=0),
+        "exponent 4": Problem(sectors=[sector(emax=4)], order_min=-4, order_max=0),
+        "5 factors": Problem(sectors=[sector(nfac=5)], order_min=-4, order_max=0),
+        "9 orders": Problem(sectors=[base], order_min=-4, order_max=4),
+        "complex with 9 variables": Problem(sectors=[Sector(a=np.zeros(9), b=np.zeros(9), factors=[
+            Factor(-1.0, 1.0, np.array([1.0, -0.5]), np.eye(9, dtype=np.uint8)[[8, 0]] * [[0], [1]])],
+            deform_factor=0)], order_min=0, order_max=0, complex_mode=True, lam=0.1),
+    }
+    set_params(ctx)
+    for name, prob in cases.items():
+        with pytest.raises(P.SdiError) as ei:
+            h = P.sdi_problem_create(ctx, prob)
+            P.sdi_problem_destroy(h)
+        assert ei.value.code in (-1, -4), name
