@@ -155,6 +155,26 @@ typedef struct {
  * valid inputs beyond this build (more than SDI_MAX_SINGULAR singular
  * variables, exponents above 3 in real mode or 7 in complex mode). */
 int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* desc, sdi_problem** out);
+
+/* An integrand given as text in the integration workers' input format
+ * (section 4.6, CIntegrate options; the text that follows the Integrate
+ * command, which may be included): a line with the number of variables n
+ * (1..SDI_MAX_VARS), a line with the number of intermediate functions m, m
+ * lines defining f[1] .. f[m], a line with the integrand, every line ended by
+ * ';', then a line '|'.  Expressions use + - * /, round brackets, decimal
+ * numbers, x[1] .. x[n], earlier f[i], p[base,exponent] (real power), l[arg]
+ * (natural logarithm), P (pi), G (Euler's gamma) and the built-in values
+ * PolyGamma[1,1], PolyGamma[2,1..4], PolyGamma[3,1..2].  The result is a
+ * problem of one sector and one order (order 0): sdi_integrate returns the
+ * integral over [0,1]^n with the lattice sampler and optional Vegas warm-up
+ * (not the flow sampler); sdi_evaluate gives the integrand at points (out
+ * [npts][1][2], imaginary part 0); sdi_sample_points works as for sectors.
+ * `text` is a NUL-terminated host string owned by the caller.  Returns
+ * SDI_EINVAL for malformed text (the message names the offset),
+ * SDI_ENOTSUP for PolyGamma arguments that are not built in, integrands of
+ * more than 2^24 operations or ones that need more than 96 live temporaries,
+ * SDI_EDEVICE if the upload fails. */
+int sdi_problem_from_text(sdi_ctx* ctx, const char* text, sdi_problem** out);
 void sdi_problem_destroy(sdi_problem* prob);
 /* Number of result orders K / of sectors of a problem (SDI_EINVAL for NULL). */
 int sdi_problem_norders(const sdi_problem* prob);

@@ -21,7 +21,7 @@ __all__ = [
     "SdiError", "load_library", "library_path", "declared_functions",
     "sdi_ctx_create", "sdi_ctx_destroy", "sdi_last_error", "sdi_device_info",
     "sdi_set_param", "sdi_get_param", "sdi_tune_save", "sdi_tune_load", "sdi_prefactor_feynman", "sdi_lattice_vector",
-    "sdi_problem_create", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_workspace_bytes",
+    "sdi_problem_create", "sdi_problem_from_text", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_workspace_bytes",
     "sdi_integrate", "sdi_sector_results", "sdi_evaluate", "sdi_sample_points",
     "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
     "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_flow_set_active", "sdi_flow_validate",
@@ -107,6 +107,7 @@ def load_library():
         "sdi_prefactor_feynman": (C.c_int, [i32, C.POINTER(i32), i32, i32, i32, C.POINTER(i32), dp]),
         "sdi_lattice_vector": (C.c_int, [i32, i32, C.POINTER(C.c_uint32)]),
         "sdi_problem_create": (C.c_int, [vp, C.POINTER(ProblemDesc), C.POINTER(vp)]),
+        "sdi_problem_from_text": (C.c_int, [vp, C.c_char_p, C.POINTER(vp)]),
         "sdi_problem_destroy": (None, [vp]),
         "sdi_problem_norders": (C.c_int, [vp]),
         "sdi_problem_nsectors": (C.c_int, [vp]),
@@ -256,6 +257,13 @@ def sdi_problem_create(ctx, problem):
                      _dptr(pre), _dptr(pim), int(problem.complex_mode), float(problem.lam))
     h = C.c_void_p()
     _check(load_library().sdi_problem_create(ctx, C.byref(pd), C.byref(h)), ctx)
+    return h
+
+
+def sdi_problem_from_text(ctx, text: str):
+    """Compile an integrand in the workers' text format (one sector, one order)."""
+    h = C.c_void_p()
+    _check(load_library().sdi_problem_from_text(ctx, text.encode(), C.byref(h)), ctx)
     return h
 
 

@@ -452,6 +452,7 @@ void sdi_problem_destroy(sdi_problem* pb) {
   if (pb->d_ws) (void)hipFree(pb->d_ws);
   if (pb->d_cx) (void)hipFree(pb->d_cx);
   if (pb->d_dir) (void)hipFree(pb->d_dir);
+  if (pb->d_expr) (void)hipFree(pb->d_expr);
   delete pb->flow;
   delete pb;
 }
@@ -473,7 +474,10 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_d
   A.x = (const double*)x_dev;
   A.out = (double*)out_dev;
   A.npts = npts;
-  if (pb->complex_mode)
+  if (pb->is_expr())
+    KCHK(ctx, launch_eval_points_expr(A, ExprArgs{pb->d_expr, (int32_t)pb->expr_nins, pb->expr_slots, pb->expr_out},
+                                      ctx->stream));
+  else if (pb->complex_mode)
     KCHK(ctx, launch_eval_points_cplx(pb->kfmax <= 4 ? 4 : 8, A, pb->d_cx + s, pb->d_dir, ctx->stream));
   else
     KCHK(ctx, launch_eval_points_real(pb->kfmax <= 4 ? 4 : 8, A, ctx->stream));

@@ -91,6 +91,11 @@ struct PassState {
   }
 };
 
+// The expression tape of a problem given as text.
+ExprArgs expr_args(const sdi_problem* pb) {
+  return ExprArgs{pb->d_expr, (int32_t)pb->expr_nins, pb->expr_slots, pb->expr_out};
+}
+
 void free_passes(std::vector<PassState*>& v) {
   for (PassState* p : v) delete p;
   v.clear();
@@ -223,6 +228,11 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   P.shmem_warm = (gmax + hmax) * 8;
   if (P.warm && P.shmem_warm > 64 * 1024)
     return fail(ctx, SDI_ENOTSUP, "Vegas grid plus histogram exceed 64 KiB of LDS; lower nbins");
+  if (pb->is_expr()) {
+    const size_t slots = expr_slot_bytes(expr_args(pb));
+    if (std::max(P.shmem_final, P.warm ? P.shmem_warm : 0) + slots > 64 * 1024)
+      return fail(ctx, SDI_ENOTSUP, "expression slots plus Vegas grid exceed 64 KiB of LDS; lower nbins");
+  }
   P.zp_final.assign((size_t)nsec * MAXV, 0);
   for (int s = 0; s < nsec; ++s) {
     const std::vector<uint32_t>& zf = lattice_vector16(msec[s]);
@@ -292,6 +302,7 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
 // Final-pass launch variants the autotuner times, encoded as 10 * points per
 // thread + minimum waves per SIMD (1: no constraint).
 std::vector<int> tile_variants(const sdi_problem* pb) {
+  if (pb->is_expr()) return {11};
   if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{11, 12, 21} : std::vector<int>{11, 12};
   if (pb->nvmax >= 16) return {14, 23, 24};
   return {14, 23, 24, 42};
@@ -299,6 +310,7 @@ std::vector<int> tile_variants(const sdi_problem* pb) {
 
 // The variant used for a fixed points-per-thread request.
 int default_variant(const sdi_problem* pb, int ppt) {
+  if (pb->is_expr()) return 11;   // one point per lane and step
   if (pb->complex_mode) return 10 * ppt + 1;
   return ppt == 4 ? 42 : 10 * ppt + 4;
 }
@@ -315,6 +327,7 @@ bool variant_known(const sdi_problem* pb, int v) {
 
 int launch_tiles(const sdi_problem* pb, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
                  hipStream_t st) {
+  if (pb->is_expr()) return launch_tiles_expr(grid, shmem, a, expr_args(pb), st);
   if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, wpe, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
   return launch_tiles_real(pb->nvmax, ppt, wpe, km, grid, shmem, a, st);
 }
@@ -322,8 +335,9 @@ int launch_tiles(const sdi_problem* pb, int ppt, int wpe, int km, int grid, size
 int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int wpe, int km, size_t shmem,
                     size_t ntiles) {
   const int nvmax = pb->nvmax;
-  int occ = pb->complex_mode ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, shmem)
-                             : tiles_real_occupancy(nvmax, mode, ppt, wpe, km, shmem);
+  int occ = pb->is_expr()      ? tiles_expr_occupancy(mode, shmem, expr_args(pb))
+            : pb->complex_mode ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, shmem)
+                               : tiles_real_occupancy(nvmax, mode, ppt, wpe, km, shmem);
   if (occ < 1) occ = 1;
   const size_t g = (size_t)occ * std::max(ctx->ncu, 1);
   return (int)std::max<size_t>(1, std::min(g, ntiles));
@@ -624,7 +638,7 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   if (prm.ppt > 0)
     ch.variant = default_variant(pb, prm.ppt);
   else if (prm.tune == 0)
-    ch.variant = pb->complex_mode ? 11 : 24;
+    ch.variant = (pb->complex_mode || pb->is_expr()) ? 11 : 24;
   if (ch.variant < 0 || tiles.size() > 1) {
     const int rc = autotune(ctx, pb, msec, warm, tiles, ch.variant, dev_ws, ws_bytes, ch);
     if (rc != SDI_OK) return rc;

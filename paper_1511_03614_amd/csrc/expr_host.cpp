@@ -1,0 +1,534 @@
+// Integrands given as text: the input format of the integration workers
+// (section 4.6): the number of variables, the number of intermediate functions,
+// one line per intermediate function f[1], f[2], ..., then the integrand, each
+// line ended by ';', and a final line '|'.  Expressions use + - * /, brackets,
+// decimal numbers, x[i] (variables), f[i] (earlier intermediate functions),
+// p[base,exponent] (power), l[arg] (natural logarithm), P (pi), G (Euler's
+// gamma) and PolyGamma[m,z] for the handful of arguments the paper lists.
+//
+// The text is parsed into a DAG with shared subexpressions merged and
+// constant subtrees folded, then linearised into an expression tape whose
+// temporaries are assigned to slots by liveness.
+#include <hip/hip_runtime.h>
+
+#include <charconv>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "host.h"
+#include "kernels.h"
+
+namespace sdi {
+namespace {
+
+enum NodeOp : int { N_CONST, N_VAR, N_ADD, N_SUB, N_MUL, N_DIV, N_NEG, N_LOG, N_POWI, N_POW };
+
+struct Node {
+  int op;
+  int a, b;      // operand nodes (-1 if unused); the variable index for N_VAR
+  int k;         // integer exponent (N_POWI)
+  double imm;    // value (N_CONST)
+};
+
+struct ParseError {
+  int code;
+  std::string msg;
+  bool slots = false;   // out of slots: worth a second try without merged operations
+};
+
+// x^k by binary powering of |k|, then one division for k < 0 (the device does the same).
+double powi_host(double x, int k) {
+  unsigned e = k < 0 ? 0u - (unsigned)k : (unsigned)k;
+  double r = 1.0, b = x;
+  while (e) {
+    if (e & 1u) r *= b;
+    e >>= 1;
+    if (e) b *= b;
+  }
+  return k < 0 ? 1.0 / r : r;
+}
+
+class Compiler {
+ public:
+  std::vector<Node> nodes;
+  bool share = true;   // merge repeated operations (leaves are always merged)
+
+  int constant(double v) { return add(Node{N_CONST, -1, -1, 0, v}); }
+  int variable(int j) { return add(Node{N_VAR, j, -1, 0, 0.0}); }
+
+  // Folds constant operands; merges identical nodes.
+  int op2(int op, int a, int b, int k = 0) {
+    const Node& A = nodes[a];
+    const bool ca = A.op == N_CONST;
+    const bool cb = b >= 0 && nodes[b].op == N_CONST;
+    if (ca && (b < 0 || cb)) {
+      const double x = A.imm, y = b >= 0 ? nodes[b].imm : 0.0;
+      double v = 0.0;
+      switch (op) {
+        case N_ADD: v = x + y; break;
+        case N_SUB: v = x - y; break;
+        case N_MUL: v = x * y; break;
+        case N_DIV: v = x / y; break;
+        case N_NEG: v = -x; break;
+        case N_LOG: v = std::log(x); break;
+        case N_POWI: v = powi_host(x, k); break;
+        case N_POW: v = std::pow(x, y); break;
+        default: break;
+      }
+      return constant(v);
+    }
+    return add(Node{op, a, b, k, 0.0});
+  }
+
+ private:
+  struct Key {
+    int op, a, b, k;
+    uint64_t bits;
+    bool operator==(const Key& o) const { return op == o.op && a == o.a && b == o.b && k == o.k && bits == o.bits; }
+  };
+  struct KeyHash {
+    size_t operator()(const Key& q) const {
+      uint64_t h = 1469598103934665603ull;
+      for (uint64_t v : {(uint64_t)q.op, (uint64_t)(uint32_t)q.a, (uint64_t)(uint32_t)q.b, (uint64_t)(uint32_t)q.k, q.bits})
+        h = (h ^ v) * 1099511628211ull;
+      return (size_t)h;
+    }
+  };
+  std::unordered_map<Key, int, KeyHash> seen_;
+
+  int add(const Node& n) {
+    uint64_t bits = 0;
+    std::memcpy(&bits, &n.imm, 8);
+    const Key key{n.op, n.a, n.b, n.k, bits};
+    const bool leaf = n.op == N_CONST || n.op == N_VAR;
+    auto it = (share || leaf) ? seen_.find(key) : seen_.end();
+    if (it != seen_.end()) return it->second;
+    if (nodes.size() >= ((size_t)1 << 24)) throw ParseError{SDI_ENOTSUP, "expression has more than 2^24 operations"};
+    nodes.push_back(n);
+    const int id = (int)nodes.size() - 1;
+    if (share || leaf) seen_.emplace(key, id);
+    return id;
+  }
+};
+
+// Recursive-descent parser of one expression (one line without its ';').
+class Parser {
+ public:
+  Parser(const std::string& text, size_t begin, size_t end, int nvars, const std::vector<int>& fnodes, Compiler& c)
+      : s_(text), p_(begin), end_(end), n_(nvars), f_(fnodes), c_(c) {}
+
+  int parse() {
+    const int v = expr();
+    ws();
+    if (p_ != end_) fail("unexpected '" + std::string(1, s_[p_]) + "'");
+    return v;
+  }
+
+ private:
+  const std::string& s_;
+  size_t p_, end_;
+  int n_;
+  const std::vector<int>& f_;
+  Compiler& c_;
+  int depth_ = 0;
+
+  [[noreturn]] void fail(const std::string& m) const {
+    throw ParseError{SDI_EINVAL, m + " at offset " + std::to_string(p_)};
+  }
+  void ws() {
+    while (p_ < end_ && (s_[p_] == ' ' || s_[p_] == '\t' || s_[p_] == '\n' || s_[p_] == '\r')) ++p_;
+  }
+  bool eat(char ch) {
+    ws();
+    if (p_ < end_ && s_[p_] == ch) {
+      ++p_;
+      return true;
+    }
+    return false;
+  }
+  void expect(char ch) {
+    if (!eat(ch)) fail(std::string("expected '") + ch + "'");
+  }
+  bool word(const char* w) {
+    ws();
+    const size_t L = std::strlen(w);
+    if (p_ + L <= end_ && s_.compare(p_, L, w) == 0) {
+      // a name must not continue with a letter or digit
+      if (p_ + L < end_ && std::isalnum((unsigned char)s_[p_ + L])) return false;
+      p_ += L;
+      return true;
+    }
+    return false;
+  }
+  long integer() {
+    ws();
+    const size_t b = p_;
+    if (p_ < end_ && (s_[p_] == '-' || s_[p_] == '+')) ++p_;
+    while (p_ < end_ && std::isdigit((unsigned char)s_[p_])) ++p_;
+    if (p_ == b || !std::isdigit((unsigned char)s_[p_ - 1])) fail("expected an integer");
+    long v = 0;
+    const auto r = std::from_chars(s_.data() + b + (s_[b] == '+'), s_.data() + p_, v);
+    if (r.ec != std::errc()) fail("integer out of range");
+    return v;
+  }
+  double number() {
+    const size_t b = p_;
+    while (p_ < end_ && std::isdigit((unsigned char)s_[p_])) ++p_;
+    if (p_ < end_ && s_[p_] == '.') {
+      ++p_;
+      while (p_ < end_ && std::isdigit((unsigned char)s_[p_])) ++p_;
+    }
+    if (p_ < end_ && (s_[p_] == 'e' || s_[p_] == 'E')) {
+      size_t q = p_ + 1;
+      if (q < end_ && (s_[q] == '+' || s_[q] == '-')) ++q;
+      if (q < end_ && std::isdigit((unsigned char)s_[q])) {
+        p_ = q;
+        while (p_ < end_ && std::isdigit((unsigned char)s_[p_])) ++p_;
+      }
+    }
+    double v = 0.0;
+    const auto r = std::from_chars(s_.data() + b, s_.data() + p_, v);
+    if (r.ec != std::errc() || r.ptr != s_.data() + p_) fail("malformed number");
+    return v;
+  }
+
+  int expr() {
+    if (++depth_ > 10000) fail("expression nested too deeply");
+    int v = term();
+    for (;;) {
+      if (eat('+')) v = c_.op2(N_ADD, v, term());
+      else if (eat('-')) v = c_.op2(N_SUB, v, term());
+      else break;
+    }
+    --depth_;
+    return v;
+  }
+  int term() {
+    int v = unary();
+    for (;;) {
+      if (eat('*')) v = c_.op2(N_MUL, v, unary());
+      else if (eat('/')) v = c_.op2(N_DIV, v, unary());
+      else break;
+    }
+    return v;
+  }
+  int unary() {
+    if (eat('-')) {
+      if (++depth_ > 10000) fail("expression nested too deeply");
+      const int v = c_.op2(N_NEG, unary(), -1);
+      --depth_;
+      return v;
+    }
+    if (eat('+')) {
+      if (++depth_ > 10000) fail("expression nested too deeply");
+      const int v = unary();
+      --depth_;
+      return v;
+    }
+    return primary();
+  }
+  int primary() {
+    ws();
+    if (p_ >= end_) fail("unexpected end of expression");
+    const char ch = s_[p_];
+    if (std::isdigit((unsigned char)ch) || ch == '.') return c_.constant(number());
+    if (eat('(')) {
+      const int v = expr();
+      expect(')');
+      return v;
+    }
+    if (word("PolyGamma")) {
+      expect('[');
+      const long m = integer();
+      expect(',');
+      const long z = integer();
+      expect(']');
+      return c_.constant(polygamma(m, z));
+    }
+    if (word("x")) {
+      expect('[');
+      const long i = integer();
+      expect(']');
+      if (i < 1 || i > n_) fail("x[" + std::to_string(i) + "] outside x[1] .. x[" + std::to_string(n_) + "]");
+      return c_.variable((int)i - 1);
+    }
+    if (word("f")) {
+      expect('[');
+      const long i = integer();
+      expect(']');
+      if (i < 1 || i > (long)f_.size()) fail("f[" + std::to_string(i) + "] is not an earlier intermediate function");
+      return f_[i - 1];
+    }
+    if (word("p")) {
+      expect('[');
+      const int base = expr();
+      expect(',');
+      const int ex = expr();
+      expect(']');
+      const Node& E = c_.nodes[ex];
+      if (E.op == N_CONST && std::nearbyint(E.imm) == E.imm && std::fabs(E.imm) <= 64.0)
+        return c_.op2(N_POWI, base, -1, (int)E.imm);
+      return c_.op2(N_POW, base, ex);
+    }
+    if (word("l")) {
+      expect('[');
+      const int v = expr();
+      expect(']');
+      return c_.op2(N_LOG, v, -1);
+    }
+    if (word("Pi") || word("P")) return c_.constant(3.14159265358979323846);
+    if (word("EulerGamma") || word("G")) return c_.constant(0.57721566490153286061);
+    fail("unknown symbol");
+  }
+
+  // The polygamma values the paper's workers know without Mathematica, from
+  // psi_1(1) = pi^2/6, psi_2(1) = -2 zeta(3), psi_3(1) = pi^4/15 and the
+  // recurrence psi_m(z+1) = psi_m(z) + (-1)^m m! / z^(m+1), to 22 digits.
+  double polygamma(long m, long z) {
+    if (m == 1 && z == 1) return 1.644934066848226436472;
+    if (m == 2 && z == 1) return -2.404113806319188570799;
+    if (m == 2 && z == 2) return -0.4041138063191885707995;
+    if (m == 2 && z == 3) return -0.1541138063191885707995;
+    if (m == 2 && z == 4) return -0.0800397322451144967254;
+    if (m == 3 && z == 1) return 6.493939402266829149096;
+    if (m == 3 && z == 2) return 0.493939402266829149096;
+    throw ParseError{SDI_ENOTSUP, "PolyGamma[" + std::to_string(m) + "," + std::to_string(z) + "] is not built in"};
+  }
+};
+
+// Splits the text into ';'-terminated statements up to the '|' line.
+std::vector<std::pair<size_t, size_t>> statements(const std::string& t, size_t from) {
+  std::vector<std::pair<size_t, size_t>> out;
+  size_t p = from;
+  for (;;) {
+    while (p < t.size() && std::isspace((unsigned char)t[p])) ++p;
+    if (p >= t.size()) throw ParseError{SDI_EINVAL, "missing the final '|' line"};
+    if (t[p] == '|') {
+      ++p;
+      while (p < t.size() && std::isspace((unsigned char)t[p])) ++p;
+      if (p != t.size()) throw ParseError{SDI_EINVAL, "text after the final '|'"};
+      return out;
+    }
+    const size_t q = t.find(';', p);
+    const size_t bar = t.find('|', p);
+    if (q == std::string::npos || (bar != std::string::npos && bar < q))
+      throw ParseError{SDI_EINVAL, "line without ';' at offset " + std::to_string(p)};
+    out.push_back({p, q});
+    p = q + 1;
+  }
+}
+
+// Parses the intermediate functions and the integrand, then lowers the DAG
+// to a tape: dead nodes dropped, slots assigned by liveness.
+int lower(const std::string& text, const std::vector<std::pair<size_t, size_t>>& st, int n, long m, bool share,
+          std::vector<ExprIns>& tape, int& nslots, int& out) {
+  {
+    Compiler e;
+    e.share = share;
+    for (int j = 0; j < n; ++j) e.variable(j);
+    std::vector<int> fn;
+    for (long i = 0; i < m; ++i) {
+      Parser q(text, st[2 + i].first, st[2 + i].second, n, fn, e);
+      fn.push_back(q.parse());
+    }
+    Parser q(text, st[2 + m].first, st[2 + m].second, n, fn, e);
+    const int root = q.parse();
+
+    // keep what the integrand needs; nodes are already in dependency order
+    const int N = (int)e.nodes.size();
+    std::vector<char> live(N, 0);
+    live[root] = 1;
+    for (int i = N - 1; i >= 0; --i) {
+      if (!live[i]) continue;
+      const Node& d = e.nodes[i];
+      if (d.op == N_VAR || d.op == N_CONST) continue;
+      live[d.a] = 1;
+      if (d.b >= 0) live[d.b] = 1;
+    }
+    std::vector<int> last(N, -1);
+    for (int i = 0; i < N; ++i) {
+      if (!live[i]) continue;
+      const Node& d = e.nodes[i];
+      if (d.op == N_VAR || d.op == N_CONST) continue;
+      last[d.a] = i;
+      if (d.b >= 0) last[d.b] = i;
+    }
+    // Variables stay in slots 0..n-1.  Constants are written right before each
+    // use into a slot that dies with it, so a constant shared by distant parts
+    // of a long integrand does not hold a slot in between.
+    std::vector<int> slot(N, -1);
+    std::vector<int> free_slots;
+    int top = n;
+    tape.clear();
+    auto alloc = [&]() {
+      int sl;
+      if (!free_slots.empty()) {
+        sl = free_slots.back();
+        free_slots.pop_back();
+      } else {
+        sl = top++;
+      }
+      if (sl >= EXPR_MAX_SLOTS)
+        throw ParseError{SDI_ENOTSUP, "the integrand needs more than " + std::to_string(EXPR_MAX_SLOTS) +
+                                          " live temporaries", true};
+      return sl;
+    };
+    auto emit_const = [&](double v) {
+      ExprIns ins{};
+      ins.op = X_CONST;
+      ins.imm = v;
+      ins.dst = (uint8_t)alloc();
+      tape.push_back(ins);
+      return (int)ins.dst;
+    };
+    for (int i = 0; i < N; ++i) {
+      if (!live[i]) continue;
+      const Node& d = e.nodes[i];
+      if (d.op == N_VAR) {
+        slot[i] = d.a;
+        continue;
+      }
+      if (d.op == N_CONST) continue;
+      std::vector<int> temps;
+      auto operand = [&](int o) {
+        if (e.nodes[o].op == N_CONST) {
+          const int sl = emit_const(e.nodes[o].imm);
+          temps.push_back(sl);
+          return sl;
+        }
+        return slot[o];
+      };
+      ExprIns ins{};
+      ins.k = d.k;
+      ins.a = (uint8_t)operand(d.a);
+      ins.b = (uint8_t)(d.b >= 0 ? operand(d.b) : 0);
+      // operands read for the last time free their slots (the device reads both
+      // operands before it writes the destination, so the destination may reuse one)
+      for (int o : {d.a, d.b})
+        if (o >= 0 && last[o] == i && e.nodes[o].op != N_VAR && e.nodes[o].op != N_CONST && slot[o] >= n) {
+          free_slots.push_back(slot[o]);
+          slot[o] = -2;
+        }
+      for (int t : temps) free_slots.push_back(t);
+      const int sdst = alloc();
+      slot[i] = sdst;
+      ins.dst = (uint8_t)sdst;
+      switch (d.op) {
+        case N_ADD: ins.op = X_ADD; break;
+        case N_SUB: ins.op = X_SUB; break;
+        case N_MUL: ins.op = X_MUL; break;
+        case N_DIV: ins.op = X_DIV; break;
+        case N_NEG: ins.op = X_NEG; break;
+        case N_LOG: ins.op = X_LOG; break;
+        case N_POWI: ins.op = X_POWI; break;
+        default: ins.op = X_POW; break;
+      }
+      tape.push_back(ins);
+    }
+    if (e.nodes[root].op == N_CONST) slot[root] = emit_const(e.nodes[root].imm);
+    out = slot[root];
+    nslots = std::max(top, n);
+    return SDI_OK;
+  }
+}
+
+
+}  // namespace
+
+// Compiles the text into a tape; n receives the number of variables.
+int compile_expression(const std::string& text, int& n, std::vector<ExprIns>& tape, int& nslots, int& out,
+                       std::string& err) {
+  try {
+    size_t start = 0;
+    {
+      size_t p = 0;
+      while (p < text.size() && std::isspace((unsigned char)text[p])) ++p;
+      if (text.compare(p, 9, "Integrate") == 0) start = p + 9;
+    }
+    const auto st = statements(text, start);
+    if (st.size() < 3) throw ParseError{SDI_EINVAL, "need the variable count, the function count and the integrand"};
+    Compiler c;
+    std::vector<int> none;
+    auto as_int = [&](size_t i, long lo, long hi, const char* what) {
+      Parser q(text, st[i].first, st[i].second, 0, none, c);
+      const int v = q.parse();
+      const Node& N = c.nodes[v];
+      if (N.op != N_CONST || std::nearbyint(N.imm) != N.imm || N.imm < lo || N.imm > hi)
+        throw ParseError{SDI_EINVAL, std::string(what) + " must be an integer in " + std::to_string(lo) + ".." +
+                                         std::to_string(hi)};
+      return (long)N.imm;
+    };
+    n = (int)as_int(0, 1, MAXV, "the number of variables");
+    const long m = as_int(1, 0, 1 << 20, "the number of intermediate functions");
+    if (st.size() != (size_t)(3 + m))
+      throw ParseError{SDI_EINVAL, "expected " + std::to_string(m) + " intermediate functions and one integrand, found " +
+                                       std::to_string(st.size() - 2) + " lines"};
+    // Merged repeated operations keep their values alive until the last use; if
+    // that needs too many slots, compile again sharing only leaves and f[i].
+    try {
+      return lower(text, st, n, m, true, tape, nslots, out);
+    } catch (const ParseError& pe) {
+      if (!pe.slots) throw;
+    }
+    return lower(text, st, n, m, false, tape, nslots, out);
+  } catch (const ParseError& pe) {
+    err = pe.msg;
+    return pe.code;
+  }
+}
+
+}  // namespace sdi
+
+using namespace sdi;
+
+extern "C" int sdi_problem_from_text(sdi_ctx* ctx, const char* text, sdi_problem** out) {
+  if (!ctx || !text || !out) return fail(ctx, SDI_EINVAL, "problem_from_text: null argument");
+  *out = nullptr;
+  int n = 0, nslots = 0, oslot = 0;
+  std::vector<ExprIns> tape;
+  std::string err;
+  const int rc = compile_expression(std::string(text), n, tape, nslots, oslot, err);
+  if (rc != SDI_OK) return fail(ctx, rc, "problem_from_text: " + err);
+  sdi_problem* pb = new sdi_problem();
+  pb->ctx = ctx;
+  pb->nsec = 1;
+  pb->K = 1;
+  pb->order_min = 0;
+  pb->kfmax = 1;
+  pb->nvmax = 16;
+  pb->expr = tape;
+  pb->expr_slots = nslots;
+  pb->expr_out = oslot;
+  SecDev R{};
+  R.n = n;
+  R.ns = 0;
+  R.nfac = 0;
+  R.kf = 1;
+  R.K = 1;
+  R.nvc = n <= 4 ? 0 : (n <= 8 ? 1 : 2);
+  R.cls = R.nvc;
+  for (int j = 0; j < n; ++j) R.perm[j] = j;
+  R.fold_re[0][0] = 1.0;
+  pb->secs.push_back(R);
+  pb->cost.push_back(1.0 + (double)tape.size());
+  pb->terms.push_back(Term{0.0, 0});
+  if (pb->expr.empty()) pb->expr.push_back(ExprIns{});   // a variable integrand: nothing to execute
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&pb->d_secs, sizeof(SecDev));
+  if (e == hipSuccess) e = hipMalloc((void**)&pb->d_terms, sizeof(Term));
+  if (e == hipSuccess) e = hipMalloc((void**)&pb->d_expr, pb->expr.size() * sizeof(ExprIns));
+  if (e == hipSuccess) e = hipMemcpy(pb->d_secs, pb->secs.data(), sizeof(SecDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(pb->d_terms, pb->terms.data(), sizeof(Term), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(pb->d_expr, pb->expr.data(), pb->expr.size() * sizeof(ExprIns), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    sdi_problem_destroy(pb);
+    return fail(ctx, SDI_EDEVICE, std::string("problem upload: ") + hipGetErrorString(e));
+  }
+  pb->expr_nins = tape.size();
+  *out = pb;
+  return SDI_OK;
+}

@@ -1,0 +1,42 @@
+// Expression tapes: integrands given as text in the integration workers' input
+// format (x[i], f[i], p[base,exponent], l[arg], P, G, + - * / and brackets),
+// compiled on the host into straight-line code over numbered slots.  Shared by
+// the host compiler and the HIP kernels (plain C++).
+//
+// Slots 0 .. n-1 hold the point's coordinates x[1] .. x[n]; every instruction
+// writes one slot from up to two others.  The host allocates the remaining
+// slots by liveness, so a slot is rewritten once its value is dead.
+#pragma once
+#include <stdint.h>
+
+namespace sdi {
+
+enum ExprOp : uint8_t {
+  X_CONST = 0,   // dst = imm
+  X_ADD,         // dst = a + b
+  X_SUB,         // dst = a - b
+  X_MUL,         // dst = a * b
+  X_DIV,         // dst = a / b
+  X_NEG,         // dst = -a
+  X_LOG,         // dst = ln a (NaN for a < 0)
+  X_POWI,        // dst = a^k for the integer k (products, then one reciprocal if k < 0)
+  X_POW,         // dst = a^b, C pow semantics (NaN for a < 0 and non-integer b)
+};
+
+struct alignas(16) ExprIns {
+  uint8_t op, dst, a, b;
+  int32_t k;
+  double imm;
+};
+
+constexpr int EXPR_MAX_SLOTS = 96;   // slots per point (LDS: 512 B each per wave)
+constexpr int EXPR_BLOCK = 64;       // threads per block of the expression kernels (one wave)
+
+struct ExprArgs {
+  const ExprIns* ins;
+  int32_t nins;
+  int32_t nslots;
+  int32_t out;                       // slot holding the integrand value
+};
+
+}  // namespace sdi

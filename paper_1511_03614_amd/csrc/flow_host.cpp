@@ -135,6 +135,7 @@ extern "C" {
 
 int sdi_flow_init(sdi_ctx* ctx, sdi_problem* pb, uint64_t seed) {
   if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_init: null argument");
+  if (pb->is_expr()) return fail(ctx, SDI_ENOTSUP, "flow: not available for integrands given as text");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   (void)hipGetLastError();
   for (int s = 0; s < pb->nsec; ++s)

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/sdint.h"
+#include "expr_types.h"
 #include "flow_types.h"
 #include "sdint_internal.h"
 
@@ -161,4 +162,10 @@ struct sdi_problem {
   uint32_t* d_dir = nullptr;
   // learned sampler (created by sdi_flow_init)
   sdi::FlowState* flow = nullptr;
+  // integrand given as text (sdi_problem_from_text): one sector, one order
+  std::vector<sdi::ExprIns> expr;
+  sdi::ExprIns* d_expr = nullptr;
+  size_t expr_nins = 0;
+  int expr_slots = 0, expr_out = 0;
+  bool is_expr() const { return d_expr != nullptr; }
 };

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cplx_args.h"
+#include "expr_types.h"
 #include "flow_types.h"
 #include "sdint_internal.h"
 
@@ -26,6 +27,14 @@ int launch_hist_reduce(const double* hist, const int64_t* hist_off, const int32_
 int launch_refit(const SecDev* secs, int nsec, const double* hsec, const int64_t* hsec_off, double* grids,
                  double alpha, hipStream_t st);
 int launch_sample_points(const SampleArgs& a, hipStream_t st);
+
+// Integrands given as text: the persistent tile kernel (a.mode 0 final pass, 1
+// warm-up with histograms; blocks of one wave; shmem = grid and histogram
+// bytes, the expression slots are added) and the point evaluator.
+size_t expr_slot_bytes(const ExprArgs& x);
+int launch_tiles_expr(int grid, size_t shmem, const TileArgs& a, const ExprArgs& x, hipStream_t st);
+int tiles_expr_occupancy(int mode, size_t shmem, const ExprArgs& x);
+int launch_eval_points_expr(const EvalArgs& a, const ExprArgs& x, hipStream_t st);
 
 // Tile kernel of variable class nvmax (4, 6, 8 or 16), points per thread ppt and
 // minimum waves per SIMD wpe (final-pass variants (1,4), (2,3), (2,4), (4,2); the
