@@ -252,6 +252,30 @@ def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, sh
         P.sdi_problem_destroy(h)
 
 
+def text_integrand_rate(P, ctx, steps: int = 5):
+    """Throughput of the text path (sdi_problem_from_text) on an integrand of the
+    size class the paper's database holds (~200 KB of text): 3000 signed terms of
+    nested powers, logs and quotients over 6 variables, 8 intermediate functions;
+    16 shifts x 2^14 lattice points per pass."""
+    from sectorgen import textgen
+    text = textgen.random_text(999, 6, nfuncs=8, depth=3, terms=3000)
+    for k, v in dict(lattice_log2=14, shifts=16, seed=1, warmup=0, sampler=0, budget=0, tile_log2=0, ppt=0).items():
+        P.sdi_set_param(ctx, k, v)
+    h = P.sdi_problem_from_text(ctx, text)
+    try:
+        P.sdi_integrate(ctx, h)
+        ms = []
+        for _ in range(steps):
+            r = P.sdi_integrate(ctx, h)
+            ms.append(r["ms_eval_kernel"])
+    finally:
+        P.sdi_problem_destroy(h)
+    ms_k = sorted(ms)[len(ms) // 2]
+    return {"text_bytes": len(text), "vars": 6, "evals_per_pass": int(r["n_evals"]),
+            "ms_kernel_median": ms_k, "evals_per_s": r["n_evals"] / (ms_k * 1e-3),
+            "tile_log2": r["tile_log2"], "blocks": r["blocks"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +351,7 @@ def main() -> int:
                    "value": [float(v.real) for v in r["value"]], "err": [float(e) for e in r["err_re"]]},
     }
     P.sdi_problem_destroy(h)
+    out["text_integrand"] = text_integrand_rate(P, ctx)
     if not args.no_equal_time:
         from sectorgen.feynman import double_box_problem
         lat = [dict(lattice_log2=m) for m in range(10, 17)]

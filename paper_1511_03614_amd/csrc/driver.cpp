@@ -446,16 +446,18 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
 }
 
 // Final-pass tile sizes (log2) to consider: the requested one, or under
-// tile_log2 = 0 every size from 2^10 to 2^14 points that is not longer than
-// the longest lattice (a tile never exceeds its sector's lattice, so larger
-// sizes would repeat a plan), largest first.  Without tuning the automatic
-// size is 2^14.
-std::vector<int> tile_candidates(const Params& prm, const std::vector<int>& msec) {
+// tile_log2 = 0 every size from 2^10 to 2^14 points (2^6 to 2^10 for text
+// integrands, whose blocks are one wave) that is not longer than the longest
+// lattice (a tile never exceeds its sector's lattice, so larger sizes would
+// repeat a plan), largest first.  Without tuning the automatic size is 2^14
+// (2^6 for text integrands: one tile per wave-step keeps every wave busy).
+std::vector<int> tile_candidates(const sdi_problem* pb, const Params& prm, const std::vector<int>& msec) {
   if (prm.tile_log2 > 0) return {prm.tile_log2};
-  if (prm.tune == 0) return {14};
+  const int top = pb->is_expr() ? 10 : 14;
+  if (prm.tune == 0) return {pb->is_expr() ? 6 : 14};
   int mmax = 4;
   for (int m : msec) mmax = std::max(mmax, m);
-  const int hi = std::min(14, mmax), lo = std::min(10, hi);
+  const int hi = std::min(top, mmax), lo = std::min(top - 4, hi);
   std::vector<int> v;
   for (int t = hi; t >= lo; --t) v.push_back(t);
   return v;
@@ -633,7 +635,7 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
         ++i;
       }
   }
-  const std::vector<int> tiles = tile_candidates(prm, msec);
+  const std::vector<int> tiles = tile_candidates(pb, prm, msec);
   TuneChoice ch{tiles.front(), -1};
   if (prm.ppt > 0)
     ch.variant = default_variant(pb, prm.ppt);
@@ -819,7 +821,7 @@ size_t sdi_workspace_bytes(sdi_ctx* ctx, const sdi_problem* prob) {
   const std::vector<int> msec(prob->nsec, m);
   // every tile size the autotuner may try is built on the same workspace
   size_t need = 0;
-  for (int t : tile_candidates(prm, msec)) {
+  for (int t : tile_candidates(prob, prm, msec)) {
     if (make_plan(ctx, &tmp, P, msec, prm.budget == 0, t) != SDI_OK) return 0;
     need = std::max(need, P.carve.total());
   }

@@ -29,25 +29,51 @@ __device__ __forceinline__ double powi_dev(double x, int k) {
   return k < 0 ? 1.0 / r : r;
 }
 
-// Runs the tape for one point per lane; R points at this lane's slot 0.
+// One tape instruction for this lane; R points at the lane's slot 0.
+__device__ __forceinline__ void exec_ins(const ExprIns& I, double* R) {
+  const int a = I.a, b = I.b;
+  double v;
+  switch (I.op) {
+    case X_CONST: v = I.imm; break;
+    case X_ADD: v = R[a * 64] + R[b * 64]; break;
+    case X_SUB: v = R[a * 64] - R[b * 64]; break;
+    case X_MUL: v = R[a * 64] * R[b * 64]; break;
+    case X_DIV: v = R[a * 64] / R[b * 64]; break;
+    case X_NEG: v = -R[a * 64]; break;
+    case X_LOG: v = log(R[a * 64]); break;
+    case X_POWI: v = powi_dev(R[a * 64], I.k); break;
+    case X_POW: v = pow(R[a * 64], R[b * 64]); break;
+    default: v = __builtin_nan(""); break;
+  }
+  R[I.dst * 64] = v;
+}
+
+__device__ __forceinline__ ExprIns load_ins(CIns* p) {
+  ExprIns r;
+  r.op = p->op;
+  r.dst = p->dst;
+  r.a = p->a;
+  r.b = p->b;
+  r.k = p->k;
+  r.imm = p->imm;
+  return r;
+}
+
+// Runs the tape for one point per lane.  Instructions are fetched eight at a
+// time, so their scalar loads are in flight together (a long tape does not fit
+// the scalar cache, and one fetch per instruction would wait on L2 each time).
 __device__ __forceinline__ double run_expr(CIns* ins, int nins, int out, double* R) {
-  for (int i = 0; i < nins; ++i) {
-    const int op = ins[i].op;
-    const int d = ins[i].dst, a = ins[i].a, b = ins[i].b;
-    double v;
-    switch (op) {
-      case X_CONST: v = ins[i].imm; break;
-      case X_ADD: v = R[a * 64] + R[b * 64]; break;
-      case X_SUB: v = R[a * 64] - R[b * 64]; break;
-      case X_MUL: v = R[a * 64] * R[b * 64]; break;
-      case X_DIV: v = R[a * 64] / R[b * 64]; break;
-      case X_NEG: v = -R[a * 64]; break;
-      case X_LOG: v = log(R[a * 64]); break;
-      case X_POWI: v = powi_dev(R[a * 64], ins[i].k); break;
-      case X_POW: v = pow(R[a * 64], R[b * 64]); break;
-      default: v = __builtin_nan(""); break;
-    }
-    R[d * 64] = v;
+  int i = 0;
+  for (; i + 8 <= nins; i += 8) {
+    ExprIns I[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) I[u] = load_ins(ins + i + u);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) exec_ins(I[u], R);
+  }
+  for (; i < nins; ++i) {
+    const ExprIns I = load_ins(ins + i);
+    exec_ins(I, R);
   }
   return R[out * 64];
 }
