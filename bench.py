@@ -283,6 +283,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-log2", type=int, default=16)
+    ap.add_argument("--tune-load", default=None,
+                    help="load autotuner decisions (sdi_tune_load) before the run, so profiles time the same instance")
+    ap.add_argument("--tune-save", default=None, help="save the autotuner decisions of the run (sdi_tune_save)")
     ap.add_argument("--no-equal-time", action="store_true",
                     help="skip the learned-sampler comparison (double box, Euclidean and physical)")
     args = ap.parse_args()
@@ -298,6 +301,8 @@ def main() -> int:
 
     problem = sectorgen.config2()
     ctx = P.sdi_ctx_create(0)
+    if args.tune_load:
+        P.sdi_tune_load(ctx, args.tune_load)
     for k, v in WORKLOAD.items():
         P.sdi_set_param(ctx, k, v)
     h = P.sdi_problem_create(ctx, problem)
@@ -344,13 +349,16 @@ def main() -> int:
                    "waves_per_simd": r["waves_per_simd"], "tile_log2": r["tile_log2"], "blocks": r["blocks"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": traffic_from_profiles(ms_k),
-                     "kernel": "k_tiles_real (final pass)", "ms_per_launch": ms_k,
+                     "kernel": f"k_tiles_real<6, {r['ppt']}, 4, 0, {r['waves_per_simd']}> (final pass)",
+                     "ms_per_launch": ms_k,
                      "flops_per_launch": fl_launch, "logs_per_s": logs_launch / (ms_k * 1e-3)},
         "error_vs_plain_qmc": None,
         "result": {"orders": list(range(problem.order_min, problem.order_max + 1)),
                    "value": [float(v.real) for v in r["value"]], "err": [float(e) for e in r["err_re"]]},
     }
     P.sdi_problem_destroy(h)
+    if args.tune_save:
+        P.sdi_tune_save(ctx, args.tune_save)
     out["text_integrand"] = text_integrand_rate(P, ctx)
     if not args.no_equal_time:
         from sectorgen.feynman import double_box_problem

@@ -233,9 +233,13 @@ int sdi_sector_results(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, double*
 /* Values of every requested order of sector s (prefactor and c_s folded in,
  * no sampling weight) at caller points: the justEvaluate integrator of
  * section 4.4.  x: device [npts][n] doubles in the sector's variable order;
- * out: device [npts][K][2] doubles (re, im).  Stream-ordered; synchronises. */
+ * out: device [npts][K][2] doubles (re, im).  cond: device [npts][K] doubles
+ * or NULL; receives per order the sum of the absolute values of every
+ * subtraction and series term (times |c_s Pi_i| of the fold), the scale of
+ * the rounding error of the value near the faces (0 for text integrands).
+ * Stream-ordered; synchronises. */
 int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, const void* x_dev,
-                 int64_t npts, void* out_dev);
+                 int64_t npts, void* out_dev, void* cond_dev);
 
 /* The exact points and weights the integrator uses for sector s, shift r,
  * lattice indices i0 .. i0+npts-1, under the current grid of that sector:

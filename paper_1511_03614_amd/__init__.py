@@ -114,7 +114,7 @@ def load_library():
         "sdi_workspace_bytes": (C.c_size_t, [vp, vp]),
         "sdi_integrate": (C.c_int, [vp, vp, vp, C.c_size_t, C.POINTER(Result)]),
         "sdi_sector_results": (C.c_int, [vp, vp, i32, dp, dp, dp, C.POINTER(i64)]),
-        "sdi_evaluate": (C.c_int, [vp, vp, i32, vp, i64, vp]),
+        "sdi_evaluate": (C.c_int, [vp, vp, i32, vp, i64, vp, vp]),
         "sdi_sample_points": (C.c_int, [vp, vp, i32, i32, i64, i64, vp, vp]),
         "sdi_tune_deformation": (C.c_int, [vp, vp, C.c_double, i32, i32, i32, dp]),
         "sdi_flow_init": (C.c_int, [vp, vp, C.c_uint64]),
@@ -319,16 +319,19 @@ def sdi_sector_results(ctx, prob, s: int, nshifts: int):
     return mean[:, 0] + 1j * mean[:, 1], err, per[..., 0] + 1j * per[..., 1], int(nev.value)
 
 
-def sdi_evaluate(ctx, prob, s: int, x):
-    """x: torch float64 cuda tensor (npts, n); returns a cuda tensor (npts, K, 2)."""
+def sdi_evaluate(ctx, prob, s: int, x, with_cond: bool = False):
+    """x: torch float64 cuda tensor (npts, n); returns a cuda tensor (npts, K, 2),
+    and with_cond also the per-order sums of |term| (npts, K)."""
     import torch
     K = sdi_problem_norders(prob)
     x = x.contiguous()
     out = torch.empty((x.shape[0], K, 2), dtype=torch.float64, device=x.device)
+    cond = torch.empty((x.shape[0], K), dtype=torch.float64, device=x.device) if with_cond else None
     torch.cuda.current_stream(x.device).synchronize()
     _check(load_library().sdi_evaluate(ctx, prob, s, C.c_void_p(x.data_ptr()), x.shape[0],
-                                       C.c_void_p(out.data_ptr())), ctx)
-    return out
+                                       C.c_void_p(out.data_ptr()),
+                                       C.c_void_p(cond.data_ptr()) if with_cond else None), ctx)
+    return (out, cond) if with_cond else out
 
 
 def sdi_sample_points(ctx, prob, s: int, shift: int, i0: int, npts: int, nvars: int, device=0):

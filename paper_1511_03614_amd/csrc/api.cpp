@@ -461,7 +461,8 @@ int sdi_problem_norders(const sdi_problem* pb) { return pb ? pb->K : SDI_EINVAL;
 
 int sdi_problem_nsectors(const sdi_problem* pb) { return pb ? pb->nsec : SDI_EINVAL; }
 
-int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_dev, int64_t npts, void* out_dev) {
+int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_dev, int64_t npts, void* out_dev,
+                 void* cond_dev) {
   if (!ctx || !pb || (!x_dev && npts > 0) || (!out_dev && npts > 0)) return fail(ctx, SDI_EINVAL, "evaluate: null argument");
   if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");
   if (npts < 0) return fail(ctx, SDI_EINVAL, "negative point count");
@@ -474,6 +475,7 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_d
   A.x = (const double*)x_dev;
   A.out = (double*)out_dev;
   A.npts = npts;
+  A.cond = (double*)cond_dev;
   if (pb->is_expr())
     KCHK(ctx, launch_eval_points_expr(A, ExprArgs{pb->d_expr, (int32_t)pb->expr_nins, pb->expr_slots, pb->expr_out},
                                       ctx->stream));

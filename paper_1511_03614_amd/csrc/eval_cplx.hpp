@@ -130,9 +130,11 @@ __device__ __forceinline__ void poly_cplx(CTerm* t, uint32_t cnt, const cd (&z)[
 
 // f_kk of one sector at PPT points, complex mode.  imf counts points whose F(z)
 // has a positive imaginary part at some corner.
-template <int NV, int PPT, int KM>
-__device__ __forceinline__ void eval_f_cplx(CSec* S, const SDI_TAPE CplxDev* X, CU32* dir, CTerm* terms,
-                                            const double (&x)[PPT][NV], cd (&f)[PPT][KM], int (&imf)[PPT]) {
+// COND: also the sums of |term| per order (cnd), for the evaluate hook.
+template <int NV, int PPT, int KM, bool COND>
+__device__ __forceinline__ void eval_f_cplx_c(CSec* S, const SDI_TAPE CplxDev* X, CU32* dir, CTerm* terms,
+                                              const double (&x)[PPT][NV], cd (&f)[PPT][KM], int (&imf)[PPT],
+                                              double (&cnd)[PPT][KM]) {
   constexpr int NT = NV * (NV + 1) / 2;
   const int n = S->n;
   const int ns = S->ns;
@@ -190,7 +192,10 @@ __device__ __forceinline__ void eval_f_cplx(CSec* S, const SDI_TAPE CplxDev* X, 
   for (int p = 0; p < PPT; ++p) {
     imf[p] = 0;
 #pragma unroll
-    for (int k = 0; k < KM; ++k) f[p][k] = cd{0.0, 0.0};
+    for (int k = 0; k < KM; ++k) {
+      f[p][k] = cd{0.0, 0.0};
+      if constexpr (COND) cnd[p][k] = 0.0;
+    }
   }
   const int C = 1 << ns;
   for (int W = 0; W < C; ++W) {
@@ -339,6 +344,7 @@ __device__ __forceinline__ void eval_f_cplx(CSec* S, const SDI_TAPE CplxDev* X, 
         for (int kk = 0; kk < KM; ++kk) {
           if (kk >= off && kk < kf) {
             f[p][kk] = cadd(f[p][kk], t);
+            if constexpr (COND) cnd[p][kk] += hypot(t.re, t.im);
             t = cscale(cmul(t, zz), 1.0 / (double)(kk - off + 1));
           }
         }
@@ -349,8 +355,18 @@ __device__ __forceinline__ void eval_f_cplx(CSec* S, const SDI_TAPE CplxDev* X, 
 #pragma unroll
   for (int p = 0; p < PPT; ++p)
 #pragma unroll
-    for (int k = 0; k < KM; ++k) f[p][k] = cscale(f[p][k], mono[p]);
+    for (int k = 0; k < KM; ++k) {
+      f[p][k] = cscale(f[p][k], mono[p]);
+      if constexpr (COND) cnd[p][k] *= fabs(mono[p]);
+    }
   (void)flags;
+}
+
+template <int NV, int PPT, int KM>
+__device__ __forceinline__ void eval_f_cplx(CSec* S, const SDI_TAPE CplxDev* X, CU32* dir, CTerm* terms,
+                                            const double (&x)[PPT][NV], cd (&f)[PPT][KM], int (&imf)[PPT]) {
+  double unused[PPT][KM];
+  eval_f_cplx_c<NV, PPT, KM, false>(S, X, dir, terms, x, f, imf, unused);
 }
 
 }  // namespace sdi

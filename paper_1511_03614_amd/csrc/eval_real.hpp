@@ -277,13 +277,15 @@ __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
   }
 }
 
-// Adds t_q = base z^q / q! to f[OFF + q] for the orders the sector keeps.
-template <int OFF, int KM>
-__device__ __forceinline__ void add_series(double (&f)[KM], double t, double z, int kf) {
+// Adds t_q = base z^q / q! to f[OFF + q] for the orders the sector keeps
+// (and |t_q| to c when COND: the conditioning sums of the evaluate hook).
+template <int OFF, int KM, bool COND>
+__device__ __forceinline__ void add_series(double (&f)[KM], double (&c)[KM], double t, double z, int kf) {
 #pragma unroll
   for (int kk = OFF; kk < KM; ++kk) {
     if (kk < kf) {
       f[kk] += t;
+      if constexpr (COND) c[kk] += fabs(t);
       t = t * z * (1.0 / (double)(kk - OFF + 1));
     }
   }
@@ -293,9 +295,10 @@ __device__ __forceinline__ void add_series(double (&f)[KM], double t, double z, 
 // non-singular monomial.  Internal variables 0..ns-1 are the singular ones.
 // Corners W and subsets T of S are wave-uniform runtime loops; the offset of
 // q = 0 in f (ns - |T|) selects one of MAXS+1 static accumulation bodies.
-template <int NV, int PPT, int KM>
-__device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms,
-                                            const double (&x)[PPT][NV], double (&f)[PPT][KM]) {
+// COND: also the sums of |term| per order (cnd), for the evaluate hook.
+template <int NV, int PPT, int KM, bool COND>
+__device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const double (&x)[PPT][NV],
+                                              double (&f)[PPT][KM], double (&cnd)[PPT][KM]) {
   const int n = S->n;
   const int ns = S->ns;
   const int kf = S->kf;
@@ -375,7 +378,10 @@ __device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms,
 #pragma unroll
   for (int p = 0; p < PPT; ++p)
 #pragma unroll
-    for (int k = 0; k < KM; ++k) f[p][k] = 0.0;
+    for (int k = 0; k < KM; ++k) {
+      f[p][k] = 0.0;
+      if constexpr (COND) cnd[p][k] = 0.0;
+    }
 
   const int C = 1 << ns;
   for (int W = 0; W < C; ++W) {
@@ -398,11 +404,11 @@ __device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms,
           }
         }
         switch (off) {
-          case 0: add_series<0, KM>(f[p], coef, z, kf); break;
-          case 1: add_series<1, KM>(f[p], coef, z, kf); break;
-          case 2: add_series<2, KM>(f[p], coef, z, kf); break;
-          case 3: add_series<3, KM>(f[p], coef, z, kf); break;
-          default: add_series<4, KM>(f[p], coef, z, kf); break;
+          case 0: add_series<0, KM, COND>(f[p], cnd[p], coef, z, kf); break;
+          case 1: add_series<1, KM, COND>(f[p], cnd[p], coef, z, kf); break;
+          case 2: add_series<2, KM, COND>(f[p], cnd[p], coef, z, kf); break;
+          case 3: add_series<3, KM, COND>(f[p], cnd[p], coef, z, kf); break;
+          default: add_series<4, KM, COND>(f[p], cnd[p], coef, z, kf); break;
         }
       }
       if (T == 0) break;
@@ -411,7 +417,17 @@ __device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms,
 #pragma unroll
   for (int p = 0; p < PPT; ++p)
 #pragma unroll
-    for (int k = 0; k < KM; ++k) f[p][k] *= mono[p];
+    for (int k = 0; k < KM; ++k) {
+      f[p][k] *= mono[p];
+      if constexpr (COND) cnd[p][k] *= fabs(mono[p]);
+    }
+}
+
+template <int NV, int PPT, int KM>
+__device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms, const double (&x)[PPT][NV],
+                                            double (&f)[PPT][KM]) {
+  double unused[PPT][KM];
+  eval_f_real_c<NV, PPT, KM, false>(S, terms, x, f, unused);
 }
 
 }  // namespace sdi

@@ -133,6 +133,7 @@ struct EvalArgs {            // explicit points (justEvaluate / parity)
   const double* x;           // [npts][n] caller variable order
   double* out;               // [npts][K][2]
   int64_t npts;
+  double* cond;              // [npts][K] sums of |term| per result order, or null
 };
 
 struct SampleArgs {

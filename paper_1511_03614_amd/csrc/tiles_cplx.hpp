@@ -193,18 +193,24 @@ __device__ __forceinline__ void eval_point_cplx(const EvalArgs& A, const CplxArg
 #pragma unroll
   for (int j = 0; j < NV; ++j) x[0][j] = j < n ? A.x[i * n + S->perm[j]] : 0.5;
   cd f[1][KM];
+  double cnd[1][KM];
   int imf[1];
-  eval_f_cplx<NV, 1, KM>(S, tape(X.cx), tape(X.dir), tape(A.terms), x, f, imf);
+  if (A.cond)
+    eval_f_cplx_c<NV, 1, KM, true>(S, tape(X.cx), tape(X.dir), tape(A.terms), x, f, imf, cnd);
+  else
+    eval_f_cplx<NV, 1, KM>(S, tape(X.cx), tape(X.dir), tape(A.terms), x, f, imf);
   (void)imf;
   for (int k = 0; k < K; ++k) {
-    double fr = 0.0, fi = 0.0;
+    double fr = 0.0, fi = 0.0, cs = 0.0;
 #pragma unroll
     for (int kk = 0; kk < KM; ++kk) {
       fr += S->fold_re[k][kk] * f[0][kk].re - S->fold_im[k][kk] * f[0][kk].im;
       fi += S->fold_re[k][kk] * f[0][kk].im + S->fold_im[k][kk] * f[0][kk].re;
+      if (A.cond) cs += hypot(S->fold_re[k][kk], S->fold_im[k][kk]) * cnd[0][kk];
     }
     A.out[(i * K + k) * 2] = fr;
     A.out[(i * K + k) * 2 + 1] = fi;
+    if (A.cond) A.cond[i * K + k] = cs;
   }
 }
 
@@ -227,7 +233,7 @@ __global__ void __launch_bounds__(BLOCK) k_eval_tiles_cplx(EvalTilesArgs T, Cplx
     const PointRun run = T.runs[r];
     const int64_t i = (c - T.chunk_prefix[r]) * BLOCK + threadIdx.x;
     if (i >= (int64_t)run.count) continue;
-    EvalArgs A;
+    EvalArgs A{};
     A.sec = T.secs + run.sector;
     A.terms = T.terms;
     A.x = T.x + run.x_off;

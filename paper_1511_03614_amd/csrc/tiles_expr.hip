@@ -173,6 +173,7 @@ __global__ void __launch_bounds__(EXPR_BLOCK) k_eval_points_expr(EvalArgs A, Exp
   if (i < A.npts) {
     A.out[2 * i] = v;
     A.out[2 * i + 1] = 0.0;
+    if (A.cond) A.cond[i] = 0.0;   // no subtraction sums in a text integrand
   }
 }
 

@@ -182,17 +182,22 @@ __device__ __forceinline__ void eval_point_real(const EvalArgs& A, int64_t i) {
   double x[1][NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) x[0][j] = j < n ? A.x[i * n + S->perm[j]] : 0.5;
-  double f[1][KM];
-  eval_f_real<NV, 1, KM>(S, tape(A.terms), x, f);
+  double f[1][KM], cnd[1][KM];
+  if (A.cond)
+    eval_f_real_c<NV, 1, KM, true>(S, tape(A.terms), x, f, cnd);
+  else
+    eval_f_real<NV, 1, KM>(S, tape(A.terms), x, f);
   for (int k = 0; k < K; ++k) {
-    double fr = 0.0, fi = 0.0;
+    double fr = 0.0, fi = 0.0, cs = 0.0;
 #pragma unroll
     for (int kk = 0; kk < KM; ++kk) {
       fr += S->fold_re[k][kk] * f[0][kk];
       fi += S->fold_im[k][kk] * f[0][kk];
+      if (A.cond) cs += hypot(S->fold_re[k][kk], S->fold_im[k][kk]) * cnd[0][kk];
     }
     A.out[(i * K + k) * 2] = fr;
     A.out[(i * K + k) * 2 + 1] = fi;
+    if (A.cond) A.cond[i * K + k] = cs;
   }
 }
 
@@ -218,7 +223,7 @@ __global__ void __launch_bounds__(BLOCK) k_eval_tiles_real(EvalTilesArgs T) {
     const PointRun run = T.runs[r];
     const int64_t i = (c - T.chunk_prefix[r]) * BLOCK + threadIdx.x;
     if (i >= (int64_t)run.count) continue;
-    EvalArgs A;
+    EvalArgs A{};
     A.sec = T.secs + run.sector;
     A.terms = T.terms;
     A.x = T.x + run.x_off;

@@ -55,13 +55,15 @@ def oracle_shift_values_c(problem, s, m, R, seed):
 def pointwise_c(ctx, prob, s, x_np):
     h = P.sdi_problem_create(ctx, prob)
     try:
-        g = P.sdi_evaluate(ctx, h, s, torch.from_numpy(x_np).cuda()).cpu().numpy()
+        g, gc = P.sdi_evaluate(ctx, h, s, torch.from_numpy(x_np).cuda(), with_cond=True)
+        g, gc = g.cpu().numpy(), gc.cpu().numpy()
     finally:
         P.sdi_problem_destroy(h)
     lead, pref = integrate.prefactor_for(prob)
     vals, cond, _ = integrand.sector_orders(prob.sectors[s], x_np, prob.order_min, prob.order_max, lead, pref,
                                             True, prob.lam)
     gv = g[..., 0].T + 1j * g[..., 1].T
+    np.testing.assert_allclose(gc.T, cond, rtol=1e-10, atol=0)
     d = np.abs(gv - vals)
     return d <= 1e-12 * np.abs(vals) + 4e-15 * cond, d <= 1e-12 * np.abs(vals)
 

@@ -56,7 +56,9 @@ def test_pointwise_matches_oracle(ctx):
         h = P.sdi_problem_from_text(ctx, text)
         try:
             assert P.sdi_problem_nsectors(h) == 1 and P.sdi_problem_norders(h) == 1
-            g = P.sdi_evaluate(ctx, h, 0, torch.from_numpy(x).cuda()).cpu().numpy()
+            g, gc = P.sdi_evaluate(ctx, h, 0, torch.from_numpy(x).cuda(), with_cond=True)
+            g = g.cpu().numpy()
+            assert torch.all(gc == 0.0)
         finally:
             P.sdi_problem_destroy(h)
         v, c = E.evaluate(e, x)

@@ -101,12 +101,15 @@ def pointwise_check(ctx, prob, s, x_np):
     h = P.sdi_problem_create(ctx, prob)
     try:
         x = torch.from_numpy(x_np).cuda()
-        g = P.sdi_evaluate(ctx, h, s, x).cpu().numpy()
+        g, gc = P.sdi_evaluate(ctx, h, s, x, with_cond=True)
+        g, gc = g.cpu().numpy(), gc.cpu().numpy()
     finally:
         P.sdi_problem_destroy(h)
     lead, pref = integrate.prefactor_for(prob)
     vals, cond, _ = integrand.sector_orders(prob.sectors[s], x_np, prob.order_min, prob.order_max, lead, pref)
     gv = g[..., 0].T + 1j * g[..., 1].T
+    # the library's own conditioning sums: sums of absolute values, so both sides agree closely
+    np.testing.assert_allclose(gc.T, cond, rtol=1e-10, atol=0)
     d = np.abs(gv - vals)
     strict = d <= 1e-12 * np.abs(vals)
     ok = strict | (d <= 1e-12 * np.abs(vals) + 4e-15 * cond)
