@@ -147,7 +147,9 @@ def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, sh
     lowers its sector's share of the relative errors and agrees with the
     lattice); then a final pass samples the kept sectors through their flows and
     the rest on the lattice, at each operating point of `finals` (parameter
-    sets).  Its GPU time is pilot + training + validation + final pass.  Plain
+    sets); its estimate combines, for flow-sampled sectors, the final pass
+    with the pilot pass (`_combine_with_pilot`).  Its GPU time is pilot +
+    training + validation + final pass.  Plain
     form: lattice passes at each parameter set of `plains`; its error at the
     learned form's time comes from a least-squares power law err = A t^-alpha
     fitted per order to all plain passes (the shift-to-shift error of a
@@ -183,12 +185,9 @@ def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, sh
             r = run(**kw)
             refs.append({"params": kw, "ms": r["ms_total"], "err": _err(r).tolist()})
         pilot = run(lattice_log2=m_pilot, budget=0)
-        var = np.zeros((ns, problem.norders))
-        val = np.zeros(problem.norders, dtype=complex)
-        for s in range(ns):
-            mean, err, _, _ = P.sdi_sector_results(ctx, h, s, 16)
-            var[s] = err[:, 0] ** 2 + err[:, 1] ** 2
-            val += mean
+        pst = _sector_stats(P, ctx, h, ns)
+        var = pst[1][:, :, 0] ** 2 + pst[1][:, :, 1] ** 2
+        val = pst[0].sum(axis=0)
         scale = np.maximum(np.abs(val) ** 2, var.sum(axis=0))
         if select_on == "top":
             scale[:-1] = np.inf
@@ -220,7 +219,7 @@ def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, sh
         for kw in finals:
             fr = run(**kw, sampler=1)
             t_learned = pilot["ms_total"] + ms_train + ms_val + fr["ms_total"]
-            ef = _err(fr)
+            fval, ef = _combine_with_pilot(pst, _sector_stats(P, ctx, h, ns), kept)
             k = int(np.clip(np.searchsorted(t, t_learned), 1, len(t) - 1))
             a = (np.log(t_learned) - np.log(t[k - 1])) / (np.log(t[k]) - np.log(t[k - 1]))
             with np.errstate(divide="ignore", invalid="ignore"):
@@ -229,7 +228,8 @@ def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, sh
                 ratio = np.where(ef > 0, e_eq / ef, np.nan)
             points.append({"final": kw, "ms_total": t_learned, "ms_final_pass": fr["ms_total"],
                            "ms_flow_sampling": fr["ms_warmup"], "err": ef.tolist(),
-                           "value_re": fr["value"].real.tolist(), "value_im": fr["value"].imag.tolist(),
+                           "err_final_pass_alone": _err(fr).tolist(),
+                           "value_re": fval.real.tolist(), "value_im": fval.imag.tolist(),
                            "plain_err_at_equal_time": e_eq.tolist(),
                            "plain_err_interpolated": e_int.tolist(),
                            "error_ratio_plain_over_learned": ratio.tolist(),
@@ -248,6 +248,161 @@ def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, sh
             "plain_references": refs,
             "error_ratio_top_order": [p["error_ratio_top_order"] for p in points],
         }
+    finally:
+        P.sdi_problem_destroy(h)
+
+
+def _sector_stats(P, ctx, h, ns):
+    """Per-sector means (complex) and standard errors (re, im) of the last pass."""
+    import numpy as np
+    means, errs = [], []
+    for s in range(ns):
+        mean, err, _, _ = P.sdi_sector_results(ctx, h, s, 16)
+        means.append(mean)
+        errs.append(err)
+    return np.array(means), np.array(errs)
+
+
+def _combine_with_pilot(pilot, final, kept):
+    """The learned form's estimate: per sector and order, a sector sampled by its
+    flow in the final pass combines that pass with the pilot lattice pass (two
+    independent estimates of the same sector integral; weights 1/sigma^2, real
+    and imaginary parts apart); the other sectors take the final pass alone.
+    Returns the sum over sectors and its standard error per order."""
+    import numpy as np
+    (pm, pe), (fm, fe) = pilot, final
+    val = np.zeros(fm.shape[1], dtype=complex)
+    var = np.zeros((fm.shape[1], 2))
+    for s in range(fm.shape[0]):
+        if not kept[s]:
+            val += fm[s]
+            var += fe[s] ** 2
+            continue
+        for part, get in ((0, np.real), (1, np.imag)):
+            a, b = get(pm[s]), get(fm[s])
+            va, vb = pe[s][:, part] ** 2, fe[s][:, part] ** 2
+            ok = (va > 0) & (vb > 0)
+            w = np.where(ok, vb / np.where(ok, va + vb, 1.0), 0.0)      # weight of the pilot
+            c = w * a + (1 - w) * b
+            v = np.where(ok, va * vb / np.where(ok, va + vb, 1.0), vb)
+            val += c if part == 0 else 1j * c
+            var[:, part] += v
+    return val, np.sqrt(var[:, 0] + var[:, 1])
+
+
+def _learned_pass(P, ctx, h, problem, seed, m_pilot, share, max_sel, iters, batch_log2, lr, final, common):
+    """One learned+batched run with the given seed: pilot lattice pass, flows
+    for the sectors carrying `share` of the pilot's relative error (at most
+    max_sel), GPU training, validation, final mixed pass.  Returns the final
+    result and the total device time (pilot + training + validation + final)."""
+    import numpy as np
+    ns = len(problem.sectors)
+
+    def run(**kw):
+        _set(P, ctx, **{**common, "seed": seed, **kw})
+        P.sdi_integrate(ctx, h)
+        return P.sdi_integrate(ctx, h)
+
+    pilot = run(lattice_log2=m_pilot, budget=0)
+    pst = _sector_stats(P, ctx, h, ns)
+    var = pst[1][:, :, 0] ** 2 + pst[1][:, :, 1] ** 2
+    val = pst[0].sum(axis=0)
+    scale = np.maximum(np.abs(val) ** 2, var.sum(axis=0))
+    w = (var / np.where(scale > 0, scale, 1.0)).sum(axis=1)
+    order = np.argsort(-w)
+    cum = np.cumsum(w[order]) / max(w.sum(), 1e-300)
+    nsel = int(min(max_sel, np.searchsorted(cum, share) + 1, ns))
+    sel = sorted(int(s) for s in order[:nsel])
+    P.sdi_flow_init(ctx, h, seed)
+    ms_train = P.sdi_flow_train(ctx, h, iters, batch_log2, lr, sectors=sel)
+    kept, ms_val = P.sdi_flow_validate(ctx, h, m_pilot)
+    fr = run(**final, sampler=1)
+    value, err = _combine_with_pilot(pst, _sector_stats(P, ctx, h, ns), kept)
+    return value, err, pilot["ms_total"] + ms_train + ms_val + fr["ms_total"], int(sum(kept))
+
+
+def seed_study(P, ctx, name, problem, lambda_max=None, m_pilot=11, share=0.9, max_sel=48, iters=20,
+               batch_log2=11, lr=6e-3, final=None, ref=None, plains=None, common=None, seeds=10):
+    """Error at equal GPU time against a reference: the learned+batched form and
+    plain batched QMC each run with `seeds` independent seeds (shifts, flow
+    initialisation and training points); per order, the RMS over seeds of
+    |estimate - reference| and of the reported standard error.  The reference is
+    one plain lattice run with 256x the points of the learned form's final pass
+    (fixed launch shape, no autotuning) and its own seed.  The plain form runs at the two lattice sizes whose device times
+    bracket the learned form's mean time; its RMS at that time is interpolated
+    in log-log between them."""
+    import numpy as np
+    final = final or dict(lattice_log2=13)
+    ref = ref or dict(lattice_log2=18, shifts=128, tile_log2=14, ppt=1)
+    plains = plains or [dict(lattice_log2=m) for m in range(10, 18)]
+    common = common or {}
+    h = P.sdi_problem_create(ctx, problem)
+
+    def run(seed, **kw):
+        _set(P, ctx, **{**common, "seed": seed, **kw})
+        P.sdi_integrate(ctx, h)
+        return P.sdi_integrate(ctx, h)
+
+    try:
+        if lambda_max is not None:
+            _set(P, ctx, **{**common, "seed": 1})
+            P.sdi_tune_deformation(ctx, h, lambda_max, 4, 10)
+        _set(P, ctx, **{**common, "seed": 104729, **ref})
+        rr = P.sdi_integrate(ctx, h)
+        refv = rr["value"]
+        times = [(kw, run(1, **kw)["ms_total"]) for kw in plains]
+        times.sort(key=lambda p: p[1])
+        est_b, t_b, kept = [], [], []
+        for sd in range(1, seeds + 1):
+            v, e, t, nk = _learned_pass(P, ctx, h, problem, 1000 + sd, m_pilot, share, max_sel, iters, batch_log2,
+                                        lr, final, common)
+            est_b.append((v, e))
+            t_b.append(t)
+            kept.append(nk)
+        tb = float(np.mean(t_b))
+        ts = np.array([t for _, t in times])
+        k = int(np.clip(np.searchsorted(ts, tb), 1, len(ts) - 1))
+
+        def rms(ests):
+            d = np.array([np.abs(v - refv) for v, _ in ests])
+            e = np.array([e for _, e in ests])
+            return np.sqrt((d ** 2).mean(axis=0)), np.sqrt((e ** 2).mean(axis=0))
+
+        ref_var = _err(rr) ** 2
+
+        def corrected(r):
+            # |est - ref|^2 averages sigma_est^2 + sigma_ref^2: remove the reference's share
+            return np.sqrt(np.maximum(r ** 2 - ref_var, 0.0))
+
+        rb, sb = rms(est_b)
+        plain = []
+        for kw, t in (times[k - 1], times[k]):
+            ests = []
+            for sd in range(1, seeds + 1):
+                r = run(2000 + sd, **kw)
+                ests.append((r["value"], _err(r)))
+            ra, sa = rms(ests)
+            plain.append({"params": kw, "ms": t, "rms_err": ra.tolist(), "rms_err_ref_corrected": corrected(ra).tolist(),
+                          "rms_sigma": sa.tolist()})
+        a = (np.log(tb) - np.log(times[k - 1][1])) / (np.log(times[k][1]) - np.log(times[k - 1][1]))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r0, r1 = np.array(plain[0]["rms_err"]), np.array(plain[1]["rms_err"])
+            r_eq = np.exp((1 - a) * np.log(r0) + a * np.log(r1))
+            ratio = np.where(rb > 0, r_eq / rb, np.nan)
+            c0, c1 = corrected(r0), corrected(r1)
+            c_eq = np.exp((1 - a) * np.log(c0) + a * np.log(c1))
+            ratio_c = np.where(corrected(rb) > 0, c_eq / corrected(rb), np.nan)
+        return {"config": name, "seeds": seeds,
+                "orders": list(range(problem.order_min, problem.order_max + 1)),
+                "reference": {"params": ref, "ms": rr["ms_total"], "err": _err(rr).tolist(),
+                              "value_re": refv.real.tolist(), "value_im": refv.imag.tolist()},
+                "learned": {"final": final, "ms_mean": tb, "flows_kept_mean": float(np.mean(kept)),
+                            "rms_err": rb.tolist(), "rms_err_ref_corrected": corrected(rb).tolist(),
+                            "rms_sigma": sb.tolist()},
+                "plain_bracket": plain,
+                "plain_rms_err_at_equal_time": r_eq.tolist(),
+                "rms_ratio_plain_over_learned": ratio.tolist(),
+                "rms_ratio_ref_corrected": ratio_c.tolist()}
     finally:
         P.sdi_problem_destroy(h)
 
@@ -379,6 +534,12 @@ def main() -> int:
                                           "lambda tuned in (0, 0.5], 30 sectors, eps^-4..eps^0)",
                                   double_box_problem(5.0, -2.0, 1.0, order_max=0, complex_mode=True, lam=0.5),
                                   lambda_max=0.5, plains=lat, finals=[dict(lattice_log2=m) for m in (12, 13, 14)]),
+        ]
+        out["error_rms_over_seeds"] = [
+            seed_study(P, ctx, "double box, s=-3, t=-1, massless (Euclidean, 282 sectors)",
+                       double_box_problem(-3.0, -1.0, 0.0, order_max=0)),
+            seed_study(P, ctx, "double box, s=5, t=-2, m^2=1 (physical, 30 sectors, lambda tuned in (0, 0.5])",
+                       double_box_problem(5.0, -2.0, 1.0, order_max=0, complex_mode=True, lam=0.5), lambda_max=0.5),
         ]
     P.sdi_ctx_destroy(ctx)
     if not args.no_cpu_baseline:

@@ -572,7 +572,8 @@ std::string tune_key(const sdi_ctx* ctx, const sdi_problem* pb, const std::vecto
 // The autotuner: times the final-pass tile kernel on the problem's own tiles
 // for every launch variant (points per thread x minimum waves per SIMD) at the
 // largest candidate tile size, then for each smaller tile size with the best
-// variant so far, and keeps the fastest pair.  Results are cached per
+// variant so far, then every variant at the best tile size, and keeps the
+// fastest pair.  Results are cached per
 // tune_key (and can be saved and loaded with the kernel build's hash).
 // fixed_variant >= 0 skips the variant search.  With a caller workspace every
 // candidate plan is built on it in turn; a size that does not fit is skipped.
@@ -590,23 +591,33 @@ int autotune(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
       }
   TuneChoice best{tiles.front(), fixed_variant >= 0 ? fixed_variant : default_variant(pb, 1)};
   float best_ms = 1e30f;
-  for (size_t i = 0; i < tiles.size(); ++i) {
+  // Coordinate search: every variant at the largest tile size, every tile size
+  // with the best variant, then every variant again at the best tile size.
+  std::vector<std::pair<int, std::vector<int>>> rounds;
+  const std::vector<int> all = fixed_variant >= 0 ? std::vector<int>{fixed_variant} : tile_variants(pb);
+  rounds.push_back({tiles.front(), all});
+  for (size_t i = 1; i < tiles.size(); ++i) rounds.push_back({tiles[i], {}});
+  if (tiles.size() > 1 && all.size() > 1) rounds.push_back({-1, all});
+  for (size_t r = 0; r < rounds.size(); ++r) {
+    const int tl = rounds[r].first < 0 ? best.tile_log2 : rounds[r].first;
+    if (rounds[r].first < 0 && tl == tiles.front()) break;   // the first round already timed these
     PassState C;
-    int rc = setup_pass(ctx, pb, C, msec, warm, tiles[i], dev_ws, ws_bytes);
-    if (rc == SDI_ENOMEM && i > 0) {
+    int rc = setup_pass(ctx, pb, C, msec, warm, tl, dev_ws, ws_bytes);
+    if (rc == SDI_ENOMEM && r > 0) {
       ctx->err.clear();
       continue;
     }
     if (rc != SDI_OK) return rc;
     if (C.P.forder.empty()) break;   // no lattice tiles to time
-    const std::vector<int> vs = (i == 0 && fixed_variant < 0) ? tile_variants(pb) : std::vector<int>{best.variant};
+    const std::vector<int> vs = rounds[r].second.empty() ? std::vector<int>{best.variant} : rounds[r].second;
     for (int v : vs) {
+      if (rounds[r].first < 0 && v == best.variant) continue;   // timed in the tile round
       float ms = 0.f;
       rc = time_final(ctx, pb, C, v, &ms);
       if (rc != SDI_OK) return rc;
       if (ms < best_ms) {
         best_ms = ms;
-        best = TuneChoice{tiles[i], v};
+        best = TuneChoice{tl, v};
       }
     }
   }
