@@ -417,6 +417,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     pb->nvmax = std::max(pb->nvmax, nvc);
     if (d->complex_mode) c *= 8.0 + 2.0 * n * n;
     pb->kfmax = std::max(pb->kfmax, R.kf);
+    pb->nsmax = std::max(pb->nsmax, R.ns);
   }
   if (pb->terms.empty()) pb->terms.push_back(Term{0.0, 0});
   hipError_t e = hipSetDevice(ctx->device);

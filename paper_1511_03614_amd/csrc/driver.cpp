@@ -329,7 +329,7 @@ int launch_tiles(const sdi_problem* pb, int ppt, int wpe, int km, int grid, size
                  hipStream_t st) {
   if (pb->is_expr()) return launch_tiles_expr(grid, shmem, a, expr_args(pb), st);
   if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, wpe, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
-  return launch_tiles_real(pb->nvmax, ppt, wpe, km, grid, shmem, a, st);
+  return launch_tiles_real(pb->nvmax, pb->nsmax, ppt, wpe, km, grid, shmem, a, st);
 }
 
 int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int wpe, int km, size_t shmem,
@@ -337,7 +337,7 @@ int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int 
   const int nvmax = pb->nvmax;
   int occ = pb->is_expr()      ? tiles_expr_occupancy(mode, shmem, expr_args(pb))
             : pb->complex_mode ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, shmem)
-                               : tiles_real_occupancy(nvmax, mode, ppt, wpe, km, shmem);
+                               : tiles_real_occupancy(nvmax, pb->nsmax, mode, ppt, wpe, km, shmem);
   if (occ < 1) occ = 1;
   const size_t g = (size_t)occ * std::max(ctx->ncu, 1);
   return (int)std::max<size_t>(1, std::min(g, ntiles));
@@ -563,9 +563,10 @@ std::string tune_key(const sdi_ctx* ctx, const sdi_problem* pb, const std::vecto
   if (p.sampler == 1 && pb->flow)
     for (uint8_t a : pb->flow->active) h = (h ^ a) * 1099511628211ull;
   char buf[320];
-  snprintf(buf, sizeof buf, "%s|c%d|nv%d|kf%d|sec%d|terms%zu|m%llx|R%d|w%d|t%d|p%d|s%d", ctx->prop.gcnArchName,
-           pb->complex_mode, pb->nvmax, pb->kfmax, pb->nsec, pb->terms.size(), h, p.R, (int)(warm && p.warmup > 0),
-           p.tile_log2, p.ppt, p.sampler);
+  snprintf(buf, sizeof buf, "%s|c%d|x%d|nv%d|ns%d|kf%d|sec%d|terms%zu|m%llx|R%d|w%d|t%d|p%d|s%d",
+           ctx->prop.gcnArchName, pb->complex_mode, (int)pb->is_expr(), pb->nvmax, pb->nsmax, pb->kfmax, pb->nsec,
+           pb->is_expr() ? pb->expr_nins : pb->terms.size(), h, p.R, (int)(warm && p.warmup > 0), p.tile_log2, p.ppt,
+           p.sampler);
   return buf;
 }
 

@@ -296,9 +296,12 @@ __device__ __forceinline__ void add_series(double (&f)[KM], double (&c)[KM], dou
 // Corners W and subsets T of S are wave-uniform runtime loops; the offset of
 // q = 0 in f (ns - |T|) selects one of MAXS+1 static accumulation bodies.
 // COND: also the sums of |term| per order (cnd), for the evaluate hook.
-template <int NV, int PPT, int KM, bool COND>
+// NSM: bound on the sector's singular variables (the per-point log x_j and
+// 1/x_j arrays are sized by it, which matters for the register budget).
+template <int NV, int PPT, int KM, bool COND, int NSM = MAXS>
 __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const double (&x)[PPT][NV],
                                               double (&f)[PPT][KM], double (&cnd)[PPT][KM]) {
+  static_assert(NSM >= 1 && NSM <= MAXS, "singular-variable bound");
   const int n = S->n;
   const int ns = S->ns;
   const int kf = S->kf;
@@ -309,9 +312,9 @@ __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const doubl
 #pragma unroll
     for (int j = 0; j < NV; ++j) x2[p][j] = x[p][j] * x[p][j];
 
-  double lx[PPT][MAXS], ix[PPT][MAXS];
+  double lx[PPT][NSM], ix[PPT][NSM];
 #pragma unroll
-  for (int i = 0; i < MAXS; ++i) {
+  for (int i = 0; i < NSM; ++i) {
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
       lx[p][i] = 0.0;
@@ -397,7 +400,7 @@ __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const doubl
         double coef = sgn * g0[p];
         double z = lrest[p] + lam[p];
 #pragma unroll
-        for (int i = 0; i < MAXS; ++i) {
+        for (int i = 0; i < NSM; ++i) {
           if (i < ns && !((T >> i) & 1)) {
             coef *= ix[p][i];
             z += S->bS[i] * lx[p][i];
@@ -423,11 +426,11 @@ __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const doubl
     }
 }
 
-template <int NV, int PPT, int KM>
+template <int NV, int PPT, int KM, int NSM = MAXS>
 __device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms, const double (&x)[PPT][NV],
                                             double (&f)[PPT][KM]) {
   double unused[PPT][KM];
-  eval_f_real_c<NV, PPT, KM, false>(S, terms, x, f, unused);
+  eval_f_real_c<NV, PPT, KM, false, NSM>(S, terms, x, f, unused);
 }
 
 }  // namespace sdi

@@ -40,12 +40,14 @@ int launch_eval_points_expr(const EvalArgs& a, const ExprArgs& x, hipStream_t st
 // minimum waves per SIMD wpe (final-pass variants (1,4), (2,3), (2,4), (4,2); the
 // last not for class 16), order capacity km (4 or 8), in the pass mode a.mode
 // (0 final, 1 warm-up with at most 2 points per thread, 2 explicit points with
-// 1; modes 1 and 2 run at 4 waves).  grid = number of persistent blocks.
-int launch_tiles_real(int nvmax, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
+// 1; modes 1 and 2 run at 4 waves).  nsmax bounds the singular variables of
+// every sector: final passes with nsmax <= 2 run instances with smaller
+// per-point arrays.  grid = number of persistent blocks.
+int launch_tiles_real(int nvmax, int nsmax, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
                       hipStream_t st);
 int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st);
 // Occupancy (resident blocks per CU) of a tile kernel instance; 0 if not built.
-int tiles_real_occupancy(int nvmax, int mode, int ppt, int wpe, int km, size_t shmem);
+int tiles_real_occupancy(int nvmax, int nsmax, int mode, int ppt, int wpe, int km, size_t shmem);
 
 // Complex mode: nvmax 4 or 8; cx is the CplxDev array (tile kernel) or one sector's
 // record (point evaluation); dir the derivative-list directory.

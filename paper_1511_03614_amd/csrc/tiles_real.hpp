@@ -11,7 +11,7 @@
 
 namespace sdi {
 
-template <int NV, int PPT, int KM, int MODE>
+template <int NV, int PPT, int KM, int MODE, int NSM>
 __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
                                               const TileDesc& td, int tc, const double* __restrict__ lgrid,
                                               double* __restrict__ lhist, double (&s)[KM],
@@ -42,7 +42,7 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
       make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
     }
     double f[PPT][KM];
-    eval_f_real<NV, PPT, KM>(S, tape(A.terms), x, f);
+    eval_f_real<NV, PPT, KM, NSM>(S, tape(A.terms), x, f);
     const int kf = S->kf;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -73,7 +73,9 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
 
 // WPE: minimum waves per SIMD the register allocation must allow (the
 // autotuner picks it with PPT; occupancy pays more than a few spills here).
-template <int NVMAX, int PPT, int KM, int MODE, int WPE>
+// NSM: bound on the singular variables of every sector of the launch (the
+// final pass has NSM = 2 instances for problems without deeper poles).
+template <int NVMAX, int PPT, int KM, int MODE, int WPE, int NSM = MAXS>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_tiles_real(TileArgs A) {
   extern __shared__ double smem[];
   __shared__ int s_tile;
@@ -117,16 +119,16 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
     const int cls = S->cls;
     switch (cls) {
       case 0:
-        run_tile_real<4, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        run_tile_real<4, PPT, KM, MODE, NSM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       case 1:
         if constexpr (NVMAX == 6)
-          run_tile_real<6, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+          run_tile_real<6, PPT, KM, MODE, NSM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         else if constexpr (NVC >= 1)
-          run_tile_real<8, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+          run_tile_real<8, PPT, KM, MODE, NSM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       case 2:
-        if constexpr (NVC >= 2) run_tile_real<16, PPT, KM, MODE>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        if constexpr (NVC >= 2) run_tile_real<16, PPT, KM, MODE, NSM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       default:
         break;

@@ -1,0 +1,34 @@
+// Final-pass instances of the real-mode tile kernel for sectors of up to 16
+// variables in problems whose sectors have at most 2 singular variables (the
+// smaller per-point arrays leave registers for the 3- and 4-wave variants).
+#include "kernels.h"
+#include "tiles_real.hpp"
+
+namespace sdi {
+
+int launch_tiles_real_nv16_s2(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st) {
+  if (a.mode != 0) return (int)hipErrorInvalidValue;
+#define SDI_L(P, W, K)                                                                       \
+  if (ppt == P && wpe == W && km == K) {                                                     \
+    k_tiles_real<16, P, K, 0, W, 2><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a);             \
+    return (int)hipGetLastError();                                                            \
+  }
+  SDI_L(1, 4, 4) SDI_L(2, 3, 4) SDI_L(2, 4, 4) SDI_L(1, 4, 8) SDI_L(2, 3, 8) SDI_L(2, 4, 8)
+#undef SDI_L
+  return (int)hipErrorInvalidValue;
+}
+
+int occupancy_tiles_real_nv16_s2(int ppt, int wpe, int km, size_t shmem) {
+  int nb = 0;
+#define SDI_O(P, W, K)                                                                                     \
+  if (ppt == P && wpe == W && km == K) {                                                                   \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles_real<16, P, K, 0, W, 2>, BLOCK, shmem) \
+        != hipSuccess) return 0;                                                                          \
+    return nb;                                                                                            \
+  }
+  SDI_O(1, 4, 4) SDI_O(2, 3, 4) SDI_O(2, 4, 4) SDI_O(1, 4, 8) SDI_O(2, 3, 8) SDI_O(2, 4, 8)
+#undef SDI_O
+  return 0;
+}
+
+}  // namespace sdi
