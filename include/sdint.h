@@ -37,7 +37,7 @@ enum {
   SDI_EINVAL = -1,      /* invalid argument or input outside the supported domain   */
   SDI_ENOMEM = -2,      /* host or device allocation failed, or workspace too small */
   SDI_EDEVICE = -3,     /* a HIP call failed                                        */
-  SDI_ENOTSUP = -4,     /* valid input that this build does not support            */
+  SDI_ENOTSUP = -4,     /* valid input that the library does not support           */
   SDI_ENONFINITE = -5,  /* results written, but some integrand values were NaN/Inf  */
   SDI_ESTATE = -6       /* call order violated (e.g. flow sampler before training)  */
 };
@@ -152,7 +152,7 @@ typedef struct {
 
 /* Validate and compile a problem into device tables (one host-to-device upload).
  * Returns SDI_EINVAL for inputs outside the domain above and SDI_ENOTSUP for
- * valid inputs beyond this build (more than SDI_MAX_SINGULAR singular
+ * valid inputs beyond the library (more than SDI_MAX_SINGULAR singular
  * variables, exponents above 3 in real mode or 7 in complex mode). */
 int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* desc, sdi_problem** out);
 
@@ -313,7 +313,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* prob, const int32_t* sectors, int3
  * sampler = 1; the others stay on the lattice (with sdi_flow_set_params or
  * training a sector becomes active; sdi_flow_init clears every flag). */
 int sdi_flow_set_active(sdi_ctx* ctx, sdi_problem* prob, int32_t s, int32_t active);
-/* Validation with the lattice as the judge: one lattice pass and one flow pass
+/* Validation with the lattice as the reference: one lattice pass and one flow pass
  * at 2^lattice_log2 points per shift (other parameters from ctx); with I_k and
  * V_k the lattice pass's estimate and total variance of order k and
  * S_k = max(|I_k|^2, V_k), an active sector keeps its flow only if
