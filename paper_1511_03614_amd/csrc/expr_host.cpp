@@ -322,119 +322,128 @@ std::vector<std::pair<size_t, size_t>> statements(const std::string& t, size_t f
 }
 
 // Parses the intermediate functions and the integrand, then lowers the DAG
-// to a tape: dead nodes dropped, slots assigned by liveness.
+// to a tape in depth-first order: dead nodes dropped, constants carried in
+// their users' immediate, slots assigned by liveness.
 int lower(const std::string& text, const std::vector<std::pair<size_t, size_t>>& st, int n, long m, bool share,
           std::vector<ExprIns>& tape, int& nslots, int& out) {
-  {
-    Compiler e;
-    e.share = share;
-    for (int j = 0; j < n; ++j) e.variable(j);
-    std::vector<int> fn;
-    for (long i = 0; i < m; ++i) {
-      Parser q(text, st[2 + i].first, st[2 + i].second, n, fn, e);
-      fn.push_back(q.parse());
-    }
-    Parser q(text, st[2 + m].first, st[2 + m].second, n, fn, e);
-    const int root = q.parse();
+  Compiler e;
+  e.share = share;
+  for (int j = 0; j < n; ++j) e.variable(j);
+  std::vector<int> fn;
+  for (long i = 0; i < m; ++i) {
+    Parser q(text, st[2 + i].first, st[2 + i].second, n, fn, e);
+    fn.push_back(q.parse());
+  }
+  Parser q(text, st[2 + m].first, st[2 + m].second, n, fn, e);
+  const int root = q.parse();
 
-    // keep what the integrand needs; nodes are already in dependency order
-    const int N = (int)e.nodes.size();
-    std::vector<char> live(N, 0);
-    live[root] = 1;
-    for (int i = N - 1; i >= 0; --i) {
-      if (!live[i]) continue;
-      const Node& d = e.nodes[i];
-      if (d.op == N_VAR || d.op == N_CONST) continue;
-      live[d.a] = 1;
-      if (d.b >= 0) live[d.b] = 1;
+  const int N = (int)e.nodes.size();
+  auto leaf = [&](int i) { return e.nodes[i].op == N_VAR || e.nodes[i].op == N_CONST; };
+  std::vector<char> live(N, 0);
+  live[root] = 1;
+  for (int i = N - 1; i >= 0; --i) {
+    if (!live[i] || leaf(i)) continue;
+    live[e.nodes[i].a] = 1;
+    if (e.nodes[i].b >= 0) live[e.nodes[i].b] = 1;
+  }
+  // operations in dependency (creation) order
+  std::vector<int> order;
+  for (int i = 0; i < N; ++i)
+    if (live[i] && !leaf(i)) order.push_back(i);
+  // last operation reading each value (positions in `order`)
+  std::vector<int> pos(N, -1);
+  for (size_t k = 0; k < order.size(); ++k) pos[order[k]] = (int)k;
+  std::vector<int> lastb(N, -1);
+  for (int i : order) {
+    const Node& d = e.nodes[i];
+    for (int o : {d.a, d.b})
+      if (o >= 0 && !leaf(o)) lastb[o] = std::max(lastb[o], pos[i]);
+  }
+  std::vector<int> slot(N, -1);
+  for (int j = 0; j < n; ++j) slot[j] = j;   // variables: nodes 0..n-1, pinned
+  std::vector<int> free_slots;
+  int top = n;
+  auto alloc = [&]() {
+    int sl;
+    if (!free_slots.empty()) {
+      sl = free_slots.back();
+      free_slots.pop_back();
+    } else {
+      sl = top++;
     }
-    std::vector<int> last(N, -1);
-    for (int i = 0; i < N; ++i) {
-      if (!live[i]) continue;
-      const Node& d = e.nodes[i];
-      if (d.op == N_VAR || d.op == N_CONST) continue;
-      last[d.a] = i;
-      if (d.b >= 0) last[d.b] = i;
-    }
-    // Variables stay in slots 0..n-1.  Constants are written right before each
-    // use into a slot that dies with it, so a constant shared by distant parts
-    // of a long integrand does not hold a slot in between.
-    std::vector<int> slot(N, -1);
-    std::vector<int> free_slots;
-    int top = n;
-    tape.clear();
-    auto alloc = [&]() {
-      int sl;
-      if (!free_slots.empty()) {
-        sl = free_slots.back();
-        free_slots.pop_back();
+    if (sl >= EXPR_MAX_SLOTS)
+      throw ParseError{SDI_ENOTSUP, "the integrand needs more than " + std::to_string(EXPR_MAX_SLOTS) +
+                                        " live temporaries", true};
+    return sl;
+  };
+  tape.clear();
+  for (size_t bi = 0; bi < order.size(); ++bi) {
+    const std::vector<int> b{order[bi]};
+    std::vector<ExprIns> ins(b.size());
+    for (size_t u = 0; u < b.size(); ++u) {
+      const Node& d = e.nodes[b[u]];
+      ExprIns& I = ins[u];
+      I = ExprIns{};
+      I.k = d.k;
+      switch (d.op) {
+        case N_ADD: I.op = X_ADD; break;
+        case N_SUB: I.op = X_SUB; break;
+        case N_MUL: I.op = X_MUL; break;
+        case N_DIV: I.op = X_DIV; break;
+        case N_NEG: I.op = X_NEG; break;
+        case N_LOG: I.op = X_LOG; break;
+        case N_POWI: I.op = X_POWI; break;
+        default: I.op = X_POW; break;
+      }
+      // constant operands ride in imm (folding leaves at most one per operation)
+      if (e.nodes[d.a].op == N_CONST) {
+        I.op |= X_IMMA;
+        I.imm = e.nodes[d.a].imm;
       } else {
-        sl = top++;
+        I.a = (uint8_t)slot[d.a];
       }
-      if (sl >= EXPR_MAX_SLOTS)
-        throw ParseError{SDI_ENOTSUP, "the integrand needs more than " + std::to_string(EXPR_MAX_SLOTS) +
-                                          " live temporaries", true};
-      return sl;
-    };
-    auto emit_const = [&](double v) {
-      ExprIns ins{};
-      ins.op = X_CONST;
-      ins.imm = v;
-      ins.dst = (uint8_t)alloc();
-      tape.push_back(ins);
-      return (int)ins.dst;
-    };
-    for (int i = 0; i < N; ++i) {
-      if (!live[i]) continue;
-      const Node& d = e.nodes[i];
-      if (d.op == N_VAR) {
-        slot[i] = d.a;
-        continue;
-      }
-      if (d.op == N_CONST) continue;
-      std::vector<int> temps;
-      auto operand = [&](int o) {
-        if (e.nodes[o].op == N_CONST) {
-          const int sl = emit_const(e.nodes[o].imm);
-          temps.push_back(sl);
-          return sl;
+      if (d.b >= 0) {
+        if (e.nodes[d.b].op == N_CONST) {
+          I.op |= X_IMMB;
+          I.imm = e.nodes[d.b].imm;
+        } else {
+          I.b = (uint8_t)slot[d.b];
         }
-        return slot[o];
-      };
-      ExprIns ins{};
-      ins.k = d.k;
-      ins.a = (uint8_t)operand(d.a);
-      ins.b = (uint8_t)(d.b >= 0 ? operand(d.b) : 0);
-      // operands read for the last time free their slots (the device reads both
-      // operands before it writes the destination, so the destination may reuse one)
+      }
+    }
+    // values read for the last time free their slots before the result is
+    // placed (an instruction reads its operands before it writes)
+    for (int i : b) {
+      const Node& d = e.nodes[i];
       for (int o : {d.a, d.b})
-        if (o >= 0 && last[o] == i && e.nodes[o].op != N_VAR && e.nodes[o].op != N_CONST && slot[o] >= n) {
+        if (o >= 0 && !leaf(o) && lastb[o] == (int)bi && slot[o] >= n) {
           free_slots.push_back(slot[o]);
           slot[o] = -2;
         }
-      for (int t : temps) free_slots.push_back(t);
-      const int sdst = alloc();
-      slot[i] = sdst;
-      ins.dst = (uint8_t)sdst;
-      switch (d.op) {
-        case N_ADD: ins.op = X_ADD; break;
-        case N_SUB: ins.op = X_SUB; break;
-        case N_MUL: ins.op = X_MUL; break;
-        case N_DIV: ins.op = X_DIV; break;
-        case N_NEG: ins.op = X_NEG; break;
-        case N_LOG: ins.op = X_LOG; break;
-        case N_POWI: ins.op = X_POWI; break;
-        default: ins.op = X_POW; break;
-      }
-      tape.push_back(ins);
     }
-    if (e.nodes[root].op == N_CONST) slot[root] = emit_const(e.nodes[root].imm);
-    out = slot[root];
-    nslots = std::max(top, n);
-    return SDI_OK;
+    for (size_t u = 0; u < b.size(); ++u) {
+      slot[b[u]] = alloc();
+      ins[u].dst = (uint8_t)slot[b[u]];
+      tape.push_back(ins[u]);
+    }
   }
+  if (e.nodes[root].op == N_CONST) {
+    ExprIns c{};
+    c.op = X_CONST;
+    c.imm = e.nodes[root].imm;
+    c.dst = (uint8_t)alloc();
+    slot[root] = c.dst;
+    tape.push_back(c);
+  }
+  while (tape.size() % EXPR_FETCH) {
+    ExprIns nop{};
+    nop.op = X_NOP;
+    tape.push_back(nop);
+  }
+  out = slot[root];
+  nslots = std::max(top, n);
+  return SDI_OK;
 }
-
 
 }  // namespace
 

@@ -4,8 +4,12 @@
 // the host compiler and the HIP kernels (plain C++).
 //
 // Slots 0 .. n-1 hold the point's coordinates x[1] .. x[n]; every instruction
-// writes one slot from up to two others.  The host allocates the remaining
-// slots by liveness, so a slot is rewritten once its value is dead.
+// writes one slot from up to two operands, each a slot or the instruction's
+// constant, reading its operands before it writes.  The host allocates the
+// remaining slots by liveness, so a slot is rewritten once its value is dead
+// (an instruction may write the slot of an operand it reads for the last
+// time).  The tape is padded with X_NOP to a multiple of EXPR_FETCH
+// instructions, the number the device fetches per round of scalar loads.
 #pragma once
 #include <stdint.h>
 
@@ -21,7 +25,13 @@ enum ExprOp : uint8_t {
   X_LOG,         // dst = ln a (NaN for a < 0)
   X_POWI,        // dst = a^k for the integer k (products, then one reciprocal if k < 0)
   X_POW,         // dst = a^b, C pow semantics (NaN for a < 0 and non-integer b)
+  X_NOP,         // nothing (padding)
 };
+
+constexpr uint8_t X_OPMASK = 0x1f;
+constexpr uint8_t X_IMMA = 0x20;     // operand a is the constant imm
+constexpr uint8_t X_IMMB = 0x40;     // operand b is the constant imm
+constexpr int EXPR_FETCH = 8;
 
 struct alignas(16) ExprIns {
   uint8_t op, dst, a, b;

@@ -29,51 +29,45 @@ __device__ __forceinline__ double powi_dev(double x, int k) {
   return k < 0 ? 1.0 / r : r;
 }
 
-// One tape instruction for this lane; R points at the lane's slot 0.
-__device__ __forceinline__ void exec_ins(const ExprIns& I, double* R) {
-  const int a = I.a, b = I.b;
-  double v;
-  switch (I.op) {
-    case X_CONST: v = I.imm; break;
-    case X_ADD: v = R[a * 64] + R[b * 64]; break;
-    case X_SUB: v = R[a * 64] - R[b * 64]; break;
-    case X_MUL: v = R[a * 64] * R[b * 64]; break;
-    case X_DIV: v = R[a * 64] / R[b * 64]; break;
-    case X_NEG: v = -R[a * 64]; break;
-    case X_LOG: v = log(R[a * 64]); break;
-    case X_POWI: v = powi_dev(R[a * 64], I.k); break;
-    case X_POW: v = pow(R[a * 64], R[b * 64]); break;
-    default: v = __builtin_nan(""); break;
+__device__ __forceinline__ double apply_op(int op, double a, double b, int k, double imm) {
+  switch (op) {
+    case X_CONST: return imm;
+    case X_ADD: return a + b;
+    case X_SUB: return a - b;
+    case X_MUL: return a * b;
+    case X_DIV: return a / b;
+    case X_NEG: return -a;
+    case X_LOG: return log(a);
+    case X_POWI: return powi_dev(a, k);
+    case X_POW: return pow(a, b);
+    default: return 0.0;
   }
-  R[I.dst * 64] = v;
 }
 
-__device__ __forceinline__ ExprIns load_ins(CIns* p) {
-  ExprIns r;
-  r.op = p->op;
-  r.dst = p->dst;
-  r.a = p->a;
-  r.b = p->b;
-  r.k = p->k;
-  r.imm = p->imm;
-  return r;
-}
 
-// Runs the tape for one point per lane.  Instructions are fetched eight at a
-// time, so their scalar loads are in flight together (a long tape does not fit
-// the scalar cache, and one fetch per instruction would wait on L2 each time).
+// Runs the tape for one point per lane; R points at the lane's slot 0.
+// Instructions come EXPR_FETCH at a time in one round of scalar loads, and the
+// empty asm statements make every word arrive before the first LDS access:
+// scalar loads and LDS accesses share one wait counter, so a field the
+// compiler loads late (an immediate, say) would otherwise hold up LDS reads.
 __device__ __forceinline__ double run_expr(CIns* ins, int nins, int out, double* R) {
-  int i = 0;
-  for (; i + 8 <= nins; i += 8) {
-    ExprIns I[8];
+  for (int i = 0; i < nins; i += EXPR_FETCH) {
+    const SDI_TAPE uint32_t* wp = (const SDI_TAPE uint32_t*)(ins + i);
+    uint32_t w[4 * EXPR_FETCH];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) I[u] = load_ins(ins + i + u);
+    for (int q = 0; q < 4 * EXPR_FETCH; ++q) w[q] = wp[q];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) exec_ins(I[u], R);
-  }
-  for (; i < nins; ++i) {
-    const ExprIns I = load_ins(ins + i);
-    exec_ins(I, R);
+    for (int q = 0; q < 4 * EXPR_FETCH; ++q) asm volatile("" ::"s"(w[q]));
+#pragma unroll
+    for (int u = 0; u < EXPR_FETCH; ++u) {
+      const uint32_t h = w[4 * u];                     // op, dst, a, b (little endian bytes)
+      const int op = h & X_OPMASK;
+      if (op == X_NOP) continue;
+      const double imm = __builtin_bit_cast(double, (uint64_t)w[4 * u + 2] | ((uint64_t)w[4 * u + 3] << 32));
+      const double a = (h & X_IMMA) ? imm : R[((h >> 16) & 0xff) * 64];
+      const double b = (h & X_IMMB) ? imm : R[(h >> 24) * 64];
+      R[((h >> 8) & 0xff) * 64] = apply_op(op, a, b, (int32_t)w[4 * u + 1], imm);
+    }
   }
   return R[out * 64];
 }
@@ -81,7 +75,8 @@ __device__ __forceinline__ double run_expr(CIns* ins, int nins, int out, double*
 // MODE 0: final pass; MODE 1: warm-up iteration with Vegas histograms.
 // Dynamic LDS: [grid n*(nb+1)] [histogram n*nb] [slots nslots*64].
 template <int MODE>
-__global__ void __launch_bounds__(EXPR_BLOCK) k_tiles_expr(TileArgs A, ExprArgs X) {
+__global__ void __launch_bounds__(EXPR_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) k_tiles_expr(TileArgs A,
+                                                                                               ExprArgs X) {
   extern __shared__ double smem[];
   const int lane = threadIdx.x;
   for (;;) {
