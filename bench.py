@@ -148,8 +148,9 @@ def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, sh
     lattice); then a final pass samples the kept sectors through their flows and
     the rest on the lattice, at each operating point of `finals` (parameter
     sets); its estimate combines, for flow-sampled sectors, the final pass
-    with the pilot pass (`_combine_with_pilot`).  Its GPU time is pilot +
-    training + validation + final pass.  Plain
+    with the pilot pass and with a lattice pass over those sectors at the
+    final size (`_combine_sectors`).  Its GPU time is pilot + training +
+    validation + final pass + that lattice pass.  Plain
     form: lattice passes at each parameter set of `plains`; its error at the
     learned form's time comes from a least-squares power law err = A t^-alpha
     fitted per order to all plain passes (the shift-to-shift error of a
@@ -218,8 +219,11 @@ def equal_time_comparison(P, ctx, name, problem, lambda_max=None, m_pilot=11, sh
         points = []
         for kw in finals:
             fr = run(**kw, sampler=1)
-            t_learned = pilot["ms_total"] + ms_train + ms_val + fr["ms_total"]
-            fval, ef = _combine_with_pilot(pst, _sector_stats(P, ctx, h, ns), kept)
+            fst = _sector_stats(P, ctx, h, ns)
+            lat, ms_lat = _flow_sector_lattice(P, ctx, problem, kept, {**kw, "seed": 8}, common)
+            t_learned = pilot["ms_total"] + ms_train + ms_val + fr["ms_total"] + ms_lat
+            pil = ({s: pst[0][s] for s in range(ns)}, {s: pst[1][s] for s in range(ns)})
+            fval, ef = _combine_sectors(fst, kept, [pil, lat])
             k = int(np.clip(np.searchsorted(t, t_learned), 1, len(t) - 1))
             a = (np.log(t_learned) - np.log(t[k - 1])) / (np.log(t[k]) - np.log(t[k - 1]))
             with np.errstate(divide="ignore", invalid="ignore"):
@@ -263,31 +267,67 @@ def _sector_stats(P, ctx, h, ns):
     return np.array(means), np.array(errs)
 
 
-def _combine_with_pilot(pilot, final, kept):
-    """The learned form's estimate: per sector and order, a sector sampled by its
-    flow in the final pass combines that pass with the pilot lattice pass (two
-    independent estimates of the same sector integral; weights 1/sigma^2, real
-    and imaginary parts apart); the other sectors take the final pass alone.
-    Returns the sum over sectors and its standard error per order."""
+def _combine_pair(m1, e1, m2, e2):
+    """Inverse-variance combination of two independent estimates (complex means,
+    errors (re, im)) of the same quantities, real and imaginary parts apart."""
     import numpy as np
-    (pm, pe), (fm, fe) = pilot, final
+    m = np.zeros_like(m1)
+    e = np.zeros_like(e1)
+    for part, get in ((0, np.real), (1, np.imag)):
+        a, b = get(m1), get(m2)
+        va, vb = e1[..., part] ** 2, e2[..., part] ** 2
+        ok = (va > 0) & (vb > 0)
+        w = np.where(ok, vb / np.where(ok, va + vb, 1.0), np.where(vb > 0, 1.0, 0.0))   # weight of the first
+        c = w * a + (1 - w) * b
+        v = np.where(ok, va * vb / np.where(ok, va + vb, 1.0), np.where(vb > 0, va, vb))
+        m = m + (c if part == 0 else 1j * c)
+        e[..., part] = np.sqrt(v)
+    return m, e
+
+
+def _combine_sectors(final, kept, extra):
+    """The learned form's estimate: a sector sampled by its flow in the final pass
+    combines that pass with every further independent estimate of the same
+    sector in `extra` (the pilot lattice pass; a lattice pass over the flow
+    sectors at the final size), weights 1/sigma^2 per order; the other sectors
+    take the final pass alone.  Returns the sum over sectors and its standard
+    error per order."""
+    import numpy as np
+    fm, fe = final
     val = np.zeros(fm.shape[1], dtype=complex)
     var = np.zeros((fm.shape[1], 2))
     for s in range(fm.shape[0]):
-        if not kept[s]:
-            val += fm[s]
-            var += fe[s] ** 2
-            continue
-        for part, get in ((0, np.real), (1, np.imag)):
-            a, b = get(pm[s]), get(fm[s])
-            va, vb = pe[s][:, part] ** 2, fe[s][:, part] ** 2
-            ok = (va > 0) & (vb > 0)
-            w = np.where(ok, vb / np.where(ok, va + vb, 1.0), 0.0)      # weight of the pilot
-            c = w * a + (1 - w) * b
-            v = np.where(ok, va * vb / np.where(ok, va + vb, 1.0), vb)
-            val += c if part == 0 else 1j * c
-            var[:, part] += v
+        m, e = fm[s], fe[s]
+        if kept[s]:
+            for xm, xe in extra:
+                if s in xm:
+                    m, e = _combine_pair(m, e, xm[s], xe[s])
+        val += m
+        var += e ** 2
     return val, np.sqrt(var[:, 0] + var[:, 1])
+
+
+def _flow_sector_lattice(P, ctx, problem, kept, params, common):
+    """A plain lattice pass over the flow-sampled sectors only (a problem of
+    those sectors, so their shifts are drawn independently of the full
+    problem's): per-sector means and errors keyed by sector, and its device time."""
+    import dataclasses
+    import numpy as np
+    idx = [s for s in range(len(problem.sectors)) if kept[s]]
+    if not idx:
+        return ({}, {}), 0.0
+    sub = dataclasses.replace(problem, sectors=[problem.sectors[s] for s in idx])
+    h = P.sdi_problem_create(ctx, sub)
+    try:
+        _set(P, ctx, **{**common, **params, "sampler": 0})
+        if problem.complex_mode:
+            P.sdi_tune_deformation(ctx, h, problem.lam, 4, 10)
+        P.sdi_integrate(ctx, h)
+        r = P.sdi_integrate(ctx, h)
+        m, e = _sector_stats(P, ctx, h, len(idx))
+    finally:
+        P.sdi_problem_destroy(h)
+    return ({s: m[i] for i, s in enumerate(idx)}, {s: e[i] for i, s in enumerate(idx)}), r["ms_total"]
 
 
 def _learned_pass(P, ctx, h, problem, seed, m_pilot, share, max_sel, iters, batch_log2, lr, final, common):
@@ -317,8 +357,11 @@ def _learned_pass(P, ctx, h, problem, seed, m_pilot, share, max_sel, iters, batc
     ms_train = P.sdi_flow_train(ctx, h, iters, batch_log2, lr, sectors=sel)
     kept, ms_val = P.sdi_flow_validate(ctx, h, m_pilot)
     fr = run(**final, sampler=1)
-    value, err = _combine_with_pilot(pst, _sector_stats(P, ctx, h, ns), kept)
-    return value, err, pilot["ms_total"] + ms_train + ms_val + fr["ms_total"], int(sum(kept))
+    fst = _sector_stats(P, ctx, h, ns)
+    lat, ms_lat = _flow_sector_lattice(P, ctx, problem, kept, {**final, "seed": seed + 7}, common)
+    pil = ({s: pst[0][s] for s in range(ns)}, {s: pst[1][s] for s in range(ns)})
+    value, err = _combine_sectors(fst, kept, [pil, lat])
+    return value, err, pilot["ms_total"] + ms_train + ms_val + fr["ms_total"] + ms_lat, int(sum(kept))
 
 
 def seed_study(P, ctx, name, problem, lambda_max=None, m_pilot=11, share=0.9, max_sel=48, iters=20,
