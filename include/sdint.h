@@ -175,6 +175,14 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* desc, sdi_problem**
  * more than 2^24 operations or ones that need more than 96 live temporaries,
  * SDI_EDEVICE if the upload fails. */
 int sdi_problem_from_text(sdi_ctx* ctx, const char* text, sdi_problem** out);
+
+/* Compiles text as sdi_problem_from_text does, on the host only (no context,
+ * no device): *nvars, *ninstructions (tape length, a multiple of 8) and
+ * *nslots (per-point slots) receive the result when not NULL; on failure the
+ * same status as sdi_problem_from_text and, if err is not NULL, the message
+ * (at most errlen bytes with the NUL). */
+int sdi_text_info(const char* text, int32_t* nvars, int64_t* ninstructions, int32_t* nslots, char* err,
+                  size_t errlen);
 void sdi_problem_destroy(sdi_problem* prob);
 /* Number of result orders K / of sectors of a problem (SDI_EINVAL for NULL). */
 int sdi_problem_norders(const sdi_problem* prob);

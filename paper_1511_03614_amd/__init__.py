@@ -21,7 +21,7 @@ __all__ = [
     "SdiError", "load_library", "library_path", "declared_functions",
     "sdi_ctx_create", "sdi_ctx_destroy", "sdi_last_error", "sdi_device_info",
     "sdi_set_param", "sdi_get_param", "sdi_tune_save", "sdi_tune_load", "sdi_prefactor_feynman", "sdi_lattice_vector",
-    "sdi_problem_create", "sdi_problem_from_text", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_workspace_bytes",
+    "sdi_problem_create", "sdi_problem_from_text", "sdi_text_info", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_workspace_bytes",
     "sdi_integrate", "sdi_sector_results", "sdi_evaluate", "sdi_sample_points",
     "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
     "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_flow_set_active", "sdi_flow_validate",
@@ -108,6 +108,8 @@ def load_library():
         "sdi_lattice_vector": (C.c_int, [i32, i32, C.POINTER(C.c_uint32)]),
         "sdi_problem_create": (C.c_int, [vp, C.POINTER(ProblemDesc), C.POINTER(vp)]),
         "sdi_problem_from_text": (C.c_int, [vp, C.c_char_p, C.POINTER(vp)]),
+        "sdi_text_info": (C.c_int, [C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                    C.c_char_p, C.c_size_t]),
         "sdi_problem_destroy": (None, [vp]),
         "sdi_problem_norders": (C.c_int, [vp]),
         "sdi_problem_nsectors": (C.c_int, [vp]),
@@ -265,6 +267,17 @@ def sdi_problem_from_text(ctx, text: str):
     h = C.c_void_p()
     _check(load_library().sdi_problem_from_text(ctx, text.encode(), C.byref(h)), ctx)
     return h
+
+
+def sdi_text_info(text: str) -> dict:
+    """Host-only compile of a text integrand: {"nvars", "ninstructions", "nslots"};
+    raises SdiError with the parser's message on failure."""
+    n, ni, ns = C.c_int32(), C.c_int64(), C.c_int32()
+    buf = C.create_string_buffer(512)
+    rc = load_library().sdi_text_info(text.encode(), C.byref(n), C.byref(ni), C.byref(ns), buf, 512)
+    if rc != 0:
+        raise SdiError(rc, buf.value.decode())
+    return {"nvars": n.value, "ninstructions": ni.value, "nslots": ns.value}
 
 
 def sdi_problem_destroy(prob):

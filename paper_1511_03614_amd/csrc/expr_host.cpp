@@ -11,6 +11,7 @@
 // temporaries are assigned to slots by liveness.
 #include <hip/hip_runtime.h>
 
+#include <cctype>
 #include <charconv>
 #include <cmath>
 #include <cstring>
@@ -492,6 +493,24 @@ int compile_expression(const std::string& text, int& n, std::vector<ExprIns>& ta
 }  // namespace sdi
 
 using namespace sdi;
+
+extern "C" int sdi_text_info(const char* text, int32_t* nvars, int64_t* ninstructions, int32_t* nslots, char* err,
+                             size_t errlen) {
+  if (err && errlen) err[0] = '\0';
+  if (!text) return SDI_EINVAL;
+  int n = 0, ns = 0, oslot = 0;
+  std::vector<ExprIns> tape;
+  std::string msg;
+  const int rc = compile_expression(std::string(text), n, tape, ns, oslot, msg);
+  if (rc != SDI_OK) {
+    if (err && errlen) snprintf(err, errlen, "%s", msg.c_str());
+    return rc;
+  }
+  if (nvars) *nvars = n;
+  if (ninstructions) *ninstructions = (int64_t)tape.size();
+  if (nslots) *nslots = ns;
+  return SDI_OK;
+}
 
 extern "C" int sdi_problem_from_text(sdi_ctx* ctx, const char* text, sdi_problem** out) {
   if (!ctx || !text || !out) return fail(ctx, SDI_EINVAL, "problem_from_text: null argument");
