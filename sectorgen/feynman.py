@@ -225,3 +225,60 @@ def massive_bubble_problem(s: float = 5.0, m2: float = 1.0, lam: float = 0.5) ->
     return Problem(sectors=secs, order_min=-1, order_max=1,
                    feynman=FeynmanPrefactor(1, (1, 1), 4), complex_mode=True, lam=lam,
                    name="massive_bubble")
+
+
+def bisect_sector(sec: Sector, j: int, p: float = 0.5) -> List[Sector]:
+    """Splits the integration over x_j at p (the BisectionVariables option of
+    section 4.4, bisection point p): the lower part maps x_j = p y, the upper
+    part x_j = 1 - (1 - p) y, so that x_j = 1 becomes the endpoint y = 0 of the
+    new variable.  The Jacobians go into the coefficient; the monomial
+    x_j^(a + b eps) becomes p^(a + b eps) y^(a + b eps) (a constant factor) in
+    the lower part and a regular factor (1 - (1 - p) y)^(a + b eps) in the
+    upper part; polynomial terms are substituted and expanded.  Returns
+    [lower, upper]; their integrals add up to the sector's."""
+    import math as _m
+    n = sec.n
+    c = 1.0 - p
+    a_j, b_j = float(sec.a[j]), float(sec.b[j])
+    lower_f, upper_f = [], []
+    for f in sec.factors:
+        lc = f.coef * np.array([p ** int(e[j]) for e in f.exps])
+        lower_f.append(Factor(f.gamma, f.delta, lc, f.exps.copy()))
+        terms = {}
+        for coef, e in zip(f.coef, f.exps):
+            for k in range(int(e[j]) + 1):
+                ne = list(int(v) for v in e)
+                ne[j] = k
+                terms[tuple(ne)] = terms.get(tuple(ne), 0.0) + coef * _m.comb(int(e[j]), k) * (-c) ** k
+        keys = sorted(terms, key=lambda t: (sum(t), t))
+        keys = [t for t in keys if terms[t] != 0.0]
+        zero = tuple([0] * n)
+        if zero in keys:                       # the constant term first, as the generators write it
+            keys.remove(zero)
+            keys.insert(0, zero)
+        upper_f.append(Factor(f.gamma, f.delta, np.array([terms[t] for t in keys]),
+                              np.array(keys, dtype=np.uint8).reshape(len(keys), n)))
+    lower_a, lower_b = sec.a.copy(), sec.b.copy()
+    upper_a, upper_b = sec.a.copy(), sec.b.copy()
+    upper_a[j], upper_b[j] = 0.0, 0.0
+    if a_j != 0.0 or b_j != 0.0:
+        lower_f.append(Factor(a_j, b_j, np.array([p]), np.zeros((1, n), dtype=np.uint8)))
+        e1 = np.zeros((2, n), dtype=np.uint8)
+        e1[1, j] = 1
+        upper_f.append(Factor(a_j, b_j, np.array([1.0, -c]), e1))
+    mono = None if sec.deform_mono is None else sec.deform_mono.copy()
+    lower = Sector(a=lower_a, b=lower_b, factors=lower_f, coeff=complex(sec.coeff) * p,
+                   deform_factor=sec.deform_factor, deform_mono=mono)
+    upper = Sector(a=upper_a, b=upper_b, factors=upper_f, coeff=complex(sec.coeff) * c,
+                   deform_factor=sec.deform_factor, deform_mono=None if mono is None else mono.copy())
+    return [lower, upper]
+
+
+def bisect_problem(problem: Problem, variables: Sequence[int], p: float = 0.5) -> Problem:
+    """Every sector bisected at p in each variable of `variables` in turn
+    (2^len(variables) parts per sector)."""
+    import dataclasses
+    secs = list(problem.sectors)
+    for j in variables:
+        secs = [part for s in secs for part in bisect_sector(s, j, p)]
+    return dataclasses.replace(problem, sectors=secs)
