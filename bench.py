@@ -73,25 +73,61 @@ def sector_work(sec, order_max: int, pref_lead: int, use_grid: bool):
     return fl, logs
 
 
-def cpu_baseline(problem, m: int) -> dict:
-    """The oracle as it stands, on all sectors, one shift of 2^m lattice points each."""
+_CPU_PROBLEM = None
+
+
+def _cpu_init():
+    global _CPU_PROBLEM
+    import sectorgen
+    _CPU_PROBLEM = sectorgen.config2()
+
+
+def _cpu_task(task):
+    """The oracle on one (sector, shift) of 2^m lattice points; returns the evaluations."""
     import numpy as np
     from oracle import integrand, integrate, points
+    s, r, m = task
+    problem = _CPU_PROBLEM
     lead, pref = integrate.prefactor_for(problem)
-    evals = 0
-    t0 = time.perf_counter()
-    for s, sec in enumerate(problem.sectors):
-        z = points.cbc_vector(m, sec.n)
-        sh = points.shift_table(1, s, 1, sec.n, m)[0]
-        x, w, _ = points.sector_points(z, m, sh, 0, 1 << m)
-        vals, _, _ = integrand.sector_orders(sec, x, problem.order_min, problem.order_max, lead, pref)
-        q = [integrate.fsum_c(v) for v in vals * w[None, :]]
-        evals += 1 << m
-        assert np.all(np.isfinite(q))
-    dt = time.perf_counter() - t0
-    return {"value": evals / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"all {len(problem.sectors)} sectors x 1 shift x 2^{m} lattice points "
-                      f"({evals} evals, {dt:.1f} s, numpy fp64 single thread)"}
+    sec = problem.sectors[s]
+    z = points.cbc_vector(m, sec.n)
+    sh = points.shift_table(1, s, r + 1, sec.n, m)[r]
+    x, w, _ = points.sector_points(z, m, sh, 0, 1 << m)
+    vals, _, _ = integrand.sector_orders(sec, x, problem.order_min, problem.order_max, lead, pref)
+    q = [integrate.fsum_c(v) for v in vals * w[None, :]]
+    assert np.all(np.isfinite(q))
+    return 1 << m
+
+
+def cpu_baseline(m: int, shifts: int = 16, workers: int = 0) -> dict:
+    """The oracle as it stands on the host's cores: every (sector, shift) of the
+    workload's final pass (all 64 sectors x `shifts` shifts x 2^m lattice points)
+    spread over a process pool, timed on the wall clock.  Runs in a process that
+    has not touched the GPU (bench.py starts it before its own GPU work)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import sectorgen
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    ns = len(sectorgen.config2().sectors)
+    tasks = [(s, r, m) for s in range(ns) for r in range(shifts)]
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork"), initializer=_cpu_init) as ex:
+        list(ex.map(_cpu_task, [(0, 0, 8)] * workers))           # start every worker before the clock
+        t0 = time.perf_counter()
+        evals = sum(ex.map(_cpu_task, tasks, chunksize=4))
+        dt = time.perf_counter() - t0
+    return {"value": evals / dt, "unit": "evals/s", "cores": workers, "kind": "oracle",
+            "sample": f"all {ns} sectors x {shifts} shifts x 2^{m} lattice points ({evals} evals, {dt:.1f} s wall, "
+                      f"numpy fp64, {workers} worker processes)"}
+
+
+def _cpu_baseline_subprocess(m: int) -> dict:
+    """cpu_baseline in a child interpreter, started before this process uses the GPU."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-log2", str(m)],
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"value": None, "error": r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def traffic_from_profiles(ms_kernel: float):
@@ -481,17 +517,23 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-log2", type=int, default=16)
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--tune-load", default=None,
                     help="load autotuner decisions (sdi_tune_load) before the run, so profiles time the same instance")
     ap.add_argument("--tune-save", default=None, help="save the autotuner decisions of the run (sdi_tune_save)")
     ap.add_argument("--no-equal-time", action="store_true",
                     help="skip the learned-sampler comparison (double box, Euclidean and physical)")
     args = ap.parse_args()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(args.cpu_log2)), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py: this benchmark measures one GPU only (asked for --gpus {args.gpus}); "
               "sectors would shard across GPUs by longest-processing-time assignment, but no multi-GPU run is made.",
               file=sys.stderr)
         return 2
+    # the oracle's CPU rate first, in a child process, before anything here touches the GPU
+    cpu = None if args.no_cpu_baseline else _cpu_baseline_subprocess(args.cpu_log2)
     import numpy as np
     import torch
     import paper_1511_03614_amd as P
@@ -585,8 +627,8 @@ def main() -> int:
                        double_box_problem(5.0, -2.0, 1.0, order_max=0, complex_mode=True, lam=0.5), lambda_max=0.5),
         ]
     P.sdi_ctx_destroy(ctx)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(problem, args.cpu_log2)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 
