@@ -449,15 +449,22 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
 // tile_log2 = 0 every size from 2^10 to 2^14 points (2^6 to 2^10 for text
 // integrands, whose blocks are one wave) that is not longer than the longest
 // lattice (a tile never exceeds its sector's lattice, so larger sizes would
-// repeat a plan), largest first.  Without tuning the automatic size is 2^14
+// repeat a plan) and gives at most about 2^20 tiles, largest first.  Without tuning the automatic size is 2^14
 // (2^6 for text integrands: one tile per wave-step keeps every wave busy).
 std::vector<int> tile_candidates(const sdi_problem* pb, const Params& prm, const std::vector<int>& msec) {
   if (prm.tile_log2 > 0) return {prm.tile_log2};
   const int top = pb->is_expr() ? 10 : 14;
   if (prm.tune == 0) return {pb->is_expr() ? 6 : 14};
   int mmax = 4;
-  for (int m : msec) mmax = std::max(mmax, m);
-  const int hi = std::min(top, mmax), lo = std::min(top - 4, hi);
+  double total = 0.0;   // points of one pass
+  for (int m : msec) {
+    mmax = std::max(mmax, m);
+    total += std::ldexp((double)prm.R, m);
+  }
+  const int hi = std::min(top, mmax);
+  int lo = std::min(top - 4, hi);
+  // smaller tiles than needed for 2^20 tiles only add plan and partial-sum size
+  while (lo < hi && total / std::ldexp(1.0, lo) > (double)(1 << 20)) ++lo;
   std::vector<int> v;
   for (int t = hi; t >= lo; --t) v.push_back(t);
   return v;
