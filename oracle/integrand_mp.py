@@ -1,0 +1,138 @@
+"""Oracle: the eps-expanded sector integrand at single points in multiprecision.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The same formula as oracle.integrand.sector_f (pole subtraction at x_j = 0 for
+j in S, eps expansion of x_j^(b_j eps) and G = G0 exp(eps Lambda); section 1
+and eq. (2)), real mode, evaluated with mpmath.  The corner terms near a face
+x_j -> 0 cancel by at most about log10(1/x_j) digits per singular variable, so
+the working precision is 40 decimal digits plus sum_{j in S} log10(1/x_j) at
+each point (or a fixed `dps`): the result keeps well over 32 correct digits,
+which makes it the exact value against which a double-double evaluation is
+judged.  This plays the part of the paper's MPFR evaluation below the SmallX
+threshold (section 4.6, mixed arithmetic).
+
+Parity unpinned by the paper itself (it prints no near-face values); pinned in
+tests/test_oracle_mp.py against the fp64 oracle where fp64 is accurate, against
+closed forms of one- and two-variable sectors that stay exact at the faces, and
+against itself at a higher precision.
+"""
+from __future__ import annotations
+
+from typing import Sequence
+
+import mpmath
+import numpy as np
+
+from .integrand import singular_set
+
+
+def _poly_mp(coef, exps, y):
+    """sum_t coef_t prod_j y_j^exps_tj with mpf arithmetic (coefficients are exact binary values)."""
+    s = mpmath.mpf(0)
+    for t in range(coef.shape[0]):
+        m = mpmath.mpf(float(coef[t]))
+        for j, e in enumerate(exps[t]):
+            if e:
+                m *= y[j] ** int(e)
+        s += m
+    return s
+
+
+def point_dps(sector, x: Sequence[float]) -> int:
+    """40 digits plus what the corner terms at x can cancel."""
+    S = singular_set(sector)
+    return 40 + int(np.ceil(sum(max(0.0, -np.log10(float(x[j]))) for j in S)))
+
+
+def sector_f_point(sector, x: Sequence[float], kf_max: int, dps: int = 0):
+    """f_k(x) for k = -|S| .. kf_max at one point, as mpf values, and the sums
+    of |term| per order (cond), both lists indexed k + |S|; dps 0: point_dps."""
+    S = singular_set(sector)
+    ns = len(S)
+    dps = dps or point_dps(sector, x)
+    nonS = [j for j in range(sector.n) if j not in S]
+    korders = kf_max + ns + 1
+    with mpmath.workdps(dps):
+        xm = [mpmath.mpf(float(v)) for v in x]
+        lnx = [mpmath.log(v) for v in xm]
+        mono = mpmath.mpf(1)
+        lrest = mpmath.mpf(0)
+        for j in nonS:
+            mono *= mpmath.power(xm[j], mpmath.mpf(float(sector.a[j])))
+            lrest += mpmath.mpf(float(sector.b[j])) * lnx[j]
+        f = [mpmath.mpf(0)] * korders
+        cond = [mpmath.mpf(0)] * korders
+        for wmask in range(1 << ns):
+            y = list(xm)
+            for i in range(ns):
+                if wmask >> i & 1:
+                    y[S[i]] = mpmath.mpf(0)
+            g0 = mpmath.mpf(1)
+            lam = mpmath.mpf(0)
+            for fac in sector.factors:
+                p = _poly_mp(fac.coef, fac.exps, y)
+                lp = mpmath.log(p) if p > 0 else mpmath.mpf("nan")
+                g0 *= mpmath.power(p, mpmath.mpf(float(fac.gamma)))
+                lam += mpmath.mpf(float(fac.delta)) * lp
+            tmask = wmask
+            while True:
+                sign = -1 if bin(wmask & ~tmask).count("1") % 2 else 1
+                nt = bin(tmask).count("1")
+                coef = mpmath.mpf(sign)
+                lt = lrest
+                for i in range(ns):
+                    j = S[i]
+                    if tmask >> i & 1:
+                        coef /= mpmath.mpf(float(sector.b[j]))
+                    else:
+                        coef /= xm[j]
+                        lt += mpmath.mpf(float(sector.b[j])) * lnx[j]
+                base = coef * mono * g0
+                zz = lt + lam
+                for k in range(-ns, kf_max + 1):
+                    q = k + nt
+                    if q < 0:
+                        continue
+                    term = base * zz ** q / mpmath.factorial(q)
+                    f[k + ns] += term
+                    cond[k + ns] += abs(term)
+                if tmask == 0:
+                    break
+                tmask = (tmask - 1) & wmask
+        return f, cond
+
+
+def sector_orders_mp(sector, x: np.ndarray, order_min: int, order_max: int, pref_lead: int,
+                     pref: Sequence[float], dps: int = 0):
+    """F_k(x) = c_s sum_i Pi_i f_{k - lead - i}(x), k = order_min .. order_max, real
+    mode, at every point of x (npts, n): the multiprecision values rounded once to
+    fp64 (K, npts), the term sums cond (K, npts) as in oracle.integrand, and
+    foldabs (K, npts) = sum_i |c_s Pi_i f_{k-lead-i}| (what an fp64 fold of exact
+    f values can lose: a few ulp of it)."""
+    S = singular_set(sector)
+    ns = len(S)
+    kf_max = order_max - pref_lead
+    K = order_max - order_min + 1
+    npts = x.shape[0]
+    cplx = any(complex(v).imag != 0.0 for v in pref) or complex(sector.coeff).imag != 0.0
+    vals = np.zeros((K, npts), dtype=np.complex128 if cplx else np.float64)
+    cnd = np.zeros((K, npts))
+    fabs_ = np.zeros((K, npts))
+    cs = complex(sector.coeff)
+    for p in range(npts):
+        d = dps or point_dps(sector, x[p])
+        f, cond = sector_f_point(sector, x[p], max(kf_max, -ns), d)
+        with mpmath.workdps(d):
+            for ki, k in enumerate(range(order_min, order_max + 1)):
+                v = mpmath.mpc(0)
+                for i, pv in enumerate(pref):
+                    kk = k - pref_lead - i
+                    if kk < -ns or kk > kf_max:
+                        continue
+                    t = mpmath.mpc(cs) * mpmath.mpc(complex(pv)) * f[kk + ns]
+                    v += t
+                    cnd[ki, p] += abs(cs) * abs(complex(pv)) * float(cond[kk + ns])
+                    fabs_[ki, p] += float(abs(t))
+                vals[ki, p] = complex(v) if cplx else float(v.real)
+    return vals, cnd, fabs_
