@@ -90,6 +90,16 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *   pilot_log2     lattice log2 of the pilot pass               (default 12)
  *   sampler        0: shifted lattice (+ Vegas grid), 1: the learned flow of
  *                  sdi_flow_init (warmup must be 0)             (default 0)
+ *   small_x        endpoint precision, a number in [0, 1] (decimal or
+ *                  exponent notation): in real mode, points whose smallest
+ *                  singular coordinate lies below it are evaluated in
+ *                  double-double arithmetic (about 106 bits) and rounded to
+ *                  fp64 once, by sdi_evaluate and by the lattice final pass,
+ *                  which then runs one instance (1 point per thread, 2 waves
+ *                  per SIMD) in place of the tuned variants; the role of the
+ *                  SmallX / MPThreshold switch to MPFR of section 4.6.  The
+ *                  warm-up, flow-sampled points, complex mode and text
+ *                  integrands stay in fp64.  0 = off         (default 0)
  * Unknown keys or malformed values return SDI_EINVAL. */
 int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value);
 int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len);

@@ -94,6 +94,15 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
     else return fail(ctx, SDI_EINVAL, "tune must be off, cached or search");
     return SDI_OK;
   }
+  if (k == "small_x") {
+    char* e = nullptr;
+    errno = 0;
+    const double d = strtod(value, &e);
+    if (errno || !e || *e != '\0' || e == value || !(d >= 0.0 && d <= 1.0))
+      return fail(ctx, SDI_EINVAL, "small_x must be a number in [0, 1]");
+    p.small_x = d;
+    return SDI_OK;
+  }
   char* end = nullptr;
   errno = 0;
   const long long iv = strtoll(value, &end, 10);
@@ -156,6 +165,9 @@ int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len) {
   long long v;
   if (k == "tune") {
     snprintf(buf, len, "%s", p.tune == 0 ? "off" : (p.tune == 1 ? "cached" : "search"));
+    return SDI_OK;
+  } else if (k == "small_x") {
+    snprintf(buf, len, "%.17g", p.small_x);
     return SDI_OK;
   } else if (k == "lattice_log2") v = p.m;
   else if (k == "shifts") v = p.R;
@@ -477,6 +489,7 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_d
   A.out = (double*)out_dev;
   A.npts = npts;
   A.cond = (double*)cond_dev;
+  A.small_x = (pb->complex_mode || pb->is_expr()) ? 0.0 : ctx->params.small_x;
   if (pb->is_expr())
     KCHK(ctx, launch_eval_points_expr(A, ExprArgs{pb->d_expr, (int32_t)pb->expr_nins, pb->expr_slots, pb->expr_out},
                                       ctx->stream));

@@ -21,6 +21,7 @@ namespace sdi {
 struct Plan {
   int R = 0, rows = 0;
   int tile_log2 = 14;            // points per final-pass tile (log2; shorter lattices make one tile)
+  double small_x = 0.0;          // endpoint-precision threshold of the lattice final pass (0: off)
   bool warm = false;
   bool flow = false;             // final points come from the learned sampler
   std::vector<PointRun> fruns;   // per final tile: its points in the flow buffers
@@ -139,6 +140,7 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   P.rows = prm.R + prm.warmup;
   P.warm = warm && prm.warmup > 0;
   P.flow = prm.sampler == 1;
+  P.small_x = (prm.small_x > 0.0 && !pb->complex_mode && !pb->is_expr()) ? prm.small_x : 0.0;
   if (P.flow && !pb->flow) return fail(ctx, SDI_ESTATE, "sampler flow needs sdi_flow_init on this problem");
   if (P.flow && prm.warmup > 0) return fail(ctx, SDI_ENOTSUP, "the flow sampler replaces the Vegas warm-up (set warmup 0)");
   P.msec = msec;
@@ -308,6 +310,14 @@ std::vector<int> tile_variants(const sdi_problem* pb) {
   return {14, 23, 24, 42};
 }
 
+// The endpoint-precision instance (real mode, small_x > 0): one point per
+// thread, at least 2 waves per SIMD; the only final-pass variant of that mode.
+constexpr int DD_VARIANT = 12;
+
+bool uses_dd(const sdi_problem* pb, const Params& p) {
+  return p.small_x > 0.0 && !pb->complex_mode && !pb->is_expr();
+}
+
 // The variant used for a fixed points-per-thread request.
 int default_variant(const sdi_problem* pb, int ppt) {
   if (pb->is_expr()) return 11;   // one point per lane and step
@@ -318,6 +328,7 @@ int default_variant(const sdi_problem* pb, int ppt) {
 // Whether an encoded variant is one the tuner or a points-per-thread request
 // can select for the problem's class.
 bool variant_known(const sdi_problem* pb, int v) {
+  if (v == DD_VARIANT && !pb->complex_mode && !pb->is_expr()) return true;
   for (int u : tile_variants(pb))
     if (u == v) return true;
   for (int p : {1, 2, 4})
@@ -329,15 +340,17 @@ int launch_tiles(const sdi_problem* pb, int ppt, int wpe, int km, int grid, size
                  hipStream_t st) {
   if (pb->is_expr()) return launch_tiles_expr(grid, shmem, a, expr_args(pb), st);
   if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, wpe, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
+  if (a.mode == 0 && a.small_x > 0.0) return launch_tiles_real_dd(km, grid, shmem, a, st);
   return launch_tiles_real(pb->nvmax, pb->nsmax, ppt, wpe, km, grid, shmem, a, st);
 }
 
 int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int wpe, int km, size_t shmem,
                     size_t ntiles) {
   const int nvmax = pb->nvmax;
-  int occ = pb->is_expr()      ? tiles_expr_occupancy(mode, shmem, expr_args(pb))
-            : pb->complex_mode ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, shmem)
-                               : tiles_real_occupancy(nvmax, pb->nsmax, mode, ppt, wpe, km, shmem);
+  int occ = pb->is_expr()                             ? tiles_expr_occupancy(mode, shmem, expr_args(pb))
+            : pb->complex_mode                        ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, shmem)
+            : mode == 0 && uses_dd(pb, ctx->params) ? occupancy_tiles_real_dd(km, shmem)
+                                                      : tiles_real_occupancy(nvmax, pb->nsmax, mode, ppt, wpe, km, shmem);
   if (occ < 1) occ = 1;
   const size_t g = (size_t)occ * std::max(ctx->ncu, 1);
   return (int)std::max<size_t>(1, std::min(g, ntiles));
@@ -347,9 +360,9 @@ std::string pass_key(const Params& p, const std::vector<int>& msec, bool warm, c
   char buf[320];
   unsigned long long h = 1469598103934665603ull;
   for (int m : msec) h = (h ^ (unsigned)m) * 1099511628211ull;
-  snprintf(buf, sizeof buf, "R%d s%llu b%d w%d/%d mw%d nb%d t%d p%d g%d f%d m%llx ws%p:%zu", p.R,
+  snprintf(buf, sizeof buf, "R%d s%llu b%d w%d/%d mw%d nb%d t%d p%d g%d f%d x%.17g m%llx ws%p:%zu", p.R,
            (unsigned long long)p.seed, p.baker, p.warmup, (int)warm, p.mw, p.nbins, p.tile_log2, p.ppt, p.graph,
-           p.sampler, h, ws, wsb);
+           p.sampler, p.small_x, h, ws, wsb);
   return buf;
 }
 
@@ -377,6 +390,7 @@ TileArgs final_args(const sdi_problem* pb, const Plan& P, bool flow = false) {
   F.pw = P.d_pw;
   F.x_off = P.d_fx_off;
   F.pt_off = P.d_fpt_off;
+  F.small_x = flow ? 0.0 : P.small_x;
   return F;
 }
 
@@ -570,10 +584,10 @@ std::string tune_key(const sdi_ctx* ctx, const sdi_problem* pb, const std::vecto
   if (p.sampler == 1 && pb->flow)
     for (uint8_t a : pb->flow->active) h = (h ^ a) * 1099511628211ull;
   char buf[320];
-  snprintf(buf, sizeof buf, "%s|c%d|x%d|nv%d|ns%d|kf%d|sec%d|terms%zu|m%llx|R%d|w%d|t%d|p%d|s%d",
+  snprintf(buf, sizeof buf, "%s|c%d|x%d|nv%d|ns%d|kf%d|sec%d|terms%zu|m%llx|R%d|w%d|t%d|p%d|s%d|d%d",
            ctx->prop.gcnArchName, pb->complex_mode, (int)pb->is_expr(), pb->nvmax, pb->nsmax, pb->kfmax, pb->nsec,
            pb->is_expr() ? pb->expr_nins : pb->terms.size(), h, p.R, (int)(warm && p.warmup > 0), p.tile_log2, p.ppt,
-           p.sampler);
+           p.sampler, (int)uses_dd(pb, p));
   return buf;
 }
 
@@ -664,7 +678,9 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   }
   const std::vector<int> tiles = tile_candidates(pb, prm, msec);
   TuneChoice ch{tiles.front(), -1};
-  if (prm.ppt > 0)
+  if (uses_dd(pb, prm))
+    ch.variant = DD_VARIANT;
+  else if (prm.ppt > 0)
     ch.variant = default_variant(pb, prm.ppt);
   else if (prm.tune == 0)
     ch.variant = (pb->complex_mode || pb->is_expr()) ? 11 : 24;

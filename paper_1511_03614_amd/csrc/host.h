@@ -56,6 +56,7 @@ struct Params {
   int alloc_max = 20;
   int pilot_log2 = 12;   // lattice log2 of the pilot pass that measures the variances
   int sampler = 0;       // 0: lattice (+ Vegas grid), 1: the learned flow
+  double small_x = 0.0;  // real mode: double-double below this smallest singular coordinate (0: off)
 };
 
 // One autotuner decision: final-pass tile size and launch variant

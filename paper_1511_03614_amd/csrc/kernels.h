@@ -48,6 +48,11 @@ int launch_tiles_real(int nvmax, int nsmax, int ppt, int wpe, int km, int grid, 
 int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st);
 // Occupancy (resident blocks per CU) of a tile kernel instance; 0 if not built.
 int tiles_real_occupancy(int nvmax, int nsmax, int mode, int ppt, int wpe, int km, size_t shmem);
+// Final pass (a.mode 0) of the endpoint-precision mode: every variable class,
+// one point per thread, points with a singular coordinate below a.small_x
+// evaluated in double-double.  km 4 or 8.
+int launch_tiles_real_dd(int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int occupancy_tiles_real_dd(int km, size_t shmem);
 
 // Complex mode: nvmax 4 or 8; cx is the CplxDev array (tile kernel) or one sector's
 // record (point evaluation); dir the derivative-list directory.

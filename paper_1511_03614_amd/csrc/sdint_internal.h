@@ -101,6 +101,8 @@ struct TileArgs {
   const double* pw;          //         and their weights at pw + pt_off[t]
   const int64_t* x_off;
   const int64_t* pt_off;
+  double small_x;            // mode 0: points whose smallest singular coordinate is below it
+                             // are evaluated in double-double (0: never)
 };
 
 // A run of points of one sector (explicit-point passes and flow batches):
@@ -134,6 +136,7 @@ struct EvalArgs {            // explicit points (justEvaluate / parity)
   double* out;               // [npts][K][2]
   int64_t npts;
   double* cond;              // [npts][K] sums of |term| per result order, or null
+  double small_x;            // double-double below this smallest singular coordinate (0: never)
 };
 
 struct SampleArgs {

@@ -7,11 +7,11 @@
 // its own partial sums (and, in warm-up, its own Vegas histogram), so the
 // result does not depend on which block ran which tile.
 #pragma once
-#include "eval_real.hpp"
+#include "eval_dd.hpp"
 
 namespace sdi {
 
-template <int NV, int PPT, int KM, int MODE, int NSM>
+template <int NV, int PPT, int KM, int MODE, int NSM, bool DD>
 __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
                                               const TileDesc& td, int tc, const double* __restrict__ lgrid,
                                               double* __restrict__ lhist, double (&s)[KM],
@@ -43,6 +43,19 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
     }
     double f[PPT][KM];
     eval_f_real<NV, PPT, KM, NSM>(S, tape(A.terms), x, f);
+    if constexpr (DD) {
+      // points near a face of a singular variable: again, in double-double
+      const int ns = S->ns;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        if (near_face<NV>(x[p], ns, A.small_x)) {
+          double xd[NV], cd[KM];
+#pragma unroll
+          for (int j = 0; j < NV; ++j) xd[j] = x[p][j];
+          eval_f_real_dd<KM>(S, tape(A.terms), xd, f[p], cd);
+        }
+      }
+    }
     const int kf = S->kf;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -75,7 +88,9 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
 // autotuner picks it with PPT; occupancy pays more than a few spills here).
 // NSM: bound on the singular variables of every sector of the launch (the
 // final pass has NSM = 2 instances for problems without deeper poles).
-template <int NVMAX, int PPT, int KM, int MODE, int WPE, int NSM = MAXS>
+// DD: points closer to a singular face than A.small_x are evaluated again in
+// double-double (the final-pass instances of the endpoint-precision mode).
+template <int NVMAX, int PPT, int KM, int MODE, int WPE, int NSM = MAXS, bool DD = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_tiles_real(TileArgs A) {
   extern __shared__ double smem[];
   __shared__ int s_tile;
@@ -119,16 +134,16 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
     const int cls = S->cls;
     switch (cls) {
       case 0:
-        run_tile_real<4, PPT, KM, MODE, NSM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        run_tile_real<4, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       case 1:
         if constexpr (NVMAX == 6)
-          run_tile_real<6, PPT, KM, MODE, NSM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+          run_tile_real<6, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         else if constexpr (NVC >= 1)
-          run_tile_real<8, PPT, KM, MODE, NSM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+          run_tile_real<8, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       case 2:
-        if constexpr (NVC >= 2) run_tile_real<16, PPT, KM, MODE, NSM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        if constexpr (NVC >= 2) run_tile_real<16, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
         break;
       default:
         break;
@@ -189,6 +204,12 @@ __device__ __forceinline__ void eval_point_real(const EvalArgs& A, int64_t i) {
     eval_f_real_c<NV, 1, KM, true>(S, tape(A.terms), x, f, cnd);
   else
     eval_f_real<NV, 1, KM>(S, tape(A.terms), x, f);
+  if (A.small_x > 0.0 && near_face<NV>(x[0], S->ns, A.small_x)) {
+    double xd[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) xd[j] = x[0][j];
+    eval_f_real_dd<KM>(S, tape(A.terms), xd, f[0], cnd[0]);
+  }
   for (int k = 0; k < K; ++k) {
     double fr = 0.0, fi = 0.0, cs = 0.0;
 #pragma unroll

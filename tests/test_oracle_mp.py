@@ -14,8 +14,11 @@ reference for the double-double evaluation of points near the faces x_j = 0.
 * Away from the faces the fp64 oracle is accurate to its rounding bound; the
   multiprecision values agree with it there, at the largest accepted shapes.
 * The value does not depend on the working precision beyond 32 digits.
+* The ln 2 split used by the device double-double exp is ln 2 to 106 bits.
 """
 import math
+import re
+from pathlib import Path
 
 import mpmath
 import numpy as np
@@ -155,3 +158,14 @@ def test_orders_fold_matches_fp64_oracle():
     assert vmp.dtype == np.complex128
     assert np.all(np.abs(vmp - v64) <= 8 * U * c64 + 4 * U * fabs_)
     np.testing.assert_allclose(cmp_, c64, rtol=1e-12)
+
+
+def test_device_ln2_split():
+    src = (Path(__file__).resolve().parents[1] / "paper_1511_03614_amd" / "csrc" / "eval_dd.hpp").read_text()
+    hi = float.fromhex(re.search(r"LN2_HI = (0x[0-9a-fp.+-]+);", src).group(1))
+    lo = float.fromhex(re.search(r"LN2_LO = (0x[0-9a-fp.+-]+);", src).group(1))
+    with mpmath.workdps(60):
+        ln2 = mpmath.log(2)
+        assert hi == float(ln2)
+        assert lo == float(ln2 - mpmath.mpf(hi))
+        assert abs(mpmath.mpf(hi) + mpmath.mpf(lo) - ln2) <= mpmath.mpf(2) ** -106
