@@ -589,7 +589,7 @@ def main() -> int:
                    "waves_per_simd": r["waves_per_simd"], "tile_log2": r["tile_log2"], "blocks": r["blocks"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": traffic_from_profiles(ms_k),
-                     "kernel": f"k_tiles_real<6, {r['ppt']}, 4, 0, {r['waves_per_simd']}, 2> (final pass)",
+                     "kernel": f"k_tiles_real<6, {r['ppt']}, 4, 0, {r['waves_per_simd']}, 2, false> (final pass)",
                      "ms_per_launch": ms_k,
                      "flops_per_launch": fl_launch, "logs_per_s": logs_launch / (ms_k * 1e-3)},
         "error_vs_plain_qmc": None,
