@@ -94,9 +94,10 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *                  exponent notation): in real mode, points whose smallest
  *                  singular coordinate lies below it are evaluated in
  *                  double-double arithmetic (about 106 bits) and rounded to
- *                  fp64 once, by sdi_evaluate and by the lattice final pass,
- *                  which then runs one instance (1 point per thread, 2 waves
- *                  per SIMD) in place of the tuned variants; the role of the
+ *                  fp64 once, by sdi_evaluate and by the lattice final pass
+ *                  (problems with at most 2 singular variables per sector
+ *                  keep the tuned launch variants; deeper ones run one
+ *                  instance, 1 point per thread, 2 waves per SIMD); the role of the
  *                  SmallX / MPThreshold switch to MPFR of section 4.6.  The
  *                  warm-up, flow-sampled points, complex mode and text
  *                  integrands stay in fp64.  0 = off         (default 0)

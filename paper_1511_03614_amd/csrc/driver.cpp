@@ -310,8 +310,10 @@ std::vector<int> tile_variants(const sdi_problem* pb) {
   return {14, 23, 24, 42};
 }
 
-// The endpoint-precision instance (real mode, small_x > 0): one point per
-// thread, at least 2 waves per SIMD; the only final-pass variant of that mode.
+// The endpoint-precision instance for problems with a sector of more than 2
+// singular variables (real mode, small_x > 0): one point per thread, at least
+// 2 waves per SIMD, the only final-pass variant there.  Problems with at most
+// 2 keep the tuned variants, in their double-double-capable copies.
 constexpr int DD_VARIANT = 12;
 
 bool uses_dd(const sdi_problem* pb, const Params& p) {
@@ -340,7 +342,6 @@ int launch_tiles(const sdi_problem* pb, int ppt, int wpe, int km, int grid, size
                  hipStream_t st) {
   if (pb->is_expr()) return launch_tiles_expr(grid, shmem, a, expr_args(pb), st);
   if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, wpe, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
-  if (a.mode == 0 && a.small_x > 0.0) return launch_tiles_real_dd(km, grid, shmem, a, st);
   return launch_tiles_real(pb->nvmax, pb->nsmax, ppt, wpe, km, grid, shmem, a, st);
 }
 
@@ -349,8 +350,8 @@ int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int 
   const int nvmax = pb->nvmax;
   int occ = pb->is_expr()                             ? tiles_expr_occupancy(mode, shmem, expr_args(pb))
             : pb->complex_mode                        ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, shmem)
-            : mode == 0 && uses_dd(pb, ctx->params) ? occupancy_tiles_real_dd(km, shmem)
-                                                      : tiles_real_occupancy(nvmax, pb->nsmax, mode, ppt, wpe, km, shmem);
+                                                      : tiles_real_occupancy(nvmax, pb->nsmax, mode, ppt, wpe, km,
+                                                                             uses_dd(pb, ctx->params), shmem);
   if (occ < 1) occ = 1;
   const size_t g = (size_t)occ * std::max(ctx->ncu, 1);
   return (int)std::max<size_t>(1, std::min(g, ntiles));
@@ -678,7 +679,7 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   }
   const std::vector<int> tiles = tile_candidates(pb, prm, msec);
   TuneChoice ch{tiles.front(), -1};
-  if (uses_dd(pb, prm))
+  if (uses_dd(pb, prm) && pb->nsmax > 2)
     ch.variant = DD_VARIANT;
   else if (prm.ppt > 0)
     ch.variant = default_variant(pb, prm.ppt);

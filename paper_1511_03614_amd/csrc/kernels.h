@@ -42,12 +42,16 @@ int launch_eval_points_expr(const EvalArgs& a, const ExprArgs& x, hipStream_t st
 // (0 final, 1 warm-up with at most 2 points per thread, 2 explicit points with
 // 1; modes 1 and 2 run at 4 waves).  nsmax bounds the singular variables of
 // every sector: final passes with nsmax <= 2 run instances with smaller
-// per-point arrays.  grid = number of persistent blocks.
+// per-point arrays.  grid = number of persistent blocks.  A final pass with
+// a.small_x > 0 (endpoint precision) runs the copies that evaluate points
+// below a.small_x again in double-double: the nsmax <= 2 variants, else the
+// one instance of launch_tiles_real_dd (ppt and wpe ignored).
 int launch_tiles_real(int nvmax, int nsmax, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
                       hipStream_t st);
 int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st);
-// Occupancy (resident blocks per CU) of a tile kernel instance; 0 if not built.
-int tiles_real_occupancy(int nvmax, int nsmax, int mode, int ppt, int wpe, int km, size_t shmem);
+// Occupancy (resident blocks per CU) of a tile kernel instance (dd: the
+// endpoint-precision one of a final pass); 0 if not built.
+int tiles_real_occupancy(int nvmax, int nsmax, int mode, int ppt, int wpe, int km, bool dd, size_t shmem);
 // Final pass (a.mode 0) of the endpoint-precision mode: every variable class,
 // one point per thread, points with a singular coordinate below a.small_x
 // evaluated in double-double.  km 4 or 8.

@@ -99,7 +99,8 @@ def mp_shift_means(prob, s, m, R, seed, small_x=1.0):
     for r in range(R):
         x, w, _ = points.sector_points(z, m, sh[r], 0, N, None, True)
         vals, cond, _ = integrand_mp.sector_orders_mp(sec, x, prob.order_min, prob.order_max, lead, pref)
-        fp64 = x[:, sing].min(axis=1) >= small_x
+        # sectors without singular variables have nothing to cancel and stay in fp64
+        fp64 = x[:, sing].min(axis=1) >= small_x if sing.any() else np.ones(x.shape[0], dtype=bool)
         wf = vals * w[None, :]
         for k in range(prob.norders):
             q[r, k] = integrate.fsum_c(wf[k]) / N
@@ -173,3 +174,31 @@ def test_threshold_mixes_paths_and_complex_mode_ignores_it(ctx):
         P.sdi_problem_destroy(h)
         set_params(ctx)
     assert math.isfinite(float(P.sdi_get_param(ctx, "small_x")))
+
+
+def test_two_singular_variables_keep_the_tuned_variants(ctx):
+    """Problems whose sectors have at most two singular variables keep the tuned
+    launch variants, in their double-double-capable copies: with every point in
+    double-double the shift means meet the 1e-10 bar against the exact means."""
+    import sectorgen
+    full = sectorgen.config2()
+    prob = sectorgen.Problem(sectors=full.sectors[:6], order_min=full.order_min, order_max=full.order_max,
+                             pref_lead=full.pref_lead, pref=full.pref)
+    m, R, seed = 6, 2, 4
+    set_params(ctx, lattice_log2=m, shifts=R, seed=seed, tile_log2=0)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        P.sdi_set_param(ctx, "small_x", 1)
+        res = P.sdi_integrate(ctx, h)
+        assert 10 * res["ppt"] + res["waves_per_simd"] in (14, 23, 24, 42)
+        for s in range(len(prob.sectors)):
+            per = P.sdi_sector_results(ctx, h, s, R)[2]
+            q, scale, bound = mp_shift_means(prob, s, m, R, seed)
+            assert not bound.any() or not (prob.sectors[s].a == -1.0).any()
+            tol = np.maximum(REL_INT * np.maximum(np.abs(q), scale[None, :]), bound)
+            d = np.abs(per - q)
+            assert (d <= tol).all(), f"sector {s}: max d/tol {np.max(d / tol)}"
+    finally:
+        P.sdi_set_param(ctx, "small_x", 0)
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
