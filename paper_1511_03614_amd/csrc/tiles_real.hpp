@@ -11,7 +11,7 @@
 
 namespace sdi {
 
-template <int NV, int PPT, int KM, int MODE, int NSM, bool DD>
+template <int NV, int PPT, int KM, int MODE, int NSM>
 __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
                                               const TileDesc& td, int tc, const double* __restrict__ lgrid,
                                               double* __restrict__ lhist, double (&s)[KM],
@@ -43,19 +43,6 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
     }
     double f[PPT][KM];
     eval_f_real<NV, PPT, KM, NSM>(S, tape(A.terms), x, f);
-    if constexpr (DD) {
-      // points near a face of a singular variable: again, in double-double
-      const int ns = S->ns;
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        if (near_face<NV>(x[p], ns, A.small_x)) {
-          double xd[NV], cd[KM];
-#pragma unroll
-          for (int j = 0; j < NV; ++j) xd[j] = x[p][j];
-          eval_f_real_dd<KM>(S, tape(A.terms), xd, f[p], cd);
-        }
-      }
-    }
     const int kf = S->kf;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -84,6 +71,114 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
   }
 }
 
+// Final-pass tile of the endpoint-precision instances.  Points whose smallest
+// singular coordinate is below A.small_x are not accumulated where they are
+// sampled: each wave queues their offsets in LDS (ballot and prefix count, all
+// control flow wave-uniform), and once 64 are queued the 64 lanes evaluate one
+// each in double-double and add it to their own sums (compensated, so the
+// order does not matter).  A flagged point thus costs one lane of a full
+// double-double call instead of holding its whole wave in one.  q: this
+// wave's DDQ_CAP entries.
+constexpr int DDQ_CAP = 128;
+
+template <int NV, int PPT, int KM, int NSM>
+__device__ __forceinline__ void dd_flush(const TileArgs& A, CSec* S, const TileDesc& td,
+                                         const double* __restrict__ lgrid, const uint32_t* q, int cnt,
+                                         double (&s)[KM], double (&c)[KM], int& nonfin) {
+  const int lane = threadIdx.x & 63;
+  if (lane < cnt) {
+    CU64* zp = tape(A.zp) + (size_t)td.sector * MAXV;
+    CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
+    double x[1][NV], w[1];
+    int bins[1][NV];
+    make_points<NV, 1>(S, zp, sh, lgrid, (uint64_t)td.i0 + q[lane], x, w, bins);
+    double f[KM], cd[KM];
+    eval_f_real_dd<KM>(S, tape(A.terms), x[0], f, cd);
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const double v = w[0] * f[k];
+      two_sum_acc(s[k], c[k], v);
+      bad |= !isfinite(v);
+    }
+    nonfin += bad ? 1 : 0;
+  }
+}
+
+template <int NV, int PPT, int KM, int NSM>
+__device__ __forceinline__ void run_tile_real_ddq(const TileArgs& A, CSec* S, const TileDesc& td,
+                                                  const double* __restrict__ lgrid, uint32_t* q,
+                                                  double (&s)[KM], double (&c)[KM], int& nonfin) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;   // lanes under this one
+  const uint32_t step = (uint32_t)blockDim.x * PPT;
+  const int ns = S->ns;
+  int qn = 0;   // queued entries of this wave (wave-uniform)
+  // every lane runs every iteration (td.count need not be a multiple of step)
+  for (uint32_t base = 0; base < td.count; base += step) {
+    asm volatile("" ::: "memory");
+    const uint32_t off = base + threadIdx.x * PPT;
+    CU64* zp = tape(A.zp) + (size_t)td.sector * MAXV;
+    CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
+    double x[PPT][NV], w[PPT];
+    int bins[PPT][NV];
+    make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+    double f[PPT][KM];
+    eval_f_real<NV, PPT, KM, NSM>(S, tape(A.terms), x, f);
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      const bool act = off + (uint32_t)p < td.count;
+      const bool flag = act && near_face<NV>(x[p], ns, A.small_x);
+      if (act && !flag) {
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          const double v = w[p] * f[p][k];
+          two_sum_acc(s[k], c[k], v);
+          bad |= !isfinite(v);
+        }
+        nonfin += bad ? 1 : 0;
+      }
+      // queue the flagged points of this round: qn < 64 here, so qn + 64 <= DDQ_CAP
+      const uint64_t bal = __ballot(flag);
+      if (flag) q[qn + __popcll(bal & below)] = off + (uint32_t)p;
+      qn += __popcll(bal);
+      if (qn >= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        dd_flush<NV, PPT, KM, NSM>(A, S, td, lgrid, q, 64, s, c, nonfin);
+        // move the rest (fewer than 64) to the front: lane l reads 64 + l, writes l
+        const uint32_t rest = lane < qn - 64 ? q[64 + lane] : 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < qn - 64) q[lane] = rest;
+        qn -= 64;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+  }
+  if (qn > 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    dd_flush<NV, PPT, KM, NSM>(A, S, td, lgrid, q, qn, s, c, nonfin);
+  }
+}
+
+template <int NV, int PPT, int KM, int MODE, int NSM, bool DD>
+__device__ __forceinline__ void run_tile_any(const TileArgs& A, CSec* S, const TileDesc& td, int tc,
+                                             const double* __restrict__ lgrid, double* __restrict__ lhist,
+                                             uint32_t* q, double (&s)[KM], double (&c)[KM], int& nonfin) {
+  if constexpr (DD)
+    run_tile_real_ddq<NV, PPT, KM, NSM>(A, S, td, lgrid, q, s, c, nonfin);
+  else
+    run_tile_real<NV, PPT, KM, MODE, NSM>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+}
+
 // WPE: minimum waves per SIMD the register allocation must allow (the
 // autotuner picks it with PPT; occupancy pays more than a few spills here).
 // NSM: bound on the singular variables of every sector of the launch (the
@@ -96,6 +191,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
   __shared__ int s_tile;
   __shared__ int s_nonfin;
   __shared__ double s_red[BLOCK / 64][KM][2];
+  __shared__ uint32_t s_q[DD ? (BLOCK / 64) * DDQ_CAP : 1];
+  static_assert(!DD || MODE == 0, "endpoint precision is a final-pass mode");
   constexpr int NVC = NVMAX <= 4 ? 0 : (NVMAX <= 8 ? 1 : 2);
   for (;;) {
     __syncthreads();
@@ -132,18 +229,19 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
     for (int k = 0; k < KM; ++k) { s[k] = 0.0; c[k] = 0.0; }
     int nonfin = 0;
     const int cls = S->cls;
+    uint32_t* q = DD ? s_q + (threadIdx.x >> 6) * DDQ_CAP : nullptr;
     switch (cls) {
       case 0:
-        run_tile_real<4, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        run_tile_any<4, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
         break;
       case 1:
         if constexpr (NVMAX == 6)
-          run_tile_real<6, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+          run_tile_any<6, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
         else if constexpr (NVC >= 1)
-          run_tile_real<8, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+          run_tile_any<8, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
         break;
       case 2:
-        if constexpr (NVC >= 2) run_tile_real<16, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+        if constexpr (NVC >= 2) run_tile_any<16, PPT, KM, MODE, NSM, DD>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
         break;
       default:
         break;
