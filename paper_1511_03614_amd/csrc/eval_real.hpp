@@ -141,10 +141,11 @@ __device__ __forceinline__ void make_points(CSec* S, CU64* zp, CU64* sh, const d
 // out += coef prod_j x_j^e_j for one term, PPT points.  The exponent word is
 // wave-uniform (an SGPR), so every exponent bit is a scalar branch; the empty
 // asm keeps the compiler from turning the skipped multiplies into per-lane
-// selects.
+// selects.  Bit 1 (x^2) multiplies by x twice: per-point squares held for the
+// whole evaluation cost more in register spills than the extra multiply.
 template <int NV, int PPT>
 __device__ __forceinline__ void add_term(double c, uint64_t e, const double (&x)[PPT][NV],
-                                         const double (&x2)[PPT][NV], double (&out)[PPT]) {
+                                         double (&out)[PPT]) {
   double m[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) m[p] = c;
@@ -162,7 +163,7 @@ __device__ __forceinline__ void add_term(double c, uint64_t e, const double (&x)
     if (w & (2u << sh)) {
       asm volatile("" ::);
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) m[p] *= x2[p][j];
+      for (int p = 0; p < PPT; ++p) m[p] = (m[p] * x[p][j]) * x[p][j];
     }
   }
 #pragma unroll
@@ -174,7 +175,7 @@ __device__ __forceinline__ void add_term(double c, uint64_t e, const double (&x)
 // flight together (one wait per four terms instead of one per term).
 template <int NV, int PPT>
 __device__ __forceinline__ void poly_real(CTerm* t, uint32_t cnt,
-                                          const double (&x)[PPT][NV], const double (&x2)[PPT][NV],
+                                          const double (&x)[PPT][NV],
                                           double (&out)[PPT]) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) out[p] = 0.0;
@@ -182,12 +183,12 @@ __device__ __forceinline__ void poly_real(CTerm* t, uint32_t cnt,
   for (; i + 4 <= cnt; i += 4) {
     const double c0 = t[i].coef, c1 = t[i + 1].coef, c2 = t[i + 2].coef, c3 = t[i + 3].coef;
     const uint64_t e0 = t[i].exps, e1 = t[i + 1].exps, e2 = t[i + 2].exps, e3 = t[i + 3].exps;
-    add_term<NV, PPT>(c0, e0, x, x2, out);
-    add_term<NV, PPT>(c1, e1, x, x2, out);
-    add_term<NV, PPT>(c2, e2, x, x2, out);
-    add_term<NV, PPT>(c3, e3, x, x2, out);
+    add_term<NV, PPT>(c0, e0, x, out);
+    add_term<NV, PPT>(c1, e1, x, out);
+    add_term<NV, PPT>(c2, e2, x, out);
+    add_term<NV, PPT>(c3, e3, x, out);
   }
-  for (; i < cnt; ++i) add_term<NV, PPT>(t[i].coef, t[i].exps, x, x2, out);
+  for (; i < cnt; ++i) add_term<NV, PPT>(t[i].coef, t[i].exps, x, out);
 }
 
 // 1/v for positive normal v: the hardware reciprocal estimate refined by two
@@ -213,7 +214,7 @@ __device__ __forceinline__ double mant_exp(double v, int& e) {
 template <int NV, int PPT>
 __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
                                                int W, const double (&x)[PPT][NV],
-                                               const double (&x2)[PPT][NV], double (&g0)[PPT],
+                                               double (&g0)[PPT],
                                                double (&lam)[PPT]) {
   const int nfac = S->nfac;
   const int flags = S->flags;
@@ -228,7 +229,7 @@ __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
     for (int fm = 0; fm < MAXF; ++fm) {
       if (fm < nfac) {
         double P[PPT];
-        poly_real<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, x2, P);
+        poly_real<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
         const int g = S->gam_int[fm];
         const int d = S->del_int[fm];
         const int ga = g < 0 ? -g : g;
@@ -261,7 +262,7 @@ __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
     for (int fm = 0; fm < MAXF; ++fm) {
       if (fm < nfac) {
         double P[PPT];
-        poly_real<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, x2, P);
+        poly_real<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
         const double gm = S->gam[fm];
         const double dm = S->del[fm];
 #pragma unroll
@@ -306,12 +307,6 @@ __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const doubl
   const int ns = S->ns;
   const int kf = S->kf;
   const int flags = S->flags;
-  double x2[PPT][NV];
-#pragma unroll
-  for (int p = 0; p < PPT; ++p)
-#pragma unroll
-    for (int j = 0; j < NV; ++j) x2[p][j] = x[p][j] * x[p][j];
-
   double lx[PPT][NSM], ix[PPT][NSM];
 #pragma unroll
   for (int i = 0; i < NSM; ++i) {
@@ -389,7 +384,7 @@ __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const doubl
   const int C = 1 << ns;
   for (int W = 0; W < C; ++W) {
     double g0[PPT], lam[PPT];
-    corner_regular<NV, PPT>(S, terms, W, x, x2, g0, lam);
+    corner_regular<NV, PPT>(S, terms, W, x, g0, lam);
     for (int T = W;; T = (T - 1) & W) {
       const int nt = __builtin_popcount(T);
       const int off = ns - nt;
