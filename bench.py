@@ -510,6 +510,26 @@ def text_integrand_rate(P, ctx, steps: int = 5):
             "tile_log2": r["tile_log2"], "blocks": r["blocks"]}
 
 
+def endpoint_precision_cost(P, ctx, problem, steps: int = 5):
+    """Final-pass kernel time of the bench workload with the endpoint-precision
+    mode (points closer to a singular face than small_x evaluated in
+    double-double) against the fp64 pass, median of `steps` passes each."""
+    for k, v in WORKLOAD.items():
+        P.sdi_set_param(ctx, k, v)
+    h = P.sdi_problem_create(ctx, problem)
+    res = {}
+    try:
+        for sx in (0, 1e-3, 1e-2):
+            P.sdi_set_param(ctx, "small_x", sx)
+            P.sdi_integrate(ctx, h)
+            ms = sorted(P.sdi_integrate(ctx, h)["ms_eval_kernel"] for _ in range(steps))
+            res[str(sx)] = ms[len(ms) // 2]
+    finally:
+        P.sdi_set_param(ctx, "small_x", 0)
+        P.sdi_problem_destroy(h)
+    return {"ms_final_pass": res, "ratio_1e-3": res["0.001"] / res["0"], "ratio_1e-2": res["0.01"] / res["0"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -600,6 +620,7 @@ def main() -> int:
     if args.tune_save:
         P.sdi_tune_save(ctx, args.tune_save)
     out["text_integrand"] = text_integrand_rate(P, ctx)
+    out["endpoint_precision"] = endpoint_precision_cost(P, ctx, problem)
     if not args.no_equal_time:
         from sectorgen.feynman import double_box_problem
         lat = [dict(lattice_log2=m) for m in range(10, 17)]
