@@ -48,9 +48,10 @@ __device__ __forceinline__ cd cexp_(cd z) {
 
 // out += coef prod_j x_j^e_j for one term with exponent bits x, x^2, x^4; the
 // bits are tested on 32-bit halves of the wave-uniform word (scalar branches).
+// The powers are repeated multiplications by x: per-point squares and fourth
+// powers held for the whole evaluation cost more in spills than the multiplies.
 template <int NV, int PPT>
 __device__ __forceinline__ void add_term3(double c, uint64_t e, const double (&x)[PPT][NV],
-                                          const double (&x2)[PPT][NV], const double (&x4)[PPT][NV],
                                           double (&out)[PPT]) {
   double m[PPT];
 #pragma unroll
@@ -68,12 +69,12 @@ __device__ __forceinline__ void add_term3(double c, uint64_t e, const double (&x
     if (w & (2u << sh)) {
       asm volatile("" ::);
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) m[p] *= x2[p][j];
+      for (int p = 0; p < PPT; ++p) m[p] = (m[p] * x[p][j]) * x[p][j];
     }
     if (w & (4u << sh)) {
       asm volatile("" ::);
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) m[p] *= x4[p][j];
+      for (int p = 0; p < PPT; ++p) m[p] = (((m[p] * x[p][j]) * x[p][j]) * x[p][j]) * x[p][j];
     }
   }
 #pragma unroll
@@ -84,17 +85,15 @@ __device__ __forceinline__ void add_term3(double c, uint64_t e, const double (&x
 // list order.
 template <int NV, int PPT>
 __device__ __forceinline__ void poly_real3(CTerm* t, uint32_t cnt, const double (&x)[PPT][NV],
-                                           const double (&x2)[PPT][NV], const double (&x4)[PPT][NV],
                                            double (&out)[PPT]) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) out[p] = 0.0;
-  for (uint32_t i = 0; i < cnt; ++i) add_term3<NV, PPT>(t[i].coef, t[i].exps, x, x2, x4, out);
+  for (uint32_t i = 0; i < cnt; ++i) add_term3<NV, PPT>(t[i].coef, t[i].exps, x, out);
 }
 
 // out += coef prod_j z_j^e_j for one term at complex points (exponents up to 3).
 template <int NV, int PPT>
-__device__ __forceinline__ void add_term_c(double c, uint64_t e, const cd (&z)[PPT][NV], const cd (&z2)[PPT][NV],
-                                           cd (&out)[PPT]) {
+__device__ __forceinline__ void add_term_c(double c, uint64_t e, const cd (&z)[PPT][NV], cd (&out)[PPT]) {
   cd m[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) m[p] = cd{c, 0.0};
@@ -111,7 +110,7 @@ __device__ __forceinline__ void add_term_c(double c, uint64_t e, const cd (&z)[P
     if (w & (2u << sh)) {
       asm volatile("" ::);
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) m[p] = cmul(m[p], z2[p][j]);
+      for (int p = 0; p < PPT; ++p) m[p] = cmul(cmul(m[p], z[p][j]), z[p][j]);
     }
   }
 #pragma unroll
@@ -122,10 +121,10 @@ __device__ __forceinline__ void add_term_c(double c, uint64_t e, const cd (&z)[P
 // terms in list order.
 template <int NV, int PPT>
 __device__ __forceinline__ void poly_cplx(CTerm* t, uint32_t cnt, const cd (&z)[PPT][NV],
-                                          const cd (&z2)[PPT][NV], cd (&out)[PPT]) {
+                                          cd (&out)[PPT]) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) out[p] = cd{0.0, 0.0};
-  for (uint32_t i = 0; i < cnt; ++i) add_term_c<NV, PPT>(t[i].coef, t[i].exps, z, z2, out);
+  for (uint32_t i = 0; i < cnt; ++i) add_term_c<NV, PPT>(t[i].coef, t[i].exps, z, out);
 }
 
 // f_kk of one sector at PPT points, complex mode.  imf counts points whose F(z)
@@ -143,14 +142,6 @@ __device__ __forceinline__ void eval_f_cplx_c(CSec* S, const SDI_TAPE CplxDev* X
   const int nfac = S->nfac;
   const double lam = X->lam;
   const int facf = X->fac_f;
-  double x2[PPT][NV], x4[PPT][NV];
-#pragma unroll
-  for (int p = 0; p < PPT; ++p)
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      x2[p][j] = x[p][j] * x[p][j];
-      x4[p][j] = x2[p][j] * x2[p][j];
-    }
   double lx[PPT][MAXS], ix[PPT][MAXS];
 #pragma unroll
   for (int i = 0; i < MAXS; ++i) {
@@ -214,7 +205,7 @@ __device__ __forceinline__ void eval_f_cplx_c(CSec* S, const SDI_TAPE CplxDev* X
       if (j < n && facf >= 0) {
         double v[PPT];
         CU32* d = dir + (size_t)X->dir_off + ((size_t)j * MAXC + W) * 2;
-        poly_real3<NV, PPT>(terms + d[0], d[1], x, x2, x4, v);
+        poly_real3<NV, PPT>(terms + d[0], d[1], x, v);
 #pragma unroll
         for (int p = 0; p < PPT; ++p) g[p][j] = v[p];
       }
@@ -240,7 +231,7 @@ __device__ __forceinline__ void eval_f_cplx_c(CSec* S, const SDI_TAPE CplxDev* X
             double v[PPT];
             const int dd = n + j * (j + 1) / 2 + k;
             CU32* d = dir + (size_t)X->dir_off + ((size_t)dd * MAXC + W) * 2;
-            poly_real3<NV, PPT>(terms + d[0], d[1], x, x2, x4, v);
+            poly_real3<NV, PPT>(terms + d[0], d[1], x, v);
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
               double sjk = r[p][j] * r[p][k] * v[p];
@@ -274,7 +265,7 @@ __device__ __forceinline__ void eval_f_cplx_c(CSec* S, const SDI_TAPE CplxDev* X
       }
     }
     // deformed point, logs of w_j
-    cd z[PPT][NV], z2[PPT][NV];
+    cd z[PPT][NV];
     cd lg[PPT], lam_w[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -288,7 +279,6 @@ __device__ __forceinline__ void eval_f_cplx_c(CSec* S, const SDI_TAPE CplxDev* X
         const double t = lam * (1.0 - y[p][j]) * g[p][j];
         const cd w = cd{1.0, -t};
         z[p][j] = cd{y[p][j], -y[p][j] * t};
-        z2[p][j] = cmul(z[p][j], z[p][j]);
         if (j < n) {
           const cd lw = clog_mi0(w);
           lg[p] = cadd(lg[p], cscale(lw, S->a[j]));
@@ -301,7 +291,7 @@ __device__ __forceinline__ void eval_f_cplx_c(CSec* S, const SDI_TAPE CplxDev* X
     for (int fm = 0; fm < MAXF; ++fm) {
       if (fm < nfac) {
         cd P[PPT];
-        poly_cplx<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], z, z2, P);
+        poly_cplx<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], z, P);
         const double gm = S->gam[fm];
         const double dm = S->del[fm];
 #pragma unroll

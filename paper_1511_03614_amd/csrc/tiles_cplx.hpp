@@ -258,16 +258,10 @@ __device__ __forceinline__ bool imf_any_corner(CSec* S, const SDI_TAPE CplxDev* 
   const int ns = S->ns;
   const int facf = X->fac_f;
   if (facf < 0) return false;
-  double x2[1][NV], x4[1][NV];
-#pragma unroll
-  for (int j = 0; j < NV; ++j) {
-    x2[0][j] = x[0][j] * x[0][j];
-    x4[0][j] = x2[0][j] * x2[0][j];
-  }
   bool pos = false;
   const int C = 1 << ns;
   for (int W = 0; W < C; ++W) {
-    cd z[1][NV], z2[1][NV];
+    cd z[1][NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const double y = (j < MAXS && ((W >> j) & 1)) ? 0.0 : x[0][j];
@@ -275,15 +269,14 @@ __device__ __forceinline__ bool imf_any_corner(CSec* S, const SDI_TAPE CplxDev* 
       if (j < n) {
         double v[1];
         CU32* d = dir + (size_t)X->dir_off + ((size_t)j * MAXC + W) * 2;
-        poly_real3<NV, 1>(terms + d[0], d[1], x, x2, x4, v);
+        poly_real3<NV, 1>(terms + d[0], d[1], x, v);
         g = v[0];
       }
       const double t = lam * (1.0 - y) * g;
       z[0][j] = cd{y, -y * t};
-      z2[0][j] = cmul(z[0][j], z[0][j]);
     }
     cd P[1];
-    poly_cplx<NV, 1>(terms + S->tab_off[facf][W], S->tab_cnt[facf][W], z, z2, P);
+    poly_cplx<NV, 1>(terms + S->tab_off[facf][W], S->tab_cnt[facf][W], z, P);
     cd fz = P[0];
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
