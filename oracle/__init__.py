@@ -19,7 +19,38 @@ What it computes (paper: FIESTA 4, arXiv:1511.03614):
 * ``integrate``  - per-sector, per-shift means, the shift-to-shift error and
   the root-sum-square combination of section 4.3.
 
+* ``integrand_mp`` - the real sector integrand in multiprecision (the
+  reference of the endpoint-precision mode).
+* ``deform``     - the automatic deformation size (ComplexMode tuning).
+* ``flow``       - the learned importance-sampling map (sampling, log q,
+  gradient, Adam, training loss weights).
+* ``expr``       - integrands in the workers' text format (section 4.6).
+
 Where the paper is silent, each function's docstring states the reading it
 takes and names the passage it follows.
+
+Pins (each function checked against something other than itself; tests in
+``tests/test_oracle_*.py``):
+
+* integrand: hypergeometric closed forms in one variable, separable products,
+  a direct integral at finite eps, the bubble's Gamma-function expansion, the
+  paper's box example (section 4.3), the massive bubble above threshold and
+  lambda invariance (Cauchy) in complex mode, the deformation Jacobian by
+  finite differences;
+* prefactor: mpmath Taylor series of the Gamma functions;
+* points: Philox known-answer vectors, exact lattice projections and shift
+  means, the exactness of the tent map; the CBC vector as the componentwise
+  minimum of the P_2 figure computed on the dual lattice;
+* vegas: the refit's fixed point against an independent shooting solver, a
+  single occupied bin, the compression exponent, the histogram against exact
+  bin integrals;
+* integrate: shift-to-shift errors calibrated against Student's t over many
+  seeds; the allocation's proportionality and clamps;
+* integrand_mp: closed forms that stay exact at the faces;
+* deform: Im F flags against plain complex arithmetic, the chosen lambda
+  against a direct scan of the candidates, small lambda never failing;
+* flow: finite-difference gradients, invertibility, unit mean weight,
+  torch's Adam, convergence to the chi^2-optimal density;
+* expr: hand-evaluated expressions and closed-form integrals.
 """
 from . import integrand, points, prefactor, vegas, integrate  # noqa: F401

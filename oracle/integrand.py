@@ -26,7 +26,10 @@ is the integrand of the eps^k coefficient of I_s / c_s.
 
 Complex mode (section 4.4, ComplexMode; the -i0 of eq. (1) and eq. (2)):
 the sector variables move to z_j = x_j - i lam x_j (1 - x_j) dF/dx_j, F the
-sector's full F polynomial, so that Im F(z) <= 0 to first order.  With
+sector's deformation polynomial x^m P_F: P_F is the sector's reduced F factor
+(what is left of F after the decomposition takes the monomial out; it has a
+constant term and carries the F - i0 branch) and m its optional monomial
+(deform_mono, zero by default, so F = P_F), so that Im F(z) <= 0 to first order.  With
 z_j = x_j w_j, w_j = 1 - i lam (1 - x_j) dF/dx_j, the monomial keeps its real
 form and
 
@@ -80,7 +83,7 @@ def log_minus_i0(p: np.ndarray) -> np.ndarray:
 
 
 def full_f_terms(sector) -> Tuple[np.ndarray, np.ndarray]:
-    """Coefficients and integer exponents of the sector's full F = x^mono * P_F."""
+    """Coefficients and integer exponents of the deformation polynomial x^mono * P_F (mono = 0: P_F)."""
     fac = sector.factors[sector.deform_factor]
     mono = sector.deform_mono if sector.deform_mono is not None else np.zeros(sector.n, np.int32)
     return fac.coef.copy(), fac.exps.astype(np.int64) + mono.astype(np.int64)[None, :]
@@ -101,7 +104,7 @@ def _poly_int(coef, exps, y):
 
 
 def f_derivatives(sector, y: np.ndarray):
-    """Gradient (npts, n) and Hessian (npts, n, n) of the full F at real points y."""
+    """Gradient (npts, n) and Hessian (npts, n, n) of the deformation polynomial at real points y."""
     coef, exps = full_f_terms(sector)
     n = sector.n
     grad = np.zeros((y.shape[0], n))

@@ -1,8 +1,10 @@
 // Complex-mode (contour-deformed) sector-integrand evaluation on gfx950.
 //
 // ComplexMode of the paper (section 4.4) moves the sector variables off the
-// real cube, z_j = y_j - i lam y_j (1 - y_j) dF/dy_j with F the sector's full F
-// polynomial, so that Im F(z) <= 0 (the F - i0 of eq. (1) and eq. (2)).  At each
+// real cube, z_j = y_j - i lam y_j (1 - y_j) dF/dy_j with F the sector's
+// deformation polynomial y^m P_F (P_F the reduced F factor, which has a
+// constant term; m the optional monomial of the sector, zero by default), so
+// that Im F(z) <= 0 (the F - i0 of eq. (1) and eq. (2)).  At each
 // corner y = x^(W) of the pole subtraction:
 //   w_j = 1 - i lam (1 - y_j) g_j,  z_j = y_j w_j,  g = grad F(y),
 //   det(dz/dy) = det(I - i lam S),  S = D_a + D_y^(1/2) H D_y^(1/2),
@@ -196,7 +198,7 @@ __device__ __forceinline__ void eval_f_cplx_c(CSec* S, const SDI_TAPE CplxDev* X
     for (int j = 0; j < NV; ++j)
 #pragma unroll
       for (int p = 0; p < PPT; ++p) y[p][j] = (j < MAXS && ((W >> j) & 1)) ? 0.0 : x[p][j];
-    // gradient of the full F at y
+    // gradient of the deformation polynomial at y
     double g[PPT][NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
