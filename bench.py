@@ -1,13 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark: sector-integrand evaluations per second on one MI355X.
 
-One step = one call of sdi_integrate on the synthetic 64-sector workload
-(3-6 variables, 4-20 terms per factor, up to 2 singular variables, orders
-eps^-2..eps^0): Vegas warm-up (5 iterations of 2^14 lattice points per sector,
-histograms and grid refit) followed by the frozen-grid pass over 16 shifted
-rank-1 lattices of 2^16 points per sector, the compensated reductions and the
-combination.  Inputs (compiled sector tables) are resident on the GPU before
-timing starts.  Prints one JSON line.
+One step = one call of sdi_integrate on the batched, uneven workload: 2000
+synthetic sectors (4-9 variables, 5-40 terms per factor, up to 3 singular
+variables, orders eps^-3..eps^0), a pilot pass of 16 shifts x 2^12 lattice
+points per sector, the variance-driven (Neyman) allocation of a 2^31-evaluation
+final budget in per-sector lattices of 2^16..2^24 evaluations, and the final
+pass in one persistent, graph-captured, autotuned launch, with the compensated
+reductions and the combination.  Inputs (compiled sector tables) are resident
+on the GPU before timing starts.  The other configurations (the bubble, the
+64-sector synthetic set, the Euclidean and the physical double box) are
+measured after the headline and reported as extra keys.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -23,28 +26,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X: 256 CUs x 4 SIMD x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
-WORKLOAD = dict(lattice_log2=16, shifts=16, seed=1, warmup=5, warmup_log2=14, nbins=128, tile_log2=0)
+# the headline workload: 2000 sectors, pilot 16 x 2^12 per sector, final budget 2^31
+# evaluations in per-sector lattices of 16 x 2^12 .. 16 x 2^20 (2^16 .. 2^24 evaluations)
+HEADLINE = dict(shifts=16, seed=1, warmup=0, budget=1 << 31, pilot_log2=12, alloc_min_log2=12, alloc_max_log2=20,
+                lattice_log2=12, tile_log2=0, ppt=0)
+SYNTH64 = dict(lattice_log2=16, shifts=16, seed=1, warmup=5, warmup_log2=14, nbins=128, tile_log2=0, ppt=0)
 KERNEL_SOURCES = ["paper_1511_03614_amd/csrc/eval_real.hpp", "paper_1511_03614_amd/csrc/tiles_real.hpp",
                   "paper_1511_03614_amd/csrc/sdint_internal.h"]
+KERNEL_SOURCES_CPLX = KERNEL_SOURCES + ["paper_1511_03614_amd/csrc/eval_cplx.hpp",
+                                        "paper_1511_03614_amd/csrc/tiles_cplx.hpp"]
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def _bits(e):
+    """Multiplies of one exponent under the term encoding (bit 0: x, bit 1: x^2 as x*x, bit 2: x^4 as four x)."""
+    return (e & 1) + 2 * ((e >> 1) & 1) + 4 * ((e >> 2) & 1)
 
 
 def sector_work(sec, order_max: int, pref_lead: int, use_grid: bool):
     """Algorithmic FP64 operations (add/sub/mul/div = 1, FMA = 2) and logarithms per evaluation.
 
     Counts the arithmetic of the method as the tile kernel performs it: lattice
-    tent map and Vegas map, powers x^2, the polynomial terms of every corner
-    (one multiply per exponent bit, one add), integer powers of the factors,
-    the subtraction/series combination for every (corner, subset) pair, the
-    monomial and the weighted accumulation.  Logarithms are counted apart and
-    not as flops; integer work and compensation (two-sum) are not counted.
+    tent map and Vegas map, the polynomial terms of every corner (one multiply
+    per exponent bit, x^2 as two multiplies, one add), integer powers of the
+    factors, the subtraction/series combination for every (corner, subset)
+    pair, the monomial and the weighted accumulation.  Logarithms are counted
+    apart and not as flops; integer work and compensation (two-sum) are not
+    counted.
     """
     import numpy as np
     n = sec.n
@@ -60,7 +75,7 @@ def sector_work(sec, order_max: int, pref_lead: int, use_grid: bool):
         for fac in sec.factors:
             alive = np.all(fac.exps[:, zero] == 0, axis=1) if zero else np.ones(len(fac.coef), bool)
             e = fac.exps[alive].astype(np.int64)
-            fl += int(np.sum((e & 1) != 0) + np.sum((e & 2) != 0)) + int(alive.sum())
+            fl += int(sum(_bits(int(v)) for v in e.ravel())) + int(alive.sum())
             fl += abs(int(fac.gamma)) + abs(int(fac.delta))
         fl += 4
         logs += 1
@@ -73,78 +88,205 @@ def sector_work(sec, order_max: int, pref_lead: int, use_grid: bool):
     return fl, logs
 
 
+def sector_work_complex(sec, order_max: int, pref_lead: int, mono_f=None):
+    """Algorithmic FP64 operations and transcendentals per evaluation of a
+    contour-deformed sector (complex multiply = 6, complex add = 2, real
+    coefficient times complex = 2): per corner the gradient and Hessian
+    polynomials of the deformation polynomial (real, at the corner point), the
+    LDL^T determinant of the n x n complex symmetric Jacobian, the deformed
+    point, the factors at complex points, the series of every (corner, subset)
+    pair and the accumulation.  Logarithms, atan2, exp and sincos are counted
+    apart as transcendentals."""
+    import numpy as np
+    n = sec.n
+    S = [j for j in range(n) if sec.a[j] == -1.0]
+    ns = len(S)
+    kf = max(0, order_max - pref_lead + ns + 1)
+    F = sec.factors[sec.deform_factor]
+    fl, tr = 2 * n + n + 2 * ns, 2 * ns + 2 * (n - ns) + 1
+
+    def deriv_terms(exps, coef, j, k=None):
+        e = exps.astype(np.int64).copy()
+        keep = e[:, j] > 0
+        e = e[keep]
+        e[:, j] -= 1
+        if k is not None:
+            keep = e[:, k] > 0
+            e = e[keep]
+            e[:, k] -= 1
+        return e
+
+    for W in range(1 << ns):
+        zero = [S[i] for i in range(ns) if W >> i & 1]
+
+        def alive(e):
+            return e[np.all(e[:, zero] == 0, axis=1)] if zero and len(e) else e
+        # gradient and Hessian polynomials (real), one multiply per exponent bit
+        for j in range(n):
+            e = alive(deriv_terms(F.exps, F.coef, j))
+            fl += int(sum(_bits(int(v)) for v in e.ravel())) + len(e)
+            for k in range(j + 1):
+                e = alive(deriv_terms(F.exps, F.coef, j, k))
+                fl += int(sum(_bits(int(v)) for v in e.ravel())) + len(e) + 4
+        fl += 3 * n                                         # sqrt(y(1-y)) arguments, diagonal terms
+        tr += n
+        for k in range(n):                                  # LDL^T of the complex symmetric matrix
+            fl += 6 + 6 + sum(6 + 8 * (i - k) for i in range(k + 1, n))
+        fl += 4 * n + 8 * n                                 # deformed point, w_j logs scaled by a_j, b_j
+        tr += 3 * n
+        for fac in sec.factors:
+            e = alive(fac.exps.astype(np.int64))
+            fl += int(sum(6 * _bits(int(v)) for v in e.ravel())) + 2 * len(e) + 8
+            tr += 3
+        fl += 6 + 2
+        tr += 3
+        for T in range(1 << ns):
+            if T & ~W:
+                continue
+            nt = bin(T).count("1")
+            fl += 2 + 2 * (ns - nt) + 10 * max(0, kf - (ns - nt))
+    fl += 2 * kf + 2 * kf
+    return fl, tr
+
+
+def launch_work(problem, nevals, lead, use_grid=False):
+    """(flops, transcendentals) of one final-pass launch: per-sector work times its evaluations."""
+    fl = tr = 0
+    for sec, ne in zip(problem.sectors, nevals):
+        if problem.complex_mode:
+            f, t = sector_work_complex(sec, problem.order_max, lead)
+        else:
+            f, t = sector_work(sec, problem.order_max, lead, use_grid)
+        fl += f * ne
+        tr += t * ne
+    return fl, tr
+
+
+# ------------------------------------------------------------------ CPU baseline (the oracle)
+
 _CPU_PROBLEM = None
 
 
 def _cpu_init():
     global _CPU_PROBLEM
     import sectorgen
-    _CPU_PROBLEM = sectorgen.config2()
+    _CPU_PROBLEM = sectorgen.config4()
 
 
 def _cpu_task(task):
-    """The oracle on one (sector, shift) of 2^m lattice points; returns the evaluations."""
+    """The oracle on one (sector, shift) of 2^m lattice points of the headline
+    workload: returns the evaluations, the per-order shift means and mean |w F|."""
     import numpy as np
     from oracle import integrand, integrate, points
-    s, r, m = task
+    s, r, m, seed = task
     problem = _CPU_PROBLEM
     lead, pref = integrate.prefactor_for(problem)
     sec = problem.sectors[s]
     z = points.cbc_vector(m, sec.n)
-    sh = points.shift_table(1, s, r + 1, sec.n, m)[r]
+    sh = points.shift_table(seed, s, r + 1, sec.n, m)[r]
     x, w, _ = points.sector_points(z, m, sh, 0, 1 << m)
     vals, _, _ = integrand.sector_orders(sec, x, problem.order_min, problem.order_max, lead, pref)
-    q = [integrate.fsum_c(v) for v in vals * w[None, :]]
-    assert np.all(np.isfinite(q))
-    return 1 << m
+    wf = vals * w[None, :]
+    q = [integrate.fsum_c(v) / (1 << m) for v in wf]
+    return 1 << m, s, r, [[c.real, c.imag] for c in q], np.abs(wf).mean(axis=1).tolist()
 
 
-def cpu_baseline(m: int, shifts: int = 16, workers: int = 0) -> dict:
-    """The oracle as it stands on the host's cores: every (sector, shift) of the
-    workload's final pass (all 64 sectors x `shifts` shifts x 2^m lattice points)
-    spread over a process pool, timed on the wall clock.  Runs in a process that
-    has not touched the GPU (bench.py starts it before its own GPU work)."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(m: int, stride: int, shifts: int = 16, workers: int = 0, seed: int = 1) -> dict:
+    """The oracle as it stands on the host's cores: a stratified sample of the
+    headline workload (every `stride`-th sector, `shifts` shifts, 2^m lattice
+    points: the pilot pass of those sectors) spread over a process pool and
+    timed on the wall clock, and the same oracle on one core over the first
+    tenth of that sample.  Runs in a process that has not touched the GPU
+    (bench.py starts it before its own GPU work).  Also returns the oracle's
+    per-shift means of the sample, against which the GPU pass is compared."""
     import concurrent.futures as cf
     import multiprocessing as mp
     import sectorgen
-    workers = workers or max(1, min(16, os.cpu_count() or 1))
-    ns = len(sectorgen.config2().sectors)
-    tasks = [(s, r, m) for s in range(ns) for r in range(shifts)]
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    workers = workers or max(1, min(16, avail))       # the GPU host grants 16 cores to one GPU's job
+    nsec = len(sectorgen.config4().sectors)
+    sample = list(range(0, nsec, stride))
+    tasks = [(s, r, m, seed) for s in sample for r in range(shifts)]
+    _cpu_init()
+    t0 = time.perf_counter()
+    one = [_cpu_task(t) for t in tasks[: max(1, len(tasks) // 10)]]
+    dt1 = time.perf_counter() - t0
+    ev1 = sum(o[0] for o in one)
     with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork"), initializer=_cpu_init) as ex:
-        list(ex.map(_cpu_task, [(0, 0, 8)] * workers))           # start every worker before the clock
+        list(ex.map(_cpu_task, [(0, 0, 6, seed)] * workers))      # start every worker before the clock
         t0 = time.perf_counter()
-        evals = sum(ex.map(_cpu_task, tasks, chunksize=4))
+        out = list(ex.map(_cpu_task, tasks, chunksize=2))
         dt = time.perf_counter() - t0
+    evals = sum(o[0] for o in out)
     return {"value": evals / dt, "unit": "evals/s", "cores": workers, "kind": "oracle",
-            "sample": f"all {ns} sectors x {shifts} shifts x 2^{m} lattice points ({evals} evals, {dt:.1f} s wall, "
-                      f"numpy fp64, {workers} worker processes)"}
+            "sample": f"every {stride}th sector of the 2000 ({len(sample)} sectors) x {shifts} shifts x 2^{m} "
+                      f"lattice points ({evals} evals, {dt:.1f} s wall, numpy fp64, {workers} worker processes)",
+            "one_core": {"value": ev1 / dt1, "evals": ev1, "s": dt1},
+            "nproc": nproc, "affinity": avail, "cpu_model": _cpu_model(),
+            "oracle_shift_means": {"m": m, "seed": seed, "shifts": shifts,
+                                   "values": [[o[1], o[2], o[3], o[4]] for o in out]}}
 
 
-def _cpu_baseline_subprocess(m: int) -> dict:
+def _cpu_baseline_subprocess(m: int, stride: int) -> dict:
     """cpu_baseline in a child interpreter, started before this process uses the GPU."""
     import subprocess
-    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-log2", str(m)],
-                       capture_output=True, text=True, timeout=600)
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-log2", str(m),
+                        "--cpu-stride", str(stride)], capture_output=True, text=True, timeout=900)
     if r.returncode != 0:
         return {"value": None, "error": r.stderr[-500:]}
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def traffic_from_profiles(ms_kernel: float):
-    """HBM bytes per launch of the tile kernel from the committed counter summary, if current."""
+def traffic_from_profiles(workload: str, sources=None):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, if current."""
     for path in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.json")):
         try:
             d = json.load(open(path))
         except (OSError, ValueError):
             continue
-        if d.get("kernel_hash") == kernel_hash() and d.get("workload") == "synthetic64":
+        if d.get("kernel_hash") == kernel_hash(sources) and d.get("workload") == workload:
             return d.get("bytes_per_launch")
     return None
 
 
+def strict_json(v):
+    """Non-finite floats become null (strict JSON), recursively."""
+    import math
+    if isinstance(v, float):
+        return v if math.isfinite(v) else None
+    if isinstance(v, dict):
+        return {k: strict_json(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [strict_json(x) for x in v]
+    try:
+        import numpy as np
+        if isinstance(v, np.generic):
+            return strict_json(v.item())
+        if isinstance(v, np.ndarray):
+            return strict_json(v.tolist())
+    except ImportError:
+        pass
+    return v
+
+
 def _set(P, ctx, **kw):
     base = dict(lattice_log2=12, shifts=16, seed=1, baker=1, warmup=0, graph=1, sampler=0, budget=0, ppt=0,
-                tile_log2=0)
+                tile_log2=0, pilot_log2=12, alloc_min_log2=12, alloc_max_log2=20, warmup_log2=14, nbins=128,
+                small_x=0)
     base.update(kw)
     for k, v in base.items():
         P.sdi_set_param(ctx, k, v)
@@ -511,11 +653,11 @@ def text_integrand_rate(P, ctx, steps: int = 5):
 
 
 def endpoint_precision_cost(P, ctx, problem, steps: int = 5):
-    """Final-pass kernel time of the bench workload with the endpoint-precision
-    mode (points closer to a singular face than small_x evaluated in
-    double-double) against the fp64 pass, median of `steps` passes each."""
-    for k, v in WORKLOAD.items():
-        P.sdi_set_param(ctx, k, v)
+    """Final-pass kernel time of the 64-sector synthetic workload with the
+    endpoint-precision mode (points closer to a singular face than small_x
+    evaluated in double-double) against the fp64 pass, median of `steps`
+    passes each."""
+    _set(P, ctx, **SYNTH64)
     h = P.sdi_problem_create(ctx, problem)
     res = {}
     try:
@@ -530,22 +672,140 @@ def endpoint_precision_cost(P, ctx, problem, steps: int = 5):
     return {"ms_final_pass": res, "ratio_1e-3": res["0.001"] / res["0"], "ratio_1e-2": res["0.01"] / res["0"]}
 
 
+def measure(P, ctx, problem, params, steps, warmup, lambda_max=None, conservative_if_imf=False):
+    """Steps of sdi_integrate on one workload: wall time per step (the clock
+    bracketed by device synchronisations), device and final-pass kernel times
+    (HIP events on the library's stream), per-sector final evaluations."""
+    import numpy as np
+    import torch
+    _set(P, ctx, **params)
+    h = P.sdi_problem_create(ctx, problem)
+    try:
+        tuned = None
+        if lambda_max is not None:
+            tuned = {"lambda": P.sdi_tune_deformation(ctx, h, lambda_max, 4, 10).tolist(), "conservative": False}
+            r = P.sdi_integrate(ctx, h)
+            if conservative_if_imf and r["n_imf_positive"] > 0:
+                tuned = {"lambda": P.sdi_tune_deformation(ctx, h, lambda_max, 4, 10, conservative=True).tolist(),
+                         "conservative": True, "imf_positive_before": int(r["n_imf_positive"])}
+        for _ in range(warmup):
+            r = P.sdi_integrate(ctx, h)
+        torch.cuda.synchronize()
+        kms, dms, evals = [], [], 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = P.sdi_integrate(ctx, h)
+            kms.append(r["ms_eval_kernel"])
+            dms.append(r["ms_total"])
+            evals += r["n_evals"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ns = len(problem.sectors)
+        R = params.get("shifts", 16)
+        nev = [P.sdi_sector_results(ctx, h, s, R)[3] for s in range(ns)]
+        return {"r": r, "evals_per_step": evals // steps, "wall_s": dt, "ms_per_step": dt / steps * 1e3,
+                "value": evals / dt, "ms_kernel": float(np.mean(kms)), "ms_device": float(np.mean(dms)),
+                "nevals": nev, "tuned": tuned, "steps": steps}
+    finally:
+        P.sdi_problem_destroy(h)
+
+
+def roofline(P, problem, m, kernel, workload, use_grid=False, sources=None):
+    lead = P._prefactor_of(problem)[0]
+    fl, tr = launch_work(problem, m["nevals"], lead, use_grid)
+    achieved = fl / (m["ms_kernel"] * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": traffic_from_profiles(workload, sources),
+            "kernel": kernel, "ms_per_launch": m["ms_kernel"], "flops_per_launch": fl,
+            "transcendentals_per_s": tr / (m["ms_kernel"] * 1e-3)}
+
+
+def _kernel_name(r, problem, nvmax, nsm):
+    if problem.complex_mode:
+        return f"k_tiles_cplx<{nvmax}, {r['ppt']}, KM, 0, {r['waves_per_simd']}> (final pass)"
+    return f"k_tiles_real<{nvmax}, {r['ppt']}, KM, 0, {r['waves_per_simd']}, {nsm}, false> (final pass)"
+
+
+def _classes(problem):
+    nv = max(s.n for s in problem.sectors)
+    nsm = max(int(sum(s.a == -1.0)) for s in problem.sectors)
+    nvc = 4 if nv <= 4 else 6 if nv <= 6 else 8 if nv <= 8 else 16
+    return nvc, (2 if nsm <= 2 else 4)
+
+
+def config_entry(P, problem, m, workload, use_grid=False, sources=None):
+    nvc, nsm = _classes(problem)
+    r = m["r"]
+    return {"evals_per_s": m["value"], "ms_per_step": m["ms_per_step"], "evals_per_step": m["evals_per_step"],
+            "steps": m["steps"], "ms_device_per_step": m["ms_device"],
+            "final_evals": int(sum(m["nevals"])), "points_per_thread": r["ppt"], "waves_per_simd": r["waves_per_simd"],
+            "tile_log2": r["tile_log2"], "blocks": r["blocks"], "n_nonfinite": int(r["n_nonfinite"]),
+            "n_imf_positive": int(r["n_imf_positive"]), "deformation": m["tuned"],
+            "roofline": roofline(P, problem, m, _kernel_name(r, problem, nvc, nsm), workload, use_grid, sources),
+            "result": {"orders": list(range(problem.order_min, problem.order_max + 1)),
+                       "value_re": r["value"].real.tolist(), "value_im": r["value"].imag.tolist(),
+                       "err_re": r["err_re"].tolist(), "err_im": r["err_im"].tolist()}}
+
+
+def parity_vs_oracle(P, ctx, problem, cpu):
+    """Per-coefficient error of the GPU against the oracle on identical points:
+    a plain pass (the pilot's lattice size, seed and shifts) over all sectors,
+    compared shift by shift with the oracle's means of the CPU sample (computed
+    by the cpu_baseline leg).  Per order: the largest |gpu - oracle| relative to
+    max(|oracle|, mean |w F|) over the sample's (sector, shift) means, and the
+    relative error of the sample's total."""
+    import numpy as np
+    om = cpu.get("oracle_shift_means") if cpu else None
+    if not om:
+        return None
+    R = om["shifts"]
+    _set(P, ctx, lattice_log2=om["m"], shifts=R, seed=om["seed"])
+    h = P.sdi_problem_create(ctx, problem)
+    try:
+        P.sdi_integrate(ctx, h)
+        K = problem.norders
+        worst = np.zeros(K)
+        tot_g = np.zeros(K, complex)
+        tot_o = np.zeros(K, complex)
+        cache = {}
+        for s, r, q, scale in om["values"]:
+            if s not in cache:
+                cache[s] = P.sdi_sector_results(ctx, h, s, R)[2]
+            g = cache[s][r]
+            o = np.array([complex(a, b) for a, b in q])
+            d = np.abs(g - o) / np.maximum(np.maximum(np.abs(o), np.array(scale)), 1e-300)
+            worst = np.maximum(worst, d)
+            tot_g += g
+            tot_o += o
+        return {"orders": list(range(problem.order_min, problem.order_max + 1)),
+                "max_rel_err_per_shift_mean": worst.tolist(),
+                "rel_err_of_sample_total": (np.abs(tot_g - tot_o) / np.abs(tot_o)).tolist(),
+                "compared": f"{len(om['values'])} (sector, shift) means, 2^{om['m']} points each"}
+    finally:
+        P.sdi_problem_destroy(h)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-log2", type=int, default=16)
+    ap.add_argument("--cpu-log2", type=int, default=12)
+    ap.add_argument("--cpu-stride", type=int, default=10)
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--tune-load", default=None,
                     help="load autotuner decisions (sdi_tune_load) before the run, so profiles time the same instance")
     ap.add_argument("--tune-save", default=None, help="save the autotuner decisions of the run (sdi_tune_save)")
+    ap.add_argument("--only", default=None,
+                    help="profiling aid: run only this workload (batched2000, synthetic64, bubble, doublebox, "
+                         "doublebox_physical) and print its entry")
     ap.add_argument("--no-equal-time", action="store_true",
                     help="skip the learned-sampler comparison (double box, Euclidean and physical)")
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     args = ap.parse_args()
     if args.cpu_baseline_only:
-        print(json.dumps(cpu_baseline(args.cpu_log2)), flush=True)
+        print(json.dumps(cpu_baseline(args.cpu_log2, args.cpu_stride)), flush=True)
         return 0
     if args.gpus != 1:
         print(f"bench.py: this benchmark measures one GPU only (asked for --gpus {args.gpus}); "
@@ -553,76 +813,80 @@ def main() -> int:
               file=sys.stderr)
         return 2
     # the oracle's CPU rate first, in a child process, before anything here touches the GPU
-    cpu = None if args.no_cpu_baseline else _cpu_baseline_subprocess(args.cpu_log2)
-    import numpy as np
-    import torch
+    cpu = None if (args.no_cpu_baseline or args.only) else _cpu_baseline_subprocess(args.cpu_log2, args.cpu_stride)
+    import torch  # noqa: F401
     import paper_1511_03614_amd as P
     import sectorgen
+    from sectorgen.feynman import double_box_problem
 
-    problem = sectorgen.config2()
     ctx = P.sdi_ctx_create(0)
     if args.tune_load:
         P.sdi_tune_load(ctx, args.tune_load)
-    for k, v in WORKLOAD.items():
-        P.sdi_set_param(ctx, k, v)
-    h = P.sdi_problem_create(ctx, problem)
-    for _ in range(args.warmup):
-        P.sdi_integrate(ctx, h)
-    torch.cuda.synchronize()
-    kms, evals = [], 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = P.sdi_integrate(ctx, h)
-        kms.append(r["ms_eval_kernel"])
-        evals += r["n_evals"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = dt / args.steps * 1e3
-    # roofline of the dominant kernel (final-pass tile kernel)
-    lead = problem.pref_lead
-    N = 1 << WORKLOAD["lattice_log2"]
-    R = WORKLOAD["shifts"]
-    fl_launch, logs_launch = 0, 0
-    for sec in problem.sectors:
-        fl, lg = sector_work(sec, problem.order_max, lead, use_grid=WORKLOAD["warmup"] > 0)
-        fl_launch += fl * R * N
-        logs_launch += lg * R * N
-    ms_k = float(np.mean(kms))
-    achieved = fl_launch / (ms_k * 1e-3) / 1e12
+    workloads = {
+        "batched2000": lambda: (sectorgen.config4(), HEADLINE, {}),
+        "synthetic64": lambda: (sectorgen.config2(), SYNTH64, {}),
+        "bubble": lambda: (sectorgen.config1(), dict(lattice_log2=13, shifts=8, seed=1), {}),
+        "doublebox": lambda: (double_box_problem(-3.0, -1.0, 0.0, order_max=0),
+                              dict(shifts=16, seed=1, budget=100_000_000, pilot_log2=10, alloc_min_log2=10,
+                                   alloc_max_log2=18), {}),
+        "doublebox_physical": lambda: (double_box_problem(5.0, -2.0, 1.0, order_max=0, complex_mode=True, lam=0.5),
+                                       dict(lattice_log2=16, shifts=16, seed=1),
+                                       dict(lambda_max=0.5, conservative_if_imf=True)),
+    }
+    if args.only:
+        prob, prm, kw = workloads[args.only]()
+        m = measure(P, ctx, prob, prm, args.steps, args.warmup, **kw)
+        ent = config_entry(P, prob, m, args.only, use_grid=prm.get("warmup", 0) > 0,
+                           sources=KERNEL_SOURCES_CPLX if prob.complex_mode else None)
+        if args.tune_save:
+            P.sdi_tune_save(ctx, args.tune_save)
+        P.sdi_ctx_destroy(ctx)
+        print(json.dumps(strict_json({"workload": args.only, **ent}), allow_nan=False), flush=True)
+        return 0
+    problem = sectorgen.config4()
+    m = measure(P, ctx, problem, HEADLINE, args.steps, args.warmup)
+    head = config_entry(P, problem, m, "batched2000")
+    r = m["r"]
     out = {
         "metric": "sector-integrand evals/s (FP64) + error vs plain QMC at equal GPU time",
-        "value": evals / dt,
+        "value": m["value"],
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "synthetic64: 64 sectors, 3-6 variables, 4-20 terms per factor, "
-                               "|S| <= 2, orders eps^-2..eps^0; Vegas warm-up 5 x 2^14 points, "
-                               "final pass 16 shifts x 2^16 lattice points per sector",
-                   "evals_per_step": evals // args.steps, "points_per_thread": r["ppt"],
-                   "waves_per_simd": r["waves_per_simd"], "tile_log2": r["tile_log2"], "blocks": r["blocks"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": traffic_from_profiles(ms_k),
-                     "kernel": f"k_tiles_real<6, {r['ppt']}, 4, 0, {r['waves_per_simd']}, 2, false> (final pass)",
-                     "ms_per_launch": ms_k,
-                     "flops_per_launch": fl_launch, "logs_per_s": logs_launch / (ms_k * 1e-3)},
-        "error_vs_plain_qmc": None,
-        "result": {"orders": list(range(problem.order_min, problem.order_max + 1)),
-                   "value": [float(v.real) for v in r["value"]], "err": [float(e) for e in r["err_re"]]},
+        "config": {"workload": "batched2000: 2000 synthetic sectors, 4-9 variables, 5-40 terms per factor, |S| <= 3, "
+                               "orders eps^-3..eps^0; per step a pilot pass of 16 shifts x 2^12 lattice points per "
+                               "sector, Neyman allocation of a 2^31-evaluation final budget in per-sector lattices of "
+                               "2^16..2^24 evaluations, one persistent graph-captured autotuned final launch",
+                   "evals_per_step": m["evals_per_step"], "final_evals_per_step": head["final_evals"],
+                   "points_per_thread": r["ppt"], "waves_per_simd": r["waves_per_simd"],
+                   "tile_log2": r["tile_log2"], "blocks": r["blocks"]},
+        "roofline": head["roofline"],
+        "result": head["result"],
+        "n_nonfinite": head["n_nonfinite"],
     }
-    P.sdi_problem_destroy(h)
     if args.tune_save:
         P.sdi_tune_save(ctx, args.tune_save)
-    out["text_integrand"] = text_integrand_rate(P, ctx)
-    out["endpoint_precision"] = endpoint_precision_cost(P, ctx, problem)
+    out["parity_vs_oracle"] = parity_vs_oracle(P, ctx, problem, cpu)
+    if not args.no_extras:
+        extra = {}
+        for name in ("synthetic64", "bubble", "doublebox", "doublebox_physical"):
+            prob, prm, kw = workloads[name]()
+            steps = 50 if name == "bubble" else 5
+            mm = measure(P, ctx, prob, prm, steps, 2, **kw)
+            extra[name] = config_entry(P, prob, mm, name, use_grid=prm.get("warmup", 0) > 0,
+                                       sources=KERNEL_SOURCES_CPLX if prob.complex_mode else None)
+        extra["bubble"]["note"] = "latency-dominated (2 sectors, 1 variable): ms_per_step is the figure, not evals/s"
+        out["configs"] = extra
+        out["text_integrand"] = text_integrand_rate(P, ctx)
+        out["endpoint_precision"] = endpoint_precision_cost(P, ctx, sectorgen.config2())
     if not args.no_equal_time:
-        from sectorgen.feynman import double_box_problem
         lat = [dict(lattice_log2=m) for m in range(10, 17)]
         alloc = dict(pilot_log2=10, alloc_min_log2=12, alloc_max_log2=20)
         out["error_vs_plain_qmc"] = [
@@ -630,11 +894,10 @@ def main() -> int:
                                   double_box_problem(-3.0, -1.0, 0.0, order_max=0), plains=lat,
                                   finals=[dict(lattice_log2=m) for m in (12, 13, 14)]),
             equal_time_comparison(P, ctx, "batched2000: 2000 synthetic sectors, 4-9 variables, 5-40 terms, "
-                                          "eps^-3..eps^0; learned form with per-sector budgets 2^16..2^24 "
-                                          "by Neyman allocation, plain form uniform",
+                                          "eps^-3..eps^0; both forms with per-sector budgets 2^16..2^24 by "
+                                          "Neyman allocation",
                                   sectorgen.config4(), m_pilot=10, max_sel=64, common=alloc,
-                                  plains=[dict(lattice_log2=m) for m in range(10, 16)],
-                                  references=[dict(budget=1 << b) for b in (28, 29, 30)],
+                                  plains=[dict(budget=1 << b) for b in range(26, 32)],
                                   finals=[dict(budget=1 << b) for b in (28, 29, 30)]),
             equal_time_comparison(P, ctx, "double box, s=5, t=-2, m^2=1 (physical, contour deformation, "
                                           "lambda tuned in (0, 0.5], 30 sectors, eps^-4..eps^0)",
@@ -649,8 +912,10 @@ def main() -> int:
         ]
     P.sdi_ctx_destroy(ctx)
     if cpu is not None:
+        cpu = dict(cpu)
+        cpu.pop("oracle_shift_means", None)
         out["cpu_baseline"] = cpu
-    print(json.dumps(out), flush=True)
+    print(json.dumps(strict_json(out), allow_nan=False), flush=True)
     return 0
 
 

@@ -126,27 +126,49 @@ def neyman_allocation(estimates: List[SectorEstimate], budget: int, nshifts: int
 
     For every order k with a nonzero total T_k = sum_s (err_re^2 + err_im^2),
     sector s gets the weight sqrt(err_re^2 + err_im^2) / sqrt(T_k); weights add
-    over orders; the sector's share of the budget is proportional to its weight
-    (equal shares if every error is zero), and the lattice log2 is the nearest
-    integer to log2(share / R), clamped to [lo, hi].  Variance-proportional
-    (Neyman) allocation of sampling effort; the paper's integrator adapts
-    points within one integral only (section 4.4), so this is a reading, not
-    the paper's rule.
+    over orders; the sector's share is n_s = budget * w_s / W (equal shares if
+    every error is zero).  Lattices are powers of two: each sector starts at the
+    largest m in [lo, hi] with R 2^m <= n_s (lo if none), then, while the
+    budget allows, the sector furthest below its share (largest n_s / 2^m,
+    ties to the lower index) among those whose doubling still fits in the
+    budget and stays <= hi is doubled.  Variance-proportional (Neyman)
+    allocation of sampling effort, spending the budget to within one lattice
+    doubling; the paper's integrator adapts points within one integral only
+    (section 4.4), so this is a reading, not the paper's rule.
     """
+    import heapq
     nsec = len(estimates)
     K = estimates[0].mean.shape[0]
     w = np.zeros(nsec)
     for k in range(K):
-        tot = sum(e.err_re[k] ** 2 + e.err_im[k] ** 2 for e in estimates)
+        tot = 0.0
+        for e in estimates:
+            tot += e.err_re[k] ** 2 + e.err_im[k] ** 2
         if not tot > 0.0 or not math.isfinite(tot):
             continue
+        rt = math.sqrt(tot)
         for s, e in enumerate(estimates):
-            w[s] += math.sqrt(e.err_re[k] ** 2 + e.err_im[k] ** 2) / math.sqrt(tot)
-    W = float(np.sum(w))
-    out = []
+            w[s] += math.sqrt(e.err_re[k] ** 2 + e.err_im[k] ** 2) / rt
+    W = 0.0
+    for v in w:
+        W += float(v)
+    share = [float(budget) * float(w[s]) / W if W > 0.0 else float(budget) / nsec for s in range(nsec)]
+    m = []
     for s in range(nsec):
-        share = budget * w[s] / W if W > 0.0 else budget / nsec
-        x = share / nshifts
-        v = int(math.floor(math.log2(x) + 0.5)) if x >= 1.0 else 0
-        out.append(min(max(v, lo), hi))
-    return out
+        v = lo
+        while v < hi and float(nshifts) * 2.0 ** (v + 1) <= share[s]:
+            v += 1
+        m.append(v)
+    used = sum(nshifts << v for v in m)
+    heap = [(-(share[s] / 2.0 ** m[s]), s) for s in range(nsec) if m[s] < hi]
+    heapq.heapify(heap)
+    while heap:
+        _, s = heapq.heappop(heap)
+        cost = nshifts << m[s]
+        if used + cost > budget:
+            continue                      # never fits later: the remaining budget only shrinks
+        used += cost
+        m[s] += 1
+        if m[s] < hi:
+            heapq.heappush(heap, (-(share[s] / 2.0 ** m[s]), s))
+    return m

@@ -771,9 +771,13 @@ int run_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, PassOut& o) {
 
 // Neyman-style allocation of the final-pass budget: for every order k with a
 // nonzero total, sector s gets the weight sigma_{s,k} / sqrt(sum_s sigma_{s,k}^2)
-// (sigma^2 = err_re^2 + err_im^2 of the pilot); weights add over orders;
-// n_s = budget * weight_s / sum weight, and m_s = round(log2(n_s / R)) clamped
-// to [alloc_min, alloc_max].  Equal weights when every pilot error is zero.
+// (sigma^2 = err_re^2 + err_im^2 of the pilot); weights add over orders and
+// the sector's share is n_s = budget * weight_s / sum weight (equal shares when
+// every pilot error is zero).  Lattices are powers of two: every sector starts
+// at the largest m in [alloc_min, alloc_max] with R 2^m <= n_s (alloc_min if
+// none); then, while a doubling fits in the budget, the sector furthest below
+// its share (largest n_s / 2^m, ties to the lower index) among those that can
+// still double is doubled.  The budget is spent to within one doubling.
 std::vector<int> neyman_allocation(const sdi_problem* pb, const std::vector<double>& sec_stats, const Params& prm) {
   const int nsec = pb->nsec;
   std::vector<double> wsec(nsec, 0.0);
@@ -792,12 +796,38 @@ std::vector<int> neyman_allocation(const sdi_problem* pb, const std::vector<doub
   }
   double W = 0.0;
   for (double w : wsec) W += w;
+  std::vector<double> share(nsec);
   std::vector<int> m(nsec);
+  int64_t used = 0;
   for (int s = 0; s < nsec; ++s) {
-    const double ns = W > 0.0 ? (double)prm.budget * wsec[s] / W : (double)prm.budget / nsec;
-    const double x = ns / prm.R;
-    int v = x >= 1.0 ? (int)std::lround(std::log2(x)) : 0;
-    m[s] = std::min(std::max(v, prm.alloc_min), prm.alloc_max);
+    share[s] = W > 0.0 ? (double)prm.budget * wsec[s] / W : (double)prm.budget / nsec;
+    int v = prm.alloc_min;
+    while (v < prm.alloc_max && (double)prm.R * std::ldexp(1.0, v + 1) <= share[s]) ++v;
+    m[s] = v;
+    used += (int64_t)prm.R << v;
+  }
+  // greedy doublings: largest share / 2^m first; a sector that does not fit
+  // now never fits later (the remaining budget only shrinks)
+  auto worse = [&](int a, int b) {
+    const double ra = std::ldexp(share[a], -m[a]), rb = std::ldexp(share[b], -m[b]);
+    return ra < rb || (ra == rb && a > b);
+  };
+  std::vector<int> heap;
+  for (int s = 0; s < nsec; ++s)
+    if (m[s] < prm.alloc_max) heap.push_back(s);
+  std::make_heap(heap.begin(), heap.end(), worse);
+  while (!heap.empty()) {
+    std::pop_heap(heap.begin(), heap.end(), worse);
+    const int s = heap.back();
+    heap.pop_back();
+    const int64_t cost = (int64_t)prm.R << m[s];
+    if (used + cost > prm.budget) continue;
+    used += cost;
+    ++m[s];
+    if (m[s] < prm.alloc_max) {
+      heap.push_back(s);
+      std::push_heap(heap.begin(), heap.end(), worse);
+    }
   }
   return m;
 }

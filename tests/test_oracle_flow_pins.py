@@ -59,11 +59,11 @@ def test_training_reaches_the_chi2_optimal_density(kind):
     else:
         f = lambda x: np.where(x < 0.3, 4.0, 1.0)
         cdf = lambda x: np.where(x < 0.3, 4.0 * x, 1.2 + (x - 0.3)) / 1.9
-    m = 11
+    m = 9
     z = points.cbc_vector(m, 1)
     P = flow.init_params(1, 3, 0)
     st = flow.adam_init(P)
-    for step in range(120):
+    for step in range(150):
         u = points.lattice_u(z, m, points.shift_table(17, 0, step + 1, 1, m)[step], 0, 1 << m)
         x, lq = flow.sample(P, u)
         c = flow.importance_weights(f(x[:, 0])[None, :], lq)

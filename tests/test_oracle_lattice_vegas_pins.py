@@ -133,7 +133,7 @@ def fixed_point_grid(coef, nb: int) -> np.ndarray:
             if poly_bin_integrals(np.array([a, 1.0]), coef)[0] * (1.0 - a) < c:
                 return None
             lo, hi = a, 1.0
-            for _ in range(200):
+            for _ in range(56):
                 mid = 0.5 * (lo + hi)
                 if (mid - a) * poly_bin_integrals(np.array([a, mid]), coef)[0] < c:
                     lo = mid
@@ -142,7 +142,7 @@ def fixed_point_grid(coef, nb: int) -> np.ndarray:
             g.append(0.5 * (lo + hi))
         return g
     lo, hi = 0.0, 1.0
-    for _ in range(200):
+    for _ in range(60):
         c = 0.5 * (lo + hi)
         g = edges_for(c)
         if g is None or g[-1] < 1.0 - 1e-15:

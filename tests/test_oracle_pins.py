@@ -382,14 +382,29 @@ def test_box_worked_example_section_4_3():
 
 
 def test_neyman_allocation_properties():
-    """Shares follow the errors, clamps hold, equal errors give equal sizes."""
+    """Shares follow the errors, clamps hold, equal errors give equal sizes, and
+    the budget is spent to within one doubling."""
     from oracle.integrate import SectorEstimate, neyman_allocation
 
     def est(e):
         return SectorEstimate(np.zeros((2, 1), complex), np.zeros(1, complex), np.array([e]), np.array([0.0]), 0, 0, None)
-    m = neyman_allocation([est(1.0), est(4.0), est(0.25)], 3 * 16 * 1024, 16, 4, 20)
-    assert m[1] > m[0] > m[2]
-    assert m[1] - m[0] == 2 and m[0] - m[2] == 2
-    assert neyman_allocation([est(1.0)] * 4, 4 * 16 * 1024, 16, 4, 20) == [10] * 4
-    assert neyman_allocation([est(0.0)] * 3, 3 * 16 * 256, 16, 4, 20) == [8] * 3
-    assert neyman_allocation([est(1e9), est(1e-9)], 1 << 40, 16, 6, 12) == [12, 6]
+    R = 16
+    budget = 3 * R * 1024
+    m = neyman_allocation([est(1.0), est(4.0), est(0.25)], budget, R, 4, 20)
+    assert m[1] > m[0] >= m[2]
+    assert m[1] - m[0] == 2
+    used = sum(R << v for v in m)
+    assert used <= budget and all(used + (R << v) > budget for v in m)   # no doubling fits any more
+    assert neyman_allocation([est(1.0)] * 4, 4 * R * 1024, R, 4, 20) == [10] * 4
+    assert neyman_allocation([est(0.0)] * 3, 3 * R * 256, R, 4, 20) == [8] * 3
+    assert neyman_allocation([est(1e9), est(1e-9)], (R << 12) + (R << 6), R, 6, 12) == [12, 6]
+    assert neyman_allocation([est(1e9), est(1e-9)], 1 << 40, R, 6, 12) == [12, 12]   # budget left over: filled
+    # a large problem: total within one smallest doubling of the budget, sizes ordered by error
+    rng = np.random.default_rng(3)
+    errs = np.exp(rng.normal(size=300) * 2)
+    b = 1 << 26
+    m = neyman_allocation([est(e) for e in errs], b, R, 8, 18)
+    used = sum(R << v for v in m)
+    assert b - (R << 18) < used <= b
+    order = np.argsort(errs)
+    assert all(m[order[i]] <= m[order[i + 2]] + 1 for i in range(len(order) - 2))
