@@ -50,16 +50,18 @@ def _bits(e):
     return (e & 1) + 2 * ((e >> 1) & 1) + 4 * ((e >> 2) & 1)
 
 
-def sector_work(sec, order_max: int, pref_lead: int, use_grid: bool):
+def sector_work(sec, order_max: int, pref_lead: int, use_grid: bool, grouped: bool = True):
     """Algorithmic FP64 operations (add/sub/mul/div = 1, FMA = 2) and logarithms per evaluation.
 
     Counts the arithmetic of the method as the tile kernel performs it: lattice
-    tent map and Vegas map, the polynomial terms of every corner (one multiply
-    per exponent bit, x^2 as two multiplies, one add), integer powers of the
-    factors, the subtraction/series combination for every (corner, subset)
-    pair, the monomial and the weighted accumulation.  Logarithms are counted
-    apart and not as flops; integer work and compensation (two-sum) are not
-    counted.
+    tent map and Vegas map; the polynomial terms (a term c prod x_j^e_j costs
+    sum e_j multiplies and one add) - with `grouped`, every term once and the
+    corner values as sums of the singular-support group sums (one add per
+    group and corner it reaches), else every corner's own list; integer powers
+    of the factors; the subtraction/series combination for every (corner,
+    subset) pair; the monomial and the weighted accumulation.  Logarithms are
+    counted apart and not as flops; integer work and compensation (two-sum)
+    are not counted.
     """
     import numpy as np
     n = sec.n
@@ -70,12 +72,22 @@ def sector_work(sec, order_max: int, pref_lead: int, use_grid: bool):
     fl += n + 2 * ns
     logs = ns + 1
     fl += sum(abs(int(sec.b[j])) + int(sec.a[j]) for j in range(n) if j not in S) + 3
+    if grouped:
+        for fac in sec.factors:
+            e = fac.exps.astype(np.int64)
+            fl += int(sum(_bits(int(v)) for v in e.ravel())) + len(e)
+            sup = np.zeros(len(e), dtype=np.int64)
+            for i, j in enumerate(S):
+                sup |= (e[:, j] != 0).astype(np.int64) << i
+            for sg in set(sup.tolist()):
+                fl += 1 << (ns - bin(sg).count("1"))
     for W in range(1 << ns):
         zero = [S[i] for i in range(ns) if W >> i & 1]
         for fac in sec.factors:
-            alive = np.all(fac.exps[:, zero] == 0, axis=1) if zero else np.ones(len(fac.coef), bool)
-            e = fac.exps[alive].astype(np.int64)
-            fl += int(sum(_bits(int(v)) for v in e.ravel())) + int(alive.sum())
+            if not grouped:
+                alive = np.all(fac.exps[:, zero] == 0, axis=1) if zero else np.ones(len(fac.coef), bool)
+                e = fac.exps[alive].astype(np.int64)
+                fl += int(sum(_bits(int(v)) for v in e.ravel())) + int(alive.sum())
             fl += abs(int(fac.gamma)) + abs(int(fac.delta))
         fl += 4
         logs += 1
@@ -149,14 +161,15 @@ def sector_work_complex(sec, order_max: int, pref_lead: int, mono_f=None):
     return fl, tr
 
 
-def launch_work(problem, nevals, lead, use_grid=False):
-    """(flops, transcendentals) of one final-pass launch: per-sector work times its evaluations."""
+def launch_work(problem, nevals, lead, use_grid=False, grouped=True):
+    """(flops, transcendentals) of one final-pass launch: per-sector work times its
+    evaluations; `grouped`: the launch evaluated every term once (sdi_result.grouped)."""
     fl = tr = 0
     for sec, ne in zip(problem.sectors, nevals):
         if problem.complex_mode:
             f, t = sector_work_complex(sec, problem.order_max, lead)
         else:
-            f, t = sector_work(sec, problem.order_max, lead, use_grid)
+            f, t = sector_work(sec, problem.order_max, lead, use_grid, grouped)
         fl += f * ne
         tr += t * ne
     return fl, tr
@@ -712,7 +725,7 @@ def measure(P, ctx, problem, params, steps, warmup, lambda_max=None, conservativ
 
 def roofline(P, problem, m, kernel, workload, use_grid=False, sources=None):
     lead = P._prefactor_of(problem)[0]
-    fl, tr = launch_work(problem, m["nevals"], lead, use_grid)
+    fl, tr = launch_work(problem, m["nevals"], lead, use_grid, bool(m["r"]["grouped"]))
     achieved = fl / (m["ms_kernel"] * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": traffic_from_profiles(workload, sources),
@@ -721,16 +734,21 @@ def roofline(P, problem, m, kernel, workload, use_grid=False, sources=None):
 
 
 def _kernel_name(r, problem, nvmax, nsm):
+    """Template arguments of the final-pass instance the run used (sdi_result:
+    points per thread, waves, grouped or per-corner term lists)."""
     if problem.complex_mode:
         return f"k_tiles_cplx<{nvmax}, {r['ppt']}, KM, 0, {r['waves_per_simd']}> (final pass)"
-    return f"k_tiles_real<{nvmax}, {r['ppt']}, KM, 0, {r['waves_per_simd']}, {nsm}, false> (final pass)"
+    if r["grouped"]:
+        return f"k_tiles_real<{nvmax}, {r['ppt']}, KM, 0, {r['waves_per_simd']}, {nsm}, false, 2> (final pass)"
+    return f"k_tiles_real<{nvmax}, {r['ppt']}, KM, 0, {r['waves_per_simd']}> (final pass, per-corner term lists)"
 
 
 def _classes(problem):
+    """Register class and singular-variable bound of the final pass instances."""
     nv = max(s.n for s in problem.sectors)
     nsm = max(int(sum(s.a == -1.0)) for s in problem.sectors)
     nvc = 4 if nv <= 4 else 6 if nv <= 6 else 8 if nv <= 8 else 16
-    return nvc, (2 if nsm <= 2 else 4)
+    return nvc, (2 if nsm <= 2 else nsm)
 
 
 def config_entry(P, problem, m, workload, use_grid=False, sources=None):

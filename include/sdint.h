@@ -198,6 +198,10 @@ void sdi_problem_destroy(sdi_problem* prob);
 /* Number of result orders K / of sectors of a problem (SDI_EINVAL for NULL). */
 int sdi_problem_norders(const sdi_problem* prob);
 int sdi_problem_nsectors(const sdi_problem* prob);
+/* Number of variables n of sector s (the column count of its points in
+ * sdi_evaluate, sdi_sample_points and the flow calls); SDI_EINVAL for a NULL
+ * problem or s out of range. */
+int sdi_problem_nvars(const sdi_problem* prob, int32_t s);
 
 /* Laurent series of the Feynman prefactor of eq. (2) with (i pi^(d/2))^l and
  * exp(-l gamma_E eps) pulled out (section 4.3):
@@ -229,6 +233,9 @@ typedef struct {
   int32_t blocks;
   int32_t tile_log2;            /* final-pass tile size used (log2 of points)         */
   int32_t waves_per_simd;       /* minimum waves per SIMD the kernel was built for    */
+  int32_t grouped;              /* 1: that kernel evaluated every polynomial term once
+                                   per point (terms grouped by singular support),
+                                   0: once per subtraction corner                      */
 } sdi_result;
 
 /* Bytes of device workspace sdi_integrate needs under the current parameters. */
@@ -265,6 +272,21 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, const void* x
  * x: device [npts][n], w: device [npts] (NULL allowed).  Synchronises. */
 int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, int32_t shift,
                       int64_t i0, int64_t npts, void* x_dev, void* w_dev);
+
+/* One refit of a Vegas grid on caller data, the step sdi_integrate's warm-up
+ * takes after every iteration (Lepage's VEGAS refinement behind the Vegas
+ * integrator of section 4.4; parity hook): for each dimension j < n,
+ * hist_dev [n][nbins][k] holds per bin the sums of |w f_kk|^2 of the points in
+ * it for the k internal orders; the importance d_b = sum over orders with a
+ * nonzero total H of h_bk / H, smoothed over 3 bins (2 at the ends), is
+ * compressed to ((r - 1) / ln r)^alpha with r = d_b / sum d, and the edges
+ * grid_dev [n][nbins + 1] (device, in place) are moved so that each new bin
+ * holds an equal share of the compressed importance, linearly inside the old
+ * bins.  A dimension whose histogram is all zero keeps its edges.  n 1..16,
+ * nbins a power of 2 in 2..256, k 1..8, alpha >= 0 (the integrator uses 1.5).
+ * Stream-ordered; synchronises.  SDI_EINVAL for arguments out of range. */
+int sdi_vegas_refit(sdi_ctx* ctx, int32_t n, int32_t nbins, int32_t k, const void* hist_dev, void* grid_dev,
+                    double alpha);
 
 /* Automatic deformation size (the ComplexMode tuning of section 4.4) for a
  * complex-mode problem: per sector, candidates lam_k = top * k / split
@@ -328,6 +350,14 @@ int sdi_flow_adam(sdi_ctx* ctx, sdi_problem* prob, double lr);
  * active.  *ms_out: device time (may be NULL). */
 int sdi_flow_train(sdi_ctx* ctx, sdi_problem* prob, const int32_t* sectors, int32_t nsel, int32_t iters,
                    int32_t batch_log2, double lr, const double* order_weights, float* ms_out);
+/* The loss weights of sdi_flow_train on caller data (parity hook): with
+ * S_k = sum_i |F_k(x_i)|^2 exp(-2 lq_i), c_i = sum over orders with S_k > 0
+ * and finite of w_k |F_k(x_i)|^2 exp(-2 lq_i) / S_k, w_k = order_weights[k]
+ * (host [K], finite, >= 0, not all zero; NULL = all 1).  f_dev device
+ * [npts][K][2] (re, im), lq_dev device [npts] (log q), c_dev device [npts]
+ * (out); npts 0..2^32-1, K 1..8.  Stream-ordered; synchronises. */
+int sdi_flow_weights(sdi_ctx* ctx, int64_t npts, int32_t K, const void* f_dev, const void* lq_dev,
+                     const double* order_weights, void* c_dev);
 /* Sectors whose flow is active take their points from it in passes with
  * sampler = 1; the others stay on the lattice (with sdi_flow_set_params or
  * training a sector becomes active; sdi_flow_init clears every flag). */

@@ -25,7 +25,7 @@ __all__ = [
     "sdi_integrate", "sdi_sector_results", "sdi_evaluate", "sdi_sample_points",
     "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
     "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_flow_set_active", "sdi_flow_validate",
-    "sdi_tune_deformation",
+    "sdi_tune_deformation", "sdi_problem_nvars", "sdi_vegas_refit", "sdi_flow_weights",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -68,7 +68,7 @@ class Result(C.Structure):
                 ("n_evals", C.c_int64), ("n_nonfinite", C.c_int64), ("n_imf_positive", C.c_int64),
                 ("ms_sample_eval_reduce", C.c_double), ("ms_refit", C.c_double), ("ms_total", C.c_double),
                 ("ms_eval_kernel", C.c_double), ("points_per_thread", C.c_int32), ("blocks", C.c_int32),
-                ("tile_log2", C.c_int32), ("waves_per_simd", C.c_int32)]
+                ("tile_log2", C.c_int32), ("waves_per_simd", C.c_int32), ("grouped", C.c_int32)]
 
 
 def library_path() -> str:
@@ -113,6 +113,9 @@ def load_library():
         "sdi_problem_destroy": (None, [vp]),
         "sdi_problem_norders": (C.c_int, [vp]),
         "sdi_problem_nsectors": (C.c_int, [vp]),
+        "sdi_problem_nvars": (C.c_int, [vp, i32]),
+        "sdi_vegas_refit": (C.c_int, [vp, i32, i32, i32, vp, vp, C.c_double]),
+        "sdi_flow_weights": (C.c_int, [vp, i64, i32, vp, vp, dp, vp]),
         "sdi_workspace_bytes": (C.c_size_t, [vp, vp]),
         "sdi_integrate": (C.c_int, [vp, vp, vp, C.c_size_t, C.POINTER(Result)]),
         "sdi_sector_results": (C.c_int, [vp, vp, i32, dp, dp, dp, C.POINTER(i64)]),
@@ -161,7 +164,33 @@ def sdi_ctx_create(device: int = 0, stream: Optional[int] = None):
         stream = torch.cuda.current_stream(device).cuda_stream
     h = C.c_void_p()
     _check(lib.sdi_ctx_create(device, C.c_void_p(stream), C.byref(h)))
+    _CTX_DEVICE[h.value] = device
     return h
+
+
+_CTX_DEVICE = {}   # context -> device ordinal, for checking device arguments
+
+
+def _device_tensor(ctx, t, name: str, shape):
+    """Checks a device argument before its pointer goes to the library (which
+    cannot check the size of a buffer): fp64, on the context's device,
+    contiguous, of the given shape (None = any extent)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise SdiError(-1, f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise SdiError(-1, f"{name} must be float64, got {t.dtype}")
+    dev = _CTX_DEVICE.get(ctx.value if hasattr(ctx, "value") else ctx)
+    if not t.is_cuda or (dev is not None and t.device.index != dev):
+        raise SdiError(-1, f"{name} must be on cuda:{dev}, got {t.device}")
+    if t.dim() != len(shape) or any(w is not None and t.shape[i] != w for i, w in enumerate(shape)):
+        raise SdiError(-1, f"{name} must have shape {tuple('*' if w is None else w for w in shape)}, "
+                           f"got {tuple(t.shape)}")
+    return t.contiguous()
+
+
+def sdi_problem_nvars(prob, s: int) -> int:
+    return _check_count(load_library().sdi_problem_nvars(prob, s))
 
 
 def sdi_ctx_destroy(ctx):
@@ -308,7 +337,7 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
     """Run the integrator; `workspace` is an optional torch uint8 cuda tensor."""
     K = sdi_problem_norders(prob)
     arrs = [np.zeros(K) for _ in range(4)]
-    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0)
+    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0)
     ptr, nbytes = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()), workspace.numel())
     if workspace is not None:
         import torch
@@ -319,7 +348,7 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
             "n_imf_positive": res.n_imf_positive, "ms_final": res.ms_sample_eval_reduce,
             "ms_warmup": res.ms_refit, "ms_total": res.ms_total, "ms_eval_kernel": res.ms_eval_kernel,
             "ppt": res.points_per_thread, "blocks": res.blocks, "tile_log2": res.tile_log2,
-            "waves_per_simd": res.waves_per_simd}
+            "waves_per_simd": res.waves_per_simd, "grouped": res.grouped}
 
 
 def sdi_sector_results(ctx, prob, s: int, nshifts: int):
@@ -337,7 +366,7 @@ def sdi_evaluate(ctx, prob, s: int, x, with_cond: bool = False):
     and with_cond also the per-order sums of |term| (npts, K)."""
     import torch
     K = sdi_problem_norders(prob)
-    x = x.contiguous()
+    x = _device_tensor(ctx, x, "x", (None, sdi_problem_nvars(prob, s)))
     out = torch.empty((x.shape[0], K, 2), dtype=torch.float64, device=x.device)
     cond = torch.empty((x.shape[0], K), dtype=torch.float64, device=x.device) if with_cond else None
     torch.cuda.current_stream(x.device).synchronize()
@@ -355,6 +384,37 @@ def sdi_sample_points(ctx, prob, s: int, shift: int, i0: int, npts: int, nvars: 
     _check(load_library().sdi_sample_points(ctx, prob, s, shift, i0, npts, C.c_void_p(x.data_ptr()),
                                             C.c_void_p(w.data_ptr())), ctx)
     return x, w
+
+
+def sdi_vegas_refit(ctx, hist, grid, alpha: float = 1.5):
+    """One Vegas refit on the device: hist (n, nbins, k) float64 cuda tensor of
+    per-bin sums of |w f_k|^2, grid (n, nbins + 1) edges, refitted in place."""
+    import torch
+    n, nb, k = hist.shape
+    hist = _device_tensor(ctx, hist, "hist", (n, nb, k))
+    if not grid.is_contiguous():
+        raise SdiError(-1, "grid must be contiguous (it is updated in place)")
+    _device_tensor(ctx, grid, "grid", (n, nb + 1))
+    torch.cuda.current_stream(grid.device).synchronize()
+    _check(load_library().sdi_vegas_refit(ctx, n, nb, k, C.c_void_p(hist.data_ptr()), C.c_void_p(grid.data_ptr()),
+                                          float(alpha)), ctx)
+    return grid
+
+
+def sdi_flow_weights(ctx, f, lq, order_weights=None):
+    """Training loss weights on the device: f (npts, K, 2) and lq (npts,) float64 cuda tensors."""
+    import torch
+    npts, K = f.shape[0], f.shape[1]
+    f = _device_tensor(ctx, f, "f", (npts, K, 2))
+    lq = _device_tensor(ctx, lq, "lq", (npts,))
+    c = torch.empty((npts,), dtype=torch.float64, device=f.device)
+    w = None if order_weights is None else np.ascontiguousarray(order_weights, dtype=np.float64)
+    if w is not None and w.shape != (K,):
+        raise ValueError("order_weights needs one weight per order")
+    torch.cuda.current_stream(f.device).synchronize()
+    _check(load_library().sdi_flow_weights(ctx, npts, K, C.c_void_p(f.data_ptr()), C.c_void_p(lq.data_ptr()),
+                                           _dptr(w) if w is not None else None, C.c_void_p(c.data_ptr())), ctx)
+    return c
 
 
 # ---------------------------------------------------------------- deformation size
@@ -399,7 +459,7 @@ def sdi_flow_set_params(ctx, prob, s: int, values):
 def sdi_flow_sample(ctx, prob, s: int, u):
     """u: torch float64 cuda tensor (npts, n); returns (x, log q) cuda tensors."""
     import torch
-    u = u.contiguous()
+    u = _device_tensor(ctx, u, "u", (None, sdi_problem_nvars(prob, s)))
     x = torch.empty_like(u)
     lq = torch.empty((u.shape[0],), dtype=torch.float64, device=u.device)
     torch.cuda.current_stream(u.device).synchronize()
@@ -411,8 +471,8 @@ def sdi_flow_sample(ctx, prob, s: int, u):
 def sdi_flow_grad(ctx, prob, s: int, x, c) -> np.ndarray:
     """x: (npts, n), c: (npts,) torch float64 cuda tensors; returns the fp32 gradient."""
     import torch
-    x = x.contiguous()
-    c = c.contiguous()
+    x = _device_tensor(ctx, x, "x", (None, sdi_problem_nvars(prob, s)))
+    c = _device_tensor(ctx, c, "c", (x.shape[0],))
     g = np.empty(sdi_flow_nparams(prob, s), dtype=np.float32)
     torch.cuda.current_stream(x.device).synchronize()
     _check(load_library().sdi_flow_grad(ctx, prob, s, C.c_void_p(x.data_ptr()), C.c_void_p(c.data_ptr()),

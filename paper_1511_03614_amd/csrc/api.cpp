@@ -331,6 +331,25 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
         }
         R.tab_cnt[m][W] = cnt;
       }
+      // the same terms by singular support (each term once)
+      R.grp_mask[m] = 0;
+      for (int sg = 0; sg < (1 << R.ns); ++sg) {
+        R.grp_off[m][sg] = (uint32_t)pb->terms.size();
+        uint32_t cnt = 0;
+        for (int t = 0; t < nt; ++t) {
+          const uint8_t* e = sd.term_exps + (t0 + t) * n;
+          int sup = 0;
+          for (int i = 0; i < R.ns; ++i)
+            if (e[S[i]] != 0) sup |= 1 << i;
+          if (sup != sg) continue;
+          uint64_t word = 0;
+          for (int j = 0; j < n; ++j) word |= (uint64_t)e[perm[j]] << (4 * j);
+          pb->terms.push_back(Term{sd.term_coef[t0 + t], word});
+          ++cnt;
+        }
+        R.grp_cnt[m][sg] = cnt;
+        if (cnt) R.grp_mask[m] |= 1u << sg;
+      }
       t0 += nt;
     }
     if (d->complex_mode) {
@@ -415,12 +434,12 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
         if (fi != 0.0) has_im = true;
       }
     if (has_im) R.flags |= F_HAS_IM;
-    // cost estimate per point: polynomial work over corners plus series and logs
+    // cost estimate per point: polynomial work (every term once, by singular
+    // support, plus the corner sums), corners with their logs, and the series
     double c = 40.0 * (n + 1);
-    for (int W = 0; W < (1 << R.ns); ++W) {
-      for (int m = 0; m < sd.nfactors; ++m) c += 6.0 * R.tab_cnt[m][W];
-      c += 80.0 + 3.0 * R.kf * (1 << R.ns);
-    }
+    for (int m = 0; m < sd.nfactors; ++m)
+      for (int sg = 0; sg < (1 << R.ns); ++sg) c += (2.0 + n) * R.grp_cnt[m][sg] + 2.0 * (1 << R.ns);
+    for (int W = 0; W < (1 << R.ns); ++W) c += 80.0 + 3.0 * R.kf * (1 << R.ns);
     pb->cost.push_back(c);
     pb->secs.push_back(R);
     // variable class of the persistent kernel instance; the <= 6 class needs fewer
@@ -430,6 +449,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     if (d->complex_mode) c *= 8.0 + 2.0 * n * n;
     pb->kfmax = std::max(pb->kfmax, R.kf);
     pb->nsmax = std::max(pb->nsmax, R.ns);
+    pb->nfmax = std::max(pb->nfmax, R.nfac);
   }
   if (pb->terms.empty()) pb->terms.push_back(Term{0.0, 0});
   hipError_t e = hipSetDevice(ctx->device);
@@ -473,6 +493,11 @@ void sdi_problem_destroy(sdi_problem* pb) {
 int sdi_problem_norders(const sdi_problem* pb) { return pb ? pb->K : SDI_EINVAL; }
 
 int sdi_problem_nsectors(const sdi_problem* pb) { return pb ? pb->nsec : SDI_EINVAL; }
+
+int sdi_problem_nvars(const sdi_problem* pb, int32_t s) {
+  if (!pb || s < 0 || s >= pb->nsec) return SDI_EINVAL;
+  return pb->secs[s].n;
+}
 
 int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_dev, int64_t npts, void* out_dev,
                  void* cond_dev) {

@@ -79,6 +79,7 @@ struct PassState {
   std::string key;
   Plan P;
   int ppt = 1, wpe = 4, km = 4, gf = 1, gw = 1, gx = 1;
+  bool lists = false;   // final pass on the generic (per-corner list) instances
   hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};   // warm-up, final tiles, reductions
   void* own_ws = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // recorded between segment launches
@@ -301,56 +302,92 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   return SDI_OK;
 }
 
-// Final-pass launch variants the autotuner times, encoded as 10 * points per
-// thread + minimum waves per SIMD (1: no constraint).
-std::vector<int> tile_variants(const sdi_problem* pb) {
-  if (pb->is_expr()) return {11};
-  if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{11, 12, 21} : std::vector<int>{11, 12};
-  if (pb->nvmax >= 16) return {14, 23, 24};
-  return {14, 23, 24, 42};
-}
-
-// The endpoint-precision instance for problems with a sector of more than 2
-// singular variables (real mode, small_x > 0): one point per thread, at least
-// 2 waves per SIMD, the only final-pass variant there.  Problems with at most
-// 2 keep the tuned variants, in their double-double-capable copies.
-constexpr int DD_VARIANT = 12;
-
 bool uses_dd(const sdi_problem* pb, const Params& p) {
   return p.small_x > 0.0 && !pb->complex_mode && !pb->is_expr();
 }
 
+// Family of real-mode final-pass instances of a problem under the current
+// parameters (see real_family).
+int final_family(const sdi_problem* pb, const Params& p) {
+  return real_family(pb->nsmax, pb->nfmax, 0, uses_dd(pb, p));
+}
+
+// Final-pass launch variants the autotuner times, encoded as 10 * points per
+// thread + minimum waves per SIMD (1: no constraint), plus CORNER_LISTS for the
+// generic instances that evaluate each corner's own term lists: where the
+// grouped instances (each term once) exist, the tuner times both kinds, since
+// the grouped ones hold every corner's factor values in registers and win only
+// where the polynomials outweigh that (measured: the 2000-sector synthetic
+// set gains, the double box with its 16 corners loses).
+constexpr int CORNER_LISTS = 100;
+
+std::vector<int> generic_variants(const sdi_problem* pb) {
+  if (pb->nvmax >= 16) return {14, 23, 24};
+  return {14, 23, 24, 42};
+}
+
+std::vector<int> tile_variants(const sdi_problem* pb, const Params& p) {
+  if (pb->is_expr()) return {11};
+  if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{11, 12, 21} : std::vector<int>{11, 12};
+  std::vector<int> v;
+  switch (final_family(pb, p)) {
+    case RF_G3: v = {12, 14, 22, 23}; break;
+    case RF_G4: v = {12, 13, 21, 22}; break;
+    case RF_S2: v = generic_variants(pb); break;
+    case RF_DD: return {12};
+    default: return generic_variants(pb);
+  }
+  if (!uses_dd(pb, p))
+    for (int g : generic_variants(pb)) v.push_back(CORNER_LISTS + g);
+  return v;
+}
+
+// The endpoint-precision instance outside the two-singular-variable family
+// (real mode, small_x > 0): one point per thread, at least 2 waves per SIMD,
+// the only final-pass variant there.  Problems in that family keep the tuned
+// variants, in their double-double-capable copies.
+constexpr int DD_VARIANT = 12;
+
 // The variant used for a fixed points-per-thread request.
-int default_variant(const sdi_problem* pb, int ppt) {
+int default_variant(const sdi_problem* pb, const Params& p, int ppt) {
   if (pb->is_expr()) return 11;   // one point per lane and step
   if (pb->complex_mode) return 10 * ppt + 1;
-  return ppt == 4 ? 42 : 10 * ppt + 4;
+  switch (final_family(pb, p)) {
+    case RF_G3: return ppt == 1 ? 14 : 22;
+    case RF_G4: return ppt == 1 ? 12 : 22;
+    case RF_DD: return DD_VARIANT;
+    default: break;
+  }
+  return ppt == 4 ? (pb->nvmax >= 16 ? 24 : 42) : 10 * ppt + 4;
 }
 
 // Whether an encoded variant is one the tuner or a points-per-thread request
 // can select for the problem's class.
-bool variant_known(const sdi_problem* pb, int v) {
-  if (v == DD_VARIANT && !pb->complex_mode && !pb->is_expr()) return true;
-  for (int u : tile_variants(pb))
+bool variant_known(const sdi_problem* pb, const Params& p, int v) {
+  for (int u : tile_variants(pb, p))
     if (u == v) return true;
-  for (int p : {1, 2, 4})
-    if (default_variant(pb, p) == v) return true;
+  for (int q : {1, 2, 4})
+    if (default_variant(pb, p, q) == v) return true;
   return false;
 }
 
+// corner_lists: the generic instances (each corner's term lists) even where
+// grouped ones exist.
 int launch_tiles(const sdi_problem* pb, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
-                 hipStream_t st) {
+                 hipStream_t st, bool corner_lists = false) {
   if (pb->is_expr()) return launch_tiles_expr(grid, shmem, a, expr_args(pb), st);
   if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, wpe, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
-  return launch_tiles_real(pb->nvmax, pb->nsmax, ppt, wpe, km, grid, shmem, a, st);
+  return launch_tiles_real(pb->nvmax, pb->nsmax, corner_lists ? MAXF + 1 : pb->nfmax, ppt, wpe, km, grid, shmem, a,
+                           st);
 }
 
 int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int wpe, int km, size_t shmem,
-                    size_t ntiles) {
+                    size_t ntiles, bool corner_lists = false) {
   const int nvmax = pb->nvmax;
+  const int nf = corner_lists ? MAXF + 1 : pb->nfmax;
   int occ = pb->is_expr()                             ? tiles_expr_occupancy(mode, shmem, expr_args(pb))
             : pb->complex_mode                        ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, shmem)
-                                                      : tiles_real_occupancy(nvmax, pb->nsmax, mode, ppt, wpe, km,
+                                                      : tiles_real_occupancy(nvmax, pb->nsmax, nf, mode, ppt, wpe, km,
                                                                              uses_dd(pb, ctx->params), shmem);
   if (occ < 1) occ = 1;
   const size_t g = (size_t)occ * std::max(ctx->ncu, 1);
@@ -447,7 +484,7 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
   } else if (seg == 1) {
     KCHK(ctx, launch_fill_i32(P.d_counter + 1, 0, 2, st));
     if (!P.forder.empty())
-      KCHK(ctx, launch_tiles(pb, S.ppt, S.wpe, S.km, S.gf, P.shmem_final, final_args(pb, P), st));
+      KCHK(ctx, launch_tiles(pb, S.ppt, S.wpe, S.km, S.gf, P.shmem_final, final_args(pb, P), st, S.lists));
     if (!P.xorder.empty())
       KCHK(ctx, launch_tiles(pb, 1, 4, S.km, S.gx, P.shmem_final, final_args(pb, P, true), st));
   } else {
@@ -554,15 +591,16 @@ int time_final(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int variant, float* 
   KCHK(ctx, launch_shifts(P.d_secs, pb->nsec, P.rows, prm.R, prm.seed, 0u, P.d_shifts, st));
   if (prm.warmup > 0 && !pb->grid_valid) KCHK(ctx, launch_grid_identity(P.d_secs, pb->nsec, pb->d_grids, st));
   const TileArgs F = final_args(pb, P);
-  const int ppt = variant / 10, wpe = variant % 10;
-  const int g = persistent_grid(ctx, pb, 0, ppt, wpe, S.km, P.shmem_final, P.forder.size());
+  const bool lists = variant >= CORNER_LISTS;
+  const int ppt = (variant % CORNER_LISTS) / 10, wpe = variant % 10;
+  const int g = persistent_grid(ctx, pb, 0, ppt, wpe, S.km, P.shmem_final, P.forder.size(), lists);
   float best = 0.f;
   int reps = 2;
   for (int rep = 0; rep < reps; ++rep) {
     float ms = 0.f;
     KCHK(ctx, launch_fill_i32(F.counter, 0, 1, st));
     HIPCHK(ctx, hipEventRecord(S.ev[1], st));
-    KCHK(ctx, launch_tiles(pb, ppt, wpe, S.km, g, P.shmem_final, F, st));
+    KCHK(ctx, launch_tiles(pb, ppt, wpe, S.km, g, P.shmem_final, F, st, lists));
     HIPCHK(ctx, hipEventRecord(S.ev[2], st));
     HIPCHK(ctx, hipEventSynchronize(S.ev[2]));
     HIPCHK(ctx, hipEventElapsedTime(&ms, S.ev[1], S.ev[2]));
@@ -585,8 +623,9 @@ std::string tune_key(const sdi_ctx* ctx, const sdi_problem* pb, const std::vecto
   if (p.sampler == 1 && pb->flow)
     for (uint8_t a : pb->flow->active) h = (h ^ a) * 1099511628211ull;
   char buf[320];
-  snprintf(buf, sizeof buf, "%s|c%d|x%d|nv%d|ns%d|kf%d|sec%d|terms%zu|m%llx|R%d|w%d|t%d|p%d|s%d|d%d",
-           ctx->prop.gcnArchName, pb->complex_mode, (int)pb->is_expr(), pb->nvmax, pb->nsmax, pb->kfmax, pb->nsec,
+  snprintf(buf, sizeof buf, "%s|c%d|x%d|nv%d|ns%d|nf%d|kf%d|sec%d|terms%zu|m%llx|R%d|w%d|t%d|p%d|s%d|d%d",
+           ctx->prop.gcnArchName, pb->complex_mode, (int)pb->is_expr(), pb->nvmax, pb->nsmax, pb->nfmax, pb->kfmax,
+           pb->nsec,
            pb->is_expr() ? pb->expr_nins : pb->terms.size(), h, p.R, (int)(warm && p.warmup > 0), p.tile_log2, p.ppt,
            p.sampler, (int)uses_dd(pb, p));
   return buf;
@@ -606,18 +645,18 @@ int autotune(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   const std::string key = tune_key(ctx, pb, msec, warm);
   if (prm.tune == 1)
     for (const TuneEntry& e : ctx->tune_cache)
-      if (e.key == key && variant_known(pb, e.variant) &&
+      if (e.key == key && variant_known(pb, prm, e.variant) &&
           std::find(tiles.begin(), tiles.end(), e.tile_log2) != tiles.end() &&
           (fixed_variant < 0 || e.variant == fixed_variant)) {
         out = TuneChoice{e.tile_log2, e.variant};
         return SDI_OK;
       }
-  TuneChoice best{tiles.front(), fixed_variant >= 0 ? fixed_variant : default_variant(pb, 1)};
+  TuneChoice best{tiles.front(), fixed_variant >= 0 ? fixed_variant : default_variant(pb, prm, 1)};
   float best_ms = 1e30f;
   // Coordinate search: every variant at the largest tile size, every tile size
   // with the best variant, then every variant again at the best tile size.
   std::vector<std::pair<int, std::vector<int>>> rounds;
-  const std::vector<int> all = fixed_variant >= 0 ? std::vector<int>{fixed_variant} : tile_variants(pb);
+  const std::vector<int> all = fixed_variant >= 0 ? std::vector<int>{fixed_variant} : tile_variants(pb, prm);
   rounds.push_back({tiles.front(), all});
   for (size_t i = 1; i < tiles.size(); ++i) rounds.push_back({tiles[i], {}});
   if (tiles.size() > 1 && all.size() > 1) rounds.push_back({-1, all});
@@ -679,12 +718,12 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   }
   const std::vector<int> tiles = tile_candidates(pb, prm, msec);
   TuneChoice ch{tiles.front(), -1};
-  if (uses_dd(pb, prm) && pb->nsmax > 2)
+  if (!pb->complex_mode && !pb->is_expr() && final_family(pb, prm) == RF_DD)
     ch.variant = DD_VARIANT;
   else if (prm.ppt > 0)
-    ch.variant = default_variant(pb, prm.ppt);
+    ch.variant = default_variant(pb, prm, prm.ppt);
   else if (prm.tune == 0)
-    ch.variant = (pb->complex_mode || pb->is_expr()) ? 11 : 24;
+    ch.variant = (pb->complex_mode || pb->is_expr()) ? 11 : default_variant(pb, prm, 2);
   if (ch.variant < 0 || tiles.size() > 1) {
     const int rc = autotune(ctx, pb, msec, warm, tiles, ch.variant, dev_ws, ws_bytes, ch);
     if (rc != SDI_OK) return rc;
@@ -703,9 +742,11 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   pb->passes.push_back(S);
   hipStream_t st = ctx->stream;
   Plan& P = S->P;
-  S->ppt = ch.variant / 10;
+  S->lists = ch.variant >= CORNER_LISTS;
+  S->ppt = (ch.variant % CORNER_LISTS) / 10;
   S->wpe = ch.variant % 10;
-  S->gf = persistent_grid(ctx, pb, 0, S->ppt, S->wpe, S->km, P.shmem_final, std::max<size_t>(1, P.forder.size()));
+  S->gf = persistent_grid(ctx, pb, 0, S->ppt, S->wpe, S->km, P.shmem_final, std::max<size_t>(1, P.forder.size()),
+                          S->lists);
   // explicit (flow) points are read by the one-point-per-thread instances
   S->gx = persistent_grid(ctx, pb, 2, 1, 4, S->km, P.shmem_final, std::max<size_t>(1, P.xorder.size()));
   S->gw = P.warm ? persistent_grid(ctx, pb, 1, S->ppt, S->wpe, S->km, P.shmem_warm, P.wtiles.size()) : 1;
@@ -971,6 +1012,11 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   out->blocks = S->gf;
   out->tile_log2 = S->P.tile_log2;
   out->waves_per_simd = S->wpe;
+  out->grouped = (!pb->complex_mode && !pb->is_expr() && !S->lists &&
+                  (final_family(pb, prm) == RF_S2 || final_family(pb, prm) == RF_G3 ||
+                   final_family(pb, prm) == RF_G4))
+                     ? 1
+                     : 0;
   return o.counts[0] ? fail(ctx, SDI_ENONFINITE, "non-finite integrand values") : SDI_OK;
 }
 
@@ -1053,6 +1099,40 @@ int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, int32_t sh
   return SDI_OK;
 }
 
+int sdi_vegas_refit(sdi_ctx* ctx, int32_t n, int32_t nbins, int32_t k, const void* hist_dev, void* grid_dev,
+                    double alpha) {
+  if (!ctx || !hist_dev || !grid_dev) return fail(ctx, SDI_EINVAL, "vegas_refit: null argument");
+  if (n < 1 || n > MAXV) return fail(ctx, SDI_EINVAL, "vegas_refit: n must be 1..16");
+  if (nbins < 2 || nbins > NBMAX || (nbins & (nbins - 1))) return fail(ctx, SDI_EINVAL, "vegas_refit: nbins must be a power of 2 in 2..256");
+  if (k < 1 || k > KMAX) return fail(ctx, SDI_EINVAL, "vegas_refit: k must be 1..8");
+  if (!(std::isfinite(alpha) && alpha >= 0.0)) return fail(ctx, SDI_EINVAL, "vegas_refit: alpha must be finite and >= 0");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  // one sector record that carries the shapes; grid and histogram at offset 0
+  SecDev one{};
+  one.n = n;
+  one.nbins = nbins;
+  one.kf = k;
+  one.grid_off = 0;
+  const int64_t off0 = 0;
+  hipStream_t st = ctx->stream;
+  SecDev* d_one = nullptr;
+  int64_t* d_off = nullptr;
+  hipError_t he = hipMalloc((void**)&d_one, sizeof(SecDev));
+  if (he == hipSuccess) he = hipMalloc((void**)&d_off, sizeof(int64_t));
+  if (he == hipSuccess) he = hipMemcpyAsync(d_one, &one, sizeof(SecDev), hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(d_off, &off0, sizeof(int64_t), hipMemcpyHostToDevice, st);
+  int e = 0;
+  if (he == hipSuccess) e = launch_refit(d_one, 1, (const double*)hist_dev, d_off, (double*)grid_dev, alpha, st);
+  const hipError_t hs = hipStreamSynchronize(st);
+  if (d_one) (void)hipFree(d_one);
+  if (d_off) (void)hipFree(d_off);
+  if (he != hipSuccess) return fail(ctx, SDI_EDEVICE, std::string("vegas_refit setup: ") + hipGetErrorString(he));
+  if (e != 0) return fail(ctx, SDI_EDEVICE, std::string("vegas_refit kernel: ") + hipGetErrorString((hipError_t)e));
+  if (hs != hipSuccess) return fail(ctx, SDI_EDEVICE, std::string("vegas_refit sync: ") + hipGetErrorString(hs));
+  return SDI_OK;
+}
+
 // Autotuner cache as JSON: {"format": ..., "kernel_hash": ..., "entries":
 // [{"key": ..., "tile_log2": t, "points_per_thread": p, "waves_per_simd": w}, ...]}.
 int sdi_tune_save(sdi_ctx* ctx, const char* path) {
@@ -1062,8 +1142,11 @@ int sdi_tune_save(sdi_ctx* ctx, const char* path) {
   fprintf(f, "{\n  \"format\": \"sdint-autotune-1\",\n  \"kernel_hash\": \"%s\",\n  \"entries\": [", SDI_KERNEL_HASH);
   for (size_t i = 0; i < ctx->tune_cache.size(); ++i) {
     const TuneEntry& e = ctx->tune_cache[i];
-    fprintf(f, "%s\n    {\"key\": \"%s\", \"tile_log2\": %d, \"points_per_thread\": %d, \"waves_per_simd\": %d}",
-            i ? "," : "", e.key.c_str(), e.tile_log2, e.variant / 10, e.variant % 10);
+    fprintf(f,
+            "%s\n    {\"key\": \"%s\", \"tile_log2\": %d, \"points_per_thread\": %d, \"waves_per_simd\": %d, "
+            "\"corner_lists\": %d}",
+            i ? "," : "", e.key.c_str(), e.tile_log2, (e.variant % CORNER_LISTS) / 10, e.variant % 10,
+            e.variant >= CORNER_LISTS ? 1 : 0);
   }
   fprintf(f, "\n  ]\n}\n");
   const bool ok = !ferror(f);
@@ -1101,7 +1184,7 @@ int sdi_tune_load(sdi_ctx* ctx, const char* path) {
         efirst = false;
         if (!r.lit('{')) return fail(ctx, SDI_EINVAL, bad);
         TuneEntry e{"", -1, -1};
-        int ppt = -1, wpe = -1;
+        int ppt = -1, wpe = -1, lists = 0;
         bool ffirst = true;
         while (!r.lit('}')) {
           if (!ffirst && !r.lit(',')) return fail(ctx, SDI_EINVAL, bad);
@@ -1113,13 +1196,14 @@ int sdi_tune_load(sdi_ctx* ctx, const char* path) {
           else if (fk == "tile_log2") ok = r.num(e.tile_log2);
           else if (fk == "points_per_thread") ok = r.num(ppt);
           else if (fk == "waves_per_simd") ok = r.num(wpe);
+          else if (fk == "corner_lists") ok = r.num(lists) && (lists == 0 || lists == 1);
           else ok = false;
           if (!ok) return fail(ctx, SDI_EINVAL, bad);
         }
         if (e.key.empty() || e.tile_log2 < 6 || e.tile_log2 > 24 || !(ppt == 1 || ppt == 2 || ppt == 4) ||
             wpe < 1 || wpe > 9)
           return fail(ctx, SDI_EINVAL, bad);
-        e.variant = 10 * ppt + wpe;
+        e.variant = 10 * ppt + wpe + (lists ? CORNER_LISTS : 0);
         entries.push_back(e);
       }
     } else {

@@ -22,35 +22,74 @@ int occupancy_tiles_real_nv6_s2(int ppt, int wpe, int km, bool dd, size_t shmem)
 int occupancy_tiles_real_nv8_s2(int ppt, int wpe, int km, bool dd, size_t shmem);
 int occupancy_tiles_real_nv16_s2(int ppt, int wpe, int km, bool dd, size_t shmem);
 
-int launch_tiles_real(int nvmax, int nsmax, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
-                      hipStream_t st) {
-  const bool dd = a.mode == 0 && a.small_x > 0.0;
-  if (a.mode == 0 && nsmax <= 2) {
-    if (nvmax <= 4) return launch_tiles_real_nv4_s2(ppt, wpe, km, dd, grid, shmem, a, st);
-    if (nvmax <= 6) return launch_tiles_real_nv6_s2(ppt, wpe, km, dd, grid, shmem, a, st);
-    if (nvmax <= 8) return launch_tiles_real_nv8_s2(ppt, wpe, km, dd, grid, shmem, a, st);
-    return launch_tiles_real_nv16_s2(ppt, wpe, km, dd, grid, shmem, a, st);
-  }
-  if (dd) return launch_tiles_real_dd(km, grid, shmem, a, st);
-  if (nvmax <= 4) return launch_tiles_real_nv4(ppt, wpe, km, grid, shmem, a, st);
-  if (nvmax <= 6) return launch_tiles_real_nv6(ppt, wpe, km, grid, shmem, a, st);
-  if (nvmax <= 8) return launch_tiles_real_nv8(ppt, wpe, km, grid, shmem, a, st);
-  return launch_tiles_real_nv16(ppt, wpe, km, grid, shmem, a, st);
+int launch_tiles_real_nv4_g(int nsm, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv6_g(int nsm, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv8_g(int nsm, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv16_g(int nsm, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int occupancy_tiles_real_nv4_g(int nsm, int ppt, int wpe, int km, size_t shmem);
+int occupancy_tiles_real_nv6_g(int nsm, int ppt, int wpe, int km, size_t shmem);
+int occupancy_tiles_real_nv8_g(int nsm, int ppt, int wpe, int km, size_t shmem);
+int occupancy_tiles_real_nv16_g(int nsm, int ppt, int wpe, int km, size_t shmem);
+
+int real_family(int nsmax, int nfmax, int mode, bool dd) {
+  if (mode != 0 || nfmax > 2) return dd && mode == 0 ? RF_DD : RF_GENERIC;
+  if (nsmax <= 2) return RF_S2;
+  if (dd) return RF_DD;
+  return nsmax == 3 ? RF_G3 : RF_G4;
 }
 
-int tiles_real_occupancy(int nvmax, int nsmax, int mode, int ppt, int wpe, int km, bool dd, size_t shmem) {
-  dd = dd && mode == 0;
-  if (mode == 0 && nsmax <= 2) {
-    if (nvmax <= 4) return occupancy_tiles_real_nv4_s2(ppt, wpe, km, dd, shmem);
-    if (nvmax <= 6) return occupancy_tiles_real_nv6_s2(ppt, wpe, km, dd, shmem);
-    if (nvmax <= 8) return occupancy_tiles_real_nv8_s2(ppt, wpe, km, dd, shmem);
-    return occupancy_tiles_real_nv16_s2(ppt, wpe, km, dd, shmem);
+int launch_tiles_real(int nvmax, int nsmax, int nfmax, int ppt, int wpe, int km, int grid, size_t shmem,
+                      const TileArgs& a, hipStream_t st) {
+  const bool dd = a.mode == 0 && a.small_x > 0.0;
+  switch (real_family(nsmax, nfmax, a.mode, dd)) {
+    case RF_S2:
+      if (nvmax <= 4) return launch_tiles_real_nv4_s2(ppt, wpe, km, dd, grid, shmem, a, st);
+      if (nvmax <= 6) return launch_tiles_real_nv6_s2(ppt, wpe, km, dd, grid, shmem, a, st);
+      if (nvmax <= 8) return launch_tiles_real_nv8_s2(ppt, wpe, km, dd, grid, shmem, a, st);
+      return launch_tiles_real_nv16_s2(ppt, wpe, km, dd, grid, shmem, a, st);
+    case RF_G3:
+    case RF_G4: {
+      const int nsm = nsmax == 3 ? 3 : 4;
+      if (nvmax <= 4) return launch_tiles_real_nv4_g(nsm, ppt, wpe, km, grid, shmem, a, st);
+      if (nvmax <= 6) return launch_tiles_real_nv6_g(nsm, ppt, wpe, km, grid, shmem, a, st);
+      if (nvmax <= 8) return launch_tiles_real_nv8_g(nsm, ppt, wpe, km, grid, shmem, a, st);
+      return launch_tiles_real_nv16_g(nsm, ppt, wpe, km, grid, shmem, a, st);
+    }
+    case RF_DD:
+      return launch_tiles_real_dd(km, grid, shmem, a, st);
+    default:
+      if (nvmax <= 4) return launch_tiles_real_nv4(ppt, wpe, km, grid, shmem, a, st);
+      if (nvmax <= 6) return launch_tiles_real_nv6(ppt, wpe, km, grid, shmem, a, st);
+      if (nvmax <= 8) return launch_tiles_real_nv8(ppt, wpe, km, grid, shmem, a, st);
+      return launch_tiles_real_nv16(ppt, wpe, km, grid, shmem, a, st);
   }
-  if (dd) return occupancy_tiles_real_dd(km, shmem);
-  if (nvmax <= 4) return occupancy_tiles_real_nv4(mode, ppt, wpe, km, shmem);
-  if (nvmax <= 6) return occupancy_tiles_real_nv6(mode, ppt, wpe, km, shmem);
-  if (nvmax <= 8) return occupancy_tiles_real_nv8(mode, ppt, wpe, km, shmem);
-  return occupancy_tiles_real_nv16(mode, ppt, wpe, km, shmem);
+}
+
+int tiles_real_occupancy(int nvmax, int nsmax, int nfmax, int mode, int ppt, int wpe, int km, bool dd,
+                         size_t shmem) {
+  dd = dd && mode == 0;
+  switch (real_family(nsmax, nfmax, mode, dd)) {
+    case RF_S2:
+      if (nvmax <= 4) return occupancy_tiles_real_nv4_s2(ppt, wpe, km, dd, shmem);
+      if (nvmax <= 6) return occupancy_tiles_real_nv6_s2(ppt, wpe, km, dd, shmem);
+      if (nvmax <= 8) return occupancy_tiles_real_nv8_s2(ppt, wpe, km, dd, shmem);
+      return occupancy_tiles_real_nv16_s2(ppt, wpe, km, dd, shmem);
+    case RF_G3:
+    case RF_G4: {
+      const int nsm = nsmax == 3 ? 3 : 4;
+      if (nvmax <= 4) return occupancy_tiles_real_nv4_g(nsm, ppt, wpe, km, shmem);
+      if (nvmax <= 6) return occupancy_tiles_real_nv6_g(nsm, ppt, wpe, km, shmem);
+      if (nvmax <= 8) return occupancy_tiles_real_nv8_g(nsm, ppt, wpe, km, shmem);
+      return occupancy_tiles_real_nv16_g(nsm, ppt, wpe, km, shmem);
+    }
+    case RF_DD:
+      return occupancy_tiles_real_dd(km, shmem);
+    default:
+      if (nvmax <= 4) return occupancy_tiles_real_nv4(mode, ppt, wpe, km, shmem);
+      if (nvmax <= 6) return occupancy_tiles_real_nv6(mode, ppt, wpe, km, shmem);
+      if (nvmax <= 8) return occupancy_tiles_real_nv8(mode, ppt, wpe, km, shmem);
+      return occupancy_tiles_real_nv16(mode, ppt, wpe, km, shmem);
+  }
 }
 
 int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st) {

@@ -74,9 +74,11 @@ __device__ __forceinline__ int find_run(const int64_t* prefix, int nruns, int64_
   return lo;
 }
 
-// Tent map u -> 2u (u < 1/2), 2(1-u) otherwise: exact in fp64.
+// Tent map u -> 2u (u < 1/2), 2(1-u) otherwise: exact in fp64.  Written as
+// 2 min(u, 1-u): for u < 1/2 the rounded 1-u is still >= 1/2 > u, for u >= 1/2
+// 1-u is exact (Sterbenz) and <= u, so both forms give the same bits.
 __device__ __forceinline__ double tent(double u) {
-  return u < 0.5 ? 2.0 * u : 2.0 * (1.0 - u);
+  return 2.0 * fmin(u, 1.0 - u);
 }
 
 // Vegas map of one coordinate, no contraction so that the host reference
@@ -191,6 +193,144 @@ __device__ __forceinline__ void poly_real(CTerm* t, uint32_t cnt,
   for (; i < cnt; ++i) add_term<NV, PPT>(t[i].coef, t[i].exps, x, out);
 }
 
+// out += coef prod_{j<NK} x_j^e_j: add_term for terms whose exponents vanish
+// beyond the first NK variables (the sector's own variable count), so that a
+// sector of n variables in a wider register class tests only its n variables.
+template <int NK, int NV, int PPT>
+__device__ __forceinline__ void add_term_k(double c, uint64_t e, const double (&x)[PPT][NV],
+                                           double (&out)[PPT]) {
+  static_assert(NK >= 1 && NK <= NV, "variable bound");
+  double m[PPT];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) m[p] = c;
+  const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
+#pragma unroll
+  for (int j = 0; j < NK; ++j) {
+    const uint32_t w = j < 8 ? elo : ehi;
+    const int sh = 4 * (j & 7);
+    if (w & (1u << sh)) {
+      asm volatile("" ::);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) m[p] *= x[p][j];
+    }
+    if (w & (2u << sh)) {
+      asm volatile("" ::);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) m[p] = (m[p] * x[p][j]) * x[p][j];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) out[p] += m[p];
+}
+
+// out += sum over one term list.  Terms are read four at a time, and the next
+// four are requested before the current four are evaluated, so their scalar
+// loads are in flight while the multiplies of these run.
+template <int NK, int NV, int PPT>
+__device__ __forceinline__ void poly_acc_k(CTerm* t, uint32_t cnt, const double (&x)[PPT][NV],
+                                           double (&out)[PPT]) {
+  uint32_t i = 0;
+  if (cnt >= 4) {
+    double c0 = t[0].coef, c1 = t[1].coef, c2 = t[2].coef, c3 = t[3].coef;
+    uint64_t e0 = t[0].exps, e1 = t[1].exps, e2 = t[2].exps, e3 = t[3].exps;
+    for (; i + 8 <= cnt; i += 4) {
+      const double n0 = t[i + 4].coef, n1 = t[i + 5].coef, n2 = t[i + 6].coef, n3 = t[i + 7].coef;
+      const uint64_t f0 = t[i + 4].exps, f1 = t[i + 5].exps, f2 = t[i + 6].exps, f3 = t[i + 7].exps;
+      add_term_k<NK, NV, PPT>(c0, e0, x, out);
+      add_term_k<NK, NV, PPT>(c1, e1, x, out);
+      add_term_k<NK, NV, PPT>(c2, e2, x, out);
+      add_term_k<NK, NV, PPT>(c3, e3, x, out);
+      c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+      e0 = f0; e1 = f1; e2 = f2; e3 = f3;
+    }
+    add_term_k<NK, NV, PPT>(c0, e0, x, out);
+    add_term_k<NK, NV, PPT>(c1, e1, x, out);
+    add_term_k<NK, NV, PPT>(c2, e2, x, out);
+    add_term_k<NK, NV, PPT>(c3, e3, x, out);
+    i += 4;
+  }
+  for (; i < cnt; ++i) add_term_k<NK, NV, PPT>(t[i].coef, t[i].exps, x, out);
+}
+
+// poly_acc_k with NK = the sector's variable count n (wave-uniform), for n in
+// K .. NV; smaller n takes NK = K.
+template <int K, int NV, int PPT>
+__device__ __forceinline__ void poly_acc_n(CTerm* t, uint32_t cnt, int n, const double (&x)[PPT][NV],
+                                           double (&out)[PPT]) {
+  if constexpr (K >= NV) {
+    poly_acc_k<NV, NV, PPT>(t, cnt, x, out);
+  } else {
+    if (n <= K)
+      poly_acc_k<K, NV, PPT>(t, cnt, x, out);
+    else
+      poly_acc_n<K + 1, NV, PPT>(t, cnt, n, x, out);
+  }
+}
+
+// Smallest variable count a sector of register class NV can have (the classes
+// are n <= 4, 5..6, 5..8 and 9..16), the first bound poly_acc_n distinguishes.
+template <int NV>
+constexpr int class_low() {
+  return NV <= 4 ? NV : (NV <= 8 ? 5 : 9);
+}
+
+// The regular factors at every corner, each term evaluated once: for every
+// non-empty group (m, sigma) of terms with singular support sigma, the group
+// sum q at x is added to Pc[m][W] for every corner W with W & sigma == 0 (the
+// corners where those terms survive).  Pc[m][W] = P_m(x^(W)) for W < 2^ns.
+template <int NV, int PPT, int NSM, int MF>
+__device__ __forceinline__ void corner_polys(CSec* S, CTerm* terms, const double (&x)[PPT][NV],
+                                             double (&Pc)[MF][1 << NSM][PPT]) {
+  constexpr int NC = 1 << NSM;
+  const int n = S->n;
+  const int nfac = S->nfac;
+  const int C = 1 << S->ns;
+#pragma unroll
+  for (int fm = 0; fm < MF; ++fm)
+#pragma unroll
+    for (int W = 0; W < NC; ++W)
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) Pc[fm][W][p] = 0.0;
+#pragma unroll
+  for (int fm = 0; fm < MF; ++fm) {
+    if (fm < nfac) {
+      uint32_t gm = S->grp_mask[fm];
+      while (gm) {
+        const int sg = __builtin_ctz(gm);
+        gm &= gm - 1;
+        double q[PPT];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) q[p] = 0.0;
+        poly_acc_n<class_low<NV>(), NV, PPT>(terms + S->grp_off[fm][sg], S->grp_cnt[fm][sg], n, x, q);
+#pragma unroll
+        for (int W = 0; W < NC; ++W) {
+          if (W < C && (W & sg) == 0) {
+            asm volatile("" ::);
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) Pc[fm][W][p] += q[p];
+          }
+        }
+      }
+    }
+  }
+}
+
+// P[m] = Pc[m][W] for a wave-uniform corner W (one scalar branch per case).
+template <int NSM, int MF, int PPT>
+__device__ __forceinline__ void select_corner(const double (&Pc)[MF][1 << NSM][PPT], int W,
+                                              double (&P)[MF][PPT]) {
+#pragma unroll
+  for (int k = 0; k < (1 << NSM); ++k) {
+    if (W == k) {
+      asm volatile("" ::);
+#pragma unroll
+      for (int fm = 0; fm < MF; ++fm)
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) P[fm][p] = Pc[fm][k][p];
+    }
+  }
+}
+
 // 1/v for positive normal v: the hardware reciprocal estimate refined by two
 // Newton-Raphson steps r <- r + r (1 - v r), each of which squares the relative
 // error; within an ulp or two of the correctly rounded quotient, in half the
@@ -278,6 +418,68 @@ __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
   }
 }
 
+// G0 and Lambda at one corner from the factor values P[m] there (as
+// corner_regular, without evaluating the polynomials).
+template <int PPT, int MF>
+__device__ __forceinline__ void corner_from_polys(CSec* S, const double (&P)[MF][PPT], double (&g0)[PPT],
+                                                  double (&lam)[PPT]) {
+  const int nfac = S->nfac;
+  const int flags = S->flags;
+  if (flags & F_INT_POW) {
+    double num[PPT], den[PPT], mnum[PPT], mden[PPT];
+    int esum[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      num[p] = 1.0; den[p] = 1.0; mnum[p] = 1.0; mden[p] = 1.0; esum[p] = 0;
+    }
+#pragma unroll
+    for (int fm = 0; fm < MF; ++fm) {
+      if (fm < nfac) {
+        const int g = S->gam_int[fm];
+        const int d = S->del_int[fm];
+        const int ga = g < 0 ? -g : g;
+        const int da = d < 0 ? -d : d;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          int e;
+          const double mt = mant_exp(P[fm][p], e);
+          double pg = 1.0, md = 1.0;
+          for (int k = 0; k < ga; ++k) pg *= P[fm][p];
+          for (int k = 0; k < da; ++k) md *= mt;
+          if (g >= 0) num[p] *= pg; else den[p] *= pg;
+          if (d >= 0) mnum[p] *= md; else mden[p] *= md;
+          esum[p] += d * e;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      const double inv = fast_rcp(den[p] * mden[p]);
+      g0[p] = num[p] * mden[p] * inv;
+      lam[p] = log(mnum[p] * den[p] * inv) + (double)esum[p] * 0.69314718055994530942;
+    }
+  } else {
+    double lg[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) { lg[p] = 0.0; lam[p] = 0.0; }
+#pragma unroll
+    for (int fm = 0; fm < MF; ++fm) {
+      if (fm < nfac) {
+        const double gm = S->gam[fm];
+        const double dm = S->del[fm];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          const double l = log(P[fm][p]);
+          lg[p] += gm * l;
+          lam[p] += dm * l;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) g0[p] = exp(lg[p]);
+  }
+}
+
 // Adds t_q = base z^q / q! to f[OFF + q] for the orders the sector keeps
 // (and |t_q| to c when COND: the conditioning sums of the evaluate hook).
 template <int OFF, int KM, bool COND>
@@ -299,7 +501,10 @@ __device__ __forceinline__ void add_series(double (&f)[KM], double (&c)[KM], dou
 // COND: also the sums of |term| per order (cnd), for the evaluate hook.
 // NSM: bound on the sector's singular variables (the per-point log x_j and
 // 1/x_j arrays are sized by it, which matters for the register budget).
-template <int NV, int PPT, int KM, bool COND, int NSM = MAXS>
+// MF: 0 evaluates each corner's own term lists (any number of factors);
+// MF > 0 (sectors of at most MF factors) evaluates every term once by singular
+// support (corner_polys) and picks the corner's values from those sums.
+template <int NV, int PPT, int KM, bool COND, int NSM = MAXS, int MF = 0>
 __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const double (&x)[PPT][NV],
                                               double (&f)[PPT][KM], double (&cnd)[PPT][KM]) {
   static_assert(NSM >= 1 && NSM <= MAXS, "singular-variable bound");
@@ -381,10 +586,19 @@ __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const doubl
       if constexpr (COND) cnd[p][k] = 0.0;
     }
 
+  constexpr int MFC = MF > 0 ? MF : 1;
+  double Pc[MFC][1 << NSM][PPT];
+  if constexpr (MF > 0) corner_polys<NV, PPT, NSM, MF>(S, terms, x, Pc);
   const int C = 1 << ns;
   for (int W = 0; W < C; ++W) {
     double g0[PPT], lam[PPT];
-    corner_regular<NV, PPT>(S, terms, W, x, g0, lam);
+    if constexpr (MF > 0) {
+      double P[MF][PPT];
+      select_corner<NSM, MF, PPT>(Pc, W, P);
+      corner_from_polys<PPT, MF>(S, P, g0, lam);
+    } else {
+      corner_regular<NV, PPT>(S, terms, W, x, g0, lam);
+    }
     for (int T = W;; T = (T - 1) & W) {
       const int nt = __builtin_popcount(T);
       const int off = ns - nt;
@@ -421,11 +635,11 @@ __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const doubl
     }
 }
 
-template <int NV, int PPT, int KM, int NSM = MAXS>
+template <int NV, int PPT, int KM, int NSM = MAXS, int MF = 0>
 __device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms, const double (&x)[PPT][NV],
                                             double (&f)[PPT][KM]) {
   double unused[PPT][KM];
-  eval_f_real_c<NV, PPT, KM, false, NSM>(S, terms, x, f, unused);
+  eval_f_real_c<NV, PPT, KM, false, NSM, MF>(S, terms, x, f, unused);
 }
 
 }  // namespace sdi

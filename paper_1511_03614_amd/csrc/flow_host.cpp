@@ -201,6 +201,45 @@ int sdi_flow_set_params(sdi_ctx* ctx, sdi_problem* pb, int32_t s, const float* i
   return SDI_OK;
 }
 
+int sdi_flow_weights(sdi_ctx* ctx, int64_t npts, int32_t K, const void* f_dev, const void* lq_dev,
+                     const double* order_weights, void* c_dev) {
+  if (!ctx || (npts > 0 && (!f_dev || !lq_dev || !c_dev))) return fail(ctx, SDI_EINVAL, "flow_weights: null argument");
+  if (npts < 0 || npts > (int64_t)0xFFFFFFFFu) return fail(ctx, SDI_EINVAL, "flow_weights: npts must be 0..2^32-1");
+  if (K < 1 || K > KMAX) return fail(ctx, SDI_EINVAL, "flow_weights: K must be 1..8");
+  std::vector<double> ow(K, 1.0);
+  if (order_weights) {
+    bool any = false;
+    for (int k = 0; k < K; ++k) {
+      if (!(std::isfinite(order_weights[k]) && order_weights[k] >= 0.0))
+        return fail(ctx, SDI_EINVAL, "flow_weights: order weights must be finite and >= 0");
+      ow[k] = order_weights[k];
+      any = any || ow[k] > 0.0;
+    }
+    if (!any) return fail(ctx, SDI_EINVAL, "flow_weights: order weights are all zero");
+  }
+  if (npts == 0) return SDI_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  FlowTile t{0, 0, 0, (uint32_t)npts, 0, 0};
+  hipStream_t st = ctx->stream;
+  FlowTile* d_t = nullptr;
+  double* d_ow = nullptr;
+  hipError_t he = hipMalloc((void**)&d_t, sizeof(FlowTile));
+  if (he == hipSuccess) he = hipMalloc((void**)&d_ow, K * sizeof(double));
+  if (he == hipSuccess) he = hipMemcpyAsync(d_t, &t, sizeof(FlowTile), hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(d_ow, ow.data(), K * sizeof(double), hipMemcpyHostToDevice, st);
+  int e = 0;
+  if (he == hipSuccess)
+    e = launch_flow_weights(d_t, 1, K, (const double*)f_dev, (const double*)lq_dev, d_ow, (double*)c_dev, st);
+  const hipError_t hs = hipStreamSynchronize(st);
+  if (d_t) (void)hipFree(d_t);
+  if (d_ow) (void)hipFree(d_ow);
+  if (he != hipSuccess) return fail(ctx, SDI_EDEVICE, std::string("flow_weights setup: ") + hipGetErrorString(he));
+  if (e != 0) return fail(ctx, SDI_EDEVICE, std::string("flow_weights kernel: ") + hipGetErrorString((hipError_t)e));
+  if (hs != hipSuccess) return fail(ctx, SDI_EDEVICE, std::string("flow_weights sync: ") + hipGetErrorString(hs));
+  return SDI_OK;
+}
+
 int sdi_flow_set_active(sdi_ctx* ctx, sdi_problem* pb, int32_t s, int32_t active) {
   if (!ctx || !pb) return fail(ctx, SDI_EINVAL, "flow_set_active: null argument");
   int rc = flow_ready(ctx, pb);

@@ -134,6 +134,7 @@ struct sdi_problem {
   sdi_ctx* ctx = nullptr;
   int nsec = 0, K = 0, order_min = 0, kfmax = 0, nvmax = 4, complex_mode = 0;
   int nsmax = 0;                      // most singular variables of any sector
+  int nfmax = 0;                      // most regular factors of any sector
   double lambda = 0.0;
   std::vector<sdi::SecDev> secs;      // host copy (updated per integrate)
   std::vector<sdi::Term> terms;

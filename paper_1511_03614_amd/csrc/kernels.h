@@ -37,21 +37,30 @@ int tiles_expr_occupancy(int mode, size_t shmem, const ExprArgs& x);
 int launch_eval_points_expr(const EvalArgs& a, const ExprArgs& x, hipStream_t st);
 
 // Tile kernel of variable class nvmax (4, 6, 8 or 16), points per thread ppt and
-// minimum waves per SIMD wpe (final-pass variants (1,4), (2,3), (2,4), (4,2); the
-// last not for class 16), order capacity km (4 or 8), in the pass mode a.mode
-// (0 final, 1 warm-up with at most 2 points per thread, 2 explicit points with
-// 1; modes 1 and 2 run at 4 waves).  nsmax bounds the singular variables of
-// every sector: final passes with nsmax <= 2 run instances with smaller
-// per-point arrays.  grid = number of persistent blocks.  A final pass with
-// a.small_x > 0 (endpoint precision) runs the copies that evaluate points
-// below a.small_x again in double-double: the nsmax <= 2 variants, else the
-// one instance of launch_tiles_real_dd (ppt and wpe ignored).
-int launch_tiles_real(int nvmax, int nsmax, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
-                      hipStream_t st);
+// minimum waves per SIMD wpe, order capacity km (4 or 8), in the pass mode
+// a.mode (0 final, 1 warm-up with at most 2 points per thread, 2 explicit
+// points with 1; modes 1 and 2 run at 4 waves).  nsmax bounds the singular
+// variables and nfmax the regular factors of every sector.  Families of
+// instances (real_family): final passes of problems with at most two factors
+// evaluate each term once by singular support, in instances sized by nsmax
+// (RF_S2: nsmax <= 2, variants (1,4), (2,3), (2,4), (4,2), the last not for
+// class 16, with endpoint-precision copies; RF_G3 / RF_G4: nsmax 3 / 4,
+// variants (1,2), (1,4), (2,2), (2,3) / (1,2), (1,3), (2,1), (2,2)); other
+// problems, warm-up and explicit points run the generic instances that
+// evaluate each corner's term lists (RF_GENERIC, final-pass variants as RF_S2);
+// endpoint precision outside RF_S2 runs the one instance of
+// launch_tiles_real_dd (RF_DD; ppt and wpe ignored).  A final pass with
+// a.small_x > 0 evaluates points below a.small_x again in double-double.
+// grid = number of persistent blocks.
+enum { RF_GENERIC = 0, RF_S2 = 1, RF_G3 = 2, RF_G4 = 3, RF_DD = 4 };
+int real_family(int nsmax, int nfmax, int mode, bool dd);
+int launch_tiles_real(int nvmax, int nsmax, int nfmax, int ppt, int wpe, int km, int grid, size_t shmem,
+                      const TileArgs& a, hipStream_t st);
 int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st);
 // Occupancy (resident blocks per CU) of a tile kernel instance (dd: the
 // endpoint-precision one of a final pass); 0 if not built.
-int tiles_real_occupancy(int nvmax, int nsmax, int mode, int ppt, int wpe, int km, bool dd, size_t shmem);
+int tiles_real_occupancy(int nvmax, int nsmax, int nfmax, int mode, int ppt, int wpe, int km, bool dd,
+                         size_t shmem);
 // Final pass (a.mode 0) of the endpoint-precision mode: every variable class,
 // one point per thread, points with a singular coordinate below a.small_x
 // evaluated in double-double.  km 4 or 8.

@@ -52,6 +52,14 @@ struct alignas(16) SecDev {
   int32_t b_int[MAXV];              // integer b_j (F_INT_MONO)
   uint32_t tab_off[MAXF][MAXC];     // term list offset per (factor, corner)
   uint32_t tab_cnt[MAXF][MAXC];
+  // The same terms grouped by their singular support: group (m, sigma) holds
+  // the terms of factor m whose exponents are nonzero exactly on the singular
+  // variables of mask sigma.  A term of group sigma is alive at corner W iff
+  // W & sigma == 0, so P_m(x^(W)) = sum over sigma with W & sigma == 0 of the
+  // group sums at x: each term is evaluated once for all corners.
+  uint32_t grp_off[MAXF][MAXC];
+  uint32_t grp_cnt[MAXF][MAXC];
+  uint32_t grp_mask[MAXF];          // bit sigma set iff group (m, sigma) is not empty
   int32_t gam_int[MAXF], del_int[MAXF];
   double gam[MAXF], del[MAXF];
   double a[MAXV], b[MAXV];

@@ -12,9 +12,9 @@ int launch_tiles_real_nv8_s2(int ppt, int wpe, int km, bool dd, int grid, size_t
 #define SDI_L(P, W, K)                                                                       \
   if (ppt == P && wpe == W && km == K) {                                                     \
     if (dd)                                                                                  \
-      k_tiles_real<8, P, K, 0, W, 2, true><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a);     \
+      k_tiles_real<8, P, K, 0, W, 2, true, 2><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a);     \
     else                                                                                     \
-      k_tiles_real<8, P, K, 0, W, 2><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a);           \
+      k_tiles_real<8, P, K, 0, W, 2, false, 2><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a);           \
     return (int)hipGetLastError();                                                            \
   }
   SDI_L(1, 4, 4) SDI_L(2, 3, 4) SDI_L(2, 4, 4) SDI_L(4, 2, 4) SDI_L(1, 4, 8) SDI_L(2, 3, 8) SDI_L(2, 4, 8) SDI_L(4, 2, 8)
@@ -27,9 +27,9 @@ int occupancy_tiles_real_nv8_s2(int ppt, int wpe, int km, bool dd, size_t shmem)
 #define SDI_O(P, W, K)                                                                                     \
   if (ppt == P && wpe == W && km == K) {                                                                   \
     const hipError_t e = dd ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-                                  &nb, k_tiles_real<8, P, K, 0, W, 2, true>, BLOCK, shmem)               \
+                                  &nb, k_tiles_real<8, P, K, 0, W, 2, true, 2>, BLOCK, shmem)               \
                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-                                  &nb, k_tiles_real<8, P, K, 0, W, 2>, BLOCK, shmem);                    \
+                                  &nb, k_tiles_real<8, P, K, 0, W, 2, false, 2>, BLOCK, shmem);                    \
     return e == hipSuccess ? nb : 0;                                                                       \
   }
   SDI_O(1, 4, 4) SDI_O(2, 3, 4) SDI_O(2, 4, 4) SDI_O(4, 2, 4) SDI_O(1, 4, 8) SDI_O(2, 3, 8) SDI_O(2, 4, 8) SDI_O(4, 2, 8)

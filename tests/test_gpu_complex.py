@@ -20,7 +20,7 @@ from sectorgen import Factor, Sector  # noqa: E402
 from sectorgen.feynman import double_box_problem, massive_bubble_problem, box_problem  # noqa: E402
 from oracle import integrand, integrate, points  # noqa: E402
 
-from test_gpu_parity import assert_close_shift, set_params  # noqa: E402
+from test_gpu_parity import assert_close_shift, log, set_params  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -215,3 +215,30 @@ def oracle_shift_values_c_sector(one, sec, s, m, R, seed):
             q[r, k] = integrate.fsum_c(wf[k]) / N
             scale[k] = max(scale[k], float(np.mean(np.abs(wf[k]))))
     return q, scale, npos
+
+
+def test_physical_double_box_lambda_invariance(ctx):
+    """Cauchy's theorem on the physical double box (s = 5, t = -2, all internal
+    masses 1): the eps^0 coefficient with the tuned deformation and with the
+    conservative (halved) one agree within 5 combined standard errors, real and
+    imaginary parts; the conservative deformation leaves no point with
+    Im F(z) > 0 in the pass."""
+    from sectorgen.feynman import double_box_problem
+    prob = double_box_problem(5.0, -2.0, 1.0, order_max=0, complex_mode=True, lam=0.5)
+    set_params(ctx, lattice_log2=14, shifts=16, seed=5, tile_log2=0)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        P.sdi_tune_deformation(ctx, h, 0.5, 4, 10)
+        a = P.sdi_integrate(ctx, h)
+        P.sdi_tune_deformation(ctx, h, 0.5, 4, 10, conservative=True)
+        b = P.sdi_integrate(ctx, h)
+        log(f"physical double box eps^0: tuned {a['value'][-1]:.6f} +- {a['err_re'][-1]:.1e}/{a['err_im'][-1]:.1e} "
+            f"({a['n_imf_positive']} points Im F > 0), conservative {b['value'][-1]:.6f} "
+            f"+- {b['err_re'][-1]:.1e}/{b['err_im'][-1]:.1e} ({b['n_imf_positive']})")
+        assert b["n_imf_positive"] == 0
+        for part, ea, eb in ((np.real, a["err_re"], b["err_re"]), (np.imag, a["err_im"], b["err_im"])):
+            d = abs(part(a["value"][-1]) - part(b["value"][-1]))
+            assert d <= 5 * np.hypot(ea[-1], eb[-1]), (d, ea[-1], eb[-1])
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)

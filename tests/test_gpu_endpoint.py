@@ -202,3 +202,36 @@ def test_two_singular_variables_keep_the_tuned_variants(ctx):
         P.sdi_set_param(ctx, "small_x", 0)
         P.sdi_problem_destroy(h)
         set_params(ctx)
+
+
+@pytest.mark.parametrize("ppt", [2, 4])
+def test_queue_carries_points_across_rounds(ctx, ppt):
+    """With 2 or 4 points per thread and a threshold that flags a large share
+    of the points, a wave queues more than 64 flagged points in one round: 64
+    are evaluated in double-double and the rest carried to the next flush.  A
+    point dropped or counted twice would move a shift mean by about |w F| / N;
+    every shift mean must stay within the fp64 rounding bound of the oracle's,
+    and the evaluation count is unchanged."""
+    import sectorgen
+    from test_gpu_limits import oracle_shift_values_cond
+    full = sectorgen.config2()
+    prob = sectorgen.Problem(sectors=full.sectors[:6], order_min=full.order_min, order_max=full.order_max,
+                             pref_lead=full.pref_lead, pref=full.pref)
+    m, R, seed = 10, 2, 9
+    set_params(ctx, lattice_log2=m, shifts=R, seed=seed, tile_log2=10, ppt=ppt)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        base = P.sdi_integrate(ctx, h)
+        P.sdi_set_param(ctx, "small_x", 0.3)
+        res = P.sdi_integrate(ctx, h)
+        assert res["ppt"] == ppt and res["n_evals"] == base["n_evals"]
+        for s in range(len(prob.sectors)):
+            per = P.sdi_sector_results(ctx, h, s, R)[2]
+            q, scale, bound = oracle_shift_values_cond(prob, s, m, R, seed)
+            tol = np.maximum(REL_INT * np.maximum(np.abs(q), scale[None, :]), bound)
+            d = np.abs(per - q)
+            assert (d <= tol).all(), f"sector {s}: max d/tol {np.max(d / tol)}"
+    finally:
+        P.sdi_set_param(ctx, "small_x", 0)
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
