@@ -273,6 +273,22 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, const void* x
 int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, int32_t shift,
                       int64_t i0, int64_t npts, void* x_dev, void* w_dev);
 
+/* sdi_sample_points for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same points and weights, bit for bit, with no hipMalloc, hipFree or other
+ * allocating call.  The sector record, generating vector and shift row the
+ * kernels read are staged in a fixed array of 8 KiB of device memory that the
+ * library holds on every device it runs on until the process ends (its
+ * address is taken once per device when the first context is created there);
+ * a call needs about 3.2 KB of it whatever npts is, and returns SDI_ENOMEM if
+ * the record ever outgrew the array.  The caller still provides x and w.  Every
+ * call on one device shares that array and overwrites it (nothing in it has
+ * to start at zero): calls that overlap on one device, from several threads or
+ * contexts, race; calls on one context are ordered, since each synchronises
+ * its stream before returning.  Arguments and errors as sdi_sample_points. */
+int sdi_sample_points_noalloc(sdi_ctx* ctx, const sdi_problem* prob, int32_t s, int32_t shift,
+                              int64_t i0, int64_t npts, void* x_dev, void* w_dev);
+
 /* One refit of a Vegas grid on caller data, the step sdi_integrate's warm-up
  * takes after every iteration (Lepage's VEGAS refinement behind the Vegas
  * integrator of section 4.4; parity hook): for each dimension j < n,

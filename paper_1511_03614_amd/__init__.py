@@ -26,6 +26,7 @@ __all__ = [
     "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
     "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_flow_set_active", "sdi_flow_validate",
     "sdi_tune_deformation", "sdi_problem_nvars", "sdi_vegas_refit", "sdi_flow_weights",
+    "sdi_sample_points_noalloc",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -114,6 +115,7 @@ def load_library():
         "sdi_problem_norders": (C.c_int, [vp]),
         "sdi_problem_nsectors": (C.c_int, [vp]),
         "sdi_problem_nvars": (C.c_int, [vp, i32]),
+        "sdi_sample_points_noalloc": (C.c_int, [vp, vp, i32, i32, i64, i64, vp, vp]),
         "sdi_vegas_refit": (C.c_int, [vp, i32, i32, i32, vp, vp, C.c_double]),
         "sdi_flow_weights": (C.c_int, [vp, i64, i32, vp, vp, dp, vp]),
         "sdi_workspace_bytes": (C.c_size_t, [vp, vp]),
@@ -415,6 +417,20 @@ def sdi_flow_weights(ctx, f, lq, order_weights=None):
     _check(load_library().sdi_flow_weights(ctx, npts, K, C.c_void_p(f.data_ptr()), C.c_void_p(lq.data_ptr()),
                                            _dptr(w) if w is not None else None, C.c_void_p(c.data_ptr())), ctx)
     return c
+
+
+def sdi_sample_points_noalloc(ctx, prob, s: int, shift: int, i0: int, x, w=None):
+    """sdi_sample_points into caller tensors x (npts, n) and w (npts,) (float64 on the
+    context's device), through the entry point that allocates no device memory."""
+    import torch
+    n = sdi_problem_nvars(prob, s)
+    x = _device_tensor(ctx, x, "x", (None, n))
+    if w is not None:
+        w = _device_tensor(ctx, w, "w", (x.shape[0],))
+    torch.cuda.current_stream(x.device).synchronize()
+    _check(load_library().sdi_sample_points_noalloc(ctx, prob, s, shift, i0, x.shape[0], C.c_void_p(x.data_ptr()),
+                                                    C.c_void_p(w.data_ptr()) if w is not None else None), ctx)
+    return x, w
 
 
 # ---------------------------------------------------------------- deformation size

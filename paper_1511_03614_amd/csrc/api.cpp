@@ -1,6 +1,8 @@
 // libsdint C ABI: context, parameters, problem compilation and the integration driver.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <cerrno>
 #include <cmath>
@@ -52,6 +54,21 @@ int sdi_ctx_create(int device_ordinal, void* hip_stream, sdi_ctx** out) {
     return SDI_EDEVICE;
   }
   c->ncu = c->prop.multiProcessorCount;
+  // the fixed scratch of the allocation-free entry point: its address on this
+  // device, taken once per device with the device current
+  {
+    static std::mutex mu;
+    static std::vector<void*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)addr.size() < ndev) addr.resize(ndev, nullptr);
+    if (!addr[device_ordinal] && noalloc_scratch_address(&addr[device_ordinal]) != 0) {
+      addr[device_ordinal] = nullptr;
+      (void)hipGetLastError();
+      delete c;
+      return SDI_EDEVICE;
+    }
+    c->scratch = addr[device_ordinal];
+  }
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {

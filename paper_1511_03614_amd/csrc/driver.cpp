@@ -1043,52 +1043,83 @@ int sdi_sector_results(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, double* m
   return SDI_OK;
 }
 
-int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, int32_t shift, int64_t i0, int64_t npts,
-                      void* x_dev, void* w_dev) {
+}  // extern "C"
+
+namespace {
+
+// Arguments of sdi_sample_points and sdi_sample_points_noalloc; on success the
+// sector's record under the current parameters (own device copy) and the
+// generating vector are filled in, and *grid is the sector's grid or NULL.
+int sample_setup(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, int32_t shift, int64_t i0, int64_t npts,
+                 const void* x_dev, SecDev& one, std::vector<uint64_t>& zp, const double** grid) {
   if (!ctx || !pb || (!x_dev && npts > 0)) return fail(ctx, SDI_EINVAL, "sample_points: null argument");
   if (s < 0 || s >= pb->nsec) return fail(ctx, SDI_EINVAL, "sector index out of range");
   const Params& prm = ctx->params;
   if (shift < 0 || shift >= prm.R) return fail(ctx, SDI_EINVAL, "shift index out of range");
   if (npts < 0 || i0 < 0 || i0 + npts > ((int64_t)1 << prm.m)) return fail(ctx, SDI_EINVAL, "point range outside the lattice");
-  if (npts == 0) return SDI_OK;
-  HIPCHK(ctx, hipSetDevice(ctx->device));
-  (void)hipGetLastError();
-  // this sector's record under the current parameters, on its own device copy
   const int rows = prm.R + prm.warmup;
   std::vector<SecDev> secs;
   size_t goff = 0;
   sector_fields(prm, pb, std::vector<int>(pb->nsec, prm.m), rows, secs, goff);
   const bool use_grid = pb->grid_valid && prm.warmup > 0 && pb->d_grids && pb->grid_nbins == prm.nbins &&
                         pb->grid_doubles >= goff;
-  SecDev one = secs[s];
+  one = secs[s];
   if (!use_grid) one.flags &= ~F_USE_GRID;
   one.shift_row = 0;
-  std::vector<uint64_t> zp(MAXV);
+  zp.assign(MAXV, 0);
   const std::vector<uint32_t>& z = lattice_vector16(prm.m);
   for (int j = 0; j < MAXV; ++j) zp[j] = (uint64_t)z[j] << (53 - prm.m);
+  *grid = use_grid ? pb->d_grids + secs[s].grid_off : nullptr;
+  return SDI_OK;
+}
+
+// Enqueues the shift row and the sampling kernel on device copies already
+// holding the record (d_one) and generating vector (d_zp); d_row receives row
+// `shift` (computed alone: the Philox counter carries the row index).
+int sample_launch(sdi_ctx* ctx, SecDev* d_one, uint64_t* d_zp, uint64_t* d_row, const double* grid, int32_t shift,
+                  int64_t i0, int64_t npts, void* x_dev, void* w_dev) {
   hipStream_t st = ctx->stream;
-  SecDev* d_one = nullptr;
-  uint64_t* d_sh = nullptr;
-  uint64_t* d_zp = nullptr;
-  hipError_t he = hipMalloc((void**)&d_one, sizeof(SecDev));
-  if (he == hipSuccess) he = hipMalloc((void**)&d_sh, (size_t)(shift + 1) * MAXV * 8);
-  if (he == hipSuccess) he = hipMalloc((void**)&d_zp, MAXV * 8);
-  int e = 0;
-  if (he == hipSuccess) he = hipMemcpyAsync(d_one, &one, sizeof(SecDev), hipMemcpyHostToDevice, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(d_zp, zp.data(), MAXV * 8, hipMemcpyHostToDevice, st);
-  if (he == hipSuccess) e = launch_shifts(d_one, 1, shift + 1, shift + 1, prm.seed, 0u, d_sh, st);
-  if (he == hipSuccess && e == 0) {
+  int e = launch_shifts(d_one, 1, 1, 1, ctx->params.seed, (uint32_t)shift, d_row, st);
+  if (e == 0) {
     SampleArgs A{};
     A.sec = d_one;
     A.zp = d_zp;
-    A.shift = d_sh + (size_t)shift * MAXV;
-    A.grid = use_grid ? pb->d_grids + secs[s].grid_off : nullptr;
+    A.shift = d_row;
+    A.grid = grid;
     A.x = (double*)x_dev;
     A.w = (double*)w_dev;
     A.i0 = (uint64_t)i0;
     A.npts = npts;
     e = launch_sample_points(A, st);
   }
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, int32_t shift, int64_t i0, int64_t npts,
+                      void* x_dev, void* w_dev) {
+  SecDev one{};
+  std::vector<uint64_t> zp;
+  const double* grid = nullptr;
+  int rc = sample_setup(ctx, pb, s, shift, i0, npts, x_dev, one, zp, &grid);
+  if (rc != SDI_OK) return rc;
+  if (npts == 0) return SDI_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  hipStream_t st = ctx->stream;
+  SecDev* d_one = nullptr;
+  uint64_t* d_sh = nullptr;
+  uint64_t* d_zp = nullptr;
+  hipError_t he = hipMalloc((void**)&d_one, sizeof(SecDev));
+  if (he == hipSuccess) he = hipMalloc((void**)&d_sh, MAXV * 8);
+  if (he == hipSuccess) he = hipMalloc((void**)&d_zp, MAXV * 8);
+  int e = 0;
+  if (he == hipSuccess) he = hipMemcpyAsync(d_one, &one, sizeof(SecDev), hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(d_zp, zp.data(), MAXV * 8, hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) e = sample_launch(ctx, d_one, d_zp, d_sh, grid, shift, i0, npts, x_dev, w_dev);
   const hipError_t hs = hipStreamSynchronize(st);
   if (d_one) (void)hipFree(d_one);
   if (d_sh) (void)hipFree(d_sh);
@@ -1096,6 +1127,37 @@ int sdi_sample_points(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, int32_t sh
   if (he != hipSuccess) return fail(ctx, SDI_EDEVICE, std::string("sample setup: ") + hipGetErrorString(he));
   if (e != 0) return fail(ctx, SDI_EDEVICE, std::string("sample kernel: ") + hipGetErrorString((hipError_t)e));
   if (hs != hipSuccess) return fail(ctx, SDI_EDEVICE, std::string("sample sync: ") + hipGetErrorString(hs));
+  return SDI_OK;
+}
+
+int sdi_sample_points_noalloc(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, int32_t shift, int64_t i0,
+                              int64_t npts, void* x_dev, void* w_dev) {
+  SecDev one{};
+  std::vector<uint64_t> zp;
+  const double* grid = nullptr;
+  int rc = sample_setup(ctx, pb, s, shift, i0, npts, x_dev, one, zp, &grid);
+  if (rc != SDI_OK) return rc;
+  // layout in this device's fixed scratch: record, generating vector, shift row
+  constexpr size_t off_zp = (sizeof(SecDev) + 255) / 256 * 256;
+  constexpr size_t off_row = off_zp + 256;
+  constexpr size_t need = off_row + MAXV * 8;
+  static_assert(need <= NOALLOC_SCRATCH_BYTES, "scratch too small for one sector record");
+  if (!ctx->scratch) return fail(ctx, SDI_ESTATE, "sample_points_noalloc: no scratch address on this context");
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, SDI_ENOMEM, "sample_points_noalloc: needs " + std::to_string(need) + " bytes of the " +
+                                     std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte scratch");
+  if (npts == 0) return SDI_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();
+  hipStream_t st = ctx->stream;
+  unsigned char* base = (unsigned char*)ctx->scratch;
+  SecDev* d_one = (SecDev*)base;
+  uint64_t* d_zp = (uint64_t*)(base + off_zp);
+  uint64_t* d_row = (uint64_t*)(base + off_row);
+  HIPCHK(ctx, hipMemcpyAsync(d_one, &one, sizeof(SecDev), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_zp, zp.data(), MAXV * 8, hipMemcpyHostToDevice, st));
+  KCHK(ctx, sample_launch(ctx, d_one, d_zp, d_row, grid, shift, i0, npts, x_dev, w_dev));
+  HIPCHK(ctx, hipStreamSynchronize(st));
   return SDI_OK;
 }
 

@@ -128,6 +128,7 @@ struct sdi_ctx {
   hipDeviceProp_t prop{};
   int ncu = 0;
   std::vector<sdi::TuneEntry> tune_cache;
+  void* scratch = nullptr;   // this device's fixed scratch array (allocation-free entry point)
 };
 
 struct sdi_problem {

@@ -28,6 +28,12 @@ int launch_refit(const SecDev* secs, int nsec, const double* hsec, const int64_t
                  double alpha, hipStream_t st);
 int launch_sample_points(const SampleArgs& a, hipStream_t st);
 
+// Bytes of the per-device fixed scratch array of the allocation-free entry
+// point, and its device address on the current device (hipGetSymbolAddress;
+// call with the device current, once per device).
+constexpr size_t NOALLOC_SCRATCH_BYTES = 8192;
+int noalloc_scratch_address(void** out);
+
 // Integrands given as text: the persistent tile kernel (a.mode 0 final pass, 1
 // warm-up with histograms; blocks of one wave; shmem = grid and histogram
 // bytes, the expression slots are added) and the point evaluator.

@@ -331,6 +331,14 @@ __global__ void k_sample_points(SampleArgs A) {
   if (A.w) A.w[i] = w;
 }
 
+// ------------------------------------------------------------ fixed scratch
+
+// Device memory of the allocation-free entry point (sdi_sample_points_noalloc):
+// the sector record, generating vector and shift row it hands to the sampling
+// kernels.  Each device holds its own copy for the life of the process; host
+// code reaches it only through the address hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
 // ------------------------------------------------------------ launchers
 
 #define SDI_CHECK(call)                    \
@@ -398,6 +406,14 @@ int launch_sample_points(const SampleArgs& a, hipStream_t st) {
   if (a.npts <= 0) return 0;
   k_sample_points<<<dim3((unsigned)((a.npts + 255) / 256)), dim3(256), 0, st>>>(a);
   return (int)hipGetLastError();
+}
+
+int noalloc_scratch_address(void** out) {
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return (int)e;
+  *out = p;
+  return 0;
 }
 
 }  // namespace sdi
