@@ -236,6 +236,10 @@ typedef struct {
   int32_t grouped;              /* 1: that kernel evaluated every polynomial term once
                                    per point (terms grouped by singular support),
                                    0: once per subtraction corner                      */
+  double ms_pilot_kernel;       /* device time of the pilot pass's tile kernel (budget
+                                   allocation; 0 without)                              */
+  int32_t pilot_same_kernel;    /* 1: the pilot pass ran the same kernel instance as the
+                                   final pass (budget allocation; 0 without)           */
 } sdi_result;
 
 /* Bytes of device workspace sdi_integrate needs under the current parameters. */

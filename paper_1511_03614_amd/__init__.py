@@ -69,7 +69,8 @@ class Result(C.Structure):
                 ("n_evals", C.c_int64), ("n_nonfinite", C.c_int64), ("n_imf_positive", C.c_int64),
                 ("ms_sample_eval_reduce", C.c_double), ("ms_refit", C.c_double), ("ms_total", C.c_double),
                 ("ms_eval_kernel", C.c_double), ("points_per_thread", C.c_int32), ("blocks", C.c_int32),
-                ("tile_log2", C.c_int32), ("waves_per_simd", C.c_int32), ("grouped", C.c_int32)]
+                ("tile_log2", C.c_int32), ("waves_per_simd", C.c_int32), ("grouped", C.c_int32),
+                ("ms_pilot_kernel", C.c_double), ("pilot_same_kernel", C.c_int32)]
 
 
 def library_path() -> str:
@@ -339,7 +340,7 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
     """Run the integrator; `workspace` is an optional torch uint8 cuda tensor."""
     K = sdi_problem_norders(prob)
     arrs = [np.zeros(K) for _ in range(4)]
-    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0)
+    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, 0.0, 0)
     ptr, nbytes = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()), workspace.numel())
     if workspace is not None:
         import torch
@@ -350,7 +351,8 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
             "n_imf_positive": res.n_imf_positive, "ms_final": res.ms_sample_eval_reduce,
             "ms_warmup": res.ms_refit, "ms_total": res.ms_total, "ms_eval_kernel": res.ms_eval_kernel,
             "ppt": res.points_per_thread, "blocks": res.blocks, "tile_log2": res.tile_log2,
-            "waves_per_simd": res.waves_per_simd, "grouped": res.grouped}
+            "waves_per_simd": res.waves_per_simd, "grouped": res.grouped, "ms_pilot_kernel": res.ms_pilot_kernel,
+            "pilot_same_kernel": res.pilot_same_kernel}
 
 
 def sdi_sector_results(ctx, prob, s: int, nshifts: int):

@@ -955,7 +955,8 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   if (prm.alloc_min > prm.alloc_max) return fail(ctx, SDI_EINVAL, "alloc_min_log2 > alloc_max_log2");
   const int nsec = pb->nsec;
   PassOut o;
-  float ms_pilot = 0.f;
+  float ms_pilot = 0.f, ms_pilot_kernel = 0.f;
+  std::vector<int> pilot_kernel;   // launch variant of the pilot's tile kernel
   int64_t pilot_evals = 0;
   std::vector<int> msec(nsec, prm.m);
   bool warm = prm.warmup > 0;
@@ -967,6 +968,8 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
     rc = run_pass(ctx, pb, *S, o);
     if (rc != SDI_OK) return rc;
     ms_pilot = o.ms_warm + o.ms_final;
+    ms_pilot_kernel = o.ms_kernel;
+    pilot_kernel = {S->ppt, S->wpe, S->lists ? 1 : 0, S->km};
     if (prm.warmup > 0) pb->grid_valid = true;   // the final pass reuses the adapted grids
     pilot_evals = ((int64_t)prm.R << prm.pilot_log2) * nsec;
     msec = neyman_allocation(pb, o.sec_stats, prm);
@@ -1008,6 +1011,8 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   out->ms_refit = o.ms_warm + ms_pilot;
   out->ms_total = o.ms_warm + o.ms_final + ms_pilot;
   out->ms_eval_kernel = o.ms_kernel;
+  out->ms_pilot_kernel = ms_pilot_kernel;
+  out->pilot_same_kernel = pilot_kernel == std::vector<int>{S->ppt, S->wpe, S->lists ? 1 : 0, S->km} ? 1 : 0;
   out->points_per_thread = S->ppt;
   out->blocks = S->gf;
   out->tile_log2 = S->P.tile_log2;
