@@ -762,7 +762,7 @@ def _classes(problem):
     """Register class and singular-variable bound of the final pass instances."""
     nv = max(s.n for s in problem.sectors)
     nsm = max(int(sum(s.a == -1.0)) for s in problem.sectors)
-    nvc = 4 if nv <= 4 else 6 if nv <= 6 else 8 if nv <= 8 else 16
+    nvc = 4 if nv <= 4 else 6 if nv <= 6 else 8 if nv <= 8 else 10 if nv <= 10 else 16
     return nvc, (2 if nsm <= 2 else nsm)
 
 

@@ -459,9 +459,10 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     for (int W = 0; W < (1 << R.ns); ++W) c += 80.0 + 3.0 * R.kf * (1 << R.ns);
     pb->cost.push_back(c);
     pb->secs.push_back(R);
-    // variable class of the persistent kernel instance; the <= 6 class needs fewer
-    // registers (higher occupancy) for the common 5-6 variable sectors
-    const int nvc = n <= 4 ? 4 : (n <= 6 ? 6 : (n <= 8 ? 8 : 16));
+    // variable class of the persistent kernel instance; the <= 6 and <= 10
+    // classes need fewer registers (higher occupancy, fewer spills) than the
+    // next larger one for the common 5-6 and 9-10 variable sectors
+    const int nvc = n <= 4 ? 4 : (n <= 6 ? 6 : (n <= 8 ? 8 : (n <= 10 ? 10 : 16)));
     pb->nvmax = std::max(pb->nvmax, nvc);
     if (d->complex_mode) c *= 8.0 + 2.0 * n * n;
     pb->kfmax = std::max(pb->kfmax, R.kf);

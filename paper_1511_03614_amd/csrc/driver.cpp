@@ -322,7 +322,7 @@ int final_family(const sdi_problem* pb, const Params& p) {
 constexpr int CORNER_LISTS = 100;
 
 std::vector<int> generic_variants(const sdi_problem* pb) {
-  if (pb->nvmax >= 16) return {14, 23, 24};
+  if (pb->nvmax >= 10) return {14, 23, 24};
   return {14, 23, 24, 42};
 }
 
@@ -358,7 +358,7 @@ int default_variant(const sdi_problem* pb, const Params& p, int ppt) {
     case RF_DD: return DD_VARIANT;
     default: break;
   }
-  return ppt == 4 ? (pb->nvmax >= 16 ? 24 : 42) : 10 * ppt + 4;
+  return ppt == 4 ? (pb->nvmax >= 10 ? 24 : 42) : 10 * ppt + 4;
 }
 
 // Whether an encoded variant is one the tuner or a points-per-thread request

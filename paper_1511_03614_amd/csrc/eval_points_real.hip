@@ -7,28 +7,34 @@ namespace sdi {
 int launch_tiles_real_nv4(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv6(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv8(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv10(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv16(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int occupancy_tiles_real_nv4(int mode, int ppt, int wpe, int km, size_t shmem);
 int occupancy_tiles_real_nv6(int mode, int ppt, int wpe, int km, size_t shmem);
 int occupancy_tiles_real_nv8(int mode, int ppt, int wpe, int km, size_t shmem);
+int occupancy_tiles_real_nv10(int mode, int ppt, int wpe, int km, size_t shmem);
 int occupancy_tiles_real_nv16(int mode, int ppt, int wpe, int km, size_t shmem);
 
 int launch_tiles_real_nv4_s2(int ppt, int wpe, int km, bool dd, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv6_s2(int ppt, int wpe, int km, bool dd, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv8_s2(int ppt, int wpe, int km, bool dd, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv10_s2(int ppt, int wpe, int km, bool dd, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv16_s2(int ppt, int wpe, int km, bool dd, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int occupancy_tiles_real_nv4_s2(int ppt, int wpe, int km, bool dd, size_t shmem);
 int occupancy_tiles_real_nv6_s2(int ppt, int wpe, int km, bool dd, size_t shmem);
 int occupancy_tiles_real_nv8_s2(int ppt, int wpe, int km, bool dd, size_t shmem);
+int occupancy_tiles_real_nv10_s2(int ppt, int wpe, int km, bool dd, size_t shmem);
 int occupancy_tiles_real_nv16_s2(int ppt, int wpe, int km, bool dd, size_t shmem);
 
 int launch_tiles_real_nv4_g(int nsm, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv6_g(int nsm, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv8_g(int nsm, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int launch_tiles_real_nv10_g(int nsm, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int launch_tiles_real_nv16_g(int nsm, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int occupancy_tiles_real_nv4_g(int nsm, int ppt, int wpe, int km, size_t shmem);
 int occupancy_tiles_real_nv6_g(int nsm, int ppt, int wpe, int km, size_t shmem);
 int occupancy_tiles_real_nv8_g(int nsm, int ppt, int wpe, int km, size_t shmem);
+int occupancy_tiles_real_nv10_g(int nsm, int ppt, int wpe, int km, size_t shmem);
 int occupancy_tiles_real_nv16_g(int nsm, int ppt, int wpe, int km, size_t shmem);
 
 int real_family(int nsmax, int nfmax, int mode, bool dd) {
@@ -46,6 +52,7 @@ int launch_tiles_real(int nvmax, int nsmax, int nfmax, int ppt, int wpe, int km,
       if (nvmax <= 4) return launch_tiles_real_nv4_s2(ppt, wpe, km, dd, grid, shmem, a, st);
       if (nvmax <= 6) return launch_tiles_real_nv6_s2(ppt, wpe, km, dd, grid, shmem, a, st);
       if (nvmax <= 8) return launch_tiles_real_nv8_s2(ppt, wpe, km, dd, grid, shmem, a, st);
+      if (nvmax <= 10) return launch_tiles_real_nv10_s2(ppt, wpe, km, dd, grid, shmem, a, st);
       return launch_tiles_real_nv16_s2(ppt, wpe, km, dd, grid, shmem, a, st);
     case RF_G3:
     case RF_G4: {
@@ -53,6 +60,7 @@ int launch_tiles_real(int nvmax, int nsmax, int nfmax, int ppt, int wpe, int km,
       if (nvmax <= 4) return launch_tiles_real_nv4_g(nsm, ppt, wpe, km, grid, shmem, a, st);
       if (nvmax <= 6) return launch_tiles_real_nv6_g(nsm, ppt, wpe, km, grid, shmem, a, st);
       if (nvmax <= 8) return launch_tiles_real_nv8_g(nsm, ppt, wpe, km, grid, shmem, a, st);
+      if (nvmax <= 10) return launch_tiles_real_nv10_g(nsm, ppt, wpe, km, grid, shmem, a, st);
       return launch_tiles_real_nv16_g(nsm, ppt, wpe, km, grid, shmem, a, st);
     }
     case RF_DD:
@@ -61,6 +69,7 @@ int launch_tiles_real(int nvmax, int nsmax, int nfmax, int ppt, int wpe, int km,
       if (nvmax <= 4) return launch_tiles_real_nv4(ppt, wpe, km, grid, shmem, a, st);
       if (nvmax <= 6) return launch_tiles_real_nv6(ppt, wpe, km, grid, shmem, a, st);
       if (nvmax <= 8) return launch_tiles_real_nv8(ppt, wpe, km, grid, shmem, a, st);
+      if (nvmax <= 10) return launch_tiles_real_nv10(ppt, wpe, km, grid, shmem, a, st);
       return launch_tiles_real_nv16(ppt, wpe, km, grid, shmem, a, st);
   }
 }
@@ -73,6 +82,7 @@ int tiles_real_occupancy(int nvmax, int nsmax, int nfmax, int mode, int ppt, int
       if (nvmax <= 4) return occupancy_tiles_real_nv4_s2(ppt, wpe, km, dd, shmem);
       if (nvmax <= 6) return occupancy_tiles_real_nv6_s2(ppt, wpe, km, dd, shmem);
       if (nvmax <= 8) return occupancy_tiles_real_nv8_s2(ppt, wpe, km, dd, shmem);
+      if (nvmax <= 10) return occupancy_tiles_real_nv10_s2(ppt, wpe, km, dd, shmem);
       return occupancy_tiles_real_nv16_s2(ppt, wpe, km, dd, shmem);
     case RF_G3:
     case RF_G4: {
@@ -80,6 +90,7 @@ int tiles_real_occupancy(int nvmax, int nsmax, int nfmax, int mode, int ppt, int
       if (nvmax <= 4) return occupancy_tiles_real_nv4_g(nsm, ppt, wpe, km, shmem);
       if (nvmax <= 6) return occupancy_tiles_real_nv6_g(nsm, ppt, wpe, km, shmem);
       if (nvmax <= 8) return occupancy_tiles_real_nv8_g(nsm, ppt, wpe, km, shmem);
+      if (nvmax <= 10) return occupancy_tiles_real_nv10_g(nsm, ppt, wpe, km, shmem);
       return occupancy_tiles_real_nv16_g(nsm, ppt, wpe, km, shmem);
     }
     case RF_DD:
@@ -88,6 +99,7 @@ int tiles_real_occupancy(int nvmax, int nsmax, int nfmax, int mode, int ppt, int
       if (nvmax <= 4) return occupancy_tiles_real_nv4(mode, ppt, wpe, km, shmem);
       if (nvmax <= 6) return occupancy_tiles_real_nv6(mode, ppt, wpe, km, shmem);
       if (nvmax <= 8) return occupancy_tiles_real_nv8(mode, ppt, wpe, km, shmem);
+      if (nvmax <= 10) return occupancy_tiles_real_nv10(mode, ppt, wpe, km, shmem);
       return occupancy_tiles_real_nv16(mode, ppt, wpe, km, shmem);
   }
 }

@@ -42,7 +42,7 @@ int launch_tiles_expr(int grid, size_t shmem, const TileArgs& a, const ExprArgs&
 int tiles_expr_occupancy(int mode, size_t shmem, const ExprArgs& x);
 int launch_eval_points_expr(const EvalArgs& a, const ExprArgs& x, hipStream_t st);
 
-// Tile kernel of variable class nvmax (4, 6, 8 or 16), points per thread ppt and
+// Tile kernel of variable class nvmax (4, 6, 8, 10 or 16), points per thread ppt and
 // minimum waves per SIMD wpe, order capacity km (4 or 8), in the pass mode
 // a.mode (0 final, 1 warm-up with at most 2 points per thread, 2 explicit
 // points with 1; modes 1 and 2 run at 4 waves).  nsmax bounds the singular

@@ -243,7 +243,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
           run_tile_any<8, PPT, KM, MODE, NSM, DD, MF>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
         break;
       case 2:
-        if constexpr (NVC >= 2) run_tile_any<16, PPT, KM, MODE, NSM, DD, MF>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
+        if constexpr (NVC >= 2)
+          run_tile_any<(NVMAX == 10 ? 10 : 16), PPT, KM, MODE, NSM, DD, MF>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
         break;
       default:
         break;
