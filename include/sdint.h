@@ -164,7 +164,9 @@ typedef struct {
 /* Validate and compile a problem into device tables (one host-to-device upload).
  * Returns SDI_EINVAL for inputs outside the domain above and SDI_ENOTSUP for
  * valid inputs beyond the library (more than SDI_MAX_SINGULAR singular
- * variables, exponents above 3 in real mode or 7 in complex mode). */
+ * variables; factor exponents above 7 in real mode or above 3 in complex
+ * mode; exponents of the deformation polynomial's monomial times P_F above 7;
+ * more than 8 variables in complex mode). */
 int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* desc, sdi_problem** out);
 
 /* An integrand given as text in the integration workers' input format

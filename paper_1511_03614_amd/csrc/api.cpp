@@ -322,15 +322,20 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     R.flags = (int_pow ? F_INT_POW : 0) | (int_mono ? F_INT_MONO : 0);
     // terms per (factor, corner)
     size_t t0 = 0;
+    bool exp7 = false;
     for (int m = 0; m < sd.nfactors; ++m) {
       const int nt = sd.fac_nterms[m];
       if (nt < 0) return bad(SDI_EINVAL, where + "negative term count");
       if (nt > 0 && (!sd.term_coef || !sd.term_exps)) return bad(SDI_EINVAL, where + "null term arrays");
       for (int t = 0; t < nt; ++t) {
         if (!std::isfinite(sd.term_coef[t0 + t])) return bad(SDI_EINVAL, where + "term coefficient not finite");
-        for (int j = 0; j < n; ++j)
-          if (sd.term_exps[(t0 + t) * n + j] > 3)
-            return bad(SDI_ENOTSUP, where + "polynomial exponents above 3 are not supported");
+        for (int j = 0; j < n; ++j) {
+          const int e = sd.term_exps[(t0 + t) * n + j];
+          if (e > (d->complex_mode ? 3 : 7))
+            return bad(SDI_ENOTSUP, where + (d->complex_mode ? "polynomial exponents above 3 are not supported in complex mode"
+                                                             : "polynomial exponents above 7 are not supported"));
+          if (e > 3) exp7 = true;
+        }
       }
       for (int W = 0; W < (1 << R.ns); ++W) {
         R.tab_off[m][W] = (uint32_t)pb->terms.size();
@@ -369,6 +374,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
       }
       t0 += nt;
     }
+    if (exp7) R.flags |= F_EXP7;
     if (d->complex_mode) {
       // derivative lists of the full F = x^mono * P_F (internal variable order), per corner
       CplxDev X{};

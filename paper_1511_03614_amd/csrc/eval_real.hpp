@@ -145,7 +145,7 @@ __device__ __forceinline__ void make_points(CSec* S, CU64* zp, CU64* sh, const d
 // asm keeps the compiler from turning the skipped multiplies into per-lane
 // selects.  Bit 1 (x^2) multiplies by x twice: per-point squares held for the
 // whole evaluation cost more in register spills than the extra multiply.
-template <int NV, int PPT>
+template <int NV, int PPT, bool E7 = false>
 __device__ __forceinline__ void add_term(double c, uint64_t e, const double (&x)[PPT][NV],
                                          double (&out)[PPT]) {
   double m[PPT];
@@ -167,6 +167,13 @@ __device__ __forceinline__ void add_term(double c, uint64_t e, const double (&x)
 #pragma unroll
       for (int p = 0; p < PPT; ++p) m[p] = (m[p] * x[p][j]) * x[p][j];
     }
+    if constexpr (E7) {
+      if (w & (4u << sh)) {
+        asm volatile("" ::);
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) m[p] = (((m[p] * x[p][j]) * x[p][j]) * x[p][j]) * x[p][j];
+      }
+    }
   }
 #pragma unroll
   for (int p = 0; p < PPT; ++p) out[p] += m[p];
@@ -175,7 +182,8 @@ __device__ __forceinline__ void add_term(double c, uint64_t e, const double (&x)
 // sum_t coef_t prod_j x_j^e_tj over one term list, for PPT points, terms in
 // list order.  Terms are read four at a time so that their scalar loads are in
 // flight together (one wait per four terms instead of one per term).
-template <int NV, int PPT>
+// E7: exponents up to 7 (the x^4 bit is tested too; sectors with F_EXP7).
+template <int NV, int PPT, bool E7 = false>
 __device__ __forceinline__ void poly_real(CTerm* t, uint32_t cnt,
                                           const double (&x)[PPT][NV],
                                           double (&out)[PPT]) {
@@ -185,18 +193,18 @@ __device__ __forceinline__ void poly_real(CTerm* t, uint32_t cnt,
   for (; i + 4 <= cnt; i += 4) {
     const double c0 = t[i].coef, c1 = t[i + 1].coef, c2 = t[i + 2].coef, c3 = t[i + 3].coef;
     const uint64_t e0 = t[i].exps, e1 = t[i + 1].exps, e2 = t[i + 2].exps, e3 = t[i + 3].exps;
-    add_term<NV, PPT>(c0, e0, x, out);
-    add_term<NV, PPT>(c1, e1, x, out);
-    add_term<NV, PPT>(c2, e2, x, out);
-    add_term<NV, PPT>(c3, e3, x, out);
+    add_term<NV, PPT, E7>(c0, e0, x, out);
+    add_term<NV, PPT, E7>(c1, e1, x, out);
+    add_term<NV, PPT, E7>(c2, e2, x, out);
+    add_term<NV, PPT, E7>(c3, e3, x, out);
   }
-  for (; i < cnt; ++i) add_term<NV, PPT>(t[i].coef, t[i].exps, x, out);
+  for (; i < cnt; ++i) add_term<NV, PPT, E7>(t[i].coef, t[i].exps, x, out);
 }
 
 // out += coef prod_{j<NK} x_j^e_j: add_term for terms whose exponents vanish
 // beyond the first NK variables (the sector's own variable count), so that a
 // sector of n variables in a wider register class tests only its n variables.
-template <int NK, int NV, int PPT>
+template <int NK, int NV, int PPT, bool E7>
 __device__ __forceinline__ void add_term_k(double c, uint64_t e, const double (&x)[PPT][NV],
                                            double (&out)[PPT]) {
   static_assert(NK >= 1 && NK <= NV, "variable bound");
@@ -218,6 +226,13 @@ __device__ __forceinline__ void add_term_k(double c, uint64_t e, const double (&
 #pragma unroll
       for (int p = 0; p < PPT; ++p) m[p] = (m[p] * x[p][j]) * x[p][j];
     }
+    if constexpr (E7) {
+      if (w & (4u << sh)) {
+        asm volatile("" ::);
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) m[p] = (((m[p] * x[p][j]) * x[p][j]) * x[p][j]) * x[p][j];
+      }
+    }
   }
 #pragma unroll
   for (int p = 0; p < PPT; ++p) out[p] += m[p];
@@ -226,7 +241,7 @@ __device__ __forceinline__ void add_term_k(double c, uint64_t e, const double (&
 // out += sum over one term list.  Terms are read four at a time, and the next
 // four are requested before the current four are evaluated, so their scalar
 // loads are in flight while the multiplies of these run.
-template <int NK, int NV, int PPT>
+template <int NK, int NV, int PPT, bool E7>
 __device__ __forceinline__ void poly_acc_k(CTerm* t, uint32_t cnt, const double (&x)[PPT][NV],
                                            double (&out)[PPT]) {
   uint32_t i = 0;
@@ -236,34 +251,34 @@ __device__ __forceinline__ void poly_acc_k(CTerm* t, uint32_t cnt, const double 
     for (; i + 8 <= cnt; i += 4) {
       const double n0 = t[i + 4].coef, n1 = t[i + 5].coef, n2 = t[i + 6].coef, n3 = t[i + 7].coef;
       const uint64_t f0 = t[i + 4].exps, f1 = t[i + 5].exps, f2 = t[i + 6].exps, f3 = t[i + 7].exps;
-      add_term_k<NK, NV, PPT>(c0, e0, x, out);
-      add_term_k<NK, NV, PPT>(c1, e1, x, out);
-      add_term_k<NK, NV, PPT>(c2, e2, x, out);
-      add_term_k<NK, NV, PPT>(c3, e3, x, out);
+      add_term_k<NK, NV, PPT, E7>(c0, e0, x, out);
+      add_term_k<NK, NV, PPT, E7>(c1, e1, x, out);
+      add_term_k<NK, NV, PPT, E7>(c2, e2, x, out);
+      add_term_k<NK, NV, PPT, E7>(c3, e3, x, out);
       c0 = n0; c1 = n1; c2 = n2; c3 = n3;
       e0 = f0; e1 = f1; e2 = f2; e3 = f3;
     }
-    add_term_k<NK, NV, PPT>(c0, e0, x, out);
-    add_term_k<NK, NV, PPT>(c1, e1, x, out);
-    add_term_k<NK, NV, PPT>(c2, e2, x, out);
-    add_term_k<NK, NV, PPT>(c3, e3, x, out);
+    add_term_k<NK, NV, PPT, E7>(c0, e0, x, out);
+    add_term_k<NK, NV, PPT, E7>(c1, e1, x, out);
+    add_term_k<NK, NV, PPT, E7>(c2, e2, x, out);
+    add_term_k<NK, NV, PPT, E7>(c3, e3, x, out);
     i += 4;
   }
-  for (; i < cnt; ++i) add_term_k<NK, NV, PPT>(t[i].coef, t[i].exps, x, out);
+  for (; i < cnt; ++i) add_term_k<NK, NV, PPT, E7>(t[i].coef, t[i].exps, x, out);
 }
 
 // poly_acc_k with NK = the sector's variable count n (wave-uniform), for n in
 // K .. NV; smaller n takes NK = K.
-template <int K, int NV, int PPT>
+template <int K, int NV, int PPT, bool E7>
 __device__ __forceinline__ void poly_acc_n(CTerm* t, uint32_t cnt, int n, const double (&x)[PPT][NV],
                                            double (&out)[PPT]) {
   if constexpr (K >= NV) {
-    poly_acc_k<NV, NV, PPT>(t, cnt, x, out);
+    poly_acc_k<NV, NV, PPT, E7>(t, cnt, x, out);
   } else {
     if (n <= K)
-      poly_acc_k<K, NV, PPT>(t, cnt, x, out);
+      poly_acc_k<K, NV, PPT, E7>(t, cnt, x, out);
     else
-      poly_acc_n<K + 1, NV, PPT>(t, cnt, n, x, out);
+      poly_acc_n<K + 1, NV, PPT, E7>(t, cnt, n, x, out);
   }
 }
 
@@ -301,7 +316,10 @@ __device__ __forceinline__ void corner_polys(CSec* S, CTerm* terms, const double
         double q[PPT];
 #pragma unroll
         for (int p = 0; p < PPT; ++p) q[p] = 0.0;
-        poly_acc_n<class_low<NV>(), NV, PPT>(terms + S->grp_off[fm][sg], S->grp_cnt[fm][sg], n, x, q);
+        if (S->flags & F_EXP7)
+          poly_acc_n<class_low<NV>(), NV, PPT, true>(terms + S->grp_off[fm][sg], S->grp_cnt[fm][sg], n, x, q);
+        else
+          poly_acc_n<class_low<NV>(), NV, PPT, false>(terms + S->grp_off[fm][sg], S->grp_cnt[fm][sg], n, x, q);
 #pragma unroll
         for (int W = 0; W < NC; ++W) {
           if (W < C && (W & sg) == 0) {
@@ -369,7 +387,10 @@ __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
     for (int fm = 0; fm < MAXF; ++fm) {
       if (fm < nfac) {
         double P[PPT];
-        poly_real<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
+        if (flags & F_EXP7)
+          poly_real<NV, PPT, true>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
+        else
+          poly_real<NV, PPT, false>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
         const int g = S->gam_int[fm];
         const int d = S->del_int[fm];
         const int ga = g < 0 ? -g : g;
@@ -402,7 +423,10 @@ __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
     for (int fm = 0; fm < MAXF; ++fm) {
       if (fm < nfac) {
         double P[PPT];
-        poly_real<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
+        if (flags & F_EXP7)
+          poly_real<NV, PPT, true>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
+        else
+          poly_real<NV, PPT, false>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
         const double gm = S->gam[fm];
         const double dm = S->del[fm];
 #pragma unroll

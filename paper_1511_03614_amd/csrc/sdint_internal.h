@@ -40,6 +40,7 @@ enum SecFlags : int32_t {
   F_INT_MONO = 4,      // non-singular a_j small non-negative integers, b_j integers |b| <= 8
   F_USE_GRID = 8,      // Vegas map active
   F_BAKER = 16,        // tent transform of the lattice
+  F_EXP7 = 32,         // some factor exponent above 3 (the x^4 bit of the term words is used)
 };
 
 struct alignas(16) SecDev {
