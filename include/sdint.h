@@ -90,6 +90,18 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *   pilot_log2     lattice log2 of the pilot pass               (default 12)
  *   sampler        0: shifted lattice (+ Vegas grid), 1: the learned flow of
  *                  sdi_flow_init (warmup must be 0)             (default 0)
+ *   slice_log2     resumable lattice pass (the -continue option of section
+ *                  4.5): > 0 makes each sdi_integrate call process the next
+ *                  2^slice_log2 lattice points of every shift of every
+ *                  sector, continuing the per-(sector, shift) sums of the
+ *                  earlier calls (sdi_checkpoint_export/import move them
+ *                  between processes); results report the points done so far,
+ *                  and once the lattice is complete they equal one call over
+ *                  the whole lattice bit for bit when tile_log2 <= slice_log2
+ *                  and tile_log2 and ppt are fixed (nonzero).  A call with
+ *                  other settings, or after the last slice, starts a new pass.
+ *                  Needs budget 0, warmup 0, sampler 0 (else SDI_ENOTSUP).
+ *                  0 = off                                      (default 0)
  *   small_x        endpoint precision, a number in [0, 1] (decimal or
  *                  exponent notation): in real mode, points whose smallest
  *                  singular coordinate lies below it are evaluated in
@@ -242,6 +254,8 @@ typedef struct {
                                    allocation; 0 without)                              */
   int32_t pilot_same_kernel;    /* 1: the pilot pass ran the same kernel instance as the
                                    final pass (budget allocation; 0 without)           */
+  int64_t lattice_done;         /* lattice points per shift the estimates rest on: 2^m,
+                                   or under slice_log2 the points done so far          */
 } sdi_result;
 
 /* Bytes of device workspace sdi_integrate needs under the current parameters. */
@@ -256,6 +270,21 @@ size_t sdi_workspace_bytes(sdi_ctx* ctx, const sdi_problem* prob);
  * value was not finite. */
 int sdi_integrate(sdi_ctx* ctx, sdi_problem* prob, void* dev_workspace, size_t ws_bytes,
                   sdi_result* out);
+
+/* Checkpoints of a resumable pass (slice_log2 > 0; the -continue option and the
+ * saved partial results of sections 2.5 and 4.5): the per-(sector, shift)
+ * double-double sums of the lattice points done so far, their non-finite and
+ * Im F > 0 counts, the progress and the settings they were made under.
+ * sdi_checkpoint_export writes them to host memory buf (len bytes); *needed
+ * receives the size (buf NULL: only the size).  SDI_ESTATE without a pass in
+ * progress, SDI_ENOMEM if len is too small.  sdi_checkpoint_import loads such
+ * a buffer into prob (same sectors and shifts) of a context whose parameters
+ * equal the checkpoint's settings (lattice_log2, shifts, seed, baker,
+ * slice_log2, tile_log2, ppt, small_x; SDI_EINVAL otherwise, naming them); the
+ * next sdi_integrate continues the pass.  The buffer is a plain host-endian
+ * binary record, valid on machines of the same byte order. */
+int sdi_checkpoint_export(sdi_ctx* ctx, const sdi_problem* prob, void* buf, size_t len, size_t* needed);
+int sdi_checkpoint_import(sdi_ctx* ctx, sdi_problem* prob, const void* buf, size_t len);
 
 /* Per-sector results of the last sdi_integrate: mean[K][2] (re, im),
  * err[K][2], per_shift[R][K][2] (may be NULL), *nevals. */

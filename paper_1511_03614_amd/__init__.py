@@ -26,7 +26,7 @@ __all__ = [
     "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
     "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_flow_set_active", "sdi_flow_validate",
     "sdi_tune_deformation", "sdi_problem_nvars", "sdi_vegas_refit", "sdi_flow_weights",
-    "sdi_sample_points_noalloc",
+    "sdi_sample_points_noalloc", "sdi_checkpoint_export", "sdi_checkpoint_import",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -70,7 +70,7 @@ class Result(C.Structure):
                 ("ms_sample_eval_reduce", C.c_double), ("ms_refit", C.c_double), ("ms_total", C.c_double),
                 ("ms_eval_kernel", C.c_double), ("points_per_thread", C.c_int32), ("blocks", C.c_int32),
                 ("tile_log2", C.c_int32), ("waves_per_simd", C.c_int32), ("grouped", C.c_int32),
-                ("ms_pilot_kernel", C.c_double), ("pilot_same_kernel", C.c_int32)]
+                ("ms_pilot_kernel", C.c_double), ("pilot_same_kernel", C.c_int32), ("lattice_done", C.c_int64)]
 
 
 def library_path() -> str:
@@ -117,6 +117,8 @@ def load_library():
         "sdi_problem_nsectors": (C.c_int, [vp]),
         "sdi_problem_nvars": (C.c_int, [vp, i32]),
         "sdi_sample_points_noalloc": (C.c_int, [vp, vp, i32, i32, i64, i64, vp, vp]),
+        "sdi_checkpoint_export": (C.c_int, [vp, vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]),
+        "sdi_checkpoint_import": (C.c_int, [vp, vp, vp, C.c_size_t]),
         "sdi_vegas_refit": (C.c_int, [vp, i32, i32, i32, vp, vp, C.c_double]),
         "sdi_flow_weights": (C.c_int, [vp, i64, i32, vp, vp, dp, vp]),
         "sdi_workspace_bytes": (C.c_size_t, [vp, vp]),
@@ -340,7 +342,7 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
     """Run the integrator; `workspace` is an optional torch uint8 cuda tensor."""
     K = sdi_problem_norders(prob)
     arrs = [np.zeros(K) for _ in range(4)]
-    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, 0.0, 0)
+    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, 0.0, 0, 0)
     ptr, nbytes = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()), workspace.numel())
     if workspace is not None:
         import torch
@@ -352,7 +354,7 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
             "ms_warmup": res.ms_refit, "ms_total": res.ms_total, "ms_eval_kernel": res.ms_eval_kernel,
             "ppt": res.points_per_thread, "blocks": res.blocks, "tile_log2": res.tile_log2,
             "waves_per_simd": res.waves_per_simd, "grouped": res.grouped, "ms_pilot_kernel": res.ms_pilot_kernel,
-            "pilot_same_kernel": res.pilot_same_kernel}
+            "pilot_same_kernel": res.pilot_same_kernel, "lattice_done": res.lattice_done}
 
 
 def sdi_sector_results(ctx, prob, s: int, nshifts: int):
@@ -433,6 +435,21 @@ def sdi_sample_points_noalloc(ctx, prob, s: int, shift: int, i0: int, x, w=None)
     _check(load_library().sdi_sample_points_noalloc(ctx, prob, s, shift, i0, x.shape[0], C.c_void_p(x.data_ptr()),
                                                     C.c_void_p(w.data_ptr()) if w is not None else None), ctx)
     return x, w
+
+
+def sdi_checkpoint_export(ctx, prob) -> bytes:
+    """The resumable pass's sums and progress as bytes."""
+    lib = load_library()
+    need = C.c_size_t(0)
+    _check(lib.sdi_checkpoint_export(ctx, prob, None, 0, C.byref(need)), ctx)
+    buf = C.create_string_buffer(need.value)
+    _check(lib.sdi_checkpoint_export(ctx, prob, buf, need.value, C.byref(need)), ctx)
+    return buf.raw[: need.value]
+
+
+def sdi_checkpoint_import(ctx, prob, data: bytes):
+    buf = C.create_string_buffer(bytes(data), len(data))
+    _check(load_library().sdi_checkpoint_import(ctx, prob, buf, len(data)), ctx)
 
 
 # ---------------------------------------------------------------- deformation size

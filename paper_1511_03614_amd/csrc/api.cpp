@@ -154,6 +154,9 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
   } else if (k == "graph") {
     if (!range(0, 1)) return fail(ctx, SDI_EINVAL, "graph must be 0 or 1");
     p.graph = (int)iv;
+  } else if (k == "slice_log2") {
+    if (!range(0, 30)) return fail(ctx, SDI_EINVAL, "slice_log2 must be in 0..30");
+    p.slice_log2 = (int)iv;
   } else if (k == "budget") {
     if (!range(0, (long long)1 << 40)) return fail(ctx, SDI_EINVAL, "budget must be in 0..2^40");
     p.budget = iv;
@@ -197,6 +200,7 @@ int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len) {
   else if (k == "ppt") v = p.ppt;
   else if (k == "graph") v = p.graph;
   else if (k == "budget") v = p.budget;
+  else if (k == "slice_log2") v = p.slice_log2;
   else if (k == "alloc_min_log2") v = p.alloc_min;
   else if (k == "alloc_max_log2") v = p.alloc_max;
   else if (k == "pilot_log2") v = p.pilot_log2;

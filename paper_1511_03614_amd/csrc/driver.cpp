@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -21,6 +22,7 @@ namespace sdi {
 struct Plan {
   int R = 0, rows = 0;
   int tile_log2 = 14;            // points per final-pass tile (log2; shorter lattices make one tile)
+  uint32_t range_lo = 0, range_hi = 0;  // lattice indices of this pass per shift (hi 0: the whole lattice)
   double small_x = 0.0;          // endpoint-precision threshold of the lattice final pass (0: off)
   bool warm = false;
   bool flow = false;             // final points come from the learned sampler
@@ -49,6 +51,10 @@ struct Plan {
   double* d_per_shift = nullptr;
   double* d_sec_stats = nullptr;
   double* d_res = nullptr;
+  double* d_carry_in = nullptr;     // resumable pass: sums and counts of the earlier slices
+  int64_t* d_carry_in_counts = nullptr;
+  double* d_carry_out = nullptr;    // ... and after this slice
+  int64_t* d_carry_out_counts = nullptr;
   int64_t* d_counts = nullptr;
   int64_t* d_pair_nonfinite = nullptr;
   int64_t* d_sec_nonfinite = nullptr;
@@ -134,10 +140,13 @@ void sector_fields(const Params& prm, const sdi_problem* pb, const std::vector<i
   }
 }
 
-int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& msec, bool warm, int tile_log2) {
+int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& msec, bool warm, int tile_log2,
+              uint32_t range_lo = 0, uint32_t range_hi = 0) {
   const Params& prm = ctx->params;
   P.R = prm.R;
   P.tile_log2 = tile_log2;
+  P.range_lo = range_lo;
+  P.range_hi = range_hi;
   P.rows = prm.R + prm.warmup;
   P.warm = warm && prm.warmup > 0;
   P.flow = prm.sampler == 1;
@@ -155,11 +164,13 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   P.ftiles.clear();
   for (int s = 0; s < nsec; ++s) {
     const uint32_t N = 1u << msec[s];
-    const uint32_t tsz = std::min<uint32_t>(N, 1u << tile_log2);
+    // a slice of a resumable pass covers indices [range_lo, range_hi) of every shift
+    const uint32_t lo = range_hi ? range_lo : 0u, hi = range_hi ? std::min(range_hi, N) : N;
+    const uint32_t tsz = std::min<uint32_t>(hi - lo, 1u << tile_log2);
     for (int r = 0; r < prm.R; ++r) {
       P.pair_start.push_back((int32_t)P.ftiles.size());
       P.pair_sector.push_back(s);
-      for (uint32_t i0 = 0; i0 < N; i0 += tsz) P.ftiles.push_back(TileDesc{s, r, i0, tsz});
+      for (uint32_t i0 = lo; i0 < hi; i0 += tsz) P.ftiles.push_back(TileDesc{s, r, i0, std::min(tsz, hi - i0)});
     }
   }
   P.pair_start.push_back((int32_t)P.ftiles.size());
@@ -261,6 +272,10 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   C.add((void**)&P.d_per_shift, npairs * KMAX * 2 * 8);
   C.add((void**)&P.d_sec_stats, (size_t)nsec * KMAX * 4 * 8);
   C.add((void**)&P.d_res, KMAX * 4 * 8);
+  C.add((void**)&P.d_carry_in, npairs * KMAX * 4 * 8);
+  C.add((void**)&P.d_carry_in_counts, npairs * 16);
+  C.add((void**)&P.d_carry_out, npairs * KMAX * 4 * 8);
+  C.add((void**)&P.d_carry_out_counts, npairs * 16);
   C.add((void**)&P.d_counts, 2 * 8);
   C.add((void**)&P.d_pair_nonfinite, npairs * 16);
   C.add((void**)&P.d_sec_nonfinite, (size_t)nsec * 16);
@@ -394,13 +409,14 @@ int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int 
   return (int)std::max<size_t>(1, std::min(g, ntiles));
 }
 
-std::string pass_key(const Params& p, const std::vector<int>& msec, bool warm, const void* ws, size_t wsb) {
-  char buf[320];
+std::string pass_key(const Params& p, const std::vector<int>& msec, bool warm, const void* ws, size_t wsb,
+                     uint32_t lo = 0, uint32_t hi = 0) {
+  char buf[360];
   unsigned long long h = 1469598103934665603ull;
   for (int m : msec) h = (h ^ (unsigned)m) * 1099511628211ull;
-  snprintf(buf, sizeof buf, "R%d s%llu b%d w%d/%d mw%d nb%d t%d p%d g%d f%d x%.17g m%llx ws%p:%zu", p.R,
+  snprintf(buf, sizeof buf, "R%d s%llu b%d w%d/%d mw%d nb%d t%d p%d g%d f%d x%.17g m%llx ws%p:%zu r%u:%u", p.R,
            (unsigned long long)p.seed, p.baker, p.warmup, (int)warm, p.mw, p.nbins, p.tile_log2, p.ppt, p.graph,
-           p.sampler, p.small_x, h, ws, wsb);
+           p.sampler, p.small_x, h, ws, wsb, lo, hi);
   return buf;
 }
 
@@ -488,8 +504,11 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
     if (!P.xorder.empty())
       KCHK(ctx, launch_tiles(pb, 1, 4, S.km, S.gx, P.shmem_final, final_args(pb, P, true), st));
   } else {
+    const bool sliced = P.range_hi != 0;
     KCHK(ctx, launch_reduce_pairs(P.d_partial, P.d_pair_start, P.d_pair_sector, P.d_secs, npairs, P.d_per_shift,
-                                  P.d_nonfinite, P.d_pair_nonfinite, st));
+                                  P.d_nonfinite, P.d_pair_nonfinite, sliced && P.range_lo ? P.d_carry_in : nullptr,
+                                  sliced && P.range_lo ? P.d_carry_in_counts : nullptr, sliced ? P.d_carry_out : nullptr,
+                                  sliced ? P.d_carry_out_counts : nullptr, sliced ? (int64_t)P.range_hi : 0, st));
     KCHK(ctx, launch_sector_stats(P.d_per_shift, nsec, prm.R, P.d_sec_stats, P.d_pair_nonfinite, P.d_sec_nonfinite,
                                   st));
     KCHK(ctx, launch_combine(P.d_sec_stats, nsec, P.d_sec_nonfinite, P.d_res, P.d_counts, st));
@@ -525,9 +544,9 @@ std::vector<int> tile_candidates(const sdi_problem* pb, const Params& prm, const
 // Builds the plan for one tile size on dev_ws (or on the pass's own
 // allocation), uploads it and waits for the copies.
 int setup_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, const std::vector<int>& msec, bool warm, int tile_log2,
-               void* dev_ws, size_t ws_bytes) {
+               void* dev_ws, size_t ws_bytes, uint32_t lo = 0, uint32_t hi = 0) {
   const Params& prm = ctx->params;
-  int rc = make_plan(ctx, pb, S.P, msec, warm, tile_log2);
+  int rc = make_plan(ctx, pb, S.P, msec, warm, tile_log2, lo, hi);
   if (rc != SDI_OK) return rc;
   Plan& P = S.P;
   const size_t need = P.carve.total();
@@ -640,7 +659,7 @@ std::string tune_key(const sdi_ctx* ctx, const sdi_problem* pb, const std::vecto
 // fixed_variant >= 0 skips the variant search.  With a caller workspace every
 // candidate plan is built on it in turn; a size that does not fit is skipped.
 int autotune(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool warm, const std::vector<int>& tiles,
-             int fixed_variant, void* dev_ws, size_t ws_bytes, TuneChoice& out) {
+             int fixed_variant, void* dev_ws, size_t ws_bytes, TuneChoice& out, uint32_t lo = 0, uint32_t hi = 0) {
   const Params& prm = ctx->params;
   const std::string key = tune_key(ctx, pb, msec, warm);
   if (prm.tune == 1)
@@ -664,7 +683,7 @@ int autotune(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
     const int tl = rounds[r].first < 0 ? best.tile_log2 : rounds[r].first;
     if (rounds[r].first < 0 && tl == tiles.front()) break;   // the first round already timed these
     PassState C;
-    int rc = setup_pass(ctx, pb, C, msec, warm, tl, dev_ws, ws_bytes);
+    int rc = setup_pass(ctx, pb, C, msec, warm, tl, dev_ws, ws_bytes, lo, hi);
     if (rc == SDI_ENOMEM && r > 0) {
       ctx->err.clear();
       continue;
@@ -698,9 +717,9 @@ int autotune(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
 // The cached pass for (parameters, per-sector lattice sizes, warm-up flag,
 // workspace), tuned, built, uploaded and captured on first use.
 int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool warm, void* dev_ws, size_t ws_bytes,
-             PassState** out) {
+             PassState** out, uint32_t lo = 0, uint32_t hi = 0) {
   const Params& prm = ctx->params;
-  const std::string key = pass_key(prm, msec, warm, dev_ws, ws_bytes);
+  const std::string key = pass_key(prm, msec, warm, dev_ws, ws_bytes, lo, hi);
   for (size_t i = 0; i < pb->passes.size(); ++i)
     if (pb->passes[i]->key == key) {
       *out = pb->passes[i];
@@ -725,11 +744,11 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
   else if (prm.tune == 0)
     ch.variant = (pb->complex_mode || pb->is_expr()) ? 11 : default_variant(pb, prm, 2);
   if (ch.variant < 0 || tiles.size() > 1) {
-    const int rc = autotune(ctx, pb, msec, warm, tiles, ch.variant, dev_ws, ws_bytes, ch);
+    const int rc = autotune(ctx, pb, msec, warm, tiles, ch.variant, dev_ws, ws_bytes, ch, lo, hi);
     if (rc != SDI_OK) return rc;
   }
   PassState* S = new PassState();
-  int rc = setup_pass(ctx, pb, *S, msec, warm, ch.tile_log2, dev_ws, ws_bytes);
+  int rc = setup_pass(ctx, pb, *S, msec, warm, ch.tile_log2, dev_ws, ws_bytes, lo, hi);
   if (rc != SDI_OK) {
     delete S;
     return rc;
@@ -776,7 +795,8 @@ int get_pass(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
 }
 
 struct PassOut {
-  std::vector<double> res, sec_stats, per_shift;
+  std::vector<double> res, sec_stats, per_shift, carry;
+  std::vector<int64_t> carry_counts;
   int64_t counts[2] = {0, 0};
   float ms_warm = 0.f, ms_final = 0.f, ms_kernel = 0.f;
 };
@@ -784,6 +804,13 @@ struct PassOut {
 int run_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, PassOut& o) {
   hipStream_t st = ctx->stream;
   Plan& P = S.P;
+  const size_t npairs = P.pair_sector.size();
+  if (P.range_hi && P.range_lo) {
+    if (pb->resume_sums.size() != npairs * KMAX * 4 || pb->resume_counts.size() != npairs * 2)
+      return fail(ctx, SDI_ESTATE, "resumable pass: no sums of the earlier slices");
+    HIPCHK(ctx, hipMemcpyAsync(P.d_carry_in, pb->resume_sums.data(), npairs * KMAX * 4 * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(P.d_carry_in_counts, pb->resume_counts.data(), npairs * 16, hipMemcpyHostToDevice, st));
+  }
   for (int seg = 0; seg < 3; ++seg) {
     HIPCHK(ctx, hipEventRecord(S.ev[seg], st));
     if (S.exec[seg]) {
@@ -801,6 +828,12 @@ int run_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, PassOut& o) {
   HIPCHK(ctx, hipMemcpyAsync(o.counts, P.d_counts, 16, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipMemcpyAsync(o.sec_stats.data(), P.d_sec_stats, o.sec_stats.size() * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipMemcpyAsync(o.per_shift.data(), P.d_per_shift, o.per_shift.size() * 8, hipMemcpyDeviceToHost, st));
+  if (P.range_hi) {
+    o.carry.assign(npairs * KMAX * 4, 0.0);
+    o.carry_counts.assign(npairs * 2, 0);
+    HIPCHK(ctx, hipMemcpyAsync(o.carry.data(), P.d_carry_out, npairs * KMAX * 4 * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipMemcpyAsync(o.carry_counts.data(), P.d_carry_out_counts, npairs * 16, hipMemcpyDeviceToHost, st));
+  }
   HIPCHK(ctx, hipStreamSynchronize(st));
   HIPCHK(ctx, hipEventElapsedTime(&o.ms_warm, S.ev[0], S.ev[1]));
   HIPCHK(ctx, hipEventElapsedTime(&o.ms_kernel, S.ev[1], S.ev[2]));
@@ -809,6 +842,17 @@ int run_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, PassOut& o) {
 }
 
 }  // namespace
+
+// Settings a resumable pass's sums belong to: a slice continues the sums of
+// the earlier ones only under the same lattice, shifts, seed, tent map, slice
+// and launch requests (the tile size and points per thread decide which
+// points a block sums, so they fix the rounding of the partial sums).
+std::string resume_key(const Params& p, int nsec) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "n%d m%d R%d s%llu b%d sl%d t%d p%d x%.17g", nsec, p.m, p.R, (unsigned long long)p.seed,
+           p.baker, p.slice_log2, p.tile_log2, p.ppt, p.small_x);
+  return buf;
+}
 
 // Neyman-style allocation of the final-pass budget: for every order k with a
 // nonzero total, sector s gets the weight sigma_{s,k} / sqrt(sum_s sigma_{s,k}^2)
@@ -954,6 +998,22 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   if (prm.budget > 0 && dev_ws) return fail(ctx, SDI_ENOTSUP, "budget allocation needs the library workspace");
   if (prm.alloc_min > prm.alloc_max) return fail(ctx, SDI_EINVAL, "alloc_min_log2 > alloc_max_log2");
   const int nsec = pb->nsec;
+  // resumable pass: this call's slice [lo, hi) of every shift
+  uint32_t lo = 0, hi = 0;
+  std::string rkey;
+  if (prm.slice_log2 > 0) {
+    if (prm.budget > 0 || prm.warmup > 0 || prm.sampler != 0)
+      return fail(ctx, SDI_ENOTSUP, "slice_log2 needs a uniform lattice pass (budget 0, warmup 0, sampler 0)");
+    rkey = resume_key(prm, nsec);
+    const uint32_t N = 1u << prm.m;
+    if (pb->resume_key != rkey || pb->resume_done <= 0 || pb->resume_done >= (int64_t)N) pb->resume_done = 0;
+    lo = (uint32_t)pb->resume_done;
+    hi = (uint32_t)std::min<uint64_t>(N, (uint64_t)lo + (1ull << std::min(prm.slice_log2, 31)));
+    if (lo == 0) {
+      pb->resume_sums.clear();
+      pb->resume_counts.clear();
+    }
+  }
   PassOut o;
   float ms_pilot = 0.f, ms_pilot_kernel = 0.f;
   std::vector<int> pilot_kernel;   // launch variant of the pilot's tile kernel
@@ -975,7 +1035,7 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
     msec = neyman_allocation(pb, o.sec_stats, prm);
     warm = false;
   }
-  rc = get_pass(ctx, pb, msec, warm, dev_ws, ws_bytes, &S);
+  rc = get_pass(ctx, pb, msec, warm, dev_ws, ws_bytes, &S, lo, hi);
   if (rc != SDI_OK) return rc;
   const bool had_warm = S->P.warm;
   rc = run_pass(ctx, pb, *S, o);
@@ -993,9 +1053,16 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   pb->sec_evals.assign(nsec, 0);
   int64_t final_evals = 0;
   for (int s = 0; s < nsec; ++s) {
-    pb->sec_evals[s] = (int64_t)prm.R << msec[s];
-    final_evals += pb->sec_evals[s];
+    pb->sec_evals[s] = hi ? (int64_t)prm.R * hi : (int64_t)prm.R << msec[s];
+    final_evals += hi ? (int64_t)prm.R * (hi - lo) : pb->sec_evals[s];
   }
+  if (hi) {
+    pb->resume_sums = o.carry;
+    pb->resume_counts = o.carry_counts;
+    pb->resume_done = hi;
+    pb->resume_key = rkey;
+  }
+  out->lattice_done = hi ? (int64_t)hi : ((int64_t)1 << prm.m);
   out->order_min = pb->order_min;
   out->norders = pb->K;
   for (int k = 0; k < pb->K; ++k) {
@@ -1163,6 +1230,80 @@ int sdi_sample_points_noalloc(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, in
   HIPCHK(ctx, hipMemcpyAsync(d_zp, zp.data(), MAXV * 8, hipMemcpyHostToDevice, st));
   KCHK(ctx, sample_launch(ctx, d_one, d_zp, d_row, grid, shift, i0, npts, x_dev, w_dev));
   HIPCHK(ctx, hipStreamSynchronize(st));
+  return SDI_OK;
+}
+
+namespace {
+struct CheckpointHeader {
+  char magic[8];
+  int32_t nsec, R, m, baker, slice_log2, tile_log2, ppt, pad;
+  uint64_t seed;
+  double small_x;
+  int64_t done, npairs;
+};
+constexpr char CKPT_MAGIC[8] = {'S', 'D', 'I', 'R', 'S', 'M', '0', '1'};
+}  // namespace
+
+int sdi_checkpoint_export(sdi_ctx* ctx, const sdi_problem* pb, void* buf, size_t len, size_t* needed) {
+  if (!ctx || !pb || !needed) return fail(ctx, SDI_EINVAL, "checkpoint_export: null argument");
+  if (pb->resume_key.empty() || pb->resume_done <= 0)
+    return fail(ctx, SDI_ESTATE, "checkpoint_export: no resumable pass in progress on this problem");
+  const size_t npairs = pb->resume_counts.size() / 2;
+  const size_t bytes = sizeof(CheckpointHeader) + npairs * KMAX * 4 * 8 + npairs * 16;
+  *needed = bytes;
+  if (!buf) return SDI_OK;
+  if (len < bytes) return fail(ctx, SDI_ENOMEM, "checkpoint_export: buffer needs " + std::to_string(bytes) + " bytes");
+  // the settings are those of the key the sums were made under
+  CheckpointHeader h{};
+  std::memcpy(h.magic, CKPT_MAGIC, 8);
+  unsigned long long seed = 0;
+  double sx = 0.0;
+  if (sscanf(pb->resume_key.c_str(), "n%d m%d R%d s%llu b%d sl%d t%d p%d x%lg", &h.nsec, &h.m, &h.R, &seed, &h.baker,
+             &h.slice_log2, &h.tile_log2, &h.ppt, &sx) != 9)
+    return fail(ctx, SDI_ESTATE, "checkpoint_export: unreadable pass settings");
+  h.seed = seed;
+  h.small_x = sx;
+  h.done = pb->resume_done;
+  h.npairs = (int64_t)npairs;
+  unsigned char* p = (unsigned char*)buf;
+  std::memcpy(p, &h, sizeof h);
+  std::memcpy(p + sizeof h, pb->resume_sums.data(), npairs * KMAX * 4 * 8);
+  std::memcpy(p + sizeof h + npairs * KMAX * 4 * 8, pb->resume_counts.data(), npairs * 16);
+  return SDI_OK;
+}
+
+int sdi_checkpoint_import(sdi_ctx* ctx, sdi_problem* pb, const void* buf, size_t len) {
+  if (!ctx || !pb || !buf) return fail(ctx, SDI_EINVAL, "checkpoint_import: null argument");
+  if (pb->ctx != ctx) return fail(ctx, SDI_EINVAL, "problem belongs to another context");
+  CheckpointHeader h{};
+  if (len < sizeof h) return fail(ctx, SDI_EINVAL, "checkpoint_import: too short");
+  std::memcpy(&h, buf, sizeof h);
+  if (std::memcmp(h.magic, CKPT_MAGIC, 8) != 0) return fail(ctx, SDI_EINVAL, "checkpoint_import: not a checkpoint");
+  if (h.npairs != (int64_t)pb->nsec * h.R || h.nsec != pb->nsec)
+    return fail(ctx, SDI_EINVAL, "checkpoint_import: made for another problem (sector or shift count differs)");
+  const size_t bytes = sizeof h + (size_t)h.npairs * KMAX * 4 * 8 + (size_t)h.npairs * 16;
+  if (len != bytes) return fail(ctx, SDI_EINVAL, "checkpoint_import: size does not match its header");
+  if (h.done <= 0 || h.m < 4 || h.m > 30 || h.done > ((int64_t)1 << h.m))
+    return fail(ctx, SDI_EINVAL, "checkpoint_import: progress outside the lattice");
+  Params q = ctx->params;
+  q.m = h.m;
+  q.R = h.R;
+  q.seed = h.seed;
+  q.baker = h.baker;
+  q.slice_log2 = h.slice_log2;
+  q.tile_log2 = h.tile_log2;
+  q.ppt = h.ppt;
+  q.small_x = h.small_x;
+  const std::string key = resume_key(q, pb->nsec);
+  if (key != resume_key(ctx->params, pb->nsec))
+    return fail(ctx, SDI_EINVAL, "checkpoint_import: the context's parameters differ from the checkpoint's (" + key + ")");
+  const unsigned char* p = (const unsigned char*)buf + sizeof h;
+  pb->resume_sums.assign((size_t)h.npairs * KMAX * 4, 0.0);
+  pb->resume_counts.assign((size_t)h.npairs * 2, 0);
+  std::memcpy(pb->resume_sums.data(), p, pb->resume_sums.size() * 8);
+  std::memcpy(pb->resume_counts.data(), p + pb->resume_sums.size() * 8, pb->resume_counts.size() * 8);
+  pb->resume_done = h.done;
+  pb->resume_key = key;
   return SDI_OK;
 }
 

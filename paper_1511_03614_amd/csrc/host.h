@@ -57,6 +57,7 @@ struct Params {
   int pilot_log2 = 12;   // lattice log2 of the pilot pass that measures the variances
   int sampler = 0;       // 0: lattice (+ Vegas grid), 1: the learned flow
   double small_x = 0.0;  // real mode: double-double below this smallest singular coordinate (0: off)
+  int slice_log2 = 0;    // > 0: a call processes the next 2^slice_log2 lattice points per shift (resumable)
 };
 
 // One autotuner decision: final-pass tile size and launch variant
@@ -136,6 +137,14 @@ struct sdi_problem {
   int nsec = 0, K = 0, order_min = 0, kfmax = 0, nvmax = 4, complex_mode = 0;
   int nsmax = 0;                      // most singular variables of any sector
   int nfmax = 0;                      // most regular factors of any sector
+  // resumable lattice pass (slice_log2 > 0): per (sector, shift) the running
+  // double-double sums [npairs][KMAX][4] (re hi, re lo, im hi, im lo) of the
+  // points done, the non-finite and Im F > 0 counts [npairs][2], the points
+  // done per shift and the settings the sums belong to
+  std::vector<double> resume_sums;
+  std::vector<int64_t> resume_counts;
+  int64_t resume_done = 0;
+  std::string resume_key;
   double lambda = 0.0;
   std::vector<sdi::SecDev> secs;      // host copy (updated per integrate)
   std::vector<sdi::Term> terms;

@@ -13,9 +13,14 @@ namespace sdi {
 int launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 int launch_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t seed, uint32_t row0,
                   uint64_t* shifts, hipStream_t st);
+// carry_in (may be null): running sums [npairs][KMAX][4] and counts [npairs][2]
+// of earlier slices of the same pass, continued by this pass's tiles in
+// order; carry_out (may be null) receives the continued sums and counts;
+// npts: points per shift done with this pass (the divisor of the means).
 int launch_reduce_pairs(const double* partial, const int32_t* pair_start, const int32_t* pair_sector,
                         const SecDev* secs, int npairs, double* out, const int32_t* nonfinite,
-                        int64_t* pair_nonfinite, hipStream_t st);
+                        int64_t* pair_nonfinite, const double* carry_in, const int64_t* carry_in_counts,
+                        double* carry_out, int64_t* carry_out_counts, int64_t npts, hipStream_t st);
 int launch_sector_stats(const double* per_shift, int nsec, int R, double* out, const int64_t* pair_nonfinite,
                         int64_t* sec_nonfinite, hipStream_t st);
 int launch_combine(const double* sec_stats, int nsec, const int64_t* sec_nonfinite, double* res, int64_t* counts,

@@ -53,21 +53,29 @@ __global__ void k_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uin
 // Per (sector, final shift): fixed-order double-double sums over the pair's
 // tiles of every internal order, Q_kk = sum / N, then the prefactor fold
 // Q_k = sum_kk fold[k][kk] Q_kk (linear, so it commutes with the sum).
-// out: [npairs][KMAX][2] = Q_re, Q_im.
+// out: [npairs][KMAX][2] = Q_re, Q_im.  A slice of a resumable pass starts
+// from the sums carried from the earlier slices (the same double-double
+// additions in the same tile order as one pass over the whole lattice) and
+// divides by the points done so far (npts > 0; 0: the whole lattice).
 __global__ void k_reduce_pairs(const double* partial, const int32_t* pair_start, const int32_t* pair_sector,
                                const SecDev* secs, int npairs, double* out, const int32_t* nonfinite,
-                               int64_t* pair_nonfinite) {
+                               int64_t* pair_nonfinite, const double* carry_in, const int64_t* carry_in_counts,
+                               double* carry_out, int64_t* carry_out_counts, int64_t npts) {
   const int pr = blockIdx.x * blockDim.x + threadIdx.x;
   if (pr >= npairs) return;
   const SecDev& S = secs[pair_sector[pr]];
-  int64_t nf = 0, np = 0;
+  int64_t nf = carry_in_counts ? carry_in_counts[2 * pr] : 0, np = carry_in_counts ? carry_in_counts[2 * pr + 1] : 0;
   for (int t = pair_start[pr]; t < pair_start[pr + 1]; ++t) {
     nf += nonfinite[2 * t];
     np += nonfinite[2 * t + 1];
   }
   pair_nonfinite[2 * pr] = nf;
   pair_nonfinite[2 * pr + 1] = np;
-  const double N = (double)(1ull << S.m);
+  if (carry_out_counts) {
+    carry_out_counts[2 * pr] = nf;
+    carry_out_counts[2 * pr + 1] = np;
+  }
+  const double N = npts > 0 ? (double)npts : (double)(1ull << S.m);
   // only the sector's kf internal orders are written by the tile kernels
   const int kf = S.kf;
   double qr[KMAX], qi[KMAX];
@@ -76,10 +84,24 @@ __global__ void k_reduce_pairs(const double* partial, const int32_t* pair_start,
     qi[kk] = 0.0;
     if (kk >= kf) continue;
     double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0;
+    if (carry_in) {
+      const double* c = carry_in + ((size_t)pr * KMAX + kk) * 4;
+      hr = c[0];
+      lr = c[1];
+      hi = c[2];
+      li = c[3];
+    }
     for (int t = pair_start[pr]; t < pair_start[pr + 1]; ++t) {
       const double* p = partial + ((size_t)t * KMAX + kk) * PART_STRIDE;
       dd_add(hr, lr, p[0], p[1]);
       dd_add(hi, li, p[2], p[3]);
+    }
+    if (carry_out) {
+      double* c = carry_out + ((size_t)pr * KMAX + kk) * 4;
+      c[0] = hr;
+      c[1] = lr;
+      c[2] = hi;
+      c[3] = li;
     }
     qr[kk] = (hr + lr) / N;
     qi[kk] = (hi + li) / N;
@@ -362,9 +384,12 @@ int launch_shifts(const SecDev* secs, int nsec, int rows, int nfinal, uint64_t s
 
 int launch_reduce_pairs(const double* partial, const int32_t* pair_start, const int32_t* pair_sector,
                         const SecDev* secs, int npairs, double* out, const int32_t* nonfinite,
-                        int64_t* pair_nonfinite, hipStream_t st) {
-  k_reduce_pairs<<<dim3((npairs + 63) / 64), dim3(64), 0, st>>>(partial, pair_start, pair_sector, secs,
-                                                                npairs, out, nonfinite, pair_nonfinite);
+                        int64_t* pair_nonfinite, const double* carry_in, const int64_t* carry_in_counts,
+                        double* carry_out, int64_t* carry_out_counts, int64_t npts, hipStream_t st) {
+  if (npairs <= 0) return 0;
+  k_reduce_pairs<<<dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, st>>>(
+      partial, pair_start, pair_sector, secs, npairs, out, nonfinite, pair_nonfinite, carry_in, carry_in_counts,
+      carry_out, carry_out_counts, npts);
   return (int)hipGetLastError();
 }
 

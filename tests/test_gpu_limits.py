@@ -192,7 +192,10 @@ def test_shapes_beyond_the_limits_are_rejected(ctx):
     cases = {
         "17 variables": Problem(sectors=[sector(n=17)], order_min=-4, order_max=0),
         "5 singular variables": Problem(sectors=[sector(ns=5)], order_min=-5, order_max=0),
-        "exponent 4": Problem(sectors=[sector(emax=4)], order_min=-4, order_max=0),
+        "exponent 8": Problem(sectors=[sector(emax=8)], order_min=-4, order_max=0),
+        "complex with exponent 4": Problem(sectors=[Sector(a=np.zeros(2), b=np.zeros(2), factors=[
+            Factor(-1.0, 1.0, np.array([1.0, -0.5]), np.array([[0, 0], [4, 1]], dtype=np.uint8))],
+            deform_factor=0)], order_min=0, order_max=0, complex_mode=True, lam=0.1),
         "5 factors": Problem(sectors=[sector(nfac=5)], order_min=-4, order_max=0),
         "9 orders": Problem(sectors=[base], order_min=-4, order_max=4),
         "complex with 9 variables": Problem(sectors=[Sector(a=np.zeros(9), b=np.zeros(9), factors=[

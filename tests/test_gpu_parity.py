@@ -41,7 +41,7 @@ def ctx():
 
 def set_params(ctx, **kw):
     base = dict(lattice_log2=10, shifts=4, seed=1, baker=1, warmup=0, warmup_log2=10, nbins=32,
-                tile_log2=14, ppt=0, graph=1, sampler=0, budget=0)
+                tile_log2=14, ppt=0, graph=1, sampler=0, budget=0, slice_log2=0)
     base.update(kw)
     for k, v in base.items():
         P.sdi_set_param(ctx, k, v)
