@@ -25,6 +25,9 @@ What it computes (paper: FIESTA 4, arXiv:1511.03614):
 * ``flow``       - the learned importance-sampling map (sampling, log q,
   gradient, Adam, training loss weights).
 * ``expr``       - integrands in the workers' text format (section 4.6).
+* ``cubature``   - globally adaptive deterministic cubature (the Cuhre
+  option of CurrentIntegrator, section 4.4): the Genz-Malik degree-7/5 rule
+  pair on dyadic regions, split along the largest fourth difference.
 
 Where the paper is silent, each function's docstring states the reading it
 takes and names the passage it follows.
@@ -51,6 +54,11 @@ Pins (each function checked against something other than itself; tests in
   against a direct scan of the candidates, small lambda never failing;
 * flow: finite-difference gradients, invertibility, unit mean weight,
   torch's Adam, convergence to the chi^2-optimal density;
-* expr: hand-evaluated expressions and closed-form integrals.
+* expr: hand-evaluated expressions and closed-form integrals;
+* cubature: the rule pair's degrees (every monomial of degree <= 7 exact,
+  degree 5 exactly for the embedded rule), polynomials on dyadic boxes of a
+  sector, the split axis of one-axis integrands, the dyadic tiling, one split
+  per round taking the largest priority, and whole runs against the bubble's
+  and the section 4.3 box's closed forms.
 """
 from . import integrand, points, prefactor, vegas, integrate  # noqa: F401
