@@ -299,7 +299,7 @@ def strict_json(v):
 def _set(P, ctx, **kw):
     base = dict(lattice_log2=12, shifts=16, seed=1, baker=1, warmup=0, graph=1, sampler=0, budget=0, ppt=0,
                 tile_log2=0, pilot_log2=12, alloc_min_log2=12, alloc_max_log2=20, warmup_log2=14, nbins=128,
-                small_x=0)
+                small_x=0, slice_log2=0, integrator=0)
     base.update(kw)
     for k, v in base.items():
         P.sdi_set_param(ctx, k, v)
@@ -641,6 +641,49 @@ def seed_study(P, ctx, name, problem, lambda_max=None, m_pilot=11, share=0.9, ma
         P.sdi_problem_destroy(h)
 
 
+def cubature_entry(P, ctx, name, problem, maxeval, steps=3, split_frac=0.25, batch_min=1024):
+    """The adaptive deterministic cubature (integrator 1) on a workload: the rule
+    kernel's rate and roofline (algorithmic flops of the evaluations it made,
+    the same per-evaluation count as the lattice kernels' per-corner form),
+    the whole call's rate (host bookkeeping of the regions included), regions,
+    rounds and error estimates; plain lattice QMC with about as many
+    evaluations beside it (16 shifts)."""
+    import numpy as np
+    ns = len(problem.sectors)
+    h = P.sdi_problem_create(ctx, problem)
+    try:
+        _set(P, ctx, integrator=1)
+        for k, v in dict(cub_maxeval=maxeval, cub_epsrel=1e-12, cub_epsabs=0.0, cub_split_frac=split_frac,
+                         cub_batch_min=batch_min).items():
+            P.sdi_set_param(ctx, k, v)
+        P.sdi_integrate(ctx, h)
+        runs = [P.sdi_integrate(ctx, h) for _ in range(steps)]
+        r = runs[-1]
+        nev = [P.sdi_sector_results(ctx, h, s, 16)[3] for s in range(ns)]
+        lead = P._prefactor_of(problem)[0]
+        fl, _ = launch_work(problem, nev, lead, False, False)
+        ms_k = float(np.mean([x["ms_eval_kernel"] for x in runs]))
+        ms_t = float(np.mean([x["ms_total"] for x in runs]))
+        achieved = fl / (ms_k * 1e-3) / 1e12
+        m = max(4, int(round(np.log2(max(1.0, r["n_evals"] / (16.0 * ns))))))
+        _set(P, ctx, lattice_log2=m, shifts=16)
+        P.sdi_integrate(ctx, h)
+        lat = P.sdi_integrate(ctx, h)
+        return {"workload": name, "maxeval": maxeval, "evals": int(r["n_evals"]), "regions": int(r["cub_regions"]),
+                "rounds": int(r["cub_rounds"]), "ms_rule_kernels": ms_k, "ms_total": ms_t,
+                "evals_per_s_kernels": r["n_evals"] / (ms_k * 1e-3), "evals_per_s_total": r["n_evals"] / (ms_t * 1e-3),
+                "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                             "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                             "kernel": "k_cubature (all rounds)"},
+                "orders": list(range(problem.order_min, problem.order_max + 1)),
+                "value_re": r["value"].real.tolist(), "err_estimate": (r["err_re"] + r["err_im"]).tolist(),
+                "lattice_same_evals": {"lattice_log2": m, "evals": int(lat["n_evals"]), "ms_total": lat["ms_total"],
+                                       "value_re": lat["value"].real.tolist(), "err_re": lat["err_re"].tolist()}}
+    finally:
+        P.sdi_problem_destroy(h)
+        _set(P, ctx)
+
+
 def text_integrand_rate(P, ctx, steps: int = 5):
     """Throughput of the text path (sdi_problem_from_text) on an integrand of the
     size class the paper's database holds (~200 KB of text): 3000 signed terms of
@@ -930,6 +973,9 @@ def main() -> int:
         extra["bubble"]["note"] = "latency-dominated (2 sectors, 1 variable): ms_per_step is the figure, not evals/s"
         out["configs"] = extra
         out["text_integrand"] = text_integrand_rate(P, ctx)
+        out["cubature"] = [cubature_entry(P, ctx, "synthetic64", sectorgen.config2(), 1 << 24),
+                           cubature_entry(P, ctx, "doublebox (Euclidean, 282 sectors)",
+                                          double_box_problem(-3.0, -1.0, 0.0, order_max=0), 1 << 24)]
         out["endpoint_precision"] = endpoint_precision_cost(P, ctx, sectorgen.config2())
     if not args.no_equal_time:
         lat = [dict(lattice_log2=m) for m in range(10, 17)]

@@ -113,6 +113,28 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *                  SmallX / MPThreshold switch to MPFR of section 4.6.  The
  *                  warm-up, flow-sampled points, complex mode and text
  *                  integrands stay in fp64.  0 = off         (default 0)
+ *   integrator     the final-stage integrator (CurrentIntegrator of section
+ *                  4.4): 0 = shifted lattice QMC with optional Vegas grids;
+ *                  1 = globally adaptive deterministic cubature, the role of
+ *                  cuhreCuba: the Genz-Malik degree-7 rule with its embedded
+ *                  degree-5 rule on dyadic regions of every sector cube,
+ *                  rounds that halve the regions of largest weighted error
+ *                  (one launch applies the rule pair to all new regions),
+ *                  each along its largest fourth difference; errors are the
+ *                  summed rule differences (not standard deviations).  It
+ *                  takes sector problems (real or complex mode), not text
+ *                  integrands, and no budget, warmup, sampler or slice_log2
+ *                  (SDI_ENOTSUP); the workspace argument is not used.
+ *                                                               (default 0)
+ *   cub_maxeval    cubature: integrand evaluations over all sectors; below one
+ *                  rule application per sector SDI_EINVAL    (default 2^24)
+ *   cub_epsrel, cub_epsabs   cubature: tolerance per order
+ *                  max(epsabs, epsrel |value|), numbers in [0, 1]
+ *                                                     (default 1e-6, 0)
+ *   cub_split_frac cubature: share of the live regions halved per round, in
+ *                  (0, 1]                                    (default 0.25)
+ *   cub_batch_min  cubature: regions halved per round at least, while there
+ *                  are as many (1..2^24)                     (default 1024)
  * Unknown keys or malformed values return SDI_EINVAL. */
 int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value);
 int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len);
@@ -180,6 +202,43 @@ typedef struct {
  * mode; exponents of the deformation polynomial's monomial times P_F above 7;
  * more than 8 variables in complex mode). */
 int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* desc, sdi_problem** out);
+
+/* A Feynman integral by its Symanzik polynomials: SDEvaluate[{U, F, l},
+ * indices, order] of section 4.3.  Eq. (2): prod_j x_j^(a_j - 1)
+ * U^(A - (l+1) d/2) / F^(A - l d/2) over the simplex, A = sum_j a_j,
+ * d = d0 - 2 eps, times exp(l gamma_E eps) Gamma(A - l d/2) / prod_j
+ * Gamma(a_j).  The library forms the primary sectors (x_k = 1) and decomposes
+ * each until U and F have constant terms after their monomials are taken out
+ * (iterated decomposition with the smallest vanishing set of variables, the
+ * classic strategy S of STRATEGY, section 4.4); result orders run from the
+ * leading pole (the prefactor's lead minus the most singular variables of any
+ * sector) to `order`.  The polynomials are host arrays owned by the caller
+ * (terms in any order; equal exponent rows are merged). */
+typedef struct {
+  int32_t nvars;              /* n Feynman parameters, 2..17 (sectors get n - 1)   */
+  int32_t loops;              /* l, 1..8                                            */
+  int32_t d0;                 /* d = d0 - 2 eps, 1..12                              */
+  int32_t order;              /* highest result order (at most 8 orders in all)     */
+  const int32_t* indices;     /* [n] propagator powers a_j, 1..8                    */
+  int32_t u_nterms, f_nterms;
+  const double* u_coef;       /* [u_nterms]                                         */
+  const uint8_t* u_exps;      /* [u_nterms][n]                                      */
+  const double* f_coef;       /* [f_nterms]                                         */
+  const uint8_t* f_exps;      /* [f_nterms][n]                                      */
+  int32_t complex_mode;       /* 1: contour deformation along the sector's F        */
+  int32_t reserved;           /* must be 0                                          */
+  double lambda;              /* deformation size (complex mode)                    */
+} sdi_feynman_desc;
+
+/* Compile the sectors of a Feynman integral (see sdi_feynman_desc).  Returns
+ * SDI_EINVAL for malformed input or an order outside the 8 orders from the
+ * leading pole, SDI_ENOTSUP where a sector exponent a_j < -1 appears (that
+ * needs higher-order subtraction) or a decomposed sector leaves the library's
+ * limits (sdi_problem_create). */
+int sdi_problem_from_feynman(sdi_ctx* ctx, const sdi_feynman_desc* desc, sdi_problem** out);
+/* The same decomposition on the host only (no context, no device): the
+ * number of sectors, the lowest result order and the variables per sector. */
+int sdi_feynman_sectors(const sdi_feynman_desc* desc, int32_t* nsectors, int32_t* order_min, int32_t* max_vars);
 
 /* An integrand given as text in the integration workers' input format
  * (section 4.6, CIntegrate options; the text that follows the Integrate
@@ -256,6 +315,9 @@ typedef struct {
                                    final pass (budget allocation; 0 without)           */
   int64_t lattice_done;         /* lattice points per shift the estimates rest on: 2^m,
                                    or under slice_log2 the points done so far          */
+  int64_t cub_regions;          /* cubature: regions the estimates sum over            */
+  int32_t cub_rounds;           /* cubature: rule launches (rounds of halving + 1)     */
+  int32_t cub_converged;        /* cubature: 1 if every order met its tolerance        */
 } sdi_result;
 
 /* Bytes of device workspace sdi_integrate needs under the current parameters. */
@@ -270,6 +332,16 @@ size_t sdi_workspace_bytes(sdi_ctx* ctx, const sdi_problem* prob);
  * value was not finite. */
 int sdi_integrate(sdi_ctx* ctx, sdi_problem* prob, void* dev_workspace, size_t ws_bytes,
                   sdi_result* out);
+
+/* Regions of the last cubature run on prob (integrator 1), in creation order:
+ * per region its sector, per caller variable the halvings level[r][16] and
+ * index[r][16] (the region is [index 2^-level, (index + 1) 2^-level] along
+ * that variable), value[r][norders][2] (its degree-7 integral),
+ * error[r][norders][2] (|degree 7 - degree 5|, re and im apart) and the axis
+ * it would be halved along.  Host arrays of cap regions (each may be NULL);
+ * *nregions receives the total.  SDI_ESTATE without such a run. */
+int sdi_cubature_regions(sdi_ctx* ctx, const sdi_problem* prob, int64_t cap, int64_t* nregions, int32_t* sector,
+                         uint8_t* level, uint32_t* index, double* value, double* error, int32_t* axis);
 
 /* Checkpoints of a resumable pass (slice_log2 > 0; the -continue option and the
  * saved partial results of sections 2.5 and 4.5): the per-(sector, shift)

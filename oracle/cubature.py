@@ -33,23 +33,35 @@ Readings where the published method leaves a choice (the same in the library):
   errors are not independent random errors).
 * Tolerance per order: tau_k = max(epsabs, epsrel |T_k|), T_k the current
   total; order weights omega_k = 1/tau_k (1 where tau_k = 0).
+* Roundoff: the rule difference and the fourth differences are differences of
+  nearly equal sums once a region is resolved, so below some size they are
+  rounding noise.  Unit u = 2^-52; a region's rounding scale for order k is
+  sigma_k = vol u sum_p (|w7_p| + |w5_p|) |F_k(x_p)|_1 (|z|_1 = |Re z| +
+  |Im z|); order k of the region counts as converged when its error
+  e_k = e_re + e_im is at most 2^20 sigma_k.
 * Split axis: the fourth divided difference along each axis,
   Delta_j = (F(c + l2 h_j e_j) + F(c - l2 h_j e_j) - 2F(c))
             - (l2^2/l3^2) (F(c + l3 h_j e_j) + F(c - l3 h_j e_j) - 2F(c)),
-  measured as D_j = max_k omega_k (|Re Delta_jk| + |Im Delta_jk|) with the
-  weights of the round in which the region is evaluated; the region is halved
-  along the axis with the largest D_j (the lowest index among equals).
-* Region priority: max_k omega_k (e_re + e_im)_k with the weights of the
-  current totals.
+  measured as D_j = max_k omega_k |Delta_jk|_1 with the weights of the round
+  in which the region is evaluated; the region is halved along the lowest axis
+  whose D_j is within 2^20 nu of the largest, nu = u max_k omega_k max_p
+  |F_k(x_p)|_1 over the centre and the 4n axis nodes (differences below that
+  are noise; a NaN counts as infinite).
+* Region priority: max_k omega_k e_k over the orders not converged (0 if
+  all are: the region is never halved), with the weights of the current
+  totals.
 * Batches: a round halves the B regions of highest priority (equal
   priorities: the older region first), B = max(ceil(split_frac |alive|),
   min(|alive|, batch_min)), cut to the longest prefix whose children fit in
   maxeval; it stops when every order meets its tolerance, when nothing fits,
   or when no region can be split (zero priority, or 30 halvings of its axis).
-* Decisions in reduced precision: priorities and the D_j are compared after
-  rounding away the 12 lowest of the 52 stored mantissa bits (``q40``), so
-  that rounding differences of a few ulps between implementations cannot
-  reorder them.
+* Priorities are compared at 8 significant bits (``coarse``; equal ones: the
+  older region first).  Sectors that are equal up to the order of their terms
+  (the symmetries of a diagram) give regions whose errors are equal up to
+  rounding noise of relative size sigma/e <= 2^-20; at 8 bits such twins
+  still compare equal (unless they straddle a rounding boundary, a chance of
+  about 2^-12 per pair at the noise threshold and far less above it), so
+  their order does not depend on the summation order.
 * Regions are dyadic: per variable a level d and an index k, the interval
   [k 2^-d, (k+1) 2^-d]; ids in creation order (sector order first, then each
   round's children, lower half before upper half, in selection order).
@@ -66,6 +78,8 @@ import numpy as np
 from . import integrate
 
 MAX_LEVEL = 30
+U = 2.0 ** -52          # unit roundoff of the rounding scales
+NOISE = 2.0 ** 20       # rule differences within NOISE units of roundoff are noise
 
 
 def lambdas():
@@ -113,13 +127,13 @@ def npoints(n: int) -> int:
     return 1 + 4 * n + 2 * n * (n - 1) + (1 << n)
 
 
-def q40(v: float) -> float:
-    """v >= 0 with the 12 lowest stored mantissa bits rounded away (half up);
-    NaN and infinity give infinity."""
+def coarse(v: float) -> float:
+    """v >= 0 rounded to 8 significant bits (the 45 lowest of the 52 stored
+    mantissa bits rounded away, half up); NaN and infinity give infinity."""
     if not math.isfinite(v) or v <= 0.0:
         return v if math.isfinite(v) else math.inf
     b = np.array([v], dtype=np.float64).view(np.uint64)[0]
-    b = (int(b) + (1 << 11)) & ~((1 << 12) - 1)
+    b = (int(b) + (1 << 44)) & ~((1 << 45) - 1)
     return float(np.array([b], dtype=np.uint64).view(np.float64)[0])
 
 
@@ -131,6 +145,7 @@ class Region:
     value: np.ndarray = None   # (K,) complex: vol * S7
     err_re: np.ndarray = None  # (K,)
     err_im: np.ndarray = None
+    sigma: np.ndarray = None   # (K,) rounding scale
     axis: int = 0
     nonfinite: int = 0
     alive: bool = True
@@ -164,17 +179,32 @@ def apply_rule(problem, region: Region, pref_lead: int, pref, omega: np.ndarray)
     region.err_re = vol * np.abs(d.real)
     region.err_im = vol * np.abs(d.imag)
     region.nonfinite = int(np.sum(~np.all(np.isfinite(vals), axis=0)))
+    l1 = np.abs(vals.real) + np.abs(vals.imag)                                  # (K, P)
+    region.sigma = vol * U * np.array([math.fsum(l1[k] * (np.abs(a7) + np.abs(a5))) for k in range(K)])
     f0 = vals[:, 0]
     r = 1.0 / 7.0                                   # l2^2 / l3^2
-    best, region.axis = -1.0, 0
+    D = np.zeros(n)
     for j in range(n):
         fp2, fm2 = vals[:, 1 + 2 * j], vals[:, 2 + 2 * j]
         fp3, fm3 = vals[:, 1 + 2 * n + 2 * j], vals[:, 2 + 2 * n + 2 * j]
         delta = (fp2 + fm2 - 2.0 * f0) - r * (fp3 + fm3 - 2.0 * f0)
-        dj = q40(float(np.max(omega * (np.abs(delta.real) + np.abs(delta.imag)))))
-        if dj > best:
-            best, region.axis = dj, j
+        d = omega * (np.abs(delta.real) + np.abs(delta.imag))
+        D[j] = math.inf if np.any(np.isnan(d)) else float(np.max(d))
+    nu = U * float(np.max(omega[:, None] * l1[:, :1 + 4 * n]))
+    tol = NOISE * nu if math.isfinite(nu) else 0.0
+    top = float(np.max(D))
+    region.axis = int(np.flatnonzero(D >= top - tol)[0])
     return region
+
+
+def priority(region: Region, omega: np.ndarray) -> float:
+    """max_k omega_k e_k over the orders not converged (at 8 significant bits; 0: none)."""
+    e = region.err_re + region.err_im
+    live = ~(e <= NOISE * region.sigma)
+    v = omega * e
+    if np.any(np.isnan(v[live])):
+        return math.inf
+    return coarse(float(np.max(v[live]))) if np.any(live) else 0.0
 
 
 def order_weights(total: np.ndarray, epsrel: float, epsabs: float):
@@ -224,7 +254,7 @@ def cubature(problem, maxeval: int, epsrel: float, epsabs: float, split_frac: fl
         for i, r in enumerate(regs):
             if not r.alive or r.level[r.axis] >= MAX_LEVEL:
                 continue
-            p = q40(float(np.max(omega * (r.err_re + r.err_im))))
+            p = priority(r, omega)
             if p > 0.0:
                 cand.append((-p, i))
         cand.sort()

@@ -21,12 +21,12 @@ __all__ = [
     "SdiError", "load_library", "library_path", "declared_functions",
     "sdi_ctx_create", "sdi_ctx_destroy", "sdi_last_error", "sdi_device_info",
     "sdi_set_param", "sdi_get_param", "sdi_tune_save", "sdi_tune_load", "sdi_prefactor_feynman", "sdi_lattice_vector",
-    "sdi_problem_create", "sdi_problem_from_text", "sdi_text_info", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_workspace_bytes",
+    "sdi_problem_create", "sdi_problem_from_text", "sdi_problem_from_feynman", "sdi_feynman_sectors", "sdi_text_info", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_workspace_bytes",
     "sdi_integrate", "sdi_sector_results", "sdi_evaluate", "sdi_sample_points",
     "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
     "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_flow_set_active", "sdi_flow_validate",
     "sdi_tune_deformation", "sdi_problem_nvars", "sdi_vegas_refit", "sdi_flow_weights",
-    "sdi_sample_points_noalloc", "sdi_checkpoint_export", "sdi_checkpoint_import",
+    "sdi_sample_points_noalloc", "sdi_checkpoint_export", "sdi_checkpoint_import", "sdi_cubature_regions",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,6 +54,14 @@ class SectorDesc(C.Structure):
                 ("term_coef", C.POINTER(C.c_double)), ("term_exps", C.POINTER(C.c_uint8))]
 
 
+class FeynmanDesc(C.Structure):
+    _fields_ = [("nvars", C.c_int32), ("loops", C.c_int32), ("d0", C.c_int32), ("order", C.c_int32),
+                ("indices", C.POINTER(C.c_int32)), ("u_nterms", C.c_int32), ("f_nterms", C.c_int32),
+                ("u_coef", C.POINTER(C.c_double)), ("u_exps", C.POINTER(C.c_uint8)),
+                ("f_coef", C.POINTER(C.c_double)), ("f_exps", C.POINTER(C.c_uint8)),
+                ("complex_mode", C.c_int32), ("reserved", C.c_int32), ("lam", C.c_double)]
+
+
 class ProblemDesc(C.Structure):
     _fields_ = [("nsectors", C.c_int32), ("sectors", C.POINTER(SectorDesc)),
                 ("order_min", C.c_int32), ("order_max", C.c_int32),
@@ -70,7 +78,8 @@ class Result(C.Structure):
                 ("ms_sample_eval_reduce", C.c_double), ("ms_refit", C.c_double), ("ms_total", C.c_double),
                 ("ms_eval_kernel", C.c_double), ("points_per_thread", C.c_int32), ("blocks", C.c_int32),
                 ("tile_log2", C.c_int32), ("waves_per_simd", C.c_int32), ("grouped", C.c_int32),
-                ("ms_pilot_kernel", C.c_double), ("pilot_same_kernel", C.c_int32), ("lattice_done", C.c_int64)]
+                ("ms_pilot_kernel", C.c_double), ("pilot_same_kernel", C.c_int32), ("lattice_done", C.c_int64),
+                ("cub_regions", C.c_int64), ("cub_rounds", C.c_int32), ("cub_converged", C.c_int32)]
 
 
 def library_path() -> str:
@@ -110,6 +119,9 @@ def load_library():
         "sdi_lattice_vector": (C.c_int, [i32, i32, C.POINTER(C.c_uint32)]),
         "sdi_problem_create": (C.c_int, [vp, C.POINTER(ProblemDesc), C.POINTER(vp)]),
         "sdi_problem_from_text": (C.c_int, [vp, C.c_char_p, C.POINTER(vp)]),
+        "sdi_problem_from_feynman": (C.c_int, [vp, C.POINTER(FeynmanDesc), C.POINTER(vp)]),
+        "sdi_feynman_sectors": (C.c_int, [C.POINTER(FeynmanDesc), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32)]),
         "sdi_text_info": (C.c_int, [C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                     C.c_char_p, C.c_size_t]),
         "sdi_problem_destroy": (None, [vp]),
@@ -119,6 +131,7 @@ def load_library():
         "sdi_sample_points_noalloc": (C.c_int, [vp, vp, i32, i32, i64, i64, vp, vp]),
         "sdi_checkpoint_export": (C.c_int, [vp, vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]),
         "sdi_checkpoint_import": (C.c_int, [vp, vp, vp, C.c_size_t]),
+        "sdi_cubature_regions": (C.c_int, [vp, vp, i64, C.POINTER(C.c_int64), vp, vp, vp, vp, vp, vp]),
         "sdi_vegas_refit": (C.c_int, [vp, i32, i32, i32, vp, vp, C.c_double]),
         "sdi_flow_weights": (C.c_int, [vp, i64, i32, vp, vp, dp, vp]),
         "sdi_workspace_bytes": (C.c_size_t, [vp, vp]),
@@ -296,6 +309,47 @@ def sdi_problem_create(ctx, problem):
     return h
 
 
+def _feynman_desc(U: dict, F: dict, loops: int, indices, order: int, d0: int, complex_mode: bool, lam: float):
+    """Descriptor of SDEvaluate[{U, F, l}, indices, order]; U and F as {exponent tuple: coefficient}."""
+    n = len(indices)
+    keep = []
+
+    def arrays(p):
+        coef = np.ascontiguousarray([float(c) for c in p.values()], dtype=np.float64)
+        exps = np.ascontiguousarray(np.array(list(p.keys()), dtype=np.uint8).reshape(len(p), n))
+        keep.extend([coef, exps])
+        return len(p), _dptr(coef), exps.ctypes.data_as(C.POINTER(C.c_uint8))
+
+    idx = np.ascontiguousarray(indices, dtype=np.int32)
+    keep.append(idx)
+    un, uc, ue = arrays(U)
+    fn, fc, fe = arrays(F)
+    d = FeynmanDesc(n, loops, d0, order, idx.ctypes.data_as(C.POINTER(C.c_int32)), un, fn, uc, ue, fc, fe,
+                    int(complex_mode), 0, float(lam))
+    return d, keep
+
+
+def sdi_problem_from_feynman(ctx, U: dict, F: dict, loops: int, indices, order: int, d0: int = 4,
+                             complex_mode: bool = False, lam: float = 0.0):
+    """Compile a Feynman integral from its Symanzik polynomials (the library decomposes it)."""
+    d, keep = _feynman_desc(U, F, loops, indices, order, d0, complex_mode, lam)
+    h = C.c_void_p()
+    _check(load_library().sdi_problem_from_feynman(ctx, C.byref(d), C.byref(h)), ctx)
+    del keep
+    return h
+
+
+def sdi_feynman_sectors(U: dict, F: dict, loops: int, indices, d0: int = 4):
+    """(sectors, lowest result order, variables per sector) of the decomposition, host only."""
+    d, keep = _feynman_desc(U, F, loops, indices, 0, d0, False, 0.0)
+    ns, om, nv = C.c_int32(), C.c_int32(), C.c_int32()
+    rc = load_library().sdi_feynman_sectors(C.byref(d), C.byref(ns), C.byref(om), C.byref(nv))
+    if rc != 0:
+        raise SdiError(rc, "feynman decomposition failed")
+    del keep
+    return ns.value, om.value, nv.value
+
+
 def sdi_problem_from_text(ctx, text: str):
     """Compile an integrand in the workers' text format (one sector, one order)."""
     h = C.c_void_p()
@@ -342,7 +396,7 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
     """Run the integrator; `workspace` is an optional torch uint8 cuda tensor."""
     K = sdi_problem_norders(prob)
     arrs = [np.zeros(K) for _ in range(4)]
-    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, 0.0, 0, 0)
+    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, 0.0, 0, 0, 0, 0, 0)
     ptr, nbytes = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()), workspace.numel())
     if workspace is not None:
         import torch
@@ -354,7 +408,8 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
             "ms_warmup": res.ms_refit, "ms_total": res.ms_total, "ms_eval_kernel": res.ms_eval_kernel,
             "ppt": res.points_per_thread, "blocks": res.blocks, "tile_log2": res.tile_log2,
             "waves_per_simd": res.waves_per_simd, "grouped": res.grouped, "ms_pilot_kernel": res.ms_pilot_kernel,
-            "pilot_same_kernel": res.pilot_same_kernel, "lattice_done": res.lattice_done}
+            "pilot_same_kernel": res.pilot_same_kernel, "lattice_done": res.lattice_done,
+            "cub_regions": res.cub_regions, "cub_rounds": res.cub_rounds, "cub_converged": res.cub_converged}
 
 
 def sdi_sector_results(ctx, prob, s: int, nshifts: int):
@@ -435,6 +490,25 @@ def sdi_sample_points_noalloc(ctx, prob, s: int, shift: int, i0: int, x, w=None)
     _check(load_library().sdi_sample_points_noalloc(ctx, prob, s, shift, i0, x.shape[0], C.c_void_p(x.data_ptr()),
                                                     C.c_void_p(w.data_ptr()) if w is not None else None), ctx)
     return x, w
+
+
+def sdi_cubature_regions(ctx, prob) -> dict:
+    """Regions of the last cubature run (sector, level, index, value, error, axis)."""
+    lib = load_library()
+    n = C.c_int64(0)
+    _check(lib.sdi_cubature_regions(ctx, prob, 0, C.byref(n), None, None, None, None, None, None), ctx)
+    K = sdi_problem_norders(prob)
+    N = n.value
+    sec = np.zeros(N, np.int32)
+    lev = np.zeros((N, 16), np.uint8)
+    idx = np.zeros((N, 16), np.uint32)
+    val = np.zeros((N, K, 2))
+    err = np.zeros((N, K, 2))
+    axis = np.zeros(N, np.int32)
+    _check(lib.sdi_cubature_regions(ctx, prob, N, C.byref(n), sec.ctypes.data, lev.ctypes.data, idx.ctypes.data,
+                                    val.ctypes.data, err.ctypes.data, axis.ctypes.data), ctx)
+    return {"sector": sec, "level": lev, "index": idx, "value": val[..., 0] + 1j * val[..., 1],
+            "err_re": err[..., 0], "err_im": err[..., 1], "axis": axis}
 
 
 def sdi_checkpoint_export(ctx, prob) -> bytes:

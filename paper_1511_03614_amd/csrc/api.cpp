@@ -111,13 +111,21 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
     else return fail(ctx, SDI_EINVAL, "tune must be off, cached or search");
     return SDI_OK;
   }
-  if (k == "small_x") {
+  if (k == "small_x" || k == "cub_epsrel" || k == "cub_epsabs" || k == "cub_split_frac") {
     char* e = nullptr;
     errno = 0;
     const double d = strtod(value, &e);
-    if (errno || !e || *e != '\0' || e == value || !(d >= 0.0 && d <= 1.0))
-      return fail(ctx, SDI_EINVAL, "small_x must be a number in [0, 1]");
-    p.small_x = d;
+    if (errno || !e || *e != '\0' || e == value) return fail(ctx, SDI_EINVAL, k + " must be a number");
+    if (k == "small_x") {
+      if (!(d >= 0.0 && d <= 1.0)) return fail(ctx, SDI_EINVAL, "small_x must be a number in [0, 1]");
+      p.small_x = d;
+    } else if (k == "cub_split_frac") {
+      if (!(d > 0.0 && d <= 1.0)) return fail(ctx, SDI_EINVAL, "cub_split_frac must be in (0, 1]");
+      p.cub_split_frac = d;
+    } else {
+      if (!(d >= 0.0 && d <= 1.0)) return fail(ctx, SDI_EINVAL, k + " must be in [0, 1]");
+      (k == "cub_epsrel" ? p.cub_epsrel : p.cub_epsabs) = d;
+    }
     return SDI_OK;
   }
   char* end = nullptr;
@@ -157,6 +165,15 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
   } else if (k == "slice_log2") {
     if (!range(0, 30)) return fail(ctx, SDI_EINVAL, "slice_log2 must be in 0..30");
     p.slice_log2 = (int)iv;
+  } else if (k == "integrator") {
+    if (!range(0, 1)) return fail(ctx, SDI_EINVAL, "integrator must be 0 (lattice) or 1 (cubature)");
+    p.integrator = (int)iv;
+  } else if (k == "cub_maxeval") {
+    if (!range(1, (long long)1 << 40)) return fail(ctx, SDI_EINVAL, "cub_maxeval must be in 1..2^40");
+    p.cub_maxeval = iv;
+  } else if (k == "cub_batch_min") {
+    if (!range(1, 1 << 24)) return fail(ctx, SDI_EINVAL, "cub_batch_min must be in 1..2^24");
+    p.cub_batch_min = (int)iv;
   } else if (k == "budget") {
     if (!range(0, (long long)1 << 40)) return fail(ctx, SDI_EINVAL, "budget must be in 0..2^40");
     p.budget = iv;
@@ -186,8 +203,9 @@ int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len) {
   if (k == "tune") {
     snprintf(buf, len, "%s", p.tune == 0 ? "off" : (p.tune == 1 ? "cached" : "search"));
     return SDI_OK;
-  } else if (k == "small_x") {
-    snprintf(buf, len, "%.17g", p.small_x);
+  } else if (k == "small_x" || k == "cub_epsrel" || k == "cub_epsabs" || k == "cub_split_frac") {
+    snprintf(buf, len, "%.17g",
+             k == "small_x" ? p.small_x : (k == "cub_epsrel" ? p.cub_epsrel : (k == "cub_epsabs" ? p.cub_epsabs : p.cub_split_frac)));
     return SDI_OK;
   } else if (k == "lattice_log2") v = p.m;
   else if (k == "shifts") v = p.R;
@@ -201,6 +219,9 @@ int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len) {
   else if (k == "graph") v = p.graph;
   else if (k == "budget") v = p.budget;
   else if (k == "slice_log2") v = p.slice_log2;
+  else if (k == "integrator") v = p.integrator;
+  else if (k == "cub_maxeval") v = p.cub_maxeval;
+  else if (k == "cub_batch_min") v = p.cub_batch_min;
   else if (k == "alloc_min_log2") v = p.alloc_min;
   else if (k == "alloc_max_log2") v = p.alloc_max;
   else if (k == "pilot_log2") v = p.pilot_log2;
@@ -515,6 +536,7 @@ void sdi_problem_destroy(sdi_problem* pb) {
   if (pb->d_dir) (void)hipFree(pb->d_dir);
   if (pb->d_expr) (void)hipFree(pb->d_expr);
   delete pb->flow;
+  delete pb->cub;
   delete pb;
 }
 

@@ -58,6 +58,12 @@ struct Params {
   int sampler = 0;       // 0: lattice (+ Vegas grid), 1: the learned flow
   double small_x = 0.0;  // real mode: double-double below this smallest singular coordinate (0: off)
   int slice_log2 = 0;    // > 0: a call processes the next 2^slice_log2 lattice points per shift (resumable)
+  int integrator = 0;    // 0: lattice QMC, 1: adaptive deterministic cubature
+  int64_t cub_maxeval = 1 << 24;  // cubature: evaluation budget over all sectors
+  double cub_epsrel = 1e-6;       // cubature: relative tolerance per order
+  double cub_epsabs = 0.0;        // cubature: absolute tolerance per order
+  double cub_split_frac = 0.25;   // cubature: share of the live regions halved per round
+  int cub_batch_min = 1024;       // cubature: regions halved per round at least (while there are as many)
 };
 
 // One autotuner decision: final-pass tile size and launch variant
@@ -115,6 +121,23 @@ struct FlowState {
   ~FlowState();
 };
 int fail(sdi_ctx* ctx, int code, const std::string& msg);
+
+// Regions of the adaptive cubature (dyadic boxes per sector, in creation
+// order) and their rule results; device buffers of a round.
+struct CubState {
+  std::vector<int32_t> sector;
+  std::vector<uint8_t> level;     // [r][MAXV] halvings per caller variable
+  std::vector<uint32_t> index;    // [r][MAXV]
+  std::vector<double> val, err;   // [r][K][2]
+  std::vector<double> sig;        // [r][K] rounding scale
+  std::vector<int32_t> axis;      // caller variable to halve
+  std::vector<int32_t> count;     // [r][2] non-finite nodes, Im F > 0 nodes
+  std::vector<uint8_t> alive;     // not yet halved
+  void* d_buf = nullptr;
+  size_t d_bytes = 0;
+  ~CubState();
+};
+int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out);
 int prefactor_series(int loops, const int32_t* idx, int nprops, int d0, int len, int* lead, double* out,
                      std::string& err);
 
@@ -175,6 +198,8 @@ struct sdi_problem {
   uint32_t* d_dir = nullptr;
   // learned sampler (created by sdi_flow_init)
   sdi::FlowState* flow = nullptr;
+  // adaptive cubature (integrator 1): regions of the last run
+  sdi::CubState* cub = nullptr;
   // integrand given as text (sdi_problem_from_text): one sector, one order
   std::vector<sdi::ExprIns> expr;
   sdi::ExprIns* d_expr = nullptr;

@@ -122,4 +122,30 @@ int launch_flow_weights(const FlowTile* tiles, int ntiles, int K, const double* 
 int launch_flow_shifts(const FlowSecDesc* fs, const FlowTile* runs, int nruns, int iters, int m, uint64_t seed,
                        uint32_t row0, uint64_t* out, hipStream_t st);
 
+// Adaptive cubature: the degree-7/degree-5 rule pair on dyadic regions (one
+// wave per region).  Region r covers [index 2^-level, (index + 1) 2^-level]
+// along every caller variable of sector reg_sector[r].
+struct CubArgs {
+  const SecDev* secs;
+  const Term* terms;
+  const CplxDev* cx;          // complex mode: per-sector deformation records, else null
+  const uint32_t* dir;
+  const int32_t* reg_sector;  // [nreg]
+  const uint8_t* reg_level;   // [nreg][MAXV], caller variable order
+  const uint32_t* reg_index;  // [nreg][MAXV]
+  const double* wtab;         // [MAXV + 1][10]: per n the degree-7 then degree-5 class weights
+  double lam[4];              // node radii l2, l3, l4, l5
+  double omega[KMAX];         // order weights of the split-axis measure
+  int64_t nreg;
+  int32_t K;
+  int32_t pad;
+  double* out_val;            // [nreg][K][2]  vol * S7
+  double* out_err;            // [nreg][K][2]  vol |Re(S7 - S5)|, vol |Im(S7 - S5)|
+  double* out_sig;            // [nreg][K]     rounding scale vol u sum_p (|w7| + |w5|) |F_k|_1
+  int32_t* out_axis;          // [nreg] caller variable to halve
+  int32_t* out_count;         // [nreg][2] nodes with a non-finite value, nodes with Im F(z) > 0
+};
+int launch_cubature_real(int nvmax, int km, const CubArgs& a, hipStream_t st);
+int launch_cubature_cplx(int nvmax, int km, const CubArgs& a, hipStream_t st);
+
 }  // namespace sdi

@@ -114,16 +114,16 @@ def test_split_axis_follows_the_fourth_difference(axis):
     assert r.axis == 0
 
 
-def test_q40_rounding():
-    assert cubature.q40(1.0) == 1.0
-    a = 1.0 + 2.0 ** -45
-    assert cubature.q40(a) == 1.0                            # below the 40-bit half step
-    assert cubature.q40(1.0 + 2.0 ** -41) == 1.0 + 2.0 ** -40      # half step rounds up
-    assert cubature.q40(1.0 + 2.0 ** -41 - 2.0 ** -52) == 1.0
-    assert cubature.q40(0.0) == 0.0 and cubature.q40(float("nan")) == math.inf
+def test_coarse_rounding():
+    assert cubature.coarse(1.0) == 1.0
+    assert cubature.coarse(1.0 + 2.0 ** -9) == 1.0                     # below the half step
+    assert cubature.coarse(1.0 + 2.0 ** -8) == 1.0 + 2.0 ** -7          # half step rounds up
+    assert cubature.coarse(1.0 + 2.0 ** -8 - 2.0 ** -40) == 1.0
+    assert cubature.coarse(255.0) == 255.0 and cubature.coarse(255.5) == 256.0
+    assert cubature.coarse(0.0) == 0.0 and cubature.coarse(float("nan")) == math.inf
     v = np.random.default_rng(1).uniform(0, 1, 1000)
-    q = np.array([cubature.q40(float(t)) for t in v])
-    assert np.all(np.abs(q - v) <= v * 2.0 ** -40)
+    q = np.array([cubature.coarse(float(t)) for t in v])
+    assert np.all(np.abs(q - v) <= v * 2.0 ** -8)
     assert np.all(np.diff(q[np.argsort(v)]) >= 0)           # monotone
 
 
@@ -200,7 +200,7 @@ def test_batches_take_the_highest_priorities():
         alive = [(i, r) for i, r in enumerate(prev.regions) if r.alive]
         total = sum(r.value for _, r in alive)
         omega, _ = cubature.order_weights(total, 1e-14, 0.0)
-        pri = [(-cubature.q40(float(np.max(omega * (r.err_re + r.err_im)))), i) for i, r in alive]
+        pri = [(-cubature.priority(r, omega), i) for i, r in alive]
         want = min(pri)[1]
         assert not cur.regions[want].alive
         assert [r.alive for i, r in enumerate(cur.regions[:len(prev.regions)]) if i != want] == \
@@ -212,3 +212,23 @@ def test_batches_take_the_highest_priorities():
         assert (a.index[p.axis], b.index[p.axis]) == (2 * p.index[p.axis], 2 * p.index[p.axis] + 1)
         assert abs(a.value + b.value - p.value).max() <= 10 * (p.err_re + p.err_im).max() + 1e-15
         prev = cur
+
+
+def test_regions_at_rounding_noise_are_not_halved():
+    """A degree-5 integrand is integrated exactly by both rules: its rule
+    difference is rounding noise, so no region is ever halved, even with a
+    zero tolerance; a degree-7 one is halved."""
+    p5 = poly_problem([1.0, 0.5, 0.25], np.array([[0, 0, 0], [2, 3, 0], [1, 1, 1]], dtype=np.uint8))
+    res = cubature.cubature(p5, maxeval=10000, epsrel=0.0, epsabs=0.0, batch_min=4)
+    assert res.rounds == 1 and not res.converged and len(res.regions) == 1
+    r = res.regions[0]
+    assert r.err_re[0] <= cubature.NOISE * r.sigma[0]
+    assert cubature.priority(r, np.ones(1)) == 0.0
+    p7 = poly_problem([1.0, 0.5], np.array([[0, 0, 0], [7, 0, 0]], dtype=np.uint8))
+    res = cubature.cubature(p7, maxeval=10000, epsrel=0.0, epsabs=0.0, batch_min=4)
+    assert res.rounds > 1 and res.regions[0].axis == 0
+    # the rounding scale is the weighted absolute mass times 2^-52
+    w7, w5 = cubature.weights(3)
+    xi, cls = cubature.nodes(3)
+    mass = sum((abs(w7[c]) + abs(w5[c])) * (1.0 + 0.5 * ((1 + x[0]) / 2) ** 7) for x, c in zip(xi, cls))
+    assert res.regions[0].sigma[0] == pytest.approx(mass * 2.0 ** -52, rel=1e-12)
