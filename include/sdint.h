@@ -152,6 +152,11 @@ int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len);
  * SDI_EINVAL if it cannot be read or is not in the format sdi_tune_save
  * writes (ctx is then unchanged).  A loaded decision is used under tune =
  * cached. */
+/* The candidates the last autotuner search timed on ctx, one line each
+ * ("tile_log2=.. ppt=.. waves=.. lists=.. ms=.."; lists = 1: per-corner term
+ * lists instead of terms grouped by singular support), empty when the last
+ * decision came from the cache.  buf NULL: *needed receives the size. */
+int sdi_tune_report(sdi_ctx* ctx, char* buf, size_t len, size_t* needed);
 int sdi_tune_save(sdi_ctx* ctx, const char* path);
 int sdi_tune_load(sdi_ctx* ctx, const char* path);
 

@@ -27,6 +27,7 @@ __all__ = [
     "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_flow_set_active", "sdi_flow_validate",
     "sdi_tune_deformation", "sdi_problem_nvars", "sdi_vegas_refit", "sdi_flow_weights",
     "sdi_sample_points_noalloc", "sdi_checkpoint_export", "sdi_checkpoint_import", "sdi_cubature_regions",
+    "sdi_tune_report",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -131,6 +132,7 @@ def load_library():
         "sdi_sample_points_noalloc": (C.c_int, [vp, vp, i32, i32, i64, i64, vp, vp]),
         "sdi_checkpoint_export": (C.c_int, [vp, vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]),
         "sdi_checkpoint_import": (C.c_int, [vp, vp, vp, C.c_size_t]),
+        "sdi_tune_report": (C.c_int, [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
         "sdi_cubature_regions": (C.c_int, [vp, vp, i64, C.POINTER(C.c_int64), vp, vp, vp, vp, vp, vp]),
         "sdi_vegas_refit": (C.c_int, [vp, i32, i32, i32, vp, vp, C.c_double]),
         "sdi_flow_weights": (C.c_int, [vp, i64, i32, vp, vp, dp, vp]),
@@ -232,6 +234,16 @@ def sdi_set_param(ctx, key: str, value):
 def sdi_get_param(ctx, key: str) -> str:
     buf = C.create_string_buffer(64)
     _check(load_library().sdi_get_param(ctx, key.encode(), buf, 64), ctx)
+    return buf.value.decode()
+
+
+def sdi_tune_report(ctx) -> str:
+    """Candidates and times of the last autotuner search (text, one line each)."""
+    lib = load_library()
+    need = C.c_size_t(0)
+    _check(lib.sdi_tune_report(ctx, None, 0, C.byref(need)), ctx)
+    buf = C.create_string_buffer(need.value)
+    _check(lib.sdi_tune_report(ctx, buf, need.value, C.byref(need)), ctx)
     return buf.value.decode()
 
 

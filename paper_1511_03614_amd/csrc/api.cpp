@@ -399,7 +399,10 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
       }
       t0 += nt;
     }
-    if (exp7) R.flags |= F_EXP7;
+    if (exp7) {
+      R.flags |= F_EXP7;
+      pb->exp7 = true;
+    }
     if (d->complex_mode) {
       // derivative lists of the full F = x^mono * P_F (internal variable order), per corner
       CplxDev X{};

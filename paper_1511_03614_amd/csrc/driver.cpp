@@ -335,6 +335,9 @@ int final_family(const sdi_problem* pb, const Params& p) {
 // where the polynomials outweigh that (measured: the 2000-sector synthetic
 // set gains, the double box with its 16 corners loses).
 constexpr int CORNER_LISTS = 100;
+// Problems with factor exponents above 3 run one generic instance (1 point per
+// thread, 4 waves per SIMD) in every mode.
+constexpr int E7_VARIANT = 14;
 
 std::vector<int> generic_variants(const sdi_problem* pb) {
   if (pb->nvmax >= 10) return {14, 23, 24};
@@ -343,6 +346,7 @@ std::vector<int> generic_variants(const sdi_problem* pb) {
 
 std::vector<int> tile_variants(const sdi_problem* pb, const Params& p) {
   if (pb->is_expr()) return {11};
+  if (pb->exp7) return {E7_VARIANT};
   if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{11, 12, 21} : std::vector<int>{11, 12};
   std::vector<int> v;
   switch (final_family(pb, p)) {
@@ -366,6 +370,7 @@ constexpr int DD_VARIANT = 12;
 // The variant used for a fixed points-per-thread request.
 int default_variant(const sdi_problem* pb, const Params& p, int ppt) {
   if (pb->is_expr()) return 11;   // one point per lane and step
+  if (pb->exp7) return E7_VARIANT;
   if (pb->complex_mode) return 10 * ppt + 1;
   switch (final_family(pb, p)) {
     case RF_G3: return ppt == 1 ? 14 : 22;
@@ -392,6 +397,7 @@ int launch_tiles(const sdi_problem* pb, int ppt, int wpe, int km, int grid, size
                  hipStream_t st, bool corner_lists = false) {
   if (pb->is_expr()) return launch_tiles_expr(grid, shmem, a, expr_args(pb), st);
   if (pb->complex_mode) return launch_tiles_cplx(pb->nvmax, ppt, wpe, km, grid, shmem, a, pb->d_cx, pb->d_dir, st);
+  if (pb->exp7) return launch_tiles_real_e7(pb->nvmax, km, grid, shmem, a, st);
   return launch_tiles_real(pb->nvmax, pb->nsmax, corner_lists ? MAXF + 1 : pb->nfmax, ppt, wpe, km, grid, shmem, a,
                            st);
 }
@@ -402,6 +408,7 @@ int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int 
   const int nf = corner_lists ? MAXF + 1 : pb->nfmax;
   int occ = pb->is_expr()                             ? tiles_expr_occupancy(mode, shmem, expr_args(pb))
             : pb->complex_mode                        ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, shmem)
+            : pb->exp7 ? occupancy_tiles_real_e7(nvmax, mode, km, mode == 0 && uses_dd(pb, ctx->params), shmem)
                                                       : tiles_real_occupancy(nvmax, pb->nsmax, nf, mode, ppt, wpe, km,
                                                                              uses_dd(pb, ctx->params), shmem);
   if (occ < 1) occ = 1;
@@ -672,6 +679,7 @@ int autotune(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
       }
   TuneChoice best{tiles.front(), fixed_variant >= 0 ? fixed_variant : default_variant(pb, prm, 1)};
   float best_ms = 1e30f;
+  ctx->tune_report.clear();
   // Coordinate search: every variant at the largest tile size, every tile size
   // with the best variant, then every variant again at the best tile size.
   std::vector<std::pair<int, std::vector<int>>> rounds;
@@ -696,6 +704,12 @@ int autotune(sdi_ctx* ctx, sdi_problem* pb, const std::vector<int>& msec, bool w
       float ms = 0.f;
       rc = time_final(ctx, pb, C, v, &ms);
       if (rc != SDI_OK) return rc;
+      {
+        char line[96];
+        snprintf(line, sizeof line, "tile_log2=%d ppt=%d waves=%d lists=%d ms=%.4f\n", tl, (v % CORNER_LISTS) / 10,
+                 v % 10, (int)(v >= CORNER_LISTS), ms);
+        ctx->tune_report += line;
+      }
       if (ms < best_ms) {
         best_ms = ms;
         best = TuneChoice{tl, v};
@@ -1305,6 +1319,15 @@ int sdi_checkpoint_import(sdi_ctx* ctx, sdi_problem* pb, const void* buf, size_t
   std::memcpy(pb->resume_counts.data(), p + pb->resume_sums.size() * 8, pb->resume_counts.size() * 8);
   pb->resume_done = h.done;
   pb->resume_key = key;
+  return SDI_OK;
+}
+
+int sdi_tune_report(sdi_ctx* ctx, char* buf, size_t len, size_t* needed) {
+  if (!ctx || !needed) return fail(ctx, SDI_EINVAL, "tune_report: null argument");
+  *needed = ctx->tune_report.size() + 1;
+  if (!buf) return SDI_OK;
+  if (len < *needed) return fail(ctx, SDI_ENOMEM, "tune_report: buffer too small");
+  std::memcpy(buf, ctx->tune_report.c_str(), *needed);
   return SDI_OK;
 }
 

@@ -293,7 +293,9 @@ constexpr int class_low() {
 // non-empty group (m, sigma) of terms with singular support sigma, the group
 // sum q at x is added to Pc[m][W] for every corner W with W & sigma == 0 (the
 // corners where those terms survive).  Pc[m][W] = P_m(x^(W)) for W < 2^ns.
-template <int NV, int PPT, int NSM, int MF>
+// E7M: 0 - exponents up to 3 only (the x^4 bit is never tested), 1 - up to 7,
+// 2 - by the sector's F_EXP7 flag (both codes in the caller).
+template <int NV, int PPT, int NSM, int MF, int E7M>
 __device__ __forceinline__ void corner_polys(CSec* S, CTerm* terms, const double (&x)[PPT][NV],
                                              double (&Pc)[MF][1 << NSM][PPT]) {
   constexpr int NC = 1 << NSM;
@@ -316,8 +318,8 @@ __device__ __forceinline__ void corner_polys(CSec* S, CTerm* terms, const double
         double q[PPT];
 #pragma unroll
         for (int p = 0; p < PPT; ++p) q[p] = 0.0;
-        if (S->flags & F_EXP7)
-          poly_acc_n<class_low<NV>(), NV, PPT, true>(terms + S->grp_off[fm][sg], S->grp_cnt[fm][sg], n, x, q);
+        if (E7M == 1 || (E7M == 2 && (S->flags & F_EXP7)))
+          poly_acc_n<class_low<NV>(), NV, PPT, E7M != 0>(terms + S->grp_off[fm][sg], S->grp_cnt[fm][sg], n, x, q);
         else
           poly_acc_n<class_low<NV>(), NV, PPT, false>(terms + S->grp_off[fm][sg], S->grp_cnt[fm][sg], n, x, q);
 #pragma unroll
@@ -369,7 +371,7 @@ __device__ __forceinline__ double mant_exp(double v, int& e) {
 }
 
 // G0 and Lambda at corner W for PPT points.
-template <int NV, int PPT>
+template <int NV, int PPT, int E7M>
 __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
                                                int W, const double (&x)[PPT][NV],
                                                double (&g0)[PPT],
@@ -387,8 +389,8 @@ __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
     for (int fm = 0; fm < MAXF; ++fm) {
       if (fm < nfac) {
         double P[PPT];
-        if (flags & F_EXP7)
-          poly_real<NV, PPT, true>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
+        if (E7M == 1 || (E7M == 2 && (flags & F_EXP7)))
+          poly_real<NV, PPT, E7M != 0>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
         else
           poly_real<NV, PPT, false>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
         const int g = S->gam_int[fm];
@@ -423,8 +425,8 @@ __device__ __forceinline__ void corner_regular(CSec* S, CTerm* terms,
     for (int fm = 0; fm < MAXF; ++fm) {
       if (fm < nfac) {
         double P[PPT];
-        if (flags & F_EXP7)
-          poly_real<NV, PPT, true>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
+        if (E7M == 1 || (E7M == 2 && (flags & F_EXP7)))
+          poly_real<NV, PPT, E7M != 0>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
         else
           poly_real<NV, PPT, false>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], x, P);
         const double gm = S->gam[fm];
@@ -528,7 +530,7 @@ __device__ __forceinline__ void add_series(double (&f)[KM], double (&c)[KM], dou
 // MF: 0 evaluates each corner's own term lists (any number of factors);
 // MF > 0 (sectors of at most MF factors) evaluates every term once by singular
 // support (corner_polys) and picks the corner's values from those sums.
-template <int NV, int PPT, int KM, bool COND, int NSM = MAXS, int MF = 0>
+template <int NV, int PPT, int KM, bool COND, int NSM = MAXS, int MF = 0, int E7M = 2>
 __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const double (&x)[PPT][NV],
                                               double (&f)[PPT][KM], double (&cnd)[PPT][KM]) {
   static_assert(NSM >= 1 && NSM <= MAXS, "singular-variable bound");
@@ -612,7 +614,7 @@ __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const doubl
 
   constexpr int MFC = MF > 0 ? MF : 1;
   double Pc[MFC][1 << NSM][PPT];
-  if constexpr (MF > 0) corner_polys<NV, PPT, NSM, MF>(S, terms, x, Pc);
+  if constexpr (MF > 0) corner_polys<NV, PPT, NSM, MF, E7M>(S, terms, x, Pc);
   const int C = 1 << ns;
   for (int W = 0; W < C; ++W) {
     double g0[PPT], lam[PPT];
@@ -621,7 +623,7 @@ __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const doubl
       select_corner<NSM, MF, PPT>(Pc, W, P);
       corner_from_polys<PPT, MF>(S, P, g0, lam);
     } else {
-      corner_regular<NV, PPT>(S, terms, W, x, g0, lam);
+      corner_regular<NV, PPT, E7M>(S, terms, W, x, g0, lam);
     }
     for (int T = W;; T = (T - 1) & W) {
       const int nt = __builtin_popcount(T);
@@ -659,11 +661,11 @@ __device__ __forceinline__ void eval_f_real_c(CSec* S, CTerm* terms, const doubl
     }
 }
 
-template <int NV, int PPT, int KM, int NSM = MAXS, int MF = 0>
+template <int NV, int PPT, int KM, int NSM = MAXS, int MF = 0, int E7M = 2>
 __device__ __forceinline__ void eval_f_real(CSec* S, CTerm* terms, const double (&x)[PPT][NV],
                                             double (&f)[PPT][KM]) {
   double unused[PPT][KM];
-  eval_f_real_c<NV, PPT, KM, false, NSM, MF>(S, terms, x, f, unused);
+  eval_f_real_c<NV, PPT, KM, false, NSM, MF, E7M>(S, terms, x, f, unused);
 }
 
 }  // namespace sdi

@@ -153,6 +153,7 @@ struct sdi_ctx {
   int ncu = 0;
   std::vector<sdi::TuneEntry> tune_cache;
   void* scratch = nullptr;   // this device's fixed scratch array (allocation-free entry point)
+  std::string tune_report;   // launch variants and times of the last autotuner search
 };
 
 struct sdi_problem {
@@ -160,6 +161,7 @@ struct sdi_problem {
   int nsec = 0, K = 0, order_min = 0, kfmax = 0, nvmax = 4, complex_mode = 0;
   int nsmax = 0;                      // most singular variables of any sector
   int nfmax = 0;                      // most regular factors of any sector
+  bool exp7 = false;                  // some factor exponent above 3 (real mode)
   // resumable lattice pass (slice_log2 > 0): per (sector, shift) the running
   // double-double sums [npairs][KMAX][4] (re hi, re lo, im hi, im lo) of the
   // points done, the non-finite and Im F > 0 counts [npairs][2], the points

@@ -76,6 +76,11 @@ int tiles_real_occupancy(int nvmax, int nsmax, int nfmax, int mode, int ppt, int
 // one point per thread, points with a singular coordinate below a.small_x
 // evaluated in double-double.  km 4 or 8.
 int launch_tiles_real_dd(int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+// Problems with factor exponents above 3: one generic instance per variable
+// class (1 point per thread, 4 waves per SIMD) for every mode, and the
+// endpoint-precision final pass (a.small_x > 0; dd for the occupancy); km 4 or 8.
+int launch_tiles_real_e7(int nvmax, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
+int occupancy_tiles_real_e7(int nvmax, int mode, int km, bool dd, size_t shmem);
 int occupancy_tiles_real_dd(int km, size_t shmem);
 
 // Complex mode: nvmax 4 or 8; cx is the CplxDev array (tile kernel) or one sector's

@@ -11,7 +11,7 @@
 
 namespace sdi {
 
-template <int NV, int PPT, int KM, int MODE, int NSM, int MF>
+template <int NV, int PPT, int KM, int MODE, int NSM, int MF, int E7M>
 __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
                                               const TileDesc& td, int tc, const double* __restrict__ lgrid,
                                               double* __restrict__ lhist, double (&s)[KM],
@@ -42,7 +42,7 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
       make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
     }
     double f[PPT][KM];
-    eval_f_real<NV, PPT, KM, NSM, MF>(S, tape(A.terms), x, f);
+    eval_f_real<NV, PPT, KM, NSM, MF, E7M>(S, tape(A.terms), x, f);
     const int kf = S->kf;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -105,7 +105,7 @@ __device__ __forceinline__ void dd_flush(const TileArgs& A, CSec* S, const TileD
   }
 }
 
-template <int NV, int PPT, int KM, int NSM, int MF>
+template <int NV, int PPT, int KM, int NSM, int MF, int E7M>
 __device__ __forceinline__ void run_tile_real_ddq(const TileArgs& A, CSec* S, const TileDesc& td,
                                                   const double* __restrict__ lgrid, uint32_t* q,
                                                   double (&s)[KM], double (&c)[KM], int& nonfin) {
@@ -124,7 +124,7 @@ __device__ __forceinline__ void run_tile_real_ddq(const TileArgs& A, CSec* S, co
     int bins[PPT][NV];
     make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
     double f[PPT][KM];
-    eval_f_real<NV, PPT, KM, NSM, MF>(S, tape(A.terms), x, f);
+    eval_f_real<NV, PPT, KM, NSM, MF, E7M>(S, tape(A.terms), x, f);
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
       const bool act = off + (uint32_t)p < td.count;
@@ -169,14 +169,14 @@ __device__ __forceinline__ void run_tile_real_ddq(const TileArgs& A, CSec* S, co
   }
 }
 
-template <int NV, int PPT, int KM, int MODE, int NSM, bool DD, int MF>
+template <int NV, int PPT, int KM, int MODE, int NSM, bool DD, int MF, int E7M>
 __device__ __forceinline__ void run_tile_any(const TileArgs& A, CSec* S, const TileDesc& td, int tc,
                                              const double* __restrict__ lgrid, double* __restrict__ lhist,
                                              uint32_t* q, double (&s)[KM], double (&c)[KM], int& nonfin) {
   if constexpr (DD)
-    run_tile_real_ddq<NV, PPT, KM, NSM, MF>(A, S, td, lgrid, q, s, c, nonfin);
+    run_tile_real_ddq<NV, PPT, KM, NSM, MF, E7M>(A, S, td, lgrid, q, s, c, nonfin);
   else
-    run_tile_real<NV, PPT, KM, MODE, NSM, MF>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
+    run_tile_real<NV, PPT, KM, MODE, NSM, MF, E7M>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
 }
 
 // WPE: minimum waves per SIMD the register allocation must allow (the
@@ -187,7 +187,10 @@ __device__ __forceinline__ void run_tile_any(const TileArgs& A, CSec* S, const T
 // double-double (the final-pass instances of the endpoint-precision mode).
 // MF: 0 evaluates each corner's term lists; 2 (problems whose sectors have at
 // most two regular factors) evaluates each term once by singular support.
-template <int NVMAX, int PPT, int KM, int MODE, int WPE, int NSM = MAXS, bool DD = false, int MF = 0>
+// E7M: 0 for problems whose factor exponents are at most 3, 1 for problems
+// with exponents up to 7 (the x^4 bit of the term words; their own instances,
+// so that the others carry no code for it).
+template <int NVMAX, int PPT, int KM, int MODE, int WPE, int NSM = MAXS, bool DD = false, int MF = 0, int E7M = 0>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_tiles_real(TileArgs A) {
   extern __shared__ double smem[];
   __shared__ int s_tile;
@@ -234,17 +237,17 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
     uint32_t* q = DD ? s_q + (threadIdx.x >> 6) * DDQ_CAP : nullptr;
     switch (cls) {
       case 0:
-        run_tile_any<4, PPT, KM, MODE, NSM, DD, MF>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
+        run_tile_any<4, PPT, KM, MODE, NSM, DD, MF, E7M>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
         break;
       case 1:
         if constexpr (NVMAX == 6)
-          run_tile_any<6, PPT, KM, MODE, NSM, DD, MF>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
+          run_tile_any<6, PPT, KM, MODE, NSM, DD, MF, E7M>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
         else if constexpr (NVC >= 1)
-          run_tile_any<8, PPT, KM, MODE, NSM, DD, MF>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
+          run_tile_any<8, PPT, KM, MODE, NSM, DD, MF, E7M>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
         break;
       case 2:
         if constexpr (NVC >= 2)
-          run_tile_any<(NVMAX == 10 ? 10 : 16), PPT, KM, MODE, NSM, DD, MF>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
+          run_tile_any<(NVMAX == 10 ? 10 : 16), PPT, KM, MODE, NSM, DD, MF, E7M>(A, S, td, tc, lgrid, lhist, q, s, c, nonfin);
         break;
       default:
         break;
