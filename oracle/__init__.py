@@ -25,6 +25,8 @@ What it computes (paper: FIESTA 4, arXiv:1511.03614):
 * ``flow``       - the learned importance-sampling map (sampling, log q,
   gradient, Adam, training loss weights).
 * ``expr``       - integrands in the workers' text format (section 4.6).
+* ``poles``      - sectors with a_j < -1 reduced to a_j >= -1 by integration
+  by parts (analytic continuation in eps), with coefficient series.
 * ``cubature``   - globally adaptive deterministic cubature (the Cuhre
   option of CurrentIntegrator, section 4.4): the Genz-Malik degree-7/5 rule
   pair on dyadic regions, split along the largest fourth difference.
@@ -55,6 +57,9 @@ Pins (each function checked against something other than itself; tests in
 * flow: finite-difference gradients, invertibility, unit mean weight,
   torch's Adam, convergence to the chi^2-optimal density;
 * expr: hand-evaluated expressions and closed-form integrals;
+* poles: hypergeometric closed forms for a = -2, -3, -1.5, a separable
+  two-variable product, an elementary polynomial case and the expansion's
+  structure;
 * cubature: the rule pair's degrees (every monomial of degree <= 7 exact,
   degree 5 exactly for the embedded rule), polynomials on dyadic boxes of a
   sector, the split axis of one-axis integrands, the dyadic tiling, one split
