@@ -133,7 +133,8 @@ def regular_part(sector, y: np.ndarray, complex_mode: bool, lam: float):
         for fac in sector.factors:
             p = poly(fac.coef, fac.exps, y)
             g0 = g0 * p ** fac.gamma
-            lam_ = lam_ + fac.delta * np.log(p)
+            if fac.delta != 0.0:            # P^gamma alone has no eps dependence (and may vanish)
+                lam_ = lam_ + fac.delta * np.log(p)
         return g0, lam_, np.zeros(npts, dtype=bool)
     if sector.deform_factor >= 0:
         grad, hess = f_derivatives(sector, y)
