@@ -135,6 +135,14 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *                  (0, 1]                                    (default 0.25)
  *   cub_batch_min  cubature: regions halved per round at least, while there
  *                  are as many (1..2^24)                     (default 1024)
+ * Aliases in the survey's terms: points (evaluations per sector = shifts x
+ * 2^lattice_log2, a power-of-two multiple of the current shifts), budget_total
+ * (= budget), budget_min / budget_max (per-sector evaluations under
+ * allocation = shifts x 2^alloc_min_log2 / 2^alloc_max_log2), iterations
+ * (= warmup), and sampler = lattice | vegas | flow (vegas: the lattice with
+ * grid adaptation, 5 warm-up iterations unless warmup is set).  lambda and
+ * complex mode belong to the problem (sdi_problem_desc), the flow's shape and
+ * training settings to sdi_flow_init / sdi_flow_train.
  * Unknown keys or malformed values return SDI_EINVAL. */
 int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value);
 int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len);
@@ -175,7 +183,7 @@ typedef struct {
   int32_t deform_factor;      /* index of the F polynomial among the factors, or -1 */
   int32_t reserved;           /* must be 0                                          */
   double coeff_re, coeff_im;  /* c_s                                                */
-  const double* mono_a;       /* [n] a_j                                            */
+  const double* mono_a;       /* [n] a_j (below -1: reduced, sdi_problem_create)   */
   const double* mono_b;       /* [n] b_j                                            */
   const int32_t* deform_mono; /* [n] exponents of a monomial m: the deformation follows
                                  the gradient of x^m P_F; NULL = 0 (P_F itself)     */
@@ -201,11 +209,21 @@ typedef struct {
 } sdi_problem_desc;
 
 /* Validate and compile a problem into device tables (one host-to-device upload).
- * Returns SDI_EINVAL for inputs outside the domain above and SDI_ENOTSUP for
- * valid inputs beyond the library (more than SDI_MAX_SINGULAR singular
- * variables; factor exponents above 7 in real mode or above 3 in complex
- * mode; exponents of the deformation polynomial's monomial times P_F above 7;
- * more than 8 variables in complex mode). */
+ * Sectors with monomial exponents a_j < -1 (b_j != 0; real mode, integer
+ * factor exponents) are reduced first, on the host, by integration by parts
+ * in x_j (the analytic continuation in eps: with alpha = a_j + 1 + b_j eps,
+ * the boundary part G(x_j = 1)/alpha and the derivative parts
+ * -(g_m + d_m eps)/alpha x_j^alpha dP_m/dx_j P_m^(g_m - 1 + d_m eps) ...),
+ * until every a_j >= -1; each part keeps a coefficient series in eps that
+ * multiplies the prefactor.  The compiled sectors are then those parts, in the
+ * order of the input sectors (sdi_problem_nsectors counts them,
+ * sdi_problem_sector_origin names the input sector of each).  Returns
+ * SDI_EINVAL for inputs outside the domain above and SDI_ENOTSUP for valid
+ * inputs beyond the library (more than SDI_MAX_SINGULAR singular variables;
+ * factor exponents above 7 in real mode or above 3 in complex mode; exponents
+ * of the deformation polynomial's monomial times P_F above 7; more than 8
+ * variables in complex mode; a_j < -1 in complex mode, with non-integer factor
+ * exponents, or needing more than SDI_MAX_FACTORS factors). */
 int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* desc, sdi_problem** out);
 
 /* A Feynman integral by its Symanzik polynomials: SDEvaluate[{U, F, l},
@@ -276,6 +294,9 @@ void sdi_problem_destroy(sdi_problem* prob);
 /* Number of result orders K / of sectors of a problem (SDI_EINVAL for NULL). */
 int sdi_problem_norders(const sdi_problem* prob);
 int sdi_problem_nsectors(const sdi_problem* prob);
+/* The input sector a compiled sector s comes from (s itself unless sectors with
+ * a_j < -1 were expanded); SDI_EINVAL for an index out of range. */
+int sdi_problem_sector_origin(const sdi_problem* prob, int32_t s);
 /* Number of variables n of sector s (the column count of its points in
  * sdi_evaluate, sdi_sample_points and the flow calls); SDI_EINVAL for a NULL
  * problem or s out of range. */
@@ -323,6 +344,9 @@ typedef struct {
   int64_t cub_regions;          /* cubature: regions the estimates sum over            */
   int32_t cub_rounds;           /* cubature: rule launches (rounds of halving + 1)     */
   int32_t cub_converged;        /* cubature: 1 if every order met its tolerance        */
+  double ms_flow_train;         /* device time of sdi_flow_train on this problem since
+                                   its previous sdi_integrate (the learned form's
+                                   training share of this result; 0 without)          */
 } sdi_result;
 
 /* Bytes of device workspace sdi_integrate needs under the current parameters. */

@@ -138,6 +138,6 @@ def expand(sectors: List[Sector]):
 
 
 def folded_prefactor(pref, series: np.ndarray) -> np.ndarray:
-    """The prefactor series times a sector's coefficient series (same leading power)."""
-    p = np.asarray(pref, complex)
-    return np.convolve(p, series)[:len(p)]
+    """The prefactor series times a sector's coefficient series (same leading
+    power; the full product, whose terms are exact as far as pref is)."""
+    return np.convolve(np.asarray(pref, complex), np.asarray(series, complex))

@@ -21,7 +21,7 @@ __all__ = [
     "SdiError", "load_library", "library_path", "declared_functions",
     "sdi_ctx_create", "sdi_ctx_destroy", "sdi_last_error", "sdi_device_info",
     "sdi_set_param", "sdi_get_param", "sdi_tune_save", "sdi_tune_load", "sdi_prefactor_feynman", "sdi_lattice_vector",
-    "sdi_problem_create", "sdi_problem_from_text", "sdi_problem_from_feynman", "sdi_feynman_sectors", "sdi_text_info", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_workspace_bytes",
+    "sdi_problem_create", "sdi_problem_from_text", "sdi_problem_from_feynman", "sdi_feynman_sectors", "sdi_text_info", "sdi_problem_destroy", "sdi_problem_norders", "sdi_problem_nsectors", "sdi_problem_sector_origin", "sdi_workspace_bytes",
     "sdi_integrate", "sdi_sector_results", "sdi_evaluate", "sdi_sample_points",
     "sdi_flow_init", "sdi_flow_nparams", "sdi_flow_params", "sdi_flow_set_params", "sdi_flow_sample",
     "sdi_flow_grad", "sdi_flow_set_grad", "sdi_flow_adam", "sdi_flow_train", "sdi_flow_set_active", "sdi_flow_validate",
@@ -80,7 +80,8 @@ class Result(C.Structure):
                 ("ms_eval_kernel", C.c_double), ("points_per_thread", C.c_int32), ("blocks", C.c_int32),
                 ("tile_log2", C.c_int32), ("waves_per_simd", C.c_int32), ("grouped", C.c_int32),
                 ("ms_pilot_kernel", C.c_double), ("pilot_same_kernel", C.c_int32), ("lattice_done", C.c_int64),
-                ("cub_regions", C.c_int64), ("cub_rounds", C.c_int32), ("cub_converged", C.c_int32)]
+                ("cub_regions", C.c_int64), ("cub_rounds", C.c_int32), ("cub_converged", C.c_int32),
+                ("ms_flow_train", C.c_double)]
 
 
 def library_path() -> str:
@@ -128,6 +129,7 @@ def load_library():
         "sdi_problem_destroy": (None, [vp]),
         "sdi_problem_norders": (C.c_int, [vp]),
         "sdi_problem_nsectors": (C.c_int, [vp]),
+        "sdi_problem_sector_origin": (C.c_int, [vp, i32]),
         "sdi_problem_nvars": (C.c_int, [vp, i32]),
         "sdi_sample_points_noalloc": (C.c_int, [vp, vp, i32, i32, i64, i64, vp, vp]),
         "sdi_checkpoint_export": (C.c_int, [vp, vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]),
@@ -283,7 +285,8 @@ def _prefactor_of(problem):
         return problem.pref_lead, p.real.copy(), p.imag.copy()
     f = problem.feynman
     lead, _ = sdi_prefactor_feynman(f.loops, f.indices, f.d0, 1)
-    max_s = max(int(np.sum(s.a == -1.0)) for s in problem.sectors)
+    # singular variables after the library's reduction of a_j < -1 (integer a_j <= -1 end at -1)
+    max_s = max(int(np.sum((s.a <= -1.0) & (s.a == np.floor(s.a)))) for s in problem.sectors)
     length = max(1, problem.order_max - lead + max_s + 1)
     lead, ser = sdi_prefactor_feynman(f.loops, f.indices, f.d0, length)
     return lead, ser, np.zeros_like(ser)
@@ -398,6 +401,11 @@ def sdi_problem_norders(prob) -> int:
     return int(load_library().sdi_problem_norders(prob))
 
 
+def sdi_problem_sector_origin(prob, s: int) -> int:
+    """Input sector of compiled sector s (sectors with a_j < -1 are expanded)."""
+    return _check_count(int(load_library().sdi_problem_sector_origin(prob, s)))
+
+
 def sdi_workspace_bytes(ctx, prob) -> int:
     return int(load_library().sdi_workspace_bytes(ctx, prob))
 
@@ -408,7 +416,7 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
     """Run the integrator; `workspace` is an optional torch uint8 cuda tensor."""
     K = sdi_problem_norders(prob)
     arrs = [np.zeros(K) for _ in range(4)]
-    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, 0.0, 0, 0, 0, 0, 0)
+    res = Result(0, K, *[_dptr(x) for x in arrs], 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, 0.0, 0, 0, 0, 0, 0, 0.0)
     ptr, nbytes = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()), workspace.numel())
     if workspace is not None:
         import torch
@@ -421,7 +429,8 @@ def sdi_integrate(ctx, prob, workspace=None) -> dict:
             "ppt": res.points_per_thread, "blocks": res.blocks, "tile_log2": res.tile_log2,
             "waves_per_simd": res.waves_per_simd, "grouped": res.grouped, "ms_pilot_kernel": res.ms_pilot_kernel,
             "pilot_same_kernel": res.pilot_same_kernel, "lattice_done": res.lattice_done,
-            "cub_regions": res.cub_regions, "cub_rounds": res.cub_rounds, "cub_converged": res.cub_converged}
+            "cub_regions": res.cub_regions, "cub_rounds": res.cub_rounds, "cub_converged": res.cub_converged,
+            "ms_flow_train": res.ms_flow_train}
 
 
 def sdi_sector_results(ctx, prob, s: int, nshifts: int):

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cerrno>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -14,7 +15,9 @@
 #include <vector>
 
 #include "host.h"
+#include "poles.h"
 #include "kernels.h"
+#include "poles.h"
 
 using namespace sdi;
 
@@ -104,6 +107,11 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
   if (!ctx || !key || !value) return fail(ctx, SDI_EINVAL, "set_param: null argument");
   const std::string k(key), v(value);
   Params& p = ctx->params;
+  if (k == "sampler" && (v == "lattice" || v == "vegas" || v == "flow")) {
+    p.sampler = v == "flow" ? 1 : 0;
+    if (v == "vegas" && p.warmup == 0) p.warmup = 5;
+    return SDI_OK;
+  }
   if (k == "tune") {
     if (v == "off") p.tune = 0;
     else if (v == "cached") p.tune = 1;
@@ -165,6 +173,29 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
   } else if (k == "slice_log2") {
     if (!range(0, 30)) return fail(ctx, SDI_EINVAL, "slice_log2 must be in 0..30");
     p.slice_log2 = (int)iv;
+  } else if (k == "points" || k == "budget_min" || k == "budget_max") {
+    // evaluations per sector = shifts x 2^m
+    const long long r = p.R;
+    if (iv < 16 * r || iv % r != 0 || ((iv / r) & (iv / r - 1)) != 0)
+      return fail(ctx, SDI_EINVAL, k + " must be shifts x 2^m with m >= 4 (shifts = " + std::to_string(r) + ")");
+    int m = 0;
+    while ((1ll << m) < iv / r) ++m;
+    if (k == "points") {
+      if (m > 30) return fail(ctx, SDI_EINVAL, "points: lattice_log2 above 30");
+      p.m = m;
+    } else if (k == "budget_min") {
+      if (m > 24) return fail(ctx, SDI_EINVAL, "budget_min: alloc_min_log2 above 24");
+      p.alloc_min = m;
+    } else {
+      if (m > 26) return fail(ctx, SDI_EINVAL, "budget_max: alloc_max_log2 above 26");
+      p.alloc_max = m;
+    }
+  } else if (k == "budget_total") {
+    if (!range(0, (long long)1 << 40)) return fail(ctx, SDI_EINVAL, "budget_total must be in 0..2^40");
+    p.budget = iv;
+  } else if (k == "iterations") {
+    if (!range(0, 64)) return fail(ctx, SDI_EINVAL, "iterations must be in 0..64");
+    p.warmup = (int)iv;
   } else if (k == "integrator") {
     if (!range(0, 1)) return fail(ctx, SDI_EINVAL, "integrator must be 0 (lattice) or 1 (cubature)");
     p.integrator = (int)iv;
@@ -220,6 +251,11 @@ int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len) {
   else if (k == "budget") v = p.budget;
   else if (k == "slice_log2") v = p.slice_log2;
   else if (k == "integrator") v = p.integrator;
+  else if (k == "points") v = (long long)p.R << p.m;
+  else if (k == "budget_total") v = p.budget;
+  else if (k == "budget_min") v = (long long)p.R << p.alloc_min;
+  else if (k == "budget_max") v = (long long)p.R << p.alloc_max;
+  else if (k == "iterations") v = p.warmup;
   else if (k == "cub_maxeval") v = p.cub_maxeval;
   else if (k == "cub_batch_min") v = p.cub_batch_min;
   else if (k == "alloc_min_log2") v = p.alloc_min;
@@ -259,9 +295,17 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
   if (d->pref_len < 1 || d->pref_len > 64 || !d->pref_re) return fail(ctx, SDI_EINVAL, "prefactor series missing");
   if (d->complex_mode && !(std::isfinite(d->lambda) && d->lambda >= 0.0))
     return fail(ctx, SDI_EINVAL, "lambda must be finite and non-negative");
+  // sectors with a_j < -1 are replaced by their integration-by-parts parts
+  PoleExpansion X;
+  {
+    std::string err;
+    const int rc = expand_poles(d, X, err);
+    if (rc != SDI_OK) return fail(ctx, rc, err);
+  }
   sdi_problem* pb = new sdi_problem();
   pb->ctx = ctx;
-  pb->nsec = d->nsectors;
+  pb->nsec = (int)X.descs.size();
+  pb->origin = X.origin;
   pb->K = K;
   pb->order_min = d->order_min;
   pb->complex_mode = d->complex_mode;
@@ -271,9 +315,10 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     return fail(ctx, code, m);
   };
   const int kf_max = d->order_max - d->pref_lead;
-  for (int s = 0; s < d->nsectors; ++s) {
-    const sdi_sector_desc& sd = d->sectors[s];
-    const std::string where = "sector " + std::to_string(s) + ": ";
+  for (int s = 0; s < pb->nsec; ++s) {
+    const sdi_sector_desc& sd = X.descs[s];
+    const std::string where = "sector " + std::to_string(X.origin[s]) +
+                              (pb->nsec != d->nsectors ? " (part " + std::to_string(s) + ")" : "") + ": ";
     const int n = sd.nvars;
     if (n < 1 || n > MAXV) return bad(SDI_EINVAL, where + "nvars must be 1..16");
     if (sd.nfactors < 0 || sd.nfactors > MAXF) return bad(SDI_EINVAL, where + "nfactors must be 0..4");
@@ -469,14 +514,20 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
       }
       pb->cx.push_back(X);
     }
-    // fold: F_k = sum_kk c_s Pi_i f_kk, i = k - lead - (kk - ns)
+    // fold: F_k = sum_kk c_s (Pi * C)_i f_kk, i = k - lead - (kk - ns), C the
+    // coefficient series of a part of a sector with a_j < -1 (1 otherwise)
     bool has_im = false;
+    const std::vector<std::complex<double>>& cser = X.series[s];
     for (int k = 0; k < K; ++k)
       for (int kk = 0; kk < KMAX; ++kk) {
         const int i = (d->order_min + k) - d->pref_lead - (kk - R.ns);
         double fr = 0.0, fi = 0.0;
-        if (kk < R.kf && i >= 0 && i < d->pref_len) {
-          const double pr = d->pref_re[i], pi = d->pref_im ? d->pref_im[i] : 0.0;
+        if (kk < R.kf && i >= 0) {
+          std::complex<double> pc = 0.0;
+          for (int q = 0; q <= i && q < (int)cser.size(); ++q)
+            if (i - q < d->pref_len)
+              pc += std::complex<double>(d->pref_re[i - q], d->pref_im ? d->pref_im[i - q] : 0.0) * cser[q];
+          const double pr = pc.real(), pi = pc.imag();
           fr = sd.coeff_re * pr - sd.coeff_im * pi;
           fi = sd.coeff_re * pi + sd.coeff_im * pr;
         }
@@ -546,6 +597,11 @@ void sdi_problem_destroy(sdi_problem* pb) {
 int sdi_problem_norders(const sdi_problem* pb) { return pb ? pb->K : SDI_EINVAL; }
 
 int sdi_problem_nsectors(const sdi_problem* pb) { return pb ? pb->nsec : SDI_EINVAL; }
+
+int sdi_problem_sector_origin(const sdi_problem* pb, int32_t s) {
+  if (!pb || s < 0 || s >= pb->nsec) return SDI_EINVAL;
+  return pb->origin.empty() ? s : pb->origin[s];
+}
 
 int sdi_problem_nvars(const sdi_problem* pb, int32_t s) {
   if (!pb || s < 0 || s >= pb->nsec) return SDI_EINVAL;

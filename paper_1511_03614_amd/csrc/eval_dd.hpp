@@ -200,9 +200,16 @@ __device__ __attribute__((noinline)) void eval_f_real_dd(CSec* S, CTerm* terms, 
         }
         P = add(P, m);
       }
-      const D lp = log(P);
-      g0 = mul(g0, (flags & F_INT_POW) ? powi(P, S->gam_int[fm]) : exp(mul(lp, S->gam[fm])));
-      lam = add(lam, mul(lp, S->del[fm]));
+      // a factor with delta = 0 has no eps dependence and may vanish (the
+      // derivative factors of the reduction of a_j < -1): no logarithm then
+      if (flags & F_INT_POW) {
+        g0 = mul(g0, powi(P, S->gam_int[fm]));
+        if (S->del[fm] != 0.0) lam = add(lam, mul(log(P), S->del[fm]));
+      } else {
+        const D lp = log(P);
+        g0 = mul(g0, exp(mul(lp, S->gam[fm])));
+        lam = add(lam, mul(lp, S->del[fm]));
+      }
     }
     for (int T = W;; T = (T - 1) & W) {
       const int off = ns - __builtin_popcount(T);

@@ -13,7 +13,8 @@
 // vanishes when they all do, and split into |Z| sectors: in sector k in Z,
 // x_i -> x_i x_k for the other i in Z, which adds to the exponent of x_k the
 // exponents of the others and the Jacobian x_k^(|Z| - 1).  Each final sector
-// keeps the two polynomials with their monomials moved into the x_j powers.
+// keeps the two polynomials with their monomials moved into the x_j powers;
+// exponents a_j < -1 are reduced by sdi_problem_create.
 #include <cmath>
 #include <map>
 
@@ -192,11 +193,6 @@ int decompose(const sdi_feynman_desc* d, std::vector<OutSector>& out, std::strin
           o.coef.push_back(c);
           o.exps.push_back(e);
         }
-        for (double v : o.a)
-          if (v < -1.0) {
-            err = "a sector exponent a_j < -1 needs higher-order subtraction";
-            return SDI_ENOTSUP;
-          }
         out.push_back(std::move(o));
         continue;
       }
@@ -270,10 +266,11 @@ int lowest_order(const std::vector<OutSector>& secs, const sdi_feynman_desc* d, 
   double one = 0.0;
   const int rc = prefactor_series(d->loops, d->indices, d->nvars, d->d0, 1, &lead, &one, err);
   if (rc != SDI_OK) return rc;
+  // singular variables after the reduction of a_j < -1: integer a_j <= -1 end at -1
   int ns = 0;
   for (auto& s : secs) {
     int c = 0;
-    for (double v : s.a) c += v == -1.0;
+    for (double v : s.a) c += v <= -1.0 && v == std::floor(v);
     ns = std::max(ns, c);
   }
   *pref_lead = lead;

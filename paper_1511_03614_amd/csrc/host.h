@@ -118,6 +118,7 @@ struct FlowState {
   float* d_grad = nullptr;
   void* d_scratch = nullptr; // training and gradient buffers, grown on demand
   size_t scratch_bytes = 0;
+  double train_ms_pending = 0.0;   // device time of sdi_flow_train since the last sdi_integrate
   ~FlowState();
 };
 int fail(sdi_ctx* ctx, int code, const std::string& msg);
@@ -161,6 +162,7 @@ struct sdi_problem {
   int nsec = 0, K = 0, order_min = 0, kfmax = 0, nvmax = 4, complex_mode = 0;
   int nsmax = 0;                      // most singular variables of any sector
   int nfmax = 0;                      // most regular factors of any sector
+  std::vector<int> origin;            // input sector of each compiled sector (parts of a_j < -1 sectors)
   bool exp7 = false;                  // some factor exponent above 3 (real mode)
   // resumable lattice pass (slice_log2 > 0): per (sector, shift) the running
   // double-double sums [npairs][KMAX][4] (re hi, re lo, im hi, im lo) of the

@@ -176,8 +176,6 @@ def feynman_sectors(U: Poly, F: Poly, indices: Sequence[int], loops: int, d0: in
                 facs.append(Factor(float(g), float(d), coef, exps.astype(np.uint8)))
                 if m == 1:
                     mono_F = np.array(gm, dtype=np.int32)
-            if any(float(v) < -1 for v in a):
-                raise NotImplementedError("sector exponent below -1 needs higher-order subtraction")
             secs.append(Sector(a=np.array([float(v) for v in a]), b=np.array([float(v) for v in b]),
                                factors=facs, coeff=1.0, deform_factor=1,
                                deform_mono=mono_F if deform_full_f else np.zeros(n - 1, dtype=np.int32)))

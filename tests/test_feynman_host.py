@@ -4,6 +4,7 @@ against the input tool's decomposition (sectorgen.feynman), on the host: the
 number of sectors and the lowest result order of the bubble, the massive
 bubble, the section 4.3 box and both double boxes; inputs with a_j < -1 are
 refused by both."""
+import numpy as np
 import pytest
 
 import paper_1511_03614_amd as P
@@ -33,14 +34,19 @@ def test_sector_counts_and_lowest_order(name):
     assert nv == len(idx) - 1
 
 
-def test_second_order_poles_are_refused_by_both():
+def test_sectors_with_a_below_minus_one_are_kept_by_both():
+    """The box in d = 2 - 2 eps has sectors with a_j = -2: both decompositions
+    keep them (the library reduces them when it compiles the problem) and
+    count one more singular variable for the leading pole."""
     try:
         P.load_library()
     except Exception as e:                       # noqa: BLE001
         pytest.skip(f"library not built: {e}")
     U, F = feynman.box_uf(3.0, 1.0)
-    with pytest.raises(NotImplementedError):
-        feynman.feynman_sectors(U, F, (1, 1, 1, 1), 1, d0=2)
-    with pytest.raises(P.SdiError) as e:
-        P.sdi_feynman_sectors(U, F, 1, (1, 1, 1, 1), d0=2)
-    assert e.value.code == -4
+    secs = feynman.feynman_sectors(U, F, (1, 1, 1, 1), 1, d0=2)
+    assert min(float(s.a.min()) for s in secs) == -2.0
+    ns, om, nv = P.sdi_feynman_sectors(U, F, 1, (1, 1, 1, 1), d0=2)
+    assert ns == len(secs) and nv == 3
+    lead = P.sdi_prefactor_feynman(1, (1, 1, 1, 1), 2, 1)[0]
+    most = max(int(sum((s.a <= -1.0) & (s.a == np.floor(s.a)))) for s in secs)
+    assert om == lead - most
