@@ -15,6 +15,28 @@ reference for the double-double evaluation of points near the faces x_j = 0.
   multiprecision values agree with it there, at the largest accepted shapes.
 * The value does not depend on the working precision beyond 32 digits.
 * The ln 2 split used by the device double-double exp is ln 2 to 106 bits.
+
+Complex mode (contour deformation, section 4.4):
+
+* The equal-mass bubble above threshold (p^2 = 5, m^2 = 1): the eps^-1 and
+  eps^0 coefficients of its closed form, 1 and
+  2 - beta ln((1 + beta)/(1 - beta)) + i pi beta with beta^2 = 1 - 4m^2/p^2,
+  from the integrand integrated by tanh-sinh quadrature (whose nodes crowd
+  both faces), at two deformation sizes (Cauchy's theorem).
+* One singular variable with a factor that changes sign inside the cube,
+  x^(-1 + b eps) (1 - s x - i0)^(gamma + delta eps), s > 1: the integral is
+  2F1(-gamma - delta eps, b eps; b eps + 1; s + i0) / (b eps); its Laurent
+  coefficients from the integrand by the same quadrature.
+* A factor that is real and negative at the face x = 0 (arg = -pi there):
+  the closed form is the phase e^(-i pi (gamma + delta eps)) times the real
+  hypergeometric integral.
+* Two singular variables, the deformation acting on one of them: the
+  integrand is the product of a complex and a real one-variable integrand,
+  so its eps series at any point is the Cauchy product of theirs (at points
+  down to 1e-14 from the faces).
+* Away from the faces it agrees with the fp64 oracle to its rounding bound,
+  at the largest complex shape (8 variables, 4 singular); near the faces it
+  does not depend on the working precision beyond 32 digits.
 """
 import math
 import re
@@ -24,9 +46,12 @@ import mpmath
 import numpy as np
 import pytest
 
-from oracle import integrand
+from oracle import integrand, integrate
 from oracle import integrand_mp as M
 from sectorgen import Factor, Sector, SplitMix64
+from sectorgen.feynman import massive_bubble_problem
+
+from shapes import max_complex_problem
 
 U = 2.0 ** -53
 
@@ -169,3 +194,125 @@ def test_device_ln2_split():
         assert hi == float(ln2)
         assert lo == float(ln2 - mpmath.mpf(hi))
         assert abs(mpmath.mpf(hi) + mpmath.mpf(lo) - ln2) <= mpmath.mpf(2) ** -106
+
+
+# ---------------------------------------------------------------- complex mode
+
+def quad_order(sec, k, lam, dps=30):
+    """int_0^1 f_k(x) dx of a one-variable sector by tanh-sinh quadrature at dps digits."""
+    ns = len(integrand.singular_set(sec))
+    with mpmath.workdps(dps):
+        return mpmath.quad(lambda x: M.sector_f_point(sec, [x], k, dps=dps, complex_mode=True, lam=lam)[0][k + ns],
+                           [0, 1])
+
+
+@pytest.mark.parametrize("lam", [0.5, 0.3])
+def test_complex_massive_bubble_closed_form(lam):
+    prob = massive_bubble_problem(5.0, 1.0, lam)
+    lead, pref = integrate.prefactor_for(prob)
+    assert lead == -1 and pref[0] == 1.0 and pref[1] == 0.0
+    with mpmath.workdps(30):
+        f0 = sum(quad_order(sec, 0, lam) for sec in prob.sectors)       # eps^-1 of the result
+        f1 = sum(quad_order(sec, 1, lam) for sec in prob.sectors)       # eps^0
+        beta = mpmath.sqrt(1 - mpmath.mpf(4) / 5)
+        fin = 2 - beta * mpmath.log((1 + beta) / (1 - beta)) + 1j * mpmath.pi * beta
+        assert abs(f0 - 1) < mpmath.mpf(10) ** -28
+        assert abs(f1 - fin) < mpmath.mpf(10) ** -28
+
+
+def hyp_complex_series(b, s, g, d, n, dps=40):
+    """Laurent coefficients eps^-1 .. eps^(n-1) of int_0^1 x^(-1+b eps) (1 - s x - i0)^(g + d eps) dx."""
+    with mpmath.workdps(dps):
+        z = mpmath.mpf(s) + mpmath.mpc(0, mpmath.mpf(10) ** -(dps + 15))     # the -i0 side of 1 - s x
+        return mpmath.taylor(lambda e: mpmath.hyp2f1(-(g + d * e), b * e, b * e + 1, z) / b, 0, n - 1)
+
+
+@pytest.mark.parametrize("b,s,g,d,lam", [(1.0, 2.0, -1.0, 1.0, 0.4), (-2.0, 3.0, 1.5, -1.0, 0.2),
+                                         (0.5, 1.5, -2.0, 0.5, 0.5)])
+def test_complex_one_variable_through_the_cut(b, s, g, d, lam):
+    sec = Sector(a=np.array([-1.0]), b=np.array([b]),
+                 factors=[Factor(g, d, np.array([1.0, -s]), np.array([[0], [1]], dtype=np.uint8))],
+                 deform_factor=0, deform_mono=np.zeros(1, np.int32))
+    ref = hyp_complex_series(b, s, g, d, 4)
+    with mpmath.workdps(30):
+        for k in range(-1, 3):
+            got = quad_order(sec, k, lam)
+            assert abs(got - ref[k + 1]) < mpmath.mpf(10) ** -24 * max(1, abs(ref[k + 1])), k
+
+
+@pytest.mark.parametrize("b,c,g,d,lam", [(1.0, 0.5, -1.5, 1.0, 0.3), (-1.0, 2.0, 0.5, -0.5, 0.2)])
+def test_complex_factor_negative_at_the_face(b, c, g, d, lam):
+    """x^(-1+b eps) (-(1 + c x) - i0)^(g + d eps) = e^(-i pi (g + d eps)) x^(-1+b eps) (1 + c x)^(g + d eps):
+    the factor is real and negative at the corner x = 0, where its argument is -pi."""
+    sec = Sector(a=np.array([-1.0]), b=np.array([b]),
+                 factors=[Factor(g, d, np.array([-1.0, -c]), np.array([[0], [1]], dtype=np.uint8))],
+                 deform_factor=0, deform_mono=np.zeros(1, np.int32))
+    with mpmath.workdps(40):
+        ref = mpmath.taylor(lambda e: mpmath.exp(-1j * mpmath.pi * (g + d * e))
+                            * mpmath.hyp2f1(-(g + d * e), b * e, b * e + 1, -c) / b, 0, 3)
+    with mpmath.workdps(30):
+        for k in range(-1, 3):
+            got = quad_order(sec, k, lam)
+            assert abs(got - ref[k + 1]) < mpmath.mpf(10) ** -24 * max(1, abs(ref[k + 1])), k
+
+
+def test_complex_two_variables_cauchy_product():
+    b1, s1, g1, d1, lam = 1.0, 2.5, -1.0, 0.5, 0.3
+    b2, c2, g2, d2 = -1.0, 0.7, 2.0, -1.0
+    one_c = Sector(a=np.array([-1.0]), b=np.array([b1]),
+                   factors=[Factor(g1, d1, np.array([1.0, -s1]), np.array([[0], [1]], dtype=np.uint8))],
+                   deform_factor=0, deform_mono=np.zeros(1, np.int32))
+    one_r = one_var(b2, c2, g2, d2)
+    two = Sector(a=np.array([-1.0, -1.0]), b=np.array([b1, b2]), factors=[
+        Factor(g1, d1, np.array([1.0, -s1]), np.array([[0, 0], [1, 0]], dtype=np.uint8)),
+        Factor(g2, d2, np.array([1.0, c2]), np.array([[0, 0], [0, 1]], dtype=np.uint8))],
+        deform_factor=0, deform_mono=np.zeros(2, np.int32))
+    for x1, x2 in [(0.3, 0.6), (1e-3, 0.8), (1e-9, 1e-5), (1e-14, 0.4), (0.7, 1e-13), (1e-12, 1e-14)]:
+        fa, _ = M.sector_f_point(one_c, [x1], 3, complex_mode=True, lam=lam)
+        fb, _ = M.sector_f_point(one_r, [x2], 3)
+        f, _ = M.sector_f_point(two, [x1, x2], 2, complex_mode=True, lam=lam)
+        with mpmath.workdps(60):
+            for k in range(-2, 3):
+                ref = sum(fa[i + 1] * fb[k - i + 1] for i in range(-1, k + 2))
+                scale = sum(abs(fa[i + 1] * fb[k - i + 1]) for i in range(-1, k + 2))
+                assert abs(f[k + 2] - ref) <= mpmath.mpf(10) ** -30 * scale, (x1, x2, k)
+
+
+def test_complex_agrees_with_fp64_oracle_away_from_faces():
+    prob = max_complex_problem()
+    rng = np.random.default_rng(3)
+    for sec in prob.sectors:
+        x = rng.uniform(0.05, 1.0, size=(3, sec.n))
+        f64, cond, _ = integrand.sector_f(sec, x, 3, True, prob.lam)
+        for p in range(x.shape[0]):
+            f, _ = M.sector_f_point(sec, x[p], 3, complex_mode=True, lam=prob.lam)
+            for k in range(f64.shape[0]):
+                assert abs(complex(f[k]) - f64[k, p]) <= 32 * U * cond[k, p], (p, k)
+
+
+def test_complex_independent_of_working_precision():
+    prob = max_complex_problem()
+    sec = prob.sectors[1]
+    rng = np.random.default_rng(6)
+    x = rng.uniform(0.0, 1.0, size=(2, sec.n))
+    x[:, :4] = 10.0 ** rng.uniform(-12, -2, size=(2, 4))
+    for p in range(2):
+        d = M.point_dps(sec, x[p])
+        f1, _ = M.sector_f_point(sec, x[p], 3, complex_mode=True, lam=prob.lam)
+        f2, _ = M.sector_f_point(sec, x[p], 3, dps=d + 30, complex_mode=True, lam=prob.lam)
+        for k in range(len(f1)):
+            with mpmath.workdps(d + 30):
+                assert abs(f1[k] - f2[k]) <= mpmath.mpf(10) ** -34 * (abs(f2[k]) + mpmath.mpf(10) ** -300)
+
+
+def test_complex_orders_fold_matches_fp64_oracle():
+    prob = max_complex_problem()
+    sec = prob.sectors[0]
+    lead, pref = integrate.prefactor_for(prob)
+    x = np.random.default_rng(10).uniform(0.1, 1.0, size=(2, sec.n))
+    v64, c64, _ = integrand.sector_orders(sec, x, prob.order_min, prob.order_max, lead, pref, True, prob.lam)
+    vmp, cmp_, fabs_ = M.sector_orders_mp(sec, x, prob.order_min, prob.order_max, lead, pref,
+                                          complex_mode=True, lam=prob.lam)
+    assert vmp.dtype == np.complex128
+    assert np.all(np.abs(vmp - v64) <= 32 * U * c64 + 4 * U * fabs_)
+    np.testing.assert_allclose(cmp_, c64, rtol=1e-10)
