@@ -103,16 +103,18 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *                  Needs budget 0, warmup 0, sampler 0 (else SDI_ENOTSUP).
  *                  0 = off                                      (default 0)
  *   small_x        endpoint precision, a number in [0, 1] (decimal or
- *                  exponent notation): in real mode, points whose smallest
- *                  singular coordinate lies below it are evaluated in
- *                  double-double arithmetic (about 106 bits) and rounded to
- *                  fp64 once, by sdi_evaluate and by the lattice final pass
- *                  (problems with at most 2 singular variables per sector
- *                  keep the tuned launch variants; deeper ones run one
- *                  instance, 1 point per thread, 2 waves per SIMD); the role of the
- *                  SmallX / MPThreshold switch to MPFR of section 4.6.  The
- *                  warm-up, flow-sampled points, complex mode and text
- *                  integrands stay in fp64.  0 = off         (default 0)
+ *                  exponent notation): points whose smallest singular
+ *                  coordinate lies below it are evaluated in double-double
+ *                  arithmetic (about 106 bits) and rounded to fp64 once, by
+ *                  sdi_evaluate and by the final pass on lattice points and
+ *                  on flow-sampled points, in real and in complex mode (real
+ *                  problems with at most 2 singular variables per sector keep
+ *                  the tuned launch variants; deeper ones run one instance, 1
+ *                  point per thread, 2 waves per SIMD; complex problems run
+ *                  one instance, 1 point per thread); the role of the SmallX
+ *                  / MPThreshold switch to MPFR of sections 4.4 and 4.6.  The
+ *                  warm-up, the adaptive cubature and text integrands stay in
+ *                  fp64.  0 = off                             (default 0)
  *   integrator     the final-stage integrator (CurrentIntegrator of section
  *                  4.4): 0 = shifted lattice QMC with optional Vegas grids;
  *                  1 = globally adaptive deterministic cubature, the role of

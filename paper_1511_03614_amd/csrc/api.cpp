@@ -623,7 +623,7 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_d
   A.out = (double*)out_dev;
   A.npts = npts;
   A.cond = (double*)cond_dev;
-  A.small_x = (pb->complex_mode || pb->is_expr()) ? 0.0 : ctx->params.small_x;
+  A.small_x = pb->is_expr() ? 0.0 : ctx->params.small_x;
   if (pb->is_expr())
     KCHK(ctx, launch_eval_points_expr(A, ExprArgs{pb->d_expr, (int32_t)pb->expr_nins, pb->expr_slots, pb->expr_out},
                                       ctx->stream));

@@ -348,6 +348,7 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
   out->cub_regions = nalive;
   out->cub_rounds = rounds;
   out->cub_converged = converged ? 1 : 0;
+  out->ms_flow_train = 0.0;
   out->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return nonfin > 0 ? SDI_ENONFINITE : SDI_OK;
 }

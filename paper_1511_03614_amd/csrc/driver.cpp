@@ -23,7 +23,7 @@ struct Plan {
   int R = 0, rows = 0;
   int tile_log2 = 14;            // points per final-pass tile (log2; shorter lattices make one tile)
   uint32_t range_lo = 0, range_hi = 0;  // lattice indices of this pass per shift (hi 0: the whole lattice)
-  double small_x = 0.0;          // endpoint-precision threshold of the lattice final pass (0: off)
+  double small_x = 0.0;          // endpoint-precision threshold of the final pass (0: off)
   bool warm = false;
   bool flow = false;             // final points come from the learned sampler
   std::vector<PointRun> fruns;   // per final tile: its points in the flow buffers
@@ -150,7 +150,7 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   P.rows = prm.R + prm.warmup;
   P.warm = warm && prm.warmup > 0;
   P.flow = prm.sampler == 1;
-  P.small_x = (prm.small_x > 0.0 && !pb->complex_mode && !pb->is_expr()) ? prm.small_x : 0.0;
+  P.small_x = (prm.small_x > 0.0 && !pb->is_expr()) ? prm.small_x : 0.0;
   if (P.flow && !pb->flow) return fail(ctx, SDI_ESTATE, "sampler flow needs sdi_flow_init on this problem");
   if (P.flow && prm.warmup > 0) return fail(ctx, SDI_ENOTSUP, "the flow sampler replaces the Vegas warm-up (set warmup 0)");
   P.msec = msec;
@@ -318,7 +318,7 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
 }
 
 bool uses_dd(const sdi_problem* pb, const Params& p) {
-  return p.small_x > 0.0 && !pb->complex_mode && !pb->is_expr();
+  return p.small_x > 0.0 && !pb->is_expr();
 }
 
 // Family of real-mode final-pass instances of a problem under the current
@@ -347,7 +347,10 @@ std::vector<int> generic_variants(const sdi_problem* pb) {
 std::vector<int> tile_variants(const sdi_problem* pb, const Params& p) {
   if (pb->is_expr()) return {11};
   if (pb->exp7) return {E7_VARIANT};
-  if (pb->complex_mode) return pb->nvmax <= 4 ? std::vector<int>{11, 12, 21} : std::vector<int>{11, 12};
+  if (pb->complex_mode) {
+    if (uses_dd(pb, p)) return {11};   // the endpoint-precision instance (one point per thread)
+    return pb->nvmax <= 4 ? std::vector<int>{11, 12, 21} : std::vector<int>{11, 12};
+  }
   std::vector<int> v;
   switch (final_family(pb, p)) {
     case RF_G3: v = {12, 14, 22, 23}; break;
@@ -371,7 +374,7 @@ constexpr int DD_VARIANT = 12;
 int default_variant(const sdi_problem* pb, const Params& p, int ppt) {
   if (pb->is_expr()) return 11;   // one point per lane and step
   if (pb->exp7) return E7_VARIANT;
-  if (pb->complex_mode) return 10 * ppt + 1;
+  if (pb->complex_mode) return uses_dd(pb, p) ? 11 : 10 * ppt + 1;
   switch (final_family(pb, p)) {
     case RF_G3: return ppt == 1 ? 14 : 22;
     case RF_G4: return ppt == 1 ? 12 : 22;
@@ -407,8 +410,8 @@ int persistent_grid(sdi_ctx* ctx, const sdi_problem* pb, int mode, int ppt, int 
   const int nvmax = pb->nvmax;
   const int nf = corner_lists ? MAXF + 1 : pb->nfmax;
   int occ = pb->is_expr()                             ? tiles_expr_occupancy(mode, shmem, expr_args(pb))
-            : pb->complex_mode                        ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, shmem)
-            : pb->exp7 ? occupancy_tiles_real_e7(nvmax, mode, km, mode == 0 && uses_dd(pb, ctx->params), shmem)
+            : pb->complex_mode ? tiles_cplx_occupancy(nvmax, mode, ppt, wpe, km, uses_dd(pb, ctx->params), shmem)
+            : pb->exp7 ? occupancy_tiles_real_e7(nvmax, mode, km, uses_dd(pb, ctx->params), shmem)
                                                       : tiles_real_occupancy(nvmax, pb->nsmax, nf, mode, ppt, wpe, km,
                                                                              uses_dd(pb, ctx->params), shmem);
   if (occ < 1) occ = 1;
@@ -451,7 +454,7 @@ TileArgs final_args(const sdi_problem* pb, const Plan& P, bool flow = false) {
   F.pw = P.d_pw;
   F.x_off = P.d_fx_off;
   F.pt_off = P.d_fpt_off;
-  F.small_x = flow ? 0.0 : P.small_x;
+  F.small_x = P.small_x;
   return F;
 }
 
@@ -1078,6 +1081,12 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
     pb->resume_key = rkey;
   }
   out->lattice_done = hi ? (int64_t)hi : ((int64_t)1 << prm.m);
+  if (pb->flow) {
+    out->ms_flow_train = pb->flow->train_ms_pending;
+    pb->flow->train_ms_pending = 0.0;
+  } else {
+    out->ms_flow_train = 0.0;
+  }
   out->order_min = pb->order_min;
   out->norders = pb->K;
   for (int k = 0; k < pb->K; ++k) {

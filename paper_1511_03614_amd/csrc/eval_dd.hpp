@@ -98,7 +98,7 @@ constexpr double LN2_LO = 0x1.abc9e3b39803fp-56;
 __device__ inline D exp(D a) {
 #pragma clang fp contract(off)
   if (a.h != a.h) return a;
-  if (a.h > 709.0) return mk(__builtin_inf());
+  if (a.h > 709.782712893384) return mk(__builtin_inf());   // above ln(DBL_MAX)
   if (a.h < -745.0) return mk(0.0);
   // a = k ln 2 + r, |r| <~ ln2/2 (k from an fp64 estimate; r is formed in double-double)
   const double k = rint(a.h * 1.4426950408889634);
@@ -115,13 +115,18 @@ __device__ inline D exp(D a) {
 }
 
 // Natural log; NaN for a < 0 (as the fp64 path: real mode has no branch cut), -inf for 0.
+// a = m 2^e with m in [0.5, 1) (exact scaling, so subnormal a is no special case):
+// ln a = y + (m e^-y - 1) + e ln 2, y the fp64 ln m (one Newton step).
 __device__ inline D log(D a) {
 #pragma clang fp contract(off)
   if (!(a.h > 0.0)) return mk(a.h == 0.0 ? -__builtin_inf() : __builtin_nan(""));
   if (a.h == __builtin_inf()) return a;
-  const double y = ::log(a.h);
-  const D r = mul(a, exp(mk(-y)));
-  return add(mk(y), sub(r, mk(1.0)));
+  int e = 0;
+  (void)frexp(a.h, &e);
+  const D m = scale2(a, -e);
+  const double y = ::log(m.h);
+  const D r = mul(m, exp(mk(-y)));
+  return add(add(mk(y), sub(r, mk(1.0))), mul(D{LN2_HI, LN2_LO}, (double)e));
 }
 
 __device__ inline D powi(D a, int k) {
@@ -133,6 +138,10 @@ __device__ inline D powi(D a, int k) {
 }
 
 }  // namespace xdd
+
+// Entries of a wave's queue of points awaiting double-double evaluation (the
+// endpoint-precision tile instances): a round adds at most 64 to fewer than 64.
+constexpr int DDQ_CAP = 128;
 
 // Whether a point is evaluated in double-double: its smallest singular
 // coordinate (internal variables 0 .. ns-1) lies below small_x.

@@ -38,7 +38,7 @@ int occupancy_tiles_real_nv10_g(int nsm, int ppt, int wpe, int km, size_t shmem)
 int occupancy_tiles_real_nv16_g(int nsm, int ppt, int wpe, int km, size_t shmem);
 
 int real_family(int nsmax, int nfmax, int mode, bool dd) {
-  if (mode != 0 || nfmax > 2) return dd && mode == 0 ? RF_DD : RF_GENERIC;
+  if (mode != 0 || nfmax > 2) return dd && mode != 1 ? RF_DD : RF_GENERIC;
   if (nsmax <= 2) return RF_S2;
   if (dd) return RF_DD;
   return nsmax == 3 ? RF_G3 : RF_G4;
@@ -46,7 +46,7 @@ int real_family(int nsmax, int nfmax, int mode, bool dd) {
 
 int launch_tiles_real(int nvmax, int nsmax, int nfmax, int ppt, int wpe, int km, int grid, size_t shmem,
                       const TileArgs& a, hipStream_t st) {
-  const bool dd = a.mode == 0 && a.small_x > 0.0;
+  const bool dd = a.mode != 1 && a.small_x > 0.0;
   switch (real_family(nsmax, nfmax, a.mode, dd)) {
     case RF_S2:
       if (nvmax <= 4) return launch_tiles_real_nv4_s2(ppt, wpe, km, dd, grid, shmem, a, st);
@@ -76,7 +76,7 @@ int launch_tiles_real(int nvmax, int nsmax, int nfmax, int ppt, int wpe, int km,
 
 int tiles_real_occupancy(int nvmax, int nsmax, int nfmax, int mode, int ppt, int wpe, int km, bool dd,
                          size_t shmem) {
-  dd = dd && mode == 0;
+  dd = dd && mode != 1;
   switch (real_family(nsmax, nfmax, mode, dd)) {
     case RF_S2:
       if (nvmax <= 4) return occupancy_tiles_real_nv4_s2(ppt, wpe, km, dd, shmem);
@@ -94,7 +94,7 @@ int tiles_real_occupancy(int nvmax, int nsmax, int nfmax, int mode, int ppt, int
       return occupancy_tiles_real_nv16_g(nsm, ppt, wpe, km, shmem);
     }
     case RF_DD:
-      return occupancy_tiles_real_dd(km, shmem);
+      return occupancy_tiles_real_dd(mode, km, shmem);
     default:
       if (nvmax <= 4) return occupancy_tiles_real_nv4(mode, ppt, wpe, km, shmem);
       if (nvmax <= 6) return occupancy_tiles_real_nv6(mode, ppt, wpe, km, shmem);

@@ -544,6 +544,7 @@ int sdi_flow_train(sdi_ctx* ctx, sdi_problem* pb, const int32_t* sectors, int32_
   float ms = 0.f;
   HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
   if (ms_out) *ms_out = ms;
+  F.train_ms_pending += ms;
   for (int s : sel) {
     F.t[s] += iters;
     F.active[s] = 1;

@@ -56,7 +56,7 @@ struct Params {
   int alloc_max = 20;
   int pilot_log2 = 12;   // lattice log2 of the pilot pass that measures the variances
   int sampler = 0;       // 0: lattice (+ Vegas grid), 1: the learned flow
-  double small_x = 0.0;  // real mode: double-double below this smallest singular coordinate (0: off)
+  double small_x = 0.0;  // double-double below this smallest singular coordinate (0: off)
   int slice_log2 = 0;    // > 0: a call processes the next 2^slice_log2 lattice points per shift (resumable)
   int integrator = 0;    // 0: lattice QMC, 1: adaptive deterministic cubature
   int64_t cub_maxeval = 1 << 24;  // cubature: evaluation budget over all sectors

@@ -60,8 +60,9 @@ int launch_eval_points_expr(const EvalArgs& a, const ExprArgs& x, hipStream_t st
 // problems, warm-up and explicit points run the generic instances that
 // evaluate each corner's term lists (RF_GENERIC, final-pass variants as RF_S2);
 // endpoint precision outside RF_S2 runs the one instance of
-// launch_tiles_real_dd (RF_DD; ppt and wpe ignored).  A final pass with
-// a.small_x > 0 evaluates points below a.small_x again in double-double.
+// launch_tiles_real_dd (RF_DD; ppt and wpe ignored).  A final pass (mode 0,
+// or mode 2 on explicit points) with a.small_x > 0 evaluates points below
+// a.small_x again in double-double.
 // grid = number of persistent blocks.
 enum { RF_GENERIC = 0, RF_S2 = 1, RF_G3 = 2, RF_G4 = 3, RF_DD = 4 };
 int real_family(int nsmax, int nfmax, int mode, bool dd);
@@ -72,22 +73,28 @@ int launch_eval_points_real(int km, const EvalArgs& a, hipStream_t st);
 // endpoint-precision one of a final pass); 0 if not built.
 int tiles_real_occupancy(int nvmax, int nsmax, int nfmax, int mode, int ppt, int wpe, int km, bool dd,
                          size_t shmem);
-// Final pass (a.mode 0) of the endpoint-precision mode: every variable class,
-// one point per thread, points with a singular coordinate below a.small_x
-// evaluated in double-double.  km 4 or 8.
+// Final pass (a.mode 0 on the lattice, 2 on explicit points) of the
+// endpoint-precision mode: every variable class, one point per thread, points
+// with a singular coordinate below a.small_x evaluated in double-double.  km 4 or 8.
 int launch_tiles_real_dd(int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 // Problems with factor exponents above 3: one generic instance per variable
 // class (1 point per thread, 4 waves per SIMD) for every mode, and the
-// endpoint-precision final pass (a.small_x > 0; dd for the occupancy); km 4 or 8.
+// endpoint-precision final pass (modes 0 and 2 with a.small_x > 0; dd for the
+// occupancy); km 4 or 8.
 int launch_tiles_real_e7(int nvmax, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st);
 int occupancy_tiles_real_e7(int nvmax, int mode, int km, bool dd, size_t shmem);
-int occupancy_tiles_real_dd(int km, size_t shmem);
+int occupancy_tiles_real_dd(int mode, int km, size_t shmem);
 
 // Complex mode: nvmax 4 or 8; cx is the CplxDev array (tile kernel) or one sector's
-// record (point evaluation); dir the derivative-list directory.
+// record (point evaluation); dir the derivative-list directory.  A final pass
+// (mode 0 or 2) with a.small_x > 0 runs the endpoint-precision instance
+// (launch_tiles_cplx_dd: one point per thread, ppt and wpe ignored, points
+// below a.small_x again in double-double; dd for the occupancy).
 int launch_tiles_cplx(int nvmax, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
                       const void* cx, const uint32_t* dir, hipStream_t st);
-int tiles_cplx_occupancy(int nvmax, int mode, int ppt, int wpe, int km, size_t shmem);
+int tiles_cplx_occupancy(int nvmax, int mode, int ppt, int wpe, int km, bool dd, size_t shmem);
+int launch_tiles_cplx_dd(int km, int grid, size_t shmem, const TileArgs& a, const CplxArgs& X, hipStream_t st);
+int occupancy_tiles_cplx_dd(int mode, int km, size_t shmem);
 int launch_tiles_cplx_nv4(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, const CplxArgs& X,
                           hipStream_t st);
 int launch_tiles_cplx_nv6(int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a, const CplxArgs& X,

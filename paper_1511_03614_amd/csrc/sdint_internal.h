@@ -110,7 +110,7 @@ struct TileArgs {
   const double* pw;          //         and their weights at pw + pt_off[t]
   const int64_t* x_off;
   const int64_t* pt_off;
-  double small_x;            // mode 0: points whose smallest singular coordinate is below it
+  double small_x;            // modes 0 and 2: points whose smallest singular coordinate is below it
                              // are evaluated in double-double (0: never)
 };
 

@@ -8,13 +8,16 @@ namespace sdi {
 int launch_tiles_cplx(int nvmax, int ppt, int wpe, int km, int grid, size_t shmem, const TileArgs& a,
                       const void* cx, const uint32_t* dir, hipStream_t st) {
   const CplxArgs X{(const CplxDev*)cx, dir};
+  if (a.mode != 1 && a.small_x > 0.0) return nvmax <= 8 ? launch_tiles_cplx_dd(km, grid, shmem, a, X, st)
+                                                        : (int)hipErrorInvalidValue;
   if (nvmax <= 4) return launch_tiles_cplx_nv4(ppt, wpe, km, grid, shmem, a, X, st);
   if (nvmax <= 6) return launch_tiles_cplx_nv6(ppt, wpe, km, grid, shmem, a, X, st);
   if (nvmax <= 8) return launch_tiles_cplx_nv8(ppt, wpe, km, grid, shmem, a, X, st);
   return (int)hipErrorInvalidValue;
 }
 
-int tiles_cplx_occupancy(int nvmax, int mode, int ppt, int wpe, int km, size_t shmem) {
+int tiles_cplx_occupancy(int nvmax, int mode, int ppt, int wpe, int km, bool dd, size_t shmem) {
+  if (mode != 1 && dd) return nvmax <= 8 ? occupancy_tiles_cplx_dd(mode, km, shmem) : 0;
   if (nvmax <= 4) return occupancy_tiles_cplx_nv4(mode, ppt, wpe, km, shmem);
   if (nvmax <= 6) return occupancy_tiles_cplx_nv6(mode, ppt, wpe, km, shmem);
   if (nvmax <= 8) return occupancy_tiles_cplx_nv8(mode, ppt, wpe, km, shmem);

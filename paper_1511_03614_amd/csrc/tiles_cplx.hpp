@@ -3,7 +3,7 @@
 // also counts the points where Im F(z) > 0 (the TestF check of section 4.6).
 #pragma once
 #include "cplx_args.h"
-#include "eval_cplx.hpp"
+#include "eval_cplx_dd.hpp"
 
 namespace sdi {
 
@@ -70,6 +70,124 @@ __device__ __forceinline__ void run_tile_cplx(const TileArgs& A, const CplxArgs&
   }
 }
 
+// One point per lane for the endpoint-precision instances: lattice point
+// td.i0 + off (MODE 0) or the tile's explicit point off (MODE 2).
+template <int NV, int MODE>
+__device__ __forceinline__ void load_point_cplx(const TileArgs& A, CSec* S, const TileDesc& td, int tc,
+                                                const double* __restrict__ lgrid, uint32_t off, double (&x)[1][NV],
+                                                double (&w)[1]) {
+  if constexpr (MODE == 2) {
+    const int n = S->n;
+    const double* xp = A.px + A.x_off[tc] + (size_t)off * n;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) x[0][j] = j < n ? xp[S->perm[j]] : 0.5;
+    w[0] = A.pw[A.pt_off[tc] + off];
+  } else {
+    CU64* zp = tape(A.zp) + (size_t)td.sector * MAXV;
+    CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
+    int bins[1][NV];
+    make_points<NV, 1>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+  }
+}
+
+template <int NV, int KM, int MODE>
+__device__ __forceinline__ void dd_flush_cplx(const TileArgs& A, const CplxArgs& X, CSec* S, const TileDesc& td,
+                                              int tc, const double* __restrict__ lgrid, const uint32_t* q, int cnt,
+                                              double (&sr)[KM], double (&cr)[KM], double (&si)[KM],
+                                              double (&ci)[KM], int& nonfin) {
+  const int lane = threadIdx.x & 63;
+  if (lane < cnt) {
+    double x[1][NV], w[1];
+    load_point_cplx<NV, MODE>(A, S, td, tc, lgrid, q[lane], x, w);
+    double fr[KM], fi[KM], cd_[KM];
+    eval_f_cplx_dd<KM>(S, tape(X.cx) + td.sector, tape(X.dir), tape(A.terms), x[0], fr, fi, cd_);
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const double vr = w[0] * fr[k];
+      const double vi = w[0] * fi[k];
+      two_sum_acc(sr[k], cr[k], vr);
+      two_sum_acc(si[k], ci[k], vi);
+      bad |= !isfinite(vr) || !isfinite(vi);
+    }
+    nonfin += bad ? 1 : 0;
+  }
+}
+
+// Final-pass tile of the endpoint-precision instances, one point per thread:
+// points whose smallest singular coordinate is below A.small_x are queued per
+// wave in LDS (ballot and prefix count) and evaluated 64 at a time in
+// double-double, as in the real kernel; their Im F(z) > 0 flags come from the
+// fp64 evaluation.  Lanes past the tile's end take a placeholder point that is
+// neither accumulated, counted nor queued.
+template <int NV, int KM, int MODE>
+__device__ __forceinline__ void run_tile_cplx_ddq(const TileArgs& A, const CplxArgs& X, CSec* S,
+                                                  const TileDesc& td, int tc, const double* __restrict__ lgrid,
+                                                  uint32_t* q, double (&sr)[KM], double (&cr)[KM], double (&si)[KM],
+                                                  double (&ci)[KM], int& nonfin, int& npos) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;   // lanes under this one
+  const SDI_TAPE CplxDev* cx = tape(X.cx) + td.sector;
+  const int ns = S->ns;
+  int qn = 0;   // queued entries of this wave (wave-uniform)
+  for (uint32_t base = 0; base < td.count; base += blockDim.x) {
+    asm volatile("" ::: "memory");
+    const uint32_t off = base + threadIdx.x;
+    const bool act = off < td.count;
+    double x[1][NV], w[1];
+    if (act) {
+      load_point_cplx<NV, MODE>(A, S, td, tc, lgrid, off, x, w);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NV; ++j) x[0][j] = 0.5;
+      w[0] = 0.0;
+    }
+    cd f[1][KM];
+    int imf[1];
+    eval_f_cplx<NV, 1, KM>(S, cx, tape(X.dir), tape(A.terms), x, f, imf);
+    const bool flag = act && near_face<NV>(x[0], ns, A.small_x);
+    if (act) npos += imf[0];
+    if (act && !flag) {
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        const double vr = w[0] * f[0][k].re;
+        const double vi = w[0] * f[0][k].im;
+        two_sum_acc(sr[k], cr[k], vr);
+        two_sum_acc(si[k], ci[k], vi);
+        bad |= !isfinite(vr) || !isfinite(vi);
+      }
+      nonfin += bad ? 1 : 0;
+    }
+    // queue the flagged points of this round: qn < 64 here, so qn + 64 <= DDQ_CAP
+    const uint64_t bal = __ballot(flag);
+    if (flag) q[qn + __popcll(bal & below)] = off;
+    qn += __popcll(bal);
+    if (qn >= 64) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      dd_flush_cplx<NV, KM, MODE>(A, X, S, td, tc, lgrid, q, 64, sr, cr, si, ci, nonfin);
+      // move the rest (fewer than 64) to the front: lane l reads 64 + l, writes l
+      const uint32_t rest = lane < qn - 64 ? q[64 + lane] : 0u;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane < qn - 64) q[lane] = rest;
+      qn -= 64;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  if (qn > 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    dd_flush_cplx<NV, KM, MODE>(A, X, S, td, tc, lgrid, q, qn, sr, cr, si, ci, nonfin);
+  }
+}
+
 // Double-double sum over the 64 lanes of a wave (every lane ends with the total).
 __device__ __forceinline__ void wave_dd_reduce(double hi, double lo, double& ohi, double& olo) {
 #pragma unroll
@@ -84,12 +202,16 @@ __device__ __forceinline__ void wave_dd_reduce(double hi, double lo, double& ohi
 
 // WPE: minimum waves per SIMD the register allocation must allow (1 = no
 // constraint; 2 trades some scratch spills for twice the waves).
-template <int NVMAX, int PPT, int KM, int MODE, int WPE>
+// DD: the endpoint-precision instances (final pass on lattice or explicit
+// points, one point per thread; points below A.small_x again in double-double).
+template <int NVMAX, int PPT, int KM, int MODE, int WPE, bool DD = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_tiles_cplx(TileArgs A,
                                                                                                  CplxArgs X) {
   extern __shared__ double smem[];
   __shared__ int s_tile, s_nonfin, s_pos;
   __shared__ double s_red[BLOCK / 64][KM][4];
+  __shared__ uint32_t s_q[DD ? (BLOCK / 64) * DDQ_CAP : 1];
+  static_assert(!DD || (PPT == 1 && MODE != 1), "endpoint precision is a final-pass mode, one point per thread");
   constexpr int NVC = NVMAX <= 4 ? 0 : 1;
   for (;;) {
     __syncthreads();
@@ -125,18 +247,33 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
 #pragma unroll
     for (int k = 0; k < KM; ++k) { sr[k] = 0.0; cr[k] = 0.0; si[k] = 0.0; ci[k] = 0.0; }
     int nonfin = 0, npos = 0;
-    switch (S->cls) {
-      case 0:
-        run_tile_cplx<4, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
-        break;
-      case 1:
-        if constexpr (NVMAX == 6)
-          run_tile_cplx<6, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
-        else if constexpr (NVC >= 1)
-          run_tile_cplx<8, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
-        break;
-      default:
-        break;
+    if constexpr (DD) {
+      uint32_t* q = s_q + (threadIdx.x >> 6) * DDQ_CAP;
+      switch (S->cls) {
+        case 0:
+          run_tile_cplx_ddq<4, KM, MODE>(A, X, S, td, tc, lgrid, q, sr, cr, si, ci, nonfin, npos);
+          break;
+        case 1:
+          if constexpr (NVC >= 1)
+            run_tile_cplx_ddq<8, KM, MODE>(A, X, S, td, tc, lgrid, q, sr, cr, si, ci, nonfin, npos);
+          break;
+        default:
+          break;
+      }
+    } else {
+      switch (S->cls) {
+        case 0:
+          run_tile_cplx<4, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+          break;
+        case 1:
+          if constexpr (NVMAX == 6)
+            run_tile_cplx<6, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+          else if constexpr (NVC >= 1)
+            run_tile_cplx<8, PPT, KM, MODE>(A, X, S, td, tc, lgrid, lhist, sr, cr, si, ci, nonfin, npos);
+          break;
+        default:
+          break;
+      }
     }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -200,6 +337,12 @@ __device__ __forceinline__ void eval_point_cplx(const EvalArgs& A, const CplxArg
   else
     eval_f_cplx<NV, 1, KM>(S, tape(X.cx), tape(X.dir), tape(A.terms), x, f, imf);
   (void)imf;
+  if (A.small_x > 0.0 && near_face<NV>(x[0], S->ns, A.small_x)) {
+    double fr[KM], fi[KM];
+    eval_f_cplx_dd<KM>(S, tape(X.cx), tape(X.dir), tape(A.terms), x[0], fr, fi, cnd[0]);
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) f[0][kk] = cd{fr[kk], fi[kk]};
+  }
   for (int k = 0; k < K; ++k) {
     double fr = 0.0, fi = 0.0, cs = 0.0;
 #pragma unroll

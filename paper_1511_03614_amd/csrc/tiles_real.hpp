@@ -78,20 +78,37 @@ __device__ __forceinline__ void run_tile_real(const TileArgs& A, CSec* S,
 // each in double-double and add it to their own sums (compensated, so the
 // order does not matter).  A flagged point thus costs one lane of a full
 // double-double call instead of holding its whole wave in one.  q: this
-// wave's DDQ_CAP entries.
-constexpr int DDQ_CAP = 128;
+// wave's DDQ_CAP entries.  MODE 2 (explicit points of a learned sampler)
+// queues the point's offset in the tile's point list the same way.
 
-template <int NV, int PPT, int KM, int NSM>
-__device__ __forceinline__ void dd_flush(const TileArgs& A, CSec* S, const TileDesc& td,
+// One point per lane for the endpoint-precision instances: lattice point
+// td.i0 + off (MODE 0) or the tile's explicit point off (MODE 2).
+template <int NV, int MODE>
+__device__ __forceinline__ void load_point_real(const TileArgs& A, CSec* S, const TileDesc& td, int tc,
+                                                const double* __restrict__ lgrid, uint32_t off, double (&x)[1][NV],
+                                                double (&w)[1]) {
+  if constexpr (MODE == 2) {
+    const int n = S->n;
+    const double* xp = A.px + A.x_off[tc] + (size_t)off * n;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) x[0][j] = j < n ? xp[S->perm[j]] : 0.5;
+    w[0] = A.pw[A.pt_off[tc] + off];
+  } else {
+    CU64* zp = tape(A.zp) + (size_t)td.sector * MAXV;
+    CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
+    int bins[1][NV];
+    make_points<NV, 1>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+  }
+}
+
+template <int NV, int KM, int MODE>
+__device__ __forceinline__ void dd_flush(const TileArgs& A, CSec* S, const TileDesc& td, int tc,
                                          const double* __restrict__ lgrid, const uint32_t* q, int cnt,
                                          double (&s)[KM], double (&c)[KM], int& nonfin) {
   const int lane = threadIdx.x & 63;
   if (lane < cnt) {
-    CU64* zp = tape(A.zp) + (size_t)td.sector * MAXV;
-    CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
     double x[1][NV], w[1];
-    int bins[1][NV];
-    make_points<NV, 1>(S, zp, sh, lgrid, (uint64_t)td.i0 + q[lane], x, w, bins);
+    load_point_real<NV, MODE>(A, S, td, tc, lgrid, q[lane], x, w);
     double f[KM], cd[KM];
     eval_f_real_dd<KM>(S, tape(A.terms), x[0], f, cd);
     bool bad = false;
@@ -105,10 +122,13 @@ __device__ __forceinline__ void dd_flush(const TileArgs& A, CSec* S, const TileD
   }
 }
 
-template <int NV, int PPT, int KM, int NSM, int MF, int E7M>
-__device__ __forceinline__ void run_tile_real_ddq(const TileArgs& A, CSec* S, const TileDesc& td,
+// Explicit points (MODE 2) are read one per thread; lanes past the tile's end
+// take a placeholder point that is neither accumulated nor queued.
+template <int NV, int PPT, int KM, int MODE, int NSM, int MF, int E7M>
+__device__ __forceinline__ void run_tile_real_ddq(const TileArgs& A, CSec* S, const TileDesc& td, int tc,
                                                   const double* __restrict__ lgrid, uint32_t* q,
                                                   double (&s)[KM], double (&c)[KM], int& nonfin) {
+  static_assert(MODE != 2 || PPT == 1, "explicit points are read one per thread");
   const int lane = threadIdx.x & 63;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;   // lanes under this one
   const uint32_t step = (uint32_t)blockDim.x * PPT;
@@ -118,11 +138,21 @@ __device__ __forceinline__ void run_tile_real_ddq(const TileArgs& A, CSec* S, co
   for (uint32_t base = 0; base < td.count; base += step) {
     asm volatile("" ::: "memory");
     const uint32_t off = base + threadIdx.x * PPT;
-    CU64* zp = tape(A.zp) + (size_t)td.sector * MAXV;
-    CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
     double x[PPT][NV], w[PPT];
-    int bins[PPT][NV];
-    make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+    if constexpr (MODE == 2) {
+      if (off < td.count) {
+        load_point_real<NV, 2>(A, S, td, tc, lgrid, off, x, w);
+      } else {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) x[0][j] = 0.5;
+        w[0] = 0.0;
+      }
+    } else {
+      CU64* zp = tape(A.zp) + (size_t)td.sector * MAXV;
+      CU64* sh = tape(A.shifts) + ((size_t)S->shift_row + td.shift) * MAXV;
+      int bins[PPT][NV];
+      make_points<NV, PPT>(S, zp, sh, lgrid, (uint64_t)td.i0 + off, x, w, bins);
+    }
     double f[PPT][KM];
     eval_f_real<NV, PPT, KM, NSM, MF, E7M>(S, tape(A.terms), x, f);
 #pragma unroll
@@ -147,7 +177,7 @@ __device__ __forceinline__ void run_tile_real_ddq(const TileArgs& A, CSec* S, co
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        dd_flush<NV, PPT, KM, NSM>(A, S, td, lgrid, q, 64, s, c, nonfin);
+        dd_flush<NV, KM, MODE>(A, S, td, tc, lgrid, q, 64, s, c, nonfin);
         // move the rest (fewer than 64) to the front: lane l reads 64 + l, writes l
         const uint32_t rest = lane < qn - 64 ? q[64 + lane] : 0u;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -165,7 +195,7 @@ __device__ __forceinline__ void run_tile_real_ddq(const TileArgs& A, CSec* S, co
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    dd_flush<NV, PPT, KM, NSM>(A, S, td, lgrid, q, qn, s, c, nonfin);
+    dd_flush<NV, KM, MODE>(A, S, td, tc, lgrid, q, qn, s, c, nonfin);
   }
 }
 
@@ -174,7 +204,7 @@ __device__ __forceinline__ void run_tile_any(const TileArgs& A, CSec* S, const T
                                              const double* __restrict__ lgrid, double* __restrict__ lhist,
                                              uint32_t* q, double (&s)[KM], double (&c)[KM], int& nonfin) {
   if constexpr (DD)
-    run_tile_real_ddq<NV, PPT, KM, NSM, MF, E7M>(A, S, td, lgrid, q, s, c, nonfin);
+    run_tile_real_ddq<NV, PPT, KM, MODE, NSM, MF, E7M>(A, S, td, tc, lgrid, q, s, c, nonfin);
   else
     run_tile_real<NV, PPT, KM, MODE, NSM, MF, E7M>(A, S, td, tc, lgrid, lhist, s, c, nonfin);
 }
@@ -184,7 +214,8 @@ __device__ __forceinline__ void run_tile_any(const TileArgs& A, CSec* S, const T
 // NSM: bound on the singular variables of every sector of the launch (the
 // final pass has NSM = 2 instances for problems without deeper poles).
 // DD: points closer to a singular face than A.small_x are evaluated again in
-// double-double (the final-pass instances of the endpoint-precision mode).
+// double-double (the final-pass instances of the endpoint-precision mode, on
+// lattice points or on a learned sampler's explicit points).
 // MF: 0 evaluates each corner's term lists; 2 (problems whose sectors have at
 // most two regular factors) evaluates each term once by singular support.
 // E7M: 0 for problems whose factor exponents are at most 3, 1 for problems
@@ -197,7 +228,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
   __shared__ int s_nonfin;
   __shared__ double s_red[BLOCK / 64][KM][2];
   __shared__ uint32_t s_q[DD ? (BLOCK / 64) * DDQ_CAP : 1];
-  static_assert(!DD || MODE == 0, "endpoint precision is a final-pass mode");
+  static_assert(!DD || MODE != 1, "endpoint precision is a final-pass mode");
   constexpr int NVC = NVMAX <= 4 ? 0 : (NVMAX <= 8 ? 1 : 2);
   for (;;) {
     __syncthreads();

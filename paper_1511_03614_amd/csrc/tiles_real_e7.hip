@@ -2,8 +2,9 @@
 // above 3 (up to 7: the x^4 bit of the term words): per variable class one
 // generic instance (each corner's term lists, one point per thread, at least
 // 4 waves per SIMD) for the final pass, the Vegas warm-up and explicit points,
-// and the endpoint-precision final pass (every class, one point per thread, 2
-// waves per SIMD, points below small_x again in double-double).
+// and the endpoint-precision final pass (lattice or explicit points; every
+// class, one point per thread, 2 waves per SIMD, points below small_x again in
+// double-double).
 #include "kernels.h"
 #include "tiles_real.hpp"
 
@@ -11,14 +12,15 @@ namespace sdi {
 
 int launch_tiles_real_e7(int nvmax, int km, int grid, size_t shmem, const TileArgs& a, hipStream_t st) {
   const int mode = a.mode;
-  if (mode == 0 && a.small_x > 0.0) {
-    if (km == 4)
-      k_tiles_real<MAXV, 1, 4, 0, 2, MAXS, true, 0, 1><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a);
-    else if (km == 8)
-      k_tiles_real<MAXV, 1, 8, 0, 2, MAXS, true, 0, 1><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a);
-    else
-      return (int)hipErrorInvalidValue;
-    return (int)hipGetLastError();
+  if (mode != 1 && a.small_x > 0.0) {
+#define SDI_D(M, K)                                                                              \
+  if (mode == M && km == K) {                                                                    \
+    k_tiles_real<MAXV, 1, K, M, 2, MAXS, true, 0, 1><<<dim3(grid), dim3(BLOCK), shmem, st>>>(a); \
+    return (int)hipGetLastError();                                                               \
+  }
+    SDI_D(0, 4) SDI_D(0, 8) SDI_D(2, 4) SDI_D(2, 8)
+#undef SDI_D
+    return (int)hipErrorInvalidValue;
   }
 #define SDI_L(NV, M, K)                                                                      \
   if (mode == M && km == K) {                                                                \
@@ -44,13 +46,16 @@ int launch_tiles_real_e7(int nvmax, int km, int grid, size_t shmem, const TileAr
 
 int occupancy_tiles_real_e7(int nvmax, int mode, int km, bool dd, size_t shmem) {
   int nb = 0;
-  if (mode == 0 && dd) {
-    const hipError_t e =
-        km == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles_real<MAXV, 1, 4, 0, 2, MAXS, true, 0, 1>,
-                                                               BLOCK, shmem)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles_real<MAXV, 1, 8, 0, 2, MAXS, true, 0, 1>,
-                                                               BLOCK, shmem);
-    return e == hipSuccess ? nb : 0;
+  if (mode != 1 && dd) {
+#define SDI_D(M, K)                                                                                         \
+  if (mode == M && km == K)                                                                                 \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles_real<MAXV, 1, K, M, 2, MAXS, true, 0, 1>, \
+                                                        BLOCK, shmem) == hipSuccess                         \
+               ? nb                                                                                         \
+               : 0;
+    SDI_D(0, 4) SDI_D(0, 8) SDI_D(2, 4) SDI_D(2, 8)
+#undef SDI_D
+    return 0;
   }
 #define SDI_O(NV, M, K)                                                                                    \
   if (mode == M && km == K) {                                                                              \

@@ -70,7 +70,8 @@ def test_front_end_equals_input_tool(ctx, name):
 def test_front_end_errors(ctx):
     U, F = feynman.box_uf(3.0, 1.0)
     with pytest.raises(P.SdiError) as e:
-        P.sdi_problem_from_feynman(ctx, U, F, 1, (1, 1, 1, 1), 0, d0=2)     # a_j < -1 in some sector
+        P.sdi_problem_from_feynman(ctx, U, F, 1, (1, 1, 1, 1), 0, d0=2,     # a_j < -1, reduced in real mode only
+                                   complex_mode=True, lam=0.1)
     assert e.value.code == -4
     with pytest.raises(P.SdiError):
         P.sdi_problem_from_feynman(ctx, U, F, 1, (1, 1, 1, 1), 9)           # beyond 8 orders
