@@ -257,9 +257,9 @@ typedef struct {
 
 /* Compile the sectors of a Feynman integral (see sdi_feynman_desc).  Returns
  * SDI_EINVAL for malformed input or an order outside the 8 orders from the
- * leading pole, SDI_ENOTSUP where a sector exponent a_j < -1 appears (that
- * needs higher-order subtraction) or a decomposed sector leaves the library's
- * limits (sdi_problem_create). */
+ * leading pole, SDI_ENOTSUP where a decomposed sector leaves the library's
+ * limits or needs what sdi_problem_create does not do (the reduction of a
+ * sector exponent a_j < -1 in complex mode). */
 int sdi_problem_from_feynman(sdi_ctx* ctx, const sdi_feynman_desc* desc, sdi_problem** out);
 /* The same decomposition on the host only (no context, no device): the
  * number of sectors, the lowest result order and the variables per sector. */
@@ -273,21 +273,27 @@ int sdi_feynman_sectors(const sdi_feynman_desc* desc, int32_t* nsectors, int32_t
  * ';', then a line '|'.  Expressions use + - * /, round brackets, decimal
  * numbers, x[1] .. x[n], earlier f[i], p[base,exponent] (real power), l[arg]
  * (natural logarithm), P (pi), G (Euler's gamma) and the built-in values
- * PolyGamma[1,1], PolyGamma[2,1..4], PolyGamma[3,1..2].  The result is a
+ * PolyGamma[1,1], PolyGamma[2,1..4], PolyGamma[3,1..2].  A text that names
+ * the imaginary unit I is a complex integrand (the complex workers of section
+ * 4.2): every value is complex, l[a] is the principal logarithm with arg = -pi
+ * on the negative real axis, p[a,b] is a^b by products for a whole-number
+ * constant |b| <= 64 and exp(b l[a]) otherwise.  The result is a
  * problem of one sector and one order (order 0): sdi_integrate returns the
  * integral over [0,1]^n with the lattice sampler and optional Vegas warm-up
  * (not the flow sampler); sdi_evaluate gives the integrand at points (out
- * [npts][1][2], imaginary part 0); sdi_sample_points works as for sectors.
+ * [npts][1][2], imaginary part 0 for a real integrand); sdi_sample_points
+ * works as for sectors.
  * `text` is a NUL-terminated host string owned by the caller.  Returns
  * SDI_EINVAL for malformed text (the message names the offset),
  * SDI_ENOTSUP for PolyGamma arguments that are not built in, integrands of
- * more than 2^24 operations or ones that need more than 96 live temporaries,
- * SDI_EDEVICE if the upload fails. */
+ * more than 2^24 operations or ones that need more than 96 live temporaries
+ * (48 complex ones), SDI_EDEVICE if the upload fails. */
 int sdi_problem_from_text(sdi_ctx* ctx, const char* text, sdi_problem** out);
 
 /* Compiles text as sdi_problem_from_text does, on the host only (no context,
  * no device): *nvars, *ninstructions (tape length, a multiple of 8) and
- * *nslots (per-point slots) receive the result when not NULL; on failure the
+ * *nslots (per-point slots, complex ones for a complex integrand) receive the
+ * result when not NULL; on failure the
  * same status as sdi_problem_from_text and, if err is not NULL, the message
  * (at most errlen bytes with the NUL). */
 int sdi_text_info(const char* text, int32_t* nvars, int64_t* ninstructions, int32_t* nslots, char* err,

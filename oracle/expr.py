@@ -18,7 +18,13 @@ Readings (the paper gives the grammar only by example):
   than + and -; binary operators associate to the left;
 * p[a, b] is a real power: NaN for a < 0 unless b is a whole number, and l[a]
   is NaN for a < 0 (a real worker has no other value to give);
-* an optional first line ``Integrate`` (the worker command) is skipped.
+* an optional first line ``Integrate`` (the worker command) is skipped;
+* complex integrands (the complex workers of section 4.2): the text names the
+  imaginary unit as ``I`` (as the Mathematica side writes it).  Such an
+  integrand is complex throughout: l[a] is the principal logarithm with
+  arg = -pi on the negative real axis (the side an F - i0 prescription
+  approaches), p[a, b] is a^k by repeated products for a whole number
+  |b| <= 64 and exp(b l[a]) otherwise.  Without ``I`` nothing changes.
 
 ``evaluate`` returns the values at the given points and, per point, a
 rounding bound ``cond``: the sum over every operation of the magnitude its
@@ -79,6 +85,7 @@ class _Parser:
         self.i = 0
         self.n = nvars
         self.nf = nfuncs
+        self.complex = False
 
     def peek(self):
         return self.t[self.i] if self.i < len(self.t) else (None, None)
@@ -170,6 +177,9 @@ class _Parser:
                 return ("pow", a, b)
             self.take("op", "]")
             return ("log", a)
+        if v == "I":
+            self.complex = True
+            return ("const", 1j)
         if v in ("P", "Pi"):
             return ("const", math.pi)
         if v in ("G", "EulerGamma"):
@@ -189,10 +199,11 @@ class _Parser:
 class Expression:
     """A parsed integrand: ``n`` variables, intermediate functions, the integrand tree."""
 
-    def __init__(self, n, funcs, body):
+    def __init__(self, n, funcs, body, complex_=False):
         self.n = n
         self.funcs = funcs
         self.body = body
+        self.complex = complex_
 
 
 def parse(text: str) -> Expression:
@@ -221,9 +232,69 @@ def parse(text: str) -> Expression:
     m = count(lines[1], 0, 1 << 20, "the number of intermediate functions")
     if len(lines) != 3 + m:
         raise ParseError(f"expected {m} intermediate functions and one integrand, found {len(lines) - 2} lines")
-    funcs = [_Parser(lines[2 + i], n, i).parse() for i in range(m)]
-    body = _Parser(lines[2 + m], n, m).parse()
-    return Expression(n, funcs, body)
+    parsers = [_Parser(lines[2 + i], n, i) for i in range(m)] + [_Parser(lines[2 + m], n, m)]
+    trees = [q.parse() for q in parsers]
+    return Expression(n, trees[:-1], trees[-1], any(q.complex for q in parsers))
+
+
+def _log_mi0(a):
+    """Principal complex logarithm, arg = -pi where a is real and negative."""
+    ang = np.where((a.imag == 0.0) & (a.real < 0.0), -np.pi, np.angle(a))
+    return np.log(np.abs(a)) + 1j * ang
+
+
+def _apply_c(node, args, x, fvals):
+    """(value, cond) of one node of a complex integrand (first-order bounds in
+    units of u: the operands' bounds carried through, plus each operation's own
+    rounding - a complex product about 3 |a||b|, a quotient 5 |v|, a logarithm
+    |v| + 4, exp(b l[a]) |v| (3 + 3 |b l[a]|) and products |v| (3 |b| + 1))."""
+    op = node[0]
+    if op == "const":
+        v = np.full(x.shape[0], complex(node[1]))
+        return v, np.zeros(x.shape[0])
+    if op == "x":
+        v = x[:, node[1]].astype(np.complex128)
+        return v, np.zeros(x.shape[0])
+    if op == "f":
+        return fvals[node[1]]
+    if op == "neg":
+        a, ca = args[0]
+        return -a, ca
+    if op == "log":
+        a, ca = args[0]
+        v = _log_mi0(a)
+        return v, ca / np.abs(a) + np.abs(v) + 4.0
+    (a, ca), (b, cb) = args
+    if op == "+":
+        v = a + b
+        return v, ca + cb + np.abs(v)
+    if op == "-":
+        v = a - b
+        return v, ca + cb + np.abs(v)
+    if op == "*":
+        v = a * b
+        return v, ca * np.abs(b) + np.abs(a) * cb + 3.0 * np.abs(a) * np.abs(b)
+    if op == "/":
+        v = a / b
+        return v, ca / np.abs(b) + np.abs(a) * cb / np.abs(b) ** 2 + 5.0 * np.abs(v)
+    if op == "pow":
+        la = _log_mi0(a)
+        whole = bool(np.all(b.imag == 0.0) and np.all(b.real == np.round(b.real)) and np.all(np.abs(b) <= 64))
+        if whole:
+            k = int(b.real[0]) if b.size else 0
+            if not np.all(b.real == k):
+                whole = False
+        if whole:
+            v = np.ones_like(a)
+            for _ in range(abs(k)):
+                v = v * a
+            if k < 0:
+                v = 1.0 / v
+        else:
+            v = np.exp(b * la)
+        own = np.abs(v) * (3.0 * np.abs(b) + 1.0 + 3.0 + 3.0 * np.abs(b * la))
+        return v, np.abs(v) * (np.abs(b) * ca / np.abs(a) + np.abs(la) * cb) + own
+    raise AssertionError(op)
 
 
 def _apply(node, args, x, fvals):
@@ -267,9 +338,10 @@ def _apply(node, args, x, fvals):
     raise AssertionError(op)
 
 
-def _eval(tree, x, fvals):
+def _eval(tree, x, fvals, apply=None):
     """(value, cond) arrays of a tree at the points x (npts, n), without recursion
     (left-nested sums of long integrands are deeper than Python's stack)."""
+    apply = apply or _apply
     out = []
     stack = [(tree, False)]
     while stack:
@@ -279,7 +351,7 @@ def _eval(tree, x, fvals):
             args = out[len(out) - nargs:] if nargs else []
             if nargs:
                 del out[len(out) - nargs:]
-            out.append(_apply(node, args, x, fvals))
+            out.append(apply(node, args, x, fvals))
             continue
         stack.append((node, True))
         for child in reversed(node[1:1 + nargs]):
@@ -288,13 +360,15 @@ def _eval(tree, x, fvals):
 
 
 def evaluate(expr: Expression, x: np.ndarray):
-    """Integrand values and rounding bounds (units of u) at points x (npts, n)."""
+    """Integrand values (complex for a complex integrand) and rounding bounds
+    (units of u) at points x (npts, n)."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     if x.ndim != 2 or x.shape[1] != expr.n:
         raise ValueError("x must be (npts, n)")
+    apply = _apply_c if expr.complex else _apply
     with np.errstate(all="ignore"):
         fvals = []
         for f in expr.funcs:
-            fvals.append(_eval(f, x, fvals))
-        v, c = _eval(expr.body, x, fvals)
+            fvals.append(_eval(f, x, fvals, apply))
+        v, c = _eval(expr.body, x, fvals, apply)
     return v, c

@@ -625,7 +625,7 @@ int sdi_evaluate(sdi_ctx* ctx, const sdi_problem* pb, int32_t s, const void* x_d
   A.cond = (double*)cond_dev;
   A.small_x = pb->is_expr() ? 0.0 : ctx->params.small_x;
   if (pb->is_expr())
-    KCHK(ctx, launch_eval_points_expr(A, ExprArgs{pb->d_expr, (int32_t)pb->expr_nins, pb->expr_slots, pb->expr_out},
+    KCHK(ctx, launch_eval_points_expr(A, ExprArgs{pb->d_expr, (int32_t)pb->expr_nins, pb->expr_slots, pb->expr_out, pb->expr_cplx ? 1 : 0},
                                       ctx->stream));
   else if (pb->complex_mode)
     KCHK(ctx, launch_eval_points_cplx(pb->kfmax <= 4 ? 4 : 8, A, pb->d_cx + s, pb->d_dir, ctx->stream));

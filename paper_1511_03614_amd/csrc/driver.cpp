@@ -101,7 +101,7 @@ struct PassState {
 
 // The expression tape of a problem given as text.
 ExprArgs expr_args(const sdi_problem* pb) {
-  return ExprArgs{pb->d_expr, (int32_t)pb->expr_nins, pb->expr_slots, pb->expr_out};
+  return ExprArgs{pb->d_expr, (int32_t)pb->expr_nins, pb->expr_slots, pb->expr_out, pb->expr_cplx ? 1 : 0};
 }
 
 void free_passes(std::vector<PassState*>& v) {

@@ -5,6 +5,8 @@
 // decimal numbers, x[i] (variables), f[i] (earlier intermediate functions),
 // p[base,exponent] (power), l[arg] (natural logarithm), P (pi), G (Euler's
 // gamma) and PolyGamma[m,z] for the handful of arguments the paper lists.
+// An integrand that uses the imaginary unit I (the complex workers of section
+// 4.2) compiles to a complex tape (expr_types.h).
 //
 // The text is parsed into a DAG with shared subexpressions merged and
 // constant subtrees folded, then linearised into an expression tape whose
@@ -25,7 +27,7 @@
 namespace sdi {
 namespace {
 
-enum NodeOp : int { N_CONST, N_VAR, N_ADD, N_SUB, N_MUL, N_DIV, N_NEG, N_LOG, N_POWI, N_POW };
+enum NodeOp : int { N_CONST, N_VAR, N_ADD, N_SUB, N_MUL, N_DIV, N_NEG, N_LOG, N_POWI, N_POW, N_IUNIT };
 
 struct Node {
   int op;
@@ -56,15 +58,32 @@ class Compiler {
  public:
   std::vector<Node> nodes;
   bool share = true;   // merge repeated operations (leaves are always merged)
+  bool cplx = false;   // complex tape: logarithms and powers of negative constants are not folded
 
   int constant(double v) { return add(Node{N_CONST, -1, -1, 0, v}); }
   int variable(int j) { return add(Node{N_VAR, j, -1, 0, 0.0}); }
+  int iunit() { return add(Node{N_IUNIT, -1, -1, 0, 0.0}); }
 
-  // Folds constant operands; merges identical nodes.
+  // Folds constant operands (real results only); merges identical nodes.
   int op2(int op, int a, int b, int k = 0) {
     const Node& A = nodes[a];
     const bool ca = A.op == N_CONST;
     const bool cb = b >= 0 && nodes[b].op == N_CONST;
+    // the complex value of a logarithm, or of a constant power, of a negative
+    // constant (arg -pi): re + im I with real constants
+    if (cplx && ca && A.imm < 0.0 && (op == N_LOG || (op == N_POW && cb))) {
+      const double x = A.imm;
+      double re, im;
+      if (op == N_LOG) {
+        re = std::log(-x);
+        im = -3.14159265358979323846;
+      } else {
+        const double y = nodes[b].imm, m = std::pow(-x, y);
+        re = m * std::cos(3.14159265358979323846 * y);
+        im = -m * std::sin(3.14159265358979323846 * y);
+      }
+      return op2(N_ADD, constant(re), op2(N_MUL, constant(im), iunit()));
+    }
     if (ca && (b < 0 || cb)) {
       const double x = A.imm, y = b >= 0 ? nodes[b].imm : 0.0;
       double v = 0.0;
@@ -120,6 +139,15 @@ class Parser {
  public:
   Parser(const std::string& text, size_t begin, size_t end, int nvars, const std::vector<int>& fnodes, Compiler& c)
       : s_(text), p_(begin), end_(end), n_(nvars), f_(fnodes), c_(c) {}
+
+  // Whether [begin, end) of the text names the imaginary unit I.
+  static bool mentions_i(const std::string& t, size_t begin, size_t end) {
+    for (size_t p = begin; p < end; ++p)
+      if (t[p] == 'I' && (p == begin || !std::isalnum((unsigned char)t[p - 1])) &&
+          (p + 1 == end || !std::isalnum((unsigned char)t[p + 1])))
+        return true;
+    return false;
+  }
 
   int parse() {
     const int v = expr();
@@ -280,6 +308,7 @@ class Parser {
       expect(']');
       return c_.op2(N_LOG, v, -1);
     }
+    if (word("I")) return c_.iunit();
     if (word("Pi") || word("P")) return c_.constant(3.14159265358979323846);
     if (word("EulerGamma") || word("G")) return c_.constant(0.57721566490153286061);
     fail("unknown symbol");
@@ -326,9 +355,11 @@ std::vector<std::pair<size_t, size_t>> statements(const std::string& t, size_t f
 // to a tape in depth-first order: dead nodes dropped, constants carried in
 // their users' immediate, slots assigned by liveness.
 int lower(const std::string& text, const std::vector<std::pair<size_t, size_t>>& st, int n, long m, bool share,
-          std::vector<ExprIns>& tape, int& nslots, int& out) {
+          bool cplx, std::vector<ExprIns>& tape, int& nslots, int& out) {
   Compiler e;
   e.share = share;
+  e.cplx = cplx;
+  const int max_slots = cplx ? EXPR_MAX_SLOTS_CPLX : EXPR_MAX_SLOTS;
   for (int j = 0; j < n; ++j) e.variable(j);
   std::vector<int> fn;
   for (long i = 0; i < m; ++i) {
@@ -344,7 +375,7 @@ int lower(const std::string& text, const std::vector<std::pair<size_t, size_t>>&
   live[root] = 1;
   for (int i = N - 1; i >= 0; --i) {
     if (!live[i] || leaf(i)) continue;
-    live[e.nodes[i].a] = 1;
+    if (e.nodes[i].a >= 0) live[e.nodes[i].a] = 1;   // X_IUNIT has no operand
     if (e.nodes[i].b >= 0) live[e.nodes[i].b] = 1;
   }
   // operations in dependency (creation) order
@@ -372,9 +403,9 @@ int lower(const std::string& text, const std::vector<std::pair<size_t, size_t>>&
     } else {
       sl = top++;
     }
-    if (sl >= EXPR_MAX_SLOTS)
-      throw ParseError{SDI_ENOTSUP, "the integrand needs more than " + std::to_string(EXPR_MAX_SLOTS) +
-                                        " live temporaries", true};
+    if (sl >= max_slots)
+      throw ParseError{SDI_ENOTSUP, "the integrand needs more than " + std::to_string(max_slots) +
+                                        (cplx ? " live complex temporaries" : " live temporaries"), true};
     return sl;
   };
   tape.clear();
@@ -394,10 +425,13 @@ int lower(const std::string& text, const std::vector<std::pair<size_t, size_t>>&
         case N_NEG: I.op = X_NEG; break;
         case N_LOG: I.op = X_LOG; break;
         case N_POWI: I.op = X_POWI; break;
+        case N_IUNIT: I.op = X_IUNIT; break;
         default: I.op = X_POW; break;
       }
       // constant operands ride in imm (folding leaves at most one per operation)
-      if (e.nodes[d.a].op == N_CONST) {
+      if (d.a < 0) {
+        // no operand
+      } else if (e.nodes[d.a].op == N_CONST) {
         I.op |= X_IMMA;
         I.imm = e.nodes[d.a].imm;
       } else {
@@ -450,7 +484,8 @@ int lower(const std::string& text, const std::vector<std::pair<size_t, size_t>>&
 
 // Compiles the text into a tape; n receives the number of variables.
 int compile_expression(const std::string& text, int& n, std::vector<ExprIns>& tape, int& nslots, int& out,
-                       std::string& err) {
+                       bool& cplx, std::string& err) {
+  cplx = false;
   try {
     size_t start = 0;
     {
@@ -476,14 +511,15 @@ int compile_expression(const std::string& text, int& n, std::vector<ExprIns>& ta
     if (st.size() != (size_t)(3 + m))
       throw ParseError{SDI_EINVAL, "expected " + std::to_string(m) + " intermediate functions and one integrand, found " +
                                        std::to_string(st.size() - 2) + " lines"};
+    for (size_t i = 2; i < st.size(); ++i) cplx = cplx || Parser::mentions_i(text, st[i].first, st[i].second);
     // Merged repeated operations keep their values alive until the last use; if
     // that needs too many slots, compile again sharing only leaves and f[i].
     try {
-      return lower(text, st, n, m, true, tape, nslots, out);
+      return lower(text, st, n, m, true, cplx, tape, nslots, out);
     } catch (const ParseError& pe) {
       if (!pe.slots) throw;
     }
-    return lower(text, st, n, m, false, tape, nslots, out);
+    return lower(text, st, n, m, false, cplx, tape, nslots, out);
   } catch (const ParseError& pe) {
     err = pe.msg;
     return pe.code;
@@ -499,9 +535,10 @@ extern "C" int sdi_text_info(const char* text, int32_t* nvars, int64_t* ninstruc
   if (err && errlen) err[0] = '\0';
   if (!text) return SDI_EINVAL;
   int n = 0, ns = 0, oslot = 0;
+  bool cplx = false;
   std::vector<ExprIns> tape;
   std::string msg;
-  const int rc = compile_expression(std::string(text), n, tape, ns, oslot, msg);
+  const int rc = compile_expression(std::string(text), n, tape, ns, oslot, cplx, msg);
   if (rc != SDI_OK) {
     if (err && errlen) snprintf(err, errlen, "%s", msg.c_str());
     return rc;
@@ -516,9 +553,10 @@ extern "C" int sdi_problem_from_text(sdi_ctx* ctx, const char* text, sdi_problem
   if (!ctx || !text || !out) return fail(ctx, SDI_EINVAL, "problem_from_text: null argument");
   *out = nullptr;
   int n = 0, nslots = 0, oslot = 0;
+  bool cplx = false;
   std::vector<ExprIns> tape;
   std::string err;
-  const int rc = compile_expression(std::string(text), n, tape, nslots, oslot, err);
+  const int rc = compile_expression(std::string(text), n, tape, nslots, oslot, cplx, err);
   if (rc != SDI_OK) return fail(ctx, rc, "problem_from_text: " + err);
   sdi_problem* pb = new sdi_problem();
   pb->ctx = ctx;
@@ -530,6 +568,7 @@ extern "C" int sdi_problem_from_text(sdi_ctx* ctx, const char* text, sdi_problem
   pb->expr = tape;
   pb->expr_slots = nslots;
   pb->expr_out = oslot;
+  pb->expr_cplx = cplx;
   SecDev R{};
   R.n = n;
   R.ns = 0;

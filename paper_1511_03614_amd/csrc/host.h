@@ -209,5 +209,6 @@ struct sdi_problem {
   sdi::ExprIns* d_expr = nullptr;
   size_t expr_nins = 0;
   int expr_slots = 0, expr_out = 0;
+  bool expr_cplx = false;          // complex tape (the text uses I)
   bool is_expr() const { return d_expr != nullptr; }
 };

@@ -55,17 +55,45 @@ def _pos(rng: SplitMix64, n: int, nf: int, depth: int) -> str:
     return f"({a}+{b})/{_num(rng)}"
 
 
-def random_text(seed: int, n: int, nfuncs: int = 2, depth: int = 4, terms: int = 3) -> str:
+def _complex_term(rng: SplitMix64, e: str) -> str:
+    """A complex expression around e (a real positive or a complex expression
+    whose real part stays positive): the imaginary unit I, logarithms and a
+    power of a real negative argument (the branch below the cut), and
+    arguments kept off the negative real axis otherwise."""
+    c = _num(rng)
+    k = rng.randint(0, 5)
+    if k == 0:
+        return f"{c}*I*{e}"
+    if k == 1:
+        return f"p[{e}+{c}*I,{rng.choice(['2', '-1', '0.5', '-1.5'])}]"
+    if k == 2:
+        return f"l[{e}-{c}-2]"                 # real and negative: arg -pi
+    if k == 3:
+        return f"l[{e}+{c}*I]"
+    if k == 4:
+        return f"p[-{e}-{c},0.5]*{e}"          # the square root of a negative real value
+    return f"{e}/({e}+{c}*I)"
+
+
+def random_text(seed: int, n: int, nfuncs: int = 2, depth: int = 4, terms: int = 3, complex_: bool = False) -> str:
     """n variables, nfuncs intermediate functions, an integrand of ``terms``
-    signed terms of positive subexpressions of the given depth."""
+    signed terms of positive subexpressions of the given depth; with complex_,
+    every other intermediate function gets an imaginary part c*I, every term a
+    complex form (the imaginary unit, logarithms and powers on or off the
+    negative real axis) and the integrand a last term c*I."""
     rng = SplitMix64(seed)
     lines: List[str] = [f"{n};", f"{nfuncs};"]
     for i in range(nfuncs):
-        lines.append(_pos(rng, n, i, depth) + ";")
+        e = _pos(rng, n, i, depth)
+        lines.append((f"{e}+{_num(rng)}*I" if complex_ and i % 2 == 0 else e) + ";")
     parts = []
     for t in range(terms):
         e = _pos(rng, n, nfuncs, depth)
+        if complex_:
+            e = _complex_term(rng, e)
         parts.append(("-" if t and rng.uniform() < 0.3 else "+" if t else "") + e)
+    if complex_:
+        parts.append(f"+{_num(rng)}*I")       # the text names I even where no term does
     lines.append("".join(parts) + ";")
     lines.append("|")
     return "\n".join(lines) + "\n"

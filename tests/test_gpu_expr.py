@@ -4,7 +4,8 @@ text oracle (oracle/expr.py) on identical points.
 Bars: per point |gpu - oracle| <= 1e-12 |oracle| + 8 u cond (cond: the
 oracle's running rounding bound, u = 2^-53); per (shift) mean <= 1e-10 of
 max(|mean|, mean |w f|), widened to the shift's mean rounding bound where that
-is larger; closed-form integrals within 5 standard errors."""
+is larger; closed-form integrals within 5 standard errors.  The same for
+complex integrands (the text uses I), real and imaginary parts together."""
 import math
 
 import numpy as np
@@ -211,3 +212,92 @@ def test_text_errors_are_reported(ctx):
         assert ei.value.code == -4
     finally:
         P.sdi_problem_destroy(h)
+
+
+
+# ---------------------------------------------------------------- complex integrands
+
+def complex_texts():
+    out = [("branch", "1;0;l[x[1]-2]+p[x[1]-3,0.5]+0*I;|"),
+           ("constant log", "1;0;l[-1]*x[1]+p[-4,0.5]+I;|"),
+           ("quotient", "2;1;x[1]+I*x[2];p[f[1],3]/(f[1]+2*I)-l[f[1]];|")]
+    for seed in range(8):
+        n = 1 + (3 * seed) % 12
+        out.append((f"random complex {seed} (n={n})",
+                    textgen.random_text(300 + seed, n, nfuncs=seed % 3, depth=2 + seed % 2, terms=1 + seed % 3,
+                                        complex_=True)))
+    out.append(("1000 complex terms", textgen.random_text(777, 5, nfuncs=4, depth=2, terms=1000, complex_=True)))
+    return out
+
+
+def test_complex_pointwise_matches_oracle(ctx):
+    rng = np.random.default_rng(17)
+    fr = []
+    for name, text in complex_texts():
+        e = E.parse(text)
+        assert e.complex, name
+        x = rng.uniform(1e-4, 1.0, size=(1000, e.n))
+        h = P.sdi_problem_from_text(ctx, text)
+        try:
+            g = P.sdi_evaluate(ctx, h, 0, torch.from_numpy(x).cuda()).cpu().numpy()
+        finally:
+            P.sdi_problem_destroy(h)
+        v, c = E.evaluate(e, x)
+        gv = g[:, 0, 0] + 1j * g[:, 0, 1]
+        d = np.abs(gv - v)
+        ok = d <= 1e-12 * np.abs(v) + 8 * U * c
+        assert ok.all(), f"{name}: {np.argwhere(~ok)[:5].ravel()} max rel {np.max(d / np.abs(v))}"
+        fr.append((d <= 1e-12 * np.abs(v)).mean())
+    log(f"complex text integrands: strict-clause fraction min {min(fr):.4f}")
+
+
+def oracle_shifts_c(text, m, R, seed):
+    e = E.parse(text)
+    z = points.cbc_vector(m, e.n)
+    sh = points.shift_table(seed, 0, R, e.n, m)
+    q, scale, bound = np.zeros(R, complex), 0.0, np.zeros(R)
+    for r in range(R):
+        x, w, _ = points.sector_points(z, m, sh[r], 0, 1 << m, None, True)
+        v, c = E.evaluate(e, x)
+        q[r] = complex(math.fsum((v * w).real), math.fsum((v * w).imag)) / (1 << m)
+        scale = max(scale, float(np.mean(np.abs(v * w))))
+        bound[r] = 8 * U * float(np.mean(c * w))
+    return q, scale, bound
+
+
+@pytest.mark.parametrize("case", [0, 2, 5, 9])
+def test_complex_integrate_matches_oracle(ctx, case):
+    name, text = complex_texts()[case]
+    m, R, seed = 12, 8, 4
+    set_params(ctx, lattice_log2=m, shifts=R, seed=seed, tile_log2=0)
+    h = P.sdi_problem_from_text(ctx, text)
+    try:
+        res = P.sdi_integrate(ctx, h)
+        _, _, per, nev = P.sdi_sector_results(ctx, h, 0, R)
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
+    assert nev == R << m and res["n_nonfinite"] == 0
+    q, scale, bound = oracle_shifts_c(text, m, R, seed)
+    tol = np.maximum(1e-10 * np.maximum(np.abs(q), scale), bound)
+    d = np.abs(per[:, 0] - q)
+    assert np.all(d <= tol), f"{name}: max d/tol {np.max(d / tol)}"
+    mean = q.mean()
+    assert abs(res["value"][0] - mean) <= max(1e-10 * max(abs(mean), scale), bound.mean())
+
+
+@pytest.mark.parametrize("text,exact", [
+    ("1;0;1/(x[1]+I);|", 0.5 * math.log(2.0) - 0.25j * math.pi),
+    ("1;0;l[x[1]-2]+0*I;|", 2.0 * math.log(2.0) - 1.0 - 1j * math.pi),
+    ("2;1;x[1]*I-x[2];p[f[1],2];|", -0.5j),
+])
+def test_complex_closed_form_integrals(ctx, text, exact):
+    set_params(ctx, lattice_log2=14, shifts=16, seed=9, warmup=1)
+    h = P.sdi_problem_from_text(ctx, text)
+    try:
+        res = P.sdi_integrate(ctx, h)
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
+    v, er, ei = res["value"][0], res["err_re"][0], res["err_im"][0]
+    assert abs(v.real - exact.real) <= 5 * er + 1e-12 and abs(v.imag - exact.imag) <= 5 * ei + 1e-12, (v, er, ei)

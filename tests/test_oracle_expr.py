@@ -1,7 +1,10 @@
 """Pins of the text-integrand oracle (oracle/expr.py) against values fixed by the
 paper's format and by mathematics: literal arithmetic, the built-in constants,
 closed-form integrals (the paper's own example among them) and the sector
-oracle's eps expansion of the massless bubble."""
+oracle's eps expansion of the massless bubble; complex integrands (the text
+uses I) against closed-form integrals that fix the branch of the logarithm
+and of non-integer powers on the negative real axis, and their rounding bound
+against a reordered evaluation."""
 import math
 
 import numpy as np
@@ -114,6 +117,48 @@ def test_rounding_bound_covers_a_reordered_evaluation():
     x = rng.uniform(0.01, 1.0, size=(256, 3))
     a = E.parse("3;0;(x[1]+x[2]+x[3])*(x[1]-x[2])/(1+x[3]);|")
     b = E.parse("3;0;(x[3]+(x[2]+x[1]))*(x[1]-x[2])/(x[3]+1);|")
+    va, ca = E.evaluate(a, x)
+    vb, _ = E.evaluate(b, x)
+    assert np.all(np.abs(va - vb) <= 2 * 2.0 ** -53 * ca)
+
+
+# ---------------------------------------------------------------- complex integrands
+
+def gl_integral(text, nodes=40):
+    """Integral over [0,1]^n of the oracle's values by tensor Gauss-Legendre quadrature."""
+    e = E.parse(text)
+    t, w = np.polynomial.legendre.leggauss(nodes)
+    t, w = 0.5 * (t + 1.0), 0.5 * w
+    grids = np.meshgrid(*([t] * e.n), indexing="ij")
+    wts = np.meshgrid(*([w] * e.n), indexing="ij")
+    x = np.stack([g.ravel() for g in grids], axis=1)
+    ww = np.prod(np.stack([g.ravel() for g in wts], axis=1), axis=1)
+    v, _ = E.evaluate(e, x)
+    return e, complex(np.sum(v * ww))
+
+
+@pytest.mark.parametrize("text,exact", [
+    ("1;0;p[x[1]+I,2];|", -2.0 / 3.0 + 1j),                                   # (x + i)^2
+    ("1;0;1/(x[1]+I);|", 0.5 * math.log(2.0) - 0.25j * math.pi),              # Log(1 + i) - Log(i)
+    ("1;0;p[x[1]+I,0.5];|", 2.0 / 3.0 * ((1 + 1j) ** 1.5 - 1j ** 1.5)),       # principal square root
+    ("1;0;l[x[1]-2]+0*I;|", 2.0 * math.log(2.0) - 1.0 - 1j * math.pi),        # negative argument: arg -pi
+    ("1;0;p[x[1]-2,-0.5]*I;|", 1j * 2.0 * (math.sqrt(2.0) - 1.0) * 1j),        # (x-2)^(-1/2) = i |x-2|^(-1/2)
+    ("2;1;x[1]*I-x[2];p[f[1],2];|", -0.5j),                                   # (i x - y)^2
+    # Log(-1 - i x) = ln(1 + x^2)/2 + i (atan x - pi): third quadrant, arg -pi at x = 0
+    ("2;0;x[2]*l[-1-x[1]*I];|", 0.5 * (0.5 * (math.log(2.0) - 2.0 + math.pi / 2.0)
+                                        - 1j * (0.75 * math.pi + 0.5 * math.log(2.0)))),
+])
+def test_complex_closed_form_integrals(text, exact):
+    e, got = gl_integral(text)
+    assert e.complex
+    assert abs(got - exact) <= 1e-12 * max(1.0, abs(exact)), (got, exact)
+
+
+def test_complex_rounding_bound_covers_a_reordered_evaluation():
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0.01, 1.0, size=(256, 3))
+    a = E.parse("3;0;(x[1]+I*x[2]+x[3])*(x[1]-I*x[2])/(1+I*x[3])*l[x[2]-x[1]-I*x[3]];|")
+    b = E.parse("3;0;(x[3]+(x[2]*I+x[1]))*(x[1]-x[2]*I)/(x[3]*I+1)*l[(x[2]-x[1])-x[3]*I];|")
     va, ca = E.evaluate(a, x)
     vb, _ = E.evaluate(b, x)
     assert np.all(np.abs(va - vb) <= 2 * 2.0 ** -53 * ca)

@@ -62,3 +62,26 @@ def test_paper_sized_integrand_fits_the_slot_budget():
     info = P.sdi_text_info(text)
     assert info["nvars"] == 6 and info["nslots"] <= 96 and info["ninstructions"] % 8 == 0
     assert 20_000 < info["ninstructions"] < 40_000
+
+
+def test_complex_integrands_compile_within_the_complex_slot_budget():
+    """A text that names I compiles to a complex tape: at most 48 complex slots
+    (the LDS of 96 real ones); I is one operation, shared; logarithms and
+    powers of negative constants fold into re + im I."""
+    info = P.sdi_text_info("1;0;x[1]+I;|")
+    assert info["nvars"] == 1 and info["ninstructions"] == 8 and info["nslots"] == 2   # i, then x + i in its slot
+    assert P.sdi_text_info("1;0;I*x[1]+I*I;|")["ninstructions"] == 8                  # i once: 4 operations
+    assert P.sdi_text_info("1;0;l[-1]*x[1]+I;|")["ninstructions"] == 8
+    text = textgen.random_text(777, 5, nfuncs=4, depth=2, terms=1000, complex_=True)
+    info = P.sdi_text_info(text)
+    assert info["nslots"] <= 48 and E.parse(text).complex
+    # a right-nested product of 60 distinct complex factors keeps all of them live
+    body = "x[1]"
+    for k in range(60, 0, -1):
+        body = f"(x[1]+{k}*I)*({body})"
+    with pytest.raises(P.SdiError) as ei:
+        P.sdi_text_info(f"1;0;{body};|")
+    assert ei.value.code == -4 and "48 live complex temporaries" in str(ei.value)
+    assert P.sdi_text_info(f"1;0;{body.replace('*I', '')};|")["nslots"] > 48     # real: 96 slots suffice
+    # the same text without I compiles as a real tape
+    assert P.sdi_text_info("1;0;x[1]+2;|")["nslots"] == 2
