@@ -177,8 +177,11 @@ int sdi_tune_load(sdi_ctx* ctx, const char* path);
  *   I_s = c_s int_[0,1]^n prod_j x_j^(a_j + b_j eps) prod_m P_m(x)^(gamma_m + delta_m eps) dx,
  *   P_m(x) = sum_t coef_t prod_j x_j^exps_tj.
  *
- * a_j must be exactly -1 (then b_j != 0) or greater than -1.  All arrays are
- * host memory owned by the caller and copied by sdi_problem_create. */
+ * a_j must be exactly -1 (then b_j != 0) or greater than -1.  Term
+ * coefficients may be complex in complex mode (complex masses, say): their
+ * imaginary parts in term_coef_im; the contour deformation then follows the
+ * gradient of the real part of x^m P_F.  All arrays are host memory owned by
+ * the caller and copied by sdi_problem_create. */
 typedef struct {
   int32_t nvars;              /* n, 1..SDI_MAX_VARS                                 */
   int32_t nfactors;           /* M, 0..SDI_MAX_FACTORS                              */
@@ -194,6 +197,8 @@ typedef struct {
   const double* fac_delta;    /* [M] delta_m                                        */
   const double* term_coef;    /* [sum nterms] coefficients, factor-major            */
   const uint8_t* term_exps;   /* [sum nterms][n] exponents, row-major               */
+  const double* term_coef_im; /* [sum nterms] imaginary parts of term_coef, or NULL
+                                 (real); non-NULL only in complex mode (SDI_EINVAL) */
 } sdi_sector_desc;
 
 /* The problem: sectors, requested orders, prefactor series, complex mode.

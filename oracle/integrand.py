@@ -35,6 +35,11 @@ form and
 
     G(x, eps) = det(dz/dx) prod_j w_j^(a_j + b_j eps) prod_m P_m(z)^(gamma_m + delta_m eps).
 
+Term coefficients may be complex in complex mode (complex masses, whose
+negative imaginary parts already put F below the real axis): the factors are
+evaluated with them, and the deformation follows the gradient of Re F (a
+reading: the paper defines the deformation for real F only).
+
 Logarithms are principal; a factor that is real and negative takes
 arg = -pi (the value approached from Im < 0, as F - i0 prescribes).  Points
 with Im F(z) > 0 are counted, as the TestF check of section 4.6 does.
@@ -83,10 +88,11 @@ def log_minus_i0(p: np.ndarray) -> np.ndarray:
 
 
 def full_f_terms(sector) -> Tuple[np.ndarray, np.ndarray]:
-    """Coefficients and integer exponents of the deformation polynomial x^mono * P_F (mono = 0: P_F)."""
+    """Coefficients and integer exponents of the deformation polynomial x^mono * P_F (mono = 0: P_F);
+    for complex coefficients (complex masses) their real parts: the deformation follows Re F."""
     fac = sector.factors[sector.deform_factor]
     mono = sector.deform_mono if sector.deform_mono is not None else np.zeros(sector.n, np.int32)
-    return fac.coef.copy(), fac.exps.astype(np.int64) + mono.astype(np.int64)[None, :]
+    return np.real(fac.coef).astype(np.float64), fac.exps.astype(np.int64) + mono.astype(np.int64)[None, :]
 
 
 def _poly_int(coef, exps, y):
@@ -128,6 +134,8 @@ def regular_part(sector, y: np.ndarray, complex_mode: bool, lam: float):
     """G0(y) and Lambda(y) of G(y, eps) = G0 exp(eps Lambda); also Im F(z) > 0 flags."""
     npts, n = y.shape
     if not complex_mode:
+        if any(np.iscomplexobj(f.coef) and np.any(np.imag(f.coef) != 0) for f in sector.factors):
+            raise ValueError("complex term coefficients need complex mode")
         g0 = np.ones(npts)
         lam_ = np.zeros(npts)
         for fac in sector.factors:

@@ -39,7 +39,8 @@ def _poly_mp(coef, exps, y):
     """sum_t coef_t prod_j y_j^exps_tj with mpf arithmetic (coefficients are exact binary values)."""
     s = mpmath.mpf(0)
     for t in range(coef.shape[0]):
-        m = mpmath.mpf(float(coef[t]))
+        c = complex(coef[t])
+        m = mpmath.mpc(c.real, c.imag) if c.imag else mpmath.mpf(c.real)
         for j, e in enumerate(exps[t]):
             if e:
                 m *= y[j] ** int(e)
@@ -62,10 +63,10 @@ def _log_mi0(p):
 
 
 def _deform_terms(sector):
-    """Coefficients and exponents of the deformation polynomial x^mono * P_F."""
+    """Coefficients (real parts: the deformation follows Re F) and exponents of x^mono * P_F."""
     fac = sector.factors[sector.deform_factor]
     mono = sector.deform_mono if sector.deform_mono is not None else np.zeros(sector.n, np.int32)
-    return fac.coef, fac.exps.astype(np.int64) + np.asarray(mono, np.int64)[None, :]
+    return np.real(fac.coef), fac.exps.astype(np.int64) + np.asarray(mono, np.int64)[None, :]
 
 
 def _derivative(coef, exps, j):

@@ -52,7 +52,8 @@ class SectorDesc(C.Structure):
                 ("mono_a", C.POINTER(C.c_double)), ("mono_b", C.POINTER(C.c_double)),
                 ("deform_mono", C.POINTER(C.c_int32)), ("fac_nterms", C.POINTER(C.c_int32)),
                 ("fac_gamma", C.POINTER(C.c_double)), ("fac_delta", C.POINTER(C.c_double)),
-                ("term_coef", C.POINTER(C.c_double)), ("term_exps", C.POINTER(C.c_uint8))]
+                ("term_coef", C.POINTER(C.c_double)), ("term_exps", C.POINTER(C.c_uint8)),
+                ("term_coef_im", C.POINTER(C.c_double))]
 
 
 class FeynmanDesc(C.Structure):
@@ -302,17 +303,21 @@ def sdi_problem_create(ctx, problem):
         nt = np.array([len(f.coef) for f in s.factors], dtype=np.int32)
         g = np.array([f.gamma for f in s.factors], dtype=np.float64)
         d = np.array([f.delta for f in s.factors], dtype=np.float64)
-        coef = np.ascontiguousarray(np.concatenate([f.coef for f in s.factors]) if s.factors else np.zeros(0))
+        allc = np.concatenate([np.asarray(f.coef) for f in s.factors]) if s.factors else np.zeros(0)
+        coef = np.ascontiguousarray(allc.real, dtype=np.float64)
+        # imaginary parts of the term coefficients (complex mode), passed only when some is nonzero
+        coef_im = (np.ascontiguousarray(allc.imag, dtype=np.float64)
+                   if np.iscomplexobj(allc) and np.any(allc.imag != 0) else None)
         exps = np.ascontiguousarray(np.concatenate([f.exps for f in s.factors]).astype(np.uint8)
                                     if s.factors else np.zeros((0, s.n), np.uint8))
         dm = (np.ascontiguousarray(s.deform_mono, dtype=np.int32) if s.deform_mono is not None else None)
-        keep += [a, b, nt, g, d, coef, exps, dm]
+        keep += [a, b, nt, g, d, coef, exps, dm, coef_im]
         c = complex(s.coeff)
         descs[i] = SectorDesc(
             s.n, len(s.factors), s.deform_factor, 0, c.real, c.imag, _dptr(a), _dptr(b),
             dm.ctypes.data_as(C.POINTER(C.c_int32)) if dm is not None else None,
             nt.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(g), _dptr(d), _dptr(coef),
-            exps.ctypes.data_as(C.POINTER(C.c_uint8)))
+            exps.ctypes.data_as(C.POINTER(C.c_uint8)), _dptr(coef_im) if coef_im is not None else None)
     lead, pre, pim = _prefactor_of(problem)
     pre = np.ascontiguousarray(pre, dtype=np.float64)
     pim = np.ascontiguousarray(pim, dtype=np.float64)

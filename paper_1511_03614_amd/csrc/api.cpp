@@ -327,6 +327,8 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     if (!sd.mono_a || !sd.mono_b || (sd.nfactors && (!sd.fac_nterms || !sd.fac_gamma || !sd.fac_delta)))
       return bad(SDI_EINVAL, where + "null array");
     if (!std::isfinite(sd.coeff_re) || !std::isfinite(sd.coeff_im)) return bad(SDI_EINVAL, where + "coefficient not finite");
+    if (sd.term_coef_im && !d->complex_mode)
+      return bad(SDI_EINVAL, where + "complex term coefficients need complex mode");
     std::vector<int> S, rest;
     for (int j = 0; j < n; ++j) {
       const double a = sd.mono_a[j], b = sd.mono_b[j];
@@ -390,15 +392,24 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
       }
     }
     R.flags = (int_pow ? F_INT_POW : 0) | (int_mono ? F_INT_MONO : 0);
-    // terms per (factor, corner)
+    // terms per (factor, corner); the imaginary parts of complex coefficients
+    // go to terms_im at the same index (0 for real ones and for the
+    // deformation lists, which follow the real part of F)
     size_t t0 = 0;
     bool exp7 = false;
+    bool cplx_coef = false;
+    auto push_term = [&](double re, double im, uint64_t word) {
+      pb->terms.push_back(Term{re, word});
+      pb->terms_im.push_back(im);
+    };
     for (int m = 0; m < sd.nfactors; ++m) {
       const int nt = sd.fac_nterms[m];
       if (nt < 0) return bad(SDI_EINVAL, where + "negative term count");
       if (nt > 0 && (!sd.term_coef || !sd.term_exps)) return bad(SDI_EINVAL, where + "null term arrays");
       for (int t = 0; t < nt; ++t) {
-        if (!std::isfinite(sd.term_coef[t0 + t])) return bad(SDI_EINVAL, where + "term coefficient not finite");
+        if (!std::isfinite(sd.term_coef[t0 + t]) || (sd.term_coef_im && !std::isfinite(sd.term_coef_im[t0 + t])))
+          return bad(SDI_EINVAL, where + "term coefficient not finite");
+        if (sd.term_coef_im && sd.term_coef_im[t0 + t] != 0.0) cplx_coef = true;
         for (int j = 0; j < n; ++j) {
           const int e = sd.term_exps[(t0 + t) * n + j];
           if (e > (d->complex_mode ? 3 : 7))
@@ -418,7 +429,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
           if (!alive) continue;
           uint64_t word = 0;
           for (int j = 0; j < n; ++j) word |= (uint64_t)e[perm[j]] << (4 * j);
-          pb->terms.push_back(Term{sd.term_coef[t0 + t], word});
+          push_term(sd.term_coef[t0 + t], sd.term_coef_im ? sd.term_coef_im[t0 + t] : 0.0, word);
           ++cnt;
         }
         R.tab_cnt[m][W] = cnt;
@@ -436,7 +447,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
           if (sup != sg) continue;
           uint64_t word = 0;
           for (int j = 0; j < n; ++j) word |= (uint64_t)e[perm[j]] << (4 * j);
-          pb->terms.push_back(Term{sd.term_coef[t0 + t], word});
+          push_term(sd.term_coef[t0 + t], sd.term_coef_im ? sd.term_coef_im[t0 + t] : 0.0, word);
           ++cnt;
         }
         R.grp_cnt[m][sg] = cnt;
@@ -453,6 +464,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
       CplxDev X{};
       X.lam = d->lambda;
       X.fac_f = sd.deform_factor;
+      X.coef_im = nullptr;   // set to the device table after the upload when cplx_coef
       for (int j = 0; j < n; ++j) X.mono_f[j] = sd.deform_mono ? sd.deform_mono[perm[j]] : 0;
       for (int j = 0; j < n; ++j)
         if (X.mono_f[j] < 0 || X.mono_f[j] > 7) return bad(SDI_ENOTSUP, where + "deform_mono outside 0..7");
@@ -495,7 +507,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
                 if (t.second[j] > 7) return false;
                 word |= (uint64_t)t.second[j] << (4 * j);
               }
-              pb->terms.push_back(Term{t.first, word});
+              push_term(t.first, 0.0, word);
               ++cnt;
             }
             pb->dir[(size_t)X.dir_off + ((size_t)dd * MAXC + W) * 2] = off;
@@ -513,6 +525,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
         }
       }
       pb->cx.push_back(X);
+      pb->cx_cplx_coef.push_back(cplx_coef ? 1 : 0);
     }
     // fold: F_k = sum_kk c_s (Pi * C)_i f_kk, i = k - lead - (kk - ns), C the
     // coefficient series of a part of a sector with a_j < -1 (1 otherwise)
@@ -554,7 +567,12 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     pb->nsmax = std::max(pb->nsmax, R.ns);
     pb->nfmax = std::max(pb->nfmax, R.nfac);
   }
-  if (pb->terms.empty()) pb->terms.push_back(Term{0.0, 0});
+  if (pb->terms.empty()) {
+    pb->terms.push_back(Term{0.0, 0});
+    pb->terms_im.push_back(0.0);
+  }
+  bool any_cplx_coef = false;
+  for (char c : pb->cx_cplx_coef) any_cplx_coef = any_cplx_coef || c;
   hipError_t e = hipSetDevice(ctx->device);
   if (e == hipSuccess) e = hipMalloc((void**)&pb->d_secs, pb->secs.size() * sizeof(SecDev));
   if (e == hipSuccess) e = hipMalloc((void**)&pb->d_terms, pb->terms.size() * sizeof(Term));
@@ -562,6 +580,14 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     e = hipMemcpy(pb->d_terms, pb->terms.data(), pb->terms.size() * sizeof(Term), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(pb->d_secs, pb->secs.data(), pb->secs.size() * sizeof(SecDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess && any_cplx_coef) {
+    e = hipMalloc((void**)&pb->d_terms_im, pb->terms_im.size() * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMemcpy(pb->d_terms_im, pb->terms_im.data(), pb->terms_im.size() * sizeof(double),
+                    hipMemcpyHostToDevice);
+    for (size_t s = 0; s < pb->cx.size(); ++s)
+      if (pb->cx_cplx_coef[s]) pb->cx[s].coef_im = pb->d_terms_im;
+  }
   if (e == hipSuccess && pb->complex_mode) {
     if (pb->dir.empty()) pb->dir.push_back(0);
     e = hipMalloc((void**)&pb->d_cx, pb->cx.size() * sizeof(CplxDev));
@@ -584,6 +610,7 @@ void sdi_problem_destroy(sdi_problem* pb) {
   free_passes(pb->passes);
   if (pb->d_secs) (void)hipFree(pb->d_secs);
   if (pb->d_terms) (void)hipFree(pb->d_terms);
+  if (pb->d_terms_im) (void)hipFree(pb->d_terms_im);
   if (pb->d_grids) (void)hipFree(pb->d_grids);
   if (pb->d_ws) (void)hipFree(pb->d_ws);
   if (pb->d_cx) (void)hipFree(pb->d_cx);

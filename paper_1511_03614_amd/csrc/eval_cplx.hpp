@@ -16,6 +16,8 @@
 //   Lambda = sum_j b_j Log w_j + sum_m delta_m Log P_m(z),
 // with principal logarithms and arg = -pi on the negative real axis.  The
 // subtraction and eps series then follow the real path with complex G0, Lambda.
+// Term coefficients may be complex (complex masses); the deformation lists
+// then hold the derivatives of the real part of F.
 #pragma once
 #include "eval_real.hpp"
 
@@ -93,12 +95,13 @@ __device__ __forceinline__ void poly_real3(CTerm* t, uint32_t cnt, const double 
   for (uint32_t i = 0; i < cnt; ++i) add_term3<NV, PPT>(t[i].coef, t[i].exps, x, out);
 }
 
-// out += coef prod_j z_j^e_j for one term at complex points (exponents up to 3).
+// out += (c + i ci) prod_j z_j^e_j for one term at complex points (exponents up to 3).
 template <int NV, int PPT>
-__device__ __forceinline__ void add_term_c(double c, uint64_t e, const cd (&z)[PPT][NV], cd (&out)[PPT]) {
+__device__ __forceinline__ void add_term_c(double c, double ci, uint64_t e, const cd (&z)[PPT][NV],
+                                           cd (&out)[PPT]) {
   cd m[PPT];
 #pragma unroll
-  for (int p = 0; p < PPT; ++p) m[p] = cd{c, 0.0};
+  for (int p = 0; p < PPT; ++p) m[p] = cd{c, ci};
   const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
@@ -119,14 +122,21 @@ __device__ __forceinline__ void add_term_c(double c, uint64_t e, const cd (&z)[P
   for (int p = 0; p < PPT; ++p) out[p] = cadd(out[p], m[p]);
 }
 
-// Polynomial with real coefficients at complex points (exponents up to 3),
-// terms in list order.
+// Polynomial at complex points (exponents up to 3), terms in list order; tim:
+// the imaginary parts of the list's coefficients, or null (real coefficients).
 template <int NV, int PPT>
-__device__ __forceinline__ void poly_cplx(CTerm* t, uint32_t cnt, const cd (&z)[PPT][NV],
-                                          cd (&out)[PPT]) {
+__device__ __forceinline__ void poly_cplx(CTerm* t, const SDI_TAPE double* tim, uint32_t cnt,
+                                          const cd (&z)[PPT][NV], cd (&out)[PPT]) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) out[p] = cd{0.0, 0.0};
-  for (uint32_t i = 0; i < cnt; ++i) add_term_c<NV, PPT>(t[i].coef, t[i].exps, z, out);
+  for (uint32_t i = 0; i < cnt; ++i) add_term_c<NV, PPT>(t[i].coef, tim ? tim[i] : 0.0, t[i].exps, z, out);
+}
+
+// The imaginary parts of the coefficients of the term list at offset off, or
+// null where the sector's coefficients are real.
+__device__ __forceinline__ const SDI_TAPE double* coef_im_at(const SDI_TAPE CplxDev* X, uint32_t off) {
+  const double* p = X->coef_im;
+  return p ? tape(p) + off : nullptr;
 }
 
 // f_kk of one sector at PPT points, complex mode.  imf counts points whose F(z)
@@ -293,7 +303,7 @@ __device__ __forceinline__ void eval_f_cplx_c(CSec* S, const SDI_TAPE CplxDev* X
     for (int fm = 0; fm < MAXF; ++fm) {
       if (fm < nfac) {
         cd P[PPT];
-        poly_cplx<NV, PPT>(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], z, P);
+        poly_cplx<NV, PPT>(terms + S->tab_off[fm][W], coef_im_at(X, S->tab_off[fm][W]), S->tab_cnt[fm][W], z, P);
         const double gm = S->gam[fm];
         const double dm = S->del[fm];
 #pragma unroll

@@ -132,12 +132,12 @@ __device__ inline D poly_dd(CTerm* t, uint32_t cnt, int n, const D* v) {
   return P;
 }
 
-// the same at complex points
-__device__ inline Z poly_zdd(CTerm* t, uint32_t cnt, int n, const Z* v) {
+// the same at complex points; tim: imaginary parts of the coefficients, or null
+__device__ inline Z poly_zdd(CTerm* t, const SDI_TAPE double* tim, uint32_t cnt, int n, const Z* v) {
   Z P = zre(mk(0.0));
   for (uint32_t u = 0; u < cnt; ++u) {
     const uint64_t e = t[u].exps;
-    Z m = zre(mk(t[u].coef));
+    Z m = Z{mk(t[u].coef), mk(tim ? tim[u] : 0.0)};
     for (int j = 0; j < n; ++j) {
       const int nib = (int)((e >> (4 * j)) & 0xfu);
       const int pw = (nib & 1) + 2 * ((nib >> 1) & 1) + 4 * ((nib >> 2) & 1);
@@ -249,7 +249,7 @@ __device__ __attribute__((noinline)) void eval_f_cplx_dd(CSec* S, const SDI_TAPE
       lw = zadd(lw, zmul(l, S->b[j]));
     }
     for (int fm = 0; fm < nfac; ++fm) {
-      const Z P = poly_zdd(terms + S->tab_off[fm][W], S->tab_cnt[fm][W], n, z);
+      const Z P = poly_zdd(terms + S->tab_off[fm][W], coef_im_at(X, S->tab_off[fm][W]), S->tab_cnt[fm][W], n, z);
       const Z l = zlog_mi0(P);
       lg = zadd(lg, zmul(l, S->gam[fm]));
       lw = zadd(lw, zmul(l, S->del[fm]));

@@ -175,6 +175,9 @@ struct sdi_problem {
   double lambda = 0.0;
   std::vector<sdi::SecDev> secs;      // host copy (updated per integrate)
   std::vector<sdi::Term> terms;
+  std::vector<double> terms_im;     // imaginary parts of the term coefficients (same indexing)
+  double* d_terms_im = nullptr;     // on the device when some sector has complex coefficients
+  std::vector<char> cx_cplx_coef;   // per sector (complex mode): its coefficients are complex
   std::vector<double> cost;           // relative cost per point of each sector
   sdi::SecDev* d_secs = nullptr;
   sdi::Term* d_terms = nullptr;

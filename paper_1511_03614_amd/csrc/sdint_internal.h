@@ -78,6 +78,9 @@ struct alignas(16) CplxDev {
   int32_t fac_f;               // factor index of F, -1 if none
   int32_t pad;
   double lam;
+  const double* coef_im;       // imaginary parts of the coefficients of the problem's term
+                               // lists (same indexing as the Term table), null if this
+                               // sector's coefficients are real
 };
 
 struct alignas(16) TileDesc {

@@ -419,7 +419,7 @@ __device__ __forceinline__ bool imf_any_corner(CSec* S, const SDI_TAPE CplxDev* 
       z[0][j] = cd{y, -y * t};
     }
     cd P[1];
-    poly_cplx<NV, 1>(terms + S->tab_off[facf][W], S->tab_cnt[facf][W], z, P);
+    poly_cplx<NV, 1>(terms + S->tab_off[facf][W], coef_im_at(X, S->tab_off[facf][W]), S->tab_cnt[facf][W], z, P);
     cd fz = P[0];
 #pragma unroll
     for (int j = 0; j < NV; ++j) {

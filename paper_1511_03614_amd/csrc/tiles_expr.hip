@@ -139,8 +139,10 @@ __device__ __forceinline__ cd run_expr_c(CIns* ins, int nins, int out, double* R
 
 // Writes the point's coordinates into slots 0 .. n-1 (imaginary parts 0 for a complex tape).
 template <bool CPLX>
-__device__ __forceinline__ void put_point(double* R, int n, const double* x) {
-  for (int j = 0; j < n; ++j) {
+__device__ __forceinline__ void put_point(double* R, int n, const double (&x)[MAXV]) {
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) {
+    if (j >= n) break;
     if constexpr (CPLX) {
       R[(2 * j) * 64] = x[j];
       R[(2 * j + 1) * 64] = 0.0;

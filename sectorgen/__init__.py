@@ -38,11 +38,12 @@ class Factor:
     """One regular factor P_m(x)^(gamma + delta*eps) with P_m = sum_t coef_t x^exps_t."""
     gamma: float
     delta: float
-    coef: np.ndarray          # (T,) float64
+    coef: np.ndarray          # (T,) float64 (complex128 for complex coefficients, complex mode only)
     exps: np.ndarray          # (T, n) uint8
 
     def __post_init__(self):
-        self.coef = np.ascontiguousarray(self.coef, dtype=np.float64)
+        c = np.asarray(self.coef)
+        self.coef = np.ascontiguousarray(c, dtype=np.complex128 if np.iscomplexobj(c) else np.float64)
         self.exps = np.ascontiguousarray(self.exps, dtype=np.uint8)
         if self.exps.ndim != 2 or self.exps.shape[0] != self.coef.shape[0]:
             raise ValueError("exps must be (T, n) with T == len(coef)")

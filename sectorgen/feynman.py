@@ -225,6 +225,24 @@ def massive_bubble_problem(s: float = 5.0, m2: float = 1.0, lam: float = 0.5) ->
                    name="massive_bubble")
 
 
+def complex_mass_bubble_problem(s: float = 5.0, m2: complex = 1.0 - 0.25j, lam: float = 0.3) -> Problem:
+    """Equal-mass one-loop bubble at p^2 = s with a complex mass m^2 = M^2 - i M Gamma:
+    the two primary sectors of the real-mass bubble, F = m^2 (1 + t)^2 - s t written
+    with complex coefficients (complex mode)."""
+    base = massive_bubble_problem(s, 1.0, lam)
+    secs = []
+    for sec in base.sectors:
+        F = sec.factors[sec.deform_factor]
+        assert F.exps[:, 0].tolist() == [0, 1, 2] and np.allclose(F.coef, [1.0, 2.0 - s, 1.0])
+        facs = list(sec.factors)
+        facs[sec.deform_factor] = Factor(F.gamma, F.delta, np.array([m2, 2.0 * m2 - s, m2], dtype=complex),
+                                         F.exps.copy())
+        secs.append(Sector(a=sec.a.copy(), b=sec.b.copy(), factors=facs, coeff=sec.coeff,
+                           deform_factor=sec.deform_factor, deform_mono=sec.deform_mono))
+    return Problem(sectors=secs, order_min=base.order_min, order_max=base.order_max, feynman=base.feynman,
+                   complex_mode=True, lam=lam, name="complex_mass_bubble")
+
+
 def bisect_sector(sec: Sector, j: int, p: float = 0.5) -> List[Sector]:
     """Splits the integration over x_j at p (the BisectionVariables option of
     section 4.4, bisection point p): the lower part maps x_j = p y, the upper

@@ -242,3 +242,89 @@ def test_physical_double_box_lambda_invariance(ctx):
     finally:
         P.sdi_problem_destroy(h)
         set_params(ctx)
+
+
+# ---------------------------------------------------------------- complex term coefficients
+
+def complex_coef_max_problem():
+    """The 8-variable complex shape with complex coefficients in the positive factor
+    (imaginary parts of either sign, so the factor's values leave the real axis)."""
+    from shapes import max_complex_problem
+    prob = max_complex_problem()
+    rng = np.random.default_rng(77)
+    for sec in prob.sectors:
+        G = sec.factors[2]
+        sec.factors[2] = Factor(G.gamma, G.delta, G.coef + 0.3j * rng.uniform(-1, 1, size=G.coef.size), G.exps)
+    return prob
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.3])
+def test_complex_mass_bubble(ctx, lam):
+    """Complex mass m^2 = 1 - i/4: per point and per shift against the oracle, and
+    the eps^0 coefficient against -int_0^1 ln(m^2 - s x(1-x)) dx within 5 sigma."""
+    import mpmath
+    from sectorgen.feynman import complex_mass_bubble_problem
+    prob = complex_mass_bubble_problem(5.0, 1.0 - 0.25j, lam)
+    rng = np.random.default_rng(12)
+    for s in range(len(prob.sectors)):
+        ok, strict = pointwise_c(ctx, prob, s, rng.uniform(1e-7, 1.0, size=(2048, 1)))
+        assert ok.all() and strict.mean() > 0.99, s
+    m, R = 12, 8
+    set_params(ctx, lattice_log2=m, shifts=R, seed=3)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        res = P.sdi_integrate(ctx, h)
+        assert res["status"] == 0 and res["n_imf_positive"] == 0
+        for s in range(len(prob.sectors)):
+            per = P.sdi_sector_results(ctx, h, s, R)[2]
+            oq, scale, npos = oracle_shift_values_c(prob, s, m, R, 3)
+            assert npos == 0
+            assert_close_shift(per, oq, scale, f"complex-mass bubble sector {s}")
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
+    with mpmath.workdps(30):
+        ref = complex(-mpmath.quad(lambda x: mpmath.log(mpmath.mpc(1, -0.25) - 5 * x * (1 - x)), [0, 0.5, 1]))
+    v = res["value"]
+    assert abs(v[0].real - 1.0) < 5 * res["err_re"][0] + 1e-12 and abs(v[0].imag) < 5 * res["err_im"][0] + 1e-12
+    assert abs(v[1].real - ref.real) < 5 * res["err_re"][1] + 1e-9
+    assert abs(v[1].imag - ref.imag) < 5 * res["err_im"][1] + 1e-9
+    log(f"complex-mass bubble, lambda {lam}: eps^0 {v[1]:.10f} vs {ref:.10f}")
+
+
+def test_complex_coefficients_at_the_largest_shape(ctx):
+    """8 variables, 4 singular, complex coefficients in one factor: per point and per
+    (sector, shift) mean against the oracle (the widening by the rounding bound
+    as in test_gpu_limits.py)."""
+    from test_gpu_limits import oracle_shift_values_cond, pointwise
+    from test_gpu_parity import REL_INT
+    prob = complex_coef_max_problem()
+    rng = np.random.default_rng(19)
+    for s, sec in enumerate(prob.sectors):
+        x = rng.uniform(1e-6, 1.0, size=(512, sec.n))
+        ok, strict = pointwise(ctx, prob, s, x)
+        assert ok.all(), f"sector {s}: {np.argwhere(~ok)[:5]}"
+    m, R, seed = 10, 4, 5
+    set_params(ctx, lattice_log2=m, shifts=R, seed=seed, tile_log2=0)
+    h = P.sdi_problem_create(ctx, prob)
+    try:
+        P.sdi_integrate(ctx, h)
+        for s in range(len(prob.sectors)):
+            per = P.sdi_sector_results(ctx, h, s, R)[2]
+            oq, scale, bound = oracle_shift_values_cond(prob, s, m, R, seed)
+            tol = np.maximum(REL_INT * np.maximum(np.abs(oq), scale[None, :]), bound)
+            d = np.abs(per - oq)
+            assert (d <= tol).all(), f"sector {s}: max d/tol {np.max(d / tol)}"
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
+
+
+def test_complex_coefficients_need_complex_mode(ctx):
+    from sectorgen.feynman import complex_mass_bubble_problem
+    prob = complex_mass_bubble_problem()
+    prob.complex_mode = False
+    with pytest.raises(P.SdiError) as e:
+        h = P.sdi_problem_create(ctx, prob)
+        P.sdi_problem_destroy(h)
+    assert e.value.code == -1
