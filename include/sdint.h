@@ -258,6 +258,8 @@ typedef struct {
   int32_t complex_mode;       /* 1: contour deformation along the sector's F        */
   int32_t reserved;           /* must be 0                                          */
   double lambda;              /* deformation size (complex mode)                    */
+  const double* f_coef_im;    /* [f_nterms] imaginary parts of F's coefficients
+                                 (complex masses), or NULL; complex mode only        */
 } sdi_feynman_desc;
 
 /* Compile the sectors of a Feynman integral (see sdi_feynman_desc).  Returns

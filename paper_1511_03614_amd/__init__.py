@@ -61,7 +61,8 @@ class FeynmanDesc(C.Structure):
                 ("indices", C.POINTER(C.c_int32)), ("u_nterms", C.c_int32), ("f_nterms", C.c_int32),
                 ("u_coef", C.POINTER(C.c_double)), ("u_exps", C.POINTER(C.c_uint8)),
                 ("f_coef", C.POINTER(C.c_double)), ("f_exps", C.POINTER(C.c_uint8)),
-                ("complex_mode", C.c_int32), ("reserved", C.c_int32), ("lam", C.c_double)]
+                ("complex_mode", C.c_int32), ("reserved", C.c_int32), ("lam", C.c_double),
+                ("f_coef_im", C.POINTER(C.c_double))]
 
 
 class ProblemDesc(C.Structure):
@@ -335,17 +336,21 @@ def _feynman_desc(U: dict, F: dict, loops: int, indices, order: int, d0: int, co
     keep = []
 
     def arrays(p):
-        coef = np.ascontiguousarray([float(c) for c in p.values()], dtype=np.float64)
+        vals = [complex(c) for c in p.values()]
+        coef = np.ascontiguousarray([c.real for c in vals], dtype=np.float64)
+        im = np.ascontiguousarray([c.imag for c in vals], dtype=np.float64)
         exps = np.ascontiguousarray(np.array(list(p.keys()), dtype=np.uint8).reshape(len(p), n))
-        keep.extend([coef, exps])
-        return len(p), _dptr(coef), exps.ctypes.data_as(C.POINTER(C.c_uint8))
+        keep.extend([coef, im, exps])
+        return len(p), _dptr(coef), exps.ctypes.data_as(C.POINTER(C.c_uint8)), (_dptr(im) if im.any() else None)
 
     idx = np.ascontiguousarray(indices, dtype=np.int32)
     keep.append(idx)
-    un, uc, ue = arrays(U)
-    fn, fc, fe = arrays(F)
+    un, uc, ue, ui = arrays(U)
+    if ui is not None:
+        raise SdiError(-1, "U has real coefficients")
+    fn, fc, fe, fi = arrays(F)
     d = FeynmanDesc(n, loops, d0, order, idx.ctypes.data_as(C.POINTER(C.c_int32)), un, fn, uc, ue, fc, fe,
-                    int(complex_mode), 0, float(lam))
+                    int(complex_mode), 0, float(lam), fi)
     return d, keep
 
 
@@ -361,7 +366,8 @@ def sdi_problem_from_feynman(ctx, U: dict, F: dict, loops: int, indices, order: 
 
 def sdi_feynman_sectors(U: dict, F: dict, loops: int, indices, d0: int = 4):
     """(sectors, lowest result order, variables per sector) of the decomposition, host only."""
-    d, keep = _feynman_desc(U, F, loops, indices, 0, d0, False, 0.0)
+    cplx = any(complex(c).imag != 0.0 for c in F.values())      # complex masses: a complex-mode input
+    d, keep = _feynman_desc(U, F, loops, indices, 0, d0, cplx, 0.0)
     ns, om, nv = C.c_int32(), C.c_int32(), C.c_int32()
     rc = load_library().sdi_feynman_sectors(C.byref(d), C.byref(ns), C.byref(om), C.byref(nv))
     if rc != 0:

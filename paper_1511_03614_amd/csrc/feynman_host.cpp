@@ -16,6 +16,7 @@
 // keeps the two polynomials with their monomials moved into the x_j powers;
 // exponents a_j < -1 are reduced by sdi_problem_create.
 #include <cmath>
+#include <complex>
 #include <map>
 
 #include "host.h"
@@ -26,13 +27,14 @@ namespace sdi {
 namespace {
 
 using Exps = std::vector<int>;
+using Coef = std::complex<double>;   // complex for complex masses (F's imaginary parts)
 
 // A polynomial as its terms in insertion order (merging keeps the position of
 // the first occurrence and adds coefficients in that order).
 struct Poly {
-  std::vector<std::pair<Exps, double>> terms;
+  std::vector<std::pair<Exps, Coef>> terms;
   std::map<Exps, size_t> at;
-  void add(const Exps& e, double c) {
+  void add(const Exps& e, Coef c) {
     auto it = at.find(e);
     if (it == at.end()) {
       at.emplace(e, terms.size());
@@ -44,7 +46,7 @@ struct Poly {
   Poly nonzero() const {
     Poly o;
     for (auto& t : terms)
-      if (t.second != 0.0) o.add(t.first, t.second);
+      if (t.second != Coef(0.0)) o.add(t.first, t.second);
     return o;
   }
 };
@@ -113,7 +115,7 @@ struct State {
 
 struct OutSector {
   std::vector<double> a, b;
-  std::vector<std::vector<double>> coef;
+  std::vector<std::vector<Coef>> coef;
   std::vector<std::vector<uint8_t>> exps;   // [factor][term * n]
 };
 
@@ -130,8 +132,10 @@ int decompose(const sdi_feynman_desc* d, std::vector<OutSector>& out, std::strin
   for (int m = 0; m < 2; ++m) {
     const int nt = m == 0 ? d->u_nterms : d->f_nterms;
     const double* c = m == 0 ? d->u_coef : d->f_coef;
+    const double* ci = m == 0 ? nullptr : d->f_coef_im;
     const uint8_t* e = m == 0 ? d->u_exps : d->f_exps;
-    for (int t = 0; t < nt; ++t) UF[m].add(Exps(e + (size_t)t * n, e + (size_t)(t + 1) * n), c[t]);
+    for (int t = 0; t < nt; ++t)
+      UF[m].add(Exps(e + (size_t)t * n, e + (size_t)(t + 1) * n), Coef(c[t], ci ? ci[t] : 0.0));
     UF[m] = UF[m].nonzero();
   }
   for (int k = 0; k < n; ++k) {
@@ -174,10 +178,10 @@ int decompose(const sdi_feynman_desc* d, std::vector<OutSector>& out, std::strin
             o.a[j] += g[j] * gam[m];
             o.b[j] += g[j] * del[m];
           }
-          std::vector<std::pair<Exps, double>> terms = s.ps[m].terms;
+          std::vector<std::pair<Exps, Coef>> terms = s.ps[m].terms;
           std::stable_sort(terms.begin(), terms.end(),
-                           [](const std::pair<Exps, double>& x, const std::pair<Exps, double>& y) { return x.first < y.first; });
-          std::vector<double> c;
+                           [](const std::pair<Exps, Coef>& x, const std::pair<Exps, Coef>& y) { return x.first < y.first; });
+          std::vector<Coef> c;
           std::vector<uint8_t> e;
           for (auto& t : terms) {
             c.push_back(t.second);
@@ -253,10 +257,15 @@ int check_desc(const sdi_feynman_desc* d, std::string& err) {
     }
   for (int t = 0; t < d->u_nterms + d->f_nterms; ++t) {
     const double c = t < d->u_nterms ? d->u_coef[t] : d->f_coef[t - d->u_nterms];
-    if (!std::isfinite(c)) {
+    const double ci = t >= d->u_nterms && d->f_coef_im ? d->f_coef_im[t - d->u_nterms] : 0.0;
+    if (!std::isfinite(c) || !std::isfinite(ci)) {
       err = "feynman: coefficients must be finite";
       return SDI_EINVAL;
     }
+  }
+  if (d->f_coef_im && !d->complex_mode) {
+    err = "feynman: complex F coefficients need complex mode";
+    return SDI_EINVAL;
   }
   return SDI_OK;
 }
@@ -325,7 +334,7 @@ int sdi_problem_from_feynman(sdi_ctx* ctx, const sdi_feynman_desc* d, sdi_proble
   const int nv = d->nvars - 1;
   std::vector<sdi_sector_desc> sd(secs.size());
   std::vector<std::vector<int32_t>> nterms(secs.size());
-  std::vector<std::vector<double>> coef(secs.size()), gam(secs.size()), del(secs.size());
+  std::vector<std::vector<double>> coef(secs.size()), coef_im(secs.size()), gam(secs.size()), del(secs.size());
   std::vector<std::vector<uint8_t>> exps(secs.size());
   int A = 0;
   for (int j = 0; j < d->nvars; ++j) A += d->indices[j];
@@ -334,7 +343,10 @@ int sdi_problem_from_feynman(sdi_ctx* ctx, const sdi_feynman_desc* d, sdi_proble
   for (size_t s = 0; s < secs.size(); ++s) {
     for (int m = 0; m < 2; ++m) {
       nterms[s].push_back((int32_t)secs[s].coef[m].size());
-      coef[s].insert(coef[s].end(), secs[s].coef[m].begin(), secs[s].coef[m].end());
+      for (const Coef& c : secs[s].coef[m]) {
+        coef[s].push_back(c.real());
+        coef_im[s].push_back(c.imag());
+      }
       exps[s].insert(exps[s].end(), secs[s].exps[m].begin(), secs[s].exps[m].end());
     }
     gam[s] = {gU, gF};
@@ -352,6 +364,7 @@ int sdi_problem_from_feynman(sdi_ctx* ctx, const sdi_feynman_desc* d, sdi_proble
     x.fac_delta = del[s].data();
     x.term_coef = coef[s].data();
     x.term_exps = exps[s].data();
+    x.term_coef_im = d->f_coef_im ? coef_im[s].data() : nullptr;
   }
   sdi_problem_desc pd{};
   pd.nsectors = (int32_t)secs.size();

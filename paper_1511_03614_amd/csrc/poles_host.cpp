@@ -177,6 +177,10 @@ int expand_poles(const sdi_problem_desc* d, PoleExpansion& X, std::string& err) 
       err = where + "a_j < -1 is reduced in real mode only";
       return SDI_ENOTSUP;
     }
+    if (sd.term_coef_im) {
+      err = where + "complex term coefficients need complex mode";
+      return SDI_EINVAL;
+    }
     const int n = sd.nvars;
     if (n < 1 || n > MAXV || sd.nfactors < 0 || sd.nfactors > MAXF || !sd.mono_b ||
         (sd.nfactors && (!sd.fac_nterms || !sd.fac_gamma || !sd.fac_delta || !sd.term_coef || !sd.term_exps))) {

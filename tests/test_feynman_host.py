@@ -50,3 +50,13 @@ def test_sectors_with_a_below_minus_one_are_kept_by_both():
     lead = P.sdi_prefactor_feynman(1, (1, 1, 1, 1), 2, 1)[0]
     most = max(int(sum((s.a <= -1.0) & (s.a == np.floor(s.a)))) for s in secs)
     assert om == lead - most
+
+
+def test_complex_masses_decompose_like_real_ones():
+    """F with complex coefficients (m^2 - i m Gamma) decomposes into the same sectors as with real ones."""
+    U = {(1, 0): 1.0, (0, 1): 1.0}
+    Fr = {(2, 0): 1.0, (1, 1): 2.0 - 5.0, (0, 2): 1.0}
+    Fc = {(2, 0): 1.0 - 0.25j, (1, 1): 2.0 * (1.0 - 0.25j) - 5.0, (0, 2): 1.0 - 0.25j}
+    assert P.sdi_feynman_sectors(U, Fc, 1, (1, 1)) == P.sdi_feynman_sectors(U, Fr, 1, (1, 1))
+    with pytest.raises(P.SdiError):
+        P.sdi_feynman_sectors({(1, 0): 1.0 + 1j, (0, 1): 1.0}, Fr, 1, (1, 1))

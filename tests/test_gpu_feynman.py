@@ -2,8 +2,9 @@
 SDEvaluate[{U, F, l}, indices, order] of section 4.3) integrate to the same
 values as the same integrals decomposed by the input tool (sectorgen.feynman)
 and compiled sector by sector: the section 4.3 box, the Euclidean double box
-and the physical (massive, complex-mode) double box, bit for bit; and the box
-lands on its textbook value."""
+the physical (massive, complex-mode) double box and the bubble with a
+complex mass (complex F coefficients), bit for bit; and the box lands on its
+textbook value."""
 import math
 
 import numpy as np
@@ -28,7 +29,19 @@ def ctx():
     P.sdi_ctx_destroy(c)
 
 
+def complex_mass_bubble_case():
+    """Equal-mass bubble at p^2 = 5 with m^2 = 1 - i/4 (complex F coefficients)."""
+    import sectorgen
+    m2, s = 1.0 - 0.25j, 5.0
+    U = {(1, 0): 1.0, (0, 1): 1.0}
+    F = {(2, 0): m2, (1, 1): 2.0 * m2 - s, (0, 2): m2}
+    prob = sectorgen.Problem(sectors=feynman.feynman_sectors(U, F, (1, 1), 1), order_min=-1, order_max=0,
+                             feynman=sectorgen.FeynmanPrefactor(1, (1, 1), 4), complex_mode=True, lam=0.3)
+    return (U, F), 1, (1, 1), prob, True, 0.3
+
+
 CASES = {
+    "bubble, complex mass": complex_mass_bubble_case,
     "box": lambda: (feynman.box_uf(3.0, 1.0), 1, (1, 1, 1, 1), feynman.box_problem(3.0, 1.0), False, 0.0),
     "double box": lambda: (feynman.double_box_uf(-3.0, -1.0, 0.0), 2, (1,) * 7,
                            feynman.double_box_problem(-3.0, -1.0, 0.0), False, 0.0),
