@@ -684,6 +684,28 @@ def cubature_entry(P, ctx, name, problem, maxeval, steps=3, split_frac=0.25, bat
         _set(P, ctx)
 
 
+def monte_carlo_entry(P, ctx, name, problem, m, R=16, warmup=0, steps=3):
+    """The Monte Carlo integrator (integrator 2: Philox points, the sampling of
+    the paper's default vegasCuba) beside the lattice on the same workload, the
+    same evaluations and the same warm-up: final-pass time and error per order."""
+    h = P.sdi_problem_create(ctx, problem)
+    try:
+        out = {"workload": name, "lattice_log2": m, "shifts": R, "warmup": warmup}
+        for key, integ in (("lattice", 0), ("monte_carlo", 2)):
+            _set(P, ctx, lattice_log2=m, shifts=R, warmup=warmup, integrator=integ)
+            P.sdi_integrate(ctx, h)
+            runs = [P.sdi_integrate(ctx, h) for _ in range(steps)]
+            r = runs[-1]
+            out[key] = {"evals": int(r["n_evals"]), "ms_eval_kernel": float(sorted(x["ms_eval_kernel"] for x in runs)[steps // 2]),
+                        "value_re": r["value"].real.tolist(), "err": _err(r).tolist()}
+        e_l, e_m = out["lattice"]["err"], out["monte_carlo"]["err"]
+        out["error_ratio_mc_over_lattice"] = [b / a if a > 0 else None for a, b in zip(e_l, e_m)]
+        return out
+    finally:
+        P.sdi_problem_destroy(h)
+        _set(P, ctx)
+
+
 def text_integrand_rate(P, ctx, steps: int = 5):
     """Throughput of the text path (sdi_problem_from_text) on an integrand of the
     size class the paper's database holds (~200 KB of text): 3000 signed terms of
@@ -977,6 +999,8 @@ def main() -> int:
                            cubature_entry(P, ctx, "doublebox (Euclidean, 282 sectors)",
                                           double_box_problem(-3.0, -1.0, 0.0, order_max=0), 1 << 24)]
         out["endpoint_precision"] = endpoint_precision_cost(P, ctx, sectorgen.config2())
+        out["monte_carlo"] = monte_carlo_entry(P, ctx, "synthetic64, 5 Vegas warm-up iterations", sectorgen.config2(),
+                                               16, warmup=5)
     if not args.no_equal_time:
         lat = [dict(lattice_log2=m) for m in range(10, 17)]
         alloc = dict(pilot_log2=10, alloc_min_log2=12, alloc_max_log2=20)

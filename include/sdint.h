@@ -126,7 +126,15 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *                  summed rule differences (not standard deviations).  It
  *                  takes sector problems (real or complex mode), not text
  *                  integrands, and no budget, warmup, sampler or slice_log2
- *                  (SDI_ENOTSUP); the workspace argument is not used.
+ *                  (SDI_ENOTSUP); the workspace argument is not used;
+ *                  2 = Monte Carlo points, the sampling of vegasCuba (the
+ *                  paper's default): the final pass takes pseudo-random points
+ *                  (Philox4x32-10, key = seed, counter = (index, variable +
+ *                  16 shift, sector, 0x4D433031), u = (top 52 bits + 1/2)
+ *                  2^-52) through the Vegas grids of the warm-up when it ran,
+ *                  the R shifts being R independent samples; everything else
+ *                  as for 0 (budget, warm-up, small_x); not with the flow
+ *                  sampler, text integrands or slice_log2 (SDI_ENOTSUP).
  *                                                               (default 0)
  *   cub_maxeval    cubature: integrand evaluations over all sectors; below one
  *                  rule application per sector SDI_EINVAL    (default 2^24)

@@ -156,6 +156,38 @@ def vegas_map(grid: np.ndarray, u: np.ndarray):
     return x, w, b
 
 
+# ---------------------------------------------------------------- Monte Carlo points
+
+MC_TAG = 0x4D433031
+
+
+def mc_u(seed: int, s: int, r: int, i0: int, count: int, n: int) -> np.ndarray:
+    """Pseudo-random points of the Monte Carlo integrator (the sampling of the
+    paper's default vegasCuba, section 4.4): point i of shift r of sector s,
+    variable c from Philox4x32-10 with key = the seed's 32-bit halves and
+    counter (i, c + 16 r, s, MC_TAG); u = (b + 1/2) 2^-52 with b the top 52 bits
+    of the first two output words (out0 * 2^20 + floor(out1 / 2^12)), so u lies
+    strictly inside (0, 1) and is exact in fp64."""
+    key = (seed & M32, (seed >> 32) & M32)
+    u = np.empty((count, n))
+    for p in range(count):
+        for c in range(n):
+            o = philox4x32_10(((i0 + p) & M32, (c + 16 * r) & M32, s & M32, MC_TAG), key)
+            b = (o[0] << 20) | (o[1] >> 12)
+            u[p, c] = (b + 0.5) * 2.0 ** -52
+    return u
+
+
+def mc_points(seed: int, s: int, r: int, i0: int, count: int, n: int, grid=None):
+    """Monte Carlo points and weights of one (sector, shift): no tent map; through
+    the sector's Vegas grid when there is one."""
+    u = mc_u(seed, s, r, i0, count, n)
+    if grid is None:
+        return u, np.ones(count)
+    x, w, _ = vegas_map(grid, u)
+    return x, w
+
+
 def sector_points(z, m: int, shifts_r: np.ndarray, i0: int, count: int, grid=None, baker=True):
     """Points and weights for one (sector, shift): lattice -> tent -> Vegas map."""
     u = lattice_u(z, m, shifts_r, i0, count)

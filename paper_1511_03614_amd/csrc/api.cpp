@@ -197,7 +197,8 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
     if (!range(0, 64)) return fail(ctx, SDI_EINVAL, "iterations must be in 0..64");
     p.warmup = (int)iv;
   } else if (k == "integrator") {
-    if (!range(0, 1)) return fail(ctx, SDI_EINVAL, "integrator must be 0 (lattice) or 1 (cubature)");
+    if (!range(0, 2))
+      return fail(ctx, SDI_EINVAL, "integrator must be 0 (lattice), 1 (cubature) or 2 (Monte Carlo points)");
     p.integrator = (int)iv;
   } else if (k == "cub_maxeval") {
     if (!range(1, (long long)1 << 40)) return fail(ctx, SDI_EINVAL, "cub_maxeval must be in 1..2^40");

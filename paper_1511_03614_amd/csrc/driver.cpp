@@ -26,6 +26,7 @@ struct Plan {
   double small_x = 0.0;          // endpoint-precision threshold of the final pass (0: off)
   bool warm = false;
   bool flow = false;             // final points come from the learned sampler
+  bool mc = false;               // final points are Monte Carlo points (integrator 2)
   std::vector<PointRun> fruns;   // per final tile: its points in the flow buffers
   std::vector<int64_t> fchunk, fx_off, fpt_off;
   int64_t fx_total = 0, fpt_total = 0;
@@ -150,7 +151,10 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   P.rows = prm.R + prm.warmup;
   P.warm = warm && prm.warmup > 0;
   P.flow = prm.sampler == 1;
+  P.mc = prm.integrator == 2;
   P.small_x = (prm.small_x > 0.0 && !pb->is_expr()) ? prm.small_x : 0.0;
+  if (P.mc && P.flow) return fail(ctx, SDI_ENOTSUP, "Monte Carlo points and the flow sampler exclude each other");
+  if (P.mc && pb->is_expr()) return fail(ctx, SDI_ENOTSUP, "Monte Carlo points: not available for integrands given as text");
   if (P.flow && !pb->flow) return fail(ctx, SDI_ESTATE, "sampler flow needs sdi_flow_init on this problem");
   if (P.flow && prm.warmup > 0) return fail(ctx, SDI_ENOTSUP, "the flow sampler replaces the Vegas warm-up (set warmup 0)");
   P.msec = msec;
@@ -181,12 +185,13 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   P.fx_off.clear();
   P.fpt_off.clear();
   P.fx_total = P.fpt_total = 0;
-  if (P.flow) {
-    // sectors with an active flow take their points from it; the others stay on the lattice
-    const std::vector<uint8_t>& act = pb->flow->active;
+  if (P.flow || P.mc) {
+    // explicit-point tiles: sectors with an active flow (or every sector, for
+    // Monte Carlo points); the others stay on the lattice
+    const std::vector<uint8_t>* act = P.flow ? &pb->flow->active : nullptr;
     int64_t chunks = 0;
     for (const TileDesc& t : P.ftiles) {
-      if (!act[t.sector]) {
+      if (act && !(*act)[t.sector]) {
         P.fx_off.push_back(-1);
         P.fpt_off.push_back(-1);
         continue;
@@ -202,10 +207,10 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
     }
     P.fchunk.push_back(chunks);
     std::vector<int32_t> lat;
-    for (int32_t t : P.forder) (act[P.ftiles[t].sector] ? P.xorder : lat).push_back(t);
+    for (int32_t t : P.forder) ((!act || (*act)[P.ftiles[t].sector]) ? P.xorder : lat).push_back(t);
     P.forder.swap(lat);
     if ((P.fx_total + P.fpt_total) * 8 > ((int64_t)64 << 30))
-      return fail(ctx, SDI_ENOTSUP, "flow pass needs more than 64 GiB of point buffers; lower the lattice size");
+      return fail(ctx, SDI_ENOTSUP, "explicit-point pass needs more than 64 GiB of point buffers; lower the lattice size");
   }
   P.wtiles.clear();
   P.whist_off.clear();
@@ -282,7 +287,7 @@ int make_plan(sdi_ctx* ctx, sdi_problem* pb, Plan& P, const std::vector<int>& ms
   C.add((void**)&P.d_counter, 8 * 4);
   C.add((void**)&P.d_shifts, (size_t)nsec * P.rows * MAXV * 8);
   C.add((void**)&P.d_zp_final, (size_t)nsec * MAXV * 8);
-  if (P.flow) {
+  if (P.flow || P.mc) {
     C.add((void**)&P.d_fruns, P.fruns.size() * sizeof(PointRun));
     C.add((void**)&P.d_fchunk, P.fchunk.size() * 8);
     C.add((void**)&P.d_fx_off, P.fx_off.size() * 8);
@@ -424,9 +429,9 @@ std::string pass_key(const Params& p, const std::vector<int>& msec, bool warm, c
   char buf[360];
   unsigned long long h = 1469598103934665603ull;
   for (int m : msec) h = (h ^ (unsigned)m) * 1099511628211ull;
-  snprintf(buf, sizeof buf, "R%d s%llu b%d w%d/%d mw%d nb%d t%d p%d g%d f%d x%.17g m%llx ws%p:%zu r%u:%u", p.R,
+  snprintf(buf, sizeof buf, "R%d s%llu b%d w%d/%d mw%d nb%d t%d p%d g%d f%d i%d x%.17g m%llx ws%p:%zu r%u:%u", p.R,
            (unsigned long long)p.seed, p.baker, p.warmup, (int)warm, p.mw, p.nbins, p.tile_log2, p.ppt, p.graph,
-           p.sampler, p.small_x, h, ws, wsb, lo, hi);
+           p.sampler, p.integrator, p.small_x, h, ws, wsb, lo, hi);
   return buf;
 }
 
@@ -507,6 +512,20 @@ int record_segment(sdi_ctx* ctx, sdi_problem* pb, PassState& S, int seg, hipStre
         KCHK(ctx, launch_refit(P.d_secs, nsec, P.d_hsec, P.d_hsec_off, pb->d_grids, 1.5, st));
       }
     }
+    if (P.mc) {
+      // Monte Carlo points through the grids the warm-up has just left
+      McArgs M{};
+      M.secs = P.d_secs;
+      M.runs = P.d_fruns;
+      M.chunk_prefix = P.d_fchunk;
+      M.nruns = (int32_t)P.fruns.size();
+      M.nchunks = P.fchunk.back();
+      M.grids = pb->d_grids;
+      M.seed = prm.seed;
+      M.x = P.d_px;
+      M.w = P.d_pw;
+      KCHK(ctx, launch_mc_points(M, st));
+    }
   } else if (seg == 1) {
     KCHK(ctx, launch_fill_i32(P.d_counter + 1, 0, 2, st));
     if (!P.forder.empty())
@@ -585,7 +604,7 @@ int setup_pass(sdi_ctx* ctx, sdi_problem* pb, PassState& S, const std::vector<in
   HIPCHK(ctx, hipMemcpyAsync(P.d_pair_start, P.pair_start.data(), (npairs + 1) * 4, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(P.d_pair_sector, P.pair_sector.data(), npairs * 4, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(P.d_zp_final, P.zp_final.data(), P.zp_final.size() * 8, hipMemcpyHostToDevice, st));
-  if (P.flow) {
+  if (P.flow || P.mc) {
     HIPCHK(ctx, hipMemcpyAsync(P.d_fruns, P.fruns.data(), P.fruns.size() * sizeof(PointRun), hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(P.d_fchunk, P.fchunk.data(), P.fchunk.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(P.d_fx_off, P.fx_off.data(), P.fx_off.size() * 8, hipMemcpyHostToDevice, st));
@@ -1020,8 +1039,9 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   uint32_t lo = 0, hi = 0;
   std::string rkey;
   if (prm.slice_log2 > 0) {
-    if (prm.budget > 0 || prm.warmup > 0 || prm.sampler != 0)
-      return fail(ctx, SDI_ENOTSUP, "slice_log2 needs a uniform lattice pass (budget 0, warmup 0, sampler 0)");
+    if (prm.budget > 0 || prm.warmup > 0 || prm.sampler != 0 || prm.integrator != 0)
+      return fail(ctx, SDI_ENOTSUP,
+                  "slice_log2 needs a uniform lattice pass (budget 0, warmup 0, sampler 0, integrator 0)");
     rkey = resume_key(prm, nsec);
     const uint32_t N = 1u << prm.m;
     if (pb->resume_key != rkey || pb->resume_done <= 0 || pb->resume_done >= (int64_t)N) pb->resume_done = 0;

@@ -126,6 +126,23 @@ int launch_flow_adam(float* params, const float* grad, float* m, float* v, const
                      hipStream_t st);
 int launch_flow_sample(const FlowSampleArgs& a, int nvmax, hipStream_t st);
 int launch_flow_sample_tiles(const FlowTileArgs& a, int nvmax, hipStream_t st);
+
+// Monte Carlo points of the final pass (integrator 2, mc_points.hip): for every
+// run (a final tile: sector, shift row, lattice index range, offsets into x and
+// w) its points from Philox4x32-10, through the sector's Vegas grid when it has
+// one, as explicit points x (caller variable order) and weights w.
+struct McArgs {
+  const SecDev* secs;
+  const PointRun* runs;
+  const int64_t* chunk_prefix;  // [nruns + 1], chunks of 64 points
+  int32_t nruns;
+  int64_t nchunks;
+  const double* grids;
+  uint64_t seed;
+  double* x;
+  double* w;
+};
+int launch_mc_points(const McArgs& a, hipStream_t st);
 int launch_flow_grad(const FlowGradArgs& a, int nvmax, int ncu, hipStream_t st);
 int launch_flow_chunk_reduce(const FlowSecDesc* fs, const FlowTile* runs, const int64_t* chunk_prefix, int nruns,
                              const float* part, int64_t stride, int64_t max_nparam, float* grad, hipStream_t st);

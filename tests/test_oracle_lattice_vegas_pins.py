@@ -279,3 +279,20 @@ def test_shift_errors_follow_student_t_over_many_seeds():
     m2 = np.mean(zs ** 2)
     assert 0.8 < m2 < 2.4, m2      # t_7: 1.4; sigma 2x too large gives 0.35, 2x too small 5.6
     assert abs(np.mean(zs)) < 0.25
+
+
+def test_monte_carlo_points():
+    """Monte Carlo points: strictly inside (0, 1), distinct per shift and sector,
+    uniform (moments within 5 sigma) and uncorrelated across variables."""
+    from oracle import points as PT
+    u = PT.mc_u(7, 3, 1, 0, 4096, 2)
+    assert np.all((u > 0.0) & (u < 1.0))
+    assert np.all(u * 2.0 ** 52 - 0.5 == np.floor(u * 2.0 ** 52))             # (b + 1/2) 2^-52
+    n = u.shape[0]
+    assert abs(u.mean() - 0.5) < 5 * math.sqrt(1 / 12 / (2 * n))
+    assert abs((u ** 2).mean() - 1 / 3) < 5 * math.sqrt((1 / 5 - 1 / 9) / (2 * n))
+    c = np.corrcoef(u[:, 0], u[:, 1])[0, 1]
+    assert abs(c) < 5 / math.sqrt(n)
+    assert not np.array_equal(PT.mc_u(7, 3, 2, 0, 8, 2), PT.mc_u(7, 3, 1, 0, 8, 2))
+    assert not np.array_equal(PT.mc_u(7, 4, 1, 0, 8, 2), PT.mc_u(7, 3, 1, 0, 8, 2))
+    assert np.array_equal(PT.mc_u(7, 3, 1, 5, 3, 2), u[5:8])                  # counter-based: any index range
