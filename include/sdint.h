@@ -134,8 +134,17 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *                  2^-52) through the Vegas grids of the warm-up when it ran,
  *                  the R shifts being R independent samples; everything else
  *                  as for 0 (budget, warm-up, small_x); not with the flow
- *                  sampler, text integrands or slice_log2 (SDI_ENOTSUP).
+ *                  sampler, text integrands or slice_log2 (SDI_ENOTSUP);
+ *                  3 = subregion-adaptive Monte Carlo, the role of suaveCuba:
+ *                  the regions, rounds, budget (cub_maxeval), tolerances and
+ *                  batches of 1, each new region sampled with suave_nnew
+ *                  Philox points (counter (point, variable, region number,
+ *                  0x53554156)), its value and standard errors from the sample,
+ *                  halved along the variable whose halves' spreads of the
+ *                  weighted |F| sum to the least; errors are root sums of
+ *                  squares; the same restrictions as 1.
  *                                                               (default 0)
+ *   suave_nnew     integrator 3: points per new region, 16..2^20 (default 1024)
  *   cub_maxeval    cubature: integrand evaluations over all sectors; below one
  *                  rule application per sector SDI_EINVAL    (default 2^24)
  *   cub_epsrel, cub_epsabs   cubature: tolerance per order

@@ -55,6 +55,24 @@ def philox4x32_10(ctr, key):
     return c
 
 
+def philox4x32_10_np(c0, c1, c2, c3, key):
+    """philox4x32_10 on arrays of counters (the same rounds on uint64 numpy arrays
+    holding 32-bit values); returns the four output words as arrays."""
+    c = [np.asarray(v, dtype=np.uint64) & np.uint64(M32) for v in (c0, c1, c2, c3)]
+    k0, k1 = int(key[0]) & M32, int(key[1]) & M32
+    m32 = np.uint64(M32)
+    for rnd in range(10):
+        if rnd:
+            k0 = (k0 + PHILOX_W0) & M32
+            k1 = (k1 + PHILOX_W1) & M32
+        p0 = np.uint64(PHILOX_M0) * c[0]
+        p1 = np.uint64(PHILOX_M1) * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & m32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & m32
+        c = [hi1 ^ c[1] ^ np.uint64(k0), lo1, hi0 ^ c[3] ^ np.uint64(k1), lo0]
+    return c
+
+
 def shift_int(seed: int, s: int, r: int, j: int, m: int) -> int:
     """53-bit shift integer D_{s,r,j} for a lattice of 2^m points."""
     key = (seed & M32, (seed >> 32) & M32)
@@ -170,11 +188,11 @@ def mc_u(seed: int, s: int, r: int, i0: int, count: int, n: int) -> np.ndarray:
     strictly inside (0, 1) and is exact in fp64."""
     key = (seed & M32, (seed >> 32) & M32)
     u = np.empty((count, n))
-    for p in range(count):
-        for c in range(n):
-            o = philox4x32_10(((i0 + p) & M32, (c + 16 * r) & M32, s & M32, MC_TAG), key)
-            b = (o[0] << 20) | (o[1] >> 12)
-            u[p, c] = (b + 0.5) * 2.0 ** -52
+    idx = np.arange(i0, i0 + count, dtype=np.uint64)
+    for c in range(n):
+        o = philox4x32_10_np(idx, np.full(count, c + 16 * r), np.full(count, s), np.full(count, MC_TAG), key)
+        b = (o[0] << np.uint64(20)) | (o[1] >> np.uint64(12))
+        u[:, c] = (b.astype(np.float64) + 0.5) * 2.0 ** -52
     return u
 
 

@@ -197,8 +197,10 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
     if (!range(0, 64)) return fail(ctx, SDI_EINVAL, "iterations must be in 0..64");
     p.warmup = (int)iv;
   } else if (k == "integrator") {
-    if (!range(0, 2))
-      return fail(ctx, SDI_EINVAL, "integrator must be 0 (lattice), 1 (cubature) or 2 (Monte Carlo points)");
+    if (!range(0, 3))
+      return fail(ctx, SDI_EINVAL,
+                  "integrator must be 0 (lattice), 1 (cubature), 2 (Monte Carlo points) or 3 (subregion-adaptive "
+                  "Monte Carlo)");
     p.integrator = (int)iv;
   } else if (k == "cub_maxeval") {
     if (!range(1, (long long)1 << 40)) return fail(ctx, SDI_EINVAL, "cub_maxeval must be in 1..2^40");
@@ -206,6 +208,9 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
   } else if (k == "cub_batch_min") {
     if (!range(1, 1 << 24)) return fail(ctx, SDI_EINVAL, "cub_batch_min must be in 1..2^24");
     p.cub_batch_min = (int)iv;
+  } else if (k == "suave_nnew") {
+    if (!range(16, 1 << 20)) return fail(ctx, SDI_EINVAL, "suave_nnew must be in 16..2^20");
+    p.suave_nnew = (int)iv;
   } else if (k == "budget") {
     if (!range(0, (long long)1 << 40)) return fail(ctx, SDI_EINVAL, "budget must be in 0..2^40");
     p.budget = iv;
@@ -259,6 +264,7 @@ int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len) {
   else if (k == "iterations") v = p.warmup;
   else if (k == "cub_maxeval") v = p.cub_maxeval;
   else if (k == "cub_batch_min") v = p.cub_batch_min;
+  else if (k == "suave_nnew") v = p.suave_nnew;
   else if (k == "alloc_min_log2") v = p.alloc_min;
   else if (k == "alloc_max_log2") v = p.alloc_max;
   else if (k == "pilot_log2") v = p.pilot_log2;

@@ -95,10 +95,10 @@ CubState::~CubState() {
   if (d_buf) (void)hipFree(d_buf);
 }
 
-// Apply the rule pair to regions [first, first + count) of C on the GPU and
-// store their values, errors, axes and counts.
+// Apply the rule pair (or, mc, the Monte Carlo sample) to regions [first,
+// first + count) of C on the GPU and store their values, errors, axes and counts.
 static int evaluate_regions(sdi_ctx* ctx, sdi_problem* pb, CubState& C, int64_t first, int64_t count,
-                            const std::vector<double>& omega, float& ms_kernel) {
+                            const std::vector<double>& omega, float& ms_kernel, bool mc) {
   if (count <= 0) return SDI_OK;
   const int K = pb->K;
   int rc = ensure_device(ctx, C, count, K);
@@ -150,7 +150,31 @@ static int evaluate_regions(sdi_ctx* ctx, sdi_problem* pb, CubState& C, int64_t 
   HIPCHK(ctx, hipEventCreate(&e1));
   HIPCHK(ctx, hipEventRecord(e0, st));
   const int km = pb->kfmax <= 4 ? 4 : 8;
-  const int krc = pb->complex_mode ? launch_cubature_cplx(pb->nvmax, km, A, st) : launch_cubature_real(pb->nvmax, km, A, st);
+  int krc = 0;
+  if (mc) {
+    SuaveArgs M{};
+    M.secs = pb->d_secs;
+    M.terms = pb->d_terms;
+    M.cx = A.cx;
+    M.dir = A.dir;
+    M.reg_sector = d_sec;
+    M.reg_level = d_lev;
+    M.reg_index = d_idx;
+    for (int k = 0; k < KMAX; ++k) M.omega[k] = A.omega[k];
+    M.nreg = count;
+    M.uid0 = first;
+    M.seed = ctx->params.seed;
+    M.K = K;
+    M.npts = ctx->params.suave_nnew;
+    M.out_val = d_val;
+    M.out_err = d_err;
+    M.out_axis = d_axis;
+    M.out_count = d_cnt;
+    krc = pb->complex_mode ? launch_suave_cplx(pb->nvmax, km, M, st) : launch_suave_real(pb->nvmax, km, M, st);
+    if (krc == 0) HIPCHK(ctx, hipMemsetAsync(d_sig, 0, (size_t)count * K * 8, st));
+  } else {
+    krc = pb->complex_mode ? launch_cubature_cplx(pb->nvmax, km, A, st) : launch_cubature_real(pb->nvmax, km, A, st);
+  }
   HIPCHK(ctx, hipEventRecord(e1, st));
   if (krc != 0) {
     (void)hipEventDestroy(e0);
@@ -187,9 +211,14 @@ static void reserve_regions(CubState& C, int64_t n, int K) {
 int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
   const Params& prm = ctx->params;
   const auto t0 = std::chrono::steady_clock::now();
-  if (pb->is_expr()) return fail(ctx, SDI_ENOTSUP, "the cubature integrator takes sector problems, not text integrands");
+  // integrator 3: the same loop over regions with a Monte Carlo sample per
+  // region (suave.hpp): errors are standard errors, combined as a root sum of
+  // squares; a region costs suave_nnew evaluations
+  const bool mc = prm.integrator == 3;
+  if (pb->is_expr()) return fail(ctx, SDI_ENOTSUP, "the adaptive integrators take sector problems, not text integrands");
   if (prm.budget > 0 || prm.warmup > 0 || prm.sampler != 0 || prm.slice_log2 > 0)
-    return fail(ctx, SDI_ENOTSUP, "the cubature integrator runs without budget, warmup, sampler or slice_log2");
+    return fail(ctx, SDI_ENOTSUP, "the adaptive integrators run without budget, warmup, sampler or slice_log2");
+  auto region_cost = [&](int n) -> int64_t { return mc ? (int64_t)prm.suave_nnew : rule_points(n); };
   const int K = pb->K, nsec = pb->nsec;
   if (!pb->cub) pb->cub = new CubState();
   CubState& C = *pb->cub;
@@ -203,9 +232,11 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
   C.count.clear();
   C.alive.clear();
   int64_t evals = 0;
-  for (int s = 0; s < nsec; ++s) evals += rule_points(pb->secs[s].n);
+  for (int s = 0; s < nsec; ++s) evals += region_cost(pb->secs[s].n);
   if (evals > prm.cub_maxeval)
-    return fail(ctx, SDI_EINVAL, "cub_maxeval is below one rule application per sector (" + std::to_string(evals) + ")");
+    return fail(ctx, SDI_EINVAL, std::string(mc ? "cub_maxeval is below suave_nnew points per sector ("
+                                                 : "cub_maxeval is below one rule application per sector (") +
+                                     std::to_string(evals) + ")");
   reserve_regions(C, nsec, K);
   for (int s = 0; s < nsec; ++s) {
     C.sector[s] = s;
@@ -215,7 +246,7 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
   std::fill(C.index.begin(), C.index.end(), 0u);
   std::vector<double> omega(K, 1.0), tau(K, 0.0);
   float ms_kernel = 0.f;
-  int rc = evaluate_regions(ctx, pb, C, 0, nsec, omega, ms_kernel);
+  int rc = evaluate_regions(ctx, pb, C, 0, nsec, omega, ms_kernel, mc);
   if (rc != SDI_OK) return rc;
   int rounds = 1;
   bool converged = false;
@@ -227,14 +258,20 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
     std::fill(tot_re.begin(), tot_re.end(), 0.0);
     std::fill(tot_im.begin(), tot_im.end(), 0.0);
     std::fill(esum.begin(), esum.end(), 0.0);
+    std::vector<double> e2re(K, 0.0), e2im(K, 0.0);
     for (int64_t r = 0; r < nreg; ++r) {
       if (!C.alive[r]) continue;
       for (int k = 0; k < K; ++k) {
         tot_re[k] += C.val[(r * K + k) * 2];
         tot_im[k] += C.val[(r * K + k) * 2 + 1];
-        esum[k] += C.err[(r * K + k) * 2] + C.err[(r * K + k) * 2 + 1];
+        const double er = C.err[(r * K + k) * 2], ei = C.err[(r * K + k) * 2 + 1];
+        esum[k] += er + ei;
+        e2re[k] += er * er;
+        e2im[k] += ei * ei;
       }
     }
+    if (mc)
+      for (int k = 0; k < K; ++k) esum[k] = std::sqrt(e2re[k]) + std::sqrt(e2im[k]);
     bool all = true;
     for (int k = 0; k < K; ++k) {
       tau[k] = std::max(prm.cub_epsabs, prm.cub_epsrel * std::hypot(tot_re[k], tot_im[k]));
@@ -266,7 +303,7 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
     std::partial_sort(cand.begin(), cand.begin() + take, cand.end());
     int64_t chosen = 0;
     for (; chosen < take; ++chosen) {
-      const int64_t cost = 2 * rule_points(pb->secs[C.sector[cand[chosen].second]].n);
+      const int64_t cost = 2 * region_cost(pb->secs[C.sector[cand[chosen].second]].n);
       if (evals + cost > prm.cub_maxeval) break;
       evals += cost;
     }
@@ -287,7 +324,7 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
       }
     }
     nalive += chosen;
-    rc = evaluate_regions(ctx, pb, C, nreg, 2 * chosen, omega, ms_kernel);
+    rc = evaluate_regions(ctx, pb, C, nreg, 2 * chosen, omega, ms_kernel, mc);
     if (rc != SDI_OK) return rc;
     ++rounds;
   }
@@ -298,31 +335,36 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
   int64_t nonfin = 0, npos = 0;
   for (int64_t r = 0; r < nreg; ++r) {
     const int s = C.sector[r];
-    pb->sec_evals[s] += rule_points(pb->secs[s].n);
+    pb->sec_evals[s] += region_cost(pb->secs[s].n);
     nonfin += C.count[2 * r];
     npos += C.count[2 * r + 1];
     if (!C.alive[r]) continue;
     for (int k = 0; k < K; ++k) {
       double* q = pb->sec_stats.data() + ((size_t)s * KMAX + k) * 4;
+      const double er = C.err[(r * K + k) * 2], ei = C.err[(r * K + k) * 2 + 1];
       q[0] += C.val[(r * K + k) * 2];
       q[1] += C.val[(r * K + k) * 2 + 1];
-      q[2] += C.err[(r * K + k) * 2];
-      q[3] += C.err[(r * K + k) * 2 + 1];
+      q[2] += mc ? er * er : er;   // Monte Carlo: squares first, roots below
+      q[3] += mc ? ei * ei : ei;
     }
   }
   for (int k = 0; k < K; ++k) {
     double vr = 0.0, vi = 0.0, er = 0.0, ei = 0.0;
     for (int s = 0; s < nsec; ++s) {
-      const double* q = pb->sec_stats.data() + ((size_t)s * KMAX + k) * 4;
+      double* q = pb->sec_stats.data() + ((size_t)s * KMAX + k) * 4;
       vr += q[0];
       vi += q[1];
       er += q[2];
       ei += q[3];
+      if (mc) {
+        q[2] = std::sqrt(q[2]);
+        q[3] = std::sqrt(q[3]);
+      }
     }
     out->val_re[k] = vr;
     out->val_im[k] = vi;
-    out->err_re[k] = er;
-    out->err_im[k] = ei;
+    out->err_re[k] = mc ? std::sqrt(er) : er;
+    out->err_im[k] = mc ? std::sqrt(ei) : ei;
   }
   pb->per_shift.clear();
   pb->last_R = 0;

@@ -64,6 +64,7 @@ struct Params {
   double cub_epsabs = 0.0;        // cubature: absolute tolerance per order
   double cub_split_frac = 0.25;   // cubature: share of the live regions halved per round
   int cub_batch_min = 1024;       // cubature: regions halved per round at least (while there are as many)
+  int suave_nnew = 1024;          // subregion-adaptive Monte Carlo: points per new region
 };
 
 // One autotuner decision: final-pass tile size and launch variant

@@ -177,4 +177,29 @@ struct CubArgs {
 int launch_cubature_real(int nvmax, int km, const CubArgs& a, hipStream_t st);
 int launch_cubature_cplx(int nvmax, int km, const CubArgs& a, hipStream_t st);
 
+// Subregion-adaptive Monte Carlo (integrator 3, suave.hpp): npts pseudo-random
+// points per region (regions uid0 .. uid0 + nreg - 1 in creation order), the
+// region's value and standard errors per result order and its split axis.
+struct SuaveArgs {
+  const SecDev* secs;
+  const Term* terms;
+  const CplxDev* cx;
+  const uint32_t* dir;
+  const int32_t* reg_sector;  // [nreg]
+  const uint8_t* reg_level;   // [nreg][MAXV], caller variable order
+  const uint32_t* reg_index;  // [nreg][MAXV]
+  double omega[KMAX];         // order weights of the split statistic
+  int64_t nreg;
+  int64_t uid0;
+  uint64_t seed;
+  int32_t K;
+  int32_t npts;
+  double* out_val;            // [nreg][K][2]  vol * mean
+  double* out_err;            // [nreg][K][2]  vol * standard error of Re, Im
+  int32_t* out_axis;          // [nreg]
+  int32_t* out_count;         // [nreg][2] points with a non-finite value, points with Im F(z) > 0
+};
+int launch_suave_real(int nvmax, int km, const SuaveArgs& a, hipStream_t st);
+int launch_suave_cplx(int nvmax, int km, const SuaveArgs& a, hipStream_t st);
+
 }  // namespace sdi

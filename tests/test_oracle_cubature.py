@@ -232,3 +232,26 @@ def test_regions_at_rounding_noise_are_not_halved():
     xi, cls = cubature.nodes(3)
     mass = sum((abs(w7[c]) + abs(w5[c])) * (1.0 + 0.5 * ((1 + x[0]) / 2) ** 7) for x, c in zip(xi, cls))
     assert res.regions[0].sigma[0] == pytest.approx(mass * 2.0 ** -52, rel=1e-12)
+
+
+def test_suave_oracle_on_the_bubble_and_a_product():
+    """The subregion-adaptive Monte Carlo oracle (oracle/suave.py): the bubble's
+    closed form within 5 standard errors, regions that tile each cube, and on a
+    separable integrand that varies along one variable only the splits follow it."""
+    import math
+    import sectorgen
+    from oracle import suave
+    exact = [1.0, 2.0, 4 - math.pi ** 2 / 12]
+    r = suave.suave(sectorgen.bubble_problem(order_max=1), 60000, 256, 1e-12, 0.0, 5, 0.25, 4)
+    z = (r.value.real - exact) / r.err_re
+    assert np.all(np.abs(z) < 5), z
+    alive = [g for g in r.regions if g.alive]
+    for s in range(2):
+        assert sum(math.ldexp(1.0, -int(g.level.sum())) for g in alive if g.sector == s) == 1.0
+    # (1 + 9 x_1)^-2 in two variables: all fluctuation is along x_1
+    sec = sectorgen.Sector(a=np.zeros(2), b=np.zeros(2), factors=[
+        sectorgen.Factor(-2.0, 0.0, np.array([1.0, 9.0]), np.array([[0, 0], [1, 0]], dtype=np.uint8))])
+    prob = sectorgen.Problem(sectors=[sec], order_min=0, order_max=0)
+    r = suave.suave(prob, 256 * 15, 256, 1e-12, 0.0, 1, 1.0, 1)
+    assert all(g.level[1] == 0 for g in r.regions)
+    assert abs(r.value[0].real - 0.1) < 5 * r.err_re[0]

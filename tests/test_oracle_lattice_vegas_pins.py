@@ -296,3 +296,13 @@ def test_monte_carlo_points():
     assert not np.array_equal(PT.mc_u(7, 3, 2, 0, 8, 2), PT.mc_u(7, 3, 1, 0, 8, 2))
     assert not np.array_equal(PT.mc_u(7, 4, 1, 0, 8, 2), PT.mc_u(7, 3, 1, 0, 8, 2))
     assert np.array_equal(PT.mc_u(7, 3, 1, 5, 3, 2), u[5:8])                  # counter-based: any index range
+
+
+def test_vectorised_philox_equals_the_scalar_one():
+    from oracle import points as PT
+    rng = np.random.default_rng(3)
+    ctr = rng.integers(0, 2 ** 32, size=(4, 64), dtype=np.uint64)
+    key = (0x12345678, 0x9ABCDEF0)
+    v = PT.philox4x32_10_np(*ctr, key)
+    for i in range(64):
+        assert [int(w[i]) for w in v] == PT.philox4x32_10([int(c[i]) for c in ctr], key)
