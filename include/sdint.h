@@ -142,9 +142,37 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *                  0x53554156)), its value and standard errors from the sample,
  *                  halved along the variable whose halves' spreads of the
  *                  weighted |F| sum to the least; errors are root sums of
- *                  squares; the same restrictions as 1.
- *                                                               (default 0)
+ *                  squares; the same restrictions as 1;
+ *                  4 = partition by spreads, then lattice rules, the role of
+ *                  divonneCuba: the loop of 3 (budget cub_maxeval, batches,
+ *                  suave_nnew Philox points per new region, counter tag
+ *                  0x44495631) halving the regions of largest spread
+ *                  vol (max g - min g) / 2 along the variable whose halves'
+ *                  larger range of g is the least, until the budget is spent;
+ *                  then every region takes the shifted lattice rule of
+ *                  2^lattice_log2 points x shifts (at least 2; shift counter
+ *                  (variable, shift, region, 0x44495632), the tent map under
+ *                  baker), value and standard error from the shift means;
+ *                  a region whose two estimates differ by more than 4
+ *                  combined errors is halved once more and its halves take
+ *                  the lattice rule.  n_evals counts both phases; the same
+ *                  restrictions as 1.                           (default 0)
  *   suave_nnew     integrator 3: points per new region, 16..2^20 (default 1024)
+ *   separate_terms SeparateTerms of section 4.4, read when a problem is
+ *                  created (sdi_problem_create, sdi_problem_from_feynman):
+ *                  1 compiles every sector with singular variables S as its
+ *                  2^|S| integrable terms, each a sector of its own for every
+ *                  integrator, sampler and the allocation.  Term T (a bit mask
+ *                  over S, variables in increasing index): prod_{j in T}
+ *                  1/(b_j eps) times the integral over the variables outside T
+ *                  of the integrand at x_T = 0 (factor terms free of x_T),
+ *                  subtracted in S \ T with no boundary terms; a term left
+ *                  with no variable gets one constant variable.  The terms of
+ *                  a sector follow each other in the order of T, and
+ *                  sdi_problem_sector_origin names their input sector.  Real
+ *                  mode only (SDI_ENOTSUP in complex mode: the deformation's
+ *                  corner factors tie the terms together); a factor with no
+ *                  term on a face x_T = 0 gives SDI_ENOTSUP.     (default 0)
  *   cub_maxeval    cubature: integrand evaluations over all sectors; below one
  *                  rule application per sector SDI_EINVAL    (default 2^24)
  *   cub_epsrel, cub_epsabs   cubature: tolerance per order
@@ -327,7 +355,8 @@ void sdi_problem_destroy(sdi_problem* prob);
 int sdi_problem_norders(const sdi_problem* prob);
 int sdi_problem_nsectors(const sdi_problem* prob);
 /* The input sector a compiled sector s comes from (s itself unless sectors with
- * a_j < -1 were expanded); SDI_EINVAL for an index out of range. */
+ * a_j < -1 were expanded or terms separated, separate_terms); SDI_EINVAL for
+ * an index out of range. */
 int sdi_problem_sector_origin(const sdi_problem* prob, int32_t s);
 /* Number of variables n of sector s (the column count of its points in
  * sdi_evaluate, sdi_sample_points and the flow calls); SDI_EINVAL for a NULL

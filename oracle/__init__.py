@@ -30,6 +30,10 @@ What it computes (paper: FIESTA 4, arXiv:1511.03614):
 * ``cubature``   - globally adaptive deterministic cubature (the Cuhre
   option of CurrentIntegrator, section 4.4): the Genz-Malik degree-7/5 rule
   pair on dyadic regions, split along the largest fourth difference.
+* ``suave``      - subregion-adaptive Monte Carlo (the Suave option):
+  sampled dyadic regions halved where the samples spread most.
+* ``separate``   - SeparateTerms (section 4.4): a sector as the sum of the
+  integrable terms of its subtraction, each a sector of its own.
 
 Where the paper is silent, each function's docstring states the reading it
 takes and names the passage it follows.

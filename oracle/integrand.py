@@ -184,8 +184,11 @@ def regular_part(sector, y: np.ndarray, complex_mode: bool, lam: float):
 def sector_f(sector, x: np.ndarray, kf_max: int, complex_mode: bool = False, lam: float = 0.0):
     """f_k(x) for k = -|S| .. kf_max (rows), with the absolute term sums (cond).
 
-    Returns (f, cond, imf_pos) with f of shape (kf_max + |S| + 1, npts).
+    Returns (f, cond, imf_pos) with f of shape (kf_max + |S| + 1, npts).  A
+    sector marked ``boundary = False`` (a separated term, oracle/separate.py)
+    keeps only the subtracted integrand, the T = {} part of the sum.
     """
+    boundary = getattr(sector, "boundary", True)
     S = singular_set(sector)
     ns = len(S)
     nonS = [j for j in range(sector.n) if j not in S]
@@ -208,7 +211,7 @@ def sector_f(sector, x: np.ndarray, kf_max: int, complex_mode: bool = False, lam
                 y[:, S[i]] = 0.0
         g0, lam_w, pos = regular_part(sector, y, complex_mode, lam)
         imf_pos |= pos
-        tmask = wmask
+        tmask = wmask if boundary else 0
         while True:                                   # every T subset of W
             sign = -1.0 if bin(wmask & ~tmask).count("1") % 2 else 1.0
             nt = bin(tmask).count("1")
@@ -240,12 +243,14 @@ def sector_orders(sector, x: np.ndarray, order_min: int, order_max: int, pref_le
                   pref: Sequence[complex], complex_mode: bool = False, lam: float = 0.0):
     """F_k(x) = c_s sum_i Pi_i f_{k - lead - i}(x) for k = order_min .. order_max.
 
-    Returns (vals (K, npts), cond (K, npts), imf_pos (npts,)).
+    A sector with ``eps_shift = s`` (a separated term) stands for eps^-s times
+    its own integral.  Returns (vals (K, npts), cond (K, npts), imf_pos (npts,)).
     """
     S = singular_set(sector)
-    ns = len(S)
+    shift = getattr(sector, "eps_shift", 0)
+    ns = len(S) + shift
     kf_max = order_max - pref_lead
-    f, cond, pos = sector_f(sector, x, max(kf_max, -ns), complex_mode, lam)
+    f, cond, pos = sector_f(sector, x, max(kf_max + shift, -len(S)), complex_mode, lam)
     K = order_max - order_min + 1
     cplx = complex_mode or any(complex(p).imag != 0.0 for p in pref) or complex(sector.coeff).imag != 0.0
     vals = np.zeros((K, x.shape[0]), dtype=np.complex128 if cplx else np.float64)

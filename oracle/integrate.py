@@ -75,7 +75,8 @@ def integrate_sector(problem, s: int, m: int, nshifts: int, seed: int, pref_lead
         zw = points.cbc_vector(warmup_m, n)
         sh = points.shift_table(seed, s, nshifts + it + 1, n, warmup_m)[nshifts + it]
         x, w, b = points.sector_points(zw, warmup_m, sh, 0, 1 << warmup_m, grid, baker)
-        f, _, _ = integrand.sector_f(sec, x, kf_max, problem.complex_mode, problem.lam)
+        f, _, _ = integrand.sector_f(sec, x, kf_max + getattr(sec, "eps_shift", 0), problem.complex_mode,
+                                     problem.lam)
         h = vegas.histogram(b, f * w[None, :], nbins)
         grid = vegas.refit(grid, vegas.importance(h))
     z = points.cbc_vector(m, n)

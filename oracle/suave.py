@@ -62,13 +62,13 @@ class MCRegion:
     alive: bool = True
 
 
-def region_u(seed: int, uid: int, n: int, N: int) -> np.ndarray:
+def region_u(seed: int, uid: int, n: int, N: int, tag: int = TAG) -> np.ndarray:
     key = (seed & points.M32, (seed >> 32) & points.M32)
     u = np.empty((N, n))
     p = np.arange(N, dtype=np.uint64)
     for c in range(n):
         o = points.philox4x32_10_np(p, np.full(N, c), np.full(N, uid & points.M32),
-                                    np.full(N, ((uid >> 32) ^ TAG) & points.M32), key)
+                                    np.full(N, ((uid >> 32) ^ tag) & points.M32), key)
         b = (o[0] << np.uint64(20)) | (o[1] >> np.uint64(12))
         u[:, c] = (b.astype(np.float64) + 0.5) * 2.0 ** -52
     return u

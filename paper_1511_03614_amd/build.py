@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-mcode-object-version=5",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include"), "-Wall", "-Wno-unused-result"]
-SOURCES = ["tiles_real_e7.hip", "cubature_real.hip", "cubature_cplx.hip", "suave_real.hip", "suave_cplx.hip", "tiles_real_dd.hip", "tiles_real_nv16.hip", "tiles_real_nv10.hip", "tiles_real_nv10_s2.hip", "tiles_real_nv10_g.hip", "tiles_real_nv8.hip", "tiles_real_nv6.hip", "tiles_real_nv4.hip",
+SOURCES = ["tiles_real_e7.hip", "cubature_real.hip", "cubature_cplx.hip", "suave_real.hip", "suave_cplx.hip", "divonne_real.hip", "divonne_cplx.hip", "tiles_real_dd.hip", "tiles_real_nv16.hip", "tiles_real_nv10.hip", "tiles_real_nv10_s2.hip", "tiles_real_nv10_g.hip", "tiles_real_nv8.hip", "tiles_real_nv6.hip", "tiles_real_nv4.hip",
            "tiles_real_nv16_s2.hip", "tiles_real_nv8_s2.hip", "tiles_real_nv6_s2.hip", "tiles_real_nv4_s2.hip", "tiles_real_nv16_g.hip", "tiles_real_nv8_g.hip", "tiles_real_nv6_g.hip", "tiles_real_nv4_g.hip", "eval_points_real.hip", "tiles_cplx.hip", "tiles_cplx_nv4.hip", "tiles_cplx_nv6.hip", "tiles_cplx_nv8.hip", "tiles_cplx_dd.hip",
            "kernels_misc.hip", "mc_points.hip", "flow.hip", "tiles_expr.hip", "expr_host.cpp", "api.cpp", "driver.cpp", "flow_host.cpp", "deform_host.cpp", "lattice_cbc.cpp", "prefactor.cpp", "cubature.cpp", "feynman_host.cpp", "poles_host.cpp"]
 

@@ -197,10 +197,10 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
     if (!range(0, 64)) return fail(ctx, SDI_EINVAL, "iterations must be in 0..64");
     p.warmup = (int)iv;
   } else if (k == "integrator") {
-    if (!range(0, 3))
+    if (!range(0, 4))
       return fail(ctx, SDI_EINVAL,
-                  "integrator must be 0 (lattice), 1 (cubature), 2 (Monte Carlo points) or 3 (subregion-adaptive "
-                  "Monte Carlo)");
+                  "integrator must be 0 (lattice), 1 (cubature), 2 (Monte Carlo points), 3 (subregion-adaptive "
+                  "Monte Carlo) or 4 (partition by spreads, then lattice rules)");
     p.integrator = (int)iv;
   } else if (k == "cub_maxeval") {
     if (!range(1, (long long)1 << 40)) return fail(ctx, SDI_EINVAL, "cub_maxeval must be in 1..2^40");
@@ -211,6 +211,9 @@ int sdi_set_param(sdi_ctx* ctx, const char* key, const char* value) {
   } else if (k == "suave_nnew") {
     if (!range(16, 1 << 20)) return fail(ctx, SDI_EINVAL, "suave_nnew must be in 16..2^20");
     p.suave_nnew = (int)iv;
+  } else if (k == "separate_terms") {
+    if (!range(0, 1)) return fail(ctx, SDI_EINVAL, "separate_terms must be 0 or 1");
+    p.separate_terms = (int)iv;
   } else if (k == "budget") {
     if (!range(0, (long long)1 << 40)) return fail(ctx, SDI_EINVAL, "budget must be in 0..2^40");
     p.budget = iv;
@@ -265,6 +268,7 @@ int sdi_get_param(sdi_ctx* ctx, const char* key, char* buf, size_t len) {
   else if (k == "cub_maxeval") v = p.cub_maxeval;
   else if (k == "cub_batch_min") v = p.cub_batch_min;
   else if (k == "suave_nnew") v = p.suave_nnew;
+  else if (k == "separate_terms") v = p.separate_terms;
   else if (k == "alloc_min_log2") v = p.alloc_min;
   else if (k == "alloc_max_log2") v = p.alloc_max;
   else if (k == "pilot_log2") v = p.pilot_log2;
@@ -306,8 +310,15 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
   PoleExpansion X;
   {
     std::string err;
-    const int rc = expand_poles(d, X, err);
+    int rc = expand_poles(d, X, err);
     if (rc != SDI_OK) return fail(ctx, rc, err);
+    if (ctx->params.separate_terms) {
+      // the subtraction terms of a deformed sector share the deformation's
+      // corner factors w_j^(b_j eps), so they are separated in real mode only
+      if (d->complex_mode) return fail(ctx, SDI_ENOTSUP, "separate_terms works in real mode only");
+      rc = separate_terms(X, err);
+      if (rc != SDI_OK) return fail(ctx, rc, err);
+    }
   }
   sdi_problem* pb = new sdi_problem();
   pb->ctx = ctx;
@@ -355,7 +366,10 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
     R.n = n;
     R.ns = (int)S.size();
     R.nfac = sd.nfactors;
-    R.kf = std::max(0, kf_max + R.ns + 1);
+    // a separated term carries eps^-shift; sub_only drops its boundary terms
+    const int shift = X.shift.empty() ? 0 : X.shift[s];
+    const bool sub_only = !X.sub_only.empty() && X.sub_only[s];
+    R.kf = std::max(0, kf_max + R.ns + shift + 1);
     if (R.kf > KMAX) return bad(SDI_ENOTSUP, where + "more than 8 internal eps orders");
     R.K = K;
     R.nvc = n <= 4 ? 0 : (n <= 8 ? 1 : 2);
@@ -383,7 +397,7 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
       double v = 1.0;
       for (int i = 0; i < R.ns; ++i)
         if (T >> i & 1) v = v / R.bS[i];
-      R.invb[T] = v;
+      R.invb[T] = (sub_only && T != 0) ? 0.0 : v;
     }
     bool int_pow = true;
     for (int m = 0; m < sd.nfactors; ++m) {
@@ -534,13 +548,14 @@ int sdi_problem_create(sdi_ctx* ctx, const sdi_problem_desc* d, sdi_problem** ou
       pb->cx.push_back(X);
       pb->cx_cplx_coef.push_back(cplx_coef ? 1 : 0);
     }
-    // fold: F_k = sum_kk c_s (Pi * C)_i f_kk, i = k - lead - (kk - ns), C the
-    // coefficient series of a part of a sector with a_j < -1 (1 otherwise)
+    // fold: F_k = sum_kk c_s (Pi * C)_i f_kk, i = k - lead - (kk - ns - shift),
+    // C the coefficient series of a part of a sector with a_j < -1 or of a
+    // separated term (1 otherwise)
     bool has_im = false;
     const std::vector<std::complex<double>>& cser = X.series[s];
     for (int k = 0; k < K; ++k)
       for (int kk = 0; kk < KMAX; ++kk) {
-        const int i = (d->order_min + k) - d->pref_lead - (kk - R.ns);
+        const int i = (d->order_min + k) - d->pref_lead - (kk - R.ns - shift);
         double fr = 0.0, fi = 0.0;
         if (kk < R.kf && i >= 0) {
           std::complex<double> pc = 0.0;

@@ -77,7 +77,7 @@ int ensure_device(sdi_ctx* ctx, CubState& C, int64_t nreg, int K) {
   const size_t need = align256((size_t)nreg * 4) + align256((size_t)nreg * MAXV) + align256((size_t)nreg * MAXV * 4) +
                       2 * align256((size_t)nreg * K * 16) + align256((size_t)nreg * K * 8) + align256((size_t)nreg * 4) +
                       align256((size_t)nreg * 8) +
-                      align256((MAXV + 1) * 10 * 8);
+                      align256((MAXV + 1) * 10 * 8) + align256((size_t)nreg * 8) + align256(MAXV * 4);
   if (need > C.d_bytes) {
     const size_t bytes = std::max(need, C.d_bytes * 2);
     if (C.d_buf) (void)hipFree(C.d_buf);
@@ -95,10 +95,15 @@ CubState::~CubState() {
   if (d_buf) (void)hipFree(d_buf);
 }
 
-// Apply the rule pair (or, mc, the Monte Carlo sample) to regions [first,
+// Counter tag of the partition phase of integrator 4 ("DIV1").
+constexpr uint32_t DIV_PART_TAG = 0x44495631u;
+
+// Apply the rule pair (mode 0), the Monte Carlo sample (1: integrator 3; 2:
+// the partition phase of integrator 4, with the spreads) to regions [first,
 // first + count) of C on the GPU and store their values, errors, axes and counts.
 static int evaluate_regions(sdi_ctx* ctx, sdi_problem* pb, CubState& C, int64_t first, int64_t count,
-                            const std::vector<double>& omega, float& ms_kernel, bool mc) {
+                            const std::vector<double>& omega, float& ms_kernel, int mode) {
+  const bool mc = mode != 0;
   if (count <= 0) return SDI_OK;
   const int K = pb->K;
   int rc = ensure_device(ctx, C, count, K);
@@ -118,6 +123,7 @@ static int evaluate_regions(sdi_ctx* ctx, sdi_problem* pb, CubState& C, int64_t 
   int32_t* d_axis = (int32_t*)carve((size_t)count * 4);
   int32_t* d_cnt = (int32_t*)carve((size_t)count * 8);
   double* d_w = (double*)carve((MAXV + 1) * 10 * 8);
+  double* d_spread = (double*)carve((size_t)count * 8);
   hipStream_t st = ctx->stream;
   const std::vector<double> wt = weight_table();
   HIPCHK(ctx, hipMemcpyAsync(d_sec, C.sector.data() + first, (size_t)count * 4, hipMemcpyHostToDevice, st));
@@ -170,7 +176,13 @@ static int evaluate_regions(sdi_ctx* ctx, sdi_problem* pb, CubState& C, int64_t 
     M.out_err = d_err;
     M.out_axis = d_axis;
     M.out_count = d_cnt;
-    krc = pb->complex_mode ? launch_suave_cplx(pb->nvmax, km, M, st) : launch_suave_real(pb->nvmax, km, M, st);
+    M.tag = DIV_PART_TAG;
+    M.out_spread = d_spread;
+    if (mode == 2)
+      krc = pb->complex_mode ? launch_divonne_part_cplx(pb->nvmax, km, M, st)
+                             : launch_divonne_part_real(pb->nvmax, km, M, st);
+    else
+      krc = pb->complex_mode ? launch_suave_cplx(pb->nvmax, km, M, st) : launch_suave_real(pb->nvmax, km, M, st);
     if (krc == 0) HIPCHK(ctx, hipMemsetAsync(d_sig, 0, (size_t)count * K * 8, st));
   } else {
     krc = pb->complex_mode ? launch_cubature_cplx(pb->nvmax, km, A, st) : launch_cubature_real(pb->nvmax, km, A, st);
@@ -186,6 +198,8 @@ static int evaluate_regions(sdi_ctx* ctx, sdi_problem* pb, CubState& C, int64_t 
   HIPCHK(ctx, hipMemcpyAsync(C.sig.data() + first * K, d_sig, (size_t)count * K * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipMemcpyAsync(C.axis.data() + first, d_axis, (size_t)count * 4, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipMemcpyAsync(C.count.data() + first * 2, d_cnt, (size_t)count * 8, hipMemcpyDeviceToHost, st));
+  if (mode == 2)
+    HIPCHK(ctx, hipMemcpyAsync(C.spread.data() + first, d_spread, (size_t)count * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
   float ms = 0.f;
   HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
@@ -206,6 +220,99 @@ static void reserve_regions(CubState& C, int64_t n, int K) {
   C.axis.resize(n);
   C.count.resize((size_t)n * 2);
   C.alive.resize(n);
+  C.spread.resize(n);
+}
+
+// The final phase of integrator 4: the lattice rule (divonne.hpp) on the
+// regions idx of C, numbered uid0, uid0 + 1, ... in that order; values,
+// errors and counts are stored at those regions.
+static int lattice_regions(sdi_ctx* ctx, sdi_problem* pb, CubState& C, const std::vector<int64_t>& idx,
+                           int64_t uid0, float& ms_kernel) {
+  const int64_t count = (int64_t)idx.size();
+  if (count == 0) return SDI_OK;
+  const int K = pb->K;
+  int rc = ensure_device(ctx, C, count, K);
+  if (rc != SDI_OK) return rc;
+  std::vector<int32_t> sec(count);
+  std::vector<uint8_t> lev((size_t)count * MAXV);
+  std::vector<uint32_t> ind((size_t)count * MAXV);
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t r = idx[i];
+    sec[i] = C.sector[r];
+    std::memcpy(&lev[(size_t)i * MAXV], &C.level[(size_t)r * MAXV], MAXV);
+    std::memcpy(&ind[(size_t)i * MAXV], &C.index[(size_t)r * MAXV], MAXV * 4);
+  }
+  const Params& prm = ctx->params;
+  const std::vector<uint32_t>& z = lattice_vector16(prm.m);
+  char* b = (char*)C.d_buf;
+  auto carve = [&](size_t bytes) {
+    char* p = b;
+    b += align256(bytes);
+    return (void*)p;
+  };
+  int32_t* d_sec = (int32_t*)carve((size_t)count * 4);
+  uint8_t* d_lev = (uint8_t*)carve((size_t)count * MAXV);
+  uint32_t* d_idx = (uint32_t*)carve((size_t)count * MAXV * 4);
+  double* d_val = (double*)carve((size_t)count * K * 16);
+  double* d_err = (double*)carve((size_t)count * K * 16);
+  int32_t* d_cnt = (int32_t*)carve((size_t)count * 8);
+  uint32_t* d_z = (uint32_t*)carve(MAXV * 4);
+  hipStream_t st = ctx->stream;
+  HIPCHK(ctx, hipMemcpyAsync(d_sec, sec.data(), (size_t)count * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_lev, lev.data(), lev.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_idx, ind.data(), ind.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(d_z, z.data(), MAXV * 4, hipMemcpyHostToDevice, st));
+  DivLatArgs A{};
+  A.secs = pb->d_secs;
+  A.terms = pb->d_terms;
+  A.cx = pb->complex_mode ? pb->d_cx : nullptr;
+  A.dir = pb->complex_mode ? pb->d_dir : nullptr;
+  A.reg_sector = d_sec;
+  A.reg_level = d_lev;
+  A.reg_index = d_idx;
+  A.zvec = d_z;
+  A.nreg = count;
+  A.uid0 = uid0;
+  A.seed = prm.seed;
+  A.K = K;
+  A.m = prm.m;
+  A.R = prm.R;
+  A.baker = prm.baker;
+  A.out_val = d_val;
+  A.out_err = d_err;
+  A.out_count = d_cnt;
+  hipEvent_t e0, e1;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  HIPCHK(ctx, hipEventRecord(e0, st));
+  const int km = pb->kfmax <= 4 ? 4 : 8;
+  const int krc = pb->complex_mode ? launch_divonne_lattice_cplx(pb->nvmax, km, A, st)
+                                   : launch_divonne_lattice_real(pb->nvmax, km, A, st);
+  HIPCHK(ctx, hipEventRecord(e1, st));
+  if (krc != 0) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    KCHK(ctx, krc);
+  }
+  std::vector<double> val((size_t)count * K * 2), err((size_t)count * K * 2);
+  std::vector<int32_t> cnt((size_t)count * 2);
+  HIPCHK(ctx, hipMemcpyAsync(val.data(), d_val, val.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(err.data(), d_err, err.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  float ms = 0.f;
+  HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+  ms_kernel += ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t r = idx[i];
+    std::memcpy(&C.val[(size_t)r * K * 2], &val[(size_t)i * K * 2], (size_t)K * 16);
+    std::memcpy(&C.err[(size_t)r * K * 2], &err[(size_t)i * K * 2], (size_t)K * 16);
+    C.count[2 * r] += cnt[2 * i];
+    C.count[2 * r + 1] += cnt[2 * i + 1];
+  }
+  return SDI_OK;
 }
 
 int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
@@ -214,7 +321,14 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
   // integrator 3: the same loop over regions with a Monte Carlo sample per
   // region (suave.hpp): errors are standard errors, combined as a root sum of
   // squares; a region costs suave_nnew evaluations
-  const bool mc = prm.integrator == 3;
+  // integrator 4: the same loop as the partition phase (Monte Carlo samples,
+  // regions halved by spread, divonne.hpp), then a lattice rule on every
+  // region of the partition and one refinement of the regions whose two
+  // estimates disagree
+  const bool div = prm.integrator == 4;
+  const bool mc = prm.integrator == 3 || div;
+  const int emode = div ? 2 : (mc ? 1 : 0);
+  if (div && prm.R < 2) return fail(ctx, SDI_EINVAL, "integrator 4 needs at least 2 shifts");
   if (pb->is_expr()) return fail(ctx, SDI_ENOTSUP, "the adaptive integrators take sector problems, not text integrands");
   if (prm.budget > 0 || prm.warmup > 0 || prm.sampler != 0 || prm.slice_log2 > 0)
     return fail(ctx, SDI_ENOTSUP, "the adaptive integrators run without budget, warmup, sampler or slice_log2");
@@ -246,7 +360,7 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
   std::fill(C.index.begin(), C.index.end(), 0u);
   std::vector<double> omega(K, 1.0), tau(K, 0.0);
   float ms_kernel = 0.f;
-  int rc = evaluate_regions(ctx, pb, C, 0, nsec, omega, ms_kernel, mc);
+  int rc = evaluate_regions(ctx, pb, C, 0, nsec, omega, ms_kernel, emode);
   if (rc != SDI_OK) return rc;
   int rounds = 1;
   bool converged = false;
@@ -278,6 +392,7 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
       omega[k] = tau[k] > 0.0 ? 1.0 / tau[k] : 1.0;
       all = all && esum[k] <= tau[k];
     }
+    if (div) all = false;   // the partition spends its budget (spreads carry the weights of their round)
     if (all) {
       converged = true;
       break;
@@ -287,6 +402,11 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
       if (!C.alive[r] || C.level[(size_t)r * MAXV + C.axis[r]] >= MAX_LEVEL) continue;
       double p = 0.0;
       bool bad = false;
+      if (div) {
+        p = std::isnan(C.spread[r]) ? INFINITY : coarse(C.spread[r]);
+        if (p > 0.0) cand.push_back({-p, r});
+        continue;
+      }
       for (int k = 0; k < K; ++k) {
         const double e = C.err[(r * K + k) * 2] + C.err[(r * K + k) * 2 + 1];
         if (e <= NOISE * C.sig[r * K + k]) continue;   // converged to rounding noise
@@ -324,9 +444,71 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
       }
     }
     nalive += chosen;
-    rc = evaluate_regions(ctx, pb, C, nreg, 2 * chosen, omega, ms_kernel, mc);
+    rc = evaluate_regions(ctx, pb, C, nreg, 2 * chosen, omega, ms_kernel, emode);
     if (rc != SDI_OK) return rc;
     ++rounds;
+  }
+  // integrator 4: the final phase and the refinement
+  const int64_t nreg_part = (int64_t)C.sector.size();
+  std::vector<int64_t> lat_evals;
+  if (div) {
+    const int64_t per = (int64_t)prm.R << prm.m;
+    const std::vector<double> v1(C.val), e1(C.err);
+    std::vector<int64_t> idx;
+    for (int64_t r = 0; r < nreg_part; ++r)
+      if (C.alive[r]) idx.push_back(r);
+    rc = lattice_regions(ctx, pb, C, idx, 0, ms_kernel);
+    if (rc != SDI_OK) return rc;
+    std::vector<int64_t> redo;
+    for (int64_t r : idx) {
+      if (C.level[(size_t)r * MAXV + C.axis[r]] >= MAX_LEVEL) continue;
+      bool bad = false;
+      for (int q = 0; q < K * 2; ++q) {
+        const size_t o = (size_t)r * K * 2 + q;
+        bad = bad || !(std::fabs(C.val[o] - v1[o]) <= 4.0 * std::hypot(C.err[o], e1[o]));
+      }
+      if (bad) redo.push_back(r);
+    }
+    const int64_t nh = 2 * (int64_t)redo.size();
+    reserve_regions(C, nreg_part + nh, K);
+    std::vector<int64_t> halves;
+    for (size_t i = 0; i < redo.size(); ++i) {
+      const int64_t r = redo[i];
+      C.alive[r] = 0;
+      const int ax = C.axis[r];
+      for (int h = 0; h < 2; ++h) {
+        const int64_t c = nreg_part + 2 * (int64_t)i + h;
+        C.sector[c] = C.sector[r];
+        std::memcpy(&C.level[(size_t)c * MAXV], &C.level[(size_t)r * MAXV], MAXV);
+        std::memcpy(&C.index[(size_t)c * MAXV], &C.index[(size_t)r * MAXV], MAXV * 4);
+        C.level[(size_t)c * MAXV + ax] += 1;
+        C.index[(size_t)c * MAXV + ax] = 2 * C.index[(size_t)r * MAXV + ax] + h;
+        C.axis[c] = ax;
+        C.alive[c] = 1;
+        halves.push_back(c);
+      }
+    }
+    rc = lattice_regions(ctx, pb, C, halves, (int64_t)idx.size(), ms_kernel);
+    if (rc != SDI_OK) return rc;
+    lat_evals.assign(nreg_part + nh, 0);
+    for (int64_t r : idx) lat_evals[r] = per;
+    for (int64_t c : halves) lat_evals[c] = per;
+    evals += (int64_t)(idx.size() + halves.size()) * per;
+    nalive += (int64_t)redo.size();
+    // converged: the final errors within the tolerance per order
+    converged = true;
+    for (int k = 0; k < K; ++k) {
+      double vr = 0.0, vi = 0.0, e2r = 0.0, e2i = 0.0;
+      for (int64_t r = 0; r < (int64_t)C.sector.size(); ++r) {
+        if (!C.alive[r]) continue;
+        vr += C.val[(r * K + k) * 2];
+        vi += C.val[(r * K + k) * 2 + 1];
+        e2r += C.err[(r * K + k) * 2] * C.err[(r * K + k) * 2];
+        e2i += C.err[(r * K + k) * 2 + 1] * C.err[(r * K + k) * 2 + 1];
+      }
+      const double t = std::max(prm.cub_epsabs, prm.cub_epsrel * std::hypot(vr, vi));
+      converged = converged && std::sqrt(e2r) + std::sqrt(e2i) <= t;
+    }
   }
   // results: sums over the regions alive, per sector and in total
   const int64_t nreg = (int64_t)C.sector.size();
@@ -335,7 +517,7 @@ int run_cubature(sdi_ctx* ctx, sdi_problem* pb, sdi_result* out) {
   int64_t nonfin = 0, npos = 0;
   for (int64_t r = 0; r < nreg; ++r) {
     const int s = C.sector[r];
-    pb->sec_evals[s] += region_cost(pb->secs[s].n);
+    pb->sec_evals[s] += (r < nreg_part ? region_cost(pb->secs[s].n) : 0) + (div ? lat_evals[r] : 0);
     nonfin += C.count[2 * r];
     npos += C.count[2 * r + 1];
     if (!C.alive[r]) continue;

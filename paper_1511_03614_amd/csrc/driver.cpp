@@ -1031,7 +1031,7 @@ int sdi_integrate(sdi_ctx* ctx, sdi_problem* pb, void* dev_ws, size_t ws_bytes, 
   HIPCHK(ctx, hipSetDevice(ctx->device));
   (void)hipGetLastError();
   const Params& prm = ctx->params;
-  if (prm.integrator == 1 || prm.integrator == 3) return run_cubature(ctx, pb, out);
+  if (prm.integrator == 1 || prm.integrator >= 3) return run_cubature(ctx, pb, out);
   if (prm.budget > 0 && dev_ws) return fail(ctx, SDI_ENOTSUP, "budget allocation needs the library workspace");
   if (prm.alloc_min > prm.alloc_max) return fail(ctx, SDI_EINVAL, "alloc_min_log2 > alloc_max_log2");
   const int nsec = pb->nsec;

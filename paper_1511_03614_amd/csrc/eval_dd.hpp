@@ -221,6 +221,7 @@ __device__ __attribute__((noinline)) void eval_f_real_dd(CSec* S, CTerm* terms, 
       }
     }
     for (int T = W;; T = (T - 1) & W) {
+      if (T != 0 && S->invb[T] == 0.0) continue;   // a separated term: no boundary terms
       const int off = ns - __builtin_popcount(T);
       D coef = g0;
       D z = add(lrest, lam);

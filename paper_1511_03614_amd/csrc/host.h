@@ -65,6 +65,7 @@ struct Params {
   double cub_split_frac = 0.25;   // cubature: share of the live regions halved per round
   int cub_batch_min = 1024;       // cubature: regions halved per round at least (while there are as many)
   int suave_nnew = 1024;          // subregion-adaptive Monte Carlo: points per new region
+  int separate_terms = 0;         // 1: problems are compiled term by term (SeparateTerms)
 };
 
 // One autotuner decision: final-pass tile size and launch variant
@@ -135,6 +136,7 @@ struct CubState {
   std::vector<int32_t> axis;      // caller variable to halve
   std::vector<int32_t> count;     // [r][2] non-finite nodes, Im F > 0 nodes
   std::vector<uint8_t> alive;     // not yet halved
+  std::vector<double> spread;     // integrator 4: vol (max g - min g) / 2 of the partition sample
   void* d_buf = nullptr;
   size_t d_bytes = 0;
   ~CubState();

@@ -198,8 +198,37 @@ struct SuaveArgs {
   double* out_err;            // [nreg][K][2]  vol * standard error of Re, Im
   int32_t* out_axis;          // [nreg]
   int32_t* out_count;         // [nreg][2] points with a non-finite value, points with Im F(z) > 0
+  uint32_t tag;               // partition phase of integrator 4: the counter's tag
+  double* out_spread;         // partition phase of integrator 4: [nreg] vol (max g - min g) / 2
 };
 int launch_suave_real(int nvmax, int km, const SuaveArgs& a, hipStream_t st);
 int launch_suave_cplx(int nvmax, int km, const SuaveArgs& a, hipStream_t st);
+
+// Integrator 4 (divonne.hpp): the partition phase (k_suave with DIV) and the
+// final phase, a shifted rank-1 lattice rule on every region.
+struct DivLatArgs {
+  const SecDev* secs;
+  const Term* terms;
+  const CplxDev* cx;
+  const uint32_t* dir;
+  const int32_t* reg_sector;  // [nreg]
+  const uint8_t* reg_level;   // [nreg][MAXV], caller variable order
+  const uint32_t* reg_index;  // [nreg][MAXV]
+  const uint32_t* zvec;       // [MAXV] generating vector of 2^m points
+  int64_t nreg;
+  int64_t uid0;
+  uint64_t seed;
+  int32_t K;
+  int32_t m;                  // 2^m points per shift
+  int32_t R;                  // shifts, >= 2
+  int32_t baker;              // tent transform of the lattice coordinates
+  double* out_val;            // [nreg][K][2]  vol * mean over shifts
+  double* out_err;            // [nreg][K][2]  vol * standard error of the shift means
+  int32_t* out_count;         // [nreg][2]
+};
+int launch_divonne_part_real(int nvmax, int km, const SuaveArgs& a, hipStream_t st);
+int launch_divonne_part_cplx(int nvmax, int km, const SuaveArgs& a, hipStream_t st);
+int launch_divonne_lattice_real(int nvmax, int km, const DivLatArgs& a, hipStream_t st);
+int launch_divonne_lattice_cplx(int nvmax, int km, const DivLatArgs& a, hipStream_t st);
 
 }  // namespace sdi

@@ -16,6 +16,7 @@ struct PoleStore {
   std::vector<double> a, b, gam, del, coef;
   std::vector<int32_t> nterms;
   std::vector<uint8_t> exps;
+  std::vector<int32_t> dmono;
 };
 
 // The problem's sectors with every a_j >= -1: input sectors without a_j < -1
@@ -26,8 +27,13 @@ struct PoleExpansion {
   std::vector<std::vector<std::complex<double>>> series;   // coefficient series per part
   std::vector<int> origin;                                  // input sector of each part
   std::vector<std::shared_ptr<PoleStore>> store;
+  // set by separate_terms (empty otherwise): per part, the eps power its
+  // integral is multiplied by is eps^-shift, and sub_only marks a part whose
+  // subtraction keeps only the subtracted integrand (no boundary terms)
+  std::vector<int> shift, sub_only;
 };
 
 int expand_poles(const sdi_problem_desc* d, PoleExpansion& out, std::string& err);
+int separate_terms(PoleExpansion& X, std::string& err);
 
 }  // namespace sdi

@@ -253,4 +253,122 @@ int expand_poles(const sdi_problem_desc* d, PoleExpansion& X, std::string& err) 
   return SDI_OK;
 }
 
+// SeparateTerms (section 4.4): the integrator receives the integrable terms of
+// a sector one by one instead of its whole expression.  With the subtraction
+// at x_j = 0 for the singular set S (a_j = -1), a sector is the sum over
+// T subset S of
+//   prod_{j in T} 1/(b_j eps) int prod_{j not in T} x_j^(a_j + b_j eps)
+//       G(x with x_T = 0) dx,   the subtraction in S \ T keeping only the
+//                               subtracted integrand,
+// an integral over the n - |T| variables outside T: the factors keep the
+// terms free of x_T (with the remaining exponent columns), the coefficient
+// series takes prod 1/b_j, and shift = |T| records the eps^-|T|.  Parts come
+// in the order of T as a bit mask over S in increasing variable index; a part
+// left with no variable gets one constant variable (a = b = 0).  Sectors that
+// fail the basic shape checks pass through unchanged (sdi_problem_create then
+// reports them); a factor with no term on a face is refused (SDI_ENOTSUP).
+int separate_terms(PoleExpansion& X, std::string& err) {
+  PoleExpansion Y;
+  for (size_t p = 0; p < X.descs.size(); ++p) {
+    const sdi_sector_desc& sd = X.descs[p];
+    const int n = sd.nvars;
+    bool ok = n >= 1 && n <= MAXV && sd.nfactors >= 0 && sd.nfactors <= MAXF && sd.mono_a && sd.mono_b &&
+              (!sd.nfactors || (sd.fac_nterms && sd.fac_gamma && sd.fac_delta));
+    std::vector<int> S;
+    size_t nt_all = 0;
+    if (ok) {
+      for (int m = 0; m < sd.nfactors; ++m) {
+        ok = ok && sd.fac_nterms[m] >= 0;
+        if (ok) nt_all += (size_t)sd.fac_nterms[m];
+      }
+      ok = ok && (nt_all == 0 || (sd.term_coef && sd.term_exps));
+      for (int j = 0; ok && j < n; ++j)
+        if (sd.mono_a[j] == -1.0) {
+          S.push_back(j);
+          ok = std::isfinite(sd.mono_b[j]) && sd.mono_b[j] != 0.0;
+        }
+      ok = ok && (int)S.size() <= MAXS;
+    }
+    if (!ok || S.empty()) {
+      Y.descs.push_back(sd);
+      Y.series.push_back(X.series[p]);
+      Y.origin.push_back(X.origin[p]);
+      Y.shift.push_back(0);
+      Y.sub_only.push_back(0);
+      continue;
+    }
+    const int ns = (int)S.size();
+    for (int T = 0; T < (1 << ns); ++T) {
+      std::vector<char> inT(n, 0);
+      double scale = 1.0;
+      for (int i = 0; i < ns; ++i)
+        if (T >> i & 1) {
+          inT[S[i]] = 1;
+          scale /= sd.mono_b[S[i]];
+        }
+      std::vector<int> keep;
+      for (int j = 0; j < n; ++j)
+        if (!inT[j]) keep.push_back(j);
+      const bool dummy = keep.empty();
+      const int nf = dummy ? 1 : (int)keep.size();
+      auto st = std::make_shared<PoleStore>();
+      for (int j : keep) {
+        st->a.push_back(sd.mono_a[j]);
+        st->b.push_back(sd.mono_b[j]);
+        st->dmono.push_back(sd.deform_mono ? sd.deform_mono[j] : 0);
+      }
+      if (dummy) {
+        st->a.push_back(0.0);
+        st->b.push_back(0.0);
+        st->dmono.push_back(0);
+      }
+      size_t t0 = 0;
+      for (int m = 0; m < sd.nfactors; ++m) {
+        int kept = 0;
+        for (int t = 0; t < sd.fac_nterms[m]; ++t) {
+          const uint8_t* e = sd.term_exps + (t0 + t) * (size_t)n;
+          bool on_face = true;
+          for (int j = 0; j < n; ++j) on_face = on_face && !(inT[j] && e[j] != 0);
+          if (!on_face) continue;
+          st->coef.push_back(sd.term_coef[t0 + t]);
+          for (int j : keep) st->exps.push_back(e[j]);
+          if (dummy) st->exps.push_back(0);
+          ++kept;
+        }
+        if (kept == 0) {
+          err = "sector " + std::to_string(X.origin[p]) + ": factor " + std::to_string(m) +
+                " has no term on the face x_j = 0 of a separated term";
+          return SDI_ENOTSUP;
+        }
+        st->nterms.push_back(kept);
+        st->gam.push_back(sd.fac_gamma[m]);
+        st->del.push_back(sd.fac_delta[m]);
+        t0 += (size_t)sd.fac_nterms[m];
+      }
+      sdi_sector_desc o = sd;
+      o.nvars = nf;
+      o.mono_a = st->a.data();
+      o.mono_b = st->b.data();
+      o.deform_mono = sd.deform_mono ? st->dmono.data() : nullptr;
+      o.fac_nterms = st->nterms.data();
+      o.fac_gamma = st->gam.data();
+      o.fac_delta = st->del.data();
+      o.term_coef = st->coef.empty() ? nullptr : st->coef.data();
+      o.term_exps = st->exps.empty() ? nullptr : st->exps.data();
+      o.term_coef_im = nullptr;
+      std::vector<cplx> ser = X.series[p];
+      for (cplx& c : ser) c *= scale;
+      Y.store.push_back(st);
+      Y.descs.push_back(o);
+      Y.series.push_back(ser);
+      Y.origin.push_back(X.origin[p]);
+      Y.shift.push_back(__builtin_popcount(T));
+      Y.sub_only.push_back(1);
+    }
+  }
+  for (auto& st : X.store) Y.store.push_back(st);
+  X = std::move(Y);
+  return SDI_OK;
+}
+
 }  // namespace sdi

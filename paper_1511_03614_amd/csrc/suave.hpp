@@ -16,6 +16,14 @@
 // half with fewer than 2 samples: infinite; all infinite: variable 0).
 //
 // One wave per region; the lanes take points p = lane, lane + 64, ... .
+//
+// DIV (the partition phase of integrator 4, divonne.hpp): the counter's last
+// word is (r / 2^32) xor A.tag, and instead of the spreads the statistic is
+// the range of g: the region's spread vol (max g - min g) / 2 goes to
+// out_spread, and the axis is the variable whose halves' ranges
+// max_h (max_h g - min_h g) are the smallest (8 significant bits, ties the
+// lowest variable, a half with fewer than 2 samples infinite, all infinite:
+// variable 0).
 #pragma once
 #include "eval_cplx.hpp"
 #include "kernels.h"
@@ -43,8 +51,9 @@ __device__ __forceinline__ void wave_dd(double& hi, double& lo) {
   }
 }
 
-template <int NV, int KM, bool CPLX>
+template <int NV, int KM, bool CPLX, bool DIV = false>
 __global__ void __launch_bounds__(BLOCK) k_suave(SuaveArgs A) {
+  const uint32_t tag = DIV ? A.tag : 0x53554156u;
   constexpr int WPB = BLOCK / 64;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
@@ -80,6 +89,18 @@ __global__ void __launch_bounds__(BLOCK) k_suave(SuaveArgs A) {
       gl[c] = g2l[c] = 0.0;
       nl[c] = 0;
     }
+    // DIV: gl / g2l hold min and max of g over the lower half, gt / g2t over
+    // the whole region, and the upper half's in hl / h2l
+    double hl[DIV ? NV : 1], h2l[DIV ? NV : 1];
+    if constexpr (DIV) {
+      gt = __builtin_inf();
+      g2t = -__builtin_inf();
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        gl[c] = hl[c] = __builtin_inf();
+        g2l[c] = h2l[c] = -__builtin_inf();
+      }
+    }
     int nonfin = 0, npos = 0;
     for (int p = lane; p < A.npts; p += 64) {
       double u[NV], xc[NV];
@@ -88,7 +109,7 @@ __global__ void __launch_bounds__(BLOCK) k_suave(SuaveArgs A) {
         u[c] = 0.5;
         xc[c] = 0.5;
         if (c < n) {
-          uint32_t ctr[4] = {(uint32_t)p, (uint32_t)c, (uint32_t)uid, (uint32_t)(uid >> 32) ^ 0x53554156u};
+          uint32_t ctr[4] = {(uint32_t)p, (uint32_t)c, (uint32_t)uid, (uint32_t)(uid >> 32) ^ tag};
           philox4x32_10(ctr, k0, k1);
           const uint64_t b = ((uint64_t)ctr[0] << 20) | (ctr[1] >> 12);
           u[c] = ((double)b + 0.5) * 0x1p-52;
@@ -146,15 +167,32 @@ __global__ void __launch_bounds__(BLOCK) k_suave(SuaveArgs A) {
         }
       }
       nonfin += fin ? 0 : 1;
-      gt += g;
-      g2t += g * g;
+      if constexpr (DIV) {
+        gt = fmin(gt, g);
+        g2t = fmax(g2t, g);
 #pragma unroll
-      for (int c = 0; c < NV; ++c)
-        if (c < n && u[c] < 0.5) {
-          gl[c] += g;
-          g2l[c] += g * g;
-          nl[c] += 1;
-        }
+        for (int c = 0; c < NV; ++c)
+          if (c < n) {
+            if (u[c] < 0.5) {
+              gl[c] = fmin(gl[c], g);
+              g2l[c] = fmax(g2l[c], g);
+              nl[c] += 1;
+            } else {
+              hl[c] = fmin(hl[c], g);
+              h2l[c] = fmax(h2l[c], g);
+            }
+          }
+      } else {
+        gt += g;
+        g2t += g * g;
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+          if (c < n && u[c] < 0.5) {
+            gl[c] += g;
+            g2l[c] += g * g;
+            nl[c] += 1;
+          }
+      }
     }
     // reductions: the double-double sums per order, the axis statistics
     double v1r[KMAX], v1i[KMAX], v2r[KMAX], v2i[KMAX];
@@ -178,8 +216,13 @@ __global__ void __launch_bounds__(BLOCK) k_suave(SuaveArgs A) {
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-      gt += __shfl_xor(gt, o, 64);
-      g2t += __shfl_xor(g2t, o, 64);
+      if constexpr (DIV) {
+        gt = fmin(gt, __shfl_xor(gt, o, 64));
+        g2t = fmax(g2t, __shfl_xor(g2t, o, 64));
+      } else {
+        gt += __shfl_xor(gt, o, 64);
+        g2t += __shfl_xor(g2t, o, 64);
+      }
       nonfin += __shfl_xor(nonfin, o, 64);
       npos += __shfl_xor(npos, o, 64);
     }
@@ -187,8 +230,15 @@ __global__ void __launch_bounds__(BLOCK) k_suave(SuaveArgs A) {
     for (int c = 0; c < NV; ++c)
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) {
-        gl[c] += __shfl_xor(gl[c], o, 64);
-        g2l[c] += __shfl_xor(g2l[c], o, 64);
+        if constexpr (DIV) {
+          gl[c] = fmin(gl[c], __shfl_xor(gl[c], o, 64));
+          g2l[c] = fmax(g2l[c], __shfl_xor(g2l[c], o, 64));
+          hl[c] = fmin(hl[c], __shfl_xor(hl[c], o, 64));
+          h2l[c] = fmax(h2l[c], __shfl_xor(h2l[c], o, 64));
+        } else {
+          gl[c] += __shfl_xor(gl[c], o, 64);
+          g2l[c] += __shfl_xor(g2l[c], o, 64);
+        }
         nl[c] += __shfl_xor(nl[c], o, 64);
       }
     if (lane == 0) {
@@ -217,9 +267,14 @@ __global__ void __launch_bounds__(BLOCK) k_suave(SuaveArgs A) {
         if (c < n) {
           const int a = nl[c], bcount = A.npts - nl[c];
           if (a >= 2 && bcount >= 2) {
-            const double ml = gl[c] / a, mr = (gt - gl[c]) / bcount;
-            const double ql = g2l[c] / a - ml * ml, qr = (g2t - g2l[c]) / bcount - mr * mr;
-            const double phi = coarse8(sqrt(ql > 0.0 ? ql : 0.0) + sqrt(qr > 0.0 ? qr : 0.0));
+            double phi;
+            if constexpr (DIV) {
+              phi = coarse8(fmax(g2l[c] - gl[c], h2l[c] - hl[c]));
+            } else {
+              const double ml = gl[c] / a, mr = (gt - gl[c]) / bcount;
+              const double ql = g2l[c] / a - ml * ml, qr = (g2t - g2l[c]) / bcount - mr * mr;
+              phi = coarse8(sqrt(ql > 0.0 ? ql : 0.0) + sqrt(qr > 0.0 ? qr : 0.0));
+            }
             if (phi < best) {
               best = phi;
               axis = c;
@@ -228,6 +283,7 @@ __global__ void __launch_bounds__(BLOCK) k_suave(SuaveArgs A) {
         }
       }
       A.out_axis[r] = axis;
+      if constexpr (DIV) A.out_spread[r] = vol * (g2t - gt) * 0.5;
       A.out_count[2 * r] = nonfin;
       A.out_count[2 * r + 1] = npos;
     }

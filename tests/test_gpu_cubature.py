@@ -217,7 +217,7 @@ def test_argument_checks(ctx):
         cub_params(ctx, cub_maxeval=10)                   # below one rule per sector (2 x 7)
         with pytest.raises(P.SdiError):
             P.sdi_integrate(ctx, h)
-        for key, val in (("cub_split_frac", 0), ("cub_epsrel", -1), ("cub_batch_min", 0), ("integrator", 4)):
+        for key, val in (("cub_split_frac", 0), ("cub_epsrel", -1), ("cub_batch_min", 0), ("integrator", 5)):
             with pytest.raises(P.SdiError):
                 P.sdi_set_param(ctx, key, val)
     finally:

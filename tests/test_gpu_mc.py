@@ -149,6 +149,6 @@ def test_refusals(ctx):
             P.sdi_set_param(ctx, "slice_log2", 0)
             P.sdi_problem_destroy(h)
         with pytest.raises(P.SdiError):
-            P.sdi_set_param(ctx, "integrator", 4)
+            P.sdi_set_param(ctx, "integrator", 5)
     finally:
         P.sdi_set_param(ctx, "integrator", 0)

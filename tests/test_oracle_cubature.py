@@ -255,3 +255,37 @@ def test_suave_oracle_on_the_bubble_and_a_product():
     r = suave.suave(prob, 256 * 15, 256, 1e-12, 0.0, 1, 1.0, 1)
     assert all(g.level[1] == 0 for g in r.regions)
     assert abs(r.value[0].real - 0.1) < 5 * r.err_re[0]
+
+
+def test_divonne_oracle_pins():
+    """The partition-then-lattice oracle (oracle/divonne.py): a linear
+    integrand on any dyadic box is integrated exactly by the tent-transformed
+    shifted lattice (the tent map of a shifted equispaced grid has mean 1/2), so
+    every region's value is exact and its error 0; the bubble's closed form
+    within 5 standard errors with regions that tile each cube; on an integrand
+    that varies along x_1 only, the partition never cuts x_2."""
+    import math
+    import sectorgen
+    from oracle import divonne, integrate, suave
+    # 1 + 3 x_1 + 2 x_2 on [1/4, 1/2] x [1/2, 1]: vol (1 + 3 * 3/8 + 2 * 3/4) = 1/8 * 3.625
+    sec = sectorgen.Sector(a=np.zeros(2), b=np.zeros(2), factors=[
+        sectorgen.Factor(1.0, 0.0, np.array([1.0, 3.0, 2.0]), np.array([[0, 0], [1, 0], [0, 1]], dtype=np.uint8))])
+    prob = sectorgen.Problem(sectors=[sec], order_min=0, order_max=0)
+    lead, pref = integrate.prefactor_for(prob)
+    reg = suave.MCRegion(0, np.array([2, 1]), np.array([1, 1]), 0)
+    v, er, ei, nf = divonne.lattice_rule(prob, reg, 7, 6, 4, 3, True, lead, pref)
+    assert abs(v[0].real - 0.125 * 3.625) < 1e-14 and er[0] < 1e-15 and nf == 0
+    exact = [1.0, 2.0, 4 - math.pi ** 2 / 12]
+    r = divonne.divonne(sectorgen.bubble_problem(order_max=1), 30000, 256, 1e-6, 0.0, 5, 8, 8)
+    z = (r.value.real - exact) / r.err_re
+    assert np.all(np.abs(z) < 5), z
+    alive = [g for g in r.regions if g.alive]
+    for s in range(2):
+        assert sum(math.ldexp(1.0, -int(g.level.sum())) for g in alive if g.sector == s) == 1.0
+    # (1 + 9 x_1)^-2 in two variables
+    sec = sectorgen.Sector(a=np.zeros(2), b=np.zeros(2), factors=[
+        sectorgen.Factor(-2.0, 0.0, np.array([1.0, 9.0]), np.array([[0, 0], [1, 0]], dtype=np.uint8))])
+    prob = sectorgen.Problem(sectors=[sec], order_min=0, order_max=0)
+    r = divonne.divonne(prob, 256 * 15, 256, 1e-12, 0.0, 1, 8, 4, split_frac=1.0, batch_min=1)
+    assert r.rounds > 1 and all(g.level[1] == 0 for g in r.regions)
+    assert abs(r.value[0].real - 0.1) < 5 * r.err_re[0] + 1e-12
