@@ -684,6 +684,37 @@ def cubature_entry(P, ctx, name, problem, maxeval, steps=3, split_frac=0.25, bat
         _set(P, ctx)
 
 
+def adaptive_mc_entry(P, ctx, name, problem, maxeval, steps=3):
+    """The sampling adaptive integrators on a workload at the same partition
+    budget: integrator 3 (subregion-adaptive Monte Carlo, 1024 points per new
+    region) and integrator 4 (partition by spreads with 256 points per new
+    region, then a lattice rule of 16 shifts x 2^8 points on every region):
+    time in their kernels and per call, regions, evaluations, value and error
+    per order."""
+    h = P.sdi_problem_create(ctx, problem)
+    try:
+        out = {"workload": name, "cub_maxeval": maxeval}
+        for key, integ, nnew in (("subregion_monte_carlo", 3, 1024), ("partition_then_lattice", 4, 256)):
+            _set(P, ctx, integrator=integ, lattice_log2=8, shifts=16)
+            for k, v in dict(cub_maxeval=maxeval, cub_epsrel=1e-12, cub_epsabs=0.0, cub_split_frac=0.25,
+                             cub_batch_min=1024, suave_nnew=nnew).items():
+                P.sdi_set_param(ctx, k, v)
+            P.sdi_integrate(ctx, h)
+            runs = [P.sdi_integrate(ctx, h) for _ in range(steps)]
+            r = runs[-1]
+            ms_k = float(sorted(x["ms_eval_kernel"] for x in runs)[steps // 2])
+            ms_t = float(sorted(x["ms_total"] for x in runs)[steps // 2])
+            out[key] = {"evals": int(r["n_evals"]), "regions": int(r["cub_regions"]), "rounds": int(r["cub_rounds"]),
+                        "ms_kernels": ms_k, "ms_total": ms_t, "evals_per_s_kernels": r["n_evals"] / (ms_k * 1e-3),
+                        "value_re": r["value"].real.tolist(), "err": _err(r).tolist()}
+        return out
+    finally:
+        P.sdi_problem_destroy(h)
+        for k, v in dict(cub_maxeval=1 << 24, cub_epsrel=1e-6, cub_batch_min=1024, suave_nnew=1024).items():
+            P.sdi_set_param(ctx, k, v)
+        _set(P, ctx)
+
+
 def monte_carlo_entry(P, ctx, name, problem, m, R=16, warmup=0, steps=3):
     """The Monte Carlo integrator (integrator 2: Philox points, the sampling of
     the paper's default vegasCuba) beside the lattice on the same workload, the
@@ -1001,6 +1032,7 @@ def main() -> int:
         out["endpoint_precision"] = endpoint_precision_cost(P, ctx, sectorgen.config2())
         out["monte_carlo"] = monte_carlo_entry(P, ctx, "synthetic64, 5 Vegas warm-up iterations", sectorgen.config2(),
                                                16, warmup=5)
+        out["adaptive_monte_carlo"] = adaptive_mc_entry(P, ctx, "synthetic64", sectorgen.config2(), 1 << 22)
     if not args.no_equal_time:
         lat = [dict(lattice_log2=m) for m in range(10, 17)]
         alloc = dict(pilot_log2=10, alloc_min_log2=12, alloc_max_log2=20)
