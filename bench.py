@@ -928,7 +928,7 @@ def main() -> int:
     ap.add_argument("--tune-save", default=None, help="save the autotuner decisions of the run (sdi_tune_save)")
     ap.add_argument("--only", default=None,
                     help="profiling aid: run only this workload (batched2000, synthetic64, bubble, doublebox, "
-                         "doublebox_physical) and print its entry")
+                         "doublebox_physical, adaptive_mc: the sampling adaptive integrators) and print its entry")
     ap.add_argument("--no-equal-time", action="store_true",
                     help="skip the learned-sampler comparison (double box, Euclidean and physical)")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
@@ -974,6 +974,11 @@ def main() -> int:
                                        dict(lattice_log2=16, shifts=16, seed=1),
                                        dict(lambda_max=0.5, conservative_if_imf=True)),
     }
+    if args.only == "adaptive_mc":
+        ent = adaptive_mc_entry(P, ctx, "synthetic64", sectorgen.config2(), 1 << 22)
+        P.sdi_ctx_destroy(ctx)
+        print(json.dumps(strict_json(ent), allow_nan=False), flush=True)
+        return 0
     if args.only:
         prob, prm, kw = workloads[args.only]()
         m = measure(P, ctx, prob, prm, args.steps, args.warmup, **kw)
