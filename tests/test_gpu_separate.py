@@ -9,6 +9,8 @@
 * The separated total agrees with the whole sectors' total within their
   combined error estimates (two estimates of the same integral), under the
   lattice and under the adaptive cubature.
+* The box of section 4.3 through the Feynman front end: the oracle's terms of
+  the input tool's sectors per shift, and the closed form.
 * Refusals: complex mode, a factor with no term on a face.
 """
 import numpy as np
@@ -120,3 +122,36 @@ def test_refusals(ctx):
         P.sdi_set_param(ctx, "separate_terms", 0)
     with pytest.raises(P.SdiError):
         P.sdi_set_param(ctx, "separate_terms", 2)
+
+
+def test_box_through_the_front_end(ctx):
+    """The one-loop box of section 4.3 built by sdi_problem_from_feynman with
+    separate_terms = 1: the oracle's terms of the input tool's sectors, the
+    same per-(term, shift) means, and the closed form."""
+    import math
+    from sectorgen import feynman
+    U, F = feynman.box_uf(3.0, 1.0)
+    P.sdi_set_param(ctx, "separate_terms", 1)
+    try:
+        h = P.sdi_problem_from_feynman(ctx, U, F, 1, (1, 1, 1, 1), 0)
+    finally:
+        P.sdi_set_param(ctx, "separate_terms", 0)
+    parts, origin = separate.separate(feynman.box_problem(3.0, 1.0))
+    try:
+        assert P.sdi_problem_nsectors(h) == len(parts.sectors)
+        assert [P.sdi_problem_sector_origin(h, s) for s in range(len(parts.sectors))] == origin
+        m, R, seed = 12, 8, 3
+        set_params(ctx, lattice_log2=m, shifts=R, seed=seed)
+        res = P.sdi_integrate(ctx, h)
+        K = len(res["value"])
+        off = res["order_min"] - parts.order_min
+        for s in range(len(parts.sectors)):
+            q, scale = oracle_shift_values(parts, s, m, R, seed)
+            assert_close_shift(P.sdi_sector_results(ctx, h, s, R)[2], q[:, off:off + K], scale[off:off + K],
+                               f"box term {s}")
+        exact = [4 / 3, -2 * math.log(3) / 3, -4 * math.pi ** 2 / 9]
+        assert np.all(np.abs(res["value"].real - exact) <= 5 * res["err_re"] + 1e-9), (res["value"], res["err_re"])
+        log(f"box through the front end: {len(parts.sectors)} terms, values {res['value'].real}")
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
