@@ -182,7 +182,7 @@ int sdi_device_info(sdi_ctx* ctx, char* buf, size_t len);
  *                  (0, 1]                                    (default 0.25)
  *   cub_batch_min  cubature: regions halved per round at least, while there
  *                  are as many (1..2^24)                     (default 1024)
- * Aliases in the survey's terms: points (evaluations per sector = shifts x
+ * Aliases: points (evaluations per sector = shifts x
  * 2^lattice_log2, a power-of-two multiple of the current shifts), budget_total
  * (= budget), budget_min / budget_max (per-sector evaluations under
  * allocation = shifts x 2^alloc_min_log2 / 2^alloc_max_log2), iterations
