@@ -157,3 +157,20 @@ def test_argument_checks(ctx):
             P.sdi_problem_destroy(h)
     finally:
         reset(ctx)
+
+
+def test_largest_variable_classes(ctx):
+    """The 10- and 16-variable instances (a few rounds), against the oracle."""
+    from shapes import max_real_problem
+    rng = np.random.default_rng(10)
+    n = 10
+    exps = np.zeros((12, n), dtype=np.uint8)
+    for t in range(1, 12):
+        exps[t, rng.choice(n, 3, replace=False)] = rng.integers(1, 4, 3)
+    sec10 = sectorgen.Sector(a=np.r_[-1.0, -1.0, np.zeros(n - 2)], b=np.r_[1.0, -2.0, np.zeros(n - 2)],
+                             factors=[sectorgen.Factor(-1.5, 1.0, rng.uniform(0.2, 1.0, 12), exps)])
+    p10 = sectorgen.Problem(sectors=[sec10, sec10], order_min=-2, order_max=0)
+    run_both(ctx, p10, "10 variables", suave_nnew=64, cub_maxeval=64 * 14, cub_batch_min=2)
+    big = max_real_problem()
+    p16 = dataclasses.replace(big, sectors=big.sectors[:2])
+    run_both(ctx, p16, "16 variables", suave_nnew=64, cub_maxeval=64 * 10, cub_batch_min=2)
