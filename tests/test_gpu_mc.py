@@ -55,15 +55,21 @@ def oracle_mc_shifts(prob, s, m, R, seed):
     return q, scale
 
 
-@pytest.mark.parametrize("which", ["synthetic", "massive bubble (complex)"])
+@pytest.mark.parametrize("which", ["synthetic", "massive bubble (complex)", "16 variables"])
 def test_points_and_shift_means_match_the_oracle(ctx, which):
+    m, R, seed = 9, 4, 11
     if which == "synthetic":
         full = sectorgen.config2()
         prob = sectorgen.Problem(sectors=full.sectors[:4], order_min=full.order_min, order_max=full.order_max,
                                  pref_lead=full.pref_lead, pref=full.pref)
+    elif which == "16 variables":
+        from shapes import max_real_problem
+        big = max_real_problem()
+        prob = sectorgen.Problem(sectors=big.sectors[:2], order_min=big.order_min, order_max=big.order_max,
+                                 pref_lead=big.pref_lead, pref=big.pref)
+        m = 6
     else:
         prob = massive_bubble_problem(5.0, 1.0, 0.5)
-    m, R, seed = 9, 4, 11
     set_params(ctx, lattice_log2=m, shifts=R, seed=seed, tile_log2=0)
     P.sdi_set_param(ctx, "integrator", 2)
     h = P.sdi_problem_create(ctx, prob)
