@@ -9,6 +9,8 @@
 * The separated total agrees with the whole sectors' total within their
   combined error estimates (two estimates of the same integral), under the
   lattice and under the adaptive cubature.
+* Under the Vegas warm-up every term adapts its own grids, as the oracle's
+  terms do (per shift at the warm-up bar).
 * The box of section 4.3 through the Feynman front end: the oracle's terms of
   the input tool's sectors per shift, and the closed form.
 * Refusals: complex mode, a factor with no term on a face.
@@ -152,6 +154,30 @@ def test_box_through_the_front_end(ctx):
         exact = [4 / 3, -2 * math.log(3) / 3, -4 * math.pi ** 2 / 9]
         assert np.all(np.abs(res["value"].real - exact) <= 5 * res["err_re"] + 1e-9), (res["value"], res["err_re"])
         log(f"box through the front end: {len(parts.sectors)} terms, values {res['value'].real}")
+    finally:
+        P.sdi_problem_destroy(h)
+        set_params(ctx)
+
+
+def test_terms_with_vegas_warmup(ctx):
+    """Separated terms under the Vegas warm-up: every term adapts its own grids
+    from all its eps rows (the eps shift included), as the oracle's terms do."""
+    from oracle import integrate
+    prob = problems()[0]
+    parts, _ = separate.separate(prob)
+    m, R, mw, nb, W = 10, 4, 10, 32, 2
+    h = create_separated(ctx, prob)
+    try:
+        set_params(ctx, lattice_log2=m, shifts=R, seed=4, warmup=W, warmup_log2=mw, nbins=nb)
+        P.sdi_integrate(ctx, h)
+        lead, pref = integrate.prefactor_for(parts)
+        for s in range(len(parts.sectors)):
+            est = integrate.integrate_sector(parts, s, m, R, 4, lead, pref, True, nb, W, mw)
+            per = P.sdi_sector_results(ctx, h, s, R)[2]
+            # grids refit from histograms summed in different orders: 1e-9 of the absolute scale
+            oq, scale = oracle_shift_values(parts, s, m, R, 4, grid=est.grid)
+            tol = 1e-9 * np.maximum(np.abs(oq), scale[None, :])
+            assert np.all(np.abs(per - oq) <= tol), s
     finally:
         P.sdi_problem_destroy(h)
         set_params(ctx)
