@@ -8,7 +8,8 @@
   which must leave the boundary terms out as the fp64 path does.
 * The separated total agrees with the whole sectors' total within their
   combined error estimates (two estimates of the same integral), under the
-  lattice and under the adaptive cubature.
+  lattice, the adaptive cubature, the subregion-adaptive Monte Carlo and the
+  partition-then-lattice integrator.
 * Under the Vegas warm-up every term adapts its own grids, as the oracle's
   terms do (per shift at the warm-up bar).
 * The box of section 4.3 through the Feynman front end: the oracle's terms of
@@ -82,21 +83,29 @@ def test_terms_match_the_oracle(ctx, which, small_x):
         set_params(ctx)
 
 
-@pytest.mark.parametrize("integrator", [0, 1])
+ADAPTIVE = {1: dict(cub_maxeval=1 << 22, cub_epsrel="1e-7"),
+            3: dict(cub_maxeval=1 << 20, cub_epsrel="1e-7", suave_nnew=1024),
+            4: dict(cub_maxeval=1 << 18, cub_epsrel="1e-7", suave_nnew=256)}
+
+
+@pytest.mark.parametrize("integrator", [0, 1, 3, 4])
 def test_separated_total_agrees_with_whole(ctx, integrator):
     prob = problems()[0]
     out = []
     for sep in (0, 1):
         h = create_separated(ctx, prob) if sep else P.sdi_problem_create(ctx, prob)
         try:
-            set_params(ctx, lattice_log2=14, shifts=16, seed=3)
+            if integrator == 4:
+                set_params(ctx, lattice_log2=8, shifts=8, seed=3)
+            else:
+                set_params(ctx, lattice_log2=14, shifts=16, seed=3)
             P.sdi_set_param(ctx, "integrator", integrator)
-            if integrator == 1:
-                P.sdi_set_param(ctx, "cub_maxeval", 1 << 22)
-                P.sdi_set_param(ctx, "cub_epsrel", "1e-7")
+            for k, v in ADAPTIVE.get(integrator, {}).items():
+                P.sdi_set_param(ctx, k, v)
             out.append(P.sdi_integrate(ctx, h))
         finally:
-            P.sdi_set_param(ctx, "integrator", 0)
+            for k, v in dict(integrator=0, cub_maxeval=1 << 24, cub_epsrel="1e-6", suave_nnew=1024).items():
+                P.sdi_set_param(ctx, k, v)
             P.sdi_problem_destroy(h)
             set_params(ctx)
     a, b = out
