@@ -32,6 +32,8 @@ What it computes (paper: FIESTA 4, arXiv:1511.03614):
   pair on dyadic regions, split along the largest fourth difference.
 * ``suave``      - subregion-adaptive Monte Carlo (the Suave option):
   sampled dyadic regions halved where the samples spread most.
+* ``divonne``    - partition by spreads, then a lattice rule per region (the
+  Divonne option): stratified sampling with one refinement.
 * ``separate``   - SeparateTerms (section 4.4): a sector as the sum of the
   integrable terms of its subtraction, each a sector of its own.
 
